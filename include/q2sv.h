@@ -1,0 +1,148 @@
+/*
+ * q2sv -- state-vector simulation of UCCSD circuits on one MI355X (gfx950).
+ *
+ * C ABI of libq2sv.so.  Plain pointers and sizes only.  Every call returns an
+ * int: SV_OK (0) on success, a negative SV_E* code on failure, with a
+ * thread-local message in sv_last_error().  No call throws or exits.
+ *
+ * Conventions (Section 3.1 Eq. 1-2, Section 3.2 Eq. 6, Section 4.1 Eq. 7,
+ * Section 5.1 Eq. 10-11, Algorithm 1):
+ *   - A state on n qubits is 2^n complex amplitudes; qubit q is bit q of the
+ *     amplitude index (little-endian).  Amplitudes are interleaved (re, im):
+ *     complex128 (SV_C128, 16 bytes) or complex64 (SV_C64, 8 bytes).
+ *   - A Pauli string is sv_pauli {x, z}: bit q of x is set when the factor on
+ *     qubit q is X or Y, bit q of z when it is Z or Y.  The operator is
+ *     P = i^{popcount(x & z)} X^x Z^z, the plain tensor product of the
+ *     factors (Hermitian, P^2 = I).
+ *   - A rotation is R(P, phi) = exp(-i phi P / 2).  The Trotter product of
+ *     Eq. 11 is a list of rotations applied in list order; the paper's
+ *     exp(i theta P) is R(P, -2 theta).
+ *   - A Pauli sum (Eq. 1) is H = sum_t c_t P_t with real c_t.
+ *
+ * Memory and streams.  The caller owns the amplitude buffer (device memory,
+ * for example a contiguous torch tensor) and the HIP stream.  Every call only
+ * enqueues work on the state's stream and returns; outputs named *_dev are
+ * device pointers to FP64 values written on that stream.  Host arrays passed
+ * to a call are read before the call returns; the caller may free them
+ * afterwards.  A handle is not re-entrant: calls on one handle must not be
+ * made concurrently from several host threads.  Distinct handles may be used
+ * concurrently on different streams.
+ *
+ * Errors.  Arguments are validated before any device work; on SV_EINVAL the
+ * state is untouched.  SV_ENOMEM: a device or pinned allocation of the
+ * library's own scratch failed.  SV_EDEVICE: a HIP launch or runtime call
+ * failed; the device may be unusable afterwards.
+ */
+#ifndef Q2SV_H
+#define Q2SV_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef struct sv_state sv_state;             /* opaque: one state vector      */
+typedef struct sv_hamiltonian sv_hamiltonian; /* opaque: resident Pauli sum    */
+typedef struct { uint64_t x, z; } sv_pauli;
+
+enum { SV_C128 = 0, SV_C64 = 1 };
+enum { SV_OK = 0, SV_EINVAL = -1, SV_ENOMEM = -2, SV_EDEVICE = -3 };
+
+/* Largest supported qubit count (a 2^34 complex128 state is 256 GiB). */
+#define SV_MAX_QUBITS 34
+
+/* Bind a caller-owned device buffer as an n-qubit state (Eq. 7).
+ *   n_qubits   1..SV_MAX_QUBITS
+ *   dtype      SV_C128 or SV_C64
+ *   amps       device pointer, 16-byte aligned, at least 2^n amplitudes
+ *   amps_bytes size of that buffer in bytes (checked against 2^n * 16 or 8)
+ *   hip_stream hipStream_t on which all work of this handle is enqueued
+ *              (NULL = the default stream)
+ *   out        receives the handle
+ * The library allocates only the handle and small scratch (reduction
+ * partials, staged tables); it never frees amps.  The amplitudes are not
+ * initialised: call sv_prepare_hf or write them yourself. */
+int sv_alloc(int n_qubits, int dtype, void *amps, size_t amps_bytes, void *hip_stream,
+             sv_state **out);
+
+/* Release the handle and its scratch (waits for the handle's stream). */
+int sv_free(sv_state *s);
+
+/* Change the stream of a handle (later calls enqueue there). */
+int sv_set_stream(sv_state *s, void *hip_stream);
+
+/* psi <- |occ_mask>, the Hartree-Fock determinant of Eq. 6 as a basis state
+ * (occupation of qubit q = bit q).  occ_mask < 2^n. */
+int sv_prepare_hf(sv_state *s, uint64_t occ_mask);
+
+/* psi <- R(p[n_rot-1], phi[n_rot-1]) ... R(p[0], phi[0]) psi   (Eq. 11).
+ * p, phi are host arrays of n_rot >= 0 entries; every (x | z) < 2^n and every
+ * phi finite.  Consecutive strings with the same x that commute are applied
+ * as one fused pass (their product is the rotation by the summed angle on
+ * each amplitude pair); runs whose x-masks fit one LDS tile are applied in
+ * one HBM pass.  The result equals the one-at-a-time product up to rounding. */
+int sv_apply_pauli_rotations(sv_state *s, const sv_pauli *p, const double *phi, int64_t n_rot);
+
+/* Expectation of a Pauli sum (Eq. 2).  Writes out_dev[0] = <psi|H|psi> /
+ * <psi|psi> and out_dev[1] = <psi|psi>, both FP64, on the state's stream.
+ * Strings are grouped by x: one read of psi serves every z-variant of an x.
+ * The reduction order is fixed by n and the term list, so repeated calls are
+ * bitwise identical. */
+int sv_expect_pauli_sum(sv_state *s, const sv_pauli *p, const double *coef, int64_t n_terms,
+                        double *out_dev);
+
+/* Reverse-mode gradient (Algorithm 1) of E = <psi|H|psi> with respect to
+ * every rotation angle.
+ *   psi     on entry U|psi0> from sv_apply_pauli_rotations with the same list;
+ *           on return approximately psi0 (the rotations are undone).
+ *   lam     scratch state with the same n and dtype; on return U^dag H U psi0.
+ *   hp, hc, n_terms  the Pauli sum H (host arrays)
+ *   rp, phi, n_rot   the rotation list that produced psi (host arrays)
+ *   energy_dev       device FP64[2]: <psi|H|psi>/<psi|psi>, <psi|psi>
+ *   grad_dev         device FP64[n_rot]: dE/dphi_k = Im <lam_k|P_k|psi_k>,
+ *                    with psi_k, lam_k taken right after rotation k. */
+int sv_adjoint_grad(sv_state *psi, sv_state *lam, const sv_pauli *hp, const double *hc,
+                    int64_t n_terms, const sv_pauli *rp, const double *phi, int64_t n_rot,
+                    double *energy_dev, double *grad_dev);
+
+/* As sv_adjoint_grad, but returns the gradient with respect to parameters
+ * theta, where phi_k = dphi_dtheta[k] * theta[param_of_rot[k]]:
+ *   grad_theta_dev[i] = sum_{k: param_of_rot[k] = i} dphi_dtheta[k] dE/dphi_k.
+ * param_of_rot entries lie in [0, n_params).  Runs are split so that one run
+ * has one parameter; on amplitude pairs where a run acts as the identity and
+ * contributes nothing to the gradient, the pass skips work. */
+int sv_adjoint_grad_params(sv_state *psi, sv_state *lam, const sv_pauli *hp, const double *hc,
+                           int64_t n_terms, const sv_pauli *rp, const double *phi, int64_t n_rot,
+                           const int32_t *param_of_rot, const double *dphi_dtheta,
+                           int64_t n_params, double *energy_dev, double *grad_theta_dev);
+
+/* Resident Pauli sums: group and upload once, then evaluate many times.
+ * The handle holds device memory on the device current at creation. */
+int sv_hamiltonian_create(int n_qubits, const sv_pauli *p, const double *coef, int64_t n_terms,
+                          sv_hamiltonian **out);
+int sv_hamiltonian_free(sv_hamiltonian *h);
+int sv_expect_hamiltonian(sv_state *s, const sv_hamiltonian *h, double *out_dev);
+int sv_adjoint_grad_params_h(sv_state *psi, sv_state *lam, const sv_hamiltonian *h,
+                             const sv_pauli *rp, const double *phi, int64_t n_rot,
+                             const int32_t *param_of_rot, const double *dphi_dtheta,
+                             int64_t n_params, double *energy_dev, double *grad_theta_dev);
+
+/* psi <- psi / ||psi|| with the norm reduced in FP64 (the scale is applied in
+ * the amplitude precision).  norm2_dev (device FP64[1], may be NULL)
+ * receives ||psi||^2 before scaling. */
+int sv_normalize(sv_state *s, double *norm2_dev);
+
+/* psi[k] for a list of host indices, copied to a device FP64 array of
+ * 2 * count values (re, im); used to check single amplitudes at scale. */
+int sv_gather_amplitudes(sv_state *s, const uint64_t *idx, int64_t count, double *out_dev);
+
+/* Message of the last failed call on this host thread ("" if none). */
+const char *sv_last_error(void);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* Q2SV_H */

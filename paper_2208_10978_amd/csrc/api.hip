@@ -1,0 +1,740 @@
+// C ABI of libq2sv.so (declared in include/q2sv.h): argument checks, plan
+// caches, staging of per-call tables, and the order of kernel launches for
+// each call.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cmath>
+#include <cstring>
+#include <memory>
+#include <string>
+#include <vector>
+
+#include "../../include/q2sv.h"
+#include "launch.h"
+#include "plan.h"
+
+using namespace q2sv;
+
+namespace {
+
+thread_local std::string g_err;
+
+int fail(int code, const std::string& msg) {
+  g_err = msg;
+  return code;
+}
+
+#define HIP_TRY(expr)                                                                       \
+  do {                                                                                      \
+    hipError_t e_ = (expr);                                                                 \
+    if (e_ != hipSuccess) return fail(SV_EDEVICE, std::string(#expr) + ": " + hipGetErrorString(e_)); \
+  } while (0)
+
+uint64_t fnv(const void* data, size_t bytes, uint64_t h = 1469598103934665603ull) {
+  const unsigned char* p = static_cast<const unsigned char*>(data);
+  for (size_t i = 0; i < bytes; ++i) {
+    h ^= p[i];
+    h *= 1099511628211ull;
+  }
+  return h;
+}
+
+// Device buffer that grows; growing waits for the stream that uses it.
+struct DevBuf {
+  void* p = nullptr;
+  size_t cap = 0;
+  int ensure(size_t bytes, hipStream_t st) {
+    if (bytes <= cap) return SV_OK;
+    if (p) {
+      if (hipStreamSynchronize(st) != hipSuccess) return fail(SV_EDEVICE, "hipStreamSynchronize failed");
+      hipFree(p);
+      p = nullptr;
+      cap = 0;
+    }
+    size_t want = std::max<size_t>(bytes, 4096);
+    want = std::max(want, cap * 2);
+    if (hipMalloc(&p, want) != hipSuccess) {
+      p = nullptr;
+      return fail(SV_ENOMEM, "device scratch allocation of " + std::to_string(want) + " bytes failed");
+    }
+    cap = want;
+    return SV_OK;
+  }
+  void release() {
+    if (p) hipFree(p);
+    p = nullptr;
+    cap = 0;
+  }
+};
+
+// Pinned staging buffer; reuse waits until the previous upload has left it.
+struct Staging {
+  void* host = nullptr;
+  size_t cap = 0;
+  hipEvent_t done = nullptr;
+  bool pending = false;
+  int ensure(size_t bytes) {
+    if (!done && hipEventCreateWithFlags(&done, hipEventDisableTiming) != hipSuccess)
+      return fail(SV_EDEVICE, "hipEventCreate failed");
+    if (pending) {
+      if (hipEventSynchronize(done) != hipSuccess) return fail(SV_EDEVICE, "hipEventSynchronize failed");
+      pending = false;
+    }
+    if (bytes <= cap) return SV_OK;
+    if (host) hipHostFree(host);
+    host = nullptr;
+    size_t want = std::max<size_t>(bytes, 1 << 16);
+    want = std::max(want, cap * 2);
+    if (hipHostMalloc(&host, want, hipHostMallocDefault) != hipSuccess) {
+      host = nullptr;
+      cap = 0;
+      return fail(SV_ENOMEM, "pinned staging allocation failed");
+    }
+    cap = want;
+    return SV_OK;
+  }
+  void release() {
+    if (done) {
+      hipEventSynchronize(done);
+      hipEventDestroy(done);
+    }
+    if (host) hipHostFree(host);
+    host = nullptr;
+    done = nullptr;
+    cap = 0;
+  }
+};
+
+// Packs several host arrays into one upload.
+struct Packer {
+  std::vector<std::pair<const void*, size_t>> parts;
+  std::vector<size_t> offs;
+  size_t total = 0;
+  size_t add(const void* p, size_t bytes) {
+    total = (total + 255) & ~size_t(255);
+    const size_t off = total;
+    parts.push_back({p, bytes});
+    offs.push_back(off);
+    total += bytes;
+    return off;
+  }
+};
+
+int upload(Staging& stg, DevBuf& dev, Packer& pk, hipStream_t st) {
+  if (pk.total == 0) return SV_OK;
+  int rc = stg.ensure(pk.total);
+  if (rc) return rc;
+  rc = dev.ensure(pk.total, st);
+  if (rc) return rc;
+  for (size_t i = 0; i < pk.parts.size(); ++i)
+    if (pk.parts[i].second) std::memcpy(static_cast<char*>(stg.host) + pk.offs[i], pk.parts[i].first, pk.parts[i].second);
+  HIP_TRY(hipMemcpyAsync(dev.p, stg.host, pk.total, hipMemcpyHostToDevice, st));
+  HIP_TRY(hipEventRecord(stg.done, st));
+  stg.pending = true;
+  return SV_OK;
+}
+
+template <typename T>
+const T* dptr(const DevBuf& d, size_t off) {
+  return reinterpret_cast<const T*>(static_cast<const char*>(d.p) + off);
+}
+
+int full_grid(uint64_t work) {
+  const uint64_t want = (work + 255) / 256;
+  return int(std::min<uint64_t>(std::max<uint64_t>(want, 1), kPartialStride));
+}
+
+}  // namespace
+
+// ---------------------------------------------------------------------------
+// resident Pauli sums
+// ---------------------------------------------------------------------------
+struct DevTiling {
+  HTiling host;
+  DevBuf buf;
+  size_t o_frames = 0, o_tg = 0, o_groups = 0, o_subs = 0, o_recs = 0;
+};
+
+struct sv_hamiltonian {
+  int n = 0;
+  int64_t n_terms = 0;
+  uint64_t key = 0;
+  std::vector<HGroup> groups;
+  std::vector<double> coef;  // (re, im) pairs
+  DevBuf coef_dev;
+  DevTiling tilings[2][2];   // [dtype][role: 0 one-tile (expectation), 1 two-tile (lambda)]
+  bool built[2][2] = {{false, false}, {false, false}};
+  int device = 0;
+};
+
+static int tiling_get(sv_hamiltonian* h, int dtype, int role, DevTiling** out) {
+  DevTiling& t = h->tilings[dtype][role];
+  if (!h->built[dtype][role]) {
+    std::vector<uint32_t> coef_off(h->groups.size());
+    uint32_t off = 0;
+    for (size_t g = 0; g < h->groups.size(); ++g) {
+      coef_off[g] = off;
+      off += uint32_t(h->groups[g].w.size() * h->groups[g].n_rec());
+    }
+    const int b = role == 0 ? tile_bits_one(dtype) : tile_bits_two(dtype);
+    const int c = std::min(dtype == 0 ? 3 : 4, h->n);
+    t.host = build_tiling(h->groups, coef_off, h->n, b, c);
+    Packer pk;
+    t.o_frames = pk.add(t.host.frames.data(), t.host.frames.size() * sizeof(FrameDesc));
+    t.o_tg = pk.add(t.host.tile_groups.data(), t.host.tile_groups.size() * sizeof(uint32_t));
+    t.o_groups = pk.add(t.host.groups.data(), t.host.groups.size() * sizeof(GroupDesc));
+    t.o_subs = pk.add(t.host.subs.data(), t.host.subs.size() * sizeof(SubDesc));
+    t.o_recs = pk.add(t.host.recbits.data(), t.host.recbits.size() * sizeof(uint64_t));
+    std::vector<char> blob(pk.total + 1);
+    for (size_t i = 0; i < pk.parts.size(); ++i)
+      if (pk.parts[i].second) std::memcpy(blob.data() + pk.offs[i], pk.parts[i].first, pk.parts[i].second);
+    int rc = t.buf.ensure(pk.total + 256, nullptr);
+    if (rc) return rc;
+    HIP_TRY(hipMemcpy(t.buf.p, blob.data(), pk.total, hipMemcpyHostToDevice));
+    h->built[dtype][role] = true;
+  }
+  *out = &t;
+  return SV_OK;
+}
+
+static int validate_paulis(const sv_pauli* p, int64_t n, int nq, const char* what) {
+  if (n < 0) return fail(SV_EINVAL, std::string(what) + ": negative count");
+  if (n > 0 && !p) return fail(SV_EINVAL, std::string(what) + ": NULL array");
+  const uint64_t lim = nq >= 64 ? ~0ull : ((uint64_t(1) << nq) - 1);
+  for (int64_t k = 0; k < n; ++k)
+    if ((p[k].x | p[k].z) & ~lim)
+      return fail(SV_EINVAL, std::string(what) + "[" + std::to_string(k) + "] acts on a qubit >= n");
+  return SV_OK;
+}
+
+static int validate_finite(const double* v, int64_t n, const char* what) {
+  if (n > 0 && !v) return fail(SV_EINVAL, std::string(what) + ": NULL array");
+  for (int64_t k = 0; k < n; ++k)
+    if (!std::isfinite(v[k])) return fail(SV_EINVAL, std::string(what) + "[" + std::to_string(k) + "] is not finite");
+  return SV_OK;
+}
+
+static int hamiltonian_make(int n, const sv_pauli* p, const double* coef, int64_t n_terms, sv_hamiltonian** out) {
+  int rc = validate_paulis(p, n_terms, n, "pauli sum");
+  if (rc) return rc;
+  rc = validate_finite(coef, n_terms, "coef");
+  if (rc) return rc;
+  std::unique_ptr<sv_hamiltonian> h(new sv_hamiltonian());
+  h->n = n;
+  h->n_terms = n_terms;
+  std::string err;
+  h->groups = build_groups(reinterpret_cast<const PauliIn*>(p), coef, n_terms, &err);
+  for (const HGroup& g : h->groups)
+    for (size_t i = 0; i < g.t_re.size(); ++i) {
+      h->coef.push_back(g.t_re[i]);
+      h->coef.push_back(g.t_im[i]);
+    }
+  if (h->coef.empty()) {
+    h->coef.push_back(0.0);
+    h->coef.push_back(0.0);
+  }
+  rc = h->coef_dev.ensure(h->coef.size() * sizeof(double), nullptr);
+  if (rc) return rc;
+  HIP_TRY(hipMemcpy(h->coef_dev.p, h->coef.data(), h->coef.size() * sizeof(double), hipMemcpyHostToDevice));
+  hipGetDevice(&h->device);
+  *out = h.release();
+  return SV_OK;
+}
+
+static void hamiltonian_destroy(sv_hamiltonian* h) {
+  if (!h) return;
+  for (auto& row : h->tilings)
+    for (auto& t : row) t.buf.release();
+  h->coef_dev.release();
+  delete h;
+}
+
+// ---------------------------------------------------------------------------
+// state
+// ---------------------------------------------------------------------------
+struct sv_state {
+  int n = 0;
+  int dtype = SV_C128;
+  void* amps = nullptr;
+  hipStream_t stream = nullptr;
+  int device = 0;
+  DevBuf scratch;      // reduction partials
+  DevBuf tables;       // per-call uploaded tables
+  DevBuf small;        // a few FP64 values
+  Staging staging;
+  sv_hamiltonian* cached_h = nullptr;  // last Pauli sum passed as raw arrays
+  uint64_t amp_count() const { return uint64_t(1) << n; }
+};
+
+struct DeviceGuard {
+  int prev = -1;
+  explicit DeviceGuard(int dev) {
+    if (hipGetDevice(&prev) == hipSuccess && prev != dev) hipSetDevice(dev);
+    else prev = -1;
+  }
+  ~DeviceGuard() {
+    if (prev >= 0) hipSetDevice(prev);
+  }
+};
+
+static int get_cached_h(sv_state* s, const sv_pauli* p, const double* coef, int64_t n_terms, sv_hamiltonian** out) {
+  int rc = validate_paulis(p, n_terms, s->n, "pauli sum");
+  if (rc) return rc;
+  rc = validate_finite(coef, n_terms, "coef");
+  if (rc) return rc;
+  uint64_t key = fnv(&n_terms, sizeof(n_terms));
+  if (n_terms) {
+    key = fnv(p, size_t(n_terms) * sizeof(sv_pauli), key);
+    key = fnv(coef, size_t(n_terms) * sizeof(double), key);
+  }
+  if (s->cached_h && s->cached_h->key == key && s->cached_h->n_terms == n_terms) {
+    *out = s->cached_h;
+    return SV_OK;
+  }
+  if (s->cached_h) {
+    HIP_TRY(hipStreamSynchronize(s->stream));
+    hamiltonian_destroy(s->cached_h);
+    s->cached_h = nullptr;
+  }
+  rc = hamiltonian_make(s->n, p, coef, n_terms, &s->cached_h);
+  if (rc) return rc;
+  s->cached_h->key = key;
+  *out = s->cached_h;
+  return SV_OK;
+}
+
+// ---------------------------------------------------------------------------
+// rotations
+// ---------------------------------------------------------------------------
+struct RotPlan {
+  std::vector<Run> runs;
+  std::vector<RunData> data;
+  std::vector<Pass> passes;
+};
+
+// grad_mode: 0 forward, 1 parameter gradient, 2 per-string gradient
+static void plan_rotations(const sv_state* s, const sv_pauli* p, const double* phi, const double* dphi,
+                           const int32_t* param, int64_t n_rot, bool reverse, int grad_mode, RotPlan& pl) {
+  const PauliIn* pin = reinterpret_cast<const PauliIn*>(p);
+  pl.runs = split_runs(pin, n_rot, param);
+  pl.data.resize(pl.runs.size());
+  for (size_t r = 0; r < pl.runs.size(); ++r)
+    pl.data[r] = build_run_data(pl.runs[r], pin, phi, dphi, reverse ? grad_mode : 0);
+  const int b = reverse ? tile_bits_two(s->dtype) : tile_bits_one(s->dtype);
+  const int c = std::min(s->dtype == 0 ? 3 : 4, s->n);
+  const int slots_per_run = grad_mode == 1 ? 1 : 0;
+  pl.passes = schedule(pl.runs, pl.data, s->n, b, c, reverse, reverse && grad_mode ? kMaxPassSlots : 0,
+                       slots_per_run);
+}
+
+// Launch a plan: forward (rev = false) or reverse with gradient partials.
+static int launch_rotations(sv_state* s, sv_state* lam, const RotPlan& pl, bool rev, int grad_mode,
+                            double* partials) {
+  const int c = std::min(s->dtype == 0 ? 3 : 4, s->n);
+  // descriptors and records of every pass, one upload
+  std::vector<RunDesc> descs;
+  std::vector<RunRec> recs;
+  std::vector<uint32_t> slot_maps;
+  struct PassOff { size_t desc0; int nruns; size_t slot0; int nslots; };
+  std::vector<PassOff> po;
+  for (const Pass& ps : pl.passes) {
+    PassOff o{descs.size(), int(ps.runs.size()), slot_maps.size(), 0};
+    int local = 0;
+    for (int ri : ps.runs) {
+      const Run& r = pl.runs[ri];
+      uint32_t slot;
+      if (ps.tile) {
+        slot = uint32_t(local);
+        if (grad_mode == 1) {
+          slot_maps.push_back(uint32_t(ri));
+          local += 1;
+        } else if (grad_mode == 2) {
+          for (int k = 0; k < r.count; ++k) slot_maps.push_back(uint32_t(r.first + k));
+          local += r.count;
+        }
+      } else {
+        slot = grad_mode == 1 ? uint32_t(ri) : uint32_t(r.first);
+      }
+      descs.push_back(make_run_desc(r, pl.data[ri], ps.qmask, slot, grad_mode == 2, recs));
+    }
+    o.nslots = local;
+    po.push_back(o);
+  }
+  if (recs.empty()) recs.push_back(RunRec{});
+  Packer pk;
+  const size_t o_desc = pk.add(descs.data(), descs.size() * sizeof(RunDesc));
+  const size_t o_recs = pk.add(recs.data(), recs.size() * sizeof(RunRec));
+  const size_t o_slot = pk.add(slot_maps.data(), slot_maps.size() * sizeof(uint32_t));
+  int rc = upload(s->staging, s->tables, pk, s->stream);
+  if (rc) return rc;
+  const RunDesc* d_desc = dptr<RunDesc>(s->tables, o_desc);
+  const RunRec* d_recs = dptr<RunRec>(s->tables, o_recs);
+  const uint32_t* d_slot = dptr<uint32_t>(s->tables, o_slot);
+  void* lam_amps = lam ? lam->amps : nullptr;
+  for (size_t i = 0; i < pl.passes.size(); ++i) {
+    const Pass& ps = pl.passes[i];
+    if (ps.tile) {
+      const FrameDesc fr = make_frame(ps.qmask, s->n, c);
+      const uint64_t n_tb = uint64_t(1) << fr.n_comp;
+      const int grid = int(std::min<uint64_t>(n_tb, rev ? kPartialStride : 2048));
+      hipError_t e;
+      if (!rev)
+        e = launch_tile_forward(s->dtype, s->amps, fr, d_desc + po[i].desc0, po[i].nruns, d_recs, n_tb, grid,
+                                s->stream);
+      else
+        e = launch_tile_reverse(s->dtype, grad_mode, s->amps, lam_amps, fr, d_desc + po[i].desc0, po[i].nruns,
+                                d_recs, d_slot + po[i].slot0, po[i].nslots, partials, kPartialStride, n_tb, grid,
+                                s->stream);
+      if (e != hipSuccess) return fail(SV_EDEVICE, std::string("tile pass launch: ") + hipGetErrorString(e));
+    } else {
+      const RunDesc& rd = descs[po[i].desc0];
+      const Run& r = pl.runs[ps.runs[0]];
+      uint64_t work;
+      if (rd.mode == kRunEnum) work = uint64_t(1) << (s->n - rd.n_sup);
+      else if (rd.mode == kRunFull) work = uint64_t(1) << (s->n - 1);
+      else work = uint64_t(1) << s->n;
+      (void)r;
+      const hipError_t e = launch_run_full(s->dtype, rev, rev ? grad_mode : 0, s->amps, lam_amps, rd, d_recs,
+                                           partials, s->n, kPartialStride, full_grid(work), s->stream);
+      if (e != hipSuccess) return fail(SV_EDEVICE, std::string("run launch: ") + hipGetErrorString(e));
+    }
+  }
+  return SV_OK;
+}
+
+// ---------------------------------------------------------------------------
+// Pauli-sum passes
+// ---------------------------------------------------------------------------
+static int dot_grid(const sv_state* s) { return full_grid(s->amp_count() / 4); }
+
+// out_dev[0] = <psi|H|psi>/<psi|psi>, out_dev[1] = <psi|psi>
+static int expect_impl(sv_state* s, sv_hamiltonian* h, double* out_dev) {
+  DevTiling* t = nullptr;
+  int rc = tiling_get(h, s->dtype, 0, &t);
+  if (rc) return rc;
+  const HTiling& ht = t->host;
+  const int T = int(ht.frames.size());
+  const uint64_t n_tb = uint64_t(1) << ht.frames[0].n_comp;
+  const uint32_t bpt = uint32_t(std::max<uint64_t>(1, std::min<uint64_t>(n_tb, std::max(1, 2048 / T))));
+  const int gfull = full_grid(s->amp_count() / 2);
+  const int gdot = dot_grid(s);
+  const size_t n_h = size_t(T) * bpt + ht.full_groups.size() * size_t(gfull);
+  const size_t need = (n_h + 2 * size_t(gdot) + 8) * sizeof(double);
+  rc = s->scratch.ensure(need, s->stream);
+  if (rc) return rc;
+  rc = s->small.ensure(16 * sizeof(double), s->stream);
+  if (rc) return rc;
+  double* part = static_cast<double*>(s->scratch.p);
+  double* sm = static_cast<double*>(s->small.p);
+  const double* d_coef = static_cast<const double*>(h->coef_dev.p);
+  hipError_t e = launch_tile_hamiltonian(
+      s->dtype, 0, s->amps, nullptr, dptr<FrameDesc>(t->buf, t->o_frames), dptr<uint32_t>(t->buf, t->o_tg),
+      dptr<GroupDesc>(t->buf, t->o_groups), dptr<SubDesc>(t->buf, t->o_subs),
+      reinterpret_cast<const double2*>(d_coef), dptr<uint64_t>(t->buf, t->o_recs), 0, T, bpt, n_tb, part,
+      s->stream);
+  if (e != hipSuccess) return fail(SV_EDEVICE, std::string("expectation tiles: ") + hipGetErrorString(e));
+  size_t off = size_t(T) * bpt;
+  for (int gi : ht.full_groups) {
+    e = launch_group_full(s->dtype, 0, s->amps, nullptr, ht.groups[gi], dptr<SubDesc>(t->buf, t->o_subs),
+                          reinterpret_cast<const double2*>(d_coef), dptr<uint64_t>(t->buf, t->o_recs), s->n,
+                          gfull, part + off, s->stream);
+    if (e != hipSuccess) return fail(SV_EDEVICE, std::string("expectation group: ") + hipGetErrorString(e));
+    off += size_t(gfull);
+  }
+  double* dpart = part + n_h;
+  e = launch_dot(s->dtype, s->amps, nullptr, s->amp_count(), gdot, dpart, s->stream);
+  if (e != hipSuccess) return fail(SV_EDEVICE, "norm launch failed");
+  HIP_TRY(launch_reduce_rows(part, 0, uint32_t(n_h), 1, sm, s->stream));
+  HIP_TRY(launch_reduce_rows(dpart + gdot, 0, uint32_t(gdot), 1, sm + 1, s->stream));
+  HIP_TRY(launch_finish_energy(sm, 1, sm + 1, out_dev, s->stream));
+  return SV_OK;
+}
+
+// lam = H psi over the two-tile tiling; energy_dev = (<psi|lam>/<psi|psi>, <psi|psi>)
+static int lambda_impl(sv_state* s, sv_state* lam, sv_hamiltonian* h, double* energy_dev) {
+  DevTiling* t = nullptr;
+  int rc = tiling_get(h, s->dtype, 1, &t);
+  if (rc) return rc;
+  const HTiling& ht = t->host;
+  const int T = int(ht.frames.size());
+  const uint64_t n_tb = uint64_t(1) << ht.frames[0].n_comp;
+  const uint32_t bpt = uint32_t(std::min<uint64_t>(n_tb, 2048));
+  const double2* d_coef = reinterpret_cast<const double2*>(h->coef_dev.p);
+  for (int tt = 0; tt < T; ++tt) {
+    hipError_t e = launch_tile_hamiltonian(
+        s->dtype, tt == 0 ? 1 : 2, s->amps, lam->amps, dptr<FrameDesc>(t->buf, t->o_frames),
+        dptr<uint32_t>(t->buf, t->o_tg), dptr<GroupDesc>(t->buf, t->o_groups), dptr<SubDesc>(t->buf, t->o_subs),
+        d_coef, dptr<uint64_t>(t->buf, t->o_recs), tt, 1, bpt, n_tb, nullptr, s->stream);
+    if (e != hipSuccess) return fail(SV_EDEVICE, std::string("lambda tile: ") + hipGetErrorString(e));
+  }
+  const int gfull = full_grid(s->amp_count() / 2);
+  for (int gi : ht.full_groups) {
+    hipError_t e = launch_group_full(s->dtype, 2, s->amps, lam->amps, ht.groups[gi], dptr<SubDesc>(t->buf, t->o_subs),
+                                     d_coef, dptr<uint64_t>(t->buf, t->o_recs), s->n, gfull, nullptr, s->stream);
+    if (e != hipSuccess) return fail(SV_EDEVICE, std::string("lambda group: ") + hipGetErrorString(e));
+  }
+  const int gdot = dot_grid(s);
+  rc = s->small.ensure(16 * sizeof(double), s->stream);
+  if (rc) return rc;
+  rc = s->scratch.ensure((2 * size_t(gdot) + 8) * sizeof(double), s->stream);
+  if (rc) return rc;
+  double* part = static_cast<double*>(s->scratch.p);
+  double* sm = static_cast<double*>(s->small.p);
+  HIP_TRY(launch_dot(s->dtype, s->amps, lam->amps, s->amp_count(), gdot, part, s->stream));
+  HIP_TRY(launch_reduce_rows(part, 0, uint32_t(gdot), 1, sm, s->stream));
+  HIP_TRY(launch_reduce_rows(part + gdot, 0, uint32_t(gdot), 1, sm + 1, s->stream));
+  HIP_TRY(launch_finish_energy(sm, 1, sm + 1, energy_dev, s->stream));
+  return SV_OK;
+}
+
+static int check_pair(sv_state* psi, sv_state* lam) {
+  if (!psi || !lam) return fail(SV_EINVAL, "NULL state");
+  if (psi == lam) return fail(SV_EINVAL, "psi and lam must be different states");
+  if (psi->n != lam->n || psi->dtype != lam->dtype) return fail(SV_EINVAL, "psi and lam differ in n or dtype");
+  if (psi->stream != lam->stream) return fail(SV_EINVAL, "psi and lam must share one stream");
+  return SV_OK;
+}
+
+// common body of the adjoint calls; param == nullptr -> per-rotation gradient
+static int adjoint_impl(sv_state* psi, sv_state* lam, sv_hamiltonian* h, const sv_pauli* rp, const double* phi,
+                        int64_t n_rot, const int32_t* param, const double* dphi, int64_t n_params,
+                        double* energy_dev, double* grad_dev) {
+  int rc = lambda_impl(psi, lam, h, energy_dev);
+  if (rc) return rc;
+  const int grad_mode = param ? 1 : 2;
+  RotPlan pl;
+  plan_rotations(psi, rp, phi, dphi, param, n_rot, true, grad_mode, pl);
+  const size_t n_slots = grad_mode == 1 ? pl.runs.size() : size_t(n_rot);
+  const size_t part_n = std::max<size_t>(n_slots, 1) * kPartialStride;
+  rc = lam->scratch.ensure((part_n + n_slots + 8) * sizeof(double), lam->stream);
+  if (rc) return rc;
+  double* partials = static_cast<double*>(lam->scratch.p);
+  double* slot_val = partials + part_n;
+  HIP_TRY(launch_fill_f64(partials, part_n, 0.0, psi->stream));
+  rc = launch_rotations(psi, lam, pl, true, grad_mode, partials);
+  if (rc) return rc;
+  if (grad_mode == 2) {
+    HIP_TRY(launch_reduce_rows(partials, kPartialStride, kPartialStride, uint32_t(n_rot), grad_dev, psi->stream));
+    return SV_OK;
+  }
+  HIP_TRY(launch_reduce_rows(partials, kPartialStride, kPartialStride, uint32_t(n_slots), slot_val, psi->stream));
+  // parameter i <- runs of parameter i, in list order
+  std::vector<uint32_t> off(size_t(n_params) + 1, 0), idx, cnt(size_t(n_params), 0);
+  for (const Run& r : pl.runs) cnt[size_t(r.param)]++;
+  for (int64_t i = 0; i < n_params; ++i) off[size_t(i) + 1] = off[size_t(i)] + cnt[size_t(i)];
+  idx.resize(off.back());
+  std::vector<uint32_t> fill(off.begin(), off.end() - 1);
+  for (size_t r = 0; r < pl.runs.size(); ++r) idx[fill[size_t(pl.runs[r].param)]++] = uint32_t(r);
+  std::vector<double> w(idx.size(), 1.0);
+  Packer pk;
+  const size_t o_off = pk.add(off.data(), off.size() * sizeof(uint32_t));
+  const size_t o_idx = pk.add(idx.data(), idx.size() * sizeof(uint32_t));
+  const size_t o_w = pk.add(w.data(), w.size() * sizeof(double));
+  // the tables buffer is still read by queued kernels; use lam's buffers
+  rc = upload(lam->staging, lam->tables, pk, lam->stream);
+  if (rc) return rc;
+  HIP_TRY(launch_gather_slots(slot_val, dptr<uint32_t>(lam->tables, o_off), dptr<uint32_t>(lam->tables, o_idx),
+                              dptr<double>(lam->tables, o_w), int(n_params), grad_dev, psi->stream));
+  return SV_OK;
+}
+
+// ---------------------------------------------------------------------------
+// C ABI
+// ---------------------------------------------------------------------------
+extern "C" {
+
+const char* sv_last_error(void) { return g_err.c_str(); }
+
+int sv_alloc(int n_qubits, int dtype, void* amps, size_t amps_bytes, void* hip_stream, sv_state** out) {
+  if (!out) return fail(SV_EINVAL, "out is NULL");
+  *out = nullptr;
+  if (n_qubits < 1 || n_qubits > SV_MAX_QUBITS) return fail(SV_EINVAL, "n_qubits out of range");
+  if (dtype != SV_C128 && dtype != SV_C64) return fail(SV_EINVAL, "unknown dtype");
+  if (!amps) return fail(SV_EINVAL, "amps is NULL");
+  if (reinterpret_cast<uintptr_t>(amps) % 16) return fail(SV_EINVAL, "amps is not 16-byte aligned");
+  const size_t need = (size_t(1) << n_qubits) * (dtype == SV_C128 ? 16 : 8);
+  if (amps_bytes < need) return fail(SV_EINVAL, "amps buffer smaller than 2^n amplitudes");
+  sv_state* s = new sv_state();
+  s->n = n_qubits;
+  s->dtype = dtype;
+  s->amps = amps;
+  s->stream = static_cast<hipStream_t>(hip_stream);
+  hipGetDevice(&s->device);
+  *out = s;
+  g_err.clear();
+  return SV_OK;
+}
+
+int sv_free(sv_state* s) {
+  if (!s) return SV_OK;
+  DeviceGuard g(s->device);
+  hipStreamSynchronize(s->stream);
+  if (s->cached_h) hamiltonian_destroy(s->cached_h);
+  s->scratch.release();
+  s->tables.release();
+  s->small.release();
+  s->staging.release();
+  delete s;
+  return SV_OK;
+}
+
+int sv_set_stream(sv_state* s, void* hip_stream) {
+  if (!s) return fail(SV_EINVAL, "NULL state");
+  DeviceGuard g(s->device);
+  HIP_TRY(hipStreamSynchronize(s->stream));
+  s->stream = static_cast<hipStream_t>(hip_stream);
+  return SV_OK;
+}
+
+int sv_prepare_hf(sv_state* s, uint64_t occ_mask) {
+  if (!s) return fail(SV_EINVAL, "NULL state");
+  if (occ_mask >> s->n) return fail(SV_EINVAL, "occ_mask has bits >= n");
+  DeviceGuard g(s->device);
+  HIP_TRY(launch_fill_basis(s->dtype, s->amps, s->amp_count(), occ_mask, s->stream));
+  return SV_OK;
+}
+
+int sv_apply_pauli_rotations(sv_state* s, const sv_pauli* p, const double* phi, int64_t n_rot) {
+  if (!s) return fail(SV_EINVAL, "NULL state");
+  int rc = validate_paulis(p, n_rot, s->n, "rotation");
+  if (rc) return rc;
+  rc = validate_finite(phi, n_rot, "phi");
+  if (rc) return rc;
+  if (n_rot == 0) return SV_OK;
+  DeviceGuard g(s->device);
+  RotPlan pl;
+  plan_rotations(s, p, phi, nullptr, nullptr, n_rot, false, 0, pl);
+  return launch_rotations(s, nullptr, pl, false, 0, nullptr);
+}
+
+int sv_expect_pauli_sum(sv_state* s, const sv_pauli* p, const double* coef, int64_t n_terms, double* out_dev) {
+  if (!s) return fail(SV_EINVAL, "NULL state");
+  if (!out_dev) return fail(SV_EINVAL, "out_dev is NULL");
+  DeviceGuard g(s->device);
+  sv_hamiltonian* h = nullptr;
+  int rc = get_cached_h(s, p, coef, n_terms, &h);
+  if (rc) return rc;
+  return expect_impl(s, h, out_dev);
+}
+
+int sv_hamiltonian_create(int n_qubits, const sv_pauli* p, const double* coef, int64_t n_terms,
+                          sv_hamiltonian** out) {
+  if (!out) return fail(SV_EINVAL, "out is NULL");
+  *out = nullptr;
+  if (n_qubits < 1 || n_qubits > SV_MAX_QUBITS) return fail(SV_EINVAL, "n_qubits out of range");
+  return hamiltonian_make(n_qubits, p, coef, n_terms, out);
+}
+
+int sv_hamiltonian_free(sv_hamiltonian* h) {
+  if (!h) return SV_OK;
+  DeviceGuard g(h->device);
+  hipDeviceSynchronize();
+  hamiltonian_destroy(h);
+  return SV_OK;
+}
+
+int sv_expect_hamiltonian(sv_state* s, const sv_hamiltonian* hc, double* out_dev) {
+  if (!s || !hc) return fail(SV_EINVAL, "NULL argument");
+  if (!out_dev) return fail(SV_EINVAL, "out_dev is NULL");
+  if (hc->n != s->n) return fail(SV_EINVAL, "Pauli sum and state differ in n");
+  DeviceGuard g(s->device);
+  return expect_impl(s, const_cast<sv_hamiltonian*>(hc), out_dev);
+}
+
+int sv_adjoint_grad(sv_state* psi, sv_state* lam, const sv_pauli* hp, const double* hcoef, int64_t n_terms,
+                    const sv_pauli* rp, const double* phi, int64_t n_rot, double* energy_dev, double* grad_dev) {
+  int rc = check_pair(psi, lam);
+  if (rc) return rc;
+  if (!energy_dev || (n_rot > 0 && !grad_dev)) return fail(SV_EINVAL, "NULL output");
+  rc = validate_paulis(rp, n_rot, psi->n, "rotation");
+  if (rc) return rc;
+  rc = validate_finite(phi, n_rot, "phi");
+  if (rc) return rc;
+  DeviceGuard g(psi->device);
+  sv_hamiltonian* h = nullptr;
+  rc = get_cached_h(psi, hp, hcoef, n_terms, &h);
+  if (rc) return rc;
+  return adjoint_impl(psi, lam, h, rp, phi, n_rot, nullptr, nullptr, 0, energy_dev, grad_dev);
+}
+
+static int check_params(const int32_t* param, const double* dphi, int64_t n_rot, int64_t n_params) {
+  if (n_params < 0) return fail(SV_EINVAL, "negative n_params");
+  if (n_rot > 0 && (!param || !dphi)) return fail(SV_EINVAL, "NULL parameter map");
+  for (int64_t k = 0; k < n_rot; ++k)
+    if (param[k] < 0 || param[k] >= n_params)
+      return fail(SV_EINVAL, "param_of_rot[" + std::to_string(k) + "] out of range");
+  return validate_finite(dphi, n_rot, "dphi_dtheta");
+}
+
+int sv_adjoint_grad_params(sv_state* psi, sv_state* lam, const sv_pauli* hp, const double* hcoef, int64_t n_terms,
+                           const sv_pauli* rp, const double* phi, int64_t n_rot, const int32_t* param,
+                           const double* dphi, int64_t n_params, double* energy_dev, double* grad_theta_dev) {
+  int rc = check_pair(psi, lam);
+  if (rc) return rc;
+  if (!energy_dev || (n_params > 0 && !grad_theta_dev)) return fail(SV_EINVAL, "NULL output");
+  rc = validate_paulis(rp, n_rot, psi->n, "rotation");
+  if (rc) return rc;
+  rc = validate_finite(phi, n_rot, "phi");
+  if (rc) return rc;
+  rc = check_params(param, dphi, n_rot, n_params);
+  if (rc) return rc;
+  DeviceGuard g(psi->device);
+  sv_hamiltonian* h = nullptr;
+  rc = get_cached_h(psi, hp, hcoef, n_terms, &h);
+  if (rc) return rc;
+  return adjoint_impl(psi, lam, h, rp, phi, n_rot, param, dphi, n_params, energy_dev, grad_theta_dev);
+}
+
+int sv_adjoint_grad_params_h(sv_state* psi, sv_state* lam, const sv_hamiltonian* hc, const sv_pauli* rp,
+                             const double* phi, int64_t n_rot, const int32_t* param, const double* dphi,
+                             int64_t n_params, double* energy_dev, double* grad_theta_dev) {
+  int rc = check_pair(psi, lam);
+  if (rc) return rc;
+  if (!hc) return fail(SV_EINVAL, "NULL Pauli sum");
+  if (hc->n != psi->n) return fail(SV_EINVAL, "Pauli sum and state differ in n");
+  if (!energy_dev || (n_params > 0 && !grad_theta_dev)) return fail(SV_EINVAL, "NULL output");
+  rc = validate_paulis(rp, n_rot, psi->n, "rotation");
+  if (rc) return rc;
+  rc = validate_finite(phi, n_rot, "phi");
+  if (rc) return rc;
+  rc = check_params(param, dphi, n_rot, n_params);
+  if (rc) return rc;
+  DeviceGuard g(psi->device);
+  return adjoint_impl(psi, lam, const_cast<sv_hamiltonian*>(hc), rp, phi, n_rot, param, dphi, n_params,
+                      energy_dev, grad_theta_dev);
+}
+
+int sv_normalize(sv_state* s, double* norm2_dev) {
+  if (!s) return fail(SV_EINVAL, "NULL state");
+  DeviceGuard g(s->device);
+  const int gdot = dot_grid(s);
+  int rc = s->scratch.ensure((2 * size_t(gdot) + 8) * sizeof(double), s->stream);
+  if (rc) return rc;
+  rc = s->small.ensure(16 * sizeof(double), s->stream);
+  if (rc) return rc;
+  double* part = static_cast<double*>(s->scratch.p);
+  double* sm = static_cast<double*>(s->small.p);
+  HIP_TRY(launch_dot(s->dtype, s->amps, nullptr, s->amp_count(), gdot, part, s->stream));
+  HIP_TRY(launch_reduce_rows(part + gdot, 0, uint32_t(gdot), 1, sm + 2, s->stream));
+  HIP_TRY(launch_scale(s->dtype, s->amps, s->amp_count(), sm + 2, s->stream));
+  if (norm2_dev) HIP_TRY(hipMemcpyAsync(norm2_dev, sm + 2, sizeof(double), hipMemcpyDeviceToDevice, s->stream));
+  return SV_OK;
+}
+
+int sv_gather_amplitudes(sv_state* s, const uint64_t* idx, int64_t count, double* out_dev) {
+  if (!s) return fail(SV_EINVAL, "NULL state");
+  if (count < 0 || (count > 0 && (!idx || !out_dev))) return fail(SV_EINVAL, "bad arguments");
+  for (int64_t i = 0; i < count; ++i)
+    if (idx[i] >> s->n) return fail(SV_EINVAL, "index out of range");
+  if (count == 0) return SV_OK;
+  DeviceGuard g(s->device);
+  Packer pk;
+  const size_t o = pk.add(idx, size_t(count) * sizeof(uint64_t));
+  int rc = upload(s->staging, s->tables, pk, s->stream);
+  if (rc) return rc;
+  HIP_TRY(launch_gather_amps(s->dtype, s->amps, dptr<uint64_t>(s->tables, o), count, out_dev, s->stream));
+  return SV_OK;
+}
+
+}  // extern "C"

@@ -1,0 +1,53 @@
+// Host-callable launchers of the gfx950 kernels (implemented in kernels.hip).
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <cstdint>
+
+#include "q2sv_internal.h"
+
+namespace q2sv {
+
+// Tile widths (frame bits) per amplitude type and pass kind, chosen so the
+// tiles fill at most 128 KiB of the 160 KiB LDS of a gfx950 compute unit.
+constexpr int kTileFwdC128 = 13, kTileFwdC64 = 14;   // one state tile
+constexpr int kTileTwoC128 = 12, kTileTwoC64 = 13;   // two tiles (psi and lam)
+constexpr int kTileThreads = 512;
+constexpr int kMaxPassSlots = 256;                   // gradient slots per reverse tile pass
+constexpr uint32_t kPartialStride = 1024;            // max blocks of a gradient pass
+
+hipError_t launch_fill_basis(int dtype, void* psi, uint64_t n_amp, uint64_t k, hipStream_t st);
+hipError_t launch_run_full(int dtype, bool rev, int grad, void* psi, void* lam, const RunDesc& run,
+                           const RunRec* recs, double* partials, int n, uint32_t nb_stride, int grid,
+                           hipStream_t st);
+hipError_t launch_tile_forward(int dtype, void* psi, const FrameDesc& fr, const RunDesc* runs, int n_runs,
+                               const RunRec* recs, uint64_t n_tb, int grid, hipStream_t st);
+hipError_t launch_tile_reverse(int dtype, int grad, void* psi, void* lam, const FrameDesc& fr,
+                               const RunDesc* runs, int n_runs, const RunRec* recs,
+                               const uint32_t* slot_map, int n_slots, double* partials, uint32_t nb_stride,
+                               uint64_t n_tb, int grid, hipStream_t st);
+hipError_t launch_tile_hamiltonian(int dtype, int mode, const void* psi, void* lam, const FrameDesc* frames,
+                                   const uint32_t* tile_groups, const GroupDesc* groups, const SubDesc* subs,
+                                   const double2* coef, const uint64_t* recbits, int tile_first,
+                                   int n_tiles_launch, uint32_t blocks_per_tile, uint64_t n_tb,
+                                   double* partials, hipStream_t st);
+hipError_t launch_group_full(int dtype, int mode, const void* psi, void* lam, const GroupDesc& g,
+                             const SubDesc* subs, const double2* coef, const uint64_t* recbits, int n,
+                             int grid, double* partials, hipStream_t st);
+hipError_t launch_dot(int dtype, const void* a, const void* b, uint64_t n_amp, int grid, double* partials,
+                      hipStream_t st);
+hipError_t launch_reduce_rows(const double* in, uint64_t stride, uint32_t len, uint32_t rows, double* out,
+                              hipStream_t st);
+hipError_t launch_finish_energy(const double* sums, int nh, const double* norm, double* out, hipStream_t st);
+hipError_t launch_gather_slots(const double* slot_val, const uint32_t* off, const uint32_t* idx,
+                               const double* weight, int n_out, double* out, hipStream_t st);
+hipError_t launch_fill_f64(double* p, uint64_t n, double v, hipStream_t st);
+hipError_t launch_scale(int dtype, void* psi, uint64_t n_amp, const double* norm2, hipStream_t st);
+hipError_t launch_gather_amps(int dtype, const void* psi, const uint64_t* idx, int64_t count, double* out,
+                              hipStream_t st);
+
+inline int tile_bits_one(int dtype) { return dtype == 0 ? kTileFwdC128 : kTileFwdC64; }
+inline int tile_bits_two(int dtype) { return dtype == 0 ? kTileTwoC128 : kTileTwoC64; }
+
+}  // namespace q2sv

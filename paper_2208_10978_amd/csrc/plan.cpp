@@ -1,0 +1,440 @@
+// Host-side planning (see plan.h).
+#include "plan.h"
+
+#include <algorithm>
+#include <cmath>
+#include <map>
+
+namespace q2sv {
+
+// ---------------------------------------------------------------------------
+// runs
+// ---------------------------------------------------------------------------
+std::vector<Run> split_runs(const PauliIn* p, int64_t n_rot, const int32_t* param) {
+  std::vector<Run> out;
+  Run cur;
+  for (int64_t k = 0; k < n_rot; ++k) {
+    const uint64_t x = p[k].x, z = p[k].z;
+    const int32_t pk = param ? param[k] : -1;
+    bool join = cur.count > 0 && cur.count < kMaxRunStrings && x == cur.x && pk == cur.param;
+    if (join) {
+      const uint64_t d = z ^ cur.z0;
+      // same-x strings commute iff |x & (z_k ^ z_0)| is even
+      if (popc(x & d) & 1) join = false;
+      else if (popc(cur.dmask | d) > kMaxSup) join = false;
+    }
+    if (join) {
+      cur.dmask |= z ^ cur.z0;
+      ++cur.count;
+    } else {
+      if (cur.count) out.push_back(cur);
+      cur = Run();
+      cur.first = k;
+      cur.count = 1;
+      cur.x = x;
+      cur.z0 = z;
+      cur.param = pk;
+    }
+  }
+  if (cur.count) out.push_back(cur);
+  return out;
+}
+
+static std::vector<int> bit_list(uint64_t m) {
+  std::vector<int> v;
+  while (m) {
+    v.push_back(__builtin_ctzll(m));
+    m &= m - 1;
+  }
+  return v;
+}
+
+RunData build_run_data(const Run& r, const PauliIn* p, const double* phi, const double* dphi, int want_grad) {
+  RunData d;
+  const int K = r.count;
+  d.omega0 = uint32_t(popc(r.x & r.z0) & 3);
+  // eps_k(m') = (omega_k / omega_0) (-1)^{|m' & (z_k ^ z_0)|}; the ratio is +/-1
+  std::vector<int> neg(K), dpat(K);
+  d.pat_glob = bit_list(r.dmask);
+  const int L = int(d.pat_glob.size());
+  for (int k = 0; k < K; ++k) {
+    const uint64_t zk = p[r.first + k].z;
+    const int diff = (popc(r.x & zk) - popc(r.x & r.z0)) & 3;  // 0 or 2
+    neg[k] = diff == 2;
+    dpat[k] = int(compress(zk ^ r.z0, r.dmask));
+    if (neg[k]) d.str_neg |= uint8_t(1u << k);
+    d.str_dpat[k] = uint8_t(dpat[k]);
+  }
+  auto entry = [&](unsigned pat, RunRec& e) {
+    double ph = 0.0, a = 0.0;
+    for (int k = 0; k < K; ++k) {
+      const bool minus = neg[k] ^ (popc(uint64_t(pat & dpat[k])) & 1);
+      ph += minus ? -phi[r.first + k] : phi[r.first + k];
+      if (dphi) a += minus ? -dphi[r.first + k] : dphi[r.first + k];
+    }
+    e.c = std::cos(0.5 * ph);
+    e.s = std::sin(0.5 * ph);
+    e.a = a;
+    e.eps_neg = 0;
+    for (int k = 0; k < K; ++k)
+      if (neg[k] ^ (popc(uint64_t(pat & dpat[k])) & 1)) e.eps_neg |= 1u << k;
+  };
+  d.sup_glob = bit_list(r.x);
+  const int S = int(d.sup_glob.size());
+  if (r.x == 0) {
+    d.mode = kRunDiag;
+    d.recs.resize(size_t(1) << L);
+    for (unsigned pat = 0; pat < (1u << L); ++pat) entry(pat, d.recs[pat]);
+    return d;
+  }
+  const bool enum_ok = S <= kMaxSup && (r.dmask & ~r.x) == 0;
+  if (!enum_ok) {
+    d.mode = kRunFull;
+    d.recs.resize(size_t(1) << L);
+    for (unsigned pat = 0; pat < (1u << L); ++pat) entry(pat, d.recs[pat]);
+    return d;
+  }
+  d.mode = kRunEnum;
+  const int pivot_rank = S - 1;  // the pivot is the highest support bit
+  for (unsigned v = 0; v < (1u << S); ++v) {
+    if (!((v >> pivot_rank) & 1u)) continue;  // m' has the pivot bit set
+    uint64_t bits = 0;
+    for (int j = 0; j < S; ++j) bits |= uint64_t((v >> j) & 1u) << d.sup_glob[j];
+    const unsigned pat = unsigned(compress(bits, r.dmask));
+    RunRec e{};
+    entry(pat, e);
+    e.bits = bits;
+    const bool identity = (e.c == 1.0 && e.s == 0.0);
+    bool keep;
+    if (want_grad == 2) keep = true;
+    else if (want_grad == 1) keep = !identity || e.a != 0.0;
+    else keep = !identity;
+    if (keep) d.recs.push_back(e);
+  }
+  return d;
+}
+
+FrameDesc make_frame(uint64_t qmask, int n, int c) {
+  FrameDesc f{};
+  int j = 0;
+  for (int q = 0; q < n; ++q)
+    if ((qmask >> q) & 1ull) f.q[j++] = uint8_t(q);
+  f.b = uint8_t(j);
+  f.c = uint8_t(c);
+  int k = 0;
+  for (int q = 0; q < n; ++q)
+    if (!((qmask >> q) & 1ull)) f.comp[k++] = uint8_t(q);
+  f.n_comp = uint8_t(k);
+  return f;
+}
+
+static int local_pos(int g, uint64_t qmask) { return popc(qmask & ((uint64_t(1) << g) - 1)); }
+
+RunDesc make_run_desc(const Run& r, const RunData& d, uint64_t qmask, uint32_t slot, int per_string,
+                      std::vector<RunRec>& recs_out) {
+  RunDesc rd{};
+  rd.x_loc = compress(r.x, qmask);
+  rd.z0_loc = compress(r.z0 & qmask, qmask);
+  rd.z0_out = r.z0 & ~qmask;
+  rd.omega0 = d.omega0;
+  rd.slot = slot;
+  rd.rec_off = uint32_t(recs_out.size());
+  rd.n_rec = uint16_t(d.recs.size());
+  rd.mode = d.mode;
+  rd.n_str = uint8_t(r.count);
+  rd.str_neg = d.str_neg;
+  for (int k = 0; k < kMaxRunStrings; ++k) rd.str_dpat[k] = d.str_dpat[k];
+  rd.per_string = uint8_t(per_string);
+  if (r.x) rd.pivot = uint8_t(local_pos(highest_bit(r.x), qmask));
+  rd.n_sup = uint8_t(d.mode == kRunEnum ? d.sup_glob.size() : 0);
+  if (d.mode == kRunEnum)
+    for (size_t j = 0; j < d.sup_glob.size(); ++j) rd.sup_pos[j] = uint8_t(local_pos(d.sup_glob[j], qmask));
+  rd.n_pat = uint8_t(d.mode == kRunEnum ? 0 : d.pat_glob.size());
+  if (d.mode != kRunEnum)
+    for (size_t j = 0; j < d.pat_glob.size(); ++j) {
+      const int g = d.pat_glob[j];
+      rd.pat_pos[j] = ((qmask >> g) & 1ull) ? uint8_t(local_pos(g, qmask)) : uint8_t(64 + g);
+    }
+  for (const RunRec& e : d.recs) {
+    RunRec o = e;
+    if (d.mode == kRunEnum) o.bits = compress(e.bits, qmask);
+    recs_out.push_back(o);
+  }
+  return rd;
+}
+
+double run_line_fraction(const RunData& d, int c) {
+  if (d.mode != kRunEnum) return 1.0;
+  const int S = int(d.sup_glob.size());
+  int low = 0;
+  for (int g : d.sup_glob)
+    if (g < c) ++low;
+  // pairs touched: n_rec of 2^(S-1) patterns; lines hold the low support bits
+  double f = double(d.recs.size()) / double(1u << (S - 1)) * double(1u << low);
+  return f < 1.0 ? f : 1.0;
+}
+
+std::vector<Pass> schedule(const std::vector<Run>& runs, const std::vector<RunData>& data, int n, int b, int c,
+                           bool reverse, int max_slots_per_pass, int slots_per_run) {
+  std::vector<Pass> out;
+  const int R = int(runs.size());
+  const uint64_t all = n >= 64 ? ~0ull : ((uint64_t(1) << n) - 1);
+  if (R == 0) return out;
+  if (n <= b) {
+    // the whole state is one tile
+    Pass ps;
+    ps.tile = true;
+    ps.qmask = all;
+    int slots = 0;
+    for (int i = 0; i < R; ++i) {
+      const int ri = reverse ? R - 1 - i : i;
+      const int need = slots_per_run ? slots_per_run : runs[ri].count;
+      if (max_slots_per_pass && slots + need > max_slots_per_pass) {
+        out.push_back(ps);
+        ps.runs.clear();
+        slots = 0;
+      }
+      ps.runs.push_back(ri);
+      slots += need;
+    }
+    out.push_back(ps);
+    return out;
+  }
+  const uint64_t low = (uint64_t(1) << c) - 1;
+  int i = 0;
+  while (i < R) {
+    uint64_t q = low;
+    std::vector<int> seg;
+    int slots = 0;
+    double alone = 0.0;
+    while (i < R) {
+      const int ri = reverse ? R - 1 - i : i;
+      const uint64_t nq = q | runs[ri].x;
+      const int need = slots_per_run ? slots_per_run : runs[ri].count;
+      if (popc(nq) > b) break;
+      if (max_slots_per_pass && slots + need > max_slots_per_pass) break;
+      q = nq;
+      slots += need;
+      seg.push_back(ri);
+      alone += run_line_fraction(data[ri], c);
+      ++i;
+    }
+    if (seg.empty()) {  // support wider than a tile: whole-state pass
+      const int ri = reverse ? R - 1 - i : i;
+      Pass ps;
+      ps.tile = false;
+      ps.qmask = all;
+      ps.runs.push_back(ri);
+      out.push_back(ps);
+      ++i;
+      continue;
+    }
+    if (seg.size() >= 2 && alone > 1.0) {
+      // fill the frame up to b qubits (extra qubits only shrink the grid)
+      for (int qq = 0; qq < n && popc(q) < b; ++qq) q |= uint64_t(1) << qq;
+      Pass ps;
+      ps.tile = true;
+      ps.qmask = q;
+      ps.runs = seg;
+      out.push_back(ps);
+    } else {
+      for (int ri : seg) {
+        Pass ps;
+        ps.tile = false;
+        ps.qmask = all;
+        ps.runs.push_back(ri);
+        out.push_back(ps);
+      }
+    }
+  }
+  return out;
+}
+
+// ---------------------------------------------------------------------------
+// grouped Pauli sums
+// ---------------------------------------------------------------------------
+std::vector<HGroup> build_groups(const PauliIn* p, const double* coef, int64_t n_terms, std::string* err) {
+  std::map<uint64_t, std::vector<int64_t>> by_x;
+  for (int64_t t = 0; t < n_terms; ++t) by_x[p[t].x].push_back(t);
+  std::vector<HGroup> out;
+  out.reserve(by_x.size());
+  for (auto& kv : by_x) {
+    HGroup g;
+    g.x = kv.first;
+    g.diag = g.x == 0;
+    g.sup = bit_list(g.x);
+    const int S = int(g.sup.size());
+    g.enumerated = !g.diag && S <= kMaxSup;
+    const uint64_t smask = g.enumerated ? g.x : 0;
+    // subgroups by w = z outside the enumerated support
+    std::map<uint64_t, std::vector<int64_t>> by_w;
+    for (int64_t t : kv.second) by_w[p[t].z & ~smask].push_back(t);
+    std::vector<uint64_t> recs;
+    if (g.enumerated) {
+      for (unsigned v = 0; v < (1u << S); ++v) {
+        if (!((v >> (S - 1)) & 1u)) continue;
+        uint64_t bits = 0;
+        for (int j = 0; j < S; ++j) bits |= uint64_t((v >> j) & 1u) << g.sup[j];
+        recs.push_back(bits);
+      }
+    } else {
+      recs.push_back(0);
+    }
+    const int NR = int(recs.size());
+    std::vector<uint64_t> ws;
+    std::vector<double> re, im;
+    double tmax = 0.0;
+    for (auto& wv : by_w) {
+      ws.push_back(wv.first);
+      for (int r = 0; r < NR; ++r) {
+        // T_w[r] = sum_t c_t i^{|x & z_t|} (-1)^{|m' & z_t^S|}
+        double a = 0.0, b = 0.0;
+        for (int64_t t : wv.second) {
+          const int ph = popc(g.x & p[t].z) & 3;
+          const int sg = popc(recs[r] & p[t].z & smask) & 1;
+          double cr = 0.0, ci = 0.0;
+          const double cv = sg ? -coef[t] : coef[t];
+          switch (ph) {
+            case 0: cr = cv; break;
+            case 1: ci = cv; break;
+            case 2: cr = -cv; break;
+            default: ci = -cv; break;
+          }
+          a += cr;
+          b += ci;
+        }
+        re.push_back(a);
+        im.push_back(b);
+        tmax = std::max(tmax, std::hypot(a, b));
+      }
+    }
+    // drop records whose entries vanish in every subgroup (exact zeros up to
+    // the rounding of the term sums: below 1e-14 of the largest entry)
+    const double tol = 1e-14 * tmax;
+    std::vector<int> keep;
+    for (int r = 0; r < NR; ++r) {
+      bool nz = !g.enumerated;
+      for (size_t w = 0; w < ws.size() && !nz; ++w)
+        if (std::hypot(re[w * NR + r], im[w * NR + r]) > tol) nz = true;
+      if (nz) keep.push_back(r);
+    }
+    if (keep.empty()) continue;  // the group is zero
+    g.w = ws;
+    for (int r : keep) g.rec_v.push_back(recs[r]);
+    if (!g.enumerated) g.rec_v.clear();
+    for (size_t w = 0; w < ws.size(); ++w)
+      for (int r : keep) {
+        g.t_re.push_back(re[w * NR + r]);
+        g.t_im.push_back(im[w * NR + r]);
+      }
+    out.push_back(std::move(g));
+  }
+  (void)err;
+  return out;
+}
+
+static GroupDesc make_group_desc(const HGroup& g, uint64_t qmask, uint32_t sub_off, uint32_t rec_off) {
+  GroupDesc d{};
+  d.x_loc = compress(g.x, qmask);
+  d.n_sub = uint32_t(g.w.size());
+  d.sub_off = sub_off;
+  d.rec_off = rec_off;
+  d.n_rec = uint16_t(g.n_rec());
+  d.enumerated = g.enumerated;
+  d.is_diag = g.diag;
+  d.n_sup = uint8_t(g.enumerated ? g.sup.size() : 0);
+  if (g.x) d.pivot = uint8_t(local_pos(highest_bit(g.x), qmask));
+  if (g.enumerated)
+    for (size_t j = 0; j < g.sup.size(); ++j) d.sup_pos[j] = uint8_t(local_pos(g.sup[j], qmask));
+  return d;
+}
+
+static void append_group(HTiling& t, const HGroup& g, uint32_t coef_off, uint64_t qmask) {
+  const uint32_t sub_off = uint32_t(t.subs.size());
+  const uint32_t rec_off = uint32_t(t.recbits.size());
+  t.groups.push_back(make_group_desc(g, qmask, sub_off, rec_off));
+  const int NR = g.n_rec();
+  for (size_t w = 0; w < g.w.size(); ++w) {
+    SubDesc s{};
+    s.w_loc = compress(g.w[w] & qmask, qmask);
+    s.w_out = g.w[w] & ~qmask;
+    s.coef_off = coef_off + uint32_t(w * NR);
+    t.subs.push_back(s);
+  }
+  for (uint64_t v : g.rec_v) t.recbits.push_back(compress(v, qmask));
+}
+
+HTiling build_tiling(const std::vector<HGroup>& gs, const std::vector<uint32_t>& coef_off, int n, int b, int c) {
+  HTiling t;
+  t.b = b;
+  t.c = c;
+  const uint64_t all = n >= 64 ? ~0ull : ((uint64_t(1) << n) - 1);
+  const uint64_t low = (uint64_t(1) << c) - 1;
+  const int G = int(gs.size());
+  std::vector<int> tile_of(G, -1);
+  if (n <= b) {
+    t.tile_q.push_back(all);
+    for (int g = 0; g < G; ++g) tile_of[g] = 0;
+  } else {
+    std::vector<int> todo;
+    for (int g = 0; g < G; ++g)
+      if (!gs[g].diag && popc(gs[g].x | low) <= b) todo.push_back(g);
+    while (!todo.empty()) {
+      // seed with the widest uncovered support, then add the qubit that
+      // completes most uncovered groups (ties: most partial progress)
+      int seed = todo[0];
+      for (int g : todo)
+        if (popc(gs[g].x & ~low) > popc(gs[seed].x & ~low)) seed = g;
+      uint64_t q = low | gs[seed].x;
+      while (popc(q) < b) {
+        std::vector<double> score(n, 0.0);
+        for (int g : todo) {
+          const uint64_t miss = gs[g].x & ~q;
+          const int k = popc(miss);
+          if (k == 0) continue;
+          const double v = k == 1 ? 1e6 : 1.0 / k;
+          uint64_t mm = miss;
+          while (mm) {
+            score[__builtin_ctzll(mm)] += v;
+            mm &= mm - 1;
+          }
+        }
+        int best = -1;
+        for (int qq = 0; qq < n; ++qq)
+          if (!((q >> qq) & 1ull) && (best < 0 || score[qq] > score[best])) best = qq;
+        q |= uint64_t(1) << best;
+      }
+      const int tid = int(t.tile_q.size());
+      t.tile_q.push_back(q);
+      std::vector<int> rest;
+      for (int g : todo) {
+        if ((gs[g].x & ~q) == 0) tile_of[g] = tid;
+        else rest.push_back(g);
+      }
+      todo.swap(rest);
+    }
+    if (t.tile_q.empty()) {
+      uint64_t q = low;
+      for (int qq = c; qq < n && popc(q) < b; ++qq) q |= uint64_t(1) << qq;
+      t.tile_q.push_back(q);
+    }
+    for (int g = 0; g < G; ++g)
+      if (gs[g].diag) tile_of[g] = 0;
+  }
+  const int T = int(t.tile_q.size());
+  for (int tt = 0; tt < T; ++tt) t.frames.push_back(make_frame(t.tile_q[tt], n, c));
+  for (int tt = 0; tt < T; ++tt) {
+    t.tile_groups.push_back(uint32_t(t.groups.size()));
+    for (int g = 0; g < G; ++g)
+      if (tile_of[g] == tt) append_group(t, gs[g], coef_off[g], t.tile_q[tt]);
+  }
+  t.tile_groups.push_back(uint32_t(t.groups.size()));
+  for (int g = 0; g < G; ++g)
+    if (tile_of[g] < 0) {
+      t.full_groups.push_back(int(t.groups.size()));
+      append_group(t, gs[g], coef_off[g], all);
+    }
+  return t;
+}
+
+}  // namespace q2sv

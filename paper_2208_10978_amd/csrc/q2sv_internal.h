@@ -1,0 +1,115 @@
+// Internal descriptors shared by the host planner and the gfx950 kernels.
+//
+// Vocabulary.
+//   frame   A pass works on blocks of 2^B amplitudes.  The block's qubits are
+//           a sorted set Q (frame-local bit j is global qubit Q[j]); the other
+//           n - B qubits are fixed per block and form its base index.  Q
+//           always holds the lowest c qubits, so a row of 2^c amplitudes is
+//           contiguous in memory.  The identity frame (B = n, base 0) is the
+//           whole state.
+//   run     Consecutive strings of a rotation list with one x mask that
+//           commute.  On each amplitude pair (m, m ^ x) every string of the
+//           run acts as +/- the same 2x2 operator, so the run is one rotation
+//           by an angle Phi that depends on m only through a few "pattern"
+//           bits (Section 5.1, Eq. 11: the strings of one UCC excitation form
+//           such a run).
+//   group   All terms of a Pauli sum that share one x mask (Section 3.1,
+//           Eq. 1-2): one read of the pair (psi[m], psi[m ^ x]) serves every
+//           z-variant.
+//   record  An "active" value of the partner index m' = m ^ x on the support
+//           of x: the pair is processed only when the run (or group) does not
+//           act as the identity (or zero) there.  Pairs are enumerated per
+//           record, so skipped patterns cost nothing.
+#pragma once
+
+#include <cstdint>
+
+namespace q2sv {
+
+constexpr int kMaxSup = 6;          // support bits enumerated per run / group
+constexpr int kMaxRunStrings = 8;   // strings fused into one run
+constexpr int kMaxFrameBits = 14;   // largest LDS tile (2^14 complex64)
+
+enum RunMode : uint8_t {
+  kRunEnum = 0,   // pattern bits inside the support; enumerate active records
+  kRunFull = 1,   // every pair; per-pair pattern lookup into a 2^L table
+  kRunDiag = 2,   // x == 0: a phase on every amplitude; 2^L table
+};
+
+// One run of commuting same-x rotations, in the coordinates of its frame.
+struct alignas(16) RunDesc {
+  uint64_t x_loc;      // flip mask (frame-local bits)
+  uint64_t z0_loc;     // reference string's z, frame-local bits
+  uint64_t z0_out;     // reference string's z, global bits outside the frame
+  uint32_t omega0;     // reference phase i^{|x & z0|}, as a power of i
+  uint32_t slot;       // first gradient slot of the run
+  uint32_t rec_off;    // first record (kRunEnum) or table entry (kRunFull/Diag)
+  uint16_t n_rec;      // number of records, or 2^L table entries
+  uint8_t mode;        // RunMode
+  uint8_t n_str;       // strings fused in the run
+  uint8_t str_neg;     // bit k: omega_k / omega_0 = -1            (kRunFull/Diag)
+  uint8_t n_sup;       // support bits (kRunEnum)
+  uint8_t pivot;       // frame-local highest bit of x             (kRunFull)
+  uint8_t n_pat;       // pattern bits L                           (kRunFull/Diag)
+  uint8_t sup_pos[kMaxSup];        // frame-local support positions, ascending
+  uint8_t pat_pos[kMaxSup];        // pattern bit j: frame-local position, or
+                                   // 64 + global position when outside the frame
+  uint8_t str_dpat[kMaxRunStrings];  // per string: pattern mask of z_k ^ z0
+  uint8_t per_string;  // gradient slots are per string (else one per run)
+  uint8_t pad[7];
+};
+
+// A record (kRunEnum) or table entry (kRunFull/Diag) of a run:
+//   c, s  cos(Phi/2), sin(Phi/2) of the fused rotation on this pattern
+//   a     sum_k dphi_k/dtheta * eps_k (parameter-gradient weight)
+//   bits  frame-local bits of m' on the support (kRunEnum only)
+//   eps_neg  bit k: eps_k = -1 on this pattern (kRunEnum only)
+struct alignas(16) RunRec {
+  uint64_t bits;
+  uint32_t eps_neg;
+  uint32_t pad0;
+  double c;
+  double s;
+  double a;
+  double pad1;
+};
+
+// One group of a Pauli sum in frame coordinates:
+//   G(m) = sum_w (-1)^{|m' & w|} T_w[r],   m' = m ^ x,
+// where r is the active record of m' (its support bits) when the group is
+// enumerated, and 0 otherwise.  (H_x psi)[m] = G(m) psi[m'].
+struct alignas(16) GroupDesc {
+  uint64_t x_loc;      // flip mask (frame-local)
+  uint32_t n_sub;      // w subgroups
+  uint32_t sub_off;    // first subgroup
+  uint32_t rec_off;    // first record: bits of m' on the support
+  uint16_t n_rec;      // records (1 when not enumerated)
+  uint8_t enumerated;  // support bits enumerated (records are patterns)
+  uint8_t is_diag;     // x == 0
+  uint8_t n_sup;       // support bits (enumerated groups)
+  uint8_t pivot;       // frame-local highest bit of x (non-enumerated groups)
+  uint8_t sup_pos[kMaxSup];
+  uint8_t pad[8];
+};
+
+// w of one subgroup; its values T_w[r] for every record r of the group sit at
+// coef[coef_off + r] (complex: re, im).
+struct alignas(16) SubDesc {
+  uint64_t w_loc;
+  uint64_t w_out;
+  uint32_t coef_off;
+  uint32_t pad0;
+  uint64_t pad1;
+};
+
+// Frame of a tile pass.
+struct alignas(16) FrameDesc {
+  uint8_t q[kMaxFrameBits];   // global position of frame-local bit j (q[j] = j for j < c)
+  uint8_t b;                  // B
+  uint8_t c;                  // contiguous low qubits
+  uint8_t comp[48];           // global positions of the other qubits, ascending
+  uint8_t n_comp;             // n - B
+  uint8_t pad[15];
+};
+
+}  // namespace q2sv

@@ -1,0 +1,150 @@
+"""Device-resident objects over the C ABI and the UCC energy autograd Function.
+
+``StateVector``   a 2^n complex torch tensor on the GPU bound to an sv_state
+``Hamiltonian``   a Pauli sum grouped and uploaded once (sv_hamiltonian)
+``UCCSDEvaluator`` energy and energy+gradient of the Trotterised UCCSD state
+                  (Eq. 10-11) for a fixed Hamiltonian: HF preparation, the
+                  rotation sweep, the grouped expectation or lambda = H psi
+                  with the reverse sweep (Algorithm 1)
+``UCCEnergy``     torch.autograd.Function whose backward returns dE/dtheta
+                  computed by the reverse sweep
+"""
+from __future__ import annotations
+
+import numpy as np
+import torch
+
+from . import binding as B
+from .problem import PauliSum, RotationList
+
+_DT = {"c128": (B.SV_C128, torch.complex128), "c64": (B.SV_C64, torch.complex64)}
+
+
+class StateVector:
+    def __init__(self, n_qubits: int, dtype: str = "c128", device: str = "cuda", stream=None):
+        code, tdt = _DT[dtype]
+        self.n = int(n_qubits)
+        self.dtype = dtype
+        self.amps = torch.empty(1 << self.n, dtype=tdt, device=device)
+        self.handle = B.sv_alloc(self.n, code, self.amps, stream)
+
+    def prepare_hf(self, occ_mask: int):
+        B.sv_prepare_hf(self.handle, occ_mask)
+
+    def apply_rotations(self, x, z, phi):
+        B.sv_apply_pauli_rotations(self.handle, x, z, phi)
+
+    def expect(self, h: "Hamiltonian", out=None) -> torch.Tensor:
+        out = out if out is not None else torch.empty(2, dtype=torch.float64, device=self.amps.device)
+        B.sv_expect_hamiltonian(self.handle, h.handle, out)
+        return out
+
+    def expect_terms(self, x, z, c, out=None) -> torch.Tensor:
+        out = out if out is not None else torch.empty(2, dtype=torch.float64, device=self.amps.device)
+        B.sv_expect_pauli_sum(self.handle, x, z, c, out)
+        return out
+
+    def normalize(self, out=None):
+        B.sv_normalize(self.handle, out)
+
+    def amplitudes(self, idx) -> torch.Tensor:
+        out = torch.empty(2 * len(idx), dtype=torch.float64, device=self.amps.device)
+        B.sv_gather_amplitudes(self.handle, idx, out)
+        return out
+
+    def set_stream(self, stream):
+        B.sv_set_stream(self.handle, stream)
+
+    def free(self):
+        if self.handle is not None:
+            B.sv_free(self.handle)
+            self.handle = None
+
+    def __del__(self):
+        try:
+            self.free()
+        except Exception:
+            pass
+
+
+class Hamiltonian:
+    def __init__(self, ps: PauliSum):
+        self.n = ps.n_qubits
+        self.terms = ps
+        self.handle = B.sv_hamiltonian_create(ps.n_qubits, ps.x, ps.z, ps.c)
+
+    def free(self):
+        if self.handle is not None:
+            B.sv_hamiltonian_free(self.handle)
+            self.handle = None
+
+    def __del__(self):
+        try:
+            self.free()
+        except Exception:
+            pass
+
+
+class UCCSDEvaluator:
+    """E(theta) = <HF| U(theta)^dag H U(theta) |HF> and its gradient.
+
+    ``renormalize`` rescales psi to unit norm (FP64 norm) after the forward
+    sweep; it is on by default for complex64 amplitudes."""
+
+    def __init__(self, ham: PauliSum, rot: RotationList, n_electrons: int, dtype: str = "c128",
+                 stream=None, renormalize=None):
+        self.n = ham.n_qubits
+        self.rot = rot
+        self.hf = (1 << n_electrons) - 1
+        self.h = Hamiltonian(ham)
+        self.psi = StateVector(self.n, dtype, stream=stream)
+        self.lam = StateVector(self.n, dtype, stream=stream)
+        self.renormalize = (dtype == "c64") if renormalize is None else renormalize
+        dev = self.psi.amps.device
+        self.energy_buf = torch.empty(2, dtype=torch.float64, device=dev)
+        self.grad_buf = torch.empty(rot.n_params, dtype=torch.float64, device=dev)
+
+    def forward_state(self, theta):
+        phi = self.rot.angles(np.asarray(theta, dtype=np.float64))
+        self.psi.prepare_hf(self.hf)
+        self.psi.apply_rotations(self.rot.x, self.rot.z, phi)
+        if self.renormalize:
+            self.psi.normalize()
+        return phi
+
+    def energy(self, theta) -> torch.Tensor:
+        """Device tensor [E, <psi|psi>] (E is the Rayleigh quotient)."""
+        self.forward_state(theta)
+        return self.psi.expect(self.h, self.energy_buf)
+
+    def energy_and_grad(self, theta):
+        phi = self.forward_state(theta)
+        B.sv_adjoint_grad_params_h(self.psi.handle, self.lam.handle, self.h.handle, self.rot.x, self.rot.z, phi,
+                                   self.rot.param, self.rot.dphi_dtheta, self.rot.n_params, self.energy_buf,
+                                   self.grad_buf)
+        return self.energy_buf, self.grad_buf
+
+    def free(self):
+        for o in (self.psi, self.lam, self.h):
+            o.free()
+
+
+class UCCEnergy(torch.autograd.Function):
+    """``E = UCCEnergy.apply(theta, evaluator)``; theta is a float64 tensor.
+    With gradients enabled the forward pass runs the reverse sweep as well and
+    keeps dE/dtheta for the backward pass."""
+
+    @staticmethod
+    def forward(ctx, theta, evaluator):
+        th = theta.detach().to("cpu", torch.float64).numpy()
+        if ctx.needs_input_grad[0]:
+            e, g = evaluator.energy_and_grad(th)
+            ctx.save_for_backward(g.clone())
+        else:
+            e = evaluator.energy(th)
+        return e[0].clone().to(theta.device)
+
+    @staticmethod
+    def backward(ctx, grad_out):
+        (g,) = ctx.saved_tensors
+        return (grad_out.to(g.device) * g).to(grad_out.device), None

@@ -1,0 +1,190 @@
+"""Host-side problem builders: the Jordan-Wigner Pauli-sum Hamiltonian and
+the Trotterised UCCSD rotation list, as packed ``uint64`` masks.
+
+Conventions (the paper leaves them open; Sections 3.1-3.2, 5.1):
+
+* qubit q is bit q of a basis index; spin orbital ``(p, alpha)`` is qubit
+  ``2p`` and ``(p, beta)`` is ``2p + 1``; the Hartree-Fock determinant fills
+  the lowest ``n_e`` qubits (Eq. 6), so its index is ``2^n_e - 1``;
+* the Hamiltonian of Eq. 3 with chemist's-notation integrals is
+  ``sum h_pq a+_ps a_qs + 1/2 sum (pq|rs) a+_ps a+_rt a_st a_qs``;
+* JW: ``a_j = Z_{<j} (X_j + i Y_j)/2``;
+* UCCSD (Eq. 10-11): singles ``a+_a a_i`` then doubles ``a+_a a+_b a_j a_i``
+  (i < j occupied, a < b virtual, spin projection conserved), each list in
+  lexicographic order; ``tau - tau^dag = i sum_j c_j P_j`` and the factor
+  ``exp(theta (tau - tau^dag))`` becomes the commuting rotations
+  ``R(P_j, phi_j)``, ``phi_j = -2 c_j theta``, listed by increasing z.
+
+The Pauli algebra here works on whole arrays of strings at once: a ladder
+word of length L expands into 2^L strings, multiplied factor by factor with
+the symplectic phase rule, then equal strings are merged.
+"""
+from __future__ import annotations
+
+import itertools
+from dataclasses import dataclass
+
+import numpy as np
+
+
+def _popc(a: np.ndarray) -> np.ndarray:
+    return np.bitwise_count(a).astype(np.int64)
+
+
+@dataclass
+class PauliSum:
+    """``H = sum_t c_t P_t`` with ``P = i^{|x&z|} X^x Z^z`` and real c."""
+    n_qubits: int
+    x: np.ndarray  # uint64
+    z: np.ndarray  # uint64
+    c: np.ndarray  # float64
+
+    def __len__(self):
+        return int(self.x.shape[0])
+
+    def truncated(self, threshold: float) -> "PauliSum":
+        keep = (np.abs(self.c) > threshold) | ((self.x == 0) & (self.z == 0))
+        return PauliSum(self.n_qubits, self.x[keep], self.z[keep], self.c[keep])
+
+    @property
+    def n_groups(self) -> int:
+        return int(np.unique(self.x).shape[0])
+
+    def one_norm(self) -> float:
+        return float(np.abs(self.c).sum())
+
+
+@dataclass
+class RotationList:
+    """Rotations ``R(P_k, phi_k) = exp(-i phi_k P_k / 2)`` applied in order;
+    ``phi_k = dphi_dtheta[k] * theta[param[k]]``."""
+    n_qubits: int
+    x: np.ndarray
+    z: np.ndarray
+    param: np.ndarray        # int32
+    dphi_dtheta: np.ndarray  # float64
+    n_params: int
+
+    def __len__(self):
+        return int(self.x.shape[0])
+
+    def angles(self, theta) -> np.ndarray:
+        theta = np.asarray(theta, dtype=np.float64)
+        return self.dphi_dtheta * theta[self.param]
+
+
+def _expand_words(qubits: np.ndarray, create: np.ndarray, coef: np.ndarray):
+    """Pauli expansion of ladder words.  ``qubits``/``create`` are (W, L);
+    word w is ``op[w,0] op[w,1] ... op[w,L-1]``.  Each factor is
+    ``(X_j Z_{<j} -/+ i Y_j Z_{<j}) / 2`` (creation takes the minus sign).
+
+    The running product is kept as ``i^ph X^x Z^z``; ``Y_j = i X_j Z_j`` adds
+    one to ph and moving ``Z^z`` past ``X^{x'}`` adds ``2 |z & x'|``.  At the
+    end ``X^x Z^z = i^{-|x & z|} P`` gives the canonical string.
+    Returns x, z (uint64) and complex coefficients of the W * 2^L strings."""
+    W, L = qubits.shape
+    one = np.uint64(1)
+    x = np.zeros(W, dtype=np.uint64)
+    z = np.zeros(W, dtype=np.uint64)
+    ph = np.zeros(W, dtype=np.int64)
+    amp = coef.astype(np.complex128) * (0.5 ** L)
+    for t in range(L):
+        q = qubits[:, t].astype(np.uint64)
+        bit = one << q
+        low = bit - one
+        fx = np.concatenate([bit, bit])
+        fz = np.concatenate([low, low | bit])
+        fph = np.concatenate([np.zeros(len(q), np.int64), np.ones(len(q), np.int64)])
+        famp = np.concatenate([np.ones(len(q)), np.where(create[:, t], -1j, 1j)])
+        x, z, ph, amp = (np.concatenate([x, x]), np.concatenate([z, z]),
+                         np.concatenate([ph, ph]), np.concatenate([amp, amp]) * famp)
+        ph = ph + fph + 2 * _popc(z & fx)
+        x, z = x ^ fx, z ^ fz
+        qubits = np.concatenate([qubits, qubits])
+        create = np.concatenate([create, create])
+    ph = ph - _popc(x & z)
+    return x, z, amp * (1j ** (ph % 4))
+
+
+def _merge(x, z, c, n_qubits, drop_tol):
+    order = np.lexsort((z, x))
+    x, z, c = x[order], z[order], c[order]
+    new = np.ones(x.shape[0], dtype=bool)
+    new[1:] = (x[1:] != x[:-1]) | (z[1:] != z[:-1])
+    idx = np.cumsum(new) - 1
+    summed = np.zeros(int(idx[-1]) + 1 if len(idx) else 0, dtype=np.complex128)
+    np.add.at(summed, idx, c)
+    ux, uz = x[new], z[new]
+    return ux, uz, summed
+
+
+def jordan_wigner(h: np.ndarray, eri: np.ndarray, drop_tol: float = 1e-12) -> PauliSum:
+    """JW Pauli sum of Eq. 3 for spatial integrals ``h`` (M, M) and chemist's
+    ``eri`` (M, M, M, M) on ``n = 2M`` qubits."""
+    M = h.shape[0]
+    n = 2 * M
+    if n > 64:
+        raise ValueError("at most 64 qubits")
+    xs, zs, cs = [], [], []
+    # one-body words a+_{ps} a_{qs}
+    pq = np.array([(p, q, s) for p in range(M) for q in range(M) for s in (0, 1) if h[p, q] != 0.0])
+    if len(pq):
+        qub = np.stack([2 * pq[:, 0] + pq[:, 2], 2 * pq[:, 1] + pq[:, 2]], axis=1)
+        cre = np.tile(np.array([True, False]), (len(pq), 1))
+        x, z, c = _expand_words(qub, cre, h[pq[:, 0], pq[:, 1]])
+        xs.append(x); zs.append(z); cs.append(c)
+    # two-body words a+_{ps} a+_{rt} a_{st} a_{qs}, weight (pq|rs)/2
+    p, q, r, s = (a.ravel() for a in np.meshgrid(*(np.arange(M),) * 4, indexing="ij"))
+    v = eri[p, q, r, s]
+    nz = v != 0.0
+    p, q, r, s, v = p[nz], q[nz], r[nz], s[nz], v[nz]
+    for sg, tg in itertools.product((0, 1), repeat=2):
+        P, Q, R, S = 2 * p + sg, 2 * q + sg, 2 * r + tg, 2 * s + tg
+        ok = (P != R) & (Q != S)
+        qub = np.stack([P[ok], R[ok], S[ok], Q[ok]], axis=1)
+        cre = np.tile(np.array([True, True, False, False]), (int(ok.sum()), 1))
+        x, z, c = _expand_words(qub, cre, 0.5 * v[ok])
+        xs.append(x); zs.append(z); cs.append(c)
+    x, z, c = _merge(np.concatenate(xs), np.concatenate(zs), np.concatenate(cs), n, drop_tol)
+    if np.abs(c.imag).max(initial=0.0) > 1e-10:
+        raise AssertionError("JW Hamiltonian has a non-real coefficient")
+    keep = np.abs(c.real) > drop_tol
+    return PauliSum(n, x[keep], z[keep], c.real[keep].copy())
+
+
+def uccsd_excitations(n_qubits: int, n_electrons: int):
+    occ = range(n_electrons)
+    vir = range(n_electrons, n_qubits)
+    singles = [(i, a) for i in occ for a in vir if i % 2 == a % 2]
+    doubles = [(i, j, a, b)
+               for i, j in itertools.combinations(occ, 2)
+               for a, b in itertools.combinations(vir, 2)
+               if sorted((i % 2, j % 2)) == sorted((a % 2, b % 2))]
+    return singles, doubles
+
+
+def uccsd_rotations(n_qubits: int, n_electrons: int) -> RotationList:
+    singles, doubles = uccsd_excitations(n_qubits, n_electrons)
+    xs, zs, ps, ds = [], [], [], []
+    for idx, exc in enumerate(singles + doubles):
+        if len(exc) == 2:
+            i, a = exc
+            word = [(a, True), (i, False)]
+        else:
+            i, j, a, b = exc
+            word = [(a, True), (b, True), (j, False), (i, False)]
+        dag = [(q, not cr) for q, cr in reversed(word)]
+        qub = np.array([[q for q, _ in word], [q for q, _ in dag]])
+        cre = np.array([[cr for _, cr in word], [cr for _, cr in dag]])
+        x, z, c = _expand_words(qub, cre, np.array([1.0, -1.0]))
+        x, z, c = _merge(x, z, c, n_qubits, 0.0)
+        keep = np.abs(c) > 1e-14
+        x, z, c = x[keep], z[keep], c[keep]
+        if np.abs(c.real).max(initial=0.0) > 1e-14:
+            raise AssertionError("excitation generator is not anti-Hermitian")
+        order = np.argsort(z, kind="stable")
+        xs.append(x[order]); zs.append(z[order])
+        ps.append(np.full(len(order), idx, dtype=np.int32))
+        ds.append(-2.0 * c.imag[order])
+    return RotationList(n_qubits, np.concatenate(xs), np.concatenate(zs), np.concatenate(ps),
+                        np.concatenate(ds), len(singles) + len(doubles))

@@ -53,3 +53,12 @@ def test_strings_are_hermitian_involutions():
         m = pauli.dense(x, z, 3)
         assert np.allclose(m, m.conj().T)
         assert np.allclose(m @ m, np.eye(8))
+
+
+def test_random_pauli_sum_refuses_impossible_counts():
+    import pytest
+    from workloads import random_pauli_sum
+    with pytest.raises(ValueError):
+        random_pauli_sum(4, 256, 0)
+    x, z, c = random_pauli_sum(4, 255, 0)
+    assert len(set(zip(x.tolist(), z.tolist()))) == 255

@@ -13,6 +13,8 @@ set when the factor on qubit q is X or Y, bit q of ``z`` when it is Z or Y.
 """
 from __future__ import annotations
 
+from math import comb
+
 import numpy as np
 
 # the 8 X/Y patterns on 4 qubits with an odd number of Y (1 = Y, 0 = X)
@@ -39,6 +41,9 @@ def random_rotations(n_qubits: int, count: int, seed: int, amplitude: float = 0.
 
 
 def random_pauli_sum(n_qubits: int, count: int, seed: int):
+    available = sum(comb(n_qubits, w) * 3 ** w for w in range(1, min(4, n_qubits) + 1))
+    if count > available:
+        raise ValueError(f"only {available} distinct strings of weight <= 4 on {n_qubits} qubits")
     rng = np.random.default_rng(seed)
     seen = set()
     xs, zs, cs = [], [], []
