@@ -138,6 +138,16 @@ int sv_normalize(sv_state *s, double *norm2_dev);
  * 2 * count values (re, im); used to check single amplitudes at scale. */
 int sv_gather_amplitudes(sv_state *s, const uint64_t *idx, int64_t count, double *out_dev);
 
+/* Kernel timing (Section 4.2 reports time per iteration; this gives it per
+ * kernel class).  sv_profile_begin starts recording a HIP event pair around
+ * every kernel the library launches, on the stream it is launched on, with
+ * the algorithmic bytes the launch must move (state reads and writes, not
+ * counting cache effects).  sv_profile_end waits for the device, writes a
+ * JSON object {class: {"launches", "ms", "bytes"}} into buf (NUL-terminated,
+ * truncated to buflen) and stops recording.  Process-wide; not re-entrant. */
+int sv_profile_begin(void);
+int sv_profile_end(char *buf, size_t buflen);
+
 /* Message of the last failed call on this host thread ("" if none). */
 const char *sv_last_error(void);
 

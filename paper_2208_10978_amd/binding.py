@@ -54,6 +54,8 @@ def lib():
             "sv_adjoint_grad_params_h": [_vp, _vp, _vp, _vp, _vp, _i64, _vp, _vp, _i64, _vp, _vp],
             "sv_normalize": [_vp, _vp],
             "sv_gather_amplitudes": [_vp, _vp, _i64, _vp],
+            "sv_profile_begin": [],
+            "sv_profile_end": [ctypes.c_char_p, _c.c_size_t],
         }
         for name, args in sig.items():
             f = getattr(L, name)
@@ -69,7 +71,7 @@ EXPORTED = (
     "sv_alloc", "sv_free", "sv_set_stream", "sv_prepare_hf", "sv_apply_pauli_rotations",
     "sv_expect_pauli_sum", "sv_adjoint_grad", "sv_adjoint_grad_params", "sv_hamiltonian_create",
     "sv_hamiltonian_free", "sv_expect_hamiltonian", "sv_adjoint_grad_params_h", "sv_normalize",
-    "sv_gather_amplitudes", "sv_last_error",
+    "sv_gather_amplitudes", "sv_profile_begin", "sv_profile_end", "sv_last_error",
 )
 
 
@@ -205,3 +207,14 @@ def sv_normalize(s, norm2_dev=None):
 def sv_gather_amplitudes(s, idx, out_dev):
     ix = np.ascontiguousarray(idx, dtype=np.uint64)
     _check(lib().sv_gather_amplitudes(s, _ptr(ix), len(ix), _dev(out_dev)))
+
+
+def sv_profile_begin():
+    _check(lib().sv_profile_begin())
+
+
+def sv_profile_end() -> dict:
+    import json
+    buf = ctypes.create_string_buffer(1 << 16)
+    _check(lib().sv_profile_end(buf, len(buf)))
+    return json.loads(buf.value.decode())

@@ -7,6 +7,7 @@
 #include <cmath>
 #include <cstring>
 #include <memory>
+#include <mutex>
 #include <string>
 #include <vector>
 
@@ -145,6 +146,60 @@ int full_grid(uint64_t work) {
   return int(std::min<uint64_t>(std::max<uint64_t>(want, 1), kPartialStride));
 }
 
+// ---------------------------------------------------------------------------
+// opt-in kernel timing: a HIP event pair per launch on its stream
+// ---------------------------------------------------------------------------
+enum ProfClass {
+  kPFill, kPRunFull, kPTileFwd, kPTileRev, kPTileHExp, kPTileHLam, kPGroupFull, kPDot, kPSmall, kPCount
+};
+const char* kProfName[kPCount] = {"k_fill_basis", "k_run_full", "k_tile_forward", "k_tile_reverse",
+                                  "k_tile_hamiltonian_expect", "k_tile_hamiltonian_lambda", "k_group_full",
+                                  "k_dot", "small"};
+
+struct ProfRec {
+  int cls;
+  hipEvent_t a, b;
+  double bytes;
+};
+
+struct Profiler {
+  std::mutex mu;
+  bool on = false;
+  std::vector<ProfRec> recs;
+  std::vector<hipEvent_t> pool;
+  hipEvent_t get() {
+    if (!pool.empty()) {
+      hipEvent_t e = pool.back();
+      pool.pop_back();
+      return e;
+    }
+    hipEvent_t e = nullptr;
+    hipEventCreate(&e);
+    return e;
+  }
+};
+Profiler g_prof;
+
+struct ProfScope {
+  hipStream_t st;
+  int cls;
+  double bytes;
+  hipEvent_t a = nullptr;
+  ProfScope(hipStream_t s, int c, double b) : st(s), cls(c), bytes(b) {
+    if (!g_prof.on) return;
+    std::lock_guard<std::mutex> lk(g_prof.mu);
+    a = g_prof.get();
+    hipEventRecord(a, st);
+  }
+  ~ProfScope() {
+    if (!a) return;
+    std::lock_guard<std::mutex> lk(g_prof.mu);
+    hipEvent_t b = g_prof.get();
+    hipEventRecord(b, st);
+    g_prof.recs.push_back({cls, a, b, bytes});
+  }
+};
+
 }  // namespace
 
 // ---------------------------------------------------------------------------
@@ -265,6 +320,7 @@ struct sv_state {
   Staging staging;
   sv_hamiltonian* cached_h = nullptr;  // last Pauli sum passed as raw arrays
   uint64_t amp_count() const { return uint64_t(1) << n; }
+  double bytes() const { return double(amp_count()) * (dtype == SV_C128 ? 16.0 : 8.0); }
 };
 
 struct DeviceGuard {
@@ -379,6 +435,7 @@ static int launch_rotations(sv_state* s, sv_state* lam, const RotPlan& pl, bool 
       const uint64_t n_tb = uint64_t(1) << fr.n_comp;
       const int grid = int(std::min<uint64_t>(n_tb, rev ? kPartialStride : 2048));
       hipError_t e;
+      ProfScope prof(s->stream, rev ? kPTileRev : kPTileFwd, (rev ? 4.0 : 2.0) * s->bytes());
       if (!rev)
         e = launch_tile_forward(s->dtype, s->amps, fr, d_desc + po[i].desc0, po[i].nruns, d_recs, n_tb, grid,
                                 s->stream);
@@ -395,6 +452,9 @@ static int launch_rotations(sv_state* s, sv_state* lam, const RotPlan& pl, bool 
       else if (rd.mode == kRunFull) work = uint64_t(1) << (s->n - 1);
       else work = uint64_t(1) << s->n;
       (void)r;
+      const double amp = s->bytes() / double(s->amp_count());
+      const double touched = rd.mode == kRunDiag ? double(work) : 2.0 * double(work);
+      ProfScope prof(s->stream, kPRunFull, touched * amp * 2.0 * (rev ? 2.0 : 1.0));
       const hipError_t e = launch_run_full(s->dtype, rev, rev ? grad_mode : 0, s->amps, lam_amps, rd, d_recs,
                                            partials, s->n, kPartialStride, full_grid(work), s->stream);
       if (e != hipSuccess) return fail(SV_EDEVICE, std::string("run launch: ") + hipGetErrorString(e));
@@ -407,6 +467,17 @@ static int launch_rotations(sv_state* s, sv_state* lam, const RotPlan& pl, bool 
 // Pauli-sum passes
 // ---------------------------------------------------------------------------
 static int dot_grid(const sv_state* s) { return full_grid(s->amp_count() / 4); }
+
+// algorithmic bytes of one whole-state group pass: the amplitude pairs it
+// reads (and, building lambda, the lambda pairs it reads and writes)
+static double group_bytes(const sv_state* s, const GroupDesc& g, bool lambda) {
+  const double amp = s->bytes() / double(s->amp_count());
+  double touched;
+  if (g.is_diag) touched = double(s->amp_count());
+  else if (g.enumerated) touched = 2.0 * double(g.n_rec) * double(uint64_t(1) << (s->n - g.n_sup));
+  else touched = double(s->amp_count());
+  return touched * amp * (lambda ? 3.0 : 1.0);
+}
 
 // out_dev[0] = <psi|H|psi>/<psi|psi>, out_dev[1] = <psi|psi>
 static int expect_impl(sv_state* s, sv_hamiltonian* h, double* out_dev) {
@@ -428,14 +499,19 @@ static int expect_impl(sv_state* s, sv_hamiltonian* h, double* out_dev) {
   double* part = static_cast<double*>(s->scratch.p);
   double* sm = static_cast<double*>(s->small.p);
   const double* d_coef = static_cast<const double*>(h->coef_dev.p);
-  hipError_t e = launch_tile_hamiltonian(
+  hipError_t e;
+  {
+  ProfScope prof(s->stream, kPTileHExp, double(T) * s->bytes());
+  e = launch_tile_hamiltonian(
       s->dtype, 0, s->amps, nullptr, dptr<FrameDesc>(t->buf, t->o_frames), dptr<uint32_t>(t->buf, t->o_tg),
       dptr<GroupDesc>(t->buf, t->o_groups), dptr<SubDesc>(t->buf, t->o_subs),
       reinterpret_cast<const double2*>(d_coef), dptr<uint64_t>(t->buf, t->o_recs), 0, T, bpt, n_tb, part,
       s->stream);
+  }
   if (e != hipSuccess) return fail(SV_EDEVICE, std::string("expectation tiles: ") + hipGetErrorString(e));
   size_t off = size_t(T) * bpt;
   for (int gi : ht.full_groups) {
+    ProfScope prof(s->stream, kPGroupFull, group_bytes(s, ht.groups[gi], false));
     e = launch_group_full(s->dtype, 0, s->amps, nullptr, ht.groups[gi], dptr<SubDesc>(t->buf, t->o_subs),
                           reinterpret_cast<const double2*>(d_coef), dptr<uint64_t>(t->buf, t->o_recs), s->n,
                           gfull, part + off, s->stream);
@@ -443,8 +519,12 @@ static int expect_impl(sv_state* s, sv_hamiltonian* h, double* out_dev) {
     off += size_t(gfull);
   }
   double* dpart = part + n_h;
+  {
+  ProfScope prof(s->stream, kPDot, s->bytes());
   e = launch_dot(s->dtype, s->amps, nullptr, s->amp_count(), gdot, dpart, s->stream);
+  }
   if (e != hipSuccess) return fail(SV_EDEVICE, "norm launch failed");
+  ProfScope prof(s->stream, kPSmall, 0.0);
   HIP_TRY(launch_reduce_rows(part, 0, uint32_t(n_h), 1, sm, s->stream));
   HIP_TRY(launch_reduce_rows(dpart + gdot, 0, uint32_t(gdot), 1, sm + 1, s->stream));
   HIP_TRY(launch_finish_energy(sm, 1, sm + 1, out_dev, s->stream));
@@ -462,6 +542,7 @@ static int lambda_impl(sv_state* s, sv_state* lam, sv_hamiltonian* h, double* en
   const uint32_t bpt = uint32_t(std::min<uint64_t>(n_tb, 2048));
   const double2* d_coef = reinterpret_cast<const double2*>(h->coef_dev.p);
   for (int tt = 0; tt < T; ++tt) {
+    ProfScope prof(s->stream, kPTileHLam, (tt == 0 ? 2.0 : 3.0) * s->bytes());
     hipError_t e = launch_tile_hamiltonian(
         s->dtype, tt == 0 ? 1 : 2, s->amps, lam->amps, dptr<FrameDesc>(t->buf, t->o_frames),
         dptr<uint32_t>(t->buf, t->o_tg), dptr<GroupDesc>(t->buf, t->o_groups), dptr<SubDesc>(t->buf, t->o_subs),
@@ -470,6 +551,7 @@ static int lambda_impl(sv_state* s, sv_state* lam, sv_hamiltonian* h, double* en
   }
   const int gfull = full_grid(s->amp_count() / 2);
   for (int gi : ht.full_groups) {
+    ProfScope prof(s->stream, kPGroupFull, group_bytes(s, ht.groups[gi], true));
     hipError_t e = launch_group_full(s->dtype, 2, s->amps, lam->amps, ht.groups[gi], dptr<SubDesc>(t->buf, t->o_subs),
                                      d_coef, dptr<uint64_t>(t->buf, t->o_recs), s->n, gfull, nullptr, s->stream);
     if (e != hipSuccess) return fail(SV_EDEVICE, std::string("lambda group: ") + hipGetErrorString(e));
@@ -481,7 +563,11 @@ static int lambda_impl(sv_state* s, sv_state* lam, sv_hamiltonian* h, double* en
   if (rc) return rc;
   double* part = static_cast<double*>(s->scratch.p);
   double* sm = static_cast<double*>(s->small.p);
-  HIP_TRY(launch_dot(s->dtype, s->amps, lam->amps, s->amp_count(), gdot, part, s->stream));
+  {
+    ProfScope prof(s->stream, kPDot, 2.0 * s->bytes());
+    HIP_TRY(launch_dot(s->dtype, s->amps, lam->amps, s->amp_count(), gdot, part, s->stream));
+  }
+  ProfScope prof(s->stream, kPSmall, 0.0);
   HIP_TRY(launch_reduce_rows(part, 0, uint32_t(gdot), 1, sm, s->stream));
   HIP_TRY(launch_reduce_rows(part + gdot, 0, uint32_t(gdot), 1, sm + 1, s->stream));
   HIP_TRY(launch_finish_energy(sm, 1, sm + 1, energy_dev, s->stream));
@@ -511,9 +597,13 @@ static int adjoint_impl(sv_state* psi, sv_state* lam, sv_hamiltonian* h, const s
   if (rc) return rc;
   double* partials = static_cast<double*>(lam->scratch.p);
   double* slot_val = partials + part_n;
-  HIP_TRY(launch_fill_f64(partials, part_n, 0.0, psi->stream));
+  {
+    ProfScope prof(psi->stream, kPSmall, 0.0);
+    HIP_TRY(launch_fill_f64(partials, part_n, 0.0, psi->stream));
+  }
   rc = launch_rotations(psi, lam, pl, true, grad_mode, partials);
   if (rc) return rc;
+  ProfScope prof(psi->stream, kPSmall, 0.0);
   if (grad_mode == 2) {
     HIP_TRY(launch_reduce_rows(partials, kPartialStride, kPartialStride, uint32_t(n_rot), grad_dev, psi->stream));
     return SV_OK;
@@ -545,6 +635,54 @@ static int adjoint_impl(sv_state* psi, sv_state* lam, sv_hamiltonian* h, const s
 extern "C" {
 
 const char* sv_last_error(void) { return g_err.c_str(); }
+
+int sv_profile_begin(void) {
+  std::lock_guard<std::mutex> lk(g_prof.mu);
+  g_prof.on = true;
+  return SV_OK;
+}
+
+int sv_profile_end(char* buf, size_t buflen) {
+  std::vector<ProfRec> recs;
+  {
+    std::lock_guard<std::mutex> lk(g_prof.mu);
+    g_prof.on = false;
+    recs.swap(g_prof.recs);
+  }
+  HIP_TRY(hipDeviceSynchronize());
+  double ms[kPCount] = {}, bytes[kPCount] = {};
+  long count[kPCount] = {};
+  for (const ProfRec& r : recs) {
+    float t = 0.f;
+    if (hipEventElapsedTime(&t, r.a, r.b) == hipSuccess) ms[r.cls] += t;
+    bytes[r.cls] += r.bytes;
+    count[r.cls] += 1;
+  }
+  {
+    std::lock_guard<std::mutex> lk(g_prof.mu);
+    for (const ProfRec& r : recs) {
+      g_prof.pool.push_back(r.a);
+      g_prof.pool.push_back(r.b);
+    }
+  }
+  std::string out = "{";
+  bool first = true;
+  for (int c = 0; c < kPCount; ++c) {
+    if (!count[c]) continue;
+    char tmp[256];
+    snprintf(tmp, sizeof(tmp), "%s\"%s\": {\"launches\": %ld, \"ms\": %.6f, \"bytes\": %.1f}", first ? "" : ", ",
+             kProfName[c], count[c], ms[c], bytes[c]);
+    out += tmp;
+    first = false;
+  }
+  out += "}";
+  if (buf && buflen) {
+    const size_t k = std::min(buflen - 1, out.size());
+    std::memcpy(buf, out.data(), k);
+    buf[k] = 0;
+  }
+  return SV_OK;
+}
 
 int sv_alloc(int n_qubits, int dtype, void* amps, size_t amps_bytes, void* hip_stream, sv_state** out) {
   if (!out) return fail(SV_EINVAL, "out is NULL");
@@ -591,6 +729,7 @@ int sv_prepare_hf(sv_state* s, uint64_t occ_mask) {
   if (!s) return fail(SV_EINVAL, "NULL state");
   if (occ_mask >> s->n) return fail(SV_EINVAL, "occ_mask has bits >= n");
   DeviceGuard g(s->device);
+  ProfScope prof(s->stream, kPFill, s->bytes());
   HIP_TRY(launch_fill_basis(s->dtype, s->amps, s->amp_count(), occ_mask, s->stream));
   return SV_OK;
 }
@@ -715,7 +854,11 @@ int sv_normalize(sv_state* s, double* norm2_dev) {
   if (rc) return rc;
   double* part = static_cast<double*>(s->scratch.p);
   double* sm = static_cast<double*>(s->small.p);
-  HIP_TRY(launch_dot(s->dtype, s->amps, nullptr, s->amp_count(), gdot, part, s->stream));
+  {
+    ProfScope prof(s->stream, kPDot, s->bytes());
+    HIP_TRY(launch_dot(s->dtype, s->amps, nullptr, s->amp_count(), gdot, part, s->stream));
+  }
+  ProfScope prof(s->stream, kPSmall, 2.0 * s->bytes());
   HIP_TRY(launch_reduce_rows(part + gdot, 0, uint32_t(gdot), 1, sm + 2, s->stream));
   HIP_TRY(launch_scale(s->dtype, s->amps, s->amp_count(), sm + 2, s->stream));
   if (norm2_dev) HIP_TRY(hipMemcpyAsync(norm2_dev, sm + 2, sizeof(double), hipMemcpyDeviceToDevice, s->stream));
