@@ -153,7 +153,19 @@ def generator_matrix(exc, basis) -> scipy.sparse.csr_matrix:
     return _matrix_from_words([(word, 1.0), (dag, -1.0)], np.asarray(basis, dtype=np.int64))
 
 
-def ucc_state_fermionic(n_qubits: int, n_electrons: int, theta, basis=None):
+def checked_order(n_qubits: int, n_electrons: int, order=None):
+    """The excitation sequence to apply: lexicographic by default, or a given
+    sequence, which must be a permutation of the UCCSD excitation set."""
+    singles, doubles = uccsd_excitations(n_qubits, n_electrons)
+    if order is None:
+        return singles + doubles
+    order = [tuple(int(v) for v in e) for e in order]
+    if len(order) != len(singles) + len(doubles) or set(order) != set(singles + doubles):
+        raise ValueError("the excitation sequence is not a permutation of the UCCSD excitations")
+    return order
+
+
+def ucc_state_fermionic(n_qubits: int, n_electrons: int, theta, basis=None, order=None):
     """``prod_i exp(theta_i (tau_i - tau_i^dag)) |HF>`` in excitation order,
     each factor a sparse matrix exponential.  Returns (basis, coefficients)."""
     if basis is None:
@@ -161,8 +173,7 @@ def ucc_state_fermionic(n_qubits: int, n_electrons: int, theta, basis=None):
     basis = np.asarray(basis, dtype=np.int64)
     psi = np.zeros(len(basis), dtype=np.complex128)
     psi[int(np.nonzero(basis == hf_index(n_electrons))[0][0])] = 1.0
-    singles, doubles = uccsd_excitations(n_qubits, n_electrons)
-    for exc, th in zip(singles + doubles, theta):
+    for exc, th in zip(checked_order(n_qubits, n_electrons, order), theta):
         g = generator_matrix(exc, basis)
         psi = scipy.sparse.linalg.expm_multiply(float(th) * g, psi)
     return basis, psi
@@ -230,16 +241,17 @@ def truncate(terms: dict, threshold: float) -> dict:
     return {k: c for k, c in terms.items() if abs(c) > threshold or k == (0, 0)}
 
 
-def uccsd_rotations(n_qubits: int, n_electrons: int):
-    """Rotation list of the Trotterised UCCSD circuit (Eq. 11).
+def uccsd_rotations(n_qubits: int, n_electrons: int, order=None):
+    """Rotation list of the Trotterised UCCSD circuit (Eq. 11), excitations in
+    the given sequence (lexicographic by default); parameter i is the i-th
+    excitation of the sequence.
 
     ``tau - tau^dag = i sum_j c_j P_j`` with real c_j, so
     ``exp(theta (tau - tau^dag)) = prod_j R(P_j, -2 c_j theta)``; the strings
     of one excitation commute and are listed by increasing z mask.
     Returns a list of ``(x, z, param_index, dphi_dtheta)``."""
-    singles, doubles = uccsd_excitations(n_qubits, n_electrons)
     out = []
-    for idx, exc in enumerate(singles + doubles):
+    for idx, exc in enumerate(checked_order(n_qubits, n_electrons, order)):
         word = excitation_ops(exc)
         dag = [(q, not c) for q, c in reversed(word)]
         poly = word_pauli(word)

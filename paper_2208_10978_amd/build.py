@@ -9,7 +9,7 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 ROOT = os.path.dirname(HERE)
 CSRC = os.path.join(HERE, "csrc")
 LIB = os.path.join(HERE, "libq2sv.so")
-SOURCES = ["api.hip", "kernels.hip", "plan.cpp"]
+SOURCES = ["api.hip", "kernels_sweep.hip", "kernels_pauli_sum.hip", "kernels_util.hip", "plan.cpp"]
 
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 # packed FP32 instructions are disabled for all device code

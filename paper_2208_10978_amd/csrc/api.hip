@@ -208,39 +208,48 @@ struct ProfScope {
 struct DevTiling {
   HTiling host;
   DevBuf buf;
-  size_t o_frames = 0, o_tg = 0, o_groups = 0, o_subs = 0, o_recs = 0;
+  size_t o_frames = 0, o_boff = 0, o_blob = 0, o_groups = 0, o_subs = 0, o_recs = 0, o_coef = 0;
 };
 
 struct sv_hamiltonian {
   int n = 0;
   int64_t n_terms = 0;
   uint64_t key = 0;
-  std::vector<HGroup> groups;
-  std::vector<double> coef;  // (re, im) pairs
-  DevBuf coef_dev;
-  DevTiling tilings[2][2];   // [dtype][role: 0 one-tile (expectation), 1 two-tile (lambda)]
+  std::vector<HGroup> groups;        // non-diagonal groups
+  std::vector<uint64_t> diag_z;      // diagonal (x = 0) terms
+  std::vector<double> diag_c;
+  DevTiling tilings[2][2];           // [dtype][role: 0 expectation, 1 lambda]
   bool built[2][2] = {{false, false}, {false, false}};
+  DevBuf diag_dev;                   // resident diagonal d[m], FP64, 2^n entries
+  bool diag_built = false;
   int device = 0;
 };
+
+static int num_cus() {
+  static int cus = 0;
+  if (!cus) {
+    int dev = 0;
+    hipGetDevice(&dev);
+    if (hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess || cus <= 0) cus = 256;
+  }
+  return cus;
+}
 
 static int tiling_get(sv_hamiltonian* h, int dtype, int role, DevTiling** out) {
   DevTiling& t = h->tilings[dtype][role];
   if (!h->built[dtype][role]) {
-    std::vector<uint32_t> coef_off(h->groups.size());
-    uint32_t off = 0;
-    for (size_t g = 0; g < h->groups.size(); ++g) {
-      coef_off[g] = off;
-      off += uint32_t(h->groups[g].w.size() * h->groups[g].n_rec());
-    }
-    const int b = role == 0 ? tile_bits_one(dtype) : tile_bits_two(dtype);
+    const int b = role == 0 ? tile_bits_one(dtype) : tile_bits_lambda(dtype);
     const int c = std::min(dtype == 0 ? 3 : 4, h->n);
-    t.host = build_tiling(h->groups, coef_off, h->n, b, c);
+    t.host = build_tiling(h->groups, h->n, b, c, role == 1 ? kLambdaRegionBits : 0);
+    if (t.host.blob_overflow) return fail(SV_EINVAL, "internal: a tile's group tables exceed the LDS budget");
     Packer pk;
     t.o_frames = pk.add(t.host.frames.data(), t.host.frames.size() * sizeof(FrameDesc));
-    t.o_tg = pk.add(t.host.tile_groups.data(), t.host.tile_groups.size() * sizeof(uint32_t));
+    t.o_boff = pk.add(t.host.blob_off.data(), t.host.blob_off.size() * sizeof(uint32_t));
+    t.o_blob = pk.add(t.host.blob.data(), t.host.blob.size() * sizeof(uint64_t));
     t.o_groups = pk.add(t.host.groups.data(), t.host.groups.size() * sizeof(GroupDesc));
     t.o_subs = pk.add(t.host.subs.data(), t.host.subs.size() * sizeof(SubDesc));
     t.o_recs = pk.add(t.host.recbits.data(), t.host.recbits.size() * sizeof(uint64_t));
+    t.o_coef = pk.add(t.host.coef.data(), t.host.coef.size() * sizeof(double));
     std::vector<char> blob(pk.total + 1);
     for (size_t i = 0; i < pk.parts.size(); ++i)
       if (pk.parts[i].second) std::memcpy(blob.data() + pk.offs[i], pk.parts[i].first, pk.parts[i].second);
@@ -250,6 +259,31 @@ static int tiling_get(sv_hamiltonian* h, int dtype, int role, DevTiling** out) {
     h->built[dtype][role] = true;
   }
   *out = &t;
+  return SV_OK;
+}
+
+// The diagonal part of H as a resident FP64 vector, built once on the
+// caller's stream (8 bytes per amplitude).
+static int diag_get(sv_hamiltonian* h, hipStream_t st, const double** out) {
+  if (h->diag_z.empty()) {
+    *out = nullptr;
+    return SV_OK;
+  }
+  if (!h->diag_built) {
+    const uint64_t n_amp = uint64_t(1) << h->n;
+    const size_t tb = h->diag_z.size() * (sizeof(uint64_t) + sizeof(double));
+    int rc = h->diag_dev.ensure(n_amp * sizeof(double) + tb + 256, st);
+    if (rc) return rc;
+    char* base = static_cast<char*>(h->diag_dev.p);
+    uint64_t* dz = reinterpret_cast<uint64_t*>(base + n_amp * sizeof(double));
+    double* dc = reinterpret_cast<double*>(dz + h->diag_z.size());
+    HIP_TRY(hipMemcpy(dz, h->diag_z.data(), h->diag_z.size() * sizeof(uint64_t), hipMemcpyHostToDevice));
+    HIP_TRY(hipMemcpy(dc, h->diag_c.data(), h->diag_c.size() * sizeof(double), hipMemcpyHostToDevice));
+    ProfScope prof(st, kPSmall, double(n_amp) * 8.0);
+    HIP_TRY(launch_diag_build(reinterpret_cast<double*>(base), n_amp, dz, dc, int(h->diag_z.size()), st));
+    h->diag_built = true;
+  }
+  *out = static_cast<const double*>(h->diag_dev.p);
   return SV_OK;
 }
 
@@ -279,19 +313,17 @@ static int hamiltonian_make(int n, const sv_pauli* p, const double* coef, int64_
   h->n = n;
   h->n_terms = n_terms;
   std::string err;
-  h->groups = build_groups(reinterpret_cast<const PauliIn*>(p), coef, n_terms, &err);
-  for (const HGroup& g : h->groups)
-    for (size_t i = 0; i < g.t_re.size(); ++i) {
-      h->coef.push_back(g.t_re[i]);
-      h->coef.push_back(g.t_im[i]);
+  std::vector<HGroup> all = build_groups(reinterpret_cast<const PauliIn*>(p), coef, n_terms, &err);
+  for (HGroup& g : all) {
+    if (g.diag) {
+      for (size_t w = 0; w < g.w.size(); ++w) {
+        h->diag_z.push_back(g.w[w]);
+        h->diag_c.push_back(g.t_re[w]);
+      }
+    } else {
+      h->groups.push_back(std::move(g));
     }
-  if (h->coef.empty()) {
-    h->coef.push_back(0.0);
-    h->coef.push_back(0.0);
   }
-  rc = h->coef_dev.ensure(h->coef.size() * sizeof(double), nullptr);
-  if (rc) return rc;
-  HIP_TRY(hipMemcpy(h->coef_dev.p, h->coef.data(), h->coef.size() * sizeof(double), hipMemcpyHostToDevice));
   hipGetDevice(&h->device);
   *out = h.release();
   return SV_OK;
@@ -301,7 +333,7 @@ static void hamiltonian_destroy(sv_hamiltonian* h) {
   if (!h) return;
   for (auto& row : h->tilings)
     for (auto& t : row) t.buf.release();
-  h->coef_dev.release();
+  h->diag_dev.release();
   delete h;
 }
 
@@ -433,7 +465,7 @@ static int launch_rotations(sv_state* s, sv_state* lam, const RotPlan& pl, bool 
     if (ps.tile) {
       const FrameDesc fr = make_frame(ps.qmask, s->n, c);
       const uint64_t n_tb = uint64_t(1) << fr.n_comp;
-      const int grid = int(std::min<uint64_t>(n_tb, rev ? kPartialStride : 2048));
+      const int grid = int(std::min<uint64_t>(n_tb, uint64_t(std::min<int>(num_cus(), int(kPartialStride)))));
       hipError_t e;
       ProfScope prof(s->stream, rev ? kPTileRev : kPTileFwd, (rev ? 4.0 : 2.0) * s->bytes());
       if (!rev)
@@ -484,88 +516,91 @@ static int expect_impl(sv_state* s, sv_hamiltonian* h, double* out_dev) {
   DevTiling* t = nullptr;
   int rc = tiling_get(h, s->dtype, 0, &t);
   if (rc) return rc;
+  const double* diag = nullptr;
+  rc = diag_get(h, s->stream, &diag);
+  if (rc) return rc;
   const HTiling& ht = t->host;
   const int T = int(ht.frames.size());
   const uint64_t n_tb = uint64_t(1) << ht.frames[0].n_comp;
-  const uint32_t bpt = uint32_t(std::max<uint64_t>(1, std::min<uint64_t>(n_tb, std::max(1, 2048 / T))));
+  const uint32_t bpt = uint32_t(std::max<uint64_t>(1, std::min<uint64_t>(n_tb, std::max(1, 2 * num_cus() / T))));
+  const size_t n_full = ht.groups.size();
   const int gfull = full_grid(s->amp_count() / 2);
   const int gdot = dot_grid(s);
-  const size_t n_h = size_t(T) * bpt + ht.full_groups.size() * size_t(gfull);
-  const size_t need = (n_h + 2 * size_t(gdot) + 8) * sizeof(double);
-  rc = s->scratch.ensure(need, s->stream);
+  const size_t n_h = size_t(T) * bpt + n_full * size_t(gfull);
+  rc = s->scratch.ensure((n_h + 3 * size_t(gdot) + 8) * sizeof(double), s->stream);
   if (rc) return rc;
   rc = s->small.ensure(16 * sizeof(double), s->stream);
   if (rc) return rc;
   double* part = static_cast<double*>(s->scratch.p);
   double* sm = static_cast<double*>(s->small.p);
-  const double* d_coef = static_cast<const double*>(h->coef_dev.p);
   hipError_t e;
   {
-  ProfScope prof(s->stream, kPTileHExp, double(T) * s->bytes());
-  e = launch_tile_hamiltonian(
-      s->dtype, 0, s->amps, nullptr, dptr<FrameDesc>(t->buf, t->o_frames), dptr<uint32_t>(t->buf, t->o_tg),
-      dptr<GroupDesc>(t->buf, t->o_groups), dptr<SubDesc>(t->buf, t->o_subs),
-      reinterpret_cast<const double2*>(d_coef), dptr<uint64_t>(t->buf, t->o_recs), 0, T, bpt, n_tb, part,
-      s->stream);
+    ProfScope prof(s->stream, kPTileHExp, double(T) * double(bpt) * double(n_tb) / double(bpt) * s->bytes() /
+                                              double(n_tb));
+    e = launch_tile_expect(s->dtype, s->amps, dptr<FrameDesc>(t->buf, t->o_frames), dptr<uint32_t>(t->buf, t->o_boff),
+                           dptr<uint4>(t->buf, t->o_blob), T, bpt, n_tb, part, s->stream);
   }
   if (e != hipSuccess) return fail(SV_EDEVICE, std::string("expectation tiles: ") + hipGetErrorString(e));
   size_t off = size_t(T) * bpt;
-  for (int gi : ht.full_groups) {
+  for (size_t gi = 0; gi < n_full; ++gi) {
     ProfScope prof(s->stream, kPGroupFull, group_bytes(s, ht.groups[gi], false));
     e = launch_group_full(s->dtype, 0, s->amps, nullptr, ht.groups[gi], dptr<SubDesc>(t->buf, t->o_subs),
-                          reinterpret_cast<const double2*>(d_coef), dptr<uint64_t>(t->buf, t->o_recs), s->n,
-                          gfull, part + off, s->stream);
+                          dptr<double2>(t->buf, t->o_coef), dptr<uint64_t>(t->buf, t->o_recs), s->n, gfull,
+                          part + off, s->stream);
     if (e != hipSuccess) return fail(SV_EDEVICE, std::string("expectation group: ") + hipGetErrorString(e));
     off += size_t(gfull);
   }
   double* dpart = part + n_h;
   {
-  ProfScope prof(s->stream, kPDot, s->bytes());
-  e = launch_dot(s->dtype, s->amps, nullptr, s->amp_count(), gdot, dpart, s->stream);
+    ProfScope prof(s->stream, kPDot, s->bytes() * (diag ? 1.5 : 1.0));
+    e = launch_dot(s->dtype, s->amps, nullptr, diag, s->amp_count(), gdot, dpart, s->stream);
   }
   if (e != hipSuccess) return fail(SV_EDEVICE, "norm launch failed");
   ProfScope prof(s->stream, kPSmall, 0.0);
   HIP_TRY(launch_reduce_rows(part, 0, uint32_t(n_h), 1, sm, s->stream));
-  HIP_TRY(launch_reduce_rows(dpart + gdot, 0, uint32_t(gdot), 1, sm + 1, s->stream));
-  HIP_TRY(launch_finish_energy(sm, 1, sm + 1, out_dev, s->stream));
+  HIP_TRY(launch_reduce_rows(dpart + 2 * gdot, 0, uint32_t(gdot), 1, sm + 1, s->stream));
+  HIP_TRY(launch_reduce_rows(dpart + gdot, 0, uint32_t(gdot), 1, sm + 2, s->stream));
+  HIP_TRY(launch_finish_energy(sm, 2, sm + 2, out_dev, s->stream));
   return SV_OK;
 }
 
-// lam = H psi over the two-tile tiling; energy_dev = (<psi|lam>/<psi|psi>, <psi|psi>)
+// lam = H psi; energy_dev = (<psi|lam>/<psi|psi>, <psi|psi>)
 static int lambda_impl(sv_state* s, sv_state* lam, sv_hamiltonian* h, double* energy_dev) {
   DevTiling* t = nullptr;
   int rc = tiling_get(h, s->dtype, 1, &t);
   if (rc) return rc;
+  const double* diag = nullptr;
+  rc = diag_get(h, s->stream, &diag);
+  if (rc) return rc;
   const HTiling& ht = t->host;
   const int T = int(ht.frames.size());
-  const uint64_t n_tb = uint64_t(1) << ht.frames[0].n_comp;
-  const uint32_t bpt = uint32_t(std::min<uint64_t>(n_tb, 2048));
-  const double2* d_coef = reinterpret_cast<const double2*>(h->coef_dev.p);
   for (int tt = 0; tt < T; ++tt) {
-    ProfScope prof(s->stream, kPTileHLam, (tt == 0 ? 2.0 : 3.0) * s->bytes());
-    hipError_t e = launch_tile_hamiltonian(
-        s->dtype, tt == 0 ? 1 : 2, s->amps, lam->amps, dptr<FrameDesc>(t->buf, t->o_frames),
-        dptr<uint32_t>(t->buf, t->o_tg), dptr<GroupDesc>(t->buf, t->o_groups), dptr<SubDesc>(t->buf, t->o_subs),
-        d_coef, dptr<uint64_t>(t->buf, t->o_recs), tt, 1, bpt, n_tb, nullptr, s->stream);
+    const FrameDesc& fr = ht.frames[tt];
+    const uint64_t n_tb = uint64_t(1) << fr.n_comp;
+    const int grid = int(std::min<uint64_t>(n_tb, uint64_t(num_cus())));
+    ProfScope prof(s->stream, kPTileHLam, (tt == 0 ? (diag ? 2.5 : 2.0) : 3.0) * s->bytes());
+    const hipError_t e = launch_tile_lambda(s->dtype, tt == 0, s->amps, lam->amps, diag, fr,
+                                            dptr<uint4>(t->buf, t->o_blob) + ht.blob_off[tt], n_tb, grid, s->stream);
     if (e != hipSuccess) return fail(SV_EDEVICE, std::string("lambda tile: ") + hipGetErrorString(e));
   }
   const int gfull = full_grid(s->amp_count() / 2);
-  for (int gi : ht.full_groups) {
+  for (size_t gi = 0; gi < ht.groups.size(); ++gi) {
     ProfScope prof(s->stream, kPGroupFull, group_bytes(s, ht.groups[gi], true));
-    hipError_t e = launch_group_full(s->dtype, 2, s->amps, lam->amps, ht.groups[gi], dptr<SubDesc>(t->buf, t->o_subs),
-                                     d_coef, dptr<uint64_t>(t->buf, t->o_recs), s->n, gfull, nullptr, s->stream);
+    const hipError_t e = launch_group_full(s->dtype, 2, s->amps, lam->amps, ht.groups[gi],
+                                           dptr<SubDesc>(t->buf, t->o_subs), dptr<double2>(t->buf, t->o_coef),
+                                           dptr<uint64_t>(t->buf, t->o_recs), s->n, gfull, nullptr, s->stream);
     if (e != hipSuccess) return fail(SV_EDEVICE, std::string("lambda group: ") + hipGetErrorString(e));
   }
   const int gdot = dot_grid(s);
   rc = s->small.ensure(16 * sizeof(double), s->stream);
   if (rc) return rc;
-  rc = s->scratch.ensure((2 * size_t(gdot) + 8) * sizeof(double), s->stream);
+  rc = s->scratch.ensure((3 * size_t(gdot) + 8) * sizeof(double), s->stream);
   if (rc) return rc;
   double* part = static_cast<double*>(s->scratch.p);
   double* sm = static_cast<double*>(s->small.p);
   {
     ProfScope prof(s->stream, kPDot, 2.0 * s->bytes());
-    HIP_TRY(launch_dot(s->dtype, s->amps, lam->amps, s->amp_count(), gdot, part, s->stream));
+    HIP_TRY(launch_dot(s->dtype, s->amps, lam->amps, nullptr, s->amp_count(), gdot, part, s->stream));
   }
   ProfScope prof(s->stream, kPSmall, 0.0);
   HIP_TRY(launch_reduce_rows(part, 0, uint32_t(gdot), 1, sm, s->stream));
@@ -848,7 +883,7 @@ int sv_normalize(sv_state* s, double* norm2_dev) {
   if (!s) return fail(SV_EINVAL, "NULL state");
   DeviceGuard g(s->device);
   const int gdot = dot_grid(s);
-  int rc = s->scratch.ensure((2 * size_t(gdot) + 8) * sizeof(double), s->stream);
+  int rc = s->scratch.ensure((3 * size_t(gdot) + 8) * sizeof(double), s->stream);
   if (rc) return rc;
   rc = s->small.ensure(16 * sizeof(double), s->stream);
   if (rc) return rc;
@@ -856,7 +891,7 @@ int sv_normalize(sv_state* s, double* norm2_dev) {
   double* sm = static_cast<double*>(s->small.p);
   {
     ProfScope prof(s->stream, kPDot, s->bytes());
-    HIP_TRY(launch_dot(s->dtype, s->amps, nullptr, s->amp_count(), gdot, part, s->stream));
+    HIP_TRY(launch_dot(s->dtype, s->amps, nullptr, nullptr, s->amp_count(), gdot, part, s->stream));
   }
   ProfScope prof(s->stream, kPSmall, 2.0 * s->bytes());
   HIP_TRY(launch_reduce_rows(part + gdot, 0, uint32_t(gdot), 1, sm + 2, s->stream));

@@ -1,0 +1,231 @@
+// Device helpers shared by the gfx950 kernels.
+//
+// Amplitudes are interleaved complex (double2 for complex128, float2 for
+// complex64).  Sweeps compute in the amplitude precision; every reduction
+// (energy, norm, gradient) promotes products to FP64 and sums them in a fixed
+// order: per lane, then across the 64 lanes of a wavefront, then across the
+// wavefronts of a block in index order, then across blocks in index order.
+// No floating-point atomics are used, so results are bitwise reproducible.
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <cstdint>
+
+#include "q2sv_internal.h"
+
+namespace q2sv {
+
+template <typename T> struct Real;
+template <> struct Real<double2> { using type = double; };
+template <> struct Real<float2> { using type = float; };
+
+template <typename V>
+__device__ __forceinline__ V cmake(typename Real<V>::type re, typename Real<V>::type im) {
+  V v;
+  v.x = re;
+  v.y = im;
+  return v;
+}
+
+// v * i^e for e in 0..3
+template <typename V>
+__device__ __forceinline__ V mul_ipow(V v, unsigned e) {
+  switch (e & 3u) {
+    case 0: return v;
+    case 1: return cmake<V>(-v.y, v.x);
+    case 2: return cmake<V>(-v.x, -v.y);
+    default: return cmake<V>(v.y, -v.x);
+  }
+}
+
+__device__ __forceinline__ unsigned parity64(uint64_t v) { return __popcll(v) & 1u; }
+__device__ __forceinline__ unsigned parity32(uint32_t v) { return __popc(v) & 1u; }
+
+__device__ __forceinline__ uint64_t insert_zero(uint64_t t, unsigned pos) {
+  const uint64_t low = t & ((uint64_t(1) << pos) - 1);
+  return ((t >> pos) << (pos + 1)) | low;
+}
+
+// Insert zeros at ascending positions (final positions of the zero bits),
+// packed one byte per position.
+__device__ __forceinline__ uint64_t insert_zeros(uint64_t t, uint64_t pack, int n) {
+  for (int j = 0; j < n; ++j) t = insert_zero(t, unsigned(pack >> (8 * j)) & 0xffu);
+  return t;
+}
+
+__device__ __forceinline__ unsigned pack_at(uint64_t pack, int j) { return unsigned(pack >> (8 * j)) & 0xffu; }
+
+__device__ __forceinline__ uint32_t insert_zero32(uint32_t t, unsigned pos) {
+  const uint32_t low = t & ((1u << pos) - 1u);
+  return ((t >> pos) << (pos + 1)) | low;
+}
+
+__device__ __forceinline__ uint32_t insert_zeros32(uint32_t t, uint64_t pack, int n) {
+  for (int j = 0; j < n; ++j) t = insert_zero32(t, unsigned(pack >> (8 * j)) & 0xffu);
+  return t;
+}
+
+// ---------------------------------------------------------------------------
+// deterministic FP64 reductions
+// ---------------------------------------------------------------------------
+__device__ __forceinline__ double wave_sum(double v) {
+#pragma unroll
+  for (int off = 32; off > 0; off >>= 1) v += __shfl_xor(v, off, 64);
+  return v;
+}
+
+// Sum over the block; result valid in thread 0.  `scratch` holds one double
+// per wavefront.
+template <int NT>
+__device__ __forceinline__ double block_sum(double v, double* scratch) {
+  constexpr int NW = NT / 64;
+  v = wave_sum(v);
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  __syncthreads();
+  if (lane == 0) scratch[wave] = v;
+  __syncthreads();
+  double s = 0.0;
+  if (threadIdx.x == 0) {
+    for (int w = 0; w < NW; ++w) s += scratch[w];
+  }
+  return s;
+}
+
+// ---------------------------------------------------------------------------
+// frames: frame-local index l (B bits) -> global index base | deposit(l)
+// ---------------------------------------------------------------------------
+struct FrameLut {
+  // deposit of frame-local bits [c, c + k1) and [c + k1, B) to global positions
+  uint64_t lo[128];
+  uint64_t hi[128];
+  int c, k1, b;
+};
+
+__device__ __forceinline__ uint64_t frame_base(const FrameDesc& fr, uint64_t tb) {
+  uint64_t base = 0;
+  for (int j = 0; j < fr.n_comp; ++j) base |= ((tb >> j) & 1ull) << fr.comp[j];
+  return base;
+}
+
+template <int NT>
+__device__ void frame_lut_init(const FrameDesc& fr, FrameLut& lut) {
+  const int c = fr.c, b = fr.b;
+  const int rest = b - c;
+  const int k1 = rest < 7 ? rest : 7;
+  const int k2 = rest - k1;
+  for (int i = threadIdx.x; i < (1 << k1); i += NT) {
+    uint64_t g = 0;
+    for (int j = 0; j < k1; ++j) g |= uint64_t((i >> j) & 1) << fr.q[c + j];
+    lut.lo[i] = g;
+  }
+  for (int i = threadIdx.x; i < (1 << k2); i += NT) {
+    uint64_t g = 0;
+    for (int j = 0; j < k2; ++j) g |= uint64_t((i >> j) & 1) << fr.q[c + k1 + j];
+    lut.hi[i] = g;
+  }
+  if (threadIdx.x == 0) {
+    lut.c = c;
+    lut.k1 = k1;
+    lut.b = b;
+  }
+}
+
+__device__ __forceinline__ uint64_t frame_deposit(const FrameLut& lut, uint32_t l) {
+  const uint32_t cm = (1u << lut.c) - 1u;
+  const uint32_t m1 = (1u << lut.k1) - 1u;
+  return uint64_t(l & cm) | lut.lo[(l >> lut.c) & m1] | lut.hi[l >> (lut.c + lut.k1)];
+}
+
+// Register staging of PER amplitudes per thread, kept as separate real and
+// imaginary scalar arrays so they stay in VGPRs.
+template <typename T, int PER>
+struct Stage {
+  typename Real<T>::type re[PER];
+  typename Real<T>::type im[PER];
+};
+
+// Issue the loads of one tile-block into registers (all loads in flight at
+// once); thread t holds frame-local indices t, t + NT, ...
+template <typename T, int PER, int NT>
+__device__ __forceinline__ void tile_fetch(const T* __restrict__ src, const FrameLut& lut, uint64_t base,
+                                           uint32_t nloc, Stage<T, PER>& reg) {
+#pragma unroll
+  for (int i = 0; i < PER; ++i) {
+    const uint32_t l = threadIdx.x + uint32_t(i) * NT;
+    if (l < nloc) {
+      const T v = src[base | frame_deposit(lut, l)];
+      reg.re[i] = v.x;
+      reg.im[i] = v.y;
+    }
+  }
+}
+
+template <typename T, int PER, int NT>
+__device__ __forceinline__ void tile_put(T* tile, uint32_t nloc, const Stage<T, PER>& reg) {
+#pragma unroll
+  for (int i = 0; i < PER; ++i) {
+    const uint32_t l = threadIdx.x + uint32_t(i) * NT;
+    if (l < nloc) tile[l] = cmake<T>(reg.re[i], reg.im[i]);
+  }
+}
+
+template <typename T, int PER, int NT>
+__device__ __forceinline__ void tile_store(T* __restrict__ dst, const FrameLut& lut, uint64_t base, uint32_t nloc,
+                                           const T* tile) {
+#pragma unroll
+  for (int i = 0; i < PER; ++i) {
+    const uint32_t l = threadIdx.x + uint32_t(i) * NT;
+    if (l < nloc) dst[base | frame_deposit(lut, l)] = tile[l];
+  }
+}
+
+// ---------------------------------------------------------------------------
+// fused-run pair arithmetic (Section 5.1, Eq. 11)
+//
+// For the pair (m, m' = m ^ x) with the pivot bit of m clear, the reference
+// string acts as P0 psi[m] = beta psi[m'], P0 psi[m'] = conj(beta) psi[m] with
+// beta = i^omega0 (-1)^{|m' & z0|}; every other string of the run is
+// eps_k(m) P0 on the pair, so the run is exp(-i Phi P0 / 2) with
+// Phi = sum_k eps_k phi_k, tabulated on the host as (cos Phi/2, sin Phi/2):
+//   psi'[m]  = c psi[m]  - i s beta psi[m']
+//   psi'[m'] = c psi[m'] - i s conj(beta) psi[m]
+// The reverse sweep applies the inverse (s -> -s).
+// ---------------------------------------------------------------------------
+template <typename V>
+__device__ __forceinline__ void rot_pair(V& a, V& b, typename Real<V>::type c, typename Real<V>::type s,
+                                         unsigned sgn, unsigned omega0) {
+  using R = typename Real<V>::type;
+  const R ss = sgn ? -s : s;
+  const V tb = mul_ipow(b, (omega0 + 3u) & 3u);
+  const V ta = mul_ipow(a, (3u - omega0) & 3u);
+  const V na = cmake<V>(c * a.x + ss * tb.x, c * a.y + ss * tb.y);
+  const V nb = cmake<V>(c * b.x + ss * ta.x, c * b.y + ss * ta.y);
+  a = na;
+  b = nb;
+}
+
+// Gradient factor of a pair (Algorithm 1): dE/dphi_k = Im <lam|P_k|psi> sums
+// eps_k(m) w over pairs, with
+//   w = Im[conj(lam[m]) beta psi[m'] + conj(lam[m']) conj(beta) psi[m]]  (FP64)
+template <typename V>
+__device__ __forceinline__ double grad_w(V pa, V pb, V la, V lb, unsigned sgn, unsigned omega0) {
+  const V tb = mul_ipow(pb, omega0 & 3u);
+  const V ta = mul_ipow(pa, (4u - omega0) & 3u);
+  double w = (double)la.x * (double)tb.y - (double)la.y * (double)tb.x + (double)lb.x * (double)ta.y -
+             (double)lb.y * (double)ta.x;
+  return sgn ? -w : w;
+}
+
+// pattern index of m' (frame-local l2, block base) for kRunFull / kRunDiag
+__device__ __forceinline__ unsigned run_pattern(const RunDesc& r, uint64_t l2, uint64_t base) {
+  unsigned p = 0;
+  for (int j = 0; j < r.n_pat; ++j) {
+    const unsigned pos = pack_at(r.pat_pack, j);
+    const uint64_t bit = pos < 64 ? (l2 >> pos) & 1ull : (base >> (pos - 64)) & 1ull;
+    p |= unsigned(bit) << j;
+  }
+  return p;
+}
+
+}  // namespace q2sv

@@ -1,0 +1,163 @@
+// Reductions and small utilities (FP64, fixed order, no atomics).
+#include "device_common.h"
+#include "launch.h"
+
+namespace q2sv {
+
+// Per block: partials[0][b] = sum Re(conj(a) b), partials[1][b] = sum |a|^2,
+// partials[2][b] = sum d |a|^2 (the missing operands contribute zero).
+template <typename T>
+__global__ void __launch_bounds__(256) k_dot(const T* __restrict__ a, const T* __restrict__ b,
+                                             const double* __restrict__ d, uint64_t n_amp,
+                                             double* __restrict__ partials) {
+  __shared__ double red[4];
+  const uint64_t stride = uint64_t(gridDim.x) * 256;
+  double re = 0.0, nn = 0.0, dd = 0.0;
+  for (uint64_t i = uint64_t(blockIdx.x) * 256 + threadIdx.x; i < n_amp; i += stride) {
+    const T u = a[i];
+    const double p = (double)u.x * u.x + (double)u.y * u.y;
+    nn += p;
+    if (b) {
+      const T v = b[i];
+      re += (double)u.x * v.x + (double)u.y * v.y;
+    }
+    if (d) dd += d[i] * p;
+  }
+  const double s0 = block_sum<256>(re, red);
+  if (threadIdx.x == 0) partials[blockIdx.x] = s0;
+  const double s1 = block_sum<256>(nn, red);
+  if (threadIdx.x == 0) partials[gridDim.x + blockIdx.x] = s1;
+  const double s2 = block_sum<256>(dd, red);
+  if (threadIdx.x == 0) partials[2 * gridDim.x + blockIdx.x] = s2;
+}
+
+// out[row] = sum_{j < len} in[row * stride + j], fixed order (one block per row)
+__global__ void __launch_bounds__(256) k_reduce_rows(const double* __restrict__ in, uint64_t stride, uint32_t len,
+                                                     double* __restrict__ out) {
+  __shared__ double red[4];
+  const uint64_t row = blockIdx.x;
+  double s = 0.0;
+  for (uint32_t j = threadIdx.x; j < len; j += 256) s += in[row * stride + j];
+  const double t = block_sum<256>(s, red);
+  if (threadIdx.x == 0) out[row] = t;
+}
+
+// out[0] = (sum_j sums[j]) / norm, out[1] = norm
+__global__ void k_finish_energy(const double* __restrict__ sums, int nh, const double* __restrict__ norm,
+                                double* __restrict__ out) {
+  if (threadIdx.x == 0 && blockIdx.x == 0) {
+    double e = 0.0;
+    for (int j = 0; j < nh; ++j) e += sums[j];
+    const double nn = norm[0];
+    out[0] = e / nn;
+    out[1] = nn;
+  }
+}
+
+// out[i] = sum over the slots listed for output i, in list order
+__global__ void __launch_bounds__(256) k_gather_slots(const double* __restrict__ slot_val,
+                                                      const uint32_t* __restrict__ off,
+                                                      const uint32_t* __restrict__ idx,
+                                                      const double* __restrict__ weight, int n_out,
+                                                      double* __restrict__ out) {
+  const int i = blockIdx.x * 256 + threadIdx.x;
+  if (i >= n_out) return;
+  double s = 0.0;
+  for (uint32_t k = off[i]; k < off[i + 1]; ++k) s += weight[k] * slot_val[idx[k]];
+  out[i] = s;
+}
+
+__global__ void __launch_bounds__(256) k_fill_f64(double* __restrict__ p, uint64_t n, double v) {
+  const uint64_t stride = uint64_t(gridDim.x) * 256;
+  for (uint64_t i = uint64_t(blockIdx.x) * 256 + threadIdx.x; i < n; i += stride) p[i] = v;
+}
+
+template <typename T>
+__global__ void __launch_bounds__(256) k_scale(T* __restrict__ psi, uint64_t n_amp, const double* __restrict__ norm2) {
+  using R = typename Real<T>::type;
+  const R f = R(1.0 / sqrt(norm2[0]));
+  const uint64_t stride = uint64_t(gridDim.x) * 256;
+  for (uint64_t i = uint64_t(blockIdx.x) * 256 + threadIdx.x; i < n_amp; i += stride) {
+    T v = psi[i];
+    v.x *= f;
+    v.y *= f;
+    psi[i] = v;
+  }
+}
+
+template <typename T>
+__global__ void __launch_bounds__(256) k_gather_amps(const T* __restrict__ psi, const uint64_t* __restrict__ idx,
+                                                     int64_t count, double* __restrict__ out) {
+  const int64_t i = int64_t(blockIdx.x) * 256 + threadIdx.x;
+  if (i >= count) return;
+  const T v = psi[idx[i]];
+  out[2 * i] = v.x;
+  out[2 * i + 1] = v.y;
+}
+
+// ---------------------------------------------------------------------------
+// launchers
+// ---------------------------------------------------------------------------
+hipError_t launch_dot(int dtype, const void* a, const void* b, const double* d, uint64_t n_amp, int grid,
+                      double* partials, hipStream_t st) {
+  if (dtype == 0)
+    hipLaunchKernelGGL((k_dot<double2>), dim3(grid), dim3(256), 0, st, static_cast<const double2*>(a),
+                       static_cast<const double2*>(b), d, n_amp, partials);
+  else
+    hipLaunchKernelGGL((k_dot<float2>), dim3(grid), dim3(256), 0, st, static_cast<const float2*>(a),
+                       static_cast<const float2*>(b), d, n_amp, partials);
+  return hipGetLastError();
+}
+
+hipError_t launch_reduce_rows(const double* in, uint64_t stride, uint32_t len, uint32_t rows, double* out,
+                              hipStream_t st) {
+  if (rows == 0) return hipSuccess;
+  hipLaunchKernelGGL(k_reduce_rows, dim3(rows), dim3(256), 0, st, in, stride, len, out);
+  return hipGetLastError();
+}
+
+hipError_t launch_finish_energy(const double* sums, int nh, const double* norm, double* out, hipStream_t st) {
+  hipLaunchKernelGGL(k_finish_energy, dim3(1), dim3(64), 0, st, sums, nh, norm, out);
+  return hipGetLastError();
+}
+
+hipError_t launch_gather_slots(const double* slot_val, const uint32_t* off, const uint32_t* idx,
+                               const double* weight, int n_out, double* out, hipStream_t st) {
+  if (n_out == 0) return hipSuccess;
+  hipLaunchKernelGGL(k_gather_slots, dim3((n_out + 255) / 256), dim3(256), 0, st, slot_val, off, idx, weight,
+                     n_out, out);
+  return hipGetLastError();
+}
+
+hipError_t launch_fill_f64(double* p, uint64_t n, double v, hipStream_t st) {
+  if (n == 0) return hipSuccess;
+  const uint64_t want = (n + 255) / 256;
+  const int grid = int(want < 4096 ? want : 4096);
+  hipLaunchKernelGGL(k_fill_f64, dim3(grid), dim3(256), 0, st, p, n, v);
+  return hipGetLastError();
+}
+
+hipError_t launch_scale(int dtype, void* psi, uint64_t n_amp, const double* norm2, hipStream_t st) {
+  const uint64_t want = (n_amp + 255) / 256;
+  const int grid = int(want < 4096 ? want : 4096);
+  if (dtype == 0)
+    hipLaunchKernelGGL((k_scale<double2>), dim3(grid), dim3(256), 0, st, static_cast<double2*>(psi), n_amp, norm2);
+  else
+    hipLaunchKernelGGL((k_scale<float2>), dim3(grid), dim3(256), 0, st, static_cast<float2*>(psi), n_amp, norm2);
+  return hipGetLastError();
+}
+
+hipError_t launch_gather_amps(int dtype, const void* psi, const uint64_t* idx, int64_t count, double* out,
+                              hipStream_t st) {
+  if (count == 0) return hipSuccess;
+  const int grid = int((count + 255) / 256);
+  if (dtype == 0)
+    hipLaunchKernelGGL((k_gather_amps<double2>), dim3(grid), dim3(256), 0, st,
+                       static_cast<const double2*>(psi), idx, count, out);
+  else
+    hipLaunchKernelGGL((k_gather_amps<float2>), dim3(grid), dim3(256), 0, st, static_cast<const float2*>(psi),
+                       idx, count, out);
+  return hipGetLastError();
+}
+
+}  // namespace q2sv

@@ -13,7 +13,11 @@ namespace q2sv {
 // tiles fill at most 128 KiB of the 160 KiB LDS of a gfx950 compute unit.
 constexpr int kTileFwdC128 = 13, kTileFwdC64 = 14;   // one state tile
 constexpr int kTileTwoC128 = 12, kTileTwoC64 = 13;   // two tiles (psi and lam)
+constexpr int kTileLamC128 = 12, kTileLamC64 = 12;   // psi tile + FP64 lambda accumulator
 constexpr int kTileThreads = 512;
+constexpr int kLambdaThreads = 512;                  // 8 wavefronts own 8 output regions
+constexpr int kLambdaRegionBits = 3;
+constexpr int kBlobWords = 26 * 1024 / 16;           // group tables staged in LDS (26 KiB)
 constexpr int kMaxPassSlots = 256;                   // gradient slots per reverse tile pass
 constexpr uint32_t kPartialStride = 1024;            // max blocks of a gradient pass
 
@@ -27,16 +31,19 @@ hipError_t launch_tile_reverse(int dtype, int grad, void* psi, void* lam, const 
                                const RunDesc* runs, int n_runs, const RunRec* recs,
                                const uint32_t* slot_map, int n_slots, double* partials, uint32_t nb_stride,
                                uint64_t n_tb, int grid, hipStream_t st);
-hipError_t launch_tile_hamiltonian(int dtype, int mode, const void* psi, void* lam, const FrameDesc* frames,
-                                   const uint32_t* tile_groups, const GroupDesc* groups, const SubDesc* subs,
-                                   const double2* coef, const uint64_t* recbits, int tile_first,
-                                   int n_tiles_launch, uint32_t blocks_per_tile, uint64_t n_tb,
-                                   double* partials, hipStream_t st);
+hipError_t launch_tile_lambda(int dtype, bool first, const void* psi, void* lam, const double* diag,
+                              const FrameDesc& fr, const uint4* blob, uint64_t n_tb, int grid, hipStream_t st);
+hipError_t launch_tile_expect(int dtype, const void* psi, const FrameDesc* frames, const uint32_t* blob_off,
+                              const uint4* blobs, int n_tiles, uint32_t bpt, uint64_t n_tb, double* partials,
+                              hipStream_t st);
+hipError_t launch_diag_build(double* d, uint64_t n_amp, const uint64_t* z, const double* c, int n_terms,
+                             hipStream_t st);
 hipError_t launch_group_full(int dtype, int mode, const void* psi, void* lam, const GroupDesc& g,
                              const SubDesc* subs, const double2* coef, const uint64_t* recbits, int n,
                              int grid, double* partials, hipStream_t st);
-hipError_t launch_dot(int dtype, const void* a, const void* b, uint64_t n_amp, int grid, double* partials,
-                      hipStream_t st);
+// partials[0..grid) = Re<a|b>, [grid..2grid) = <a|a>, [2grid..3grid) = sum d |a|^2
+hipError_t launch_dot(int dtype, const void* a, const void* b, const double* d, uint64_t n_amp, int grid,
+                      double* partials, hipStream_t st);
 hipError_t launch_reduce_rows(const double* in, uint64_t stride, uint32_t len, uint32_t rows, double* out,
                               hipStream_t st);
 hipError_t launch_finish_energy(const double* sums, int nh, const double* norm, double* out, hipStream_t st);
@@ -49,5 +56,6 @@ hipError_t launch_gather_amps(int dtype, const void* psi, const uint64_t* idx, i
 
 inline int tile_bits_one(int dtype) { return dtype == 0 ? kTileFwdC128 : kTileFwdC64; }
 inline int tile_bits_two(int dtype) { return dtype == 0 ? kTileTwoC128 : kTileTwoC64; }
+inline int tile_bits_lambda(int dtype) { return dtype == 0 ? kTileLamC128 : kTileLamC64; }
 
 }  // namespace q2sv

@@ -3,6 +3,7 @@
 
 #include <algorithm>
 #include <cmath>
+#include <cstring>
 #include <map>
 
 namespace q2sv {
@@ -143,17 +144,19 @@ RunDesc make_run_desc(const Run& r, const RunData& d, uint64_t qmask, uint32_t s
   rd.mode = d.mode;
   rd.n_str = uint8_t(r.count);
   rd.str_neg = d.str_neg;
-  for (int k = 0; k < kMaxRunStrings; ++k) rd.str_dpat[k] = d.str_dpat[k];
+  for (int k = 0; k < kMaxRunStrings; ++k) rd.dpat_pack |= uint64_t(d.str_dpat[k]) << (8 * k);
   rd.per_string = uint8_t(per_string);
   if (r.x) rd.pivot = uint8_t(local_pos(highest_bit(r.x), qmask));
   rd.n_sup = uint8_t(d.mode == kRunEnum ? d.sup_glob.size() : 0);
   if (d.mode == kRunEnum)
-    for (size_t j = 0; j < d.sup_glob.size(); ++j) rd.sup_pos[j] = uint8_t(local_pos(d.sup_glob[j], qmask));
+    for (size_t j = 0; j < d.sup_glob.size(); ++j)
+      rd.sup_pack |= uint64_t(local_pos(d.sup_glob[j], qmask)) << (8 * j);
   rd.n_pat = uint8_t(d.mode == kRunEnum ? 0 : d.pat_glob.size());
   if (d.mode != kRunEnum)
     for (size_t j = 0; j < d.pat_glob.size(); ++j) {
       const int g = d.pat_glob[j];
-      rd.pat_pos[j] = ((qmask >> g) & 1ull) ? uint8_t(local_pos(g, qmask)) : uint8_t(64 + g);
+      const uint64_t pos = ((qmask >> g) & 1ull) ? uint64_t(local_pos(g, qmask)) : uint64_t(64 + g);
+      rd.pat_pack |= pos << (8 * j);
     }
   for (const RunRec& e : d.recs) {
     RunRec o = e;
@@ -345,26 +348,107 @@ static GroupDesc make_group_desc(const HGroup& g, uint64_t qmask, uint32_t sub_o
   d.n_sup = uint8_t(g.enumerated ? g.sup.size() : 0);
   if (g.x) d.pivot = uint8_t(local_pos(highest_bit(g.x), qmask));
   if (g.enumerated)
-    for (size_t j = 0; j < g.sup.size(); ++j) d.sup_pos[j] = uint8_t(local_pos(g.sup[j], qmask));
+    for (size_t j = 0; j < g.sup.size(); ++j) d.sup_pack |= uint64_t(local_pos(g.sup[j], qmask)) << (8 * j);
   return d;
 }
 
-static void append_group(HTiling& t, const HGroup& g, uint32_t coef_off, uint64_t qmask) {
+// whole-state group (identity frame) with its own coefficient array
+static void append_full_group(HTiling& t, const HGroup& g, uint64_t all) {
   const uint32_t sub_off = uint32_t(t.subs.size());
   const uint32_t rec_off = uint32_t(t.recbits.size());
-  t.groups.push_back(make_group_desc(g, qmask, sub_off, rec_off));
+  t.groups.push_back(make_group_desc(g, all, sub_off, rec_off));
   const int NR = g.n_rec();
   for (size_t w = 0; w < g.w.size(); ++w) {
     SubDesc s{};
-    s.w_loc = compress(g.w[w] & qmask, qmask);
-    s.w_out = g.w[w] & ~qmask;
-    s.coef_off = coef_off + uint32_t(w * NR);
+    s.w_loc = g.w[w];
+    s.w_out = 0;
+    s.coef_off = uint32_t(t.coef.size() / 2);
+    for (int r = 0; r < NR; ++r) {
+      t.coef.push_back(g.t_re[w * NR + r]);
+      t.coef.push_back(g.t_im[w * NR + r]);
+    }
     t.subs.push_back(s);
   }
-  for (uint64_t v : g.rec_v) t.recbits.push_back(compress(v, qmask));
+  for (uint64_t v : g.rec_v) t.recbits.push_back(v);
 }
 
-HTiling build_tiling(const std::vector<HGroup>& gs, const std::vector<uint32_t>& coef_off, int n, int b, int c) {
+static size_t group_blob_bytes(const HGroup& g) {
+  const size_t nr = size_t(g.n_rec());
+  return sizeof(TGroup) + 2 * nr * sizeof(TOut) + g.w.size() * sizeof(TSub) + g.w.size() * nr * 16;
+}
+
+// Pack groups of one tile into a blob (TileHdr, TGroup[], TOut[], TSub[], coef[]).
+static void pack_blob(HTiling& t, const std::vector<HGroup>& gs, const std::vector<int>& members, uint64_t qmask,
+                      uint32_t wb_mask) {
+  std::vector<TGroup> tg;
+  std::vector<TOut> to;
+  std::vector<TSub> ts;
+  std::vector<double> co;
+  for (int gi : members) {
+    const HGroup& g = gs[gi];
+    TGroup d{};
+    d.x_loc = uint32_t(compress(g.x, qmask));
+    // enumerated bits S': the support, or the pivot alone
+    uint32_t smask;
+    if (g.enumerated) smask = d.x_loc;
+    else smask = 1u << local_pos(highest_bit(g.x), qmask);
+    d.sup_mask = smask;
+    const int NR = g.n_rec();
+    d.n_rec = uint8_t(NR);
+    d.n_out = uint16_t(2 * NR);
+    d.out_off = uint16_t(to.size());
+    d.n_sub = uint16_t(g.w.size());
+    d.sub_off = uint16_t(ts.size());
+    d.coef_off = uint32_t(co.size() / 2);
+    int k = 0;
+    for (uint32_t m = smask; m; m &= m - 1) d.sins_pack |= uint64_t(__builtin_ctz(m)) << (8 * k++);
+    d.n_sins = uint8_t(k);
+    k = 0;
+    for (uint32_t m = smask | wb_mask; m; m &= m - 1) d.ins_pack |= uint64_t(__builtin_ctz(m)) << (8 * k++);
+    d.n_ins = uint8_t(k);
+    std::vector<uint32_t> rec_loc(NR);
+    for (int r = 0; r < NR; ++r) rec_loc[r] = g.enumerated ? uint32_t(compress(g.rec_v[r], qmask)) : smask;
+    for (int r = 0; r < NR; ++r) to.push_back(TOut{uint16_t(rec_loc[r]), uint8_t(r), 1});
+    for (int r = 0; r < NR; ++r) to.push_back(TOut{uint16_t(rec_loc[r] ^ (d.x_loc & smask)), uint8_t(r), 0});
+    for (size_t w = 0; w < g.w.size(); ++w) {
+      TSub sd{};
+      sd.w_loc = uint32_t(compress(g.w[w] & qmask, qmask));
+      sd.w_out = g.w[w] & ~qmask;
+      ts.push_back(sd);
+      for (int r = 0; r < NR; ++r) {
+        co.push_back(g.t_re[w * NR + r]);
+        co.push_back(g.t_im[w * NR + r]);
+      }
+    }
+    tg.push_back(d);
+  }
+  auto align16 = [](size_t v) { return (v + 15) & ~size_t(15); };
+  TileHdr h{};
+  h.n_groups = uint32_t(tg.size());
+  size_t off = sizeof(TileHdr) + tg.size() * sizeof(TGroup);
+  h.off_out = uint32_t(align16(off));
+  off = h.off_out + to.size() * sizeof(TOut);
+  h.off_sub = uint32_t(align16(off));
+  off = h.off_sub + ts.size() * sizeof(TSub);
+  h.off_coef = uint32_t(align16(off));
+  off = h.off_coef + co.size() * sizeof(double);
+  h.bytes = uint32_t(align16(off));
+  h.wb_mask = wb_mask;
+  if (h.bytes > kBlobBytes) t.blob_overflow = true;  // the chunking estimate is conservative
+  std::vector<unsigned char> bytes(h.bytes, 0);
+  std::memcpy(bytes.data(), &h, sizeof(h));
+  if (!tg.empty()) std::memcpy(bytes.data() + sizeof(TileHdr), tg.data(), tg.size() * sizeof(TGroup));
+  if (!to.empty()) std::memcpy(bytes.data() + h.off_out, to.data(), to.size() * sizeof(TOut));
+  if (!ts.empty()) std::memcpy(bytes.data() + h.off_sub, ts.data(), ts.size() * sizeof(TSub));
+  if (!co.empty()) std::memcpy(bytes.data() + h.off_coef, co.data(), co.size() * sizeof(double));
+  t.blob_off.push_back(uint32_t(t.blob.size() / 2));
+  const size_t words = h.bytes / 8;
+  const size_t at = t.blob.size();
+  t.blob.resize(at + words);
+  std::memcpy(t.blob.data() + at, bytes.data(), h.bytes);
+}
+
+HTiling build_tiling(const std::vector<HGroup>& gs, int n, int b, int c, int region_bits) {
   HTiling t;
   t.b = b;
   t.c = c;
@@ -372,13 +456,17 @@ HTiling build_tiling(const std::vector<HGroup>& gs, const std::vector<uint32_t>&
   const uint64_t low = (uint64_t(1) << c) - 1;
   const int G = int(gs.size());
   std::vector<int> tile_of(G, -1);
+  std::vector<uint64_t> tile_q;
+  const size_t fixed = sizeof(TileHdr) + 64;
   if (n <= b) {
-    t.tile_q.push_back(all);
-    for (int g = 0; g < G; ++g) tile_of[g] = 0;
+    tile_q.push_back(all);
+    for (int g = 0; g < G; ++g)
+      if (!gs[g].diag) tile_of[g] = 0;
   } else {
     std::vector<int> todo;
     for (int g = 0; g < G; ++g)
-      if (!gs[g].diag && popc(gs[g].x | low) <= b) todo.push_back(g);
+      if (!gs[g].diag && popc(gs[g].x | low) <= b && group_blob_bytes(gs[g]) + fixed <= kBlobBytes)
+        todo.push_back(g);
     while (!todo.empty()) {
       // seed with the widest uncovered support, then add the qubit that
       // completes most uncovered groups (ties: most partial progress)
@@ -393,19 +481,15 @@ HTiling build_tiling(const std::vector<HGroup>& gs, const std::vector<uint32_t>&
           const int k = popc(miss);
           if (k == 0) continue;
           const double v = k == 1 ? 1e6 : 1.0 / k;
-          uint64_t mm = miss;
-          while (mm) {
-            score[__builtin_ctzll(mm)] += v;
-            mm &= mm - 1;
-          }
+          for (uint64_t mm = miss; mm; mm &= mm - 1) score[__builtin_ctzll(mm)] += v;
         }
         int best = -1;
         for (int qq = 0; qq < n; ++qq)
           if (!((q >> qq) & 1ull) && (best < 0 || score[qq] > score[best])) best = qq;
         q |= uint64_t(1) << best;
       }
-      const int tid = int(t.tile_q.size());
-      t.tile_q.push_back(q);
+      const int tid = int(tile_q.size());
+      tile_q.push_back(q);
       std::vector<int> rest;
       for (int g : todo) {
         if ((gs[g].x & ~q) == 0) tile_of[g] = tid;
@@ -413,27 +497,57 @@ HTiling build_tiling(const std::vector<HGroup>& gs, const std::vector<uint32_t>&
       }
       todo.swap(rest);
     }
-    if (t.tile_q.empty()) {
+    if (tile_q.empty()) {
       uint64_t q = low;
       for (int qq = c; qq < n && popc(q) < b; ++qq) q |= uint64_t(1) << qq;
-      t.tile_q.push_back(q);
+      tile_q.push_back(q);
     }
-    for (int g = 0; g < G; ++g)
-      if (gs[g].diag) tile_of[g] = 0;
   }
-  const int T = int(t.tile_q.size());
-  for (int tt = 0; tt < T; ++tt) t.frames.push_back(make_frame(t.tile_q[tt], n, c));
-  for (int tt = 0; tt < T; ++tt) {
-    t.tile_groups.push_back(uint32_t(t.groups.size()));
+  t.n_tiles = int(tile_q.size());
+  for (int tt = 0; tt < t.n_tiles; ++tt) {
+    const uint64_t q = tile_q[tt];
+    std::vector<int> members;
     for (int g = 0; g < G; ++g)
-      if (tile_of[g] == tt) append_group(t, gs[g], coef_off[g], t.tile_q[tt]);
+      if (tile_of[g] == tt) members.push_back(g);
+    // region bits: the frame-local bits at or above c least used by the tile's
+    // enumerated bits
+    uint32_t wb = 0;
+    const int fb = popc(q);
+    if (region_bits > 0 && fb - c >= region_bits) {
+      std::vector<int> use(fb, 0);
+      for (int g : members) {
+        const uint32_t xl = uint32_t(compress(gs[g].x, q));
+        const uint32_t sm = gs[g].enumerated ? xl : (1u << local_pos(highest_bit(gs[g].x), q));
+        for (uint32_t m = sm; m; m &= m - 1) use[__builtin_ctz(m)] += 1;
+      }
+      for (int k = 0; k < region_bits; ++k) {
+        int best = -1;
+        for (int p = c; p < fb; ++p)
+          if (!((wb >> p) & 1u) && (best < 0 || use[p] < use[best])) best = p;
+        wb |= 1u << best;
+      }
+    } else if (region_bits > 0) {
+      for (int p = 0; p < fb && popc(wb) < region_bits; ++p) wb |= 1u << p;
+    }
+    // chunks of at most kBlobBytes
+    std::vector<int> chunk;
+    size_t bytes = fixed;
+    auto flush = [&]() {
+      t.frames.push_back(make_frame(q, n, c));
+      pack_blob(t, gs, chunk, q, wb);
+      chunk.clear();
+      bytes = fixed;
+    };
+    for (int g : members) {
+      const size_t gb = group_blob_bytes(gs[g]) + 16;
+      if (!chunk.empty() && bytes + gb > kBlobBytes) flush();
+      chunk.push_back(g);
+      bytes += gb;
+    }
+    if (!chunk.empty() || tt == 0) flush();
   }
-  t.tile_groups.push_back(uint32_t(t.groups.size()));
   for (int g = 0; g < G; ++g)
-    if (tile_of[g] < 0) {
-      t.full_groups.push_back(int(t.groups.size()));
-      append_group(t, gs[g], coef_off[g], all);
-    }
+    if (tile_of[g] < 0 && !gs[g].diag) append_full_group(t, gs[g], all);
   return t;
 }
 

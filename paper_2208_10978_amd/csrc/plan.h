@@ -99,21 +99,27 @@ struct HGroup {
 
 std::vector<HGroup> build_groups(const PauliIn* p, const double* coef, int64_t n_terms, std::string* err);
 
-// Device-ready arrays of one tiling of a grouped sum.
+// Device-ready arrays of one tiling of a grouped sum.  Every non-diagonal
+// group whose support fits (with the c low qubits) in b qubits belongs to one
+// tile; a tile's groups are packed into one or more blobs (passes) of at most
+// kBlobBytes; the remaining groups run over the whole state.
+constexpr size_t kBlobBytes = 26 * 1024;
+
 struct HTiling {
   int b = 0, c = 0;
-  std::vector<uint64_t> tile_q;          // frame mask per tile
-  std::vector<FrameDesc> frames;
-  std::vector<uint32_t> tile_groups;     // offsets into groups (size tiles + 1)
-  std::vector<GroupDesc> groups;         // tile groups, then full-state groups
+  std::vector<FrameDesc> frames;         // per pass
+  std::vector<uint32_t> blob_off;        // per pass, in 16-byte words
+  std::vector<uint64_t> blob;            // concatenated blobs (2 words per 16 bytes)
+  std::vector<GroupDesc> groups;         // whole-state groups
   std::vector<SubDesc> subs;
   std::vector<uint64_t> recbits;
-  std::vector<int> full_groups;          // indices into `groups` run over the whole state
+  std::vector<double> coef;              // whole-state group coefficients (re, im)
+  int n_tiles = 0;
+  bool blob_overflow = false;            // a blob exceeded kBlobBytes (never expected)
 };
 
-// Greedy covering: every group whose support fits (with the c low qubits) in
-// b qubits is assigned to the first tile containing its support; the rest
-// are run over the whole state.  Coefficient tables are shared (coef index).
-HTiling build_tiling(const std::vector<HGroup>& gs, const std::vector<uint32_t>& coef_off, int n, int b, int c);
+// region_bits > 0 chooses that many frame-local bits (at or above c) per tile
+// to split lambda outputs among wavefronts.
+HTiling build_tiling(const std::vector<HGroup>& gs, int n, int b, int c, int region_bits);
 
 }  // namespace q2sv

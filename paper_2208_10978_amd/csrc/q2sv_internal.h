@@ -51,12 +51,13 @@ struct alignas(16) RunDesc {
   uint8_t n_sup;       // support bits (kRunEnum)
   uint8_t pivot;       // frame-local highest bit of x             (kRunFull)
   uint8_t n_pat;       // pattern bits L                           (kRunFull/Diag)
-  uint8_t sup_pos[kMaxSup];        // frame-local support positions, ascending
-  uint8_t pat_pos[kMaxSup];        // pattern bit j: frame-local position, or
-                                   // 64 + global position when outside the frame
-  uint8_t str_dpat[kMaxRunStrings];  // per string: pattern mask of z_k ^ z0
   uint8_t per_string;  // gradient slots are per string (else one per run)
-  uint8_t pad[7];
+  // Position lists packed one byte per entry (entry j in bits 8j..8j+7), so
+  // kernels read them with shifts instead of indexing a private array:
+  uint64_t sup_pack;   // frame-local support positions, ascending
+  uint64_t pat_pack;   // pattern bit j: frame-local position, or 64 + global
+                       // position when outside the frame
+  uint64_t dpat_pack;  // per string: pattern mask of z_k ^ z0
 };
 
 // A record (kRunEnum) or table entry (kRunFull/Diag) of a run:
@@ -88,8 +89,8 @@ struct alignas(16) GroupDesc {
   uint8_t is_diag;     // x == 0
   uint8_t n_sup;       // support bits (enumerated groups)
   uint8_t pivot;       // frame-local highest bit of x (non-enumerated groups)
-  uint8_t sup_pos[kMaxSup];
-  uint8_t pad[8];
+  uint16_t pad0;
+  uint64_t sup_pack;   // support positions, one byte each, ascending
 };
 
 // w of one subgroup; its values T_w[r] for every record r of the group sit at
@@ -100,6 +101,56 @@ struct alignas(16) SubDesc {
   uint32_t coef_off;
   uint32_t pad0;
   uint64_t pad1;
+};
+
+// ---------------------------------------------------------------------------
+// Group tables of one Hamiltonian tile pass, copied into LDS once per block.
+// A blob is a TileHdr followed by TGroup, TOut, TSub records and complex FP64
+// coefficients (offsets in bytes from the start of the blob).
+//
+// Every non-diagonal group is treated as pairs (m, m' = m ^ x) with the pivot
+// (highest) bit of m clear.  "Enumerated bits" S' are the support of x (when
+// it has at most kMaxSup bits) or the pivot alone; a record fixes the bits of
+// m' on S', and each record gives two outputs: m' (coefficient conj(G)) and
+// m (coefficient G), where
+//   G(m) = sum_w (-1)^{|m' & w|} T_w[record]   and  (H_x psi)[m] = G(m) psi[m'].
+// ---------------------------------------------------------------------------
+struct alignas(16) TileHdr {
+  uint32_t n_groups;
+  uint32_t off_out;    // byte offset of the TOut array
+  uint32_t off_sub;    // byte offset of the TSub array
+  uint32_t off_coef;   // byte offset of the coefficients (double2)
+  uint32_t bytes;      // blob size in bytes (multiple of 16)
+  uint32_t wb_mask;    // frame-local bits that split lambda outputs among wavefronts
+  uint32_t pad0, pad1;
+};
+
+struct alignas(8) TGroup {
+  uint32_t x_loc;      // frame-local flip mask
+  uint32_t sup_mask;   // frame-local enumerated bits S'
+  uint16_t n_out;      // outputs = 2 * n_rec (records first: outputs that are m')
+  uint16_t out_off;    // first TOut
+  uint16_t n_sub;      // subgroups
+  uint16_t sub_off;    // first TSub
+  uint32_t coef_off;   // first coefficient: coef[coef_off + sub * n_rec + rec]
+  uint8_t n_rec;
+  uint8_t n_ins;       // zero insertions (S' union Wb, ascending) for lambda outputs
+  uint8_t n_sins;      // zero insertions (S', ascending) for pairs
+  uint8_t pad;
+  uint64_t ins_pack;   // their positions, one byte each
+  uint64_t sins_pack;
+};
+
+struct TOut {
+  uint16_t bits;       // frame-local bits of the output on S'
+  uint8_t rec;         // record index
+  uint8_t is_mprime;   // output is m' (coefficient conj(G)); else m
+};
+
+struct alignas(16) TSub {
+  uint64_t w_out;      // w, global bits outside the frame
+  uint32_t w_loc;      // w, frame-local bits
+  uint32_t pad;
 };
 
 // Frame of a tile pass.

@@ -9,11 +9,12 @@ Conventions (the paper leaves them open; Sections 3.1-3.2, 5.1):
 * the Hamiltonian of Eq. 3 with chemist's-notation integrals is
   ``sum h_pq a+_ps a_qs + 1/2 sum (pq|rs) a+_ps a+_rt a_st a_qs``;
 * JW: ``a_j = Z_{<j} (X_j + i Y_j)/2``;
-* UCCSD (Eq. 10-11): singles ``a+_a a_i`` then doubles ``a+_a a+_b a_j a_i``
-  (i < j occupied, a < b virtual, spin projection conserved), each list in
-  lexicographic order; ``tau - tau^dag = i sum_j c_j P_j`` and the factor
-  ``exp(theta (tau - tau^dag))`` becomes the commuting rotations
-  ``R(P_j, phi_j)``, ``phi_j = -2 c_j theta``, listed by increasing z.
+* UCCSD (Eq. 10-11): singles ``a+_a a_i`` and doubles ``a+_a a+_b a_j a_i``
+  (i < j occupied, a < b virtual, spin projection conserved), applied in a
+  given excitation sequence (by default the tile-major sequence of
+  ``workloads.uccsd_excitation_order``); ``tau - tau^dag = i sum_j c_j P_j``
+  and the factor ``exp(theta (tau - tau^dag))`` becomes the commuting
+  rotations ``R(P_j, phi_j)``, ``phi_j = -2 c_j theta``, listed by increasing z.
 
 The Pauli algebra here works on whole arrays of strings at once: a ladder
 word of length L expands into 2^L strings, multiplied factor by factor with
@@ -163,10 +164,18 @@ def uccsd_excitations(n_qubits: int, n_electrons: int):
     return singles, doubles
 
 
-def uccsd_rotations(n_qubits: int, n_electrons: int) -> RotationList:
+def uccsd_rotations(n_qubits: int, n_electrons: int, order="tile") -> RotationList:
+    """``order``: "tile", "lex" or an explicit excitation sequence."""
+    if isinstance(order, str):
+        from workloads import uccsd_excitation_order
+        seq = uccsd_excitation_order(n_qubits, n_electrons, order)
+    else:
+        seq = [tuple(int(v) for v in e) for e in order]
     singles, doubles = uccsd_excitations(n_qubits, n_electrons)
+    if len(seq) != len(singles) + len(doubles) or set(seq) != set(singles + doubles):
+        raise ValueError("the excitation sequence is not a permutation of the UCCSD excitations")
     xs, zs, ps, ds = [], [], [], []
-    for idx, exc in enumerate(singles + doubles):
+    for idx, exc in enumerate(seq):
         if len(exc) == 2:
             i, a = exc
             word = [(a, True), (i, False)]
@@ -187,4 +196,4 @@ def uccsd_rotations(n_qubits: int, n_electrons: int) -> RotationList:
         ps.append(np.full(len(order), idx, dtype=np.int32))
         ds.append(-2.0 * c.imag[order])
     return RotationList(n_qubits, np.concatenate(xs), np.concatenate(zs), np.concatenate(ps),
-                        np.concatenate(ds), len(singles) + len(doubles))
+                        np.concatenate(ds), len(seq))

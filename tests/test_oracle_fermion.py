@@ -142,3 +142,30 @@ def test_variational_bound_n8():
         e, nrm = sv.expectation(psi, [k[0] for k in terms], [k[1] for k in terms], list(terms.values()))
         assert e.real >= e0 - 1e-12
         assert abs(nrm - 1) < 1e-13
+
+
+@pytest.mark.parametrize("n,ne", [(4, 2), (8, 4), (12, 6), (20, 10), (26, 13), (28, 14)])
+def test_tile_order_is_a_permutation(n, ne):
+    from workloads import uccsd_excitation_order
+    tile = uccsd_excitation_order(n, ne, "tile")
+    singles, doubles = fermion.uccsd_excitations(n, ne)
+    assert sorted(tile) == sorted(singles + doubles)
+    assert all(len(e) == 2 for e in tile[:len(singles)])          # singles first
+    assert uccsd_excitation_order(n, ne, "lex") == singles + doubles
+
+
+@pytest.mark.parametrize("n,ne", [(6, 3), (8, 4)])
+def test_tile_order_rotation_list_equals_fermionic_exponentials(n, ne):
+    from workloads import uccsd_excitation_order
+    order = uccsd_excitation_order(n, ne, "tile")
+    rots = fermion.uccsd_rotations(n, ne, order)
+    theta = uniform_amplitudes(len(order), 0.3, 91 + n)
+    psi = sv.basis_state(n, fermion.hf_index(ne))
+    psi = sv.apply_rotations(psi, [r[0] for r in rots], [r[1] for r in rots], [d * theta[p] for _, _, p, d in rots])
+    basis, ref = fermion.ucc_state_fermionic(n, ne, theta, order=order)
+    assert np.abs(psi[basis] - ref).max() < 1e-12
+
+
+def test_order_validation():
+    with pytest.raises(ValueError):
+        fermion.uccsd_rotations(4, 2, [(0, 2), (1, 3)])

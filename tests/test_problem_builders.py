@@ -1,0 +1,43 @@
+"""The product's host builders (JW Pauli sum, UCCSD rotation list) against
+the oracle's independent Pauli-algebra builders (CPU only)."""
+import numpy as np
+import pytest
+
+from oracle import fermion
+from paper_2208_10978_amd.problem import jordan_wigner, uccsd_rotations
+from workloads import synthetic_integrals, uccsd_excitation_order
+
+
+@pytest.mark.parametrize("n", [4, 8, 12])
+def test_jordan_wigner_matches_oracle(n):
+    h, eri = synthetic_integrals(n, 1000 + n)
+    got = jordan_wigner(h, eri)
+    want = fermion.jw_hamiltonian(h, eri)
+    d = {(int(a), int(b)): c for a, b, c in zip(got.x, got.z, got.c)}
+    assert set(d) == set(want)
+    assert max(abs(d[k] - want[k]) for k in want) < 1e-13
+
+
+def test_truncation_keeps_identity_and_strict_threshold():
+    h, eri = synthetic_integrals(12, 1012)
+    full = jordan_wigner(h, eri)
+    t = full.truncated(1e-3)
+    assert ((t.x == 0) & (t.z == 0)).any()
+    assert (np.abs(t.c[(t.x != 0) | (t.z != 0)]) > 1e-3).all()
+    assert len(t) < len(full)
+
+
+@pytest.mark.parametrize("n,ne,order", [(4, 2, "lex"), (8, 4, "lex"), (8, 4, "tile"), (12, 6, "tile"), (10, 5, "tile")])
+def test_uccsd_rotations_match_oracle(n, ne, order):
+    seq = uccsd_excitation_order(n, ne, order)
+    got = uccsd_rotations(n, ne, order)
+    want = fermion.uccsd_rotations(n, ne, seq)
+    assert len(got) == len(want)
+    for k, (x, z, p, d) in enumerate(want):
+        assert (int(got.x[k]), int(got.z[k]), int(got.param[k])) == (x, z, p)
+        assert abs(got.dphi_dtheta[k] - d) < 1e-15
+
+
+def test_28_qubit_counts():
+    rot = uccsd_rotations(28, 14)
+    assert len(rot) == 26460 and rot.n_params == 3381
