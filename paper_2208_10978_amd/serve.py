@@ -1,0 +1,185 @@
+"""Continuous-batching request loop for UCCSD energy + gradient evaluations.
+
+Requests arrive with their own qubit count, Hamiltonian and amplitudes.  The
+server keeps every admitted request's state vectors and Hamiltonian resident
+in HBM, admits a waiting request as soon as a slot is free and its bytes fit
+the HBM budget (in arrival order; a request that does not fit yet may be
+passed by a smaller one that does), and runs each admitted request on its own
+HIP stream, so the work of requests in flight together overlaps on the
+device.  A request's arithmetic (its plans and reduction orders) depends only
+on the request, so its result is bitwise the same alone and in any mix.
+
+Host-side preparation (the JW Pauli sum and the rotation list) runs in a
+thread pool ahead of admission.  ``fifo=True`` gives the one-request-at-a-
+time baseline on the same trace.  The device work is behind an executor
+(``GpuExecutor``); the scheduling logic itself is plain Python.
+"""
+from __future__ import annotations
+
+import concurrent.futures as cf
+import time
+from dataclasses import dataclass
+
+import numpy as np
+
+from .problem import PauliSum, RotationList, jordan_wigner, uccsd_rotations
+
+
+@dataclass
+class Request:
+    rid: int
+    n_qubits: int
+    n_electrons: int
+    h_seed: int
+    theta_seed: int
+    t_arrival: float = 0.0          # seconds after the start of the trace
+    theta_amplitude: float = 0.05
+    dtype: str = "c64"
+    # filled by the server
+    ham: PauliSum | None = None
+    rot: RotationList | None = None
+    theta: np.ndarray | None = None
+    energy: float | None = None
+    norm: float | None = None
+    grad: np.ndarray | None = None
+    error: str | None = None
+    t_admit: float | None = None
+    t_done: float | None = None
+
+    @property
+    def latency(self):
+        return None if self.t_done is None else self.t_done - self.t_arrival
+
+    def device_bytes(self) -> int:
+        amp = 16 if self.dtype == "c128" else 8
+        n_amp = 1 << self.n_qubits
+        # psi + lam + resident FP64 diagonal + tables and reduction partials
+        return 2 * n_amp * amp + n_amp * 8 + (64 << 20)
+
+
+def prepare(req: Request) -> Request:
+    """Host-side problem build (no device work)."""
+    from workloads import synthetic_integrals, uniform_amplitudes
+    if not 0 < req.n_electrons <= req.n_qubits or req.n_qubits % 2:
+        raise ValueError(f"bad request: {req.n_qubits} qubits, {req.n_electrons} electrons")
+    h, eri = synthetic_integrals(req.n_qubits, req.h_seed)
+    req.ham = jordan_wigner(h, eri)
+    req.rot = uccsd_rotations(req.n_qubits, req.n_electrons, "tile")
+    req.theta = np.asarray(uniform_amplitudes(req.rot.n_params, req.theta_amplitude, req.theta_seed))
+    if not np.all(np.isfinite(req.theta)):
+        raise ValueError("non-finite amplitudes")
+    return req
+
+
+class GpuExecutor:
+    """Launches a request on its own HIP stream; completion via a HIP event."""
+
+    class Job:
+        def __init__(self, req):
+            import torch
+            from .engine import UCCSDEvaluator
+            self.stream = torch.cuda.Stream()
+            with torch.cuda.stream(self.stream):
+                self.ev = UCCSDEvaluator(req.ham, req.rot, req.n_electrons, req.dtype, stream=self.stream)
+                e, g = self.ev.energy_and_grad(req.theta)
+                self.e_host = torch.empty(2, dtype=torch.float64, pin_memory=True)
+                self.g_host = torch.empty(req.rot.n_params, dtype=torch.float64, pin_memory=True)
+                self.e_host.copy_(e, non_blocking=True)
+                self.g_host.copy_(g, non_blocking=True)
+                self.done = torch.cuda.Event()
+                self.done.record(self.stream)
+
+        def ready(self) -> bool:
+            return self.done.query()
+
+        def result(self):
+            out = float(self.e_host[0]), float(self.e_host[1]), self.g_host.numpy().copy()
+            self.ev.free()
+            return out
+
+    def budget(self) -> int:
+        import torch
+        free, _ = torch.cuda.mem_get_info()
+        return int(free * 0.8)
+
+    def launch(self, req):
+        return GpuExecutor.Job(req)
+
+
+class Server:
+    def __init__(self, executor=None, hbm_budget_bytes: int | None = None, max_slots: int = 8,
+                 prep_workers: int = 4, fifo: bool = False):
+        self.ex = executor if executor is not None else GpuExecutor()
+        self.budget = int(hbm_budget_bytes if hbm_budget_bytes is not None else self.ex.budget())
+        self.max_slots = 1 if fifo else int(max_slots)
+        self.pool = cf.ThreadPoolExecutor(max_workers=prep_workers)
+        self.fifo = fifo
+        self.peak_bytes = 0
+        self.peak_slots = 0
+
+    def run(self, requests, realtime: bool = True, on_done=None):
+        """Serve a trace.  With ``realtime`` a request becomes visible at its
+        arrival time (relative to the start); otherwise all are present at
+        once.  Returns the requests with results and timestamps."""
+        reqs = sorted(requests, key=lambda r: (r.t_arrival, r.rid))
+        for r in reqs:
+            if r.device_bytes() > self.budget:
+                r.error = "request can never fit the HBM budget"
+        futures = {r.rid: self.pool.submit(prepare, r) for r in reqs if r.error is None}
+        t0 = time.perf_counter()
+        waiting: list = []
+        active: list = []
+        used = 0
+        nxt = 0
+        n_done = sum(1 for r in reqs if r.error is not None)
+        while n_done < len(reqs):
+            now = time.perf_counter() - t0
+            while nxt < len(reqs) and (not realtime or reqs[nxt].t_arrival <= now):
+                if reqs[nxt].error is None:
+                    waiting.append(reqs[nxt])
+                nxt += 1
+            for job, r in list(active):  # completions
+                if job.ready():
+                    r.energy, r.norm, r.grad = job.result()
+                    r.t_done = time.perf_counter() - t0
+                    used -= r.device_bytes()
+                    active.remove((job, r))
+                    n_done += 1
+                    if on_done:
+                        on_done(r)
+            i = 0  # admissions
+            while i < len(waiting) and len(active) < self.max_slots:
+                r = waiting[i]
+                fut = futures[r.rid]
+                if not fut.done() or used + r.device_bytes() > self.budget:
+                    if self.fifo:
+                        break
+                    i += 1
+                    continue
+                waiting.pop(i)
+                try:
+                    fut.result()
+                    r.t_admit = time.perf_counter() - t0
+                    active.append((self.ex.launch(r), r))
+                    used += r.device_bytes()
+                    self.peak_bytes = max(self.peak_bytes, used)
+                    self.peak_slots = max(self.peak_slots, len(active))
+                except Exception as exc:  # a malformed request fails alone
+                    r.error = f"{type(exc).__name__}: {exc}"
+                    r.t_done = time.perf_counter() - t0
+                    n_done += 1
+            if not active and not waiting and nxt < len(reqs) and realtime:
+                time.sleep(max(0.0, min(0.01, reqs[nxt].t_arrival - (time.perf_counter() - t0))))
+            else:
+                time.sleep(0.0002)
+        return reqs
+
+
+def latency_stats(reqs):
+    ok = [r for r in reqs if r.error is None and r.t_done is not None]
+    if not ok:
+        return {}
+    lat = np.array([r.latency for r in ok])
+    span = max(r.t_done for r in ok) - min(r.t_arrival for r in ok)
+    return {"requests": len(ok), "p50_s": float(np.percentile(lat, 50)), "p99_s": float(np.percentile(lat, 99)),
+            "mean_s": float(lat.mean()), "evals_per_s": float(len(ok) / span) if span > 0 else None}

@@ -1,0 +1,114 @@
+"""GPU checks at the full workload sizes, where the oracle cannot run the whole
+state: closed forms and invariants that hold at any size (computed by the
+oracle on single determinants), and finite differences of the GPU energy.
+
+28 qubits, complex128 (two 4 GiB states + a 2 GiB diagonal)."""
+import numpy as np
+import pytest
+import torch
+
+from oracle import fermion
+from paper_2208_10978_amd.engine import StateVector, UCCSDEvaluator
+from paper_2208_10978_amd.problem import PauliSum, jordan_wigner, uccsd_rotations
+from tests.gpu_common import announce
+from workloads import synthetic_integrals, uccsd_excitation_order, uniform_amplitudes
+
+pytestmark = pytest.mark.gpu
+
+N, NE = 28, 14
+
+
+@pytest.fixture(scope="module")
+def problem():
+    announce("28-qubit problem setup")
+    h, eri = synthetic_integrals(N, 1000 + N)
+    ham = jordan_wigner(h, eri)                 # untruncated: closed forms use the full integrals
+    order = uccsd_excitation_order(N, NE, "tile")
+    rot = uccsd_rotations(N, NE, order)
+    ev = UCCSDEvaluator(ham, rot, NE, "c128")
+    hf = fermion.hf_index(NE)
+    row = fermion.hamiltonian_on_basis_state(h, eri, hf)
+    yield {"h": h, "eri": eri, "ham": ham, "rot": rot, "order": order, "ev": ev, "hf": hf, "row": row}
+    ev.free()
+
+
+def test_hf_energy_and_gradient_at_zero(problem):
+    """E(0) = Slater-Condon E_HF; dE/dtheta_X(0) = 2 <HF|H tau_X|HF> for all X."""
+    announce("28q theta=0")
+    ev, row, hf = problem["ev"], problem["row"], problem["hf"]
+    e_hf = fermion.slater_condon_hf_energy(problem["h"], problem["eri"], NE)
+    e, g = ev.energy_and_grad(np.zeros(ev.rot.n_params))
+    torch.cuda.synchronize()
+    e = e.cpu().numpy()
+    g = g.cpu().numpy()
+    assert abs(e[0] - e_hf) <= 1e-12 * abs(e_hf)
+    assert abs(e[1] - 1.0) <= 1e-14
+    want = np.zeros(len(g))
+    for idx, exc in enumerate(problem["order"]):
+        kx, sgn = fermion.excited_determinant(exc, NE)
+        want[idx] = 2.0 * sgn * row.get(kx, 0.0)
+    assert np.abs(g - want).max() <= 1e-12 * max(1.0, np.abs(want).max())
+
+
+@pytest.mark.parametrize("which", [0, 50, 2000])
+def test_single_excitation_closed_form(problem, which):
+    """One nonzero amplitude: psi = cos th |HF> + sin th tau|HF>; two
+    amplitudes change and E follows the 2x2 closed form."""
+    announce(f"28q single excitation {which}")
+    ev, row, hf = problem["ev"], problem["row"], problem["hf"]
+    exc = problem["order"][which]
+    kx, sgn = fermion.excited_determinant(exc, NE)
+    e_hf = row[hf]
+    e_x = fermion.hamiltonian_on_basis_state(problem["h"], problem["eri"], kx)[kx]
+    h0x = sgn * row.get(kx, 0.0)
+    th = 0.3
+    theta = np.zeros(ev.rot.n_params)
+    theta[which] = th
+    e = ev.energy(theta).cpu().numpy()
+    amps = ev.psi.amplitudes([hf, kx]).cpu().numpy()
+    want = np.cos(th) ** 2 * e_hf + np.sin(th) ** 2 * e_x + 2 * np.sin(th) * np.cos(th) * h0x
+    assert abs(e[0] - want) <= 1e-12 * abs(want)
+    assert np.allclose(amps, [np.cos(th), 0.0, sgn * np.sin(th), 0.0], atol=1e-14)
+
+
+def test_invariants_and_finite_differences(problem):
+    """Random amplitudes: unit norm, <N> = n_e, <S_z> = 0, Var(N) = 0, the
+    reverse sweep returns psi to |HF>, and the adjoint gradient agrees with a
+    4-point finite difference of the GPU energy on 8 seeded parameters."""
+    announce("28q random theta")
+    ev = problem["ev"]
+    theta = uniform_amplitudes(ev.rot.n_params, 0.02, 2000 + N)
+    ev.forward_state(theta)
+    one = np.uint64(1)
+    zq = np.array([one << np.uint64(q) for q in range(N)], dtype=np.uint64)
+    zero = np.zeros(N, dtype=np.uint64)
+    # N = n/2 - 1/2 sum Z_q ; S_z = 1/4 sum_p (Z_{2p+1} - Z_{2p})
+    nx = np.concatenate([[0], zero]).astype(np.uint64)
+    nz = np.concatenate([[0], zq]).astype(np.uint64)
+    num = ev.psi.expect_terms(nx, nz, np.concatenate([[N / 2], -0.5 * np.ones(N)])).cpu().numpy()
+    sz = ev.psi.expect_terms(zero, zq, np.array([0.25 if q % 2 else -0.25 for q in range(N)])).cpu().numpy()
+    # N^2 = n^2/4 + n/4 - (n/2) sum Z_q + 1/2 sum_{q<r} Z_q Z_r
+    pz = [0] + [1 << q for q in range(N)] + [(1 << q) | (1 << r) for q in range(N) for r in range(q + 1, N)]
+    pc = [N * N / 4 + N / 4] + [-N / 2] * N + [0.5] * (N * (N - 1) // 2)
+    n2 = ev.psi.expect_terms(np.zeros(len(pz), dtype=np.uint64), np.array(pz, dtype=np.uint64),
+                             np.array(pc)).cpu().numpy()
+    assert abs(num[1] - 1.0) < 1e-12
+    assert abs(num[0] - NE) < 1e-10
+    assert abs(sz[0]) < 1e-10
+    assert abs(n2[0] - NE * NE) < 1e-8
+
+    e0, g = ev.energy_and_grad(theta)
+    g = g.cpu().numpy().copy()
+    back = ev.psi.amplitudes([problem["hf"]]).cpu().numpy()
+    assert abs(back[0] - 1.0) < 1e-12 and abs(back[1]) < 1e-12
+    rng = np.random.default_rng(3000 + N)
+    picks = rng.choice(ev.rot.n_params, size=8, replace=False)
+    d = 1e-3
+    for p in picks:
+        vals = []
+        for s in (2, 1, -1, -2):
+            th = theta.copy()
+            th[p] += s * d
+            vals.append(ev.energy(th)[0].item())
+        fd = (-vals[0] + 8 * vals[1] - 8 * vals[2] + vals[3]) / (12 * d)
+        assert abs(fd - g[p]) <= 1e-9 + 1e-6 * abs(g[p]), (p, fd, g[p])

@@ -1,0 +1,42 @@
+"""Serving loop on the GPU: every request's energy and gradient are bitwise
+the same alone and in a mix of concurrent requests, and match the oracle."""
+import numpy as np
+import pytest
+
+from oracle import fermion
+from oracle import statevector as osv
+from paper_2208_10978_amd.serve import Request, Server, latency_stats
+from tests.gpu_common import announce
+from workloads import synthetic_integrals
+
+pytestmark = pytest.mark.gpu
+
+
+def trace():
+    sizes = [8, 12, 10, 14, 8, 12, 16, 10]
+    return [Request(rid=r, n_qubits=n, n_electrons=n // 2, h_seed=10 ** 6 + r, theta_seed=2 * 10 ** 6 + r,
+                    t_arrival=0.01 * r, theta_amplitude=0.05, dtype=("c64" if r % 2 else "c128"))
+            for r, n in enumerate(sizes)]
+
+
+def test_alone_equals_mix_and_oracle():
+    announce("serve mix")
+    mixed = Server(max_slots=6).run(trace(), realtime=True)
+    stats = latency_stats(mixed)
+    announce(f"serve stats {stats}")
+    for r in mixed:
+        assert r.error is None, r.error
+        alone = Server(max_slots=1).run([Request(r.rid, r.n_qubits, r.n_electrons, r.h_seed, r.theta_seed,
+                                                 0.0, r.theta_amplitude, r.dtype)], realtime=False)[0]
+        assert alone.energy == r.energy
+        assert np.array_equal(alone.grad, r.grad)
+    # spot-check two requests against the oracle
+    for r in (mixed[0], mixed[1]):
+        h, eri = synthetic_integrals(r.n_qubits, r.h_seed)
+        ph = r.rot.angles(r.theta)
+        e_ref, g_rot = osv.reverse_mode_gradient(osv.basis_state(r.n_qubits, fermion.hf_index(r.n_electrons)),
+                                                 r.ham.x, r.ham.z, r.ham.c, r.rot.x, r.rot.z, ph)
+        g_ref = osv.chain_to_parameters(g_rot, r.rot.param, r.rot.dphi_dtheta, r.rot.n_params)
+        tol = 1e-10 if r.dtype == "c128" else 1e-5
+        assert abs(r.energy - e_ref) <= tol * abs(e_ref)
+        assert np.abs(r.grad - g_ref).max() <= tol * 10 * max(1.0, np.abs(g_ref).max())

@@ -1,0 +1,101 @@
+"""Scheduling logic of the serving loop on the CPU, with a fake executor (a
+test double that evaluates requests with the FP64 oracle and completes them
+after a simulated device time).  No product path runs here."""
+import time
+
+import numpy as np
+
+from oracle import statevector as osv
+from paper_2208_10978_amd.serve import Request, Server, latency_stats
+
+
+class FakeExecutor:
+    def __init__(self, device_time=0.02, budget=10 ** 12):
+        self.device_time = device_time
+        self._budget = budget
+        self.launch_order = []
+        self.live = 0
+        self.max_live = 0
+
+    def budget(self):
+        return self._budget
+
+    class Job:
+        def __init__(self, ex, req):
+            self.ex, self.req = ex, req
+            self.t_ready = time.perf_counter() + ex.device_time
+            phi = req.rot.angles(req.theta)
+            e, g = osv.reverse_mode_gradient(osv.basis_state(req.n_qubits, (1 << req.n_electrons) - 1),
+                                             req.ham.x, req.ham.z, req.ham.c, req.rot.x, req.rot.z, phi)
+            self.out = (e, 1.0, osv.chain_to_parameters(g, req.rot.param, req.rot.dphi_dtheta, req.rot.n_params))
+
+        def ready(self):
+            return time.perf_counter() >= self.t_ready
+
+        def result(self):
+            self.ex.live -= 1
+            return self.out
+
+    def launch(self, req):
+        self.launch_order.append(req.rid)
+        self.live += 1
+        self.max_live = max(self.max_live, self.live)
+        return FakeExecutor.Job(self, req)
+
+
+def trace(k=8, gap=0.005):
+    return [Request(rid=r, n_qubits=(4, 6)[r % 2], n_electrons=(2, 3)[r % 2], h_seed=100 + r, theta_seed=200 + r,
+                    t_arrival=r * gap, theta_amplitude=0.3) for r in range(k)]
+
+
+def test_results_identical_alone_and_in_the_mix():
+    mixed = Server(FakeExecutor(), max_slots=4).run(trace(), realtime=True)
+    for r in trace():
+        alone = Server(FakeExecutor(), max_slots=1).run([r], realtime=False)[0]
+        m = next(x for x in mixed if x.rid == r.rid)
+        assert m.error is None and alone.error is None
+        assert m.energy == alone.energy
+        assert np.array_equal(m.grad, alone.grad)
+
+
+def test_slots_and_budget_are_respected():
+    ex = FakeExecutor(device_time=0.05)
+    one = Request(0, 6, 3, 1, 1).device_bytes()
+    srv = Server(ex, hbm_budget_bytes=3 * one, max_slots=8)
+    out = srv.run(trace(10, gap=0.0), realtime=False)
+    assert all(r.error is None for r in out)
+    assert srv.peak_bytes <= 3 * one and ex.max_live <= 3
+    srv2 = Server(FakeExecutor(device_time=0.05), max_slots=2)
+    srv2.run(trace(6, gap=0.0), realtime=False)
+    assert srv2.peak_slots <= 2
+
+
+def test_requests_that_cannot_fit_or_are_malformed_fail_alone():
+    reqs = trace(4)
+    reqs.append(Request(rid=100, n_qubits=30, n_electrons=15, h_seed=1, theta_seed=1, t_arrival=0.0))
+    reqs.append(Request(rid=101, n_qubits=6, n_electrons=9, h_seed=1, theta_seed=1, t_arrival=0.001))
+    one = Request(0, 6, 3, 1, 1).device_bytes()
+    out = Server(FakeExecutor(), hbm_budget_bytes=4 * one, max_slots=4).run(reqs, realtime=True)
+    by = {r.rid: r for r in out}
+    assert "never fit" in by[100].error
+    assert "bad request" in by[101].error
+    assert all(by[r].error is None and by[r].energy is not None for r in range(4))
+
+
+def test_fifo_runs_one_at_a_time_in_arrival_order():
+    ex = FakeExecutor(device_time=0.01)
+    out = Server(ex, fifo=True).run(trace(6, gap=0.0), realtime=False)
+    assert ex.launch_order == list(range(6)) and ex.max_live == 1
+    assert all(r.error is None for r in out)
+
+
+def test_continuous_batching_admits_while_others_run():
+    ex = FakeExecutor(device_time=0.2)
+    reqs = trace(4, gap=0.05)
+    out = Server(ex, max_slots=4).run(reqs, realtime=True)
+    first = next(r for r in out if r.rid == 0)
+    later = [r for r in out if r.rid > 0]
+    assert any(r.t_admit < first.t_done for r in later)     # admitted before the first finished
+    assert ex.max_live >= 2
+    stats = latency_stats(out)
+    assert stats["requests"] == 4 and stats["p99_s"] >= stats["p50_s"] > 0
