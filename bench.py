@@ -83,6 +83,59 @@ def cpu_baseline(n, ham, rot, theta):
     }
 
 
+def bench_c4(n_rot: int, n_terms: int):
+    """32 qubits, complex64 (32 GiB): a prefix of the random 4-qubit-support
+    rotation stream and the expectation of a random weight<=4 Pauli sum."""
+    import torch
+    from paper_2208_10978_amd import binding as B
+    from paper_2208_10978_amd.engine import Hamiltonian, StateVector
+    from paper_2208_10978_amd.problem import PauliSum
+    from workloads import random_pauli_sum, random_rotations
+
+    n = 32
+    log(f"C4: allocating a {n}-qubit complex64 state (32 GiB)")
+    s = StateVector(n, "c64")
+    x, z, phi = random_rotations(n, n_rot, 4242)
+    hx, hz, hc = random_pauli_sum(n, n_terms, 4343)
+    ham = Hamiltonian(PauliSum(n, hx, hz, hc))
+    s.prepare_hf((1 << 16) - 1)
+    s.apply_rotations(x[:64], z[:64], phi[:64])       # warm-up (plans, code load)
+    out = s.expect(ham)                               # builds the tiling and the diagonal
+    torch.cuda.synchronize()
+    B.sv_profile_begin()
+    t0 = time.perf_counter()
+    s.apply_rotations(x, z, phi)
+    torch.cuda.synchronize()
+    t_rot = time.perf_counter() - t0
+    prof_rot = B.sv_profile_end()
+    B.sv_profile_begin()
+    t0 = time.perf_counter()
+    out = s.expect(ham)
+    torch.cuda.synchronize()
+    t_exp = time.perf_counter() - t0
+    prof_exp = B.sv_profile_end()
+    norm = float(out[1].item())
+    groups = int(np.unique(hx).shape[0])
+    rot_bytes = sum(v["bytes"] for v in prof_rot.values())
+    rot_ms = sum(v["ms"] for v in prof_rot.values())
+    res = {
+        "workload": f"{n_rot}-rotation prefix of the 10^5-rotation stream + {n_terms}-term expectation, "
+                    f"{n} qubits complex64",
+        "rotations_per_s": n_rot / t_rot,
+        "rotation_passes": int(sum(v["launches"] for k, v in prof_rot.items() if k in
+                                   ("k_run_full", "k_tile_forward"))),
+        "rotation_sweep_GB_s": rot_bytes / (rot_ms / 1e3) / 1e9 if rot_ms else None,
+        "rotation_sweep_hbm_frac": (rot_bytes / (rot_ms / 1e3) / 1e9) / HBM_PEAK_GBS if rot_ms else None,
+        "expectation_s": t_exp,
+        "x_groups_per_s": groups / t_exp,
+        "expectation_kernels": {k: {"ms": round(v["ms"], 3), "launches": v["launches"]} for k, v in prof_exp.items()},
+        "norm_after": norm,
+    }
+    s.free()
+    ham.free()
+    return res
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -91,6 +144,8 @@ def main():
     ap.add_argument("--qubits", type=int, default=28)
     ap.add_argument("--dtype", default="c128", choices=["c128", "c64"])
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-c4", action="store_true", help="skip the 32-qubit complex64 raw-sweep figures")
+    ap.add_argument("--c4-rotations", type=int, default=1000)
     args = ap.parse_args()
     if args.gpus != 1:
         print(json.dumps({"error": "this build runs on one GPU only; --gpus must be 1"}))
@@ -188,6 +243,10 @@ def main():
         "kernels": kernels,
     }
     ev.free()
+    del ev
+    torch.cuda.empty_cache()
+    if not args.no_c4:
+        result["c4"] = bench_c4(args.c4_rotations, 10_000)
     if not args.no_cpu_baseline:
         log("timing the oracle sample on the host")
         result["cpu_baseline"] = cpu_baseline(n, ham, rot, theta)

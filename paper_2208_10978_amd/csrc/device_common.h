@@ -66,6 +66,12 @@ __device__ __forceinline__ uint32_t insert_zeros32(uint32_t t, uint64_t pack, in
   return t;
 }
 
+// As above for frame-local positions (< 16) packed four bits each (up to 16).
+__device__ __forceinline__ uint32_t insert_zeros32_p4(uint32_t t, uint64_t pack, int n) {
+  for (int j = 0; j < n; ++j) t = insert_zero32(t, unsigned(pack >> (4 * j)) & 0xfu);
+  return t;
+}
+
 // ---------------------------------------------------------------------------
 // deterministic FP64 reductions
 // ---------------------------------------------------------------------------

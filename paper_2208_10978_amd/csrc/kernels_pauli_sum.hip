@@ -80,12 +80,12 @@ __global__ void __launch_bounds__(NT) k_tile_lambda(const T* __restrict__ psi, T
   for (uint32_t m = wbm; m; m &= m - 1) {
     const int p = __ffs(m) - 1;
     wbits |= uint32_t((wave >> nwb) & 1) << p;
-    wpack |= uint64_t(p) << (8 * nwb);
+    wpack |= uint64_t(p) << (4 * nwb);
     ++nwb;
   }
   const bool owner = wave < (1 << nwb);
   const uint32_t nreg = nloc >> nwb;
-  auto region_l = [&](uint32_t i) { return insert_zeros32(i, wpack, nwb) | wbits; };
+  auto region_l = [&](uint32_t i) { return insert_zeros32_p4(i, wpack, nwb) | wbits; };
 
   Stage<T, PER> rp;
   Stage<T, RPER> rl;
@@ -158,11 +158,11 @@ __global__ void __launch_bounds__(NT) k_tile_lambda(const T* __restrict__ psi, T
         };
         if (nf <= 6) {
           const uint32_t t = uint32_t(lane) & ((1u << nf) - 1u);
-          const uint32_t ob = insert_zeros32(t, g.ins_pack, g.n_ins);
+          const uint32_t ob = insert_zeros32_p4(t, g.ins_pack, g.n_ins);
           for (uint32_t j = uint32_t(lane) >> nf; j < g.n_out; j += (64u >> nf)) emit(ob, j);
         } else {
           for (uint32_t t = uint32_t(lane); t < (1u << nf); t += 64u) {
-            const uint32_t ob = insert_zeros32(t, g.ins_pack, g.n_ins);
+            const uint32_t ob = insert_zeros32_p4(t, g.ins_pack, g.n_ins);
             for (uint32_t j = 0; j < g.n_out; ++j) emit(ob, j);
           }
         }
@@ -221,7 +221,7 @@ __global__ void __launch_bounds__(NT) k_tile_expect(const T* __restrict__ psi, c
       for (uint32_t idx = threadIdx.x; idx < np; idx += NT) {
         const uint32_t r = idx >> ns, t = idx & ((1u << ns) - 1u);
         const TOut o = bv.outs[g.out_off + r];  // the first n_rec outputs are the records (m')
-        const uint32_t l2 = insert_zeros32(t, g.sins_pack, g.n_sins) | o.bits;
+        const uint32_t l2 = insert_zeros32_p4(t, g.sins_pack, g.n_sins) | o.bits;
         const uint32_t l = l2 ^ g.x_loc;
         double gre, gim;
         group_coef(bv, g, o, l2, base, gre, gim);  // o is m': conj(G); undo below

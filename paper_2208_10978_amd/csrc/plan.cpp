@@ -401,10 +401,10 @@ static void pack_blob(HTiling& t, const std::vector<HGroup>& gs, const std::vect
     d.sub_off = uint16_t(ts.size());
     d.coef_off = uint32_t(co.size() / 2);
     int k = 0;
-    for (uint32_t m = smask; m; m &= m - 1) d.sins_pack |= uint64_t(__builtin_ctz(m)) << (8 * k++);
+    for (uint32_t m = smask; m; m &= m - 1) d.sins_pack |= uint64_t(__builtin_ctz(m)) << (4 * k++);
     d.n_sins = uint8_t(k);
     k = 0;
-    for (uint32_t m = smask | wb_mask; m; m &= m - 1) d.ins_pack |= uint64_t(__builtin_ctz(m)) << (8 * k++);
+    for (uint32_t m = smask | wb_mask; m; m &= m - 1) d.ins_pack |= uint64_t(__builtin_ctz(m)) << (4 * k++);
     d.n_ins = uint8_t(k);
     std::vector<uint32_t> rec_loc(NR);
     for (int r = 0; r < NR; ++r) rec_loc[r] = g.enumerated ? uint32_t(compress(g.rec_v[r], qmask)) : smask;

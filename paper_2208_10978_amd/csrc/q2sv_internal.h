@@ -137,7 +137,7 @@ struct alignas(8) TGroup {
   uint8_t n_ins;       // zero insertions (S' union Wb, ascending) for lambda outputs
   uint8_t n_sins;      // zero insertions (S', ascending) for pairs
   uint8_t pad;
-  uint64_t ins_pack;   // their positions, one byte each
+  uint64_t ins_pack;   // their frame-local positions, four bits each
   uint64_t sins_pack;
 };
 
