@@ -240,7 +240,10 @@ static int tiling_get(sv_hamiltonian* h, int dtype, int role, DevTiling** out) {
   if (!h->built[dtype][role]) {
     const int b = role == 0 ? tile_bits_one(dtype) : tile_bits_lambda(dtype);
     const int c = std::min(dtype == 0 ? 3 : 4, h->n);
-    t.host = build_tiling(h->groups, h->n, b, c, role == 1 ? kLambdaRegionBits : 0);
+    // expectation blobs are staged in LDS; lambda reads its tables through
+    // scalar loads, so a tile's groups need not be split
+    t.host = build_tiling(h->groups, h->n, b, c, role == 1 ? kLambdaRegionBits : 0,
+                          role == 1 ? size_t(1) << 20 : size_t(kBlobWords) * 16);
     if (t.host.blob_overflow) return fail(SV_EINVAL, "internal: a tile's group tables exceed the LDS budget");
     Packer pk;
     t.o_frames = pk.add(t.host.frames.data(), t.host.frames.size() * sizeof(FrameDesc));
@@ -413,7 +416,7 @@ static void plan_rotations(const sv_state* s, const sv_pauli* p, const double* p
   const int c = std::min(s->dtype == 0 ? 3 : 4, s->n);
   const int slots_per_run = grad_mode == 1 ? 1 : 0;
   pl.passes = schedule(pl.runs, pl.data, s->n, b, c, reverse, reverse && grad_mode ? kMaxPassSlots : 0,
-                       slots_per_run);
+                       slots_per_run, kMaxPassRuns, kMaxPassRecs);
 }
 
 // Launch a plan: forward (rev = false) or reverse with gradient partials.
@@ -424,10 +427,10 @@ static int launch_rotations(sv_state* s, sv_state* lam, const RotPlan& pl, bool 
   std::vector<RunDesc> descs;
   std::vector<RunRec> recs;
   std::vector<uint32_t> slot_maps;
-  struct PassOff { size_t desc0; int nruns; size_t slot0; int nslots; };
+  struct PassOff { size_t desc0; int nruns; size_t slot0; int nslots; size_t rec0; int nrecs; };
   std::vector<PassOff> po;
   for (const Pass& ps : pl.passes) {
-    PassOff o{descs.size(), int(ps.runs.size()), slot_maps.size(), 0};
+    PassOff o{descs.size(), int(ps.runs.size()), slot_maps.size(), 0, recs.size(), 0};
     int local = 0;
     for (int ri : ps.runs) {
       const Run& r = pl.runs[ri];
@@ -445,8 +448,10 @@ static int launch_rotations(sv_state* s, sv_state* lam, const RotPlan& pl, bool 
         slot = grad_mode == 1 ? uint32_t(ri) : uint32_t(r.first);
       }
       descs.push_back(make_run_desc(r, pl.data[ri], ps.qmask, slot, grad_mode == 2, recs));
+      if (ps.tile) descs.back().rec_off -= uint32_t(o.rec0);  // tile passes index their own records
     }
     o.nslots = local;
+    o.nrecs = int(recs.size() - o.rec0);
     po.push_back(o);
   }
   if (recs.empty()) recs.push_back(RunRec{});
@@ -469,12 +474,12 @@ static int launch_rotations(sv_state* s, sv_state* lam, const RotPlan& pl, bool 
       hipError_t e;
       ProfScope prof(s->stream, rev ? kPTileRev : kPTileFwd, (rev ? 4.0 : 2.0) * s->bytes());
       if (!rev)
-        e = launch_tile_forward(s->dtype, s->amps, fr, d_desc + po[i].desc0, po[i].nruns, d_recs, n_tb, grid,
-                                s->stream);
+        e = launch_tile_forward(s->dtype, s->amps, fr, d_desc + po[i].desc0, po[i].nruns, d_recs + po[i].rec0,
+                                po[i].nrecs, n_tb, grid, s->stream);
       else
         e = launch_tile_reverse(s->dtype, grad_mode, s->amps, lam_amps, fr, d_desc + po[i].desc0, po[i].nruns,
-                                d_recs, d_slot + po[i].slot0, po[i].nslots, partials, kPartialStride, n_tb, grid,
-                                s->stream);
+                                d_recs + po[i].rec0, po[i].nrecs, d_slot + po[i].slot0, po[i].nslots, partials,
+                                kPartialStride, n_tb, grid, s->stream);
       if (e != hipSuccess) return fail(SV_EDEVICE, std::string("tile pass launch: ") + hipGetErrorString(e));
     } else {
       const RunDesc& rd = descs[po[i].desc0];

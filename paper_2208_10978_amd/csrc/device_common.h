@@ -108,9 +108,14 @@ struct FrameLut {
   int c, k1, b;
 };
 
+// Deposit of the tile-block index into the complementary positions, walking
+// the set bits of the mask: with a uniform index this stays on the scalar
+// unit and touches no memory (a byte-table lookup would be a vector load,
+// whose wait would also drain the tile loads and stores in flight).
 __device__ __forceinline__ uint64_t frame_base(const FrameDesc& fr, uint64_t tb) {
   uint64_t base = 0;
-  for (int j = 0; j < fr.n_comp; ++j) base |= ((tb >> j) & 1ull) << fr.comp[j];
+  for (uint64_t m = fr.comp_mask; m; m &= m - 1, tb >>= 1)
+    if (tb & 1ull) base |= m & (~m + 1ull);
   return base;
 }
 

@@ -16,16 +16,18 @@ namespace q2sv {
 struct BlobView {
   const TileHdr* hdr;
   const TGroup* groups;
-  const TOut* outs;
+  const uint32_t* recs;
   const TSub* subs;
   const double2* coef;
+  const TFast* fast;
   __device__ explicit BlobView(const uint4* blob) {
     const char* b = reinterpret_cast<const char*>(blob);
     hdr = reinterpret_cast<const TileHdr*>(b);
     groups = reinterpret_cast<const TGroup*>(b + sizeof(TileHdr));
-    outs = reinterpret_cast<const TOut*>(b + hdr->off_out);
+    recs = reinterpret_cast<const uint32_t*>(b + hdr->off_rec);
     subs = reinterpret_cast<const TSub*>(b + hdr->off_sub);
     coef = reinterpret_cast<const double2*>(b + hdr->off_coef);
+    fast = reinterpret_cast<const TFast*>(b + hdr->off_fast);
   }
 };
 
@@ -35,45 +37,88 @@ __device__ __forceinline__ void blob_stage(const uint4* __restrict__ src, uint4*
   for (uint32_t i = threadIdx.x; i < words; i += NT) dst[i] = src[i];
 }
 
-// G of one output: sum over subgroups of (-1)^{|m' & w|} T_w[rec], conjugated
-// when the output is m'.
-__device__ __forceinline__ void group_coef(const BlobView& bv, const TGroup& g, const TOut& o, uint32_t mp,
-                                           uint64_t base, double& gre, double& gim) {
-  gre = 0.0;
-  gim = 0.0;
-  for (uint32_t k = 0; k < g.n_sub; ++k) {
-    const TSub sd = bv.subs[g.sub_off + k];
-    const double2 cv = bv.coef[g.coef_off + k * g.n_rec + o.rec];
-    const unsigned sg = parity32(mp & sd.w_loc) ^ parity64(base & sd.w_out);
-    gre += sg ? -cv.x : cv.x;
-    gim += sg ? -cv.y : cv.y;
-  }
-  if (o.is_mprime) gim = -gim;
-}
-
 // ---------------------------------------------------------------------------
 // lambda over one tile: MODE 1 lam = diag * psi + H_tile psi; MODE 2 lam += H_tile psi
+//
+// The tile's group tables stay in global memory: every index into them is
+// uniform over a wavefront, so they arrive through scalar loads into SGPRs
+// and feed the vector arithmetic directly.  Contributions land in the FP64
+// accumulator tile (real and imaginary parts in separate arrays) with LDS
+// atomic adds, which return nothing, so an update is never a load-modify-
+// store chain.  Each output is only ever touched by the one wavefront owning
+// its region, in program order, so the rounding order (and the result) is
+// fixed.
 // ---------------------------------------------------------------------------
+__device__ __forceinline__ void lds_add(double* p, double v) {
+  __hip_atomic_fetch_add(p, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
+}
+
+// x * (-1)^s for s in {0, 1}: flips the sign bit
+__device__ __forceinline__ double signed_by(double x, unsigned s) {
+  return __hiloint2double(__double2hiint(x) ^ int(s << 31), __double2loint(x));
+}
+
+// t with zero bits inserted at ascending positions p_j (lo[j] = 2^p_j - 1,
+// all ones for an unused slot): each step moves the bits at and above p_j up
+// by one and leaves a stray copy at p_j, cleared at the end by ins_mask.
+__device__ __forceinline__ uint32_t insert_zeros_lo(uint32_t t, const uint32_t (&lo)[kFastIns], uint32_t ins_mask) {
+#pragma unroll
+  for (int j = 0; j < kFastIns; ++j) t = (t & lo[j]) | ((t << 1) & ~lo[j]);
+  return t & ~ins_mask;
+}
+
+// The pairs (m', m = m' ^ x) of every record of a one-subgroup group at one
+// position of its free bits.  Which endpoints lie in this wavefront's region
+// is uniform (it depends on the record and the fixed region bits only); an
+// endpoint elsewhere sends its update to the lane's own dummy slot, so the
+// code has no branches and all loads issue before any use.
+template <int NR, typename T>
+__device__ __forceinline__ void fast_pairs(const TFast& f, uint32_t ob, uint32_t keep, uint32_t wbm, uint32_t wbits,
+                                           unsigned so, uint32_t dummy, const T* tp, double* tlr, double* tli) {
+  uint32_t lmp[NR];
+  T pm[NR], pp[NR];
+#pragma unroll
+  for (int r = 0; r < NR; ++r) {
+    lmp[r] = ob | f.bits[r];
+    pm[r] = tp[lmp[r] ^ f.x_loc];
+    pp[r] = tp[lmp[r]];
+  }
+#pragma unroll
+  for (int r = 0; r < NR; ++r) {
+    const unsigned sg = __popc(lmp[r] & f.w_loc) + so;
+    const double gre = signed_by(f.coef[2 * r], sg), gim = signed_by(f.coef[2 * r + 1], sg);
+    const uint32_t reg_mp = (keep | f.bits[r]) & wbm;  // region bits of m'
+    const uint32_t dm = ((reg_mp ^ f.x_loc) & wbm) == wbits ? lmp[r] ^ f.x_loc : dummy;
+    const uint32_t dmp = reg_mp == wbits ? lmp[r] : dummy;
+    lds_add(&tlr[dm], gre * (double)pp[r].x - gim * (double)pp[r].y);  // lam[m] += G psi[m']
+    lds_add(&tli[dm], gre * (double)pp[r].y + gim * (double)pp[r].x);
+    lds_add(&tlr[dmp], gre * (double)pm[r].x + gim * (double)pm[r].y);  // lam[m'] += conj(G) psi[m]
+    lds_add(&tli[dmp], gre * (double)pm[r].y - gim * (double)pm[r].x);
+  }
+}
+
 template <typename T, int B, int NT, int MODE>
 __global__ void __launch_bounds__(NT) k_tile_lambda(const T* __restrict__ psi, T* __restrict__ lam,
                                                     const double* __restrict__ diag, FrameDesc fr,
-                                                    const uint4* __restrict__ blob_g, uint64_t n_tb) {
+                                                    const uint4* __restrict__ blob, uint64_t n_tb) {
   using R = typename Real<T>::type;
   constexpr int NW = NT / 64;
   constexpr int PER = (1 << B) / NT;
   constexpr int RPER = ((1 << B) / NW + 63) / 64;
+  constexpr int NACC = (1 << B) + NT;  // accumulators, then one dummy slot per lane
   __shared__ T tp[1 << B];
-  __shared__ double2 tl[1 << B];
+  __shared__ double tlr[NACC], tli[NACC];
   __shared__ FrameLut lut;
-  __shared__ uint4 blob[kBlobWords];
-  blob_stage<NT>(blob_g, blob);
   frame_lut_init<NT>(fr, lut);
   __syncthreads();
   const BlobView bv(blob);
-  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  const int lane = threadIdx.x & 63;
+  const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+  const uint32_t dummy = (1u << B) + threadIdx.x;
   const uint32_t nloc = 1u << fr.b;
   // this wavefront's output region: frame bits wb_mask equal to `wave`
   const uint32_t wbm = bv.hdr->wb_mask;
+  const uint32_t n_groups = bv.hdr->n_groups, n_fast = bv.hdr->n_fast;
   uint64_t wpack = 0;
   int nwb = 0;
   uint32_t wbits = 0;
@@ -123,47 +168,76 @@ __global__ void __launch_bounds__(NT) k_tile_lambda(const T* __restrict__ psi, T
         const uint32_t i = uint32_t(lane) + 64u * k;
         if (i < nreg) {
           const uint32_t l = region_l(i);
-          double2 v;
           if (MODE == 1) {
             const T a = tp[l];
-            v.x = rd[k] * (double)a.x;
-            v.y = rd[k] * (double)a.y;
+            tlr[l] = rd[k] * (double)a.x;
+            tli[l] = rd[k] * (double)a.y;
           } else {
-            v.x = (double)rl.re[k];
-            v.y = (double)rl.im[k];
+            tlr[l] = (double)rl.re[k];
+            tli[l] = (double)rl.im[k];
           }
-          tl[l] = v;
         }
       }
     }
     const uint64_t nx = tb + gridDim.x;
     if (nx < n_tb) fetch(nx);
     if (owner) {
-      for (uint32_t gi = 0; gi < bv.hdr->n_groups; ++gi) {
-        const TGroup g = bv.groups[gi];
-        const uint32_t s_wb = g.sup_mask & wbm;
-        const int nf = int(fr.b) - int(g.n_ins);
-        auto emit = [&](uint32_t ob, uint32_t j) {
-          const TOut o = bv.outs[g.out_off + j];
-          if ((uint32_t(o.bits) ^ wbits) & s_wb) return;  // pattern lies in another region
-          const uint32_t l = ob | o.bits | (wbits & ~g.sup_mask);
-          const uint32_t src = l ^ g.x_loc;
-          double gre, gim;
-          group_coef(bv, g, o, o.is_mprime ? l : src, base, gre, gim);
-          const T a = tp[src];
-          double2 v = tl[l];
-          v.x += gre * (double)a.x - gim * (double)a.y;
-          v.y += gre * (double)a.y + gim * (double)a.x;
-          tl[l] = v;
-        };
-        if (nf <= 6) {
-          const uint32_t t = uint32_t(lane) & ((1u << nf) - 1u);
-          const uint32_t ob = insert_zeros32_p4(t, g.ins_pack, g.n_ins);
-          for (uint32_t j = uint32_t(lane) >> nf; j < g.n_out; j += (64u >> nf)) emit(ob, j);
-        } else {
+      // one-subgroup groups: a lane takes one position of the free bits (a
+      // "cube" over the support) and every record's pair there.  Region bits
+      // outside the support are inserted fixed: equal to this wavefront's bits
+      // for m', and, where x flips one of them, a second walk with them equal
+      // for m.
+      for (uint32_t fi = 0; fi < n_fast; ++fi) {
+        const TFast f = bv.fast[fi];
+        const int nf = int(fr.b) - int(f.n_ins);
+        const uint32_t ins_mask = f.sup_mask | wbm;
+        const uint32_t kmask = wbm & ~f.sup_mask;
+        const uint32_t keep0 = wbits & kmask, keep1 = (wbits ^ f.x_loc) & kmask;
+        const unsigned so = __popcll(base & f.w_out);
+        for (int h = 0; h < (keep0 == keep1 ? 1 : 2); ++h) {
+          const uint32_t keep = h ? keep1 : keep0;
           for (uint32_t t = uint32_t(lane); t < (1u << nf); t += 64u) {
-            const uint32_t ob = insert_zeros32_p4(t, g.ins_pack, g.n_ins);
-            for (uint32_t j = 0; j < g.n_out; ++j) emit(ob, j);
+            const uint32_t ob = insert_zeros_lo(t, f.ins_lo, ins_mask) | keep;
+            switch (f.n_rec) {
+              case 1: fast_pairs<1>(f, ob, keep, wbm, wbits, so, dummy, tp, tlr, tli); break;
+              case 2: fast_pairs<2>(f, ob, keep, wbm, wbits, so, dummy, tp, tlr, tli); break;
+              case 3: fast_pairs<3>(f, ob, keep, wbm, wbits, so, dummy, tp, tlr, tli); break;
+              default: fast_pairs<4>(f, ob, keep, wbm, wbits, so, dummy, tp, tlr, tli); break;
+            }
+          }
+        }
+      }
+      // other groups: the same walk, with G(m) summed over the subgroups
+      for (uint32_t gi = 0; gi < n_groups; ++gi) {
+        const TGroup g = bv.groups[gi];
+        const int nf = int(fr.b) - int(g.n_ins);
+        const uint32_t kmask = wbm & ~g.sup_mask;
+        const uint32_t keep0 = wbits & kmask, keep1 = (wbits ^ g.x_loc) & kmask;
+        for (int h = 0; h < (keep0 == keep1 ? 1 : 2); ++h) {
+          const uint32_t keep = h ? keep1 : keep0;
+          for (uint32_t t = uint32_t(lane); t < (1u << nf); t += 64u) {
+            const uint32_t ob = insert_zeros32_p4(t, g.ins_pack, g.n_ins) | keep;
+            for (uint32_t r = 0; r < g.n_rec; ++r) {
+              const uint32_t bp = bv.recs[g.rec_off + r];
+              const uint32_t lmp = ob | bp, lm = lmp ^ g.x_loc;
+              const uint32_t reg_mp = (keep | bp) & wbm;
+              const bool own_mp = reg_mp == wbits, own_m = ((reg_mp ^ g.x_loc) & wbm) == wbits;
+              if (!own_mp && !own_m) continue;
+              double gre = 0.0, gim = 0.0;  // G(m)
+              for (uint32_t k = 0; k < g.n_sub; ++k) {
+                const TSub sd = bv.subs[g.sub_off + k];
+                const double2 cv = bv.coef[g.coef_off + k * g.n_rec + r];
+                const unsigned sg = __popc(lmp & sd.w_loc) + __popcll(base & sd.w_out);
+                gre += signed_by(cv.x, sg);
+                gim += signed_by(cv.y, sg);
+              }
+              const T pm = tp[lm], pp = tp[lmp];
+              const uint32_t dm = own_m ? lm : dummy, dmp = own_mp ? lmp : dummy;
+              lds_add(&tlr[dm], gre * (double)pp.x - gim * (double)pp.y);  // lam[m] += G psi[m']
+              lds_add(&tli[dm], gre * (double)pp.y + gim * (double)pp.x);
+              lds_add(&tlr[dmp], gre * (double)pm.x + gim * (double)pm.y);  // lam[m'] += conj(G) psi[m]
+              lds_add(&tli[dmp], gre * (double)pm.y - gim * (double)pm.x);
+            }
           }
         }
       }
@@ -173,8 +247,7 @@ __global__ void __launch_bounds__(NT) k_tile_lambda(const T* __restrict__ psi, T
         const uint32_t i = uint32_t(lane) + 64u * k;
         if (i < nreg) {
           const uint32_t l = region_l(i);
-          const double2 v = tl[l];
-          lam[base | frame_deposit(lut, l)] = cmake<T>(R(v.x), R(v.y));
+          lam[base | frame_deposit(lut, l)] = cmake<T>(R(tlr[l]), R(tli[l]));
         }
       }
     }
@@ -182,11 +255,6 @@ __global__ void __launch_bounds__(NT) k_tile_lambda(const T* __restrict__ psi, T
   }
 }
 
-// ---------------------------------------------------------------------------
-// expectation over tiles: partials[block] = sum over the tile's groups of
-// sum_m conj(psi[m]) (H_x psi)[m], as 2 Re(conj(psi[m]) G psi[m']) per pair.
-// Block b works on tile b / bpt; tiles are independent (psi is only read).
-// ---------------------------------------------------------------------------
 template <typename T, int B, int NT>
 __global__ void __launch_bounds__(NT) k_tile_expect(const T* __restrict__ psi, const FrameDesc* __restrict__ frames,
                                                     const uint32_t* __restrict__ blob_off,
@@ -220,12 +288,16 @@ __global__ void __launch_bounds__(NT) k_tile_expect(const T* __restrict__ psi, c
       const uint32_t np = uint32_t(g.n_rec) << ns;
       for (uint32_t idx = threadIdx.x; idx < np; idx += NT) {
         const uint32_t r = idx >> ns, t = idx & ((1u << ns) - 1u);
-        const TOut o = bv.outs[g.out_off + r];  // the first n_rec outputs are the records (m')
-        const uint32_t l2 = insert_zeros32_p4(t, g.sins_pack, g.n_sins) | o.bits;
+        const uint32_t l2 = insert_zeros32_p4(t, g.sins_pack, g.n_sins) | bv.recs[g.rec_off + r];  // m'
         const uint32_t l = l2 ^ g.x_loc;
-        double gre, gim;
-        group_coef(bv, g, o, l2, base, gre, gim);  // o is m': conj(G); undo below
-        gim = -gim;
+        double gre = 0.0, gim = 0.0;  // G(m)
+        for (uint32_t k = 0; k < g.n_sub; ++k) {
+          const TSub sd = bv.subs[g.sub_off + k];
+          const double2 cv = bv.coef[g.coef_off + k * g.n_rec + r];
+          const unsigned sg = __popc(l2 & sd.w_loc) + __popcll(base & sd.w_out);
+          gre += signed_by(cv.x, sg);
+          gim += signed_by(cv.y, sg);
+        }
         const T a = tp[l], b = tp[l2];
         const double gbr = gre * (double)b.x - gim * (double)b.y, gbi = gre * (double)b.y + gim * (double)b.x;
         e += 2.0 * ((double)a.x * gbr + (double)a.y * gbi);

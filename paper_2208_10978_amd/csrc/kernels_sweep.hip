@@ -230,14 +230,32 @@ __device__ __forceinline__ void tile_run(const RunDesc& run, const RunRec* __res
 // ---------------------------------------------------------------------------
 // LDS tile, forward: load, apply every run of the pass, store.
 // ---------------------------------------------------------------------------
+// Copy the pass's run descriptors and records into LDS (once per block).
+template <int NT>
+__device__ __forceinline__ void stage_pass(const RunDesc* __restrict__ runs, int n_runs,
+                                           const RunRec* __restrict__ recs, int n_recs, RunDesc* s_runs,
+                                           RunRec* s_recs) {
+  const uint4* src = reinterpret_cast<const uint4*>(runs);
+  uint4* dst = reinterpret_cast<uint4*>(s_runs);
+  const int w1 = n_runs * int(sizeof(RunDesc) / 16);
+  for (int i = threadIdx.x; i < w1; i += NT) dst[i] = src[i];
+  src = reinterpret_cast<const uint4*>(recs);
+  dst = reinterpret_cast<uint4*>(s_recs);
+  const int w2 = n_recs * int(sizeof(RunRec) / 16);
+  for (int i = threadIdx.x; i < w2; i += NT) dst[i] = src[i];
+}
+
 template <typename T, int B, int NT>
 __global__ void __launch_bounds__(NT) k_tile_forward(T* __restrict__ psi, FrameDesc fr,
-                                                     const RunDesc* __restrict__ runs, int n_runs,
-                                                     const RunRec* __restrict__ recs, uint64_t n_tb) {
+                                                     const RunDesc* __restrict__ runs_g, int n_runs,
+                                                     const RunRec* __restrict__ recs_g, int n_recs, uint64_t n_tb) {
   constexpr int PER = (1 << B) / NT;
   __shared__ T tile[1 << B];
   __shared__ FrameLut lut;
+  __shared__ RunDesc runs[kMaxPassRuns];
+  __shared__ RunRec recs[kMaxPassRecs];
   frame_lut_init<NT>(fr, lut);
+  stage_pass<NT>(runs_g, n_runs, recs_g, n_recs, runs, recs);
   __syncthreads();
   const uint32_t nloc = 1u << fr.b;
   double dummy[1];
@@ -272,8 +290,8 @@ struct GradAcc {
 
 template <typename T, int B, int NT, int GRAD, int MAXS>
 __global__ void __launch_bounds__(NT) k_tile_reverse(T* __restrict__ psi, T* __restrict__ lam, FrameDesc fr,
-                                                     const RunDesc* __restrict__ runs, int n_runs,
-                                                     const RunRec* __restrict__ recs,
+                                                     const RunDesc* __restrict__ runs_g, int n_runs,
+                                                     const RunRec* __restrict__ recs_g, int n_recs,
                                                      const uint32_t* __restrict__ slot_map, int n_slots,
                                                      double* __restrict__ partials, uint32_t nb_stride,
                                                      uint64_t n_tb) {
@@ -283,8 +301,11 @@ __global__ void __launch_bounds__(NT) k_tile_reverse(T* __restrict__ psi, T* __r
   __shared__ T tl[1 << B];
   __shared__ FrameLut lut;
   __shared__ GradAcc<NW, MAXS> gacc;
+  __shared__ RunDesc runs[kMaxPassRuns];
+  __shared__ RunRec recs[kMaxPassRecs];
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
   frame_lut_init<NT>(fr, lut);
+  stage_pass<NT>(runs_g, n_runs, recs_g, n_recs, runs, recs);
   for (int i = threadIdx.x; i < MAXS * NW; i += NT) (&gacc.v[0][0])[i] = 0.0;
   __syncthreads();
   const uint32_t nloc = 1u << fr.b;
@@ -372,43 +393,45 @@ hipError_t launch_run_full(int dtype, bool rev, int grad, void* psi, void* lam, 
 }
 
 hipError_t launch_tile_forward(int dtype, void* psi, const FrameDesc& fr, const RunDesc* runs, int n_runs,
-                               const RunRec* recs, uint64_t n_tb, int grid, hipStream_t st) {
+                               const RunRec* recs, int n_recs, uint64_t n_tb, int grid, hipStream_t st) {
+  if (n_runs > kMaxPassRuns || n_recs > kMaxPassRecs) return hipErrorInvalidValue;
   if (dtype == 0)
     hipLaunchKernelGGL((k_tile_forward<double2, kTileFwdC128, kTileThreads>), dim3(grid), dim3(kTileThreads), 0,
-                       st, static_cast<double2*>(psi), fr, runs, n_runs, recs, n_tb);
+                       st, static_cast<double2*>(psi), fr, runs, n_runs, recs, n_recs, n_tb);
   else
     hipLaunchKernelGGL((k_tile_forward<float2, kTileFwdC64, kTileThreads>), dim3(grid), dim3(kTileThreads), 0,
-                       st, static_cast<float2*>(psi), fr, runs, n_runs, recs, n_tb);
+                       st, static_cast<float2*>(psi), fr, runs, n_runs, recs, n_recs, n_tb);
   return hipGetLastError();
 }
 
 template <typename T, int B>
 static hipError_t tile_reverse_t(int grad, void* psi, void* lam, const FrameDesc& fr, const RunDesc* runs,
-                                 int n_runs, const RunRec* recs, const uint32_t* slot_map, int n_slots,
+                                 int n_runs, const RunRec* recs, int n_recs, const uint32_t* slot_map, int n_slots,
                                  double* partials, uint32_t nb, uint64_t n_tb, int grid, hipStream_t st) {
   T* p = static_cast<T*>(psi);
   T* l = static_cast<T*>(lam);
   if (grad == 0)
     hipLaunchKernelGGL((k_tile_reverse<T, B, kTileThreads, 0, 1>), dim3(grid), dim3(kTileThreads), 0, st, p, l,
-                       fr, runs, n_runs, recs, slot_map, n_slots, partials, nb, n_tb);
+                       fr, runs, n_runs, recs, n_recs, slot_map, n_slots, partials, nb, n_tb);
   else if (grad == 1)
     hipLaunchKernelGGL((k_tile_reverse<T, B, kTileThreads, 1, kMaxPassSlots>), dim3(grid), dim3(kTileThreads), 0,
-                       st, p, l, fr, runs, n_runs, recs, slot_map, n_slots, partials, nb, n_tb);
+                       st, p, l, fr, runs, n_runs, recs, n_recs, slot_map, n_slots, partials, nb, n_tb);
   else
     hipLaunchKernelGGL((k_tile_reverse<T, B, kTileThreads, 2, kMaxPassSlots>), dim3(grid), dim3(kTileThreads), 0,
-                       st, p, l, fr, runs, n_runs, recs, slot_map, n_slots, partials, nb, n_tb);
+                       st, p, l, fr, runs, n_runs, recs, n_recs, slot_map, n_slots, partials, nb, n_tb);
   return hipGetLastError();
 }
 
 hipError_t launch_tile_reverse(int dtype, int grad, void* psi, void* lam, const FrameDesc& fr,
-                               const RunDesc* runs, int n_runs, const RunRec* recs, const uint32_t* slot_map,
-                               int n_slots, double* partials, uint32_t nb_stride, uint64_t n_tb, int grid,
-                               hipStream_t st) {
+                               const RunDesc* runs, int n_runs, const RunRec* recs, int n_recs,
+                               const uint32_t* slot_map, int n_slots, double* partials, uint32_t nb_stride,
+                               uint64_t n_tb, int grid, hipStream_t st) {
+  if (n_runs > kMaxPassRuns || n_recs > kMaxPassRecs || n_slots > kMaxPassSlots) return hipErrorInvalidValue;
   if (dtype == 0)
-    return tile_reverse_t<double2, kTileTwoC128>(grad, psi, lam, fr, runs, n_runs, recs, slot_map, n_slots,
-                                                 partials, nb_stride, n_tb, grid, st);
-  return tile_reverse_t<float2, kTileTwoC64>(grad, psi, lam, fr, runs, n_runs, recs, slot_map, n_slots, partials,
-                                             nb_stride, n_tb, grid, st);
+    return tile_reverse_t<double2, kTileTwoC128>(grad, psi, lam, fr, runs, n_runs, recs, n_recs, slot_map,
+                                                 n_slots, partials, nb_stride, n_tb, grid, st);
+  return tile_reverse_t<float2, kTileTwoC64>(grad, psi, lam, fr, runs, n_runs, recs, n_recs, slot_map, n_slots,
+                                             partials, nb_stride, n_tb, grid, st);
 }
 
 }  // namespace q2sv

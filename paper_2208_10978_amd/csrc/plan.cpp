@@ -124,7 +124,10 @@ FrameDesc make_frame(uint64_t qmask, int n, int c) {
   f.c = uint8_t(c);
   int k = 0;
   for (int q = 0; q < n; ++q)
-    if (!((qmask >> q) & 1ull)) f.comp[k++] = uint8_t(q);
+    if (!((qmask >> q) & 1ull)) {
+      f.comp[k++] = uint8_t(q);
+      f.comp_mask |= uint64_t(1) << q;
+    }
   f.n_comp = uint8_t(k);
   return f;
 }
@@ -178,7 +181,7 @@ double run_line_fraction(const RunData& d, int c) {
 }
 
 std::vector<Pass> schedule(const std::vector<Run>& runs, const std::vector<RunData>& data, int n, int b, int c,
-                           bool reverse, int max_slots_per_pass, int slots_per_run) {
+                           bool reverse, int max_slots_per_pass, int slots_per_run, int max_runs, int max_recs) {
   std::vector<Pass> out;
   const int R = int(runs.size());
   const uint64_t all = n >= 64 ? ~0ull : ((uint64_t(1) << n) - 1);
@@ -188,17 +191,21 @@ std::vector<Pass> schedule(const std::vector<Run>& runs, const std::vector<RunDa
     Pass ps;
     ps.tile = true;
     ps.qmask = all;
-    int slots = 0;
+    int slots = 0, nrec = 0;
     for (int i = 0; i < R; ++i) {
       const int ri = reverse ? R - 1 - i : i;
       const int need = slots_per_run ? slots_per_run : runs[ri].count;
-      if (max_slots_per_pass && slots + need > max_slots_per_pass) {
+      const int rec = int(data[ri].recs.size());
+      if ((max_slots_per_pass && slots + need > max_slots_per_pass) || int(ps.runs.size()) >= max_runs ||
+          nrec + rec > max_recs) {
         out.push_back(ps);
         ps.runs.clear();
         slots = 0;
+        nrec = 0;
       }
       ps.runs.push_back(ri);
       slots += need;
+      nrec += rec;
     }
     out.push_back(ps);
     return out;
@@ -208,16 +215,19 @@ std::vector<Pass> schedule(const std::vector<Run>& runs, const std::vector<RunDa
   while (i < R) {
     uint64_t q = low;
     std::vector<int> seg;
-    int slots = 0;
+    int slots = 0, nrec = 0;
     double alone = 0.0;
     while (i < R) {
       const int ri = reverse ? R - 1 - i : i;
       const uint64_t nq = q | runs[ri].x;
       const int need = slots_per_run ? slots_per_run : runs[ri].count;
+      const int rec = int(data[ri].recs.size());
       if (popc(nq) > b) break;
       if (max_slots_per_pass && slots + need > max_slots_per_pass) break;
+      if (int(seg.size()) >= max_runs || nrec + rec > max_recs) break;
       q = nq;
       slots += need;
+      nrec += rec;
       seg.push_back(ri);
       alone += run_line_fraction(data[ri], c);
       ++i;
@@ -374,18 +384,44 @@ static void append_full_group(HTiling& t, const HGroup& g, uint64_t all) {
 
 static size_t group_blob_bytes(const HGroup& g) {
   const size_t nr = size_t(g.n_rec());
-  return sizeof(TGroup) + 2 * nr * sizeof(TOut) + g.w.size() * sizeof(TSub) + g.w.size() * nr * 16;
+  return sizeof(TGroup) + nr * sizeof(uint32_t) + g.w.size() * sizeof(TSub) + g.w.size() * nr * 16;
 }
 
-// Pack groups of one tile into a blob (TileHdr, TGroup[], TOut[], TSub[], coef[]).
+// Pack groups of one tile into a blob (TileHdr, TGroup[], record bits[], TSub[], coef[], TFast[]).
+static bool fast_group(const HGroup& g, uint64_t qmask, uint32_t wb_mask) {
+  if (g.w.size() != 1 || g.n_rec() > kFastRecs) return false;
+  const uint32_t sm = g.enumerated ? uint32_t(compress(g.x, qmask)) : (1u << local_pos(highest_bit(g.x), qmask));
+  return popc(uint64_t(sm | wb_mask)) <= kFastIns;
+}
+
 static void pack_blob(HTiling& t, const std::vector<HGroup>& gs, const std::vector<int>& members, uint64_t qmask,
-                      uint32_t wb_mask) {
+                      uint32_t wb_mask, size_t max_blob, bool use_fast) {
   std::vector<TGroup> tg;
-  std::vector<TOut> to;
+  std::vector<uint32_t> to;
   std::vector<TSub> ts;
   std::vector<double> co;
+  std::vector<TFast> tf;
   for (int gi : members) {
     const HGroup& g = gs[gi];
+    if (use_fast && fast_group(g, qmask, wb_mask)) {
+      TFast f{};
+      f.x_loc = uint32_t(compress(g.x, qmask));
+      f.sup_mask = g.enumerated ? f.x_loc : (1u << local_pos(highest_bit(g.x), qmask));
+      int k = 0;
+      for (uint32_t m = f.sup_mask | wb_mask; m; m &= m - 1) f.ins_lo[k++] = (1u << __builtin_ctz(m)) - 1u;
+      f.n_ins = uint32_t(k);
+      for (int j = k; j < kFastIns; ++j) f.ins_lo[j] = ~0u;  // no-op steps
+      f.n_rec = uint32_t(g.n_rec());
+      f.w_loc = uint32_t(compress(g.w[0] & qmask, qmask));
+      f.w_out = g.w[0] & ~qmask;
+      for (int r = 0; r < g.n_rec(); ++r) {
+        f.bits[r] = g.enumerated ? uint32_t(compress(g.rec_v[r], qmask)) : f.sup_mask;
+        f.coef[2 * r] = g.t_re[r];
+        f.coef[2 * r + 1] = g.t_im[r];
+      }
+      tf.push_back(f);
+      continue;
+    }
     TGroup d{};
     d.x_loc = uint32_t(compress(g.x, qmask));
     // enumerated bits S': the support, or the pivot alone
@@ -394,22 +430,20 @@ static void pack_blob(HTiling& t, const std::vector<HGroup>& gs, const std::vect
     else smask = 1u << local_pos(highest_bit(g.x), qmask);
     d.sup_mask = smask;
     const int NR = g.n_rec();
-    d.n_rec = uint8_t(NR);
-    d.n_out = uint16_t(2 * NR);
-    d.out_off = uint16_t(to.size());
-    d.n_sub = uint16_t(g.w.size());
-    d.sub_off = uint16_t(ts.size());
+    d.n_rec = uint32_t(NR);
+    d.rec_off = uint32_t(to.size());
+    d.n_sub = uint32_t(g.w.size());
+    d.sub_off = uint32_t(ts.size());
     d.coef_off = uint32_t(co.size() / 2);
     int k = 0;
     for (uint32_t m = smask; m; m &= m - 1) d.sins_pack |= uint64_t(__builtin_ctz(m)) << (4 * k++);
-    d.n_sins = uint8_t(k);
+    d.n_sins = uint32_t(k);
     k = 0;
     for (uint32_t m = smask | wb_mask; m; m &= m - 1) d.ins_pack |= uint64_t(__builtin_ctz(m)) << (4 * k++);
-    d.n_ins = uint8_t(k);
+    d.n_ins = uint32_t(k);
     std::vector<uint32_t> rec_loc(NR);
     for (int r = 0; r < NR; ++r) rec_loc[r] = g.enumerated ? uint32_t(compress(g.rec_v[r], qmask)) : smask;
-    for (int r = 0; r < NR; ++r) to.push_back(TOut{uint16_t(rec_loc[r]), uint8_t(r), 1});
-    for (int r = 0; r < NR; ++r) to.push_back(TOut{uint16_t(rec_loc[r] ^ (d.x_loc & smask)), uint8_t(r), 0});
+    for (int r = 0; r < NR; ++r) to.push_back(rec_loc[r]);
     for (size_t w = 0; w < g.w.size(); ++w) {
       TSub sd{};
       sd.w_loc = uint32_t(compress(g.w[w] & qmask, qmask));
@@ -426,21 +460,25 @@ static void pack_blob(HTiling& t, const std::vector<HGroup>& gs, const std::vect
   TileHdr h{};
   h.n_groups = uint32_t(tg.size());
   size_t off = sizeof(TileHdr) + tg.size() * sizeof(TGroup);
-  h.off_out = uint32_t(align16(off));
-  off = h.off_out + to.size() * sizeof(TOut);
+  h.off_rec = uint32_t(align16(off));
+  off = h.off_rec + to.size() * sizeof(uint32_t);
   h.off_sub = uint32_t(align16(off));
   off = h.off_sub + ts.size() * sizeof(TSub);
   h.off_coef = uint32_t(align16(off));
   off = h.off_coef + co.size() * sizeof(double);
+  h.off_fast = uint32_t(align16(off));
+  h.n_fast = uint32_t(tf.size());
+  off = h.off_fast + tf.size() * sizeof(TFast);
   h.bytes = uint32_t(align16(off));
   h.wb_mask = wb_mask;
-  if (h.bytes > kBlobBytes) t.blob_overflow = true;  // the chunking estimate is conservative
+  if (h.bytes > max_blob) t.blob_overflow = true;
   std::vector<unsigned char> bytes(h.bytes, 0);
   std::memcpy(bytes.data(), &h, sizeof(h));
   if (!tg.empty()) std::memcpy(bytes.data() + sizeof(TileHdr), tg.data(), tg.size() * sizeof(TGroup));
-  if (!to.empty()) std::memcpy(bytes.data() + h.off_out, to.data(), to.size() * sizeof(TOut));
+  if (!to.empty()) std::memcpy(bytes.data() + h.off_rec, to.data(), to.size() * sizeof(uint32_t));
   if (!ts.empty()) std::memcpy(bytes.data() + h.off_sub, ts.data(), ts.size() * sizeof(TSub));
   if (!co.empty()) std::memcpy(bytes.data() + h.off_coef, co.data(), co.size() * sizeof(double));
+  if (!tf.empty()) std::memcpy(bytes.data() + h.off_fast, tf.data(), tf.size() * sizeof(TFast));
   t.blob_off.push_back(uint32_t(t.blob.size() / 2));
   const size_t words = h.bytes / 8;
   const size_t at = t.blob.size();
@@ -448,7 +486,7 @@ static void pack_blob(HTiling& t, const std::vector<HGroup>& gs, const std::vect
   std::memcpy(t.blob.data() + at, bytes.data(), h.bytes);
 }
 
-HTiling build_tiling(const std::vector<HGroup>& gs, int n, int b, int c, int region_bits) {
+HTiling build_tiling(const std::vector<HGroup>& gs, int n, int b, int c, int region_bits, size_t max_blob) {
   HTiling t;
   t.b = b;
   t.c = c;
@@ -465,7 +503,7 @@ HTiling build_tiling(const std::vector<HGroup>& gs, int n, int b, int c, int reg
   } else {
     std::vector<int> todo;
     for (int g = 0; g < G; ++g)
-      if (!gs[g].diag && popc(gs[g].x | low) <= b && group_blob_bytes(gs[g]) + fixed <= kBlobBytes)
+      if (!gs[g].diag && popc(gs[g].x | low) <= b && group_blob_bytes(gs[g]) + fixed <= max_blob)
         todo.push_back(g);
     while (!todo.empty()) {
       // seed with the widest uncovered support, then add the qubit that
@@ -520,27 +558,30 @@ HTiling build_tiling(const std::vector<HGroup>& gs, int n, int b, int c, int reg
         const uint32_t sm = gs[g].enumerated ? xl : (1u << local_pos(highest_bit(gs[g].x), q));
         for (uint32_t m = sm; m; m &= m - 1) use[__builtin_ctz(m)] += 1;
       }
+      // prefer bits above the lowest four: lanes then walk the contiguous
+      // low bits and their 16-byte LDS accesses do not share banks
+      const int lo = fb - std::max(c, 4) >= region_bits ? std::max(c, 4) : c;
       for (int k = 0; k < region_bits; ++k) {
         int best = -1;
-        for (int p = c; p < fb; ++p)
+        for (int p = lo; p < fb; ++p)
           if (!((wb >> p) & 1u) && (best < 0 || use[p] < use[best])) best = p;
         wb |= 1u << best;
       }
     } else if (region_bits > 0) {
       for (int p = 0; p < fb && popc(wb) < region_bits; ++p) wb |= 1u << p;
     }
-    // chunks of at most kBlobBytes
+    // chunks of at most max_blob bytes
     std::vector<int> chunk;
     size_t bytes = fixed;
     auto flush = [&]() {
       t.frames.push_back(make_frame(q, n, c));
-      pack_blob(t, gs, chunk, q, wb);
+      pack_blob(t, gs, chunk, q, wb, max_blob, region_bits > 0);
       chunk.clear();
       bytes = fixed;
     };
     for (int g : members) {
       const size_t gb = group_blob_bytes(gs[g]) + 16;
-      if (!chunk.empty() && bytes + gb > kBlobBytes) flush();
+      if (!chunk.empty() && bytes + gb > max_blob) flush();
       chunk.push_back(g);
       bytes += gb;
     }

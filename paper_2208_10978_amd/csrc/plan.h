@@ -80,8 +80,10 @@ struct Pass {
 // Greedy consecutive schedule.  forward: runs in list order; reverse: runs in
 // reverse order.  A pass becomes an LDS tile pass when it holds at least two
 // runs and is cheaper than applying its runs one by one.
+// A tile pass holds at most max_runs runs and max_recs records.
 std::vector<Pass> schedule(const std::vector<Run>& runs, const std::vector<RunData>& data, int n, int b,
-                           int c, bool reverse, int max_slots_per_pass, int slots_per_run);
+                           int c, bool reverse, int max_slots_per_pass, int slots_per_run, int max_runs,
+                           int max_recs);
 
 // ---------------------------------------------------------------------------
 // grouped Pauli sums
@@ -102,8 +104,7 @@ std::vector<HGroup> build_groups(const PauliIn* p, const double* coef, int64_t n
 // Device-ready arrays of one tiling of a grouped sum.  Every non-diagonal
 // group whose support fits (with the c low qubits) in b qubits belongs to one
 // tile; a tile's groups are packed into one or more blobs (passes) of at most
-// kBlobBytes; the remaining groups run over the whole state.
-constexpr size_t kBlobBytes = 26 * 1024;
+// max_blob bytes; the remaining groups run over the whole state.
 
 struct HTiling {
   int b = 0, c = 0;
@@ -115,11 +116,11 @@ struct HTiling {
   std::vector<uint64_t> recbits;
   std::vector<double> coef;              // whole-state group coefficients (re, im)
   int n_tiles = 0;
-  bool blob_overflow = false;            // a blob exceeded kBlobBytes (never expected)
+  bool blob_overflow = false;            // a blob exceeded max_blob (never expected)
 };
 
 // region_bits > 0 chooses that many frame-local bits (at or above c) per tile
 // to split lambda outputs among wavefronts.
-HTiling build_tiling(const std::vector<HGroup>& gs, int n, int b, int c, int region_bits);
+HTiling build_tiling(const std::vector<HGroup>& gs, int n, int b, int c, int region_bits, size_t max_blob);
 
 }  // namespace q2sv

@@ -104,9 +104,11 @@ struct alignas(16) SubDesc {
 };
 
 // ---------------------------------------------------------------------------
-// Group tables of one Hamiltonian tile pass, copied into LDS once per block.
-// A blob is a TileHdr followed by TGroup, TOut, TSub records and complex FP64
-// coefficients (offsets in bytes from the start of the blob).
+// Group tables of one Hamiltonian tile pass (the expectation kernel copies
+// them into LDS once per block; the lambda kernel reads them in place).  A
+// blob is a TileHdr followed by TGroup records, record bits, TSub records,
+// complex FP64 coefficients and TFast records (offsets in bytes from the
+// start of the blob).
 //
 // Every non-diagonal group is treated as pairs (m, m' = m ^ x) with the pivot
 // (highest) bit of m clear.  "Enumerated bits" S' are the support of x (when
@@ -117,34 +119,49 @@ struct alignas(16) SubDesc {
 // ---------------------------------------------------------------------------
 struct alignas(16) TileHdr {
   uint32_t n_groups;
-  uint32_t off_out;    // byte offset of the TOut array
+  uint32_t off_rec;    // byte offset of the record bits (uint32 each)
   uint32_t off_sub;    // byte offset of the TSub array
   uint32_t off_coef;   // byte offset of the coefficients (double2)
   uint32_t bytes;      // blob size in bytes (multiple of 16)
   uint32_t wb_mask;    // frame-local bits that split lambda outputs among wavefronts
-  uint32_t pad0, pad1;
+  uint32_t n_fast;     // TFast records (lambda tilings only)
+  uint32_t off_fast;   // byte offset of the TFast array
 };
 
+// Every field is a full 32 or 64 bits: a kernel reading these tables from
+// global memory with a uniform index then gets scalar loads (a sub-dword
+// field would become a vector load, whose wait also drains the tile loads
+// in flight).
 struct alignas(8) TGroup {
   uint32_t x_loc;      // frame-local flip mask
   uint32_t sup_mask;   // frame-local enumerated bits S'
-  uint16_t n_out;      // outputs = 2 * n_rec (records first: outputs that are m')
-  uint16_t out_off;    // first TOut
-  uint16_t n_sub;      // subgroups
-  uint16_t sub_off;    // first TSub
+  uint32_t rec_off;    // first record: frame-local bits of m' on S'
+  uint32_t n_rec;
+  uint32_t n_sub;      // subgroups
+  uint32_t sub_off;    // first TSub
   uint32_t coef_off;   // first coefficient: coef[coef_off + sub * n_rec + rec]
-  uint8_t n_rec;
-  uint8_t n_ins;       // zero insertions (S' union Wb, ascending) for lambda outputs
-  uint8_t n_sins;      // zero insertions (S', ascending) for pairs
-  uint8_t pad;
+  uint32_t n_ins;      // zero insertions (S' union Wb, ascending) for lambda outputs
+  uint32_t n_sins;     // zero insertions (S', ascending) for pairs
+  uint32_t pad;
   uint64_t ins_pack;   // their frame-local positions, four bits each
   uint64_t sins_pack;
 };
 
-struct TOut {
-  uint16_t bits;       // frame-local bits of the output on S'
-  uint8_t rec;         // record index
-  uint8_t is_mprime;   // output is m' (coefficient conj(G)); else m
+// A group with one subgroup and at most four records, in one self-contained
+// record (lambda tilings): G(m) = (-1)^{|m' & w|} T[record].
+constexpr int kFastRecs = 4;
+constexpr int kFastIns = 8;
+struct alignas(16) TFast {
+  uint32_t ins_lo[kFastIns];  // zero insertions (S' union Wb, ascending) at p: the masks 2^p - 1
+  uint64_t w_out;      // w, global bits outside the frame
+  uint32_t x_loc;      // frame-local flip mask
+  uint32_t sup_mask;   // frame-local enumerated bits S'
+  uint32_t w_loc;      // w, frame-local bits
+  uint32_t n_ins;
+  uint32_t n_rec;
+  uint32_t pad[3];
+  uint32_t bits[kFastRecs];   // m' of each record on S'
+  double coef[2 * kFastRecs]; // T[record] (re, im)
 };
 
 struct alignas(16) TSub {
@@ -160,7 +177,8 @@ struct alignas(16) FrameDesc {
   uint8_t c;                  // contiguous low qubits
   uint8_t comp[48];           // global positions of the other qubits, ascending
   uint8_t n_comp;             // n - B
-  uint8_t pad[15];
+  uint8_t pad[7];
+  uint64_t comp_mask;         // the same positions as a mask
 };
 
 }  // namespace q2sv
