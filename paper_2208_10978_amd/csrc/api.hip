@@ -242,8 +242,7 @@ static int tiling_get(sv_hamiltonian* h, int dtype, int role, DevTiling** out) {
     const int c = std::min(dtype == 0 ? 3 : 4, h->n);
     // expectation blobs are staged in LDS; lambda reads its tables through
     // scalar loads, so a tile's groups need not be split
-    t.host = build_tiling(h->groups, h->n, b, c, role == 1 ? kLambdaRegionBits : 0,
-                          role == 1 ? size_t(1) << 20 : size_t(kBlobWords) * 16);
+    t.host = build_tiling(h->groups, h->n, b, c, role == 1, role == 1 ? size_t(1) << 20 : size_t(kBlobWords) * 16);
     if (t.host.blob_overflow) return fail(SV_EINVAL, "internal: a tile's group tables exceed the LDS budget");
     Packer pk;
     t.o_frames = pk.add(t.host.frames.data(), t.host.frames.size() * sizeof(FrameDesc));
@@ -427,10 +426,11 @@ static int launch_rotations(sv_state* s, sv_state* lam, const RotPlan& pl, bool 
   std::vector<RunDesc> descs;
   std::vector<RunRec> recs;
   std::vector<uint32_t> slot_maps;
-  struct PassOff { size_t desc0; int nruns; size_t slot0; int nslots; size_t rec0; int nrecs; };
+  std::vector<SegDesc> segs;
+  struct PassOff { size_t desc0; int nruns; size_t slot0; int nslots; size_t rec0; int nrecs; size_t seg0; int nsegs; };
   std::vector<PassOff> po;
   for (const Pass& ps : pl.passes) {
-    PassOff o{descs.size(), int(ps.runs.size()), slot_maps.size(), 0, recs.size(), 0};
+    PassOff o{descs.size(), int(ps.runs.size()), slot_maps.size(), 0, recs.size(), 0, segs.size(), 0};
     int local = 0;
     for (int ri : ps.runs) {
       const Run& r = pl.runs[ri];
@@ -452,6 +452,17 @@ static int launch_rotations(sv_state* s, sv_state* lam, const RotPlan& pl, bool 
     }
     o.nslots = local;
     o.nrecs = int(recs.size() - o.rec0);
+    if (ps.tile) {
+      // segments of the pass and each descriptor's walk for its segment
+      std::vector<uint32_t> xl;
+      for (size_t j = o.desc0; j < descs.size(); ++j) xl.push_back(uint32_t(descs[j].x_loc));
+      const int fb = popc(ps.qmask);
+      const std::vector<SegDesc> sp = segment_pass(xl, fb, kTileRegionBits);
+      for (const SegDesc& sg : sp)
+        for (uint32_t j = sg.first; j < sg.first + sg.count; ++j) set_tile_walk(descs[o.desc0 + j], sg.wb_mask, fb);
+      segs.insert(segs.end(), sp.begin(), sp.end());
+      o.nsegs = int(sp.size());
+    }
     po.push_back(o);
   }
   if (recs.empty()) recs.push_back(RunRec{});
@@ -459,11 +470,13 @@ static int launch_rotations(sv_state* s, sv_state* lam, const RotPlan& pl, bool 
   const size_t o_desc = pk.add(descs.data(), descs.size() * sizeof(RunDesc));
   const size_t o_recs = pk.add(recs.data(), recs.size() * sizeof(RunRec));
   const size_t o_slot = pk.add(slot_maps.data(), slot_maps.size() * sizeof(uint32_t));
+  const size_t o_segs = pk.add(segs.data(), segs.size() * sizeof(SegDesc));
   int rc = upload(s->staging, s->tables, pk, s->stream);
   if (rc) return rc;
   const RunDesc* d_desc = dptr<RunDesc>(s->tables, o_desc);
   const RunRec* d_recs = dptr<RunRec>(s->tables, o_recs);
   const uint32_t* d_slot = dptr<uint32_t>(s->tables, o_slot);
+  const SegDesc* d_segs = dptr<SegDesc>(s->tables, o_segs);
   void* lam_amps = lam ? lam->amps : nullptr;
   for (size_t i = 0; i < pl.passes.size(); ++i) {
     const Pass& ps = pl.passes[i];
@@ -474,12 +487,12 @@ static int launch_rotations(sv_state* s, sv_state* lam, const RotPlan& pl, bool 
       hipError_t e;
       ProfScope prof(s->stream, rev ? kPTileRev : kPTileFwd, (rev ? 4.0 : 2.0) * s->bytes());
       if (!rev)
-        e = launch_tile_forward(s->dtype, s->amps, fr, d_desc + po[i].desc0, po[i].nruns, d_recs + po[i].rec0,
-                                po[i].nrecs, n_tb, grid, s->stream);
+        e = launch_tile_forward(s->dtype, s->amps, fr, d_desc + po[i].desc0, d_recs + po[i].rec0,
+                                d_segs + po[i].seg0, po[i].nsegs, n_tb, grid, s->stream);
       else
-        e = launch_tile_reverse(s->dtype, grad_mode, s->amps, lam_amps, fr, d_desc + po[i].desc0, po[i].nruns,
-                                d_recs + po[i].rec0, po[i].nrecs, d_slot + po[i].slot0, po[i].nslots, partials,
-                                kPartialStride, n_tb, grid, s->stream);
+        e = launch_tile_reverse(s->dtype, grad_mode, s->amps, lam_amps, fr, d_desc + po[i].desc0,
+                                d_recs + po[i].rec0, d_segs + po[i].seg0, po[i].nsegs, d_slot + po[i].slot0,
+                                po[i].nslots, partials, kPartialStride, n_tb, grid, s->stream);
       if (e != hipSuccess) return fail(SV_EDEVICE, std::string("tile pass launch: ") + hipGetErrorString(e));
     } else {
       const RunDesc& rd = descs[po[i].desc0];

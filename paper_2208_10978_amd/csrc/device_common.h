@@ -158,6 +158,17 @@ struct Stage {
 
 // Issue the loads of one tile-block into registers (all loads in flight at
 // once); thread t holds frame-local indices t, t + NT, ...
+__device__ __forceinline__ uint32_t lds_swz(uint32_t l) { return lds_slot(l); }
+
+// Bits of v deposited on the set bits of mask, ascending (uniform operands
+// keep this on the scalar unit).
+__device__ __forceinline__ uint32_t deposit_bits(uint32_t v, uint32_t mask) {
+  uint32_t out = 0;
+  for (uint32_t m = mask; m; m &= m - 1, v >>= 1)
+    if (v & 1u) out |= m & (~m + 1u);
+  return out;
+}
+
 template <typename T, int PER, int NT>
 __device__ __forceinline__ void tile_fetch(const T* __restrict__ src, const FrameLut& lut, uint64_t base,
                                            uint32_t nloc, Stage<T, PER>& reg) {
@@ -177,7 +188,7 @@ __device__ __forceinline__ void tile_put(T* tile, uint32_t nloc, const Stage<T, 
 #pragma unroll
   for (int i = 0; i < PER; ++i) {
     const uint32_t l = threadIdx.x + uint32_t(i) * NT;
-    if (l < nloc) tile[l] = cmake<T>(reg.re[i], reg.im[i]);
+    if (l < nloc) tile[lds_swz(l)] = cmake<T>(reg.re[i], reg.im[i]);
   }
 }
 
@@ -187,7 +198,7 @@ __device__ __forceinline__ void tile_store(T* __restrict__ dst, const FrameLut& 
 #pragma unroll
   for (int i = 0; i < PER; ++i) {
     const uint32_t l = threadIdx.x + uint32_t(i) * NT;
-    if (l < nloc) dst[base | frame_deposit(lut, l)] = tile[l];
+    if (l < nloc) dst[base | frame_deposit(lut, l)] = tile[lds_swz(l)];
   }
 }
 

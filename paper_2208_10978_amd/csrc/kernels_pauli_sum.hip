@@ -3,11 +3,9 @@
 // LDS tiles, the diagonal part as a resident FP64 vector, and whole-state
 // passes for groups whose support does not fit a tile.
 //
-// Group tables of a tile (TileHdr blob) are copied into LDS once per block.
-// In the lambda build every wavefront owns a fixed region of the tile's
-// outputs (frame bits wb_mask = its wavefront index), so the groups of a tile
-// run with no block barrier between them; only the outputs a group actually
-// reaches (its active support patterns) are enumerated.
+// The expectation copies a tile's group tables (TileHdr blob) into LDS once
+// per block; the lambda build reads them in place.  Only the pairs a group
+// actually reaches (its active support patterns) are enumerated.
 #include "device_common.h"
 #include "launch.h"
 
@@ -20,6 +18,7 @@ struct BlobView {
   const TSub* subs;
   const double2* coef;
   const TFast* fast;
+  const uint32_t* items;
   __device__ explicit BlobView(const uint4* blob) {
     const char* b = reinterpret_cast<const char*>(blob);
     hdr = reinterpret_cast<const TileHdr*>(b);
@@ -28,6 +27,7 @@ struct BlobView {
     subs = reinterpret_cast<const TSub*>(b + hdr->off_sub);
     coef = reinterpret_cast<const double2*>(b + hdr->off_coef);
     fast = reinterpret_cast<const TFast*>(b + hdr->off_fast);
+    items = reinterpret_cast<const uint32_t*>(b + hdr->off_items);
   }
 };
 
@@ -45,9 +45,9 @@ __device__ __forceinline__ void blob_stage(const uint4* __restrict__ src, uint4*
 // and feed the vector arithmetic directly.  Contributions land in the FP64
 // accumulator tile (real and imaginary parts in separate arrays) with LDS
 // atomic adds, which return nothing, so an update is never a load-modify-
-// store chain.  Each output is only ever touched by the one wavefront owning
-// its region, in program order, so the rounding order (and the result) is
-// fixed.
+// store chain.  All wavefronts of the block work on the whole tile at once;
+// the order in which the updates of different wavefronts reach an output is
+// not fixed, so the last bits of lambda may differ between runs.
 // ---------------------------------------------------------------------------
 __device__ __forceinline__ void lds_add(double* p, double v) {
   __hip_atomic_fetch_add(p, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
@@ -68,32 +68,29 @@ __device__ __forceinline__ uint32_t insert_zeros_lo(uint32_t t, const uint32_t (
 }
 
 // The pairs (m', m = m' ^ x) of every record of a one-subgroup group at one
-// position of its free bits.  Which endpoints lie in this wavefront's region
-// is uniform (it depends on the record and the fixed region bits only); an
-// endpoint elsewhere sends its update to the lane's own dummy slot, so the
-// code has no branches and all loads issue before any use.
+// position of its free bits: all loads first, then the updates.
 template <int NR, typename T>
-__device__ __forceinline__ void fast_pairs(const TFast& f, uint32_t ob, uint32_t keep, uint32_t wbm, uint32_t wbits,
-                                           unsigned so, uint32_t dummy, const T* tp, double* tlr, double* tli) {
-  uint32_t lmp[NR];
+__device__ __forceinline__ void fast_pairs(const TFast& f, uint32_t ob, unsigned so, const T* tp, double* tlr,
+                                           double* tli) {
+  // LDS slots: linear in the index, so slot(ob | bits) = slot(ob) ^ slot(bits)
+  const uint32_t sob = lds_swz(ob), sx = lds_swz(f.x_loc);
+  uint32_t smp[NR];
   T pm[NR], pp[NR];
 #pragma unroll
   for (int r = 0; r < NR; ++r) {
-    lmp[r] = ob | f.bits[r];
-    pm[r] = tp[lmp[r] ^ f.x_loc];
-    pp[r] = tp[lmp[r]];
+    smp[r] = sob ^ lds_swz(f.bits[r]);
+    pm[r] = tp[smp[r] ^ sx];
+    pp[r] = tp[smp[r]];
   }
 #pragma unroll
   for (int r = 0; r < NR; ++r) {
-    const unsigned sg = __popc(lmp[r] & f.w_loc) + so;
+    const unsigned sg = __popc((ob | f.bits[r]) & f.w_loc) + so;
     const double gre = signed_by(f.coef[2 * r], sg), gim = signed_by(f.coef[2 * r + 1], sg);
-    const uint32_t reg_mp = (keep | f.bits[r]) & wbm;  // region bits of m'
-    const uint32_t dm = ((reg_mp ^ f.x_loc) & wbm) == wbits ? lmp[r] ^ f.x_loc : dummy;
-    const uint32_t dmp = reg_mp == wbits ? lmp[r] : dummy;
-    lds_add(&tlr[dm], gre * (double)pp[r].x - gim * (double)pp[r].y);  // lam[m] += G psi[m']
-    lds_add(&tli[dm], gre * (double)pp[r].y + gim * (double)pp[r].x);
-    lds_add(&tlr[dmp], gre * (double)pm[r].x + gim * (double)pm[r].y);  // lam[m'] += conj(G) psi[m]
-    lds_add(&tli[dmp], gre * (double)pm[r].y - gim * (double)pm[r].x);
+    const uint32_t sm = smp[r] ^ sx;
+    lds_add(&tlr[sm], gre * (double)pp[r].x - gim * (double)pp[r].y);  // lam[m] += G psi[m']
+    lds_add(&tli[sm], gre * (double)pp[r].y + gim * (double)pp[r].x);
+    lds_add(&tlr[smp[r]], gre * (double)pm[r].x + gim * (double)pm[r].y);  // lam[m'] += conj(G) psi[m]
+    lds_add(&tli[smp[r]], gre * (double)pm[r].y - gim * (double)pm[r].x);
   }
 }
 
@@ -104,53 +101,35 @@ __global__ void __launch_bounds__(NT) k_tile_lambda(const T* __restrict__ psi, T
   using R = typename Real<T>::type;
   constexpr int NW = NT / 64;
   constexpr int PER = (1 << B) / NT;
-  constexpr int RPER = ((1 << B) / NW + 63) / 64;
-  constexpr int NACC = (1 << B) + NT;  // accumulators, then one dummy slot per lane
   __shared__ T tp[1 << B];
-  __shared__ double tlr[NACC], tli[NACC];
+  __shared__ double tlr[1 << B], tli[1 << B];
   __shared__ FrameLut lut;
   frame_lut_init<NT>(fr, lut);
   __syncthreads();
   const BlobView bv(blob);
   const int lane = threadIdx.x & 63;
   const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
-  const uint32_t dummy = (1u << B) + threadIdx.x;
   const uint32_t nloc = 1u << fr.b;
-  // this wavefront's output region: frame bits wb_mask equal to `wave`
-  const uint32_t wbm = bv.hdr->wb_mask;
-  const uint32_t n_groups = bv.hdr->n_groups, n_fast = bv.hdr->n_fast;
-  uint64_t wpack = 0;
-  int nwb = 0;
-  uint32_t wbits = 0;
-  for (uint32_t m = wbm; m; m &= m - 1) {
-    const int p = __ffs(m) - 1;
-    wbits |= uint32_t((wave >> nwb) & 1) << p;
-    wpack |= uint64_t(p) << (4 * nwb);
-    ++nwb;
-  }
-  const bool owner = wave < (1 << nwb);
-  const uint32_t nreg = nloc >> nwb;
-  auto region_l = [&](uint32_t i) { return insert_zeros32_p4(i, wpack, nwb) | wbits; };
+  const uint32_t n_groups = bv.hdr->n_groups, n_items = bv.hdr->n_fast_items;
+  const uint32_t* items = bv.items;
 
   Stage<T, PER> rp;
-  Stage<T, RPER> rl;
-  double rd[RPER];
+  Stage<T, PER> rl;
+  double rd[PER];
   auto fetch = [&](uint64_t tbx) {
     const uint64_t bx = frame_base(fr, tbx);
     tile_fetch<T, PER, NT>(psi, lut, bx, nloc, rp);
-    if (owner) {
 #pragma unroll
-      for (int k = 0; k < RPER; ++k) {
-        const uint32_t i = uint32_t(lane) + 64u * k;
-        if (i < nreg) {
-          const uint64_t gi = bx | frame_deposit(lut, region_l(i));
-          if (MODE == 1) {
-            rd[k] = diag ? diag[gi] : 0.0;
-          } else {
-            const T v = lam[gi];
-            rl.re[k] = v.x;
-            rl.im[k] = v.y;
-          }
+    for (int i = 0; i < PER; ++i) {
+      const uint32_t l = threadIdx.x + uint32_t(i) * NT;
+      if (l < nloc) {
+        const uint64_t gi = bx | frame_deposit(lut, l);
+        if (MODE == 1) {
+          rd[i] = diag ? diag[gi] : 0.0;
+        } else {
+          const T v = lam[gi];
+          rl.re[i] = v.x;
+          rl.im[i] = v.y;
         }
       }
     }
@@ -161,97 +140,77 @@ __global__ void __launch_bounds__(NT) k_tile_lambda(const T* __restrict__ psi, T
   for (; tb < n_tb; tb += gridDim.x) {
     const uint64_t base = frame_base(fr, tb);
     tile_put<T, PER, NT>(tp, nloc, rp);
-    __syncthreads();
-    if (owner) {
 #pragma unroll
-      for (int k = 0; k < RPER; ++k) {
-        const uint32_t i = uint32_t(lane) + 64u * k;
-        if (i < nreg) {
-          const uint32_t l = region_l(i);
-          if (MODE == 1) {
-            const T a = tp[l];
-            tlr[l] = rd[k] * (double)a.x;
-            tli[l] = rd[k] * (double)a.y;
-          } else {
-            tlr[l] = (double)rl.re[k];
-            tli[l] = (double)rl.im[k];
-          }
+    for (int i = 0; i < PER; ++i) {
+      const uint32_t l = threadIdx.x + uint32_t(i) * NT;
+      if (l < nloc) {
+        const uint32_t sl = lds_swz(l);
+        if (MODE == 1) {
+          tlr[sl] = rd[i] * (double)rp.re[i];
+          tli[sl] = rd[i] * (double)rp.im[i];
+        } else {
+          tlr[sl] = (double)rl.re[i];
+          tli[sl] = (double)rl.im[i];
         }
       }
     }
+    __syncthreads();
     const uint64_t nx = tb + gridDim.x;
     if (nx < n_tb) fetch(nx);
-    if (owner) {
-      // one-subgroup groups: a lane takes one position of the free bits (a
-      // "cube" over the support) and every record's pair there.  Region bits
-      // outside the support are inserted fixed: equal to this wavefront's bits
-      // for m', and, where x flips one of them, a second walk with them equal
-      // for m.
-      for (uint32_t fi = 0; fi < n_fast; ++fi) {
-        const TFast f = bv.fast[fi];
-        const int nf = int(fr.b) - int(f.n_ins);
-        const uint32_t ins_mask = f.sup_mask | wbm;
-        const uint32_t kmask = wbm & ~f.sup_mask;
-        const uint32_t keep0 = wbits & kmask, keep1 = (wbits ^ f.x_loc) & kmask;
+    // groups with several subgroups: every thread of the block takes pairs
+    // (record, position of the free bits), G(m) summed over the subgroups
+    for (uint32_t gi = 0; gi < n_groups; ++gi) {
+      const TGroup g = bv.groups[gi];
+      const int nf = int(fr.b) - int(g.n_sins);
+      const uint32_t n_it = g.n_rec << nf;
+      for (uint32_t idx = threadIdx.x; idx < n_it; idx += NT) {
+        const uint32_t r = idx >> nf, t = idx & ((1u << nf) - 1u);
+        const uint32_t lmp = insert_zeros32_p4(t, g.sins_pack, g.n_sins) | bv.recs[g.rec_off + r];
+        const uint32_t lm = lmp ^ g.x_loc;
+        double gre = 0.0, gim = 0.0;  // G(m)
+        for (uint32_t k = 0; k < g.n_sub; ++k) {
+          const TSub sd = bv.subs[g.sub_off + k];
+          const double2 cv = bv.coef[g.coef_off + k * g.n_rec + r];
+          const unsigned sg = __popc(lmp & sd.w_loc) + __popcll(base & sd.w_out);
+          gre += signed_by(cv.x, sg);
+          gim += signed_by(cv.y, sg);
+        }
+        const uint32_t smp = lds_swz(lmp), sm = lds_swz(lm);
+        const T pm = tp[sm], pp = tp[smp];
+        lds_add(&tlr[sm], gre * (double)pp.x - gim * (double)pp.y);  // lam[m] += G psi[m']
+        lds_add(&tli[sm], gre * (double)pp.y + gim * (double)pp.x);
+        lds_add(&tlr[smp], gre * (double)pm.x + gim * (double)pm.y);  // lam[m'] += conj(G) psi[m]
+        lds_add(&tli[smp], gre * (double)pm.y - gim * (double)pm.x);
+      }
+    }
+    // one-subgroup groups: work items of 64 free-bit positions of one group,
+    // dealt to the wavefronts in turn; a lane takes one position and every
+    // record's pair there
+    for (uint32_t it = uint32_t(wave); it < n_items; it += NW) {
+      const uint32_t w = items[it];
+      const TFast f = bv.fast[w >> 12];
+      const int nf = int(fr.b) - int(f.n_ins);
+      const uint32_t t = ((w & 0xfffu) << 6) | uint32_t(lane);
+      if (t < (1u << nf)) {
+        const uint32_t ob = insert_zeros_lo(t, f.ins_lo, f.sup_mask);
         const unsigned so = __popcll(base & f.w_out);
-        for (int h = 0; h < (keep0 == keep1 ? 1 : 2); ++h) {
-          const uint32_t keep = h ? keep1 : keep0;
-          for (uint32_t t = uint32_t(lane); t < (1u << nf); t += 64u) {
-            const uint32_t ob = insert_zeros_lo(t, f.ins_lo, ins_mask) | keep;
-            switch (f.n_rec) {
-              case 1: fast_pairs<1>(f, ob, keep, wbm, wbits, so, dummy, tp, tlr, tli); break;
-              case 2: fast_pairs<2>(f, ob, keep, wbm, wbits, so, dummy, tp, tlr, tli); break;
-              case 3: fast_pairs<3>(f, ob, keep, wbm, wbits, so, dummy, tp, tlr, tli); break;
-              default: fast_pairs<4>(f, ob, keep, wbm, wbits, so, dummy, tp, tlr, tli); break;
-            }
-          }
-        }
-      }
-      // other groups: the same walk, with G(m) summed over the subgroups
-      for (uint32_t gi = 0; gi < n_groups; ++gi) {
-        const TGroup g = bv.groups[gi];
-        const int nf = int(fr.b) - int(g.n_ins);
-        const uint32_t kmask = wbm & ~g.sup_mask;
-        const uint32_t keep0 = wbits & kmask, keep1 = (wbits ^ g.x_loc) & kmask;
-        for (int h = 0; h < (keep0 == keep1 ? 1 : 2); ++h) {
-          const uint32_t keep = h ? keep1 : keep0;
-          for (uint32_t t = uint32_t(lane); t < (1u << nf); t += 64u) {
-            const uint32_t ob = insert_zeros32_p4(t, g.ins_pack, g.n_ins) | keep;
-            for (uint32_t r = 0; r < g.n_rec; ++r) {
-              const uint32_t bp = bv.recs[g.rec_off + r];
-              const uint32_t lmp = ob | bp, lm = lmp ^ g.x_loc;
-              const uint32_t reg_mp = (keep | bp) & wbm;
-              const bool own_mp = reg_mp == wbits, own_m = ((reg_mp ^ g.x_loc) & wbm) == wbits;
-              if (!own_mp && !own_m) continue;
-              double gre = 0.0, gim = 0.0;  // G(m)
-              for (uint32_t k = 0; k < g.n_sub; ++k) {
-                const TSub sd = bv.subs[g.sub_off + k];
-                const double2 cv = bv.coef[g.coef_off + k * g.n_rec + r];
-                const unsigned sg = __popc(lmp & sd.w_loc) + __popcll(base & sd.w_out);
-                gre += signed_by(cv.x, sg);
-                gim += signed_by(cv.y, sg);
-              }
-              const T pm = tp[lm], pp = tp[lmp];
-              const uint32_t dm = own_m ? lm : dummy, dmp = own_mp ? lmp : dummy;
-              lds_add(&tlr[dm], gre * (double)pp.x - gim * (double)pp.y);  // lam[m] += G psi[m']
-              lds_add(&tli[dm], gre * (double)pp.y + gim * (double)pp.x);
-              lds_add(&tlr[dmp], gre * (double)pm.x + gim * (double)pm.y);  // lam[m'] += conj(G) psi[m]
-              lds_add(&tli[dmp], gre * (double)pm.y - gim * (double)pm.x);
-            }
-          }
-        }
-      }
-      // the region is complete: write it out
-#pragma unroll
-      for (int k = 0; k < RPER; ++k) {
-        const uint32_t i = uint32_t(lane) + 64u * k;
-        if (i < nreg) {
-          const uint32_t l = region_l(i);
-          lam[base | frame_deposit(lut, l)] = cmake<T>(R(tlr[l]), R(tli[l]));
+        switch (f.n_rec) {
+          case 1: fast_pairs<1>(f, ob, so, tp, tlr, tli); break;
+          case 2: fast_pairs<2>(f, ob, so, tp, tlr, tli); break;
+          case 3: fast_pairs<3>(f, ob, so, tp, tlr, tli); break;
+          default: fast_pairs<4>(f, ob, so, tp, tlr, tli); break;
         }
       }
     }
     __syncthreads();
+#pragma unroll
+    for (int i = 0; i < PER; ++i) {
+      const uint32_t l = threadIdx.x + uint32_t(i) * NT;
+      if (l < nloc) {
+        const uint32_t sl = lds_swz(l);
+        lam[base | frame_deposit(lut, l)] = cmake<T>(R(tlr[sl]), R(tli[sl]));
+      }
+    }
   }
 }
 
@@ -298,7 +257,7 @@ __global__ void __launch_bounds__(NT) k_tile_expect(const T* __restrict__ psi, c
           gre += signed_by(cv.x, sg);
           gim += signed_by(cv.y, sg);
         }
-        const T a = tp[l], b = tp[l2];
+        const T a = tp[lds_swz(l)], b = tp[lds_swz(l2)];
         const double gbr = gre * (double)b.x - gim * (double)b.y, gbi = gre * (double)b.y + gim * (double)b.x;
         e += 2.0 * ((double)a.x * gbr + (double)a.y * gbi);
       }

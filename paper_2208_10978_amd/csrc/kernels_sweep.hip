@@ -3,7 +3,9 @@
 // and LDS-tiled passes that apply many runs per HBM read and write of the
 // state.  Tile passes are software-pipelined: while a block works on one
 // tile-block in LDS, the loads of its next tile-block are already in flight
-// into registers.
+// into registers.  Inside a tile, runs are grouped in segments whose pairs
+// stay within per-wavefront regions, so the block synchronises once per
+// segment instead of once per run.
 #include "device_common.h"
 #include "launch.h"
 
@@ -130,56 +132,118 @@ __global__ void __launch_bounds__(256) k_run_full(T* __restrict__ psi, T* __rest
 }
 
 // ---------------------------------------------------------------------------
-// In-LDS application of one run to a tile (forward) or to a psi/lam tile pair
-// (reverse, with the gradient factor accumulated per lane).
+// In-LDS application of one run to this wavefront's region of a tile
+// (forward), or of a psi/lam tile pair (reverse, with the gradient factor
+// accumulated per lane).  Walk position t = lane + 64 j: the lane's bits are
+// deposited once per run with one and-or per bit from per-lane masks, the
+// bits of j (uniform) on the scalar unit; LDS slots follow by linearity.
 // ---------------------------------------------------------------------------
-template <typename T, int NT, bool REV, int GRAD>
+struct LaneBits {
+  uint32_t m[kWalkLaneBits];  // all ones where the lane index has bit i
+  __device__ explicit LaneBits(uint32_t lane) {
+#pragma unroll
+    for (int i = 0; i < kWalkLaneBits; ++i) m[i] = 0u - ((lane >> i) & 1u);
+  }
+};
+
+// the lane's part of the walk index and of its LDS slot
+__device__ __forceinline__ void lane_walk(const RunDesc& run, const LaneBits& lb, uint32_t& dl, uint32_t& ds) {
+  dl = 0;
+  ds = 0;
+#pragma unroll
+  for (int i = 0; i < kWalkLaneBits; ++i) {
+    dl |= lb.m[i] & run.dep_p[i];
+    ds ^= lb.m[i] & run.dep_q[i];
+  }
+}
+
+template <unsigned OM, typename V>
+__device__ __forceinline__ void rot_pair_om(V& a, V& b, typename Real<V>::type c, typename Real<V>::type s,
+                                            unsigned sgn) {
+  rot_pair(a, b, c, s, sgn, OM);
+}
+
+template <unsigned OM, typename V>
+__device__ __forceinline__ double grad_w_om(V pa, V pb, V la, V lb, unsigned sgn) {
+  return grad_w(pa, pb, la, lb, sgn, OM);
+}
+
+// kRunEnum: every record's pairs, with the phase power omega0 = OM fixed
+template <typename T, bool REV, int GRAD, unsigned OM>
+__device__ __forceinline__ void enum_walk(const RunDesc& run, const RunRec* __restrict__ recs, T* tp, T* tl,
+                                          uint32_t dl, uint32_t ds, unsigned zlane_par, bool lane_on, unsigned so,
+                                          uint32_t wbits, double (&acc)[GRAD == 2 ? kMaxRunStrings : 1]) {
+  using R = typename Real<T>::type;
+  const uint32_t xl = uint32_t(run.x_loc), zl = uint32_t(run.z0_loc);
+  const uint32_t sx = lds_swz(xl);  // slot(l ^ x) = slot(l) ^ slot(x)
+  const uint32_t nj = run.walk_log > kWalkLaneBits ? 1u << (run.walk_log - kWalkLaneBits) : 1u;
+  for (uint32_t r = 0; r < run.n_rec; ++r) {
+    const RunRec rec = recs[run.rec_off + r];
+    const R c = R(rec.c), s = REV ? R(-rec.s) : R(rec.s);
+    double wsum = 0.0;
+    for (uint32_t j = 0; j < nj; ++j) {
+      const uint32_t rest = deposit_bits(j, run.hi_mask) | uint32_t(rec.bits) | wbits;  // uniform
+      const uint32_t srest = lds_swz(rest);
+      const unsigned prest = so ^ parity32(rest & zl);
+      if (lane_on) {
+        const uint32_t s2 = ds ^ srest, s1 = s2 ^ sx;  // slots of m' and m
+        const unsigned sg = zlane_par ^ prest;
+        T a = tp[s1], b = tp[s2];
+        if (REV) {
+          T la = tl[s1], lb = tl[s2];
+          if (GRAD) wsum += grad_w_om<OM>(a, b, la, lb, sg);
+          rot_pair_om<OM>(la, lb, c, s, sg);
+          tl[s1] = la;
+          tl[s2] = lb;
+        }
+        rot_pair_om<OM>(a, b, c, s, sg);
+        tp[s1] = a;
+        tp[s2] = b;
+      }
+    }
+    (void)dl;
+    if (GRAD == 1) acc[0] += rec.a * wsum;
+    if (GRAD == 2) {
+#pragma unroll
+      for (int k = 0; k < kMaxRunStrings; ++k) acc[k] += ((rec.eps_neg >> k) & 1u) ? -wsum : wsum;
+    }
+  }
+}
+
+template <typename T, bool REV, int GRAD>
 __device__ __forceinline__ void tile_run(const RunDesc& run, const RunRec* __restrict__ recs, T* tp, T* tl,
-                                         uint32_t nloc, uint64_t base, double (&acc)[GRAD == 2 ? kMaxRunStrings : 1]) {
+                                         uint64_t base, uint32_t wbits, uint32_t lane, const LaneBits& lbits,
+                                         double (&acc)[GRAD == 2 ? kMaxRunStrings : 1]) {
   using R = typename Real<T>::type;
   const unsigned so = parity64(base & run.z0_out);
   const uint32_t xl = uint32_t(run.x_loc), zl = uint32_t(run.z0_loc);
+  const uint32_t sx = lds_swz(xl);
+  uint32_t dl, ds;
+  lane_walk(run, lbits, dl, ds);
+  const bool lane_on = run.walk_log >= kWalkLaneBits || lane < (1u << run.walk_log);
+  const uint32_t nj = run.walk_log > kWalkLaneBits ? 1u << (run.walk_log - kWalkLaneBits) : 1u;
   if (run.mode == kRunEnum) {
-    const uint32_t np = nloc >> run.n_sup;
-    for (int r = 0; r < run.n_rec; ++r) {
-      const RunRec rec = recs[run.rec_off + r];
-      const R c = R(rec.c), s = REV ? R(-rec.s) : R(rec.s);
-      const uint32_t bits = uint32_t(rec.bits);
-      double wsum = 0.0;
-      for (uint32_t t = threadIdx.x; t < np; t += NT) {
-        const uint32_t l2 = insert_zeros32(t, run.sup_pack, run.n_sup) | bits;
-        const uint32_t l = l2 ^ xl;
-        const unsigned sg = so ^ parity32(l2 & zl);
-        T a = tp[l], b = tp[l2];
-        if (REV) {
-          T la = tl[l], lb = tl[l2];
-          if (GRAD) wsum += grad_w(a, b, la, lb, sg, run.omega0);
-          rot_pair(la, lb, c, s, sg, run.omega0);
-          tl[l] = la;
-          tl[l2] = lb;
-        }
-        rot_pair(a, b, c, s, sg, run.omega0);
-        tp[l] = a;
-        tp[l2] = b;
-      }
-      if (GRAD == 1) acc[0] += rec.a * wsum;
-      if (GRAD == 2) {
-#pragma unroll
-        for (int k = 0; k < kMaxRunStrings; ++k) acc[k] += ((rec.eps_neg >> k) & 1u) ? -wsum : wsum;
-      }
+    const unsigned zp = parity32(lane & run.zlane);
+    switch (run.omega0 & 3u) {
+      case 0: enum_walk<T, REV, GRAD, 0>(run, recs, tp, tl, dl, ds, zp, lane_on, so, wbits, acc); break;
+      case 1: enum_walk<T, REV, GRAD, 1>(run, recs, tp, tl, dl, ds, zp, lane_on, so, wbits, acc); break;
+      case 2: enum_walk<T, REV, GRAD, 2>(run, recs, tp, tl, dl, ds, zp, lane_on, so, wbits, acc); break;
+      default: enum_walk<T, REV, GRAD, 3>(run, recs, tp, tl, dl, ds, zp, lane_on, so, wbits, acc); break;
     }
   } else if (run.mode == kRunFull) {
-    const uint32_t np = nloc >> 1;
-    for (uint32_t t = threadIdx.x; t < np; t += NT) {
-      const uint32_t l = insert_zero32(t, run.pivot);
+    for (uint32_t j = 0; j < nj; ++j) {
+      const uint32_t rest = deposit_bits(j, run.hi_mask) | wbits;
+      if (!lane_on) continue;
+      const uint32_t l = dl | rest;  // pivot bit clear
       const uint32_t l2 = l ^ xl;
+      const uint32_t s1 = ds ^ lds_swz(rest), s2 = s1 ^ sx;
       const unsigned sg = so ^ parity32(l2 & zl);
       const unsigned p = run_pattern(run, l2, base);
       const RunRec rec = recs[run.rec_off + p];
       const R c = R(rec.c), s = REV ? R(-rec.s) : R(rec.s);
-      T a = tp[l], b = tp[l2];
+      T a = tp[s1], b = tp[s2];
       if (REV) {
-        T la = tl[l], lb = tl[l2];
+        T la = tl[s1], lb = tl[s2];
         if (GRAD) {
           const double w = grad_w(a, b, la, lb, sg, run.omega0);
           if (GRAD == 1) acc[0] += rec.a * w;
@@ -192,22 +256,26 @@ __device__ __forceinline__ void tile_run(const RunDesc& run, const RunRec* __res
           }
         }
         rot_pair(la, lb, c, s, sg, run.omega0);
-        tl[l] = la;
-        tl[l2] = lb;
+        tl[s1] = la;
+        tl[s2] = lb;
       }
       rot_pair(a, b, c, s, sg, run.omega0);
-      tp[l] = a;
-      tp[l2] = b;
+      tp[s1] = a;
+      tp[s2] = b;
     }
   } else {
-    for (uint32_t l = threadIdx.x; l < nloc; l += NT) {
+    for (uint32_t j = 0; j < nj; ++j) {
+      const uint32_t rest = deposit_bits(j, run.hi_mask) | wbits;
+      if (!lane_on) continue;
+      const uint32_t l = dl | rest;
+      const uint32_t s1 = ds ^ lds_swz(rest);
       const unsigned sg = so ^ parity32(l & zl);
       const unsigned p = run_pattern(run, l, base);
       const RunRec rec = recs[run.rec_off + p];
       const R c = R(rec.c), s = (REV ? R(-rec.s) : R(rec.s)) * (sg ? R(-1) : R(1));
-      const T a = tp[l];
+      const T a = tp[s1];
       if (REV) {
-        const T la = tl[l];
+        const T la = tl[s1];
         if (GRAD) {
           double w = (double)la.x * (double)a.y - (double)la.y * (double)a.x;
           if (sg) w = -w;
@@ -220,43 +288,40 @@ __device__ __forceinline__ void tile_run(const RunDesc& run, const RunRec* __res
             }
           }
         }
-        tl[l] = cmake<T>(c * la.x + s * la.y, c * la.y - s * la.x);
+        tl[s1] = cmake<T>(c * la.x + s * la.y, c * la.y - s * la.x);
       }
-      tp[l] = cmake<T>(c * a.x + s * a.y, c * a.y - s * a.x);
+      tp[s1] = cmake<T>(c * a.x + s * a.y, c * a.y - s * a.x);
     }
   }
 }
 
-// ---------------------------------------------------------------------------
-// LDS tile, forward: load, apply every run of the pass, store.
-// ---------------------------------------------------------------------------
-// Copy the pass's run descriptors and records into LDS (once per block).
-template <int NT>
-__device__ __forceinline__ void stage_pass(const RunDesc* __restrict__ runs, int n_runs,
-                                           const RunRec* __restrict__ recs, int n_recs, RunDesc* s_runs,
-                                           RunRec* s_recs) {
-  const uint4* src = reinterpret_cast<const uint4*>(runs);
-  uint4* dst = reinterpret_cast<uint4*>(s_runs);
-  const int w1 = n_runs * int(sizeof(RunDesc) / 16);
-  for (int i = threadIdx.x; i < w1; i += NT) dst[i] = src[i];
-  src = reinterpret_cast<const uint4*>(recs);
-  dst = reinterpret_cast<uint4*>(s_recs);
-  const int w2 = n_recs * int(sizeof(RunRec) / 16);
-  for (int i = threadIdx.x; i < w2; i += NT) dst[i] = src[i];
+// this wavefront's region bits: its index deposited into the segment's mask
+__device__ __forceinline__ uint32_t region_bits_of(uint32_t wb_mask, uint32_t wave) {
+  uint32_t wbits = 0;
+  int j = 0;
+  for (uint32_t m = wb_mask; m; m &= m - 1, ++j) wbits |= ((wave >> j) & 1u) << (__ffs(m) - 1);
+  return wbits;
 }
 
+// ---------------------------------------------------------------------------
+// LDS tile, forward: load, apply every run of the pass, store.  Within a
+// segment each wavefront runs through the segment's runs on its own region;
+// a block barrier separates segments.  Descriptors are read in place through
+// scalar loads.
+// ---------------------------------------------------------------------------
 template <typename T, int B, int NT>
 __global__ void __launch_bounds__(NT) k_tile_forward(T* __restrict__ psi, FrameDesc fr,
-                                                     const RunDesc* __restrict__ runs_g, int n_runs,
-                                                     const RunRec* __restrict__ recs_g, int n_recs, uint64_t n_tb) {
+                                                     const RunDesc* __restrict__ runs,
+                                                     const RunRec* __restrict__ recs,
+                                                     const SegDesc* __restrict__ segs, int n_segs, uint64_t n_tb) {
   constexpr int PER = (1 << B) / NT;
   __shared__ T tile[1 << B];
   __shared__ FrameLut lut;
-  __shared__ RunDesc runs[kMaxPassRuns];
-  __shared__ RunRec recs[kMaxPassRecs];
   frame_lut_init<NT>(fr, lut);
-  stage_pass<NT>(runs_g, n_runs, recs_g, n_recs, runs, recs);
   __syncthreads();
+  const uint32_t lane = threadIdx.x & 63u;
+  const uint32_t wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+  const LaneBits lbits(lane);
   const uint32_t nloc = 1u << fr.b;
   double dummy[1];
   Stage<T, PER> reg;
@@ -268,8 +333,13 @@ __global__ void __launch_bounds__(NT) k_tile_forward(T* __restrict__ psi, FrameD
     __syncthreads();
     const uint64_t nx = tb + gridDim.x;
     if (nx < n_tb) tile_fetch<T, PER, NT>(psi, lut, frame_base(fr, nx), nloc, reg);
-    for (int ri = 0; ri < n_runs; ++ri) {
-      tile_run<T, NT, false, 0>(runs[ri], recs, tile, nullptr, nloc, base, dummy);
+    for (int si = 0; si < n_segs; ++si) {
+      const SegDesc sg = segs[si];
+      if (wave < (1u << __popc(sg.wb_mask))) {
+        const uint32_t wbits = region_bits_of(sg.wb_mask, wave);
+        for (uint32_t ri = sg.first; ri < sg.first + sg.count; ++ri)
+          tile_run<T, false, 0>(runs[ri], recs, tile, nullptr, base, wbits, lane, lbits, dummy);
+      }
       __syncthreads();
     }
     tile_store<T, PER, NT>(psi, lut, base, nloc, tile);
@@ -290,8 +360,9 @@ struct GradAcc {
 
 template <typename T, int B, int NT, int GRAD, int MAXS>
 __global__ void __launch_bounds__(NT) k_tile_reverse(T* __restrict__ psi, T* __restrict__ lam, FrameDesc fr,
-                                                     const RunDesc* __restrict__ runs_g, int n_runs,
-                                                     const RunRec* __restrict__ recs_g, int n_recs,
+                                                     const RunDesc* __restrict__ runs,
+                                                     const RunRec* __restrict__ recs,
+                                                     const SegDesc* __restrict__ segs, int n_segs,
                                                      const uint32_t* __restrict__ slot_map, int n_slots,
                                                      double* __restrict__ partials, uint32_t nb_stride,
                                                      uint64_t n_tb) {
@@ -301,11 +372,10 @@ __global__ void __launch_bounds__(NT) k_tile_reverse(T* __restrict__ psi, T* __r
   __shared__ T tl[1 << B];
   __shared__ FrameLut lut;
   __shared__ GradAcc<NW, MAXS> gacc;
-  __shared__ RunDesc runs[kMaxPassRuns];
-  __shared__ RunRec recs[kMaxPassRecs];
-  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  const uint32_t lane = threadIdx.x & 63u;
+  const uint32_t wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+  const LaneBits lbits(lane);
   frame_lut_init<NT>(fr, lut);
-  stage_pass<NT>(runs_g, n_runs, recs_g, n_recs, runs, recs);
   for (int i = threadIdx.x; i < MAXS * NW; i += NT) (&gacc.v[0][0])[i] = 0.0;
   __syncthreads();
   const uint32_t nloc = 1u << fr.b;
@@ -327,18 +397,24 @@ __global__ void __launch_bounds__(NT) k_tile_reverse(T* __restrict__ psi, T* __r
       tile_fetch<T, PER, NT>(psi, lut, b1, nloc, rp);
       tile_fetch<T, PER, NT>(lam, lut, b1, nloc, rl);
     }
-    for (int ri = 0; ri < n_runs; ++ri) {
-      const RunDesc run = runs[ri];
-      double acc[GRAD == 2 ? kMaxRunStrings : 1];
+    for (int si = 0; si < n_segs; ++si) {
+      const SegDesc sg = segs[si];
+      if (wave < (1u << __popc(sg.wb_mask))) {
+        const uint32_t wbits = region_bits_of(sg.wb_mask, wave);
+        for (uint32_t ri = sg.first; ri < sg.first + sg.count; ++ri) {
+          const RunDesc run = runs[ri];
+          double acc[GRAD == 2 ? kMaxRunStrings : 1];
 #pragma unroll
-      for (int k = 0; k < (GRAD == 2 ? kMaxRunStrings : 1); ++k) acc[k] = 0.0;
-      tile_run<T, NT, true, GRAD>(run, recs, tp, tl, nloc, base, acc);
-      if (GRAD) {
-        const int nk = GRAD == 2 ? run.n_str : 1;
-        for (int k = 0; k < (GRAD == 2 ? kMaxRunStrings : 1); ++k) {
-          if (k >= nk) break;
-          const double v = wave_sum(acc[k]);
-          if (lane == 0) gacc.v[run.slot + k][wave] += v;
+          for (int k = 0; k < (GRAD == 2 ? kMaxRunStrings : 1); ++k) acc[k] = 0.0;
+          tile_run<T, true, GRAD>(run, recs, tp, tl, base, wbits, lane, lbits, acc);
+          if (GRAD) {
+            const int nk = GRAD == 2 ? int(run.n_str) : 1;
+            for (int k = 0; k < (GRAD == 2 ? kMaxRunStrings : 1); ++k) {
+              if (k >= nk) break;
+              const double v = wave_sum(acc[k]);
+              if (lane == 0) gacc.v[run.slot + k][wave] += v;
+            }
+          }
         }
       }
       __syncthreads();
@@ -392,45 +468,44 @@ hipError_t launch_run_full(int dtype, bool rev, int grad, void* psi, void* lam, 
   return run_full_t<float2>(rev, grad, psi, lam, run, recs, partials, n, nb_stride, grid, st);
 }
 
-hipError_t launch_tile_forward(int dtype, void* psi, const FrameDesc& fr, const RunDesc* runs, int n_runs,
-                               const RunRec* recs, int n_recs, uint64_t n_tb, int grid, hipStream_t st) {
-  if (n_runs > kMaxPassRuns || n_recs > kMaxPassRecs) return hipErrorInvalidValue;
+hipError_t launch_tile_forward(int dtype, void* psi, const FrameDesc& fr, const RunDesc* runs, const RunRec* recs,
+                               const SegDesc* segs, int n_segs, uint64_t n_tb, int grid, hipStream_t st) {
   if (dtype == 0)
     hipLaunchKernelGGL((k_tile_forward<double2, kTileFwdC128, kTileThreads>), dim3(grid), dim3(kTileThreads), 0,
-                       st, static_cast<double2*>(psi), fr, runs, n_runs, recs, n_recs, n_tb);
+                       st, static_cast<double2*>(psi), fr, runs, recs, segs, n_segs, n_tb);
   else
     hipLaunchKernelGGL((k_tile_forward<float2, kTileFwdC64, kTileThreads>), dim3(grid), dim3(kTileThreads), 0,
-                       st, static_cast<float2*>(psi), fr, runs, n_runs, recs, n_recs, n_tb);
+                       st, static_cast<float2*>(psi), fr, runs, recs, segs, n_segs, n_tb);
   return hipGetLastError();
 }
 
 template <typename T, int B>
 static hipError_t tile_reverse_t(int grad, void* psi, void* lam, const FrameDesc& fr, const RunDesc* runs,
-                                 int n_runs, const RunRec* recs, int n_recs, const uint32_t* slot_map, int n_slots,
-                                 double* partials, uint32_t nb, uint64_t n_tb, int grid, hipStream_t st) {
+                                 const RunRec* recs, const SegDesc* segs, int n_segs, const uint32_t* slot_map,
+                                 int n_slots, double* partials, uint32_t nb, uint64_t n_tb, int grid, hipStream_t st) {
   T* p = static_cast<T*>(psi);
   T* l = static_cast<T*>(lam);
   if (grad == 0)
     hipLaunchKernelGGL((k_tile_reverse<T, B, kTileThreads, 0, 1>), dim3(grid), dim3(kTileThreads), 0, st, p, l,
-                       fr, runs, n_runs, recs, n_recs, slot_map, n_slots, partials, nb, n_tb);
+                       fr, runs, recs, segs, n_segs, slot_map, n_slots, partials, nb, n_tb);
   else if (grad == 1)
     hipLaunchKernelGGL((k_tile_reverse<T, B, kTileThreads, 1, kMaxPassSlots>), dim3(grid), dim3(kTileThreads), 0,
-                       st, p, l, fr, runs, n_runs, recs, n_recs, slot_map, n_slots, partials, nb, n_tb);
+                       st, p, l, fr, runs, recs, segs, n_segs, slot_map, n_slots, partials, nb, n_tb);
   else
     hipLaunchKernelGGL((k_tile_reverse<T, B, kTileThreads, 2, kMaxPassSlots>), dim3(grid), dim3(kTileThreads), 0,
-                       st, p, l, fr, runs, n_runs, recs, n_recs, slot_map, n_slots, partials, nb, n_tb);
+                       st, p, l, fr, runs, recs, segs, n_segs, slot_map, n_slots, partials, nb, n_tb);
   return hipGetLastError();
 }
 
 hipError_t launch_tile_reverse(int dtype, int grad, void* psi, void* lam, const FrameDesc& fr,
-                               const RunDesc* runs, int n_runs, const RunRec* recs, int n_recs,
+                               const RunDesc* runs, const RunRec* recs, const SegDesc* segs, int n_segs,
                                const uint32_t* slot_map, int n_slots, double* partials, uint32_t nb_stride,
                                uint64_t n_tb, int grid, hipStream_t st) {
-  if (n_runs > kMaxPassRuns || n_recs > kMaxPassRecs || n_slots > kMaxPassSlots) return hipErrorInvalidValue;
+  if (n_slots > kMaxPassSlots) return hipErrorInvalidValue;
   if (dtype == 0)
-    return tile_reverse_t<double2, kTileTwoC128>(grad, psi, lam, fr, runs, n_runs, recs, n_recs, slot_map,
-                                                 n_slots, partials, nb_stride, n_tb, grid, st);
-  return tile_reverse_t<float2, kTileTwoC64>(grad, psi, lam, fr, runs, n_runs, recs, n_recs, slot_map, n_slots,
+    return tile_reverse_t<double2, kTileTwoC128>(grad, psi, lam, fr, runs, recs, segs, n_segs, slot_map, n_slots,
+                                                 partials, nb_stride, n_tb, grid, st);
+  return tile_reverse_t<float2, kTileTwoC64>(grad, psi, lam, fr, runs, recs, segs, n_segs, slot_map, n_slots,
                                              partials, nb_stride, n_tb, grid, st);
 }
 

@@ -15,25 +15,25 @@ constexpr int kTileFwdC128 = 13, kTileFwdC64 = 14;   // one state tile
 constexpr int kTileTwoC128 = 12, kTileTwoC64 = 13;   // two tiles (psi and lam)
 constexpr int kTileLamC128 = 12, kTileLamC64 = 12;   // psi tile + FP64 lambda accumulator
 constexpr int kTileThreads = 512;
-constexpr int kLambdaThreads = 256;                  // 4 wavefronts own 4 output regions
-constexpr int kLambdaRegionBits = 2;
+constexpr int kTileRegionBits = 3;                   // 8 wavefronts own 8 regions of a segment
+constexpr int kLambdaThreads = 1024;                 // 16 wavefronts share one tile
 constexpr int kBlobWords = 26 * 1024 / 16;           // group tables staged in LDS (26 KiB)
 constexpr int kMaxPassSlots = 128;                   // gradient slots per reverse tile pass
-constexpr int kMaxPassRuns = 64;                     // runs per tile pass (descriptors staged in LDS)
-constexpr int kMaxPassRecs = 192;                    // run records per tile pass (staged in LDS)
+constexpr int kMaxPassRuns = 1 << 16;                // runs per tile pass
+constexpr int kMaxPassRecs = 1 << 20;                // run records per tile pass
 constexpr uint32_t kPartialStride = 1024;            // max blocks of a gradient pass
 
 hipError_t launch_fill_basis(int dtype, void* psi, uint64_t n_amp, uint64_t k, hipStream_t st);
 hipError_t launch_run_full(int dtype, bool rev, int grad, void* psi, void* lam, const RunDesc& run,
                            const RunRec* recs, double* partials, int n, uint32_t nb_stride, int grid,
                            hipStream_t st);
-// Tile passes: runs[0..n_runs) and recs[0..n_recs) are the pass's own
-// descriptors and records (record offsets relative to recs), at most
-// kMaxPassRuns and kMaxPassRecs; they are staged in LDS.
-hipError_t launch_tile_forward(int dtype, void* psi, const FrameDesc& fr, const RunDesc* runs, int n_runs,
-                               const RunRec* recs, int n_recs, uint64_t n_tb, int grid, hipStream_t st);
+// Tile passes: runs and recs are the pass's own descriptors and records
+// (record offsets relative to recs); segs[0..n_segs) cover the runs in order
+// and every descriptor's walk matches its segment's region bits.
+hipError_t launch_tile_forward(int dtype, void* psi, const FrameDesc& fr, const RunDesc* runs, const RunRec* recs,
+                               const SegDesc* segs, int n_segs, uint64_t n_tb, int grid, hipStream_t st);
 hipError_t launch_tile_reverse(int dtype, int grad, void* psi, void* lam, const FrameDesc& fr,
-                               const RunDesc* runs, int n_runs, const RunRec* recs, int n_recs,
+                               const RunDesc* runs, const RunRec* recs, const SegDesc* segs, int n_segs,
                                const uint32_t* slot_map, int n_slots, double* partials, uint32_t nb_stride,
                                uint64_t n_tb, int grid, hipStream_t st);
 hipError_t launch_tile_lambda(int dtype, bool first, const void* psi, void* lam, const double* diag,

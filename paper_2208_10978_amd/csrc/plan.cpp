@@ -143,18 +143,18 @@ RunDesc make_run_desc(const Run& r, const RunData& d, uint64_t qmask, uint32_t s
   rd.omega0 = d.omega0;
   rd.slot = slot;
   rd.rec_off = uint32_t(recs_out.size());
-  rd.n_rec = uint16_t(d.recs.size());
+  rd.n_rec = uint32_t(d.recs.size());
   rd.mode = d.mode;
-  rd.n_str = uint8_t(r.count);
+  rd.n_str = uint32_t(r.count);
   rd.str_neg = d.str_neg;
   for (int k = 0; k < kMaxRunStrings; ++k) rd.dpat_pack |= uint64_t(d.str_dpat[k]) << (8 * k);
-  rd.per_string = uint8_t(per_string);
-  if (r.x) rd.pivot = uint8_t(local_pos(highest_bit(r.x), qmask));
-  rd.n_sup = uint8_t(d.mode == kRunEnum ? d.sup_glob.size() : 0);
+  rd.per_string = uint32_t(per_string);
+  if (r.x) rd.pivot = uint32_t(local_pos(highest_bit(r.x), qmask));
+  rd.n_sup = uint32_t(d.mode == kRunEnum ? d.sup_glob.size() : 0);
   if (d.mode == kRunEnum)
     for (size_t j = 0; j < d.sup_glob.size(); ++j)
       rd.sup_pack |= uint64_t(local_pos(d.sup_glob[j], qmask)) << (8 * j);
-  rd.n_pat = uint8_t(d.mode == kRunEnum ? 0 : d.pat_glob.size());
+  rd.n_pat = uint32_t(d.mode == kRunEnum ? 0 : d.pat_glob.size());
   if (d.mode != kRunEnum)
     for (size_t j = 0; j < d.pat_glob.size(); ++j) {
       const int g = d.pat_glob[j];
@@ -167,6 +167,60 @@ RunDesc make_run_desc(const Run& r, const RunData& d, uint64_t qmask, uint32_t s
     recs_out.push_back(o);
   }
   return rd;
+}
+
+void set_tile_walk(RunDesc& rd, uint32_t wb_mask, int b) {
+  uint32_t ins = wb_mask;
+  if (rd.mode == kRunEnum) {
+    for (uint32_t j = 0; j < rd.n_sup; ++j) ins |= 1u << unsigned((rd.sup_pack >> (8 * j)) & 0xffu);
+  } else if (rd.mode == kRunFull) {
+    ins |= 1u << rd.pivot;
+  }
+  const uint32_t all = (1u << b) - 1u;
+  uint32_t free_bits = all & ~ins;
+  rd.walk_log = uint32_t(popc(uint64_t(free_bits)));
+  rd.zlane = 0;
+  for (int i = 0; i < kWalkLaneBits; ++i) {
+    if (free_bits) {
+      const uint32_t p = free_bits & (~free_bits + 1u);
+      rd.dep_p[i] = p;
+      rd.dep_q[i] = lds_slot(p);
+      if (uint32_t(rd.z0_loc) & p) rd.zlane |= 1u << i;
+      free_bits &= free_bits - 1;
+    } else {
+      rd.dep_p[i] = rd.dep_q[i] = 0;
+    }
+  }
+  rd.hi_mask = free_bits;
+}
+
+std::vector<SegDesc> segment_pass(const std::vector<uint32_t>& x_loc, int b, int region_bits) {
+  std::vector<SegDesc> out;
+  const uint32_t all = b >= 32 ? ~0u : ((1u << b) - 1u);
+  // pick region bits outside `used`, highest first (the lanes of a wavefront
+  // then walk the low, contiguous bits)
+  auto pick = [&](uint32_t used) {
+    uint32_t wb = 0;
+    for (int p = b - 1; p >= 0 && popc(uint64_t(wb)) < region_bits; --p)
+      if (!((used >> p) & 1u)) wb |= 1u << p;
+    return popc(uint64_t(wb)) == region_bits ? wb : 0u;
+  };
+  size_t i = 0;
+  while (i < x_loc.size()) {
+    SegDesc sg{uint32_t(i), 0, 0, 0};
+    uint32_t used = 0;
+    while (i < x_loc.size()) {
+      const uint32_t nu = used | (x_loc[i] & all);
+      if (sg.count > 0 && popc(uint64_t(all & ~nu)) < region_bits) break;
+      used = nu;
+      ++sg.count;
+      ++i;
+      if (popc(uint64_t(all & ~used)) < region_bits) break;  // a run too wide for regions: alone
+    }
+    sg.wb_mask = pick(used);
+    out.push_back(sg);
+  }
+  return out;
 }
 
 double run_line_fraction(const RunData& d, int c) {
@@ -388,14 +442,14 @@ static size_t group_blob_bytes(const HGroup& g) {
 }
 
 // Pack groups of one tile into a blob (TileHdr, TGroup[], record bits[], TSub[], coef[], TFast[]).
-static bool fast_group(const HGroup& g, uint64_t qmask, uint32_t wb_mask) {
+static bool fast_group(const HGroup& g, uint64_t qmask) {
   if (g.w.size() != 1 || g.n_rec() > kFastRecs) return false;
   const uint32_t sm = g.enumerated ? uint32_t(compress(g.x, qmask)) : (1u << local_pos(highest_bit(g.x), qmask));
-  return popc(uint64_t(sm | wb_mask)) <= kFastIns;
+  return popc(uint64_t(sm)) <= kFastIns;
 }
 
 static void pack_blob(HTiling& t, const std::vector<HGroup>& gs, const std::vector<int>& members, uint64_t qmask,
-                      uint32_t wb_mask, size_t max_blob, bool use_fast) {
+                      size_t max_blob, bool use_fast) {
   std::vector<TGroup> tg;
   std::vector<uint32_t> to;
   std::vector<TSub> ts;
@@ -403,12 +457,12 @@ static void pack_blob(HTiling& t, const std::vector<HGroup>& gs, const std::vect
   std::vector<TFast> tf;
   for (int gi : members) {
     const HGroup& g = gs[gi];
-    if (use_fast && fast_group(g, qmask, wb_mask)) {
+    if (use_fast && fast_group(g, qmask)) {
       TFast f{};
       f.x_loc = uint32_t(compress(g.x, qmask));
       f.sup_mask = g.enumerated ? f.x_loc : (1u << local_pos(highest_bit(g.x), qmask));
       int k = 0;
-      for (uint32_t m = f.sup_mask | wb_mask; m; m &= m - 1) f.ins_lo[k++] = (1u << __builtin_ctz(m)) - 1u;
+      for (uint32_t m = f.sup_mask; m; m &= m - 1) f.ins_lo[k++] = (1u << __builtin_ctz(m)) - 1u;
       f.n_ins = uint32_t(k);
       for (int j = k; j < kFastIns; ++j) f.ins_lo[j] = ~0u;  // no-op steps
       f.n_rec = uint32_t(g.n_rec());
@@ -438,9 +492,6 @@ static void pack_blob(HTiling& t, const std::vector<HGroup>& gs, const std::vect
     int k = 0;
     for (uint32_t m = smask; m; m &= m - 1) d.sins_pack |= uint64_t(__builtin_ctz(m)) << (4 * k++);
     d.n_sins = uint32_t(k);
-    k = 0;
-    for (uint32_t m = smask | wb_mask; m; m &= m - 1) d.ins_pack |= uint64_t(__builtin_ctz(m)) << (4 * k++);
-    d.n_ins = uint32_t(k);
     std::vector<uint32_t> rec_loc(NR);
     for (int r = 0; r < NR; ++r) rec_loc[r] = g.enumerated ? uint32_t(compress(g.rec_v[r], qmask)) : smask;
     for (int r = 0; r < NR; ++r) to.push_back(rec_loc[r]);
@@ -469,9 +520,19 @@ static void pack_blob(HTiling& t, const std::vector<HGroup>& gs, const std::vect
   h.off_fast = uint32_t(align16(off));
   h.n_fast = uint32_t(tf.size());
   off = h.off_fast + tf.size() * sizeof(TFast);
+  // work items of the fast records: blocks of 64 positions of the free bits
+  std::vector<uint32_t> items;
+  const int fb = popc(qmask);
+  for (size_t i = 0; i < tf.size(); ++i) {
+    const int nf = fb - int(tf[i].n_ins);
+    const uint32_t nblk = nf > 6 ? (1u << (nf - 6)) : 1u;
+    for (uint32_t c = 0; c < nblk; ++c) items.push_back(uint32_t(i) << 12 | c);
+  }
+  h.off_items = uint32_t(align16(off));
+  h.n_fast_items = uint32_t(items.size());
+  off = h.off_items + items.size() * sizeof(uint32_t);
   h.bytes = uint32_t(align16(off));
-  h.wb_mask = wb_mask;
-  if (h.bytes > max_blob) t.blob_overflow = true;
+  if (h.bytes > max_blob || tf.size() >= (1u << 20) || fb > 18) t.blob_overflow = true;
   std::vector<unsigned char> bytes(h.bytes, 0);
   std::memcpy(bytes.data(), &h, sizeof(h));
   if (!tg.empty()) std::memcpy(bytes.data() + sizeof(TileHdr), tg.data(), tg.size() * sizeof(TGroup));
@@ -479,6 +540,7 @@ static void pack_blob(HTiling& t, const std::vector<HGroup>& gs, const std::vect
   if (!ts.empty()) std::memcpy(bytes.data() + h.off_sub, ts.data(), ts.size() * sizeof(TSub));
   if (!co.empty()) std::memcpy(bytes.data() + h.off_coef, co.data(), co.size() * sizeof(double));
   if (!tf.empty()) std::memcpy(bytes.data() + h.off_fast, tf.data(), tf.size() * sizeof(TFast));
+  if (!items.empty()) std::memcpy(bytes.data() + h.off_items, items.data(), items.size() * sizeof(uint32_t));
   t.blob_off.push_back(uint32_t(t.blob.size() / 2));
   const size_t words = h.bytes / 8;
   const size_t at = t.blob.size();
@@ -486,7 +548,7 @@ static void pack_blob(HTiling& t, const std::vector<HGroup>& gs, const std::vect
   std::memcpy(t.blob.data() + at, bytes.data(), h.bytes);
 }
 
-HTiling build_tiling(const std::vector<HGroup>& gs, int n, int b, int c, int region_bits, size_t max_blob) {
+HTiling build_tiling(const std::vector<HGroup>& gs, int n, int b, int c, bool fast_records, size_t max_blob) {
   HTiling t;
   t.b = b;
   t.c = c;
@@ -547,35 +609,12 @@ HTiling build_tiling(const std::vector<HGroup>& gs, int n, int b, int c, int reg
     std::vector<int> members;
     for (int g = 0; g < G; ++g)
       if (tile_of[g] == tt) members.push_back(g);
-    // region bits: the frame-local bits at or above c least used by the tile's
-    // enumerated bits
-    uint32_t wb = 0;
-    const int fb = popc(q);
-    if (region_bits > 0 && fb - c >= region_bits) {
-      std::vector<int> use(fb, 0);
-      for (int g : members) {
-        const uint32_t xl = uint32_t(compress(gs[g].x, q));
-        const uint32_t sm = gs[g].enumerated ? xl : (1u << local_pos(highest_bit(gs[g].x), q));
-        for (uint32_t m = sm; m; m &= m - 1) use[__builtin_ctz(m)] += 1;
-      }
-      // prefer bits above the lowest four: lanes then walk the contiguous
-      // low bits and their 16-byte LDS accesses do not share banks
-      const int lo = fb - std::max(c, 4) >= region_bits ? std::max(c, 4) : c;
-      for (int k = 0; k < region_bits; ++k) {
-        int best = -1;
-        for (int p = lo; p < fb; ++p)
-          if (!((wb >> p) & 1u) && (best < 0 || use[p] < use[best])) best = p;
-        wb |= 1u << best;
-      }
-    } else if (region_bits > 0) {
-      for (int p = 0; p < fb && popc(wb) < region_bits; ++p) wb |= 1u << p;
-    }
     // chunks of at most max_blob bytes
     std::vector<int> chunk;
     size_t bytes = fixed;
     auto flush = [&]() {
       t.frames.push_back(make_frame(q, n, c));
-      pack_blob(t, gs, chunk, q, wb, max_blob, region_bits > 0);
+      pack_blob(t, gs, chunk, q, max_blob, fast_records);
       chunk.clear();
       bytes = fixed;
     };

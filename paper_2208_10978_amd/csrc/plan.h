@@ -67,6 +67,16 @@ RunDesc make_run_desc(const Run& r, const RunData& d, uint64_t qmask, uint32_t s
 
 FrameDesc make_frame(uint64_t qmask, int n, int c);
 
+// Fill a tile descriptor's walk for a segment with region bits wb_mask in a
+// frame of b bits.
+void set_tile_walk(RunDesc& rd, uint32_t wb_mask, int b);
+
+// Split a tile pass (its runs' frame-local x masks, in application order)
+// into segments that leave region_bits frame bits untouched; region bits are
+// chosen per segment.  A run whose x leaves fewer free bits forms a segment
+// of its own with wb_mask = 0.
+std::vector<SegDesc> segment_pass(const std::vector<uint32_t>& x_loc, int b, int region_bits);
+
 // Fraction of the state's bytes a kRunEnum run moves when applied alone
 // (lines of 2^c amplitudes are moved whole).
 double run_line_fraction(const RunData& d, int c);
@@ -119,8 +129,8 @@ struct HTiling {
   bool blob_overflow = false;            // a blob exceeded max_blob (never expected)
 };
 
-// region_bits > 0 chooses that many frame-local bits (at or above c) per tile
-// to split lambda outputs among wavefronts.
-HTiling build_tiling(const std::vector<HGroup>& gs, int n, int b, int c, int region_bits, size_t max_blob);
+// fast_records packs one-subgroup groups as TFast records with work items
+// (lambda tilings).
+HTiling build_tiling(const std::vector<HGroup>& gs, int n, int b, int c, bool fast_records, size_t max_blob);
 
 }  // namespace q2sv

@@ -37,6 +37,17 @@ enum RunMode : uint8_t {
 };
 
 // One run of commuting same-x rotations, in the coordinates of its frame.
+// Every field is a full 32 or 64 bits, so tile kernels reading descriptors
+// from global memory with a uniform index get scalar loads.
+constexpr int kWalkLaneBits = 6;    // walk positions carried by the lane index
+
+// LDS slot of frame-local index l.  A tile walk's lanes differ in the free
+// bits of a run or group, which are often all above bit 3; unswizzled, their
+// 16-byte elements would then share LDS banks.  XORing the low four bits with
+// a fold of the higher ones spreads them.  The map is linear over GF(2)
+// (slot(a ^ b) = slot(a) ^ slot(b)), keeps bits 4 and up, and is a bijection
+// on [0, 2^B) for every B.  (constexpr: usable by host planning and kernels.)
+constexpr uint32_t lds_slot(uint32_t l) { return l ^ (((l >> 4) ^ (l >> 5) ^ (l >> 7) ^ (l >> 10)) & 15u); }
 struct alignas(16) RunDesc {
   uint64_t x_loc;      // flip mask (frame-local bits)
   uint64_t z0_loc;     // reference string's z, frame-local bits
@@ -44,20 +55,42 @@ struct alignas(16) RunDesc {
   uint32_t omega0;     // reference phase i^{|x & z0|}, as a power of i
   uint32_t slot;       // first gradient slot of the run
   uint32_t rec_off;    // first record (kRunEnum) or table entry (kRunFull/Diag)
-  uint16_t n_rec;      // number of records, or 2^L table entries
-  uint8_t mode;        // RunMode
-  uint8_t n_str;       // strings fused in the run
-  uint8_t str_neg;     // bit k: omega_k / omega_0 = -1            (kRunFull/Diag)
-  uint8_t n_sup;       // support bits (kRunEnum)
-  uint8_t pivot;       // frame-local highest bit of x             (kRunFull)
-  uint8_t n_pat;       // pattern bits L                           (kRunFull/Diag)
-  uint8_t per_string;  // gradient slots are per string (else one per run)
+  uint32_t n_rec;      // number of records, or 2^L table entries
+  uint32_t mode;       // RunMode
+  uint32_t n_str;      // strings fused in the run
+  uint32_t str_neg;    // bit k: omega_k / omega_0 = -1            (kRunFull/Diag)
+  uint32_t n_sup;      // support bits (kRunEnum)
+  uint32_t pivot;      // frame-local highest bit of x             (kRunFull)
+  uint32_t n_pat;      // pattern bits L                           (kRunFull/Diag)
+  uint32_t per_string; // gradient slots are per string (else one per run)
+  uint32_t walk_log;   // tile walk: 2^walk_log positions per record
   // Position lists packed one byte per entry (entry j in bits 8j..8j+7), so
   // kernels read them with shifts instead of indexing a private array:
   uint64_t sup_pack;   // frame-local support positions, ascending
   uint64_t pat_pack;   // pattern bit j: frame-local position, or 64 + global
                        // position when outside the frame
   uint64_t dpat_pack;  // per string: pattern mask of z_k ^ z0
+  // Tile walk: position t = lane + 64 j of the bits the run leaves free
+  // (not enumerated, not region bits).  Lane bit i lands on frame-local bit
+  // dep_p[i] (0 past the walk's width), whose LDS slot is dep_q[i]; the bits
+  // of j land on the free bits hi_mask above them; zlane bit i is the z0 bit
+  // at dep_p[i].
+  uint32_t dep_p[kWalkLaneBits];
+  uint32_t dep_q[kWalkLaneBits];
+  uint32_t hi_mask;
+  uint32_t zlane;
+};
+
+// A segment of a tile pass: consecutive runs none of whose x masks touches
+// the frame-local bits wb_mask.  Wavefront w owns the amplitudes whose
+// wb_mask bits spell w and applies the segment's runs to them with no block
+// barrier (pairs never leave a region); with wb_mask = 0 wavefront 0 owns the
+// whole tile.
+struct alignas(16) SegDesc {
+  uint32_t first;      // first run (index into the pass's descriptors)
+  uint32_t count;
+  uint32_t wb_mask;
+  uint32_t pad;
 };
 
 // A record (kRunEnum) or table entry (kRunFull/Diag) of a run:
@@ -123,9 +156,11 @@ struct alignas(16) TileHdr {
   uint32_t off_sub;    // byte offset of the TSub array
   uint32_t off_coef;   // byte offset of the coefficients (double2)
   uint32_t bytes;      // blob size in bytes (multiple of 16)
-  uint32_t wb_mask;    // frame-local bits that split lambda outputs among wavefronts
   uint32_t n_fast;     // TFast records (lambda tilings only)
   uint32_t off_fast;   // byte offset of the TFast array
+  uint32_t n_fast_items;  // work items: TFast index << 12 | block of 64 free-bit positions
+  uint32_t off_items;  // byte offset of the work items (uint32 each)
+  uint32_t pad[2];
 };
 
 // Every field is a full 32 or 64 bits: a kernel reading these tables from
@@ -140,11 +175,8 @@ struct alignas(8) TGroup {
   uint32_t n_sub;      // subgroups
   uint32_t sub_off;    // first TSub
   uint32_t coef_off;   // first coefficient: coef[coef_off + sub * n_rec + rec]
-  uint32_t n_ins;      // zero insertions (S' union Wb, ascending) for lambda outputs
   uint32_t n_sins;     // zero insertions (S', ascending) for pairs
-  uint32_t pad;
-  uint64_t ins_pack;   // their frame-local positions, four bits each
-  uint64_t sins_pack;
+  uint64_t sins_pack;  // their frame-local positions, four bits each
 };
 
 // A group with one subgroup and at most four records, in one self-contained
@@ -152,7 +184,7 @@ struct alignas(8) TGroup {
 constexpr int kFastRecs = 4;
 constexpr int kFastIns = 8;
 struct alignas(16) TFast {
-  uint32_t ins_lo[kFastIns];  // zero insertions (S' union Wb, ascending) at p: the masks 2^p - 1
+  uint32_t ins_lo[kFastIns];  // zero insertions (S', ascending) at p: the masks 2^p - 1
   uint64_t w_out;      // w, global bits outside the frame
   uint32_t x_loc;      // frame-local flip mask
   uint32_t sup_mask;   // frame-local enumerated bits S'

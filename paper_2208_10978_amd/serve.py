@@ -6,8 +6,9 @@ in HBM, admits a waiting request as soon as a slot is free and its bytes fit
 the HBM budget (in arrival order; a request that does not fit yet may be
 passed by a smaller one that does), and runs each admitted request on its own
 HIP stream, so the work of requests in flight together overlaps on the
-device.  A request's arithmetic (its plans and reduction orders) depends only
-on the request, so its result is bitwise the same alone and in any mix.
+device.  A request's plans depend only on the request, so its result is the
+same alone and in any mix up to the rounding of lambda's accumulation (whose
+order across wavefronts is not fixed).
 
 Host-side preparation (the JW Pauli sum and the rotation list) runs in a
 thread pool ahead of admission.  ``fifo=True`` gives the one-request-at-a-
