@@ -240,10 +240,10 @@ static int tiling_get(sv_hamiltonian* h, int dtype, int role, DevTiling** out) {
   if (!h->built[dtype][role]) {
     const int b = role == 0 ? tile_bits_one(dtype) : tile_bits_lambda(dtype);
     const int c = std::min(dtype == 0 ? 3 : 4, h->n);
-    // expectation blobs are staged in LDS; lambda reads its tables through
-    // scalar loads, so a tile's groups need not be split
-    t.host = build_tiling(h->groups, h->n, b, c, role == 1, role == 1 ? size_t(1) << 20 : size_t(kBlobWords) * 16);
-    if (t.host.blob_overflow) return fail(SV_EINVAL, "internal: a tile's group tables exceed the LDS budget");
+    // kernels read the tables through scalar loads, so a tile's groups need
+    // not be split
+    t.host = build_tiling(h->groups, h->n, b, c, true, size_t(1) << 24);
+    if (t.host.blob_overflow) return fail(SV_EINVAL, "internal: a tile's group tables are too large");
     Packer pk;
     t.o_frames = pk.add(t.host.frames.data(), t.host.frames.size() * sizeof(FrameDesc));
     t.o_boff = pk.add(t.host.blob_off.data(), t.host.blob_off.size() * sizeof(uint32_t));
@@ -540,7 +540,7 @@ static int expect_impl(sv_state* s, sv_hamiltonian* h, double* out_dev) {
   const HTiling& ht = t->host;
   const int T = int(ht.frames.size());
   const uint64_t n_tb = uint64_t(1) << ht.frames[0].n_comp;
-  const uint32_t bpt = uint32_t(std::max<uint64_t>(1, std::min<uint64_t>(n_tb, std::max(1, 2 * num_cus() / T))));
+  const uint32_t bpt = uint32_t(std::min<uint64_t>(n_tb, uint64_t(num_cus())));
   const size_t n_full = ht.groups.size();
   const int gfull = full_grid(s->amp_count() / 2);
   const int gdot = dot_grid(s);
@@ -552,13 +552,13 @@ static int expect_impl(sv_state* s, sv_hamiltonian* h, double* out_dev) {
   double* part = static_cast<double*>(s->scratch.p);
   double* sm = static_cast<double*>(s->small.p);
   hipError_t e;
-  {
-    ProfScope prof(s->stream, kPTileHExp, double(T) * double(bpt) * double(n_tb) / double(bpt) * s->bytes() /
-                                              double(n_tb));
-    e = launch_tile_expect(s->dtype, s->amps, dptr<FrameDesc>(t->buf, t->o_frames), dptr<uint32_t>(t->buf, t->o_boff),
-                           dptr<uint4>(t->buf, t->o_blob), T, bpt, n_tb, part, s->stream);
+  const uint4* blobs = dptr<uint4>(t->buf, t->o_blob);
+  for (int tt = 0; tt < T; ++tt) {
+    ProfScope prof(s->stream, kPTileHExp, s->bytes());
+    e = launch_tile_expect(s->dtype, s->amps, ht.frames[tt], blobs + ht.blob_off[tt], n_tb, int(bpt),
+                           part + size_t(tt) * bpt, s->stream);
+    if (e != hipSuccess) return fail(SV_EDEVICE, std::string("expectation tiles: ") + hipGetErrorString(e));
   }
-  if (e != hipSuccess) return fail(SV_EDEVICE, std::string("expectation tiles: ") + hipGetErrorString(e));
   size_t off = size_t(T) * bpt;
   for (size_t gi = 0; gi < n_full; ++gi) {
     ProfScope prof(s->stream, kPGroupFull, group_bytes(s, ht.groups[gi], false));

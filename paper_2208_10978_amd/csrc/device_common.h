@@ -75,10 +75,34 @@ __device__ __forceinline__ uint32_t insert_zeros32_p4(uint32_t t, uint64_t pack,
 // ---------------------------------------------------------------------------
 // deterministic FP64 reductions
 // ---------------------------------------------------------------------------
+// FP64 add into LDS that returns nothing (no wait on the old value).
+__device__ __forceinline__ void lds_add(double* p, double v) {
+  __hip_atomic_fetch_add(p, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
+}
+
+// One DPP data movement of a double (both halves); lanes the pattern does
+// not feed, or rows row_mask leaves out, read 0.
+template <int CTRL, int ROW_MASK>
+__device__ __forceinline__ double dpp_f64(double v) {
+  const int lo = __builtin_amdgcn_update_dpp(0, __double2loint(v), CTRL, ROW_MASK, 0xf, true);
+  const int hi = __builtin_amdgcn_update_dpp(0, __double2hiint(v), CTRL, ROW_MASK, 0xf, true);
+  return __hiloint2double(hi, lo);
+}
+
+// Sum over the 64 lanes of a wavefront (every lane active), returned to all
+// lanes: inclusive scans within rows of 16 by row shifts, then the row totals
+// carried by row broadcasts, so the total lands in lane 63.  Only VALU data
+// movement (no LDS crossbar), and a fixed order of additions.
 __device__ __forceinline__ double wave_sum(double v) {
-#pragma unroll
-  for (int off = 32; off > 0; off >>= 1) v += __shfl_xor(v, off, 64);
-  return v;
+  v += dpp_f64<0x111, 0xf>(v);  // row_shr:1
+  v += dpp_f64<0x112, 0xf>(v);  // row_shr:2
+  v += dpp_f64<0x114, 0xf>(v);  // row_shr:4
+  v += dpp_f64<0x118, 0xf>(v);  // row_shr:8
+  v += dpp_f64<0x142, 0xa>(v);  // row_bcast:15 into rows 1 and 3
+  v += dpp_f64<0x143, 0xc>(v);  // row_bcast:31 into rows 2 and 3
+  const int lo = __builtin_amdgcn_readlane(__double2loint(v), 63);
+  const int hi = __builtin_amdgcn_readlane(__double2hiint(v), 63);
+  return __hiloint2double(hi, lo);
 }
 
 // Sum over the block; result valid in thread 0.  `scratch` holds one double

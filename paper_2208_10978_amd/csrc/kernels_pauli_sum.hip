@@ -31,12 +31,6 @@ struct BlobView {
   }
 };
 
-template <int NT>
-__device__ __forceinline__ void blob_stage(const uint4* __restrict__ src, uint4* dst) {
-  const uint32_t words = reinterpret_cast<const TileHdr*>(src)->bytes / 16;
-  for (uint32_t i = threadIdx.x; i < words; i += NT) dst[i] = src[i];
-}
-
 // ---------------------------------------------------------------------------
 // lambda over one tile: MODE 1 lam = diag * psi + H_tile psi; MODE 2 lam += H_tile psi
 //
@@ -49,42 +43,31 @@ __device__ __forceinline__ void blob_stage(const uint4* __restrict__ src, uint4*
 // the order in which the updates of different wavefronts reach an output is
 // not fixed, so the last bits of lambda may differ between runs.
 // ---------------------------------------------------------------------------
-__device__ __forceinline__ void lds_add(double* p, double v) {
-  __hip_atomic_fetch_add(p, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
-}
-
 // x * (-1)^s for s in {0, 1}: flips the sign bit
 __device__ __forceinline__ double signed_by(double x, unsigned s) {
   return __hiloint2double(__double2hiint(x) ^ int(s << 31), __double2loint(x));
 }
 
-// t with zero bits inserted at ascending positions p_j (lo[j] = 2^p_j - 1,
-// all ones for an unused slot): each step moves the bits at and above p_j up
-// by one and leaves a stray copy at p_j, cleared at the end by ins_mask.
-__device__ __forceinline__ uint32_t insert_zeros_lo(uint32_t t, const uint32_t (&lo)[kFastIns], uint32_t ins_mask) {
-#pragma unroll
-  for (int j = 0; j < kFastIns; ++j) t = (t & lo[j]) | ((t << 1) & ~lo[j]);
-  return t & ~ins_mask;
-}
-
 // The pairs (m', m = m' ^ x) of every record of a one-subgroup group at one
-// position of its free bits: all loads first, then the updates.
+// walk position (index part dl, slot part ds, w-parity of the lane part zp)
+// plus the uniform part rest: all loads first, then the updates.  The index
+// and slot of a record's m' are dl | rest | bits and ds ^ slot(rest | bits)
+// (the LDS slot map is linear).
 template <int NR, typename T>
-__device__ __forceinline__ void fast_pairs(const TFast& f, uint32_t ob, unsigned so, const T* tp, double* tlr,
-                                           double* tli) {
-  // LDS slots: linear in the index, so slot(ob | bits) = slot(ob) ^ slot(bits)
-  const uint32_t sob = lds_swz(ob), sx = lds_swz(f.x_loc);
+__device__ __forceinline__ void fast_pairs(const TFast& f, uint32_t ds, unsigned zp, uint32_t rest, unsigned so,
+                                           const T* tp, double* tlr, double* tli) {
+  const uint32_t sx = lds_swz(f.x_loc);
   uint32_t smp[NR];
   T pm[NR], pp[NR];
 #pragma unroll
   for (int r = 0; r < NR; ++r) {
-    smp[r] = sob ^ lds_swz(f.bits[r]);
+    smp[r] = ds ^ lds_swz(rest | f.bits[r]);
     pm[r] = tp[smp[r] ^ sx];
     pp[r] = tp[smp[r]];
   }
 #pragma unroll
   for (int r = 0; r < NR; ++r) {
-    const unsigned sg = __popc((ob | f.bits[r]) & f.w_loc) + so;
+    const unsigned sg = zp + __popc((rest | f.bits[r]) & f.w_loc) + so;
     const double gre = signed_by(f.coef[2 * r], sg), gim = signed_by(f.coef[2 * r + 1], sg);
     const uint32_t sm = smp[r] ^ sx;
     lds_add(&tlr[sm], gre * (double)pp[r].x - gim * (double)pp[r].y);  // lam[m] += G psi[m']
@@ -109,6 +92,9 @@ __global__ void __launch_bounds__(NT) k_tile_lambda(const T* __restrict__ psi, T
   const BlobView bv(blob);
   const int lane = threadIdx.x & 63;
   const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+  uint32_t lbit[kWalkLaneBits];  // all ones where the lane index has bit i
+#pragma unroll
+  for (int i = 0; i < kWalkLaneBits; ++i) lbit[i] = 0u - ((uint32_t(lane) >> i) & 1u);
   const uint32_t nloc = 1u << fr.b;
   const uint32_t n_groups = bv.hdr->n_groups, n_items = bv.hdr->n_fast_items;
   const uint32_t* items = bv.items;
@@ -183,22 +169,40 @@ __global__ void __launch_bounds__(NT) k_tile_lambda(const T* __restrict__ psi, T
         lds_add(&tli[smp], gre * (double)pm.y - gim * (double)pm.x);
       }
     }
-    // one-subgroup groups: work items of 64 free-bit positions of one group,
-    // dealt to the wavefronts in turn; a lane takes one position and every
-    // record's pair there
-    for (uint32_t it = uint32_t(wave); it < n_items; it += NW) {
-      const uint32_t w = items[it];
-      const TFast f = bv.fast[w >> 12];
-      const int nf = int(fr.b) - int(f.n_ins);
-      const uint32_t t = ((w & 0xfffu) << 6) | uint32_t(lane);
-      if (t < (1u << nf)) {
-        const uint32_t ob = insert_zeros_lo(t, f.ins_lo, f.sup_mask);
-        const unsigned so = __popcll(base & f.w_out);
-        switch (f.n_rec) {
-          case 1: fast_pairs<1>(f, ob, so, tp, tlr, tli); break;
-          case 2: fast_pairs<2>(f, ob, so, tp, tlr, tli); break;
-          case 3: fast_pairs<3>(f, ob, so, tp, tlr, tli); break;
-          default: fast_pairs<4>(f, ob, so, tp, tlr, tli); break;
+    // one-subgroup groups: work items of 64 walk positions of one group; a
+    // wavefront takes a contiguous run of items (a group's items are
+    // consecutive), reloads a group's record only when the group changes and
+    // steps the uniform part of the position incrementally; a lane takes one
+    // position and every record's pair there
+    {
+      const uint32_t per = (n_items + NW - 1) / NW;
+      const uint32_t i1 = min(n_items, uint32_t(wave + 1) * per);
+      uint32_t cur = ~0u, ds = 0, rest = 0;
+      unsigned zp = 0, so = 0;
+      bool on = false;
+      TFast f;
+      for (uint32_t it = uint32_t(wave) * per; it < i1; ++it) {
+        const uint32_t w = items[it];
+        if ((w >> 12) != cur) {
+          cur = w >> 12;
+          f = bv.fast[cur];
+          on = f.walk_log >= kWalkLaneBits || uint32_t(lane) < (1u << f.walk_log);
+          ds = 0;
+#pragma unroll
+          for (int i = 0; i < kWalkLaneBits; ++i) ds ^= lbit[i] & f.dep_q[i];
+          zp = __popc(uint32_t(lane) & f.wlane);
+          so = __popcll(base & f.w_out);
+          rest = deposit_bits(w & 0xfffu, f.hi_mask);  // uniform
+        } else {
+          rest = (rest - f.hi_mask) & f.hi_mask;  // the next block of the same group
+        }
+        if (on) {
+          switch (f.n_rec) {
+            case 1: fast_pairs<1>(f, ds, zp, rest, so, tp, tlr, tli); break;
+            case 2: fast_pairs<2>(f, ds, zp, rest, so, tp, tlr, tli); break;
+            case 3: fast_pairs<3>(f, ds, zp, rest, so, tp, tlr, tli); break;
+            default: fast_pairs<4>(f, ds, zp, rest, so, tp, tlr, tli); break;
+          }
         }
       }
     }
@@ -214,37 +218,68 @@ __global__ void __launch_bounds__(NT) k_tile_lambda(const T* __restrict__ psi, T
   }
 }
 
+// ---------------------------------------------------------------------------
+// Expectation over one tile: the sum over the tile's groups of
+// 2 Re(conj(psi[m]) G(m) psi[m']) over their pairs (the diagonal part comes
+// from the resident diagonal).  Tables read in place as in the lambda build;
+// each lane accumulates its own FP64 sum, reduced per block in a fixed order.
+// ---------------------------------------------------------------------------
+template <int NR, typename T>
+__device__ __forceinline__ double fast_expect(const TFast& f, uint32_t ds, unsigned zp, uint32_t rest, unsigned so,
+                                              const T* tp) {
+  const uint32_t sx = lds_swz(f.x_loc);
+  T pm[NR], pp[NR];
+#pragma unroll
+  for (int r = 0; r < NR; ++r) {
+    const uint32_t smp = ds ^ lds_swz(rest | f.bits[r]);
+    pm[r] = tp[smp ^ sx];
+    pp[r] = tp[smp];
+  }
+  double e = 0.0;
+#pragma unroll
+  for (int r = 0; r < NR; ++r) {
+    const unsigned sg = zp + __popc((rest | f.bits[r]) & f.w_loc) + so;
+    const double gre = signed_by(f.coef[2 * r], sg), gim = signed_by(f.coef[2 * r + 1], sg);
+    const double gbr = gre * (double)pp[r].x - gim * (double)pp[r].y;  // G psi[m']
+    const double gbi = gre * (double)pp[r].y + gim * (double)pp[r].x;
+    e += (double)pm[r].x * gbr + (double)pm[r].y * gbi;
+  }
+  return e;
+}
+
 template <typename T, int B, int NT>
-__global__ void __launch_bounds__(NT) k_tile_expect(const T* __restrict__ psi, const FrameDesc* __restrict__ frames,
-                                                    const uint32_t* __restrict__ blob_off,
-                                                    const uint4* __restrict__ blobs, uint32_t bpt, uint64_t n_tb,
+__global__ void __launch_bounds__(NT) k_tile_expect(const T* __restrict__ psi, FrameDesc fr,
+                                                    const uint4* __restrict__ blob, uint64_t n_tb,
                                                     double* __restrict__ partials) {
+  constexpr int NW = NT / 64;
   constexpr int PER = (1 << B) / NT;
   __shared__ T tp[1 << B];
   __shared__ FrameLut lut;
-  __shared__ uint4 blob[kBlobWords];
-  __shared__ double red[NT / 64];
-  const uint32_t tile = blockIdx.x / bpt, bi = blockIdx.x % bpt;
-  const FrameDesc& fr = frames[tile];
-  blob_stage<NT>(blobs + blob_off[tile], blob);
+  __shared__ double red[NW];
   frame_lut_init<NT>(fr, lut);
   __syncthreads();
   const BlobView bv(blob);
+  const int lane = threadIdx.x & 63;
+  const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+  uint32_t lbit[kWalkLaneBits];
+#pragma unroll
+  for (int i = 0; i < kWalkLaneBits; ++i) lbit[i] = 0u - ((uint32_t(lane) >> i) & 1u);
   const uint32_t nloc = 1u << fr.b;
+  const uint32_t n_groups = bv.hdr->n_groups, n_items = bv.hdr->n_fast_items;
   double e = 0.0;
   Stage<T, PER> rp;
-  uint64_t tb = bi;
+  uint64_t tb = blockIdx.x;
   if (tb < n_tb) tile_fetch<T, PER, NT>(psi, lut, frame_base(fr, tb), nloc, rp);
-  for (; tb < n_tb; tb += bpt) {
+  for (; tb < n_tb; tb += gridDim.x) {
     const uint64_t base = frame_base(fr, tb);
     tile_put<T, PER, NT>(tp, nloc, rp);
     __syncthreads();
-    const uint64_t nx = tb + bpt;
+    const uint64_t nx = tb + gridDim.x;
     if (nx < n_tb) tile_fetch<T, PER, NT>(psi, lut, frame_base(fr, nx), nloc, rp);
-    for (uint32_t gi = 0; gi < bv.hdr->n_groups; ++gi) {
+    for (uint32_t gi = 0; gi < n_groups; ++gi) {
       const TGroup g = bv.groups[gi];
       const int ns = int(fr.b) - int(g.n_sins);
-      const uint32_t np = uint32_t(g.n_rec) << ns;
+      const uint32_t np = g.n_rec << ns;
       for (uint32_t idx = threadIdx.x; idx < np; idx += NT) {
         const uint32_t r = idx >> ns, t = idx & ((1u << ns) - 1u);
         const uint32_t l2 = insert_zeros32_p4(t, g.sins_pack, g.n_sins) | bv.recs[g.rec_off + r];  // m'
@@ -259,12 +294,44 @@ __global__ void __launch_bounds__(NT) k_tile_expect(const T* __restrict__ psi, c
         }
         const T a = tp[lds_swz(l)], b = tp[lds_swz(l2)];
         const double gbr = gre * (double)b.x - gim * (double)b.y, gbi = gre * (double)b.y + gim * (double)b.x;
-        e += 2.0 * ((double)a.x * gbr + (double)a.y * gbi);
+        e += (double)a.x * gbr + (double)a.y * gbi;
+      }
+    }
+    {
+      const uint32_t per = (n_items + NW - 1) / NW;
+      const uint32_t i1 = min(n_items, uint32_t(wave + 1) * per);
+      uint32_t cur = ~0u, ds = 0, rest = 0;
+      unsigned zp = 0, so = 0;
+      bool on = false;
+      TFast f;
+      for (uint32_t it = uint32_t(wave) * per; it < i1; ++it) {
+        const uint32_t w = bv.items[it];
+        if ((w >> 12) != cur) {
+          cur = w >> 12;
+          f = bv.fast[cur];
+          on = f.walk_log >= kWalkLaneBits || uint32_t(lane) < (1u << f.walk_log);
+          ds = 0;
+#pragma unroll
+          for (int i = 0; i < kWalkLaneBits; ++i) ds ^= lbit[i] & f.dep_q[i];
+          zp = __popc(uint32_t(lane) & f.wlane);
+          so = __popcll(base & f.w_out);
+          rest = deposit_bits(w & 0xfffu, f.hi_mask);
+        } else {
+          rest = (rest - f.hi_mask) & f.hi_mask;
+        }
+        if (on) {
+          switch (f.n_rec) {
+            case 1: e += fast_expect<1>(f, ds, zp, rest, so, tp); break;
+            case 2: e += fast_expect<2>(f, ds, zp, rest, so, tp); break;
+            case 3: e += fast_expect<3>(f, ds, zp, rest, so, tp); break;
+            default: e += fast_expect<4>(f, ds, zp, rest, so, tp); break;
+          }
+        }
       }
     }
     __syncthreads();
   }
-  const double s = block_sum<NT>(e, red);
+  const double s = block_sum<NT>(2.0 * e, red);
   if (threadIdx.x == 0) partials[blockIdx.x] = s;
 }
 
@@ -357,16 +424,14 @@ hipError_t launch_tile_lambda(int dtype, bool first, const void* psi, void* lam,
   return hipGetLastError();
 }
 
-hipError_t launch_tile_expect(int dtype, const void* psi, const FrameDesc* frames, const uint32_t* blob_off,
-                              const uint4* blobs, int n_tiles, uint32_t bpt, uint64_t n_tb, double* partials,
-                              hipStream_t st) {
-  const dim3 grid(uint32_t(n_tiles) * bpt);
+hipError_t launch_tile_expect(int dtype, const void* psi, const FrameDesc& fr, const uint4* blob, uint64_t n_tb,
+                              int grid, double* partials, hipStream_t st) {
   if (dtype == 0)
-    hipLaunchKernelGGL((k_tile_expect<double2, kTileFwdC128, kTileThreads>), grid, dim3(kTileThreads), 0, st,
-                       static_cast<const double2*>(psi), frames, blob_off, blobs, bpt, n_tb, partials);
+    hipLaunchKernelGGL((k_tile_expect<double2, kTileFwdC128, kExpectThreads>), dim3(grid), dim3(kExpectThreads), 0,
+                       st, static_cast<const double2*>(psi), fr, blob, n_tb, partials);
   else
-    hipLaunchKernelGGL((k_tile_expect<float2, kTileFwdC64, kTileThreads>), grid, dim3(kTileThreads), 0, st,
-                       static_cast<const float2*>(psi), frames, blob_off, blobs, bpt, n_tb, partials);
+    hipLaunchKernelGGL((k_tile_expect<float2, kTileFwdC64, kExpectThreads>), dim3(grid), dim3(kExpectThreads), 0,
+                       st, static_cast<const float2*>(psi), fr, blob, n_tb, partials);
   return hipGetLastError();
 }
 

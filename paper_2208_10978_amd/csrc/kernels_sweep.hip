@@ -412,7 +412,7 @@ __global__ void __launch_bounds__(NT) k_tile_reverse(T* __restrict__ psi, T* __r
             for (int k = 0; k < (GRAD == 2 ? kMaxRunStrings : 1); ++k) {
               if (k >= nk) break;
               const double v = wave_sum(acc[k]);
-              if (lane == 0) gacc.v[run.slot + k][wave] += v;
+              if (lane == 0) lds_add(&gacc.v[run.slot + k][wave], v);  // only this wavefront adds here
             }
           }
         }

@@ -17,7 +17,7 @@ constexpr int kTileLamC128 = 12, kTileLamC64 = 12;   // psi tile + FP64 lambda a
 constexpr int kTileThreads = 512;
 constexpr int kTileRegionBits = 3;                   // 8 wavefronts own 8 regions of a segment
 constexpr int kLambdaThreads = 1024;                 // 16 wavefronts share one tile
-constexpr int kBlobWords = 26 * 1024 / 16;           // group tables staged in LDS (26 KiB)
+constexpr int kExpectThreads = 1024;                 // 16 wavefronts share one tile
 constexpr int kMaxPassSlots = 128;                   // gradient slots per reverse tile pass
 constexpr int kMaxPassRuns = 1 << 16;                // runs per tile pass
 constexpr int kMaxPassRecs = 1 << 20;                // run records per tile pass
@@ -38,9 +38,8 @@ hipError_t launch_tile_reverse(int dtype, int grad, void* psi, void* lam, const 
                                uint64_t n_tb, int grid, hipStream_t st);
 hipError_t launch_tile_lambda(int dtype, bool first, const void* psi, void* lam, const double* diag,
                               const FrameDesc& fr, const uint4* blob, uint64_t n_tb, int grid, hipStream_t st);
-hipError_t launch_tile_expect(int dtype, const void* psi, const FrameDesc* frames, const uint32_t* blob_off,
-                              const uint4* blobs, int n_tiles, uint32_t bpt, uint64_t n_tb, double* partials,
-                              hipStream_t st);
+hipError_t launch_tile_expect(int dtype, const void* psi, const FrameDesc& fr, const uint4* blob, uint64_t n_tb,
+                              int grid, double* partials, hipStream_t st);
 hipError_t launch_diag_build(double* d, uint64_t n_amp, const uint64_t* z, const double* c, int n_terms,
                              hipStream_t st);
 hipError_t launch_group_full(int dtype, int mode, const void* psi, void* lam, const GroupDesc& g,

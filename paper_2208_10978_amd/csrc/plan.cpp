@@ -442,11 +442,7 @@ static size_t group_blob_bytes(const HGroup& g) {
 }
 
 // Pack groups of one tile into a blob (TileHdr, TGroup[], record bits[], TSub[], coef[], TFast[]).
-static bool fast_group(const HGroup& g, uint64_t qmask) {
-  if (g.w.size() != 1 || g.n_rec() > kFastRecs) return false;
-  const uint32_t sm = g.enumerated ? uint32_t(compress(g.x, qmask)) : (1u << local_pos(highest_bit(g.x), qmask));
-  return popc(uint64_t(sm)) <= kFastIns;
-}
+static bool fast_group(const HGroup& g) { return g.w.size() == 1 && g.n_rec() <= kFastRecs; }
 
 static void pack_blob(HTiling& t, const std::vector<HGroup>& gs, const std::vector<int>& members, uint64_t qmask,
                       size_t max_blob, bool use_fast) {
@@ -457,17 +453,23 @@ static void pack_blob(HTiling& t, const std::vector<HGroup>& gs, const std::vect
   std::vector<TFast> tf;
   for (int gi : members) {
     const HGroup& g = gs[gi];
-    if (use_fast && fast_group(g, qmask)) {
+    if (use_fast && fast_group(g)) {
       TFast f{};
       f.x_loc = uint32_t(compress(g.x, qmask));
       f.sup_mask = g.enumerated ? f.x_loc : (1u << local_pos(highest_bit(g.x), qmask));
-      int k = 0;
-      for (uint32_t m = f.sup_mask; m; m &= m - 1) f.ins_lo[k++] = (1u << __builtin_ctz(m)) - 1u;
-      f.n_ins = uint32_t(k);
-      for (int j = k; j < kFastIns; ++j) f.ins_lo[j] = ~0u;  // no-op steps
       f.n_rec = uint32_t(g.n_rec());
       f.w_loc = uint32_t(compress(g.w[0] & qmask, qmask));
       f.w_out = g.w[0] & ~qmask;
+      uint32_t free_bits = ((1u << popc(qmask)) - 1u) & ~f.sup_mask;
+      f.walk_log = uint32_t(popc(uint64_t(free_bits)));
+      for (int i = 0; i < kWalkLaneBits; ++i) {
+        const uint32_t p = free_bits & (~free_bits + 1u);
+        f.dep_p[i] = p;
+        f.dep_q[i] = lds_slot(p);
+        if (f.w_loc & p) f.wlane |= 1u << i;
+        free_bits &= free_bits - 1;
+      }
+      f.hi_mask = free_bits;
       for (int r = 0; r < g.n_rec(); ++r) {
         f.bits[r] = g.enumerated ? uint32_t(compress(g.rec_v[r], qmask)) : f.sup_mask;
         f.coef[2 * r] = g.t_re[r];
@@ -524,8 +526,8 @@ static void pack_blob(HTiling& t, const std::vector<HGroup>& gs, const std::vect
   std::vector<uint32_t> items;
   const int fb = popc(qmask);
   for (size_t i = 0; i < tf.size(); ++i) {
-    const int nf = fb - int(tf[i].n_ins);
-    const uint32_t nblk = nf > 6 ? (1u << (nf - 6)) : 1u;
+    const int nf = int(tf[i].walk_log);
+    const uint32_t nblk = nf > kWalkLaneBits ? (1u << (nf - kWalkLaneBits)) : 1u;
     for (uint32_t c = 0; c < nblk; ++c) items.push_back(uint32_t(i) << 12 | c);
   }
   h.off_items = uint32_t(align16(off));

@@ -158,7 +158,7 @@ struct alignas(16) TileHdr {
   uint32_t bytes;      // blob size in bytes (multiple of 16)
   uint32_t n_fast;     // TFast records (lambda tilings only)
   uint32_t off_fast;   // byte offset of the TFast array
-  uint32_t n_fast_items;  // work items: TFast index << 12 | block of 64 free-bit positions
+  uint32_t n_fast_items;  // work items: TFast index << 12 | block c of 64 walk positions
   uint32_t off_items;  // byte offset of the work items (uint32 each)
   uint32_t pad[2];
 };
@@ -180,18 +180,23 @@ struct alignas(8) TGroup {
 };
 
 // A group with one subgroup and at most four records, in one self-contained
-// record (lambda tilings): G(m) = (-1)^{|m' & w|} T[record].
+// record (lambda tilings): G(m) = (-1)^{|m' & w|} T[record].  Its pairs are
+// walked at positions t = lane + 64 c of the bits outside S': lane bit i
+// lands on frame-local bit dep_p[i] (LDS slot dep_q[i]; 0 past the walk's
+// width), the bits of c on hi_mask; wlane bit i is the w bit at dep_p[i].
 constexpr int kFastRecs = 4;
-constexpr int kFastIns = 8;
 struct alignas(16) TFast {
-  uint32_t ins_lo[kFastIns];  // zero insertions (S', ascending) at p: the masks 2^p - 1
   uint64_t w_out;      // w, global bits outside the frame
   uint32_t x_loc;      // frame-local flip mask
   uint32_t sup_mask;   // frame-local enumerated bits S'
   uint32_t w_loc;      // w, frame-local bits
-  uint32_t n_ins;
   uint32_t n_rec;
+  uint32_t walk_log;   // 2^walk_log positions
+  uint32_t hi_mask;
+  uint32_t wlane;
   uint32_t pad[3];
+  uint32_t dep_p[kWalkLaneBits];
+  uint32_t dep_q[kWalkLaneBits];
   uint32_t bits[kFastRecs];   // m' of each record on S'
   double coef[2 * kFastRecs]; // T[record] (re, im)
 };
