@@ -459,7 +459,10 @@ static int launch_rotations(sv_state* s, sv_state* lam, const RotPlan& pl, bool 
       const int fb = popc(ps.qmask);
       const std::vector<SegDesc> sp = segment_pass(xl, fb, kTileRegionBits);
       for (const SegDesc& sg : sp)
-        for (uint32_t j = sg.first; j < sg.first + sg.count; ++j) set_tile_walk(descs[o.desc0 + j], sg.wb_mask, fb);
+        for (uint32_t j = sg.first; j < sg.first + sg.count; ++j) {
+          set_tile_walk(descs[o.desc0 + j], sg.wb_mask, fb);
+          set_short_form(descs[o.desc0 + j], recs.data() + o.rec0);
+        }
       segs.insert(segs.end(), sp.begin(), sp.end());
       o.nsegs = int(sp.size());
     }

@@ -210,6 +210,57 @@ __device__ __forceinline__ void enum_walk(const RunDesc& run, const RunRec* __re
   }
 }
 
+// Short runs (kRunEnum, at most two records, one position per lane): every
+// uniform quantity comes precomputed with the descriptor, and the slot and
+// sign of a pair follow from the lane part and per-record constants.
+template <typename T, bool REV, int GRAD, unsigned OM>
+__device__ __forceinline__ void short_walk(const RunDesc& run, T* tp, T* tl, uint32_t ds, unsigned sgn0, uint32_t swb,
+                                           bool lane_on, double (&acc)[GRAD == 2 ? kMaxRunStrings : 1]) {
+  using R = typename Real<T>::type;
+  for (uint32_t r = 0; r < run.n_rec; ++r) {
+    const R c = R(run.rec_c[r]), s = REV ? R(-run.rec_s[r]) : R(run.rec_s[r]);
+    double w = 0.0;
+    if (lane_on) {
+      const uint32_t s2 = ds ^ run.rec_sbits[r] ^ swb, s1 = s2 ^ run.sx;  // slots of m' and m
+      const unsigned sg = sgn0 ^ run.rec_pbits[r];
+      T a = tp[s1], b = tp[s2];
+      if (REV) {
+        T la = tl[s1], lb = tl[s2];
+        if (GRAD) w = grad_w_om<OM>(a, b, la, lb, sg);
+        rot_pair_om<OM>(la, lb, c, s, sg);
+        tl[s1] = la;
+        tl[s2] = lb;
+      }
+      rot_pair_om<OM>(a, b, c, s, sg);
+      tp[s1] = a;
+      tp[s2] = b;
+    }
+    if (GRAD == 1) acc[0] += run.rec_a[r] * w;
+    if (GRAD == 2) {
+#pragma unroll
+      for (int k = 0; k < kMaxRunStrings; ++k) acc[k] += ((run.rec_eps[r] >> k) & 1u) ? -w : w;
+    }
+  }
+}
+
+template <typename T, bool REV, int GRAD>
+__device__ __forceinline__ void short_run(const RunDesc& run, T* tp, T* tl, uint64_t base, uint32_t wbits, uint32_t swb,
+                                          uint32_t lane, const LaneBits& lb,
+                                          double (&acc)[GRAD == 2 ? kMaxRunStrings : 1]) {
+  uint32_t ds = 0;
+#pragma unroll
+  for (int i = 0; i < kWalkLaneBits; ++i) ds ^= lb.m[i] & run.dep_q[i];
+  const unsigned sgn0 = (parity64(base & run.z0_out) ^ parity32(wbits & uint32_t(run.z0_loc))) ^
+                        parity32(lane & run.zlane);
+  const bool lane_on = lane < (1u << run.walk_log);
+  switch (run.omega0 & 3u) {
+    case 0: short_walk<T, REV, GRAD, 0>(run, tp, tl, ds, sgn0, swb, lane_on, acc); break;
+    case 1: short_walk<T, REV, GRAD, 1>(run, tp, tl, ds, sgn0, swb, lane_on, acc); break;
+    case 2: short_walk<T, REV, GRAD, 2>(run, tp, tl, ds, sgn0, swb, lane_on, acc); break;
+    default: short_walk<T, REV, GRAD, 3>(run, tp, tl, ds, sgn0, swb, lane_on, acc); break;
+  }
+}
+
 template <typename T, bool REV, int GRAD>
 __device__ __forceinline__ void tile_run(const RunDesc& run, const RunRec* __restrict__ recs, T* tp, T* tl,
                                          uint64_t base, uint32_t wbits, uint32_t lane, const LaneBits& lbits,
@@ -336,9 +387,13 @@ __global__ void __launch_bounds__(NT) k_tile_forward(T* __restrict__ psi, FrameD
     for (int si = 0; si < n_segs; ++si) {
       const SegDesc sg = segs[si];
       if (wave < (1u << __popc(sg.wb_mask))) {
-        const uint32_t wbits = region_bits_of(sg.wb_mask, wave);
-        for (uint32_t ri = sg.first; ri < sg.first + sg.count; ++ri)
-          tile_run<T, false, 0>(runs[ri], recs, tile, nullptr, base, wbits, lane, lbits, dummy);
+        const uint32_t wbits = region_bits_of(sg.wb_mask, wave), swb = lds_swz(wbits);
+        for (uint32_t ri = sg.first; ri < sg.first + sg.count; ++ri) {
+          if (runs[ri].short_form)
+            short_run<T, false, 0>(runs[ri], tile, nullptr, base, wbits, swb, lane, lbits, dummy);
+          else
+            tile_run<T, false, 0>(runs[ri], recs, tile, nullptr, base, wbits, lane, lbits, dummy);
+        }
       }
       __syncthreads();
     }
@@ -400,13 +455,14 @@ __global__ void __launch_bounds__(NT) k_tile_reverse(T* __restrict__ psi, T* __r
     for (int si = 0; si < n_segs; ++si) {
       const SegDesc sg = segs[si];
       if (wave < (1u << __popc(sg.wb_mask))) {
-        const uint32_t wbits = region_bits_of(sg.wb_mask, wave);
+        const uint32_t wbits = region_bits_of(sg.wb_mask, wave), swb = lds_swz(wbits);
         for (uint32_t ri = sg.first; ri < sg.first + sg.count; ++ri) {
-          const RunDesc run = runs[ri];
+          const RunDesc& run = runs[ri];
           double acc[GRAD == 2 ? kMaxRunStrings : 1];
 #pragma unroll
           for (int k = 0; k < (GRAD == 2 ? kMaxRunStrings : 1); ++k) acc[k] = 0.0;
-          tile_run<T, true, GRAD>(run, recs, tp, tl, base, wbits, lane, lbits, acc);
+          if (run.short_form) short_run<T, true, GRAD>(run, tp, tl, base, wbits, swb, lane, lbits, acc);
+          else tile_run<T, true, GRAD>(run, recs, tp, tl, base, wbits, lane, lbits, acc);
           if (GRAD) {
             const int nk = GRAD == 2 ? int(run.n_str) : 1;
             for (int k = 0; k < (GRAD == 2 ? kMaxRunStrings : 1); ++k) {

@@ -194,6 +194,22 @@ void set_tile_walk(RunDesc& rd, uint32_t wb_mask, int b) {
   rd.hi_mask = free_bits;
 }
 
+void set_short_form(RunDesc& rd, const RunRec* recs) {
+  rd.sx = lds_slot(uint32_t(rd.x_loc));
+  rd.short_form = rd.mode == kRunEnum && rd.n_rec <= uint32_t(kShortRecs) && rd.walk_log <= uint32_t(kWalkLaneBits);
+  if (!rd.short_form) return;
+  for (uint32_t r = 0; r < rd.n_rec; ++r) {
+    const RunRec& e = recs[rd.rec_off + r];
+    const uint32_t bits = uint32_t(e.bits);
+    rd.rec_sbits[r] = lds_slot(bits);
+    rd.rec_pbits[r] = uint32_t(popc(uint64_t(bits & uint32_t(rd.z0_loc))) & 1);
+    rd.rec_eps[r] = e.eps_neg;
+    rd.rec_c[r] = e.c;
+    rd.rec_s[r] = e.s;
+    rd.rec_a[r] = e.a;
+  }
+}
+
 std::vector<SegDesc> segment_pass(const std::vector<uint32_t>& x_loc, int b, int region_bits) {
   std::vector<SegDesc> out;
   const uint32_t all = b >= 32 ? ~0u : ((1u << b) - 1u);

@@ -71,6 +71,10 @@ FrameDesc make_frame(uint64_t qmask, int n, int c);
 // frame of b bits.
 void set_tile_walk(RunDesc& rd, uint32_t wb_mask, int b);
 
+// After set_tile_walk: inline the records of a short run (recs indexed by the
+// descriptor's rec_off).
+void set_short_form(RunDesc& rd, const RunRec* recs);
+
 // Split a tile pass (its runs' frame-local x masks, in application order)
 // into segments that leave region_bits frame bits untouched; region bits are
 // chosen per segment.  A run whose x leaves fewer free bits forms a segment

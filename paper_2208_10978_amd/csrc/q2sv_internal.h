@@ -79,7 +79,17 @@ struct alignas(16) RunDesc {
   uint32_t dep_q[kWalkLaneBits];
   uint32_t hi_mask;
   uint32_t zlane;
+  // Short form (kRunEnum, at most kShortRecs records, walk_log <= 6: one
+  // position per lane): the records inline, with the LDS slot and the z0
+  // parity of their bits on S', so a tile walk needs no further loads.
+  uint32_t short_form;
+  uint32_t sx;                     // LDS slot of x_loc
+  uint32_t rec_sbits[2];           // slot(bits)
+  uint32_t rec_pbits[2];           // parity(bits & z0_loc)
+  uint32_t rec_eps[2];             // eps_neg
+  double rec_c[2], rec_s[2], rec_a[2];
 };
+constexpr int kShortRecs = 2;
 
 // A segment of a tile pass: consecutive runs none of whose x masks touches
 // the frame-local bits wb_mask.  Wavefront w owns the amplitudes whose
