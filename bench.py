@@ -136,6 +136,47 @@ def bench_c4(n_rot: int, n_terms: int):
     return res
 
 
+def bench_serve(n_req: int, rho: float, seed: int):
+    """Served stream (continuous batching) against the one-request-at-a-time
+    path on the same Poisson trace: energy + gradient requests with qubit
+    counts uniform in {12, 16, 20, 24, 26}, electrons = qubits / 2, seeded
+    synthetic H and UCCSD amplitudes per request, complex64 amplitudes with FP64
+    reductions.  The offered rate is rho times the measured one-at-a-time
+    throughput."""
+    from paper_2208_10978_amd.serve import Request, Server, latency_stats
+    from workloads import poisson_requests
+
+    base = poisson_requests(n_req, 1.0, seed)
+
+    def trace(rate):
+        return [Request(rid=d["id"], n_qubits=d["n_qubits"], n_electrons=d["n_electrons"], h_seed=d["h_seed"],
+                        theta_seed=d["theta_seed"], t_arrival=d["t_arrival"] / rate, theta_amplitude=0.05,
+                        dtype="c64") for d in base]
+
+    Server(fifo=True).run(trace(1e9)[:2], realtime=False)  # code load, allocator warm-up
+    t0 = time.perf_counter()
+    alone = Server(fifo=True).run(trace(1e9), realtime=False)
+    span = time.perf_counter() - t0
+    if any(r.error for r in alone):
+        raise RuntimeError(f"serving: {[r.error for r in alone if r.error][:3]}")
+    fifo_rate = n_req / span
+    rate = rho * fifo_rate
+    log(f"serving: one-at-a-time {fifo_rate:.2f} evals/s; offering {rate:.2f} requests/s")
+    srv = Server(max_slots=8)
+    mixed = srv.run(trace(rate), realtime=True)
+    fifo = Server(fifo=True).run(trace(rate), realtime=True)
+    return {
+        "workload": f"{n_req} Poisson energy+gradient requests, qubits uniform in {{12,16,20,24,26}}, complex64, "
+                    f"offered at {rho:g} x the one-at-a-time throughput (seed {seed})",
+        "one_at_a_time_evals_per_s": fifo_rate,
+        "offered_requests_per_s": rate,
+        "continuous_batching": latency_stats(mixed),
+        "fifo_same_trace": latency_stats(fifo),
+        "peak_slots": srv.peak_slots,
+        "peak_hbm_bytes": srv.peak_bytes,
+    }
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -146,6 +187,8 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-c4", action="store_true", help="skip the 32-qubit complex64 raw-sweep figures")
     ap.add_argument("--c4-rotations", type=int, default=1000)
+    ap.add_argument("--no-serve", action="store_true", help="skip the served-stream figures")
+    ap.add_argument("--serve-requests", type=int, default=40)
     args = ap.parse_args()
     if args.gpus != 1:
         print(json.dumps({"error": "this build runs on one GPU only; --gpus must be 1"}))
@@ -247,6 +290,8 @@ def main():
     torch.cuda.empty_cache()
     if not args.no_c4:
         result["c4"] = bench_c4(args.c4_rotations, 10_000)
+    if not args.no_serve:
+        result["serving"] = bench_serve(args.serve_requests, 0.8, 5151)
     if not args.no_cpu_baseline:
         log("timing the oracle sample on the host")
         result["cpu_baseline"] = cpu_baseline(n, ham, rot, theta)

@@ -54,22 +54,21 @@ __device__ __forceinline__ double signed_by(double x, unsigned s) {
 // and slot of a record's m' are dl | rest | bits and ds ^ slot(rest | bits)
 // (the LDS slot map is linear).
 template <int NR, typename T>
-__device__ __forceinline__ void fast_pairs(const TFast& f, uint32_t ds, unsigned zp, uint32_t rest, unsigned so,
+__device__ __forceinline__ void fast_pairs(const TFast& f, uint32_t ds, unsigned zp, uint32_t srest, unsigned so,
                                            const T* tp, double* tlr, double* tli) {
-  const uint32_t sx = lds_swz(f.x_loc);
   uint32_t smp[NR];
   T pm[NR], pp[NR];
 #pragma unroll
   for (int r = 0; r < NR; ++r) {
-    smp[r] = ds ^ lds_swz(rest | f.bits[r]);
-    pm[r] = tp[smp[r] ^ sx];
+    smp[r] = ds ^ srest ^ f.sbits[r];
+    pm[r] = tp[smp[r] ^ f.sx];
     pp[r] = tp[smp[r]];
   }
 #pragma unroll
   for (int r = 0; r < NR; ++r) {
-    const unsigned sg = zp + __popc((rest | f.bits[r]) & f.w_loc) + so;
+    const unsigned sg = zp + f.pbits[r] + so;
     const double gre = signed_by(f.coef[2 * r], sg), gim = signed_by(f.coef[2 * r + 1], sg);
-    const uint32_t sm = smp[r] ^ sx;
+    const uint32_t sm = smp[r] ^ f.sx;
     lds_add(&tlr[sm], gre * (double)pp[r].x - gim * (double)pp[r].y);  // lam[m] += G psi[m']
     lds_add(&tli[sm], gre * (double)pp[r].y + gim * (double)pp[r].x);
     lds_add(&tlr[smp[r]], gre * (double)pm[r].x + gim * (double)pm[r].y);  // lam[m'] += conj(G) psi[m]
@@ -149,11 +148,11 @@ __global__ void __launch_bounds__(NT) k_tile_lambda(const T* __restrict__ psi, T
       const TGroup g = bv.groups[gi];
       const int nf = int(fr.b) - int(g.n_sins);
       const uint32_t n_it = g.n_rec << nf;
-      for (uint32_t idx = threadIdx.x; idx < n_it; idx += NT) {
-        const uint32_t r = idx >> nf, t = idx & ((1u << nf) - 1u);
+      auto pair = [&](uint32_t r, uint32_t t) {
         const uint32_t lmp = insert_zeros32_p4(t, g.sins_pack, g.n_sins) | bv.recs[g.rec_off + r];
         const uint32_t lm = lmp ^ g.x_loc;
         double gre = 0.0, gim = 0.0;  // G(m)
+#pragma unroll 4
         for (uint32_t k = 0; k < g.n_sub; ++k) {
           const TSub sd = bv.subs[g.sub_off + k];
           const double2 cv = bv.coef[g.coef_off + k * g.n_rec + r];
@@ -167,6 +166,15 @@ __global__ void __launch_bounds__(NT) k_tile_lambda(const T* __restrict__ psi, T
         lds_add(&tli[sm], gre * (double)pp.y + gim * (double)pp.x);
         lds_add(&tlr[smp], gre * (double)pm.x + gim * (double)pm.y);  // lam[m'] += conj(G) psi[m]
         lds_add(&tli[smp], gre * (double)pm.y - gim * (double)pm.x);
+      };
+      if (nf >= 6) {
+        // 2^nf >= 64: a wavefront's positions share one record, so its index
+        // is uniform and the tables arrive by scalar loads (a vector load here
+        // would also wait for the tile loads in flight)
+        for (uint32_t idx = threadIdx.x; idx < n_it; idx += NT)
+          pair(__builtin_amdgcn_readfirstlane(idx >> nf), idx & ((1u << nf) - 1u));
+      } else {
+        for (uint32_t idx = threadIdx.x; idx < n_it; idx += NT) pair(idx >> nf, idx & ((1u << nf) - 1u));
       }
     }
     // one-subgroup groups: work items of 64 walk positions of one group; a
@@ -196,12 +204,14 @@ __global__ void __launch_bounds__(NT) k_tile_lambda(const T* __restrict__ psi, T
         } else {
           rest = (rest - f.hi_mask) & f.hi_mask;  // the next block of the same group
         }
+        const uint32_t srest = lds_swz(rest);  // uniform: slot and w parity of the block's high bits
+        const unsigned prest = __popc(rest & f.w_loc) & 1u;
         if (on) {
           switch (f.n_rec) {
-            case 1: fast_pairs<1>(f, ds, zp, rest, so, tp, tlr, tli); break;
-            case 2: fast_pairs<2>(f, ds, zp, rest, so, tp, tlr, tli); break;
-            case 3: fast_pairs<3>(f, ds, zp, rest, so, tp, tlr, tli); break;
-            default: fast_pairs<4>(f, ds, zp, rest, so, tp, tlr, tli); break;
+            case 1: fast_pairs<1>(f, ds, zp, srest, so ^ prest, tp, tlr, tli); break;
+            case 2: fast_pairs<2>(f, ds, zp, srest, so ^ prest, tp, tlr, tli); break;
+            case 3: fast_pairs<3>(f, ds, zp, srest, so ^ prest, tp, tlr, tli); break;
+            default: fast_pairs<4>(f, ds, zp, srest, so ^ prest, tp, tlr, tli); break;
           }
         }
       }
@@ -225,20 +235,19 @@ __global__ void __launch_bounds__(NT) k_tile_lambda(const T* __restrict__ psi, T
 // each lane accumulates its own FP64 sum, reduced per block in a fixed order.
 // ---------------------------------------------------------------------------
 template <int NR, typename T>
-__device__ __forceinline__ double fast_expect(const TFast& f, uint32_t ds, unsigned zp, uint32_t rest, unsigned so,
+__device__ __forceinline__ double fast_expect(const TFast& f, uint32_t ds, unsigned zp, uint32_t srest, unsigned so,
                                               const T* tp) {
-  const uint32_t sx = lds_swz(f.x_loc);
   T pm[NR], pp[NR];
 #pragma unroll
   for (int r = 0; r < NR; ++r) {
-    const uint32_t smp = ds ^ lds_swz(rest | f.bits[r]);
-    pm[r] = tp[smp ^ sx];
+    const uint32_t smp = ds ^ srest ^ f.sbits[r];
+    pm[r] = tp[smp ^ f.sx];
     pp[r] = tp[smp];
   }
   double e = 0.0;
 #pragma unroll
   for (int r = 0; r < NR; ++r) {
-    const unsigned sg = zp + __popc((rest | f.bits[r]) & f.w_loc) + so;
+    const unsigned sg = zp + f.pbits[r] + so;
     const double gre = signed_by(f.coef[2 * r], sg), gim = signed_by(f.coef[2 * r + 1], sg);
     const double gbr = gre * (double)pp[r].x - gim * (double)pp[r].y;  // G psi[m']
     const double gbi = gre * (double)pp[r].y + gim * (double)pp[r].x;
@@ -280,11 +289,11 @@ __global__ void __launch_bounds__(NT) k_tile_expect(const T* __restrict__ psi, F
       const TGroup g = bv.groups[gi];
       const int ns = int(fr.b) - int(g.n_sins);
       const uint32_t np = g.n_rec << ns;
-      for (uint32_t idx = threadIdx.x; idx < np; idx += NT) {
-        const uint32_t r = idx >> ns, t = idx & ((1u << ns) - 1u);
+      auto pair = [&](uint32_t r, uint32_t t) {
         const uint32_t l2 = insert_zeros32_p4(t, g.sins_pack, g.n_sins) | bv.recs[g.rec_off + r];  // m'
         const uint32_t l = l2 ^ g.x_loc;
         double gre = 0.0, gim = 0.0;  // G(m)
+#pragma unroll 4
         for (uint32_t k = 0; k < g.n_sub; ++k) {
           const TSub sd = bv.subs[g.sub_off + k];
           const double2 cv = bv.coef[g.coef_off + k * g.n_rec + r];
@@ -295,6 +304,12 @@ __global__ void __launch_bounds__(NT) k_tile_expect(const T* __restrict__ psi, F
         const T a = tp[lds_swz(l)], b = tp[lds_swz(l2)];
         const double gbr = gre * (double)b.x - gim * (double)b.y, gbi = gre * (double)b.y + gim * (double)b.x;
         e += (double)a.x * gbr + (double)a.y * gbi;
+      };
+      if (ns >= 6) {
+        for (uint32_t idx = threadIdx.x; idx < np; idx += NT)
+          pair(__builtin_amdgcn_readfirstlane(idx >> ns), idx & ((1u << ns) - 1u));
+      } else {
+        for (uint32_t idx = threadIdx.x; idx < np; idx += NT) pair(idx >> ns, idx & ((1u << ns) - 1u));
       }
     }
     {
@@ -319,12 +334,14 @@ __global__ void __launch_bounds__(NT) k_tile_expect(const T* __restrict__ psi, F
         } else {
           rest = (rest - f.hi_mask) & f.hi_mask;
         }
+        const uint32_t srest = lds_swz(rest);
+        const unsigned prest = __popc(rest & f.w_loc) & 1u;
         if (on) {
           switch (f.n_rec) {
-            case 1: e += fast_expect<1>(f, ds, zp, rest, so, tp); break;
-            case 2: e += fast_expect<2>(f, ds, zp, rest, so, tp); break;
-            case 3: e += fast_expect<3>(f, ds, zp, rest, so, tp); break;
-            default: e += fast_expect<4>(f, ds, zp, rest, so, tp); break;
+            case 1: e += fast_expect<1>(f, ds, zp, srest, so ^ prest, tp); break;
+            case 2: e += fast_expect<2>(f, ds, zp, srest, so ^ prest, tp); break;
+            case 3: e += fast_expect<3>(f, ds, zp, srest, so ^ prest, tp); break;
+            default: e += fast_expect<4>(f, ds, zp, srest, so ^ prest, tp); break;
           }
         }
       }

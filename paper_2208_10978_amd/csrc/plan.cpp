@@ -486,8 +486,11 @@ static void pack_blob(HTiling& t, const std::vector<HGroup>& gs, const std::vect
         free_bits &= free_bits - 1;
       }
       f.hi_mask = free_bits;
+      f.sx = lds_slot(f.x_loc);
       for (int r = 0; r < g.n_rec(); ++r) {
         f.bits[r] = g.enumerated ? uint32_t(compress(g.rec_v[r], qmask)) : f.sup_mask;
+        f.sbits[r] = lds_slot(f.bits[r]);
+        f.pbits[r] = uint32_t(popc(uint64_t(f.bits[r] & f.w_loc)) & 1);
         f.coef[2 * r] = g.t_re[r];
         f.coef[2 * r + 1] = g.t_im[r];
       }

@@ -204,10 +204,14 @@ struct alignas(16) TFast {
   uint32_t walk_log;   // 2^walk_log positions
   uint32_t hi_mask;
   uint32_t wlane;
-  uint32_t pad[3];
+  uint32_t sx;         // LDS slot of x_loc
+  uint32_t pad[2];
   uint32_t dep_p[kWalkLaneBits];
   uint32_t dep_q[kWalkLaneBits];
   uint32_t bits[kFastRecs];   // m' of each record on S'
+  uint32_t sbits[kFastRecs];  // LDS slot of bits
+  uint32_t pbits[kFastRecs];  // parity(bits & w_loc)
+  uint32_t pad2[kFastRecs];
   double coef[2 * kFastRecs]; // T[record] (re, im)
 };
 

@@ -73,7 +73,12 @@ def prepare(req: Request) -> Request:
 
 
 class GpuExecutor:
-    """Launches a request on its own HIP stream; completion via a HIP event."""
+    """Launches a request on its own HIP stream; completion via a HIP event.
+
+    A launch (the Hamiltonian's grouping and tiling, the rotation plans, the
+    uploads and the kernel enqueues) runs on a small thread pool: the library
+    releases the GIL, so host planning of one request overlaps the serving
+    loop and the device work of the others."""
 
     class Job:
         def __init__(self, req):
@@ -98,13 +103,26 @@ class GpuExecutor:
             self.ev.free()
             return out
 
+    class Pending:
+        def __init__(self, fut):
+            self.fut = fut
+
+        def ready(self) -> bool:
+            return self.fut.done() and self.fut.result().ready()
+
+        def result(self):
+            return self.fut.result().result()
+
+    def __init__(self, launch_workers: int = 4):
+        self.pool = cf.ThreadPoolExecutor(max_workers=launch_workers)
+
     def budget(self) -> int:
         import torch
         free, _ = torch.cuda.mem_get_info()
         return int(free * 0.8)
 
     def launch(self, req):
-        return GpuExecutor.Job(req)
+        return GpuExecutor.Pending(self.pool.submit(GpuExecutor.Job, req))
 
 
 class Server:
@@ -139,15 +157,19 @@ class Server:
                 if reqs[nxt].error is None:
                     waiting.append(reqs[nxt])
                 nxt += 1
-            for job, r in list(active):  # completions
-                if job.ready():
+            for job, r in list(active):  # completions (a launch that failed fails its request alone)
+                try:
+                    if not job.ready():
+                        continue
                     r.energy, r.norm, r.grad = job.result()
-                    r.t_done = time.perf_counter() - t0
-                    used -= r.device_bytes()
-                    active.remove((job, r))
-                    n_done += 1
-                    if on_done:
-                        on_done(r)
+                except Exception as exc:
+                    r.error = f"{type(exc).__name__}: {exc}"
+                r.t_done = time.perf_counter() - t0
+                used -= r.device_bytes()
+                active.remove((job, r))
+                n_done += 1
+                if on_done:
+                    on_done(r)
             i = 0  # admissions
             while i < len(waiting) and len(active) < self.max_slots:
                 r = waiting[i]

@@ -99,3 +99,27 @@ def test_continuous_batching_admits_while_others_run():
     assert ex.max_live >= 2
     stats = latency_stats(out)
     assert stats["requests"] == 4 and stats["p99_s"] >= stats["p50_s"] > 0
+
+
+def test_a_device_failure_after_launch_fails_its_request_alone():
+    class FailingExecutor(FakeExecutor):
+        class Bad:
+            def __init__(self, ex):
+                self.ex = ex
+
+            def ready(self):
+                self.ex.live -= 1
+                raise RuntimeError("device error")
+
+        def launch(self, req):
+            if req.rid == 2:
+                self.live += 1
+                return FailingExecutor.Bad(self)
+            return super().launch(req)
+
+    ex = FailingExecutor()
+    out = Server(ex, max_slots=3).run(trace(5), realtime=True)
+    by = {r.rid: r for r in out}
+    assert "device error" in by[2].error and by[2].t_done is not None
+    assert all(by[r].error is None and by[r].energy is not None for r in (0, 1, 3, 4))
+    assert ex.live == 0
