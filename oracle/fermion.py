@@ -61,6 +61,26 @@ def uccsd_excitations(n_qubits: int, n_electrons: int):
     return singles, doubles
 
 
+def uccgsd_excitations(n_qubits: int):
+    """Generalized singles and doubles (Table 1's UCCGSD: excitation
+    operators that do not tell occupied from virtual orbitals): singles
+    ``a+_q a_p`` for p < q of one spin, doubles ``a+_r a+_s a_q a_p`` for
+    p < q, r < s, {p, q} and {r, s} disjoint, (p, q) < (r, s), spin
+    projection conserved.  Each unordered pair of index pairs appears once
+    (the generator of (r, s) -> (p, q) is minus that of (p, q) -> (r, s))."""
+    singles = [(p, q) for p, q in itertools.combinations(range(n_qubits), 2) if spin_of(p) == spin_of(q)]
+    pairs = list(itertools.combinations(range(n_qubits), 2))
+    doubles = []
+    for a in range(len(pairs)):
+        for b in range(a + 1, len(pairs)):
+            (p, q), (r, s) = pairs[a], pairs[b]
+            if {p, q} & {r, s}:
+                continue
+            if sorted((spin_of(p), spin_of(q))) == sorted((spin_of(r), spin_of(s))):
+                doubles.append((p, q, r, s))
+    return singles, doubles
+
+
 def excitation_ops(exc):
     """Ladder-operator word of tau, rightmost applied first: list of
     ``(qubit, is_creation)`` in left-to-right order."""
@@ -165,15 +185,18 @@ def checked_order(n_qubits: int, n_electrons: int, order=None):
     return order
 
 
-def ucc_state_fermionic(n_qubits: int, n_electrons: int, theta, basis=None, order=None):
+def ucc_state_fermionic(n_qubits: int, n_electrons: int, theta, basis=None, order=None, excitations=None):
     """``prod_i exp(theta_i (tau_i - tau_i^dag)) |HF>`` in excitation order,
-    each factor a sparse matrix exponential.  Returns (basis, coefficients)."""
+    each factor a sparse matrix exponential.  ``excitations`` (any sequence of
+    singles (i, a) and doubles (i, j, a, b)) replaces the UCCSD sequence.
+    Returns (basis, coefficients)."""
     if basis is None:
         basis = sector_basis(n_qubits, *electron_counts(n_electrons))
     basis = np.asarray(basis, dtype=np.int64)
     psi = np.zeros(len(basis), dtype=np.complex128)
     psi[int(np.nonzero(basis == hf_index(n_electrons))[0][0])] = 1.0
-    for exc, th in zip(checked_order(n_qubits, n_electrons, order), theta):
+    seq = checked_order(n_qubits, n_electrons, order) if excitations is None else [tuple(e) for e in excitations]
+    for exc, th in zip(seq, theta):
         g = generator_matrix(exc, basis)
         psi = scipy.sparse.linalg.expm_multiply(float(th) * g, psi)
     return basis, psi
@@ -244,14 +267,22 @@ def truncate(terms: dict, threshold: float) -> dict:
 def uccsd_rotations(n_qubits: int, n_electrons: int, order=None):
     """Rotation list of the Trotterised UCCSD circuit (Eq. 11), excitations in
     the given sequence (lexicographic by default); parameter i is the i-th
-    excitation of the sequence.
+    excitation of the sequence.  See ``excitation_rotations``."""
+    return excitation_rotations(checked_order(n_qubits, n_electrons, order))
+
+
+def excitation_rotations(excitations, first_param: int = 0):
+    """Rotation list of ``prod_i exp(theta_i (tau_i - tau_i^dag))`` (Eq. 11)
+    for any sequence of excitations; parameter ``first_param + i`` is the
+    i-th excitation.
 
     ``tau - tau^dag = i sum_j c_j P_j`` with real c_j, so
     ``exp(theta (tau - tau^dag)) = prod_j R(P_j, -2 c_j theta)``; the strings
     of one excitation commute and are listed by increasing z mask.
     Returns a list of ``(x, z, param_index, dphi_dtheta)``."""
     out = []
-    for idx, exc in enumerate(checked_order(n_qubits, n_electrons, order)):
+    for pos, exc in enumerate(excitations):
+        idx = first_param + pos
         word = excitation_ops(exc)
         dag = [(q, not c) for q, c in reversed(word)]
         poly = word_pauli(word)
@@ -267,6 +298,17 @@ def uccsd_rotations(n_qubits: int, n_electrons: int, order=None):
         for x, z, c in sorted(strings, key=lambda t: t[1]):
             out.append((x, z, idx, -2.0 * c))
     return out
+
+
+def pool_gradients(h, eri, n_qubits: int, n_electrons: int, theta, pool, excitations=None):
+    """ADAPT operator-pool screening (Section 5.1): for each pool
+    operator A = tau - tau^dag appended after the circuit with amplitude 0,
+    dE/dtheta_A = <psi|[H, A]|psi> = 2 Re <psi|H A|psi>, from the
+    determinant-space H and A (bitstring action, no Pauli algebra)."""
+    basis = sector_basis(n_qubits, *electron_counts(n_electrons))
+    _, psi = ucc_state_fermionic(n_qubits, n_electrons, theta, basis=basis, excitations=excitations)
+    hpsi = determinant_hamiltonian(h, eri, basis) @ psi
+    return np.array([2.0 * np.real(np.vdot(hpsi, generator_matrix(exc, basis) @ psi)) for exc in pool])
 
 
 def hamiltonian_on_basis_state(h, eri, k: int) -> dict:

@@ -124,6 +124,20 @@ class UCCSDEvaluator:
                                    self.grad_buf)
         return self.energy_buf, self.grad_buf
 
+    def pool_gradients(self, theta, pool: RotationList) -> torch.Tensor:
+        """ADAPT operator-pool screening (Section 5.1): dE/dtheta_A at
+        theta_A = 0 for every pool operator A appended after the circuit.
+        The pool's rotations are the identity there, so one reverse sweep over
+        the pool alone (Algorithm 1 with lambda = H psi) gives every
+        Im <lambda|P|psi> of its strings.  Returns a device float64 tensor of
+        pool.n_params entries; psi is left at U(theta)|HF>."""
+        self.forward_state(theta)
+        out = torch.empty(pool.n_params, dtype=torch.float64, device=self.psi.amps.device)
+        B.sv_adjoint_grad_params_h(self.psi.handle, self.lam.handle, self.h.handle, pool.x, pool.z,
+                                   np.zeros(len(pool)), pool.param, pool.dphi_dtheta, pool.n_params,
+                                   self.energy_buf, out)
+        return out
+
     def free(self):
         for o in (self.psi, self.lam, self.h):
             o.free()

@@ -174,6 +174,36 @@ def uccsd_rotations(n_qubits: int, n_electrons: int, order="tile") -> RotationLi
     singles, doubles = uccsd_excitations(n_qubits, n_electrons)
     if len(seq) != len(singles) + len(doubles) or set(seq) != set(singles + doubles):
         raise ValueError("the excitation sequence is not a permutation of the UCCSD excitations")
+    return excitation_rotations(n_qubits, seq)
+
+
+def uccgsd_excitations(n_qubits: int):
+    """Generalized singles (p -> q, p < q, one spin) and doubles
+    ((p, q) -> (r, s), p < q, r < s, disjoint pairs, (p, q) < (r, s), spin
+    projection conserved): the UCCGSD operators of Table 1, which do not tell
+    occupied from virtual orbitals."""
+    singles = [(p, q) for p, q in itertools.combinations(range(n_qubits), 2) if p % 2 == q % 2]
+    pairs = list(itertools.combinations(range(n_qubits), 2))
+    doubles = [(p, q, r, s)
+               for k, (p, q) in enumerate(pairs) for (r, s) in pairs[k + 1:]
+               if not ({p, q} & {r, s}) and sorted((p % 2, q % 2)) == sorted((r % 2, s % 2))]
+    return singles, doubles
+
+
+def uccgsd_rotations(n_qubits: int) -> RotationList:
+    """Trotterised UCCGSD: generalized singles, then doubles."""
+    singles, doubles = uccgsd_excitations(n_qubits)
+    return excitation_rotations(n_qubits, singles + doubles)
+
+
+def excitation_rotations(n_qubits: int, seq) -> RotationList:
+    """Rotation list of ``prod_i exp(theta_i (tau_i - tau_i^dag))`` (Eq. 11) for
+    a sequence of excitations: singles (i, a) with ``tau = a+_a a_i`` and
+    doubles (i, j, a, b) with ``tau = a+_a a+_b a_j a_i``; parameter i is the
+    i-th excitation.  ``tau - tau^dag = i sum_j c_j P_j``, so the factor is
+    ``prod_j R(P_j, -2 c_j theta)``; the strings of one excitation commute and
+    are listed by increasing z."""
+    seq = [tuple(int(v) for v in e) for e in seq]
     xs, zs, ps, ds = [], [], [], []
     for idx, exc in enumerate(seq):
         if len(exc) == 2:
@@ -195,5 +225,8 @@ def uccsd_rotations(n_qubits: int, n_electrons: int, order="tile") -> RotationLi
         xs.append(x[order]); zs.append(z[order])
         ps.append(np.full(len(order), idx, dtype=np.int32))
         ds.append(-2.0 * c.imag[order])
+    if not seq:
+        return RotationList(n_qubits, np.zeros(0, np.uint64), np.zeros(0, np.uint64), np.zeros(0, np.int32),
+                            np.zeros(0, np.float64), 0)
     return RotationList(n_qubits, np.concatenate(xs), np.concatenate(zs), np.concatenate(ps),
                         np.concatenate(ds), len(seq))

@@ -41,3 +41,17 @@ def test_uccsd_rotations_match_oracle(n, ne, order):
 def test_28_qubit_counts():
     rot = uccsd_rotations(28, 14)
     assert len(rot) == 26460 and rot.n_params == 3381
+
+
+@pytest.mark.parametrize("n", [4, 6, 8])
+def test_uccgsd_rotations_match_oracle(n):
+    from paper_2208_10978_amd.problem import uccgsd_excitations, uccgsd_rotations
+    singles, doubles = uccgsd_excitations(n)
+    osingles, odoubles = fermion.uccgsd_excitations(n)
+    assert singles == osingles and doubles == odoubles
+    rot = uccgsd_rotations(n)
+    ref = fermion.excitation_rotations(osingles + odoubles)
+    assert len(rot) == len(ref) and rot.n_params == len(osingles) + len(odoubles)
+    for k, (x, z, p, d) in enumerate(ref):
+        assert (int(rot.x[k]), int(rot.z[k]), int(rot.param[k])) == (x, z, p)
+        assert abs(rot.dphi_dtheta[k] - d) < 1e-15
