@@ -227,6 +227,75 @@ __device__ __forceinline__ void tile_store(T* __restrict__ dst, const FrameLut& 
 }
 
 // ---------------------------------------------------------------------------
+// Full tiles (a frame of exactly B bits).  The frame-local index
+// l = threadIdx.x + i NT has the thread's bits and the element's bits apart,
+// and the frame map is a bit deposit, so l's global offset is thr | el(i):
+// a per-thread part computed once and a part shared by the block.  No lookup
+// table and no per-element guard: the loads of one tile leave back to back,
+// and the compiler can count them instead of waiting for all memory traffic
+// before each one.
+// ---------------------------------------------------------------------------
+constexpr int ilog2c(unsigned v) { return v <= 1u ? 0 : 1 + ilog2c(v >> 1); }
+
+template <int NT, int PER>
+struct TileAddr {
+  static constexpr int kT = ilog2c(NT), kE = ilog2c(PER);
+  uint64_t thr;
+  uint64_t eb[kE > 0 ? kE : 1];
+  __device__ __forceinline__ explicit TileAddr(const FrameDesc& fr) {
+    thr = 0;
+#pragma unroll
+    for (int j = 0; j < kT; ++j) thr |= uint64_t((threadIdx.x >> j) & 1u) << fr.q[j];
+#pragma unroll
+    for (int k = 0; k < kE; ++k) eb[k] = uint64_t(1) << fr.q[kT + k];
+  }
+  __device__ __forceinline__ uint64_t el(int i) const {
+    uint64_t g = 0;
+#pragma unroll
+    for (int k = 0; k < kE; ++k)
+      if ((i >> k) & 1) g |= eb[k];
+    return g;
+  }
+};
+
+template <typename T, int PER, int NT>
+__device__ __forceinline__ void tile_fetch_full(const T* __restrict__ src, const TileAddr<NT, PER>& a, uint64_t base,
+                                                Stage<T, PER>& reg) {
+  const T* p = src + (base | a.thr);
+#pragma unroll
+  for (int i = 0; i < PER; ++i) {
+    const T v = p[a.el(i)];
+    reg.re[i] = v.x;
+    reg.im[i] = v.y;
+  }
+}
+
+template <typename T, int PER, int NT>
+__device__ __forceinline__ void tile_put_full(T* tile, const Stage<T, PER>& reg) {
+#pragma unroll
+  for (int i = 0; i < PER; ++i) tile[lds_swz(threadIdx.x + uint32_t(i) * NT)] = cmake<T>(reg.re[i], reg.im[i]);
+}
+
+// The thread's own slots (the ones tile_put_full writes) into registers.
+template <typename T, int PER, int NT>
+__device__ __forceinline__ void tile_take(const T* tile, Stage<T, PER>& reg) {
+#pragma unroll
+  for (int i = 0; i < PER; ++i) {
+    const T v = tile[lds_swz(threadIdx.x + uint32_t(i) * NT)];
+    reg.re[i] = v.x;
+    reg.im[i] = v.y;
+  }
+}
+
+template <typename T, int PER, int NT>
+__device__ __forceinline__ void tile_send(T* __restrict__ dst, const TileAddr<NT, PER>& a, uint64_t base,
+                                          const Stage<T, PER>& reg) {
+  T* p = dst + (base | a.thr);
+#pragma unroll
+  for (int i = 0; i < PER; ++i) p[a.el(i)] = cmake<T>(reg.re[i], reg.im[i]);
+}
+
+// ---------------------------------------------------------------------------
 // fused-run pair arithmetic (Section 5.1, Eq. 11)
 //
 // For the pair (m, m' = m ^ x) with the pivot bit of m clear, the reference

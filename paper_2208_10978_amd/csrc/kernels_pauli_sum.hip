@@ -76,7 +76,7 @@ __device__ __forceinline__ void fast_pairs(const TFast& f, uint32_t ds, unsigned
   }
 }
 
-template <typename T, int B, int NT, int MODE>
+template <typename T, int B, int NT, int MODE, bool FULL>
 __global__ void __launch_bounds__(NT) k_tile_lambda(const T* __restrict__ psi, T* __restrict__ lam,
                                                     const double* __restrict__ diag, FrameDesc fr,
                                                     const uint4* __restrict__ blob, uint64_t n_tb) {
@@ -85,63 +85,16 @@ __global__ void __launch_bounds__(NT) k_tile_lambda(const T* __restrict__ psi, T
   constexpr int PER = (1 << B) / NT;
   __shared__ T tp[1 << B];
   __shared__ double tlr[1 << B], tli[1 << B];
-  __shared__ FrameLut lut;
-  frame_lut_init<NT>(fr, lut);
-  __syncthreads();
   const BlobView bv(blob);
   const int lane = threadIdx.x & 63;
   const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
   uint32_t lbit[kWalkLaneBits];  // all ones where the lane index has bit i
 #pragma unroll
   for (int i = 0; i < kWalkLaneBits; ++i) lbit[i] = 0u - ((uint32_t(lane) >> i) & 1u);
-  const uint32_t nloc = 1u << fr.b;
   const uint32_t n_groups = bv.hdr->n_groups, n_items = bv.hdr->n_fast_items;
   const uint32_t* items = bv.items;
 
-  Stage<T, PER> rp;
-  Stage<T, PER> rl;
-  double rd[PER];
-  auto fetch = [&](uint64_t tbx) {
-    const uint64_t bx = frame_base(fr, tbx);
-    tile_fetch<T, PER, NT>(psi, lut, bx, nloc, rp);
-#pragma unroll
-    for (int i = 0; i < PER; ++i) {
-      const uint32_t l = threadIdx.x + uint32_t(i) * NT;
-      if (l < nloc) {
-        const uint64_t gi = bx | frame_deposit(lut, l);
-        if (MODE == 1) {
-          rd[i] = diag ? diag[gi] : 0.0;
-        } else {
-          const T v = lam[gi];
-          rl.re[i] = v.x;
-          rl.im[i] = v.y;
-        }
-      }
-    }
-  };
-
-  uint64_t tb = blockIdx.x;
-  if (tb < n_tb) fetch(tb);
-  for (; tb < n_tb; tb += gridDim.x) {
-    const uint64_t base = frame_base(fr, tb);
-    tile_put<T, PER, NT>(tp, nloc, rp);
-#pragma unroll
-    for (int i = 0; i < PER; ++i) {
-      const uint32_t l = threadIdx.x + uint32_t(i) * NT;
-      if (l < nloc) {
-        const uint32_t sl = lds_swz(l);
-        if (MODE == 1) {
-          tlr[sl] = rd[i] * (double)rp.re[i];
-          tli[sl] = rd[i] * (double)rp.im[i];
-        } else {
-          tlr[sl] = (double)rl.re[i];
-          tli[sl] = (double)rl.im[i];
-        }
-      }
-    }
-    __syncthreads();
-    const uint64_t nx = tb + gridDim.x;
-    if (nx < n_tb) fetch(nx);
+  auto apply_groups = [&](uint64_t base) {
     // groups with several subgroups: every thread of the block takes pairs
     // (record, position of the free bits), G(m) summed over the subgroups
     for (uint32_t gi = 0; gi < n_groups; ++gi) {
@@ -217,12 +170,108 @@ __global__ void __launch_bounds__(NT) k_tile_lambda(const T* __restrict__ psi, T
       }
     }
     __syncthreads();
+  };
+
+  Stage<T, PER> rp;
+  Stage<T, PER> rl;
+  double rd[PER];
+  uint64_t tb = blockIdx.x;
+  if constexpr (FULL) {
+    // next loads before the groups; this tile's lambda leaves only after the
+    // next tile is in place, so its stores overlap the next tile's groups
+    const TileAddr<NT, PER> ta(fr);
+    auto fetch = [&](uint64_t bx) {
+      tile_fetch_full<T, PER, NT>(psi, ta, bx, rp);
+      if (MODE == 1) {
+        if (diag) {
+          const double* d = diag + (bx | ta.thr);
 #pragma unroll
-    for (int i = 0; i < PER; ++i) {
-      const uint32_t l = threadIdx.x + uint32_t(i) * NT;
-      if (l < nloc) {
-        const uint32_t sl = lds_swz(l);
-        lam[base | frame_deposit(lut, l)] = cmake<T>(R(tlr[sl]), R(tli[sl]));
+          for (int i = 0; i < PER; ++i) rd[i] = d[ta.el(i)];
+        } else {
+#pragma unroll
+          for (int i = 0; i < PER; ++i) rd[i] = 0.0;
+        }
+      } else {
+        tile_fetch_full<T, PER, NT>(lam, ta, bx, rl);
+      }
+    };
+    auto put = [&]() {
+      tile_put_full<T, PER, NT>(tp, rp);
+#pragma unroll
+      for (int i = 0; i < PER; ++i) {
+        const uint32_t sl = lds_swz(threadIdx.x + uint32_t(i) * NT);
+        tlr[sl] = MODE == 1 ? rd[i] * (double)rp.re[i] : (double)rl.re[i];
+        tli[sl] = MODE == 1 ? rd[i] * (double)rp.im[i] : (double)rl.im[i];
+      }
+    };
+    if (tb < n_tb) {
+      fetch(frame_base(fr, tb));
+      put();
+    }
+    __syncthreads();
+    for (; tb < n_tb; tb += gridDim.x) {
+      const uint64_t base = frame_base(fr, tb);
+      const uint64_t nx = tb + gridDim.x;
+      if (nx < n_tb) fetch(frame_base(fr, nx));
+      apply_groups(base);
+      Stage<T, PER> out;
+#pragma unroll
+      for (int i = 0; i < PER; ++i) {
+        const uint32_t sl = lds_swz(threadIdx.x + uint32_t(i) * NT);
+        out.re[i] = R(tlr[sl]);
+        out.im[i] = R(tli[sl]);
+      }
+      if (nx < n_tb) put();
+      tile_send<T, PER, NT>(lam, ta, base, out);
+      __syncthreads();
+    }
+  } else {
+    __shared__ FrameLut lut;
+    frame_lut_init<NT>(fr, lut);
+    __syncthreads();
+    const uint32_t nloc = 1u << fr.b;
+    auto fetch = [&](uint64_t tbx) {
+      const uint64_t bx = frame_base(fr, tbx);
+      tile_fetch<T, PER, NT>(psi, lut, bx, nloc, rp);
+#pragma unroll
+      for (int i = 0; i < PER; ++i) {
+        const uint32_t l = threadIdx.x + uint32_t(i) * NT;
+        if (l < nloc) {
+          const uint64_t gi = bx | frame_deposit(lut, l);
+          if (MODE == 1) {
+            rd[i] = diag ? diag[gi] : 0.0;
+          } else {
+            const T v = lam[gi];
+            rl.re[i] = v.x;
+            rl.im[i] = v.y;
+          }
+        }
+      }
+    };
+    if (tb < n_tb) fetch(tb);
+    for (; tb < n_tb; tb += gridDim.x) {
+      const uint64_t base = frame_base(fr, tb);
+      tile_put<T, PER, NT>(tp, nloc, rp);
+#pragma unroll
+      for (int i = 0; i < PER; ++i) {
+        const uint32_t l = threadIdx.x + uint32_t(i) * NT;
+        if (l < nloc) {
+          const uint32_t sl = lds_swz(l);
+          tlr[sl] = MODE == 1 ? rd[i] * (double)rp.re[i] : (double)rl.re[i];
+          tli[sl] = MODE == 1 ? rd[i] * (double)rp.im[i] : (double)rl.im[i];
+        }
+      }
+      __syncthreads();
+      const uint64_t nx = tb + gridDim.x;
+      if (nx < n_tb) fetch(nx);
+      apply_groups(base);
+#pragma unroll
+      for (int i = 0; i < PER; ++i) {
+        const uint32_t l = threadIdx.x + uint32_t(i) * NT;
+        if (l < nloc) {
+          const uint32_t sl = lds_swz(l);
+          lam[base | frame_deposit(lut, l)] = cmake<T>(R(tlr[sl]), R(tli[sl]));
+        }
       }
     }
   }
@@ -256,35 +305,23 @@ __device__ __forceinline__ double fast_expect(const TFast& f, uint32_t ds, unsig
   return e;
 }
 
-template <typename T, int B, int NT>
+template <typename T, int B, int NT, bool FULL>
 __global__ void __launch_bounds__(NT) k_tile_expect(const T* __restrict__ psi, FrameDesc fr,
                                                     const uint4* __restrict__ blob, uint64_t n_tb,
                                                     double* __restrict__ partials) {
   constexpr int NW = NT / 64;
   constexpr int PER = (1 << B) / NT;
   __shared__ T tp[1 << B];
-  __shared__ FrameLut lut;
   __shared__ double red[NW];
-  frame_lut_init<NT>(fr, lut);
-  __syncthreads();
   const BlobView bv(blob);
   const int lane = threadIdx.x & 63;
   const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
   uint32_t lbit[kWalkLaneBits];
 #pragma unroll
   for (int i = 0; i < kWalkLaneBits; ++i) lbit[i] = 0u - ((uint32_t(lane) >> i) & 1u);
-  const uint32_t nloc = 1u << fr.b;
   const uint32_t n_groups = bv.hdr->n_groups, n_items = bv.hdr->n_fast_items;
   double e = 0.0;
-  Stage<T, PER> rp;
-  uint64_t tb = blockIdx.x;
-  if (tb < n_tb) tile_fetch<T, PER, NT>(psi, lut, frame_base(fr, tb), nloc, rp);
-  for (; tb < n_tb; tb += gridDim.x) {
-    const uint64_t base = frame_base(fr, tb);
-    tile_put<T, PER, NT>(tp, nloc, rp);
-    __syncthreads();
-    const uint64_t nx = tb + gridDim.x;
-    if (nx < n_tb) tile_fetch<T, PER, NT>(psi, lut, frame_base(fr, nx), nloc, rp);
+  auto apply_groups = [&](uint64_t base) {
     for (uint32_t gi = 0; gi < n_groups; ++gi) {
       const TGroup g = bv.groups[gi];
       const int ns = int(fr.b) - int(g.n_sins);
@@ -347,6 +384,34 @@ __global__ void __launch_bounds__(NT) k_tile_expect(const T* __restrict__ psi, F
       }
     }
     __syncthreads();
+  };
+  Stage<T, PER> rp;
+  uint64_t tb = blockIdx.x;
+  if constexpr (FULL) {
+    const TileAddr<NT, PER> ta(fr);
+    if (tb < n_tb) tile_fetch_full<T, PER, NT>(psi, ta, frame_base(fr, tb), rp);
+    for (; tb < n_tb; tb += gridDim.x) {
+      const uint64_t base = frame_base(fr, tb);
+      tile_put_full<T, PER, NT>(tp, rp);
+      __syncthreads();
+      const uint64_t nx = tb + gridDim.x;
+      if (nx < n_tb) tile_fetch_full<T, PER, NT>(psi, ta, frame_base(fr, nx), rp);
+      apply_groups(base);
+    }
+  } else {
+    __shared__ FrameLut lut;
+    frame_lut_init<NT>(fr, lut);
+    __syncthreads();
+    const uint32_t nloc = 1u << fr.b;
+    if (tb < n_tb) tile_fetch<T, PER, NT>(psi, lut, frame_base(fr, tb), nloc, rp);
+    for (; tb < n_tb; tb += gridDim.x) {
+      const uint64_t base = frame_base(fr, tb);
+      tile_put<T, PER, NT>(tp, nloc, rp);
+      __syncthreads();
+      const uint64_t nx = tb + gridDim.x;
+      if (nx < n_tb) tile_fetch<T, PER, NT>(psi, lut, frame_base(fr, nx), nloc, rp);
+      apply_groups(base);
+    }
   }
   const double s = block_sum<NT>(2.0 * e, red);
   if (threadIdx.x == 0) partials[blockIdx.x] = s;
@@ -425,30 +490,47 @@ __global__ void __launch_bounds__(256) k_group_full(const T* __restrict__ psi, T
 // ---------------------------------------------------------------------------
 // launchers
 // ---------------------------------------------------------------------------
+template <typename T, int B, int M>
+static void tile_lambda_t(const void* psi, void* lam, const double* diag, const FrameDesc& fr, const uint4* blob,
+                          uint64_t n_tb, int grid, hipStream_t st) {
+  const T* p = static_cast<const T*>(psi);
+  T* l = static_cast<T*>(lam);
+  if (fr.b == B)
+    hipLaunchKernelGGL((k_tile_lambda<T, B, kLambdaThreads, M, true>), dim3(grid), dim3(kLambdaThreads), 0, st, p,
+                       l, diag, fr, blob, n_tb);
+  else
+    hipLaunchKernelGGL((k_tile_lambda<T, B, kLambdaThreads, M, false>), dim3(grid), dim3(kLambdaThreads), 0, st, p,
+                       l, diag, fr, blob, n_tb);
+}
+
 hipError_t launch_tile_lambda(int dtype, bool first, const void* psi, void* lam, const double* diag,
                               const FrameDesc& fr, const uint4* blob, uint64_t n_tb, int grid, hipStream_t st) {
-#define Q2SV_TL(T, B, M)                                                                                   \
-  hipLaunchKernelGGL((k_tile_lambda<T, B, kLambdaThreads, M>), dim3(grid), dim3(kLambdaThreads), 0, st, \
-                     static_cast<const T*>(psi), static_cast<T*>(lam), diag, fr, blob, n_tb)
   if (dtype == 0) {
-    if (first) Q2SV_TL(double2, kTileLamC128, 1);
-    else Q2SV_TL(double2, kTileLamC128, 2);
+    if (first) tile_lambda_t<double2, kTileLamC128, 1>(psi, lam, diag, fr, blob, n_tb, grid, st);
+    else tile_lambda_t<double2, kTileLamC128, 2>(psi, lam, diag, fr, blob, n_tb, grid, st);
   } else {
-    if (first) Q2SV_TL(float2, kTileLamC64, 1);
-    else Q2SV_TL(float2, kTileLamC64, 2);
+    if (first) tile_lambda_t<float2, kTileLamC64, 1>(psi, lam, diag, fr, blob, n_tb, grid, st);
+    else tile_lambda_t<float2, kTileLamC64, 2>(psi, lam, diag, fr, blob, n_tb, grid, st);
   }
-#undef Q2SV_TL
   return hipGetLastError();
+}
+
+template <typename T, int B>
+static void tile_expect_t(const void* psi, const FrameDesc& fr, const uint4* blob, uint64_t n_tb, int grid,
+                          double* partials, hipStream_t st) {
+  const T* p = static_cast<const T*>(psi);
+  if (fr.b == B)
+    hipLaunchKernelGGL((k_tile_expect<T, B, kExpectThreads, true>), dim3(grid), dim3(kExpectThreads), 0, st, p, fr,
+                       blob, n_tb, partials);
+  else
+    hipLaunchKernelGGL((k_tile_expect<T, B, kExpectThreads, false>), dim3(grid), dim3(kExpectThreads), 0, st, p, fr,
+                       blob, n_tb, partials);
 }
 
 hipError_t launch_tile_expect(int dtype, const void* psi, const FrameDesc& fr, const uint4* blob, uint64_t n_tb,
                               int grid, double* partials, hipStream_t st) {
-  if (dtype == 0)
-    hipLaunchKernelGGL((k_tile_expect<double2, kTileFwdC128, kExpectThreads>), dim3(grid), dim3(kExpectThreads), 0,
-                       st, static_cast<const double2*>(psi), fr, blob, n_tb, partials);
-  else
-    hipLaunchKernelGGL((k_tile_expect<float2, kTileFwdC64, kExpectThreads>), dim3(grid), dim3(kExpectThreads), 0,
-                       st, static_cast<const float2*>(psi), fr, blob, n_tb, partials);
+  if (dtype == 0) tile_expect_t<double2, kTileFwdC128>(psi, fr, blob, n_tb, grid, partials, st);
+  else tile_expect_t<float2, kTileFwdC64>(psi, fr, blob, n_tb, grid, partials, st);
   return hipGetLastError();
 }
 

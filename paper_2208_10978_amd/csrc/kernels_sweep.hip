@@ -359,31 +359,26 @@ __device__ __forceinline__ uint32_t region_bits_of(uint32_t wb_mask, uint32_t wa
 // segment each wavefront runs through the segment's runs on its own region;
 // a block barrier separates segments.  Descriptors are read in place through
 // scalar loads.
+//
+// Full tiles (FULL): the next tile's loads leave before the runs of this one;
+// after the runs each thread takes its own slots into registers, puts the
+// next tile's amplitudes in their place and only then sends this tile's
+// stores, so stores stay in flight over the next tile's runs and nothing
+// waits for them.  Frames narrower than B (states of fewer than B qubits)
+// take the guarded loop.
 // ---------------------------------------------------------------------------
-template <typename T, int B, int NT>
+template <typename T, int B, int NT, bool FULL>
 __global__ void __launch_bounds__(NT) k_tile_forward(T* __restrict__ psi, FrameDesc fr,
                                                      const RunDesc* __restrict__ runs,
                                                      const RunRec* __restrict__ recs,
                                                      const SegDesc* __restrict__ segs, int n_segs, uint64_t n_tb) {
   constexpr int PER = (1 << B) / NT;
   __shared__ T tile[1 << B];
-  __shared__ FrameLut lut;
-  frame_lut_init<NT>(fr, lut);
-  __syncthreads();
   const uint32_t lane = threadIdx.x & 63u;
   const uint32_t wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
   const LaneBits lbits(lane);
-  const uint32_t nloc = 1u << fr.b;
   double dummy[1];
-  Stage<T, PER> reg;
-  uint64_t tb = blockIdx.x;
-  if (tb < n_tb) tile_fetch<T, PER, NT>(psi, lut, frame_base(fr, tb), nloc, reg);
-  for (; tb < n_tb; tb += gridDim.x) {
-    const uint64_t base = frame_base(fr, tb);
-    tile_put<T, PER, NT>(tile, nloc, reg);
-    __syncthreads();
-    const uint64_t nx = tb + gridDim.x;
-    if (nx < n_tb) tile_fetch<T, PER, NT>(psi, lut, frame_base(fr, nx), nloc, reg);
+  auto apply_runs = [&](uint64_t base) {
     for (int si = 0; si < n_segs; ++si) {
       const SegDesc sg = segs[si];
       if (wave < (1u << __popc(sg.wb_mask))) {
@@ -397,8 +392,43 @@ __global__ void __launch_bounds__(NT) k_tile_forward(T* __restrict__ psi, FrameD
       }
       __syncthreads();
     }
-    tile_store<T, PER, NT>(psi, lut, base, nloc, tile);
+  };
+  Stage<T, PER> reg;
+  uint64_t tb = blockIdx.x;
+  if constexpr (FULL) {
+    const TileAddr<NT, PER> ta(fr);
+    Stage<T, PER> out;
+    if (tb < n_tb) {
+      tile_fetch_full<T, PER, NT>(psi, ta, frame_base(fr, tb), reg);
+      tile_put_full<T, PER, NT>(tile, reg);
+    }
     __syncthreads();
+    for (; tb < n_tb; tb += gridDim.x) {
+      const uint64_t base = frame_base(fr, tb);
+      const uint64_t nx = tb + gridDim.x;
+      if (nx < n_tb) tile_fetch_full<T, PER, NT>(psi, ta, frame_base(fr, nx), reg);
+      apply_runs(base);
+      tile_take<T, PER, NT>(tile, out);
+      if (nx < n_tb) tile_put_full<T, PER, NT>(tile, reg);
+      tile_send<T, PER, NT>(psi, ta, base, out);
+      __syncthreads();
+    }
+  } else {
+    __shared__ FrameLut lut;
+    frame_lut_init<NT>(fr, lut);
+    __syncthreads();
+    const uint32_t nloc = 1u << fr.b;
+    if (tb < n_tb) tile_fetch<T, PER, NT>(psi, lut, frame_base(fr, tb), nloc, reg);
+    for (; tb < n_tb; tb += gridDim.x) {
+      const uint64_t base = frame_base(fr, tb);
+      tile_put<T, PER, NT>(tile, nloc, reg);
+      __syncthreads();
+      const uint64_t nx = tb + gridDim.x;
+      if (nx < n_tb) tile_fetch<T, PER, NT>(psi, lut, frame_base(fr, nx), nloc, reg);
+      apply_runs(base);
+      tile_store<T, PER, NT>(psi, lut, base, nloc, tile);
+      __syncthreads();
+    }
   }
 }
 
@@ -413,7 +443,7 @@ struct GradAcc {
   double v[MAXS][NW];
 };
 
-template <typename T, int B, int NT, int GRAD, int MAXS>
+template <typename T, int B, int NT, int GRAD, int MAXS, bool FULL>
 __global__ void __launch_bounds__(NT) k_tile_reverse(T* __restrict__ psi, T* __restrict__ lam, FrameDesc fr,
                                                      const RunDesc* __restrict__ runs,
                                                      const RunRec* __restrict__ recs,
@@ -425,33 +455,12 @@ __global__ void __launch_bounds__(NT) k_tile_reverse(T* __restrict__ psi, T* __r
   constexpr int PER = (1 << B) / NT;
   __shared__ T tp[1 << B];
   __shared__ T tl[1 << B];
-  __shared__ FrameLut lut;
   __shared__ GradAcc<NW, MAXS> gacc;
   const uint32_t lane = threadIdx.x & 63u;
   const uint32_t wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
   const LaneBits lbits(lane);
-  frame_lut_init<NT>(fr, lut);
   for (int i = threadIdx.x; i < MAXS * NW; i += NT) (&gacc.v[0][0])[i] = 0.0;
-  __syncthreads();
-  const uint32_t nloc = 1u << fr.b;
-  Stage<T, PER> rp, rl;
-  uint64_t tb = blockIdx.x;
-  if (tb < n_tb) {
-    const uint64_t b0 = frame_base(fr, tb);
-    tile_fetch<T, PER, NT>(psi, lut, b0, nloc, rp);
-    tile_fetch<T, PER, NT>(lam, lut, b0, nloc, rl);
-  }
-  for (; tb < n_tb; tb += gridDim.x) {
-    const uint64_t base = frame_base(fr, tb);
-    tile_put<T, PER, NT>(tp, nloc, rp);
-    tile_put<T, PER, NT>(tl, nloc, rl);
-    __syncthreads();
-    const uint64_t nx = tb + gridDim.x;
-    if (nx < n_tb) {
-      const uint64_t b1 = frame_base(fr, nx);
-      tile_fetch<T, PER, NT>(psi, lut, b1, nloc, rp);
-      tile_fetch<T, PER, NT>(lam, lut, b1, nloc, rl);
-    }
+  auto apply_runs = [&](uint64_t base) {
     for (int si = 0; si < n_segs; ++si) {
       const SegDesc sg = segs[si];
       if (wave < (1u << __popc(sg.wb_mask))) {
@@ -475,11 +484,70 @@ __global__ void __launch_bounds__(NT) k_tile_reverse(T* __restrict__ psi, T* __r
       }
       __syncthreads();
     }
-    tile_store<T, PER, NT>(psi, lut, base, nloc, tp);
-    tile_store<T, PER, NT>(lam, lut, base, nloc, tl);
+  };
+  Stage<T, PER> rp, rl;
+  uint64_t tb = blockIdx.x;
+  if constexpr (FULL) {
+    // as in the forward pass: next loads before the runs, stores after the
+    // next tile is in place
+    const TileAddr<NT, PER> ta(fr);
+    Stage<T, PER> op, ol;
+    if (tb < n_tb) {
+      const uint64_t b0 = frame_base(fr, tb);
+      tile_fetch_full<T, PER, NT>(psi, ta, b0, rp);
+      tile_fetch_full<T, PER, NT>(lam, ta, b0, rl);
+      tile_put_full<T, PER, NT>(tp, rp);
+      tile_put_full<T, PER, NT>(tl, rl);
+    }
     __syncthreads();
+    for (; tb < n_tb; tb += gridDim.x) {
+      const uint64_t base = frame_base(fr, tb);
+      const uint64_t nx = tb + gridDim.x;
+      if (nx < n_tb) {
+        const uint64_t b1 = frame_base(fr, nx);
+        tile_fetch_full<T, PER, NT>(psi, ta, b1, rp);
+        tile_fetch_full<T, PER, NT>(lam, ta, b1, rl);
+      }
+      apply_runs(base);
+      tile_take<T, PER, NT>(tp, op);
+      tile_take<T, PER, NT>(tl, ol);
+      if (nx < n_tb) {
+        tile_put_full<T, PER, NT>(tp, rp);
+        tile_put_full<T, PER, NT>(tl, rl);
+      }
+      tile_send<T, PER, NT>(psi, ta, base, op);
+      tile_send<T, PER, NT>(lam, ta, base, ol);
+      __syncthreads();
+    }
+  } else {
+    __shared__ FrameLut lut;
+    frame_lut_init<NT>(fr, lut);
+    __syncthreads();
+    const uint32_t nloc = 1u << fr.b;
+    if (tb < n_tb) {
+      const uint64_t b0 = frame_base(fr, tb);
+      tile_fetch<T, PER, NT>(psi, lut, b0, nloc, rp);
+      tile_fetch<T, PER, NT>(lam, lut, b0, nloc, rl);
+    }
+    for (; tb < n_tb; tb += gridDim.x) {
+      const uint64_t base = frame_base(fr, tb);
+      tile_put<T, PER, NT>(tp, nloc, rp);
+      tile_put<T, PER, NT>(tl, nloc, rl);
+      __syncthreads();
+      const uint64_t nx = tb + gridDim.x;
+      if (nx < n_tb) {
+        const uint64_t b1 = frame_base(fr, nx);
+        tile_fetch<T, PER, NT>(psi, lut, b1, nloc, rp);
+        tile_fetch<T, PER, NT>(lam, lut, b1, nloc, rl);
+      }
+      apply_runs(base);
+      tile_store<T, PER, NT>(psi, lut, base, nloc, tp);
+      tile_store<T, PER, NT>(lam, lut, base, nloc, tl);
+      __syncthreads();
+    }
   }
   if (GRAD) {
+    __syncthreads();
     for (int i = threadIdx.x; i < n_slots; i += NT) {
       double s = 0.0;
       for (int w = 0; w < NW; ++w) s += gacc.v[i][w];
@@ -524,14 +592,37 @@ hipError_t launch_run_full(int dtype, bool rev, int grad, void* psi, void* lam, 
   return run_full_t<float2>(rev, grad, psi, lam, run, recs, partials, n, nb_stride, grid, st);
 }
 
+template <typename T, int B>
+static hipError_t tile_forward_t(void* psi, const FrameDesc& fr, const RunDesc* runs, const RunRec* recs,
+                                 const SegDesc* segs, int n_segs, uint64_t n_tb, int grid, hipStream_t st) {
+  T* p = static_cast<T*>(psi);
+  if (fr.b == B)
+    hipLaunchKernelGGL((k_tile_forward<T, B, kTileThreads, true>), dim3(grid), dim3(kTileThreads), 0, st, p, fr,
+                       runs, recs, segs, n_segs, n_tb);
+  else
+    hipLaunchKernelGGL((k_tile_forward<T, B, kTileThreads, false>), dim3(grid), dim3(kTileThreads), 0, st, p, fr,
+                       runs, recs, segs, n_segs, n_tb);
+  return hipGetLastError();
+}
+
 hipError_t launch_tile_forward(int dtype, void* psi, const FrameDesc& fr, const RunDesc* runs, const RunRec* recs,
                                const SegDesc* segs, int n_segs, uint64_t n_tb, int grid, hipStream_t st) {
-  if (dtype == 0)
-    hipLaunchKernelGGL((k_tile_forward<double2, kTileFwdC128, kTileThreads>), dim3(grid), dim3(kTileThreads), 0,
-                       st, static_cast<double2*>(psi), fr, runs, recs, segs, n_segs, n_tb);
+  if (dtype == 0) return tile_forward_t<double2, kTileFwdC128>(psi, fr, runs, recs, segs, n_segs, n_tb, grid, st);
+  return tile_forward_t<float2, kTileFwdC64>(psi, fr, runs, recs, segs, n_segs, n_tb, grid, st);
+}
+
+template <typename T, int B, int GRAD, int MAXS>
+static hipError_t tile_reverse_g(void* psi, void* lam, const FrameDesc& fr, const RunDesc* runs, const RunRec* recs,
+                                 const SegDesc* segs, int n_segs, const uint32_t* slot_map, int n_slots,
+                                 double* partials, uint32_t nb, uint64_t n_tb, int grid, hipStream_t st) {
+  T* p = static_cast<T*>(psi);
+  T* l = static_cast<T*>(lam);
+  if (fr.b == B)
+    hipLaunchKernelGGL((k_tile_reverse<T, B, kTileThreads, GRAD, MAXS, true>), dim3(grid), dim3(kTileThreads), 0,
+                       st, p, l, fr, runs, recs, segs, n_segs, slot_map, n_slots, partials, nb, n_tb);
   else
-    hipLaunchKernelGGL((k_tile_forward<float2, kTileFwdC64, kTileThreads>), dim3(grid), dim3(kTileThreads), 0,
-                       st, static_cast<float2*>(psi), fr, runs, recs, segs, n_segs, n_tb);
+    hipLaunchKernelGGL((k_tile_reverse<T, B, kTileThreads, GRAD, MAXS, false>), dim3(grid), dim3(kTileThreads), 0,
+                       st, p, l, fr, runs, recs, segs, n_segs, slot_map, n_slots, partials, nb, n_tb);
   return hipGetLastError();
 }
 
@@ -539,18 +630,14 @@ template <typename T, int B>
 static hipError_t tile_reverse_t(int grad, void* psi, void* lam, const FrameDesc& fr, const RunDesc* runs,
                                  const RunRec* recs, const SegDesc* segs, int n_segs, const uint32_t* slot_map,
                                  int n_slots, double* partials, uint32_t nb, uint64_t n_tb, int grid, hipStream_t st) {
-  T* p = static_cast<T*>(psi);
-  T* l = static_cast<T*>(lam);
   if (grad == 0)
-    hipLaunchKernelGGL((k_tile_reverse<T, B, kTileThreads, 0, 1>), dim3(grid), dim3(kTileThreads), 0, st, p, l,
-                       fr, runs, recs, segs, n_segs, slot_map, n_slots, partials, nb, n_tb);
-  else if (grad == 1)
-    hipLaunchKernelGGL((k_tile_reverse<T, B, kTileThreads, 1, kMaxPassSlots>), dim3(grid), dim3(kTileThreads), 0,
-                       st, p, l, fr, runs, recs, segs, n_segs, slot_map, n_slots, partials, nb, n_tb);
-  else
-    hipLaunchKernelGGL((k_tile_reverse<T, B, kTileThreads, 2, kMaxPassSlots>), dim3(grid), dim3(kTileThreads), 0,
-                       st, p, l, fr, runs, recs, segs, n_segs, slot_map, n_slots, partials, nb, n_tb);
-  return hipGetLastError();
+    return tile_reverse_g<T, B, 0, 1>(psi, lam, fr, runs, recs, segs, n_segs, slot_map, n_slots, partials, nb, n_tb,
+                                      grid, st);
+  if (grad == 1)
+    return tile_reverse_g<T, B, 1, kMaxPassSlots>(psi, lam, fr, runs, recs, segs, n_segs, slot_map, n_slots,
+                                                  partials, nb, n_tb, grid, st);
+  return tile_reverse_g<T, B, 2, kMaxPassSlots>(psi, lam, fr, runs, recs, segs, n_segs, slot_map, n_slots, partials,
+                                                nb, n_tb, grid, st);
 }
 
 hipError_t launch_tile_reverse(int dtype, int grad, void* psi, void* lam, const FrameDesc& fr,
