@@ -4,8 +4,11 @@
 // complex64).  Sweeps compute in the amplitude precision; every reduction
 // (energy, norm, gradient) promotes products to FP64 and sums them in a fixed
 // order: per lane, then across the 64 lanes of a wavefront, then across the
-// wavefronts of a block in index order, then across blocks in index order.
-// No floating-point atomics are used, so results are bitwise reproducible.
+// wavefronts of a block in index order, then across blocks in index order,
+// so these sums are bitwise reproducible for given inputs.  The exception is
+// the lambda = H psi build, whose FP64 accumulator tile takes LDS atomic adds
+// from all wavefronts of a block in no fixed order: lambda, and the adjoint
+// gradient computed from it, may differ in the last bits between runs.
 #pragma once
 
 #include <hip/hip_runtime.h>
@@ -240,31 +243,29 @@ constexpr int ilog2c(unsigned v) { return v <= 1u ? 0 : 1 + ilog2c(v >> 1); }
 template <int NT, int PER>
 struct TileAddr {
   static constexpr int kT = ilog2c(NT), kE = ilog2c(PER);
-  uint64_t thr;
-  uint64_t eb[kE > 0 ? kE : 1];
+  uint64_t off[PER];  // thr | el(i), per thread (VGPRs; the uniform parts would hold SGPRs all kernel long)
   __device__ __forceinline__ explicit TileAddr(const FrameDesc& fr) {
-    thr = 0;
+    uint64_t thr = 0;
 #pragma unroll
     for (int j = 0; j < kT; ++j) thr |= uint64_t((threadIdx.x >> j) & 1u) << fr.q[j];
 #pragma unroll
-    for (int k = 0; k < kE; ++k) eb[k] = uint64_t(1) << fr.q[kT + k];
-  }
-  __device__ __forceinline__ uint64_t el(int i) const {
-    uint64_t g = 0;
+    for (int i = 0; i < PER; ++i) {
+      uint64_t g = thr;
 #pragma unroll
-    for (int k = 0; k < kE; ++k)
-      if ((i >> k) & 1) g |= eb[k];
-    return g;
+      for (int k = 0; k < kE; ++k)
+        if ((i >> k) & 1) g |= uint64_t(1) << fr.q[kT + k];
+      off[i] = g;
+    }
   }
 };
 
 template <typename T, int PER, int NT>
 __device__ __forceinline__ void tile_fetch_full(const T* __restrict__ src, const TileAddr<NT, PER>& a, uint64_t base,
                                                 Stage<T, PER>& reg) {
-  const T* p = src + (base | a.thr);
+  const T* p = src + base;
 #pragma unroll
   for (int i = 0; i < PER; ++i) {
-    const T v = p[a.el(i)];
+    const T v = p[a.off[i]];
     reg.re[i] = v.x;
     reg.im[i] = v.y;
   }
@@ -290,9 +291,9 @@ __device__ __forceinline__ void tile_take(const T* tile, Stage<T, PER>& reg) {
 template <typename T, int PER, int NT>
 __device__ __forceinline__ void tile_send(T* __restrict__ dst, const TileAddr<NT, PER>& a, uint64_t base,
                                           const Stage<T, PER>& reg) {
-  T* p = dst + (base | a.thr);
+  T* p = dst + base;
 #pragma unroll
-  for (int i = 0; i < PER; ++i) p[a.el(i)] = cmake<T>(reg.re[i], reg.im[i]);
+  for (int i = 0; i < PER; ++i) p[a.off[i]] = cmake<T>(reg.re[i], reg.im[i]);
 }
 
 // ---------------------------------------------------------------------------

@@ -184,9 +184,9 @@ __global__ void __launch_bounds__(NT) k_tile_lambda(const T* __restrict__ psi, T
       tile_fetch_full<T, PER, NT>(psi, ta, bx, rp);
       if (MODE == 1) {
         if (diag) {
-          const double* d = diag + (bx | ta.thr);
+          const double* d = diag + bx;
 #pragma unroll
-          for (int i = 0; i < PER; ++i) rd[i] = d[ta.el(i)];
+          for (int i = 0; i < PER; ++i) rd[i] = d[ta.off[i]];
         } else {
 #pragma unroll
           for (int i = 0; i < PER; ++i) rd[i] = 0.0;

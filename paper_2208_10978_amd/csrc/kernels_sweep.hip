@@ -211,54 +211,143 @@ __device__ __forceinline__ void enum_walk(const RunDesc& run, const RunRec* __re
 }
 
 // Short runs (kRunEnum, at most two records, one position per lane): every
-// uniform quantity comes precomputed with the descriptor, and the slot and
-// sign of a pair follow from the lane part and per-record constants.
-template <typename T, bool REV, int GRAD, unsigned OM>
-__device__ __forceinline__ void short_walk(const RunDesc& run, T* tp, T* tl, uint32_t ds, unsigned sgn0, uint32_t swb,
-                                           bool lane_on, double (&acc)[GRAD == 2 ? kMaxRunStrings : 1]) {
+// uniform quantity comes precomputed with the descriptor head, and the slot
+// and sign of a pair follow from the lane part and per-record constants.
+//
+// The head is read in one batch and held in SGPRs before the first branch of
+// the run: a field first used under a branch would otherwise be loaded there,
+// and every branch level would wait for its own scalar-cache round trip.
+struct ShortHead {
+  uint32_t short_form, n_rec, omega0, walk_log, zlane, sx, slot;
+  uint32_t z0_loc;
+  uint64_t z0_out;
+  uint32_t dep_q[kWalkLaneBits];
+  uint32_t sb[2], pb[2];
+  double c[2], s[2], a[2];
+};
+
+__device__ __forceinline__ void sgpr_here(uint32_t v) { asm volatile("" ::"s"(v)); }
+__device__ __forceinline__ void sgpr_here(uint64_t v) { asm volatile("" ::"s"(v)); }
+__device__ __forceinline__ void sgpr_here(double v) { asm volatile("" ::"s"(v)); }
+
+template <int GRAD>
+__device__ __forceinline__ ShortHead load_head(const RunDesc& run) {
+  ShortHead h;
+  h.short_form = run.short_form;
+  h.n_rec = run.n_rec;
+  h.omega0 = run.omega0;
+  h.walk_log = run.walk_log;
+  h.zlane = run.zlane;
+  h.sx = run.sx;
+  h.slot = run.slot;
+  h.z0_loc = uint32_t(run.z0_loc);
+  h.z0_out = run.z0_out;
+#pragma unroll
+  for (int i = 0; i < kWalkLaneBits; ++i) h.dep_q[i] = run.dep_q[i];
+#pragma unroll
+  for (int r = 0; r < 2; ++r) {
+    h.sb[r] = run.rec_sbits[r];
+    h.pb[r] = run.rec_pbits[r];
+    h.c[r] = run.rec_c[r];
+    h.s[r] = run.rec_s[r];
+    h.a[r] = GRAD == 1 ? run.rec_a[r] : 0.0;
+  }
+  sgpr_here(h.short_form);
+  sgpr_here(h.n_rec);
+  sgpr_here(h.omega0);
+  sgpr_here(h.walk_log);
+  sgpr_here(h.zlane);
+  sgpr_here(h.sx);
+  sgpr_here(h.slot);
+  sgpr_here(h.z0_loc);
+  sgpr_here(h.z0_out);
+#pragma unroll
+  for (int i = 0; i < kWalkLaneBits; ++i) sgpr_here(h.dep_q[i]);
+#pragma unroll
+  for (int r = 0; r < 2; ++r) {
+    sgpr_here(h.sb[r]);
+    sgpr_here(h.pb[r]);
+    sgpr_here(h.c[r]);
+    sgpr_here(h.s[r]);
+    if (GRAD == 1) sgpr_here(h.a[r]);
+  }
+  return h;
+}
+
+// One record, or two (every double excitation): the records' pairs are
+// disjoint, so all LDS reads of the run leave first, then the updates, then
+// the writes; one LDS round trip per run.
+template <typename T, bool REV, int GRAD, unsigned OM, int NR>
+__device__ __forceinline__ void short_walk(const ShortHead& h, const RunDesc& run, T* tp, T* tl, uint32_t ds,
+                                           unsigned sgn0, uint32_t swb, bool lane_on,
+                                           double (&acc)[GRAD == 2 ? kMaxRunStrings : 1]) {
   using R = typename Real<T>::type;
-  for (uint32_t r = 0; r < run.n_rec; ++r) {
-    const R c = R(run.rec_c[r]), s = REV ? R(-run.rec_s[r]) : R(run.rec_s[r]);
-    double w = 0.0;
-    if (lane_on) {
-      const uint32_t s2 = ds ^ run.rec_sbits[r] ^ swb, s1 = s2 ^ run.sx;  // slots of m' and m
-      const unsigned sg = sgn0 ^ run.rec_pbits[r];
-      T a = tp[s1], b = tp[s2];
+  double w[NR];
+#pragma unroll
+  for (int r = 0; r < NR; ++r) w[r] = 0.0;
+  if (lane_on) {
+    uint32_t s1[NR], s2[NR];
+    T a[NR], b[NR], la[NR], lb[NR];
+#pragma unroll
+    for (int r = 0; r < NR; ++r) {
+      s2[r] = ds ^ h.sb[r] ^ swb;  // slot of m'
+      s1[r] = s2[r] ^ h.sx;        // slot of m
+      a[r] = tp[s1[r]];
+      b[r] = tp[s2[r]];
       if (REV) {
-        T la = tl[s1], lb = tl[s2];
-        if (GRAD) w = grad_w_om<OM>(a, b, la, lb, sg);
-        rot_pair_om<OM>(la, lb, c, s, sg);
-        tl[s1] = la;
-        tl[s2] = lb;
+        la[r] = tl[s1[r]];
+        lb[r] = tl[s2[r]];
       }
-      rot_pair_om<OM>(a, b, c, s, sg);
-      tp[s1] = a;
-      tp[s2] = b;
     }
-    if (GRAD == 1) acc[0] += run.rec_a[r] * w;
+#pragma unroll
+    for (int r = 0; r < NR; ++r) {
+      const R c = R(h.c[r]), s = REV ? R(-h.s[r]) : R(h.s[r]);
+      const unsigned sg = sgn0 ^ h.pb[r];
+      if (REV) {
+        if (GRAD) w[r] = grad_w_om<OM>(a[r], b[r], la[r], lb[r], sg);
+        rot_pair_om<OM>(la[r], lb[r], c, s, sg);
+      }
+      rot_pair_om<OM>(a[r], b[r], c, s, sg);
+    }
+#pragma unroll
+    for (int r = 0; r < NR; ++r) {
+      tp[s1[r]] = a[r];
+      tp[s2[r]] = b[r];
+      if (REV) {
+        tl[s1[r]] = la[r];
+        tl[s2[r]] = lb[r];
+      }
+    }
+  }
+#pragma unroll
+  for (int r = 0; r < NR; ++r) {
+    if (GRAD == 1) acc[0] += h.a[r] * w[r];
     if (GRAD == 2) {
 #pragma unroll
-      for (int k = 0; k < kMaxRunStrings; ++k) acc[k] += ((run.rec_eps[r] >> k) & 1u) ? -w : w;
+      for (int k = 0; k < kMaxRunStrings; ++k) acc[k] += ((run.rec_eps[r] >> k) & 1u) ? -w[r] : w[r];
     }
   }
 }
 
 template <typename T, bool REV, int GRAD>
-__device__ __forceinline__ void short_run(const RunDesc& run, T* tp, T* tl, uint64_t base, uint32_t wbits, uint32_t swb,
-                                          uint32_t lane, const LaneBits& lb,
+__device__ __forceinline__ void short_run(const ShortHead& h, const RunDesc& run, T* tp, T* tl, uint64_t base,
+                                          uint32_t wbits, uint32_t swb, uint32_t lane, const LaneBits& lb,
                                           double (&acc)[GRAD == 2 ? kMaxRunStrings : 1]) {
   uint32_t ds = 0;
 #pragma unroll
-  for (int i = 0; i < kWalkLaneBits; ++i) ds ^= lb.m[i] & run.dep_q[i];
-  const unsigned sgn0 = (parity64(base & run.z0_out) ^ parity32(wbits & uint32_t(run.z0_loc))) ^
-                        parity32(lane & run.zlane);
-  const bool lane_on = lane < (1u << run.walk_log);
-  switch (run.omega0 & 3u) {
-    case 0: short_walk<T, REV, GRAD, 0>(run, tp, tl, ds, sgn0, swb, lane_on, acc); break;
-    case 1: short_walk<T, REV, GRAD, 1>(run, tp, tl, ds, sgn0, swb, lane_on, acc); break;
-    case 2: short_walk<T, REV, GRAD, 2>(run, tp, tl, ds, sgn0, swb, lane_on, acc); break;
-    default: short_walk<T, REV, GRAD, 3>(run, tp, tl, ds, sgn0, swb, lane_on, acc); break;
+  for (int i = 0; i < kWalkLaneBits; ++i) ds ^= lb.m[i] & h.dep_q[i];
+  const unsigned sgn0 = (parity64(base & h.z0_out) ^ parity32(wbits & h.z0_loc)) ^ parity32(lane & h.zlane);
+  const bool lane_on = lane < (1u << h.walk_log);
+#define Q2SV_SHORT(OMV)                                                                        \
+  if (h.n_rec == 2) short_walk<T, REV, GRAD, OMV, 2>(h, run, tp, tl, ds, sgn0, swb, lane_on, acc); \
+  else short_walk<T, REV, GRAD, OMV, 1>(h, run, tp, tl, ds, sgn0, swb, lane_on, acc);
+  switch (h.omega0 & 3u) {
+    case 0: Q2SV_SHORT(0) break;
+    case 1: Q2SV_SHORT(1) break;
+    case 2: Q2SV_SHORT(2) break;
+    default: Q2SV_SHORT(3) break;
   }
+#undef Q2SV_SHORT
 }
 
 template <typename T, bool REV, int GRAD>
@@ -384,8 +473,9 @@ __global__ void __launch_bounds__(NT) k_tile_forward(T* __restrict__ psi, FrameD
       if (wave < (1u << __popc(sg.wb_mask))) {
         const uint32_t wbits = region_bits_of(sg.wb_mask, wave), swb = lds_swz(wbits);
         for (uint32_t ri = sg.first; ri < sg.first + sg.count; ++ri) {
-          if (runs[ri].short_form)
-            short_run<T, false, 0>(runs[ri], tile, nullptr, base, wbits, swb, lane, lbits, dummy);
+          const ShortHead h = load_head<0>(runs[ri]);
+          if (h.short_form)
+            short_run<T, false, 0>(h, runs[ri], tile, nullptr, base, wbits, swb, lane, lbits, dummy);
           else
             tile_run<T, false, 0>(runs[ri], recs, tile, nullptr, base, wbits, lane, lbits, dummy);
         }
@@ -470,14 +560,15 @@ __global__ void __launch_bounds__(NT) k_tile_reverse(T* __restrict__ psi, T* __r
           double acc[GRAD == 2 ? kMaxRunStrings : 1];
 #pragma unroll
           for (int k = 0; k < (GRAD == 2 ? kMaxRunStrings : 1); ++k) acc[k] = 0.0;
-          if (run.short_form) short_run<T, true, GRAD>(run, tp, tl, base, wbits, swb, lane, lbits, acc);
+          const ShortHead h = load_head<GRAD>(run);
+          if (h.short_form) short_run<T, true, GRAD>(h, run, tp, tl, base, wbits, swb, lane, lbits, acc);
           else tile_run<T, true, GRAD>(run, recs, tp, tl, base, wbits, lane, lbits, acc);
           if (GRAD) {
             const int nk = GRAD == 2 ? int(run.n_str) : 1;
             for (int k = 0; k < (GRAD == 2 ? kMaxRunStrings : 1); ++k) {
               if (k >= nk) break;
               const double v = wave_sum(acc[k]);
-              if (lane == 0) lds_add(&gacc.v[run.slot + k][wave], v);  // only this wavefront adds here
+              if (lane == 0) lds_add(&gacc.v[h.slot + k][wave], v);  // only this wavefront adds here
             }
           }
         }

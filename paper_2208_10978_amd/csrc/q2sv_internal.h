@@ -49,13 +49,32 @@ constexpr int kWalkLaneBits = 6;    // walk positions carried by the lane index
 // on [0, 2^B) for every B.  (constexpr: usable by host planning and kernels.)
 constexpr uint32_t lds_slot(uint32_t l) { return l ^ (((l >> 4) ^ (l >> 5) ^ (l >> 7) ^ (l >> 10)) & 15u); }
 struct alignas(16) RunDesc {
-  uint64_t x_loc;      // flip mask (frame-local bits)
+  // Short-form head (kRunEnum, at most kShortRecs records, walk_log <= 6: one
+  // position per lane): every uniform field a tile walk needs, contiguous so
+  // a kernel fetches it in one batch of scalar loads; the records inline,
+  // with the LDS slot and the z0 parity of their bits on S'.
+  uint32_t short_form;
+  uint32_t n_rec;      // number of records, or 2^L table entries
+  uint32_t omega0;     // reference phase i^{|x & z0|}, as a power of i
+  uint32_t walk_log;   // tile walk: 2^walk_log positions per record
+  uint32_t zlane;      // lane bit i -> z0 bit at dep_p[i]
+  uint32_t sx;         // LDS slot of x_loc
+  uint32_t slot;       // first gradient slot of the run
+  uint32_t pad0;
   uint64_t z0_loc;     // reference string's z, frame-local bits
   uint64_t z0_out;     // reference string's z, global bits outside the frame
-  uint32_t omega0;     // reference phase i^{|x & z0|}, as a power of i
-  uint32_t slot;       // first gradient slot of the run
+  // Tile walk: position t = lane + 64 j of the bits the run leaves free
+  // (not enumerated, not region bits).  Lane bit i lands on frame-local bit
+  // dep_p[i] (0 past the walk's width), whose LDS slot is dep_q[i]; the bits
+  // of j land on the free bits hi_mask above them.
+  uint32_t dep_q[kWalkLaneBits];
+  uint32_t rec_sbits[2];           // slot(bits)
+  uint32_t rec_pbits[2];           // parity(bits & z0_loc)
+  uint32_t pad1[2];
+  double rec_c[2], rec_s[2], rec_a[2];
+  // rest
+  uint64_t x_loc;      // flip mask (frame-local bits)
   uint32_t rec_off;    // first record (kRunEnum) or table entry (kRunFull/Diag)
-  uint32_t n_rec;      // number of records, or 2^L table entries
   uint32_t mode;       // RunMode
   uint32_t n_str;      // strings fused in the run
   uint32_t str_neg;    // bit k: omega_k / omega_0 = -1            (kRunFull/Diag)
@@ -63,31 +82,15 @@ struct alignas(16) RunDesc {
   uint32_t pivot;      // frame-local highest bit of x             (kRunFull)
   uint32_t n_pat;      // pattern bits L                           (kRunFull/Diag)
   uint32_t per_string; // gradient slots are per string (else one per run)
-  uint32_t walk_log;   // tile walk: 2^walk_log positions per record
+  uint32_t hi_mask;
+  uint32_t rec_eps[2];             // eps_neg
   // Position lists packed one byte per entry (entry j in bits 8j..8j+7), so
   // kernels read them with shifts instead of indexing a private array:
   uint64_t sup_pack;   // frame-local support positions, ascending
   uint64_t pat_pack;   // pattern bit j: frame-local position, or 64 + global
                        // position when outside the frame
   uint64_t dpat_pack;  // per string: pattern mask of z_k ^ z0
-  // Tile walk: position t = lane + 64 j of the bits the run leaves free
-  // (not enumerated, not region bits).  Lane bit i lands on frame-local bit
-  // dep_p[i] (0 past the walk's width), whose LDS slot is dep_q[i]; the bits
-  // of j land on the free bits hi_mask above them; zlane bit i is the z0 bit
-  // at dep_p[i].
   uint32_t dep_p[kWalkLaneBits];
-  uint32_t dep_q[kWalkLaneBits];
-  uint32_t hi_mask;
-  uint32_t zlane;
-  // Short form (kRunEnum, at most kShortRecs records, walk_log <= 6: one
-  // position per lane): the records inline, with the LDS slot and the z0
-  // parity of their bits on S', so a tile walk needs no further loads.
-  uint32_t short_form;
-  uint32_t sx;                     // LDS slot of x_loc
-  uint32_t rec_sbits[2];           // slot(bits)
-  uint32_t rec_pbits[2];           // parity(bits & z0_loc)
-  uint32_t rec_eps[2];             // eps_neg
-  double rec_c[2], rec_s[2], rec_a[2];
 };
 constexpr int kShortRecs = 2;
 
