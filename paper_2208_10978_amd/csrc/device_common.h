@@ -75,6 +75,13 @@ __device__ __forceinline__ uint32_t insert_zeros32_p4(uint32_t t, uint64_t pack,
   return t;
 }
 
+// An empty use that needs v in an SGPR here: scalar loads feeding it all
+// leave before this point (and are waited for once) instead of being sunk
+// one by one into the branches that first use them.
+__device__ __forceinline__ void sgpr_here(uint32_t v) { asm volatile("" ::"s"(v)); }
+__device__ __forceinline__ void sgpr_here(uint64_t v) { asm volatile("" ::"s"(v)); }
+__device__ __forceinline__ void sgpr_here(double v) { asm volatile("" ::"s"(v)); }
+
 // ---------------------------------------------------------------------------
 // deterministic FP64 reductions
 // ---------------------------------------------------------------------------

@@ -48,13 +48,106 @@ __device__ __forceinline__ double signed_by(double x, unsigned s) {
   return __hiloint2double(__double2hiint(x) ^ int(s << 31), __double2loint(x));
 }
 
+// The uniform fields of a one-subgroup group record, fetched in one batch of
+// scalar loads and held in SGPRs (see sgpr_here).
+struct FastHead {
+  uint64_t w_out;
+  uint32_t w_loc, n_rec, walk_log, hi_mask, wlane, sx;
+  uint32_t dep_q[kWalkLaneBits];
+  uint32_t sbits[kFastRecs], pbits[kFastRecs];
+  double coef[2 * kFastRecs];
+};
+
+__device__ __forceinline__ FastHead load_fast(const TFast& t) {
+  FastHead f;
+  f.w_out = t.w_out;
+  f.w_loc = t.w_loc;
+  f.n_rec = t.n_rec;
+  f.walk_log = t.walk_log;
+  f.hi_mask = t.hi_mask;
+  f.wlane = t.wlane;
+  f.sx = t.sx;
+#pragma unroll
+  for (int i = 0; i < kWalkLaneBits; ++i) f.dep_q[i] = t.dep_q[i];
+#pragma unroll
+  for (int r = 0; r < kFastRecs; ++r) {
+    f.sbits[r] = t.sbits[r];
+    f.pbits[r] = t.pbits[r];
+    f.coef[2 * r] = t.coef[2 * r];
+    f.coef[2 * r + 1] = t.coef[2 * r + 1];
+  }
+  sgpr_here(f.w_out);
+  sgpr_here(f.w_loc);
+  sgpr_here(f.n_rec);
+  sgpr_here(f.walk_log);
+  sgpr_here(f.hi_mask);
+  sgpr_here(f.wlane);
+  sgpr_here(f.sx);
+#pragma unroll
+  for (int i = 0; i < kWalkLaneBits; ++i) sgpr_here(f.dep_q[i]);
+#pragma unroll
+  for (int r = 0; r < kFastRecs; ++r) {
+    sgpr_here(f.sbits[r]);
+    sgpr_here(f.pbits[r]);
+    sgpr_here(f.coef[2 * r]);
+    sgpr_here(f.coef[2 * r + 1]);
+  }
+  return f;
+}
+
+// A wavefront's share of the one-subgroup work items: items [i0, i1) in
+// order, each 64 walk positions of one group.  A group's items are its
+// blocks 0, 1, ... in a row and groups follow in index order, so only the
+// first item is read: the walk steps block and group arithmetically, and a
+// group's record is fetched once, when the walk reaches it.  body(f, ds, zp,
+// srest, sgn, on) gets the lane's slot part, lane parity, the block's slot
+// and the uniform sign parity.
+template <typename Body>
+__device__ __forceinline__ void walk_fast_items(const BlobView& bv, uint32_t i0, uint32_t i1, uint64_t base,
+                                                uint32_t lane, const uint32_t (&lbit)[kWalkLaneBits], Body body) {
+  if (i0 >= i1) return;
+  const uint32_t w0 = bv.items[i0];
+  uint32_t cur = w0 >> 12, blk = w0 & 0xfffu;
+  FastHead f = load_fast(bv.fast[cur]);
+  auto setup = [&](uint32_t& ds, unsigned& zp, unsigned& so, bool& on, uint32_t& nb) {
+    on = f.walk_log >= kWalkLaneBits || lane < (1u << f.walk_log);
+    nb = f.walk_log > kWalkLaneBits ? 1u << (f.walk_log - kWalkLaneBits) : 1u;
+    ds = 0;
+#pragma unroll
+    for (int i = 0; i < kWalkLaneBits; ++i) ds ^= lbit[i] & f.dep_q[i];
+    zp = __popc(lane & f.wlane);
+    so = __popcll(base & f.w_out);
+  };
+  uint32_t ds, nb;
+  unsigned zp, so;
+  bool on;
+  setup(ds, zp, so, on, nb);
+  uint32_t rest = deposit_bits(blk, f.hi_mask);  // uniform
+  for (uint32_t it = i0; it < i1; ++it) {
+    const uint32_t srest = lds_swz(rest);  // uniform: slot and w parity of the block's high bits
+    const unsigned prest = __popc(rest & f.w_loc) & 1u;
+    body(f, ds, zp, srest, so ^ prest, on);
+    if (++blk == nb) {
+      if (it + 1 < i1) {
+        ++cur;
+        blk = 0;
+        rest = 0;
+        f = load_fast(bv.fast[cur]);
+        setup(ds, zp, so, on, nb);
+      }
+    } else {
+      rest = (rest - f.hi_mask) & f.hi_mask;  // the next block of the same group
+    }
+  }
+}
+
 // The pairs (m', m = m' ^ x) of every record of a one-subgroup group at one
 // walk position (index part dl, slot part ds, w-parity of the lane part zp)
 // plus the uniform part rest: all loads first, then the updates.  The index
 // and slot of a record's m' are dl | rest | bits and ds ^ slot(rest | bits)
 // (the LDS slot map is linear).
 template <int NR, typename T>
-__device__ __forceinline__ void fast_pairs(const TFast& f, uint32_t ds, unsigned zp, uint32_t srest, unsigned so,
+__device__ __forceinline__ void fast_pairs(const FastHead& f, uint32_t ds, unsigned zp, uint32_t srest, unsigned so,
                                            const T* tp, double* tlr, double* tli) {
   uint32_t smp[NR];
   T pm[NR], pp[NR];
@@ -92,7 +185,6 @@ __global__ void __launch_bounds__(NT) k_tile_lambda(const T* __restrict__ psi, T
 #pragma unroll
   for (int i = 0; i < kWalkLaneBits; ++i) lbit[i] = 0u - ((uint32_t(lane) >> i) & 1u);
   const uint32_t n_groups = bv.hdr->n_groups, n_items = bv.hdr->n_fast_items;
-  const uint32_t* items = bv.items;
 
   auto apply_groups = [&](uint64_t base) {
     // groups with several subgroups: every thread of the block takes pairs
@@ -130,44 +222,21 @@ __global__ void __launch_bounds__(NT) k_tile_lambda(const T* __restrict__ psi, T
         for (uint32_t idx = threadIdx.x; idx < n_it; idx += NT) pair(idx >> nf, idx & ((1u << nf) - 1u));
       }
     }
-    // one-subgroup groups: work items of 64 walk positions of one group; a
-    // wavefront takes a contiguous run of items (a group's items are
-    // consecutive), reloads a group's record only when the group changes and
-    // steps the uniform part of the position incrementally; a lane takes one
-    // position and every record's pair there
+    // one-subgroup groups: a wavefront takes a contiguous run of work items;
+    // a lane takes one position and every record's pair there
     {
       const uint32_t per = (n_items + NW - 1) / NW;
-      const uint32_t i1 = min(n_items, uint32_t(wave + 1) * per);
-      uint32_t cur = ~0u, ds = 0, rest = 0;
-      unsigned zp = 0, so = 0;
-      bool on = false;
-      TFast f;
-      for (uint32_t it = uint32_t(wave) * per; it < i1; ++it) {
-        const uint32_t w = items[it];
-        if ((w >> 12) != cur) {
-          cur = w >> 12;
-          f = bv.fast[cur];
-          on = f.walk_log >= kWalkLaneBits || uint32_t(lane) < (1u << f.walk_log);
-          ds = 0;
-#pragma unroll
-          for (int i = 0; i < kWalkLaneBits; ++i) ds ^= lbit[i] & f.dep_q[i];
-          zp = __popc(uint32_t(lane) & f.wlane);
-          so = __popcll(base & f.w_out);
-          rest = deposit_bits(w & 0xfffu, f.hi_mask);  // uniform
-        } else {
-          rest = (rest - f.hi_mask) & f.hi_mask;  // the next block of the same group
-        }
-        const uint32_t srest = lds_swz(rest);  // uniform: slot and w parity of the block's high bits
-        const unsigned prest = __popc(rest & f.w_loc) & 1u;
-        if (on) {
-          switch (f.n_rec) {
-            case 1: fast_pairs<1>(f, ds, zp, srest, so ^ prest, tp, tlr, tli); break;
-            case 2: fast_pairs<2>(f, ds, zp, srest, so ^ prest, tp, tlr, tli); break;
-            case 3: fast_pairs<3>(f, ds, zp, srest, so ^ prest, tp, tlr, tli); break;
-            default: fast_pairs<4>(f, ds, zp, srest, so ^ prest, tp, tlr, tli); break;
-          }
-        }
-      }
+      walk_fast_items(bv, min(n_items, uint32_t(wave) * per), min(n_items, uint32_t(wave + 1) * per), base,
+                      uint32_t(lane), lbit,
+                      [&](const FastHead& f, uint32_t ds, unsigned zp, uint32_t srest, unsigned sgn, bool on) {
+                        if (!on) return;
+                        switch (f.n_rec) {
+                          case 1: fast_pairs<1>(f, ds, zp, srest, sgn, tp, tlr, tli); break;
+                          case 2: fast_pairs<2>(f, ds, zp, srest, sgn, tp, tlr, tli); break;
+                          case 3: fast_pairs<3>(f, ds, zp, srest, sgn, tp, tlr, tli); break;
+                          default: fast_pairs<4>(f, ds, zp, srest, sgn, tp, tlr, tli); break;
+                        }
+                      });
     }
     __syncthreads();
   };
@@ -284,7 +353,7 @@ __global__ void __launch_bounds__(NT) k_tile_lambda(const T* __restrict__ psi, T
 // each lane accumulates its own FP64 sum, reduced per block in a fixed order.
 // ---------------------------------------------------------------------------
 template <int NR, typename T>
-__device__ __forceinline__ double fast_expect(const TFast& f, uint32_t ds, unsigned zp, uint32_t srest, unsigned so,
+__device__ __forceinline__ double fast_expect(const FastHead& f, uint32_t ds, unsigned zp, uint32_t srest, unsigned so,
                                               const T* tp) {
   T pm[NR], pp[NR];
 #pragma unroll
@@ -351,37 +420,17 @@ __global__ void __launch_bounds__(NT) k_tile_expect(const T* __restrict__ psi, F
     }
     {
       const uint32_t per = (n_items + NW - 1) / NW;
-      const uint32_t i1 = min(n_items, uint32_t(wave + 1) * per);
-      uint32_t cur = ~0u, ds = 0, rest = 0;
-      unsigned zp = 0, so = 0;
-      bool on = false;
-      TFast f;
-      for (uint32_t it = uint32_t(wave) * per; it < i1; ++it) {
-        const uint32_t w = bv.items[it];
-        if ((w >> 12) != cur) {
-          cur = w >> 12;
-          f = bv.fast[cur];
-          on = f.walk_log >= kWalkLaneBits || uint32_t(lane) < (1u << f.walk_log);
-          ds = 0;
-#pragma unroll
-          for (int i = 0; i < kWalkLaneBits; ++i) ds ^= lbit[i] & f.dep_q[i];
-          zp = __popc(uint32_t(lane) & f.wlane);
-          so = __popcll(base & f.w_out);
-          rest = deposit_bits(w & 0xfffu, f.hi_mask);
-        } else {
-          rest = (rest - f.hi_mask) & f.hi_mask;
-        }
-        const uint32_t srest = lds_swz(rest);
-        const unsigned prest = __popc(rest & f.w_loc) & 1u;
-        if (on) {
-          switch (f.n_rec) {
-            case 1: e += fast_expect<1>(f, ds, zp, srest, so ^ prest, tp); break;
-            case 2: e += fast_expect<2>(f, ds, zp, srest, so ^ prest, tp); break;
-            case 3: e += fast_expect<3>(f, ds, zp, srest, so ^ prest, tp); break;
-            default: e += fast_expect<4>(f, ds, zp, srest, so ^ prest, tp); break;
-          }
-        }
-      }
+      walk_fast_items(bv, min(n_items, uint32_t(wave) * per), min(n_items, uint32_t(wave + 1) * per), base,
+                      uint32_t(lane), lbit,
+                      [&](const FastHead& f, uint32_t ds, unsigned zp, uint32_t srest, unsigned sgn, bool on) {
+                        if (!on) return;
+                        switch (f.n_rec) {
+                          case 1: e += fast_expect<1>(f, ds, zp, srest, sgn, tp); break;
+                          case 2: e += fast_expect<2>(f, ds, zp, srest, sgn, tp); break;
+                          case 3: e += fast_expect<3>(f, ds, zp, srest, sgn, tp); break;
+                          default: e += fast_expect<4>(f, ds, zp, srest, sgn, tp); break;
+                        }
+                      });
     }
     __syncthreads();
   };

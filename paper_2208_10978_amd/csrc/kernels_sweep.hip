@@ -226,10 +226,6 @@ struct ShortHead {
   double c[2], s[2], a[2];
 };
 
-__device__ __forceinline__ void sgpr_here(uint32_t v) { asm volatile("" ::"s"(v)); }
-__device__ __forceinline__ void sgpr_here(uint64_t v) { asm volatile("" ::"s"(v)); }
-__device__ __forceinline__ void sgpr_here(double v) { asm volatile("" ::"s"(v)); }
-
 template <int GRAD>
 __device__ __forceinline__ ShortHead load_head(const RunDesc& run) {
   ShortHead h;
