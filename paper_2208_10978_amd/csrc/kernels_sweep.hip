@@ -325,6 +325,49 @@ __device__ __forceinline__ void short_walk(const ShortHead& h, const RunDesc& ru
   }
 }
 
+// Two records whose walks fit half a wavefront (walk_log < 6, every double
+// excitation in an 8-region tile), reverse sweep: lane bit walk_log picks the
+// record, so each lane updates one pair of psi and one of lambda and no lane
+// idles (the forward sweep, with half the work per pair, gains nothing).  The record's constants are
+// selected per lane; the lane bits below walk_log are the walk position.
+template <typename T, bool REV, int GRAD, unsigned OM>
+__device__ __forceinline__ void short_walk_split(const ShortHead& h, const RunDesc& run, T* tp, T* tl, uint32_t ds,
+                                                 unsigned sgn0, uint32_t swb, uint32_t lane,
+                                                 double (&acc)[GRAD == 2 ? kMaxRunStrings : 1]) {
+  using R = typename Real<T>::type;
+  const bool r1 = (lane >> h.walk_log) & 1u;
+  const bool lane_on = lane < (2u << h.walk_log);
+  double w = 0.0;
+  if (lane_on) {
+    const uint32_t s2 = ds ^ (r1 ? h.sb[1] : h.sb[0]) ^ swb;  // slot of m'
+    const uint32_t s1 = s2 ^ h.sx;                            // slot of m
+    T a = tp[s1], b = tp[s2];
+    T la, lb;
+    if (REV) {
+      la = tl[s1];
+      lb = tl[s2];
+    }
+    const R c = R(r1 ? h.c[1] : h.c[0]);
+    const R s = REV ? R(-(r1 ? h.s[1] : h.s[0])) : R(r1 ? h.s[1] : h.s[0]);
+    const unsigned sg = sgn0 ^ (r1 ? h.pb[1] : h.pb[0]);
+    if (REV) {
+      if (GRAD) w = grad_w_om<OM>(a, b, la, lb, sg);
+      rot_pair_om<OM>(la, lb, c, s, sg);
+      tl[s1] = la;
+      tl[s2] = lb;
+    }
+    rot_pair_om<OM>(a, b, c, s, sg);
+    tp[s1] = a;
+    tp[s2] = b;
+  }
+  if (GRAD == 1) acc[0] += (r1 ? h.a[1] : h.a[0]) * w;
+  if (GRAD == 2) {
+    const uint32_t eps = r1 ? run.rec_eps[1] : run.rec_eps[0];
+#pragma unroll
+    for (int k = 0; k < kMaxRunStrings; ++k) acc[k] += ((eps >> k) & 1u) ? -w : w;
+  }
+}
+
 template <typename T, bool REV, int GRAD>
 __device__ __forceinline__ void short_run(const ShortHead& h, const RunDesc& run, T* tp, T* tl, uint64_t base,
                                           uint32_t wbits, uint32_t swb, uint32_t lane, const LaneBits& lb,
@@ -334,8 +377,10 @@ __device__ __forceinline__ void short_run(const ShortHead& h, const RunDesc& run
   for (int i = 0; i < kWalkLaneBits; ++i) ds ^= lb.m[i] & h.dep_q[i];
   const unsigned sgn0 = (parity64(base & h.z0_out) ^ parity32(wbits & h.z0_loc)) ^ parity32(lane & h.zlane);
   const bool lane_on = lane < (1u << h.walk_log);
+  const bool split = REV && h.n_rec == 2 && h.walk_log < uint32_t(kWalkLaneBits);
 #define Q2SV_SHORT(OMV)                                                                        \
-  if (h.n_rec == 2) short_walk<T, REV, GRAD, OMV, 2>(h, run, tp, tl, ds, sgn0, swb, lane_on, acc); \
+  if (split) short_walk_split<T, REV, GRAD, OMV>(h, run, tp, tl, ds, sgn0, swb, lane, acc);        \
+  else if (h.n_rec == 2) short_walk<T, REV, GRAD, OMV, 2>(h, run, tp, tl, ds, sgn0, swb, lane_on, acc); \
   else short_walk<T, REV, GRAD, OMV, 1>(h, run, tp, tl, ds, sgn0, swb, lane_on, acc);
   switch (h.omega0 & 3u) {
     case 0: Q2SV_SHORT(0) break;
