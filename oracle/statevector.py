@@ -8,6 +8,8 @@
 * Energy ``E = sum_t c_t <psi|P_t|psi>`` term by term (Eq. 2), no grouping.
 * Reverse-mode differentiation, Algorithm 1 (Section 4.3), with one unitary
   per rotation ``U_k = R(P_k, phi_k)`` and ``dU_k/dphi_k = (-i/2) P_k U_k``.
+* Variational quantum deflation (Section 5.1, Eq. 12): the same with H
+  replaced by ``H + sum_j alpha_j |Psi_j><Psi_j|``.
 """
 from __future__ import annotations
 
@@ -55,8 +57,12 @@ def reverse_mode_gradient(psi0: np.ndarray, hx, hz, hc, rx, rz, rphi):
     E with respect to every rotation angle."""
     psi = apply_rotations(psi0.copy(), rx, rz, rphi)
     psi_l = apply_hamiltonian(psi, hx, hz, hc)
-    energy = float(np.vdot(psi, psi_l).real)
-    psi_r = psi
+    return float(np.vdot(psi, psi_l).real), _backward(psi, psi_l, rx, rz, rphi)
+
+
+def _backward(psi_r, psi_l, rx, rz, rphi):
+    """The backward loop of Algorithm 1 from the circuit output psi_r and
+    psi_l = H psi_r."""
     g = np.zeros(len(rphi))
     for i in range(len(rphi) - 1, -1, -1):
         x, z, phi = int(rx[i]), int(rz[i]), float(rphi[i])
@@ -64,7 +70,25 @@ def reverse_mode_gradient(psi0: np.ndarray, hx, hz, hc, rx, rz, rphi):
         d_u_psi = -0.5j * pauli.apply(rotate(psi_r, x, z, phi), x, z)
         g[i] = 2.0 * np.vdot(psi_l, d_u_psi).real
         psi_l = rotate(psi_l, x, z, -phi)
-    return energy, g
+    return g
+
+
+def deflated_energy(psi: np.ndarray, hx, hz, hc, proj, alphas) -> float:
+    """Eq. 12: ``<psi|H_eff|psi>`` with ``H_eff = H + sum_j alpha_j
+    |Psi_j><Psi_j|`` (the lower states Psi_j as given), for a unit psi."""
+    e, _ = expectation(psi, hx, hz, hc)
+    return float(e.real) + sum(float(a) * abs(np.vdot(p, psi)) ** 2 for p, a in zip(proj, alphas))
+
+
+def deflated_reverse_gradient(psi0: np.ndarray, hx, hz, hc, proj, alphas, rx, rz, rphi):
+    """Algorithm 1 for the effective Hamiltonian of Eq. 12: the forward sweep,
+    ``psi_l = H_eff psi = H psi + sum_j alpha_j <Psi_j|psi> Psi_j``, then the
+    same backward loop.  Returns ``(<psi|H_eff|psi>, g)``."""
+    psi = apply_rotations(psi0.copy(), rx, rz, rphi)
+    psi_l = apply_hamiltonian(psi, hx, hz, hc)
+    for p, a in zip(proj, alphas):
+        psi_l = psi_l + float(a) * np.vdot(p, psi) * p
+    return float(np.vdot(psi, psi_l).real), _backward(psi, psi_l, rx, rz, rphi)
 
 
 def chain_to_parameters(g_rot, param_of_rot, dphi_dtheta, n_params: int) -> np.ndarray:
