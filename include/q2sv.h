@@ -129,6 +129,33 @@ int sv_adjoint_grad_params_h(sv_state *psi, sv_state *lam, const sv_hamiltonian 
                              const int32_t *param_of_rot, const double *dphi_dtheta,
                              int64_t n_params, double *energy_dev, double *grad_theta_dev);
 
+/* Variational quantum deflation (Section 5.1, Eq. 12): the k-th excited
+ * state minimizes <psi|H_eff|psi> with
+ *   H_eff = H + sum_{j < n_proj} alpha[j] |Psi_j><Psi_j|.
+ * As sv_adjoint_grad_params_h with H replaced by H_eff: the adjoint sweep
+ * (Algorithm 1) starts from lambda = H psi + sum_j alpha[j] <Psi_j|psi> Psi_j.
+ *   proj     host array of n_proj states (0 <= n_proj <= 8): same n, dtype
+ *            and device as psi, neither psi nor lam; read on psi's stream,
+ *            so writes to them from another stream must be ordered first by
+ *            the caller.  Their normalization is the caller's.
+ *   alpha    host FP64[n_proj], finite (copied before return)
+ *   energy_dev  device FP64[2]: <psi|H_eff|psi>/<psi|psi>, <psi|psi>
+ *   ovl_dev     device FP64[2 n_proj] or NULL: <Psi_j|psi> (re, im) at the
+ *               circuit output
+ * n_proj = 0 gives the plain call.  Errors as sv_adjoint_grad_params_h, and
+ * SV_EINVAL for a bad deflation list. */
+int sv_adjoint_grad_params_deflated(sv_state *psi, sv_state *lam, const sv_hamiltonian *h,
+                                    const sv_state *const *proj, const double *alpha, int n_proj,
+                                    const sv_pauli *rp, const double *phi, int64_t n_rot,
+                                    const int32_t *param_of_rot, const double *dphi_dtheta,
+                                    int64_t n_params, double *energy_dev, double *ovl_dev,
+                                    double *grad_theta_dev);
+
+/* Overlap <a|b> = sum_k conj(a[k]) b[k], reduced in FP64 in a fixed order
+ * (the overlap term of Eq. 12).  out_dev: device FP64[2] = (re, im).  a and
+ * b share n, dtype and device; both are read on b's stream. */
+int sv_overlap(const sv_state *a, const sv_state *b, double *out_dev);
+
 /* psi <- psi / ||psi|| with the norm reduced in FP64 (the scale is applied in
  * the amplitude precision).  norm2_dev (device FP64[1], may be NULL)
  * receives ||psi||^2 before scaling. */

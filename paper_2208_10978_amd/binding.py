@@ -52,6 +52,9 @@ def lib():
             "sv_hamiltonian_free": [_vp],
             "sv_expect_hamiltonian": [_vp, _vp, _vp],
             "sv_adjoint_grad_params_h": [_vp, _vp, _vp, _vp, _vp, _i64, _vp, _vp, _i64, _vp, _vp],
+            "sv_adjoint_grad_params_deflated": [_vp, _vp, _vp, _vp, _vp, ctypes.c_int, _vp, _vp, _i64, _vp, _vp,
+                                                _i64, _vp, _vp, _vp],
+            "sv_overlap": [_vp, _vp, _vp],
             "sv_normalize": [_vp, _vp],
             "sv_gather_amplitudes": [_vp, _vp, _i64, _vp],
             "sv_profile_begin": [],
@@ -70,7 +73,8 @@ def lib():
 EXPORTED = (
     "sv_alloc", "sv_free", "sv_set_stream", "sv_prepare_hf", "sv_apply_pauli_rotations",
     "sv_expect_pauli_sum", "sv_adjoint_grad", "sv_adjoint_grad_params", "sv_hamiltonian_create",
-    "sv_hamiltonian_free", "sv_expect_hamiltonian", "sv_adjoint_grad_params_h", "sv_normalize",
+    "sv_hamiltonian_free", "sv_expect_hamiltonian", "sv_adjoint_grad_params_h",
+    "sv_adjoint_grad_params_deflated", "sv_overlap", "sv_normalize",
     "sv_gather_amplitudes", "sv_profile_begin", "sv_profile_end", "sv_last_error",
 )
 
@@ -198,6 +202,27 @@ def sv_adjoint_grad_params_h(psi, lam, h, rx, rz, phi, param_of_rot, dphi_dtheta
     d = _f64(dphi_dtheta)
     _check(lib().sv_adjoint_grad_params_h(psi, lam, h, _ptr(rp), _ptr(ph), len(ph), _ptr(pr), _ptr(d),
                                           int(n_params), _dev(energy_dev), _dev(grad_theta_dev)))
+
+
+def sv_adjoint_grad_params_deflated(psi, lam, h, proj, alpha, rx, rz, phi, param_of_rot, dphi_dtheta, n_params,
+                                    energy_dev, ovl_dev, grad_theta_dev):
+    """proj: sequence of state handles; alpha: their weights (Eq. 12)."""
+    k = len(proj)
+    arr = (_vp * max(k, 1))(*[ctypes.c_void_p(p.value if isinstance(p, ctypes.c_void_p) else p) for p in proj])
+    al = _f64(alpha)
+    if len(al) != k:
+        raise ValueError("alpha and proj differ in length")
+    rp = _paulis(rx, rz)
+    ph = _f64(phi)
+    pr = np.ascontiguousarray(param_of_rot, dtype=np.int32)
+    d = _f64(dphi_dtheta)
+    _check(lib().sv_adjoint_grad_params_deflated(psi, lam, h, ctypes.cast(arr, _vp), _ptr(al), k, _ptr(rp),
+                                                 _ptr(ph), len(ph), _ptr(pr), _ptr(d), int(n_params),
+                                                 _dev(energy_dev), _dev(ovl_dev), _dev(grad_theta_dev)))
+
+
+def sv_overlap(a, b, out_dev):
+    _check(lib().sv_overlap(a, b, _dev(out_dev)))
 
 
 def sv_normalize(s, norm2_dev=None):

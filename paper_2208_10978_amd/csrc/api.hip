@@ -639,11 +639,52 @@ static int check_pair(sv_state* psi, sv_state* lam) {
 }
 
 // common body of the adjoint calls; param == nullptr -> per-rotation gradient
+// lam += sum_j alpha_j <P_j|psi> P_j (Eq. 12), then energy_dev = Rayleigh
+// quotient of H_eff from <psi|lam>; ovl_dev (optional) gets the overlaps.
+static int deflate_impl(sv_state* psi, sv_state* lam, const ProjArgs& pa, double* energy_dev, double* ovl_dev) {
+  const int g = dot_grid(psi);
+  int rc = psi->scratch.ensure((2 * size_t(pa.k) * size_t(g) + 3 * size_t(g) + 8) * sizeof(double), psi->stream);
+  if (rc) return rc;
+  rc = psi->small.ensure((16 + 2 * kMaxProj) * sizeof(double), psi->stream);
+  if (rc) return rc;
+  double* part = static_cast<double*>(psi->scratch.p);
+  double* sm = static_cast<double*>(psi->small.p);
+  double* ovl = sm + 16;
+  {
+    ProfScope prof(psi->stream, kPDot, (1.0 + pa.k) * psi->bytes());
+    HIP_TRY(launch_overlaps(psi->dtype, psi->amps, pa, psi->amp_count(), g, part, psi->stream));
+  }
+  {
+    ProfScope prof(psi->stream, kPSmall, 0.0);
+    HIP_TRY(launch_reduce_rows(part, uint64_t(g), uint32_t(g), uint32_t(2 * pa.k), ovl, psi->stream));
+  }
+  {
+    ProfScope prof(psi->stream, kPDot, (2.0 + pa.k) * psi->bytes());
+    HIP_TRY(launch_deflate(psi->dtype, lam->amps, pa, ovl, psi->amp_count(), g, psi->stream));
+  }
+  {
+    ProfScope prof(psi->stream, kPDot, 2.0 * psi->bytes());
+    HIP_TRY(launch_dot(psi->dtype, psi->amps, lam->amps, nullptr, psi->amp_count(), g, part, psi->stream));
+  }
+  ProfScope prof(psi->stream, kPSmall, 0.0);
+  HIP_TRY(launch_reduce_rows(part, 0, uint32_t(g), 1, sm, psi->stream));
+  HIP_TRY(launch_reduce_rows(part + g, 0, uint32_t(g), 1, sm + 1, psi->stream));
+  HIP_TRY(launch_finish_energy(sm, 1, sm + 1, energy_dev, psi->stream));
+  if (ovl_dev)
+    HIP_TRY(hipMemcpyAsync(ovl_dev, ovl, 2 * size_t(pa.k) * sizeof(double), hipMemcpyDeviceToDevice, psi->stream));
+  return SV_OK;
+}
+
 static int adjoint_impl(sv_state* psi, sv_state* lam, sv_hamiltonian* h, const sv_pauli* rp, const double* phi,
                         int64_t n_rot, const int32_t* param, const double* dphi, int64_t n_params,
-                        double* energy_dev, double* grad_dev) {
+                        double* energy_dev, double* grad_dev, const ProjArgs* defl = nullptr,
+                        double* ovl_dev = nullptr) {
   int rc = lambda_impl(psi, lam, h, energy_dev);
   if (rc) return rc;
+  if (defl && defl->k > 0) {
+    rc = deflate_impl(psi, lam, *defl, energy_dev, ovl_dev);
+    if (rc) return rc;
+  }
   const int grad_mode = param ? 1 : 2;
   RotPlan pl;
   plan_rotations(psi, rp, phi, dphi, param, n_rot, true, grad_mode, pl);
@@ -898,6 +939,65 @@ int sv_adjoint_grad_params_h(sv_state* psi, sv_state* lam, const sv_hamiltonian*
   DeviceGuard g(psi->device);
   return adjoint_impl(psi, lam, const_cast<sv_hamiltonian*>(hc), rp, phi, n_rot, param, dphi, n_params,
                       energy_dev, grad_theta_dev);
+}
+
+int sv_adjoint_grad_params_deflated(sv_state* psi, sv_state* lam, const sv_hamiltonian* hc,
+                                    const sv_state* const* proj, const double* alpha, int n_proj,
+                                    const sv_pauli* rp, const double* phi, int64_t n_rot, const int32_t* param,
+                                    const double* dphi, int64_t n_params, double* energy_dev, double* ovl_dev,
+                                    double* grad_theta_dev) {
+  int rc = check_pair(psi, lam);
+  if (rc) return rc;
+  if (!hc) return fail(SV_EINVAL, "NULL Pauli sum");
+  if (hc->n != psi->n) return fail(SV_EINVAL, "Pauli sum and state differ in n");
+  if (!energy_dev || (n_params > 0 && !grad_theta_dev)) return fail(SV_EINVAL, "NULL output");
+  if (n_proj < 0 || n_proj > kMaxProj) return fail(SV_EINVAL, "n_proj out of range (0..8)");
+  if (n_proj > 0 && (!proj || !alpha)) return fail(SV_EINVAL, "NULL deflation states or weights");
+  ProjArgs pa{};
+  pa.k = n_proj;
+  for (int j = 0; j < n_proj; ++j) {
+    const sv_state* q = proj[j];
+    if (!q) return fail(SV_EINVAL, "NULL deflation state");
+    if (q == psi || q == lam) return fail(SV_EINVAL, "a deflation state is psi or lam");
+    if (q->n != psi->n || q->dtype != psi->dtype) return fail(SV_EINVAL, "deflation state differs in n or dtype");
+    if (q->device != psi->device) return fail(SV_EINVAL, "deflation state on another device");
+    if (!std::isfinite(alpha[j])) return fail(SV_EINVAL, "alpha is not finite");
+    pa.p[j] = q->amps;
+    pa.alpha[j] = alpha[j];
+  }
+  rc = validate_paulis(rp, n_rot, psi->n, "rotation");
+  if (rc) return rc;
+  rc = validate_finite(phi, n_rot, "phi");
+  if (rc) return rc;
+  rc = check_params(param, dphi, n_rot, n_params);
+  if (rc) return rc;
+  DeviceGuard g(psi->device);
+  return adjoint_impl(psi, lam, const_cast<sv_hamiltonian*>(hc), rp, phi, n_rot, param, dphi, n_params,
+                      energy_dev, grad_theta_dev, &pa, ovl_dev);
+}
+
+int sv_overlap(const sv_state* a, const sv_state* b, double* out_dev) {
+  if (!a || !b) return fail(SV_EINVAL, "NULL state");
+  if (!out_dev) return fail(SV_EINVAL, "NULL output");
+  if (a->n != b->n || a->dtype != b->dtype) return fail(SV_EINVAL, "states differ in n or dtype");
+  if (a->device != b->device) return fail(SV_EINVAL, "states on different devices");
+  DeviceGuard g(b->device);
+  sv_state* s = const_cast<sv_state*>(b);
+  ProjArgs pa{};
+  pa.k = 1;
+  pa.p[0] = a->amps;
+  const int gd = dot_grid(s);
+  int rc = s->scratch.ensure((2 * size_t(gd) + 8) * sizeof(double), s->stream);
+  if (rc) return rc;
+  double* part = static_cast<double*>(s->scratch.p);
+  {
+    ProfScope prof(s->stream, kPDot, 2.0 * s->bytes());
+    HIP_TRY(launch_overlaps(s->dtype, s->amps, pa, s->amp_count(), gd, part, s->stream));
+  }
+  ProfScope prof(s->stream, kPSmall, 0.0);
+  HIP_TRY(launch_reduce_rows(part, uint64_t(gd), uint32_t(gd), 2, out_dev, s->stream));
+  g_err.clear();
+  return SV_OK;
 }
 
 int sv_normalize(sv_state* s, double* norm2_dev) {

@@ -96,6 +96,67 @@ __global__ void __launch_bounds__(256) k_gather_amps(const T* __restrict__ psi, 
 }
 
 // ---------------------------------------------------------------------------
+// Deflation (Eq. 12): H_eff = H + sum_j alpha_j |Psi_j><Psi_j|.  The adjoint
+// needs lambda = H_eff psi = H psi + sum_j alpha_j <Psi_j|psi> Psi_j: one pass
+// forms every overlap <Psi_j|psi> (psi read once, FP64 partials per block),
+// a second adds the rank-one terms into lambda.
+// ---------------------------------------------------------------------------
+// partials[(2j) * grid + block] = Re <P_j|psi>, [(2j + 1) * grid + block] = Im
+template <typename T>
+__global__ void __launch_bounds__(256) k_overlaps(const T* __restrict__ psi, ProjArgs pa, uint64_t n_amp,
+                                                  double* __restrict__ partials) {
+  __shared__ double red[4];
+  const uint64_t stride = uint64_t(gridDim.x) * 256;
+  double re[kMaxProj], im[kMaxProj];
+#pragma unroll
+  for (int j = 0; j < kMaxProj; ++j) re[j] = im[j] = 0.0;
+  for (uint64_t i = uint64_t(blockIdx.x) * 256 + threadIdx.x; i < n_amp; i += stride) {
+    const T u = psi[i];
+#pragma unroll
+    for (int j = 0; j < kMaxProj; ++j) {
+      if (j >= pa.k) break;
+      const T v = static_cast<const T*>(pa.p[j])[i];
+      re[j] += (double)v.x * u.x + (double)v.y * u.y;  // conj(v) u
+      im[j] += (double)v.x * u.y - (double)v.y * u.x;
+    }
+  }
+  for (int j = 0; j < pa.k; ++j) {
+    const double a = block_sum<256>(re[j], red);
+    if (threadIdx.x == 0) partials[uint64_t(2 * j) * gridDim.x + blockIdx.x] = a;
+    const double b = block_sum<256>(im[j], red);
+    if (threadIdx.x == 0) partials[uint64_t(2 * j + 1) * gridDim.x + blockIdx.x] = b;
+  }
+}
+
+// lam += sum_j alpha_j ovl_j P_j, ovl = (re, im) pairs in device memory
+template <typename T>
+__global__ void __launch_bounds__(256) k_deflate(T* __restrict__ lam, ProjArgs pa, const double* __restrict__ ovl,
+                                                 uint64_t n_amp) {
+  using R = typename Real<T>::type;
+  double cr[kMaxProj], ci[kMaxProj];
+#pragma unroll
+  for (int j = 0; j < kMaxProj; ++j) {
+    cr[j] = j < pa.k ? pa.alpha[j] * ovl[2 * j] : 0.0;
+    ci[j] = j < pa.k ? pa.alpha[j] * ovl[2 * j + 1] : 0.0;
+  }
+  const uint64_t stride = uint64_t(gridDim.x) * 256;
+  for (uint64_t i = uint64_t(blockIdx.x) * 256 + threadIdx.x; i < n_amp; i += stride) {
+    T l = lam[i];
+    double lr = l.x, li = l.y;
+#pragma unroll
+    for (int j = 0; j < kMaxProj; ++j) {
+      if (j >= pa.k) break;
+      const T v = static_cast<const T*>(pa.p[j])[i];
+      lr += cr[j] * v.x - ci[j] * v.y;
+      li += cr[j] * v.y + ci[j] * v.x;
+    }
+    l.x = R(lr);
+    l.y = R(li);
+    lam[i] = l;
+  }
+}
+
+// ---------------------------------------------------------------------------
 // launchers
 // ---------------------------------------------------------------------------
 hipError_t launch_dot(int dtype, const void* a, const void* b, const double* d, uint64_t n_amp, int grid,
@@ -157,6 +218,29 @@ hipError_t launch_gather_amps(int dtype, const void* psi, const uint64_t* idx, i
   else
     hipLaunchKernelGGL((k_gather_amps<float2>), dim3(grid), dim3(256), 0, st, static_cast<const float2*>(psi),
                        idx, count, out);
+  return hipGetLastError();
+}
+
+
+hipError_t launch_overlaps(int dtype, const void* psi, const ProjArgs& pa, uint64_t n_amp, int grid,
+                           double* partials, hipStream_t st) {
+  if (dtype == 0)
+    hipLaunchKernelGGL((k_overlaps<double2>), dim3(grid), dim3(256), 0, st, static_cast<const double2*>(psi), pa,
+                       n_amp, partials);
+  else
+    hipLaunchKernelGGL((k_overlaps<float2>), dim3(grid), dim3(256), 0, st, static_cast<const float2*>(psi), pa,
+                       n_amp, partials);
+  return hipGetLastError();
+}
+
+hipError_t launch_deflate(int dtype, void* lam, const ProjArgs& pa, const double* ovl, uint64_t n_amp, int grid,
+                          hipStream_t st) {
+  if (dtype == 0)
+    hipLaunchKernelGGL((k_deflate<double2>), dim3(grid), dim3(256), 0, st, static_cast<double2*>(lam), pa, ovl,
+                       n_amp);
+  else
+    hipLaunchKernelGGL((k_deflate<float2>), dim3(grid), dim3(256), 0, st, static_cast<float2*>(lam), pa, ovl,
+                       n_amp);
   return hipGetLastError();
 }
 

@@ -58,6 +58,20 @@ hipError_t launch_scale(int dtype, void* psi, uint64_t n_amp, const double* norm
 hipError_t launch_gather_amps(int dtype, const void* psi, const uint64_t* idx, int64_t count, double* out,
                               hipStream_t st);
 
+// Deflation states (Eq. 12), passed by value: at most kMaxProj states.
+constexpr int kMaxProj = 8;
+struct ProjArgs {
+  const void* p[kMaxProj];
+  double alpha[kMaxProj];
+  int k;
+};
+// partials[(2j) * grid + b], [(2j + 1) * grid + b] = Re, Im <P_j|psi> of block b
+hipError_t launch_overlaps(int dtype, const void* psi, const ProjArgs& pa, uint64_t n_amp, int grid,
+                           double* partials, hipStream_t st);
+// lam += sum_j alpha_j ovl_j P_j (ovl: device FP64 (re, im) pairs)
+hipError_t launch_deflate(int dtype, void* lam, const ProjArgs& pa, const double* ovl, uint64_t n_amp, int grid,
+                          hipStream_t st);
+
 inline int tile_bits_one(int dtype) { return dtype == 0 ? kTileFwdC128 : kTileFwdC64; }
 inline int tile_bits_two(int dtype) { return dtype == 0 ? kTileTwoC128 : kTileTwoC64; }
 inline int tile_bits_lambda(int dtype) { return dtype == 0 ? kTileLamC128 : kTileLamC64; }

@@ -26,7 +26,20 @@ class StateVector:
         self.n = int(n_qubits)
         self.dtype = dtype
         self.amps = torch.empty(1 << self.n, dtype=tdt, device=device)
+        self.stream = stream
         self.handle = B.sv_alloc(self.n, code, self.amps, stream)
+
+    def clone(self) -> "StateVector":
+        """A new state with a copy of these amplitudes (same n, dtype, stream)."""
+        c = StateVector(self.n, self.dtype, device=self.amps.device, stream=self.stream)
+        c.amps.copy_(self.amps)
+        return c
+
+    def overlap(self, other: "StateVector", out=None) -> torch.Tensor:
+        """<self|other> as a device FP64 tensor (re, im)."""
+        out = out if out is not None else torch.empty(2, dtype=torch.float64, device=self.amps.device)
+        B.sv_overlap(self.handle, other.handle, out)
+        return out
 
     def prepare_hf(self, occ_mask: int):
         B.sv_prepare_hf(self.handle, occ_mask)
@@ -137,6 +150,24 @@ class UCCSDEvaluator:
                                    np.zeros(len(pool)), pool.param, pool.dphi_dtheta, pool.n_params,
                                    self.energy_buf, out)
         return out
+
+    def energy_and_grad_deflated(self, theta, lower, alphas):
+        """Variational quantum deflation (Eq. 12): energy and dE/dtheta of
+        <psi|H_eff|psi>, H_eff = H + sum_j alphas[j] |lower_j><lower_j|, with
+        the lower states as StateVectors.  Returns device tensors
+        (energy[2], grad[n_params], overlaps <lower_j|psi> as (re, im) pairs)."""
+        phi = self.forward_state(theta)
+        ovl = torch.empty(max(1, 2 * len(lower)), dtype=torch.float64, device=self.psi.amps.device)
+        B.sv_adjoint_grad_params_deflated(self.psi.handle, self.lam.handle, self.h.handle,
+                                          [s.handle for s in lower], list(alphas), self.rot.x, self.rot.z, phi,
+                                          self.rot.param, self.rot.dphi_dtheta, self.rot.n_params,
+                                          self.energy_buf, ovl if lower else None, self.grad_buf)
+        return self.energy_buf, self.grad_buf, ovl[:2 * len(lower)]
+
+    def state(self, theta) -> StateVector:
+        """U(theta)|HF> as a new StateVector."""
+        self.forward_state(theta)
+        return self.psi.clone()
 
     def free(self):
         for o in (self.psi, self.lam, self.h):

@@ -45,3 +45,32 @@ def vqe(fun_and_grad, theta0, maxiter: int = 200, gtol: float = 1e-9, method: st
     wall = time.perf_counter() - t0
     return {"energy": float(res.fun), "theta": np.asarray(res.x), "n_iter": int(res.nit), "n_eval": n_eval[0],
             "history": history, "converged": bool(res.success), "seconds_per_eval": wall / max(1, n_eval[0])}
+
+
+def deflated_objective(evaluator, lower, alphas):
+    """(energy, gradient) of Eq. 12's effective Hamiltonian on the device."""
+    def fun_and_grad(theta):
+        e, g, _ = evaluator.energy_and_grad_deflated(np.asarray(theta, dtype=np.float64), lower, alphas)
+        return float(e[0].item()), g.detach().to("cpu").numpy().astype(np.float64)
+    return fun_and_grad
+
+
+def vqd(evaluator, n_states: int, alpha: float, theta0s, maxiter: int = 200, gtol: float = 1e-9):
+    """Variational quantum deflation (Section 5.1, Eq. 12): state k minimizes
+    <psi|H_eff^k|psi>, H_eff^k = H_eff^{k-1} + alpha |Psi_{k-1}><Psi_{k-1}|,
+    starting from theta0s[k] (one start, or a list of starts whose best
+    minimum is kept).  Returns one dict per state: the minimum of the
+    effective energy, the plain energy <H> there, the amplitudes, and the
+    state itself (a StateVector; the caller frees it)."""
+    lower, out = [], []
+    for k in range(n_states):
+        starts = theta0s[k]
+        starts = [starts] if np.ndim(starts[0]) == 0 else starts
+        f = deflated_objective(evaluator, lower, [alpha] * len(lower))
+        best = min((vqe(f, t0, maxiter=maxiter, gtol=gtol) for t0 in starts), key=lambda r: r["energy"])
+        e_h = float(evaluator.energy(best["theta"])[0].item())
+        st = evaluator.state(best["theta"])
+        lower.append(st)
+        out.append({"energy_eff": best["energy"], "energy": e_h, "theta": best["theta"], "state": st,
+                    "n_eval": best["n_eval"], "converged": best["converged"]})
+    return out
