@@ -237,10 +237,16 @@ def poly_mul(a: dict, b: dict) -> dict:
     return out
 
 
-def word_pauli(word) -> dict:
+def qubit_ladder_pauli(j: int, create: bool):
+    """Qubit ladder without a string: ``Q_j = (X_j + i Y_j)/2`` lowers qubit j
+    (|1> -> |0>), ``Q+_j = (X_j - i Y_j)/2`` raises it."""
+    return {(1 << j, 0): 0.5, (1 << j, 1 << j): (-0.5j if create else 0.5j)}
+
+
+def word_pauli(word, ladder=ladder_pauli) -> dict:
     poly = {(0, 0): 1.0 + 0j}
     for q, create in word:
-        poly = poly_mul(poly, ladder_pauli(q, create))
+        poly = poly_mul(poly, ladder(q, create))
     return poly
 
 
@@ -271,7 +277,16 @@ def uccsd_rotations(n_qubits: int, n_electrons: int, order=None):
     return excitation_rotations(checked_order(n_qubits, n_electrons, order))
 
 
-def excitation_rotations(excitations, first_param: int = 0):
+def qubit_excitation_rotations(excitations, first_param: int = 0):
+    """Qubit-excitation-based operators (Section 5.1): the rotation list of
+    ``prod_i exp(theta_i (T_i - T_i^dag))`` where ``T_i`` is the excitation's
+    word with qubit ladders (``qubit_ladder_pauli``) in place of fermionic
+    ones, so no Jordan-Wigner strings.  Same output form as
+    ``excitation_rotations``."""
+    return excitation_rotations(excitations, first_param, ladder=qubit_ladder_pauli)
+
+
+def excitation_rotations(excitations, first_param: int = 0, ladder=ladder_pauli):
     """Rotation list of ``prod_i exp(theta_i (tau_i - tau_i^dag))`` (Eq. 11)
     for any sequence of excitations; parameter ``first_param + i`` is the
     i-th excitation.
@@ -285,8 +300,8 @@ def excitation_rotations(excitations, first_param: int = 0):
         idx = first_param + pos
         word = excitation_ops(exc)
         dag = [(q, not c) for q, c in reversed(word)]
-        poly = word_pauli(word)
-        for k, v in word_pauli(dag).items():
+        poly = word_pauli(word, ladder)
+        for k, v in word_pauli(dag, ladder).items():
             poly[k] = poly.get(k, 0) - v
         strings = []
         for (x, z), g in poly.items():

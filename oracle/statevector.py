@@ -73,6 +73,14 @@ def _backward(psi_r, psi_l, rx, rz, rphi):
     return g
 
 
+def rotation_pool_gradients(psi: np.ndarray, hx, hz, hc, px, pz) -> np.ndarray:
+    """Screening of Pauli rotations appended after the circuit (the Pauli
+    entanglers of Section 5.1 with ADAPT): for ``R(P, tau)`` at tau = 0,
+    ``dE/dtau = Im <H psi|P psi>`` (from ``dR/dtau = -i P / 2`` at 0)."""
+    hpsi = apply_hamiltonian(psi, hx, hz, hc)
+    return np.array([np.vdot(hpsi, pauli.apply(psi, int(x), int(z))).imag for x, z in zip(px, pz)])
+
+
 def deflated_energy(psi: np.ndarray, hx, hz, hc, proj, alphas) -> float:
     """Eq. 12: ``<psi|H_eff|psi>`` with ``H_eff = H + sum_j alpha_j
     |Psi_j><Psi_j|`` (the lower states Psi_j as given), for a unit psi."""

@@ -93,3 +93,65 @@ def test_uccgsd_vqe_reaches_the_exact_ground_state_at_4_qubits():
         return e(th), np.array([(e(th + 1e-6 * eye[k]) - e(th - 1e-6 * eye[k])) / 2e-6 for k in range(len(th))])
     best = min(vqe(fg, uniform_amplitudes(len(seq), 1.0, s))["energy"] for s in range(3))
     assert abs(best - e0) < 1e-9
+
+
+def dense_raise(n, j):
+    """|1><0| on qubit j of n (qubit q = bit q of the index), by Kronecker
+    products; independent of the Pauli algebra."""
+    up = np.array([[0.0, 0.0], [1.0, 0.0]])
+    m = np.array([[1.0]])
+    for q in range(n - 1, -1, -1):
+        m = np.kron(m, up if q == j else np.eye(2))
+    return m
+
+
+@pytest.mark.parametrize("n", [4, 5])
+def test_qubit_excitation_rotations_equal_the_dense_exponential(n):
+    from scipy.linalg import expm
+    singles = [(i, a) for i, a in itertools.combinations(range(n), 2)]
+    doubles = [(i, j, a, b) for i, j, a, b in itertools.permutations(range(n), 4) if i < j and a < b][:6]
+    seq = singles[:5] + doubles
+    theta = uniform_amplitudes(len(seq), 0.6, 1500 + n)
+    rots = fermion.qubit_excitation_rotations(seq)
+    rng = np.random.default_rng(n)
+    psi = rng.normal(size=1 << n) + 1j * rng.normal(size=1 << n)
+    got = sv.apply_rotations(psi.copy(), [r[0] for r in rots], [r[1] for r in rots],
+                             [r[3] * theta[r[2]] for r in rots])
+    ref = psi.copy()
+    for t, exc in zip(theta, seq):
+        if len(exc) == 2:
+            i, a = exc
+            T = dense_raise(n, a) @ dense_raise(n, i).T
+        else:
+            i, j, a, b = exc
+            T = dense_raise(n, a) @ dense_raise(n, b) @ dense_raise(n, j).T @ dense_raise(n, i).T
+        ref = expm(t * (T - T.T)) @ ref
+    assert np.abs(got - ref).max() < 1e-12
+    # no Jordan-Wigner tails: every string lives on the excitation's qubits
+    for (x, z, p, _), exc in zip(rots, [seq[r[2]] for r in rots]):
+        sup = sum(1 << q for q in exc)
+        assert x == sup and (z & ~sup) == 0
+
+
+def test_rotation_pool_gradient_equals_finite_difference():
+    n, ne = 6, 2
+    h, eri = synthetic_integrals(n, 616)
+    terms = fermion.jw_hamiltonian(h, eri)
+    hx, hz, hc = [k[0] for k in terms], [k[1] for k in terms], list(terms.values())
+    s, d = fermion.uccsd_excitations(n, ne)
+    rots = fermion.excitation_rotations(s + d)
+    theta = uniform_amplitudes(len(s + d), 0.3, 617)
+    psi = sv.apply_rotations(sv.basis_state(n, fermion.hf_index(ne)), [r[0] for r in rots], [r[1] for r in rots],
+                             [r[3] * theta[r[2]] for r in rots])
+    # odd-Y strings on flip masks of the Hamiltonian, and a few others
+    px = [k[0] for k in terms if k[0]][:12] + [0b110000, 0b000111]
+    pz = [x & -x for x in px]
+    g = sv.rotation_pool_gradients(psi, hx, hz, hc, px, pz)
+    dd = 1e-4
+    for k, (x, z) in enumerate(zip(px, pz)):
+        def e(t):
+            p = sv.rotate(psi, x, z, t)
+            return sv.expectation(p, hx, hz, hc)[0].real
+        fd = (-e(2 * dd) + 8 * e(dd) - 8 * e(-dd) + e(-2 * dd)) / (12 * dd)
+        assert abs(fd - g[k]) < 1e-9 + 1e-7 * abs(g[k])
+    assert np.abs(g).max() > 1e-3
