@@ -105,11 +105,13 @@ class UCCSDEvaluator:
     sweep; it is on by default for complex64 amplitudes."""
 
     def __init__(self, ham: PauliSum, rot: RotationList, n_electrons: int, dtype: str = "c128",
-                 stream=None, renormalize=None):
+                 stream=None, renormalize=None, hamiltonian: "Hamiltonian" = None):
         self.n = ham.n_qubits
         self.rot = rot
         self.hf = (1 << n_electrons) - 1
-        self.h = Hamiltonian(ham)
+        # a resident Hamiltonian may be shared (then the caller frees it)
+        self.own_h = hamiltonian is None
+        self.h = Hamiltonian(ham) if hamiltonian is None else hamiltonian
         self.psi = StateVector(self.n, dtype, stream=stream)
         self.lam = StateVector(self.n, dtype, stream=stream)
         self.renormalize = (dtype == "c64") if renormalize is None else renormalize
@@ -169,9 +171,14 @@ class UCCSDEvaluator:
         self.forward_state(theta)
         return self.psi.clone()
 
+    def free_states(self):
+        self.psi.free()
+        self.lam.free()
+
     def free(self):
-        for o in (self.psi, self.lam, self.h):
-            o.free()
+        self.free_states()
+        if self.own_h:
+            self.h.free()
 
 
 class UCCEnergy(torch.autograd.Function):

@@ -74,10 +74,11 @@ class RotationList:
         return self.dphi_dtheta * theta[self.param]
 
 
-def _expand_words(qubits: np.ndarray, create: np.ndarray, coef: np.ndarray):
+def _expand_words(qubits: np.ndarray, create: np.ndarray, coef: np.ndarray, jw: bool = True):
     """Pauli expansion of ladder words.  ``qubits``/``create`` are (W, L);
     word w is ``op[w,0] op[w,1] ... op[w,L-1]``.  Each factor is
-    ``(X_j Z_{<j} -/+ i Y_j Z_{<j}) / 2`` (creation takes the minus sign).
+    ``(X_j Z_{<j} -/+ i Y_j Z_{<j}) / 2`` (creation takes the minus sign);
+    with ``jw=False`` the qubit ladder ``(X_j -/+ i Y_j) / 2`` (no Z string).
 
     The running product is kept as ``i^ph X^x Z^z``; ``Y_j = i X_j Z_j`` adds
     one to ph and moving ``Z^z`` past ``X^{x'}`` adds ``2 |z & x'|``.  At the
@@ -94,6 +95,8 @@ def _expand_words(qubits: np.ndarray, create: np.ndarray, coef: np.ndarray):
         bit = one << q
         low = bit - one
         fx = np.concatenate([bit, bit])
+        if not jw:
+            low = np.zeros_like(bit)
         fz = np.concatenate([low, low | bit])
         fph = np.concatenate([np.zeros(len(q), np.int64), np.ones(len(q), np.int64)])
         famp = np.concatenate([np.ones(len(q)), np.where(create[:, t], -1j, 1j)])
@@ -203,6 +206,59 @@ def excitation_rotations(n_qubits: int, seq) -> RotationList:
     i-th excitation.  ``tau - tau^dag = i sum_j c_j P_j``, so the factor is
     ``prod_j R(P_j, -2 c_j theta)``; the strings of one excitation commute and
     are listed by increasing z."""
+    return _generator_rotations(n_qubits, seq, True)
+
+
+def qeb_rotations(n_qubits: int, seq) -> RotationList:
+    """Qubit-excitation-based operators (Section 5.1): as
+    ``excitation_rotations`` with the qubit ladder ``Q+_j = (X_j - i Y_j)/2``,
+    ``Q_j = (X_j + i Y_j)/2`` in place of the fermionic one, so the strings
+    carry no Jordan-Wigner Z tails (2 strings per single, 8 per double, on the
+    excitation's own qubits only)."""
+    return _generator_rotations(n_qubits, seq, False)
+
+
+def operator_of(pool: RotationList, k: int, new_param: int) -> RotationList:
+    """The rotations of pool operator (parameter) k, renumbered to new_param."""
+    sel = pool.param == k
+    return RotationList(pool.n_qubits, pool.x[sel].copy(), pool.z[sel].copy(),
+                        np.full(int(sel.sum()), new_param, dtype=np.int32), pool.dphi_dtheta[sel].copy(),
+                        new_param + 1)
+
+
+def concat_rotations(a: RotationList, b: RotationList) -> RotationList:
+    """a then b; b's parameters follow a's."""
+    return RotationList(a.n_qubits, np.concatenate([a.x, b.x]), np.concatenate([a.z, b.z]),
+                        np.concatenate([a.param, b.param + a.n_params]).astype(np.int32),
+                        np.concatenate([a.dphi_dtheta, b.dphi_dtheta]), a.n_params + b.n_params)
+
+
+def empty_rotations(n_qubits: int) -> RotationList:
+    return RotationList(n_qubits, np.zeros(0, np.uint64), np.zeros(0, np.uint64), np.zeros(0, np.int32),
+                        np.zeros(0, np.float64), 0)
+
+
+def pauli_entangler_rotations(n_qubits: int, x, z) -> RotationList:
+    """One parameter per Pauli string: ``exp(-i theta_k P_k / 2)`` in order
+    (the Pauli entanglers of Section 5.1)."""
+    x = np.ascontiguousarray(x, dtype=np.uint64)
+    z = np.ascontiguousarray(z, dtype=np.uint64)
+    k = len(x)
+    return RotationList(n_qubits, x, z, np.arange(k, dtype=np.int32), np.ones(k), k)
+
+
+def entangler_pool(ham: PauliSum, max_weight: int = 4):
+    """A Pauli-entangler pool from the Hamiltonian's flip masks: for every
+    distinct nonzero x of its strings with at most ``max_weight`` flipped
+    qubits, the string with Y on the lowest flipped qubit and X on the others
+    (an odd number of Y, so its rotation keeps real amplitudes real).
+    Returns (x, z) arrays, x ascending."""
+    xs = np.unique(np.asarray(ham.x, dtype=np.uint64))
+    xs = xs[(xs != 0) & (_popc(xs) <= max_weight)]
+    return xs, xs & (~xs + np.uint64(1))
+
+
+def _generator_rotations(n_qubits: int, seq, jw: bool) -> RotationList:
     seq = [tuple(int(v) for v in e) for e in seq]
     xs, zs, ps, ds = [], [], [], []
     for idx, exc in enumerate(seq):
@@ -215,7 +271,7 @@ def excitation_rotations(n_qubits: int, seq) -> RotationList:
         dag = [(q, not cr) for q, cr in reversed(word)]
         qub = np.array([[q for q, _ in word], [q for q, _ in dag]])
         cre = np.array([[cr for _, cr in word], [cr for _, cr in dag]])
-        x, z, c = _expand_words(qub, cre, np.array([1.0, -1.0]))
+        x, z, c = _expand_words(qub, cre, np.array([1.0, -1.0]), jw)
         x, z, c = _merge(x, z, c, n_qubits, 0.0)
         keep = np.abs(c) > 1e-14
         x, z, c = x[keep], z[keep], c[keep]

@@ -6,6 +6,11 @@ quasi-Newton optimiser driven by the adjoint gradient (Algorithm 1).
 ``UCCSDEvaluator`` (any rotation list: UCCSD, UCCGSD, ADAPT-grown) so every
 evaluation runs on the GPU; only the scalar energy and the gradient vector
 cross to the host for the optimiser.
+
+``vqd`` runs the deflation sequence of Eq. 12 and ``adapt_vqe`` grows a
+circuit from an operator pool (Section 5.1: fermionic UCCGSD, qubit-
+excitation or Pauli-entangler pools), screening the pool with one reverse
+sweep per iteration.
 """
 from __future__ import annotations
 
@@ -74,3 +79,64 @@ def vqd(evaluator, n_states: int, alpha: float, theta0s, maxiter: int = 200, gto
         out.append({"energy_eff": best["energy"], "energy": e_h, "theta": best["theta"], "state": st,
                     "n_eval": best["n_eval"], "converged": best["converged"]})
     return out
+
+
+def adapt_vqe(make_objective, screen, pool, n_qubits: int, max_ops: int = 20, grad_tol: float = 1e-6,
+              maxiter: int = 200, gtol: float = 1e-9):
+    """ADAPT-VQE (Section 5.1).  ``pool`` is a RotationList whose parameters
+    are the pool operators.  Each iteration screens the pool at the current
+    optimum (``screen(circuit, theta, pool)`` -> dE/dtheta_A of every pool
+    operator appended with amplitude 0), appends the operator of largest
+    magnitude, and re-optimises every amplitude (Eq. 9) from the previous
+    optimum with 0 for the new one; ``make_objective(circuit)`` gives the
+    (E, grad) callable.  Stops when the largest magnitude is below grad_tol
+    or after max_ops operators.  Returns the circuit, amplitudes, chosen pool
+    indices and the energy and largest screening gradient per iteration."""
+    from .problem import concat_rotations, empty_rotations, operator_of
+
+    circuit = empty_rotations(n_qubits)
+    theta = np.zeros(0)
+    chosen, energies, gmax = [], [], []
+    for _ in range(max_ops):
+        g = np.asarray(screen(circuit, theta, pool), dtype=np.float64)
+        k = int(np.argmax(np.abs(g)))
+        gmax.append(float(abs(g[k])))
+        if gmax[-1] < grad_tol:
+            break
+        chosen.append(k)
+        circuit = concat_rotations(circuit, operator_of(pool, k, 0))
+        res = vqe(make_objective(circuit), np.append(theta, 0.0), maxiter=maxiter, gtol=gtol)
+        theta = res["theta"]
+        energies.append(res["energy"])
+    return {"circuit": circuit, "theta": theta, "chosen": chosen, "energies": energies, "max_gradients": gmax}
+
+
+def gpu_adapt_vqe(ham, n_electrons: int, pool, dtype: str = "c128", **kw):
+    """adapt_vqe with every energy, gradient and pool screening on the GPU
+    (one evaluator per circuit length, all sharing one resident Hamiltonian)."""
+    from .engine import Hamiltonian, UCCSDEvaluator
+
+    h = Hamiltonian(ham)
+    cache = {}
+
+    def evaluator(circuit):
+        key = len(circuit)
+        if key not in cache:
+            for ev in cache.values():
+                ev.free_states()
+            cache.clear()
+            cache[key] = UCCSDEvaluator(ham, circuit, n_electrons, dtype, hamiltonian=h)
+        return cache[key]
+
+    def make_objective(circuit):
+        return evaluator_objective(evaluator(circuit))
+
+    def screen(circuit, theta, pool_):
+        return evaluator(circuit).pool_gradients(theta, pool_).cpu().numpy()
+
+    try:
+        return adapt_vqe(make_objective, screen, pool, ham.n_qubits, **kw)
+    finally:
+        for ev in cache.values():
+            ev.free_states()
+        h.free()

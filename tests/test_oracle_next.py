@@ -155,3 +155,21 @@ def test_rotation_pool_gradient_equals_finite_difference():
         fd = (-e(2 * dd) + 8 * e(dd) - 8 * e(-dd) + e(-2 * dd)) / (12 * dd)
         assert abs(fd - g[k]) < 1e-9 + 1e-7 * abs(g[k])
     assert np.abs(g).max() > 1e-3
+
+
+def test_adapt_loop_with_oracle_callables_reaches_the_exact_ground_state_at_4_qubits():
+    """The ADAPT loop (Section 5.1) over the generalized pool, every number
+    from the oracle: it stops on a vanishing pool gradient at the exact
+    ground-state energy."""
+    from paper_2208_10978_amd.problem import uccgsd_rotations
+    from paper_2208_10978_amd.vqe import adapt_vqe
+    from tests.adapt_oracle import oracle_callables
+    n, ne = 4, 2
+    h, eri = synthetic_integrals(n, 77)
+    basis = fermion.sector_basis(n, *fermion.electron_counts(ne))
+    e0 = np.linalg.eigvalsh(fermion.determinant_hamiltonian(h, eri, basis).toarray())[0]
+    mk, screen = oracle_callables(h, eri, n, ne)
+    res = adapt_vqe(mk, screen, uccgsd_rotations(n), n, max_ops=8, grad_tol=1e-6)
+    assert abs(res["energies"][-1] - e0) < 1e-8
+    assert res["max_gradients"][-1] < 1e-6 or len(res["chosen"]) == 8
+    assert all(b <= a + 1e-12 for a, b in zip(res["energies"], res["energies"][1:]))
