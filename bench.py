@@ -203,6 +203,78 @@ def bench_serve(n_req: int, rho: float, seed: int):
     }
 
 
+def bench_next(n: int = 20, reps: int = 3):
+    """Figures of the rows beyond the UCCSD hot path on the 20-qubit
+    configuration (10 electrons, synthetic integrals seed 1020, amplitudes
+    seed 2020, complex128): generalized (UCCGSD) and qubit-excitation
+    circuits through the same kernels, ADAPT pool screening over the UCCGSD
+    and Pauli-entangler pools, the Eq. 9 loop and the deflated (Eq. 12)
+    evaluation.  Each time is the mean of `reps` calls after one warm call."""
+    import torch
+    from paper_2208_10978_amd.engine import Hamiltonian, UCCSDEvaluator
+    from paper_2208_10978_amd.problem import (entangler_pool, excitation_rotations, jordan_wigner,
+                                              pauli_entangler_rotations, qeb_rotations, uccgsd_excitations,
+                                              uccgsd_rotations, uccsd_excitations, uccsd_rotations)
+    from paper_2208_10978_amd.vqe import evaluator_objective, vqe
+    from workloads import synthetic_integrals, uniform_amplitudes
+
+    ne = n // 2
+    h, eri = synthetic_integrals(n, 1000 + n)
+    ham = jordan_wigner(h, eri)
+    H = Hamiltonian(ham)
+    out = {"workload": f"{n} qubits, {ne} electrons, complex128, {len(ham)} Pauli strings"}
+
+    def timed(fn):
+        fn()
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for _ in range(reps):
+            fn()
+        torch.cuda.synchronize()
+        return (time.perf_counter() - t0) / reps
+
+    def eval_row(rot, label):
+        ev = UCCSDEvaluator(ham, rot, ne, "c128", hamiltonian=H)
+        th = uniform_amplitudes(rot.n_params, 0.05, 2000 + n)
+        dt = timed(lambda: ev.energy_and_grad(th))
+        ev.free_states()
+        out[label] = {"parameters": rot.n_params, "rotations": len(rot), "energy_grad_ms": 1e3 * dt,
+                      "rotations_per_s_fwd_and_rev": 2 * len(rot) / dt}
+        log(f"next: {label} {1e3 * dt:.1f} ms per energy+gradient")
+
+    s, d = uccsd_excitations(n, ne)
+    uccsd = uccsd_rotations(n, ne)
+    eval_row(uccsd, "uccsd")
+    eval_row(uccgsd_rotations(n), "uccgsd")
+    eval_row(qeb_rotations(n, s + d), "qeb")
+
+    ev = UCCSDEvaluator(ham, uccsd, ne, "c128", hamiltonian=H)
+    th = uniform_amplitudes(uccsd.n_params, 0.05, 2000 + n)
+    gs, gd = uccgsd_excitations(n)
+    pool = excitation_rotations(n, gs + gd)
+    dt = timed(lambda: ev.pool_gradients(th, pool))
+    out["adapt_screen_uccgsd_pool"] = {"operators": pool.n_params, "rotations": len(pool), "ms": 1e3 * dt,
+                                       "operators_per_s": pool.n_params / dt}
+    ent = pauli_entangler_rotations(n, *entangler_pool(ham, 4))
+    dt = timed(lambda: ev.pool_gradients(th, ent))
+    out["adapt_screen_entangler_pool"] = {"operators": ent.n_params, "ms": 1e3 * dt,
+                                          "operators_per_s": ent.n_params / dt}
+    log(f"next: pool screening {out['adapt_screen_uccgsd_pool']['ms']:.1f} ms for {pool.n_params} operators")
+
+    res = vqe(evaluator_objective(ev), np.zeros(uccsd.n_params), maxiter=10)
+    out["vqe_10_iterations"] = {"evaluations": res["n_eval"], "seconds_per_eval": res["seconds_per_eval"],
+                                "energy": res["energy"]}
+
+    lower = [ev.state(uniform_amplitudes(uccsd.n_params, 0.05, 3000 + k)) for k in range(2)]
+    dt = timed(lambda: ev.energy_and_grad_deflated(th, lower, [0.5, 0.5]))
+    out["vqd_deflated_2_states"] = {"energy_grad_ms": 1e3 * dt}
+    for st in lower:
+        st.free()
+    ev.free_states()
+    H.free()
+    return out
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -214,6 +286,7 @@ def main():
     ap.add_argument("--no-c4", action="store_true", help="skip the 32-qubit complex64 raw-sweep figures")
     ap.add_argument("--c4-rotations", type=int, default=1000)
     ap.add_argument("--no-serve", action="store_true", help="skip the served-stream figures")
+    ap.add_argument("--no-next", action="store_true", help="skip the 20-qubit figures of the pool/VQD rows")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="only run a plain 4 GiB device copy three times (calibrates HBM byte counters)")
     ap.add_argument("--serve-requests", type=int, default=40)
@@ -330,6 +403,8 @@ def main():
         result["c4"] = bench_c4(args.c4_rotations, 10_000)
     if not args.no_serve:
         result["serving"] = bench_serve(args.serve_requests, 0.8, 5151)
+    if not args.no_next:
+        result["next_rows"] = bench_next()
     if not args.no_cpu_baseline:
         log("timing the oracle sample on the host")
         result["cpu_baseline"] = cpu_baseline(n, ham, rot, theta)
