@@ -162,13 +162,13 @@ def bench_c4(n_rot: int, n_terms: int):
     return res
 
 
-def bench_serve(n_req: int, rho: float, seed: int):
+def bench_serve(n_req: int, rhos, seed: int):
     """Served stream (continuous batching) against the one-request-at-a-time
     path on the same Poisson trace: energy + gradient requests with qubit
     counts uniform in {12, 16, 20, 24, 26}, electrons = qubits / 2, seeded
     synthetic H and UCCSD amplitudes per request, complex64 amplitudes with FP64
     reductions.  The offered rate is rho times the measured one-at-a-time
-    throughput."""
+    throughput, for each rho in rhos."""
     from paper_2208_10978_amd.serve import Request, Server, latency_stats
     from workloads import poisson_requests
 
@@ -186,21 +186,22 @@ def bench_serve(n_req: int, rho: float, seed: int):
     if any(r.error for r in alone):
         raise RuntimeError(f"serving: {[r.error for r in alone if r.error][:3]}")
     fifo_rate = n_req / span
-    rate = rho * fifo_rate
-    log(f"serving: one-at-a-time {fifo_rate:.2f} evals/s; offering {rate:.2f} requests/s")
-    srv = Server(max_slots=8)
-    mixed = srv.run(trace(rate), realtime=True)
-    fifo = Server(fifo=True).run(trace(rate), realtime=True)
-    return {
+    out = {
         "workload": f"{n_req} Poisson energy+gradient requests, qubits uniform in {{12,16,20,24,26}}, complex64, "
-                    f"offered at {rho:g} x the one-at-a-time throughput (seed {seed})",
+                    f"offered at rho x the one-at-a-time throughput (seed {seed})",
         "one_at_a_time_evals_per_s": fifo_rate,
-        "offered_requests_per_s": rate,
-        "continuous_batching": latency_stats(mixed),
-        "fifo_same_trace": latency_stats(fifo),
-        "peak_slots": srv.peak_slots,
-        "peak_hbm_bytes": srv.peak_bytes,
+        "loads": [],
     }
+    for rho in rhos:
+        rate = rho * fifo_rate
+        log(f"serving: one-at-a-time {fifo_rate:.2f} evals/s; offering {rate:.2f} requests/s (rho {rho:g})")
+        srv = Server(max_slots=8)
+        mixed = srv.run(trace(rate), realtime=True)
+        fifo = Server(fifo=True).run(trace(rate), realtime=True)
+        out["loads"].append({"rho": rho, "offered_requests_per_s": rate,
+                             "continuous_batching": latency_stats(mixed), "fifo_same_trace": latency_stats(fifo),
+                             "peak_slots": srv.peak_slots, "peak_hbm_bytes": srv.peak_bytes})
+    return out
 
 
 def bench_next(n: int = 20, reps: int = 3):
@@ -402,7 +403,7 @@ def main():
     if not args.no_c4:
         result["c4"] = bench_c4(args.c4_rotations, 10_000)
     if not args.no_serve:
-        result["serving"] = bench_serve(args.serve_requests, 0.8, 5151)
+        result["serving"] = bench_serve(args.serve_requests, (0.5, 0.8, 1.0), 5151)
     if not args.no_next:
         result["next_rows"] = bench_next()
     if not args.no_cpu_baseline:

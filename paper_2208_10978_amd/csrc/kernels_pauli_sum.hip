@@ -141,6 +141,60 @@ __device__ __forceinline__ void walk_fast_items(const BlobView& bv, uint32_t i0,
   }
 }
 
+// The folded part B(base)[record] of every factored group (see TGroup): the
+// wavefront w takes the factored groups with index w mod NW (uniform loops,
+// tables through scalar loads) and leaves one FP64 complex per record in LDS.
+template <int NW>
+__device__ __forceinline__ void factored_base(const BlobView& bv, uint32_t n_groups, uint64_t base, int wave,
+                                              int lane, double2* fB) {
+  for (uint32_t gi = 0; gi < n_groups; ++gi) {
+    const uint32_t fi = bv.groups[gi].fact_idx;
+    if (fi == ~0u || int(fi % uint32_t(NW)) != wave) continue;
+    const TGroup g = bv.groups[gi];
+    for (uint32_t r = 0; r < g.n_rec; ++r) {
+      double br = 0.0, bi = 0.0;
+      for (uint32_t k = g.n_in; k < g.n_sub; ++k) {
+        const unsigned sg = __popcll(base & bv.subs[g.sub_off + k].w_out);
+        const double2 cv = bv.coef[g.coef_off + k * g.n_rec + r];
+        br += signed_by(cv.x, sg);
+        bi += signed_by(cv.y, sg);
+      }
+      if (lane == 0) fB[fi * kFactRecs + r] = make_double2(br, bi);
+    }
+  }
+}
+
+// G(m) of a general group at the pair whose m' has frame-local bits lmp.
+__device__ __forceinline__ void general_g(const BlobView& bv, const TGroup& g, uint32_t r, uint32_t lmp,
+                                          uint64_t base, const double2* fB, double& gre, double& gim) {
+  gre = 0.0;
+  gim = 0.0;
+  if (g.fact_idx != ~0u) {
+    const double2 b0 = fB[g.fact_idx * kFactRecs + r];
+    gre = b0.x;
+    gim = b0.y;
+#pragma unroll 4
+    for (uint32_t k = 0; k < g.n_in; ++k) {
+      const unsigned sg = __popc(lmp & bv.subs[g.sub_off + k].w_loc);
+      const double2 cv = bv.coef[g.coef_off + k * g.n_rec + r];
+      gre += signed_by(cv.x, sg);
+      gim += signed_by(cv.y, sg);
+    }
+    const unsigned s0 = __popc(lmp & g.w0_loc) + __popcll(base & g.w0_out);
+    gre = signed_by(gre, s0);
+    gim = signed_by(gim, s0);
+    return;
+  }
+#pragma unroll 4
+  for (uint32_t k = 0; k < g.n_sub; ++k) {
+    const TSub sd = bv.subs[g.sub_off + k];
+    const double2 cv = bv.coef[g.coef_off + k * g.n_rec + r];
+    const unsigned sg = __popc(lmp & sd.w_loc) + __popcll(base & sd.w_out);
+    gre += signed_by(cv.x, sg);
+    gim += signed_by(cv.y, sg);
+  }
+}
+
 // The pairs (m', m = m' ^ x) of every record of a one-subgroup group at one
 // walk position (index part dl, slot part ds, w-parity of the lane part zp)
 // plus the uniform part rest: all loads first, then the updates.  The index
@@ -178,15 +232,20 @@ __global__ void __launch_bounds__(NT) k_tile_lambda(const T* __restrict__ psi, T
   constexpr int PER = (1 << B) / NT;
   __shared__ T tp[1 << B];
   __shared__ double tlr[1 << B], tli[1 << B];
+  __shared__ double2 fB[kMaxFactored * kFactRecs];
   const BlobView bv(blob);
   const int lane = threadIdx.x & 63;
   const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
   uint32_t lbit[kWalkLaneBits];  // all ones where the lane index has bit i
 #pragma unroll
   for (int i = 0; i < kWalkLaneBits; ++i) lbit[i] = 0u - ((uint32_t(lane) >> i) & 1u);
-  const uint32_t n_groups = bv.hdr->n_groups, n_items = bv.hdr->n_fast_items;
+  const uint32_t n_groups = bv.hdr->n_groups, n_items = bv.hdr->n_fast_items, n_fact = bv.hdr->n_fact;
 
   auto apply_groups = [&](uint64_t base) {
+    if (n_fact) {
+      factored_base<NW>(bv, n_groups, base, wave, lane, fB);
+      __syncthreads();
+    }
     // groups with several subgroups: every thread of the block takes pairs
     // (record, position of the free bits), G(m) summed over the subgroups
     for (uint32_t gi = 0; gi < n_groups; ++gi) {
@@ -196,15 +255,8 @@ __global__ void __launch_bounds__(NT) k_tile_lambda(const T* __restrict__ psi, T
       auto pair = [&](uint32_t r, uint32_t t) {
         const uint32_t lmp = insert_zeros32_p4(t, g.sins_pack, g.n_sins) | bv.recs[g.rec_off + r];
         const uint32_t lm = lmp ^ g.x_loc;
-        double gre = 0.0, gim = 0.0;  // G(m)
-#pragma unroll 4
-        for (uint32_t k = 0; k < g.n_sub; ++k) {
-          const TSub sd = bv.subs[g.sub_off + k];
-          const double2 cv = bv.coef[g.coef_off + k * g.n_rec + r];
-          const unsigned sg = __popc(lmp & sd.w_loc) + __popcll(base & sd.w_out);
-          gre += signed_by(cv.x, sg);
-          gim += signed_by(cv.y, sg);
-        }
+        double gre, gim;  // G(m)
+        general_g(bv, g, r, lmp, base, fB, gre, gim);
         const uint32_t smp = lds_swz(lmp), sm = lds_swz(lm);
         const T pm = tp[sm], pp = tp[smp];
         lds_add(&tlr[sm], gre * (double)pp.x - gim * (double)pp.y);  // lam[m] += G psi[m']
@@ -382,15 +434,20 @@ __global__ void __launch_bounds__(NT) k_tile_expect(const T* __restrict__ psi, F
   constexpr int PER = (1 << B) / NT;
   __shared__ T tp[1 << B];
   __shared__ double red[NW];
+  __shared__ double2 fB[kMaxFactored * kFactRecs];
   const BlobView bv(blob);
   const int lane = threadIdx.x & 63;
   const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
   uint32_t lbit[kWalkLaneBits];
 #pragma unroll
   for (int i = 0; i < kWalkLaneBits; ++i) lbit[i] = 0u - ((uint32_t(lane) >> i) & 1u);
-  const uint32_t n_groups = bv.hdr->n_groups, n_items = bv.hdr->n_fast_items;
+  const uint32_t n_groups = bv.hdr->n_groups, n_items = bv.hdr->n_fast_items, n_fact = bv.hdr->n_fact;
   double e = 0.0;
   auto apply_groups = [&](uint64_t base) {
+    if (n_fact) {
+      factored_base<NW>(bv, n_groups, base, wave, lane, fB);
+      __syncthreads();
+    }
     for (uint32_t gi = 0; gi < n_groups; ++gi) {
       const TGroup g = bv.groups[gi];
       const int ns = int(fr.b) - int(g.n_sins);
@@ -398,15 +455,8 @@ __global__ void __launch_bounds__(NT) k_tile_expect(const T* __restrict__ psi, F
       auto pair = [&](uint32_t r, uint32_t t) {
         const uint32_t l2 = insert_zeros32_p4(t, g.sins_pack, g.n_sins) | bv.recs[g.rec_off + r];  // m'
         const uint32_t l = l2 ^ g.x_loc;
-        double gre = 0.0, gim = 0.0;  // G(m)
-#pragma unroll 4
-        for (uint32_t k = 0; k < g.n_sub; ++k) {
-          const TSub sd = bv.subs[g.sub_off + k];
-          const double2 cv = bv.coef[g.coef_off + k * g.n_rec + r];
-          const unsigned sg = __popc(l2 & sd.w_loc) + __popcll(base & sd.w_out);
-          gre += signed_by(cv.x, sg);
-          gim += signed_by(cv.y, sg);
-        }
+        double gre, gim;  // G(m)
+        general_g(bv, g, r, l2, base, fB, gre, gim);
         const T a = tp[lds_swz(l)], b = tp[lds_swz(l2)];
         const double gbr = gre * (double)b.x - gim * (double)b.y, gbi = gre * (double)b.y + gim * (double)b.x;
         e += (double)a.x * gbr + (double)a.y * gbi;

@@ -467,6 +467,7 @@ static void pack_blob(HTiling& t, const std::vector<HGroup>& gs, const std::vect
   std::vector<TSub> ts;
   std::vector<double> co;
   std::vector<TFast> tf;
+  int n_fact = 0;
   for (int gi : members) {
     const HGroup& g = gs[gi];
     if (use_fast && fast_group(g)) {
@@ -516,14 +517,47 @@ static void pack_blob(HTiling& t, const std::vector<HGroup>& gs, const std::vect
     std::vector<uint32_t> rec_loc(NR);
     for (int r = 0; r < NR; ++r) rec_loc[r] = g.enumerated ? uint32_t(compress(g.rec_v[r], qmask)) : smask;
     for (int r = 0; r < NR; ++r) to.push_back(rec_loc[r]);
-    for (size_t w = 0; w < g.w.size(); ++w) {
+    auto push_sub = [&](size_t w, uint32_t w_loc, uint64_t w_out) {
       TSub sd{};
-      sd.w_loc = uint32_t(compress(g.w[w] & qmask, qmask));
-      sd.w_out = g.w[w] & ~qmask;
+      sd.w_loc = w_loc;
+      sd.w_out = w_out;
       ts.push_back(sd);
       for (int r = 0; r < NR; ++r) {
         co.push_back(g.t_re[w * NR + r]);
         co.push_back(g.t_im[w * NR + r]);
+      }
+    };
+    // factor when a reference mask w0 leaves every d_k = w_k ^ w0 with at
+    // most one bit (worth it from three subgroups on)
+    int ref = -1;
+    if (n_fact < kMaxFactored && NR <= kFactRecs && g.w.size() >= 3) {
+      for (size_t a = 0; a < g.w.size() && ref < 0; ++a) {
+        bool ok = true;
+        for (uint64_t w : g.w)
+          if (popc(w ^ g.w[a]) > 1) {
+            ok = false;
+            break;
+          }
+        if (ok) ref = int(a);
+      }
+    }
+    d.fact_idx = ~0u;
+    if (ref < 0) {
+      for (size_t w = 0; w < g.w.size(); ++w)
+        push_sub(w, uint32_t(compress(g.w[w] & qmask, qmask)), g.w[w] & ~qmask);
+    } else {
+      const uint64_t w0 = g.w[size_t(ref)];
+      d.fact_idx = uint32_t(n_fact++);
+      d.w0_loc = uint32_t(compress(w0 & qmask, qmask));
+      d.w0_out = w0 & ~qmask;
+      for (size_t w = 0; w < g.w.size(); ++w) {
+        const uint64_t dk = g.w[w] ^ w0;
+        if (dk & qmask) push_sub(w, uint32_t(compress(dk, qmask)), 0);
+      }
+      d.n_in = uint32_t(ts.size() - d.sub_off);
+      for (size_t w = 0; w < g.w.size(); ++w) {
+        const uint64_t dk = g.w[w] ^ w0;
+        if (!(dk & qmask)) push_sub(w, 0, dk);
       }
     }
     tg.push_back(d);
@@ -531,6 +565,7 @@ static void pack_blob(HTiling& t, const std::vector<HGroup>& gs, const std::vect
   auto align16 = [](size_t v) { return (v + 15) & ~size_t(15); };
   TileHdr h{};
   h.n_groups = uint32_t(tg.size());
+  h.n_fact = uint32_t(n_fact);
   size_t off = sizeof(TileHdr) + tg.size() * sizeof(TGroup);
   h.off_rec = uint32_t(align16(off));
   off = h.off_rec + to.size() * sizeof(uint32_t);

@@ -173,8 +173,20 @@ struct alignas(16) TileHdr {
   uint32_t off_fast;   // byte offset of the TFast array
   uint32_t n_fast_items;  // work items: TFast index << 12 | block c of 64 walk positions
   uint32_t off_items;  // byte offset of the work items (uint32 each)
-  uint32_t pad[2];
+  uint32_t n_fact;     // factored groups (fact_idx 0 .. n_fact - 1)
+  uint32_t pad;
 };
+
+// Factored groups: when every subgroup mask is w_k = w0 ^ d_k with at most
+// one bit in d_k (the Jordan-Wigner hopping groups: one Z string, with or
+// without one more Z), G(m) = (-1)^{|m' & w0|} (B(base) + sum_in T_k
+// (-1)^{|m' & d_k|}): the subgroups whose d_k lies outside the frame (or is
+// empty) fold into B, one uniform value per tile-block and record, and only
+// the frame-local d_k stay in the per-pair sum.  Their TSub entries come
+// first (w_loc = the d_k bit, w_out = 0), then the folded ones (w_loc = 0,
+// w_out = the d_k bit or 0).
+constexpr int kMaxFactored = 64;  // per blob
+constexpr int kFactRecs = 4;
 
 // Every field is a full 32 or 64 bits: a kernel reading these tables from
 // global memory with a uniform index then gets scalar loads (a sub-dword
@@ -190,6 +202,11 @@ struct alignas(8) TGroup {
   uint32_t coef_off;   // first coefficient: coef[coef_off + sub * n_rec + rec]
   uint32_t n_sins;     // zero insertions (S', ascending) for pairs
   uint64_t sins_pack;  // their frame-local positions, four bits each
+  uint32_t fact_idx;   // factored group index, or ~0u
+  uint32_t n_in;       // factored: subgroups with a frame-local d_k (first n_in TSub)
+  uint32_t w0_loc;     // factored: w0, frame-local bits
+  uint32_t pad;
+  uint64_t w0_out;     // factored: w0, global bits outside the frame
 };
 
 // A group with one subgroup and at most four records, in one self-contained

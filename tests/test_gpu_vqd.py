@@ -92,3 +92,32 @@ def test_vqd_reaches_the_two_lowest_energies_at_4_qubits():
     for r in res:
         r["state"].free()
     ev.free()
+
+
+def test_deflated_call_rejects_bad_deflation_lists():
+    """Validation is synchronous: bad lists raise and leave psi untouched."""
+    from paper_2208_10978_amd import binding as B
+    announce("deflated call error paths")
+    n, ne = 6, 2
+    h, eri = synthetic_integrals(n, 4500)
+    s, d = fermion.uccsd_excitations(n, ne)
+    ev = UCCSDEvaluator(jordan_wigner(h, eri), excitation_rotations(n, s + d), ne, "c128")
+    theta = uniform_amplitudes(ev.rot.n_params, 0.1, 4501)
+    ok = device_state(random_unit(n, 4502), "c128")
+    other = device_state(random_unit(n + 1, 4503), "c128")
+    ev.forward_state(theta)
+    before = ev.psi.amps.clone()
+    phi = ev.rot.angles(theta)
+
+    def call(proj, alphas):
+        B.sv_adjoint_grad_params_deflated(ev.psi.handle, ev.lam.handle, ev.h.handle, [p.handle for p in proj], alphas,
+                                          ev.rot.x, ev.rot.z, phi, ev.rot.param, ev.rot.dphi_dtheta,
+                                          ev.rot.n_params, ev.energy_buf, None, ev.grad_buf)
+    for proj, alphas in [([ok] * 9, [1.0] * 9), ([ev.psi], [1.0]), ([other], [1.0]), ([ok], [float("nan")])]:
+        with pytest.raises(B.Q2svError):
+            call(proj, alphas)
+    torch.cuda.synchronize()
+    assert torch.equal(ev.psi.amps, before)
+    for st in (ok, other):
+        st.free()
+    ev.free()
