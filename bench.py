@@ -293,7 +293,7 @@ def main():
     ap.add_argument("--serve-requests", type=int, default=40)
     args = ap.parse_args()
     if args.gpus != 1:
-        print(json.dumps({"error": "this build runs on one GPU only; --gpus must be 1"}))
+        print(json.dumps({"error": "q2sv runs on one GPU: --gpus must be 1 (the sharded design is described, not built)"}))
         sys.exit(2)
 
     import torch
