@@ -77,20 +77,22 @@ def cpu_baseline(n, ham, rot, theta):
     one rotation, one Pauli-string application and one inner product on a
     2^n state, then scale to the operation counts of one energy + gradient
     evaluation by Algorithm 1 as the oracle performs it."""
-    os.environ.setdefault("OMP_NUM_THREADS", "1")
+    from threadpoolctl import threadpool_limits
+
     from oracle import pauli as op
     from oracle import statevector as osv
-    psi = osv.basis_state(n, (1 << (n // 2)) - 1)
-    x, z = int(rot.x[0]), int(rot.z[0])
-    t0 = time.perf_counter()
-    psi = osv.rotate(psi, x, z, 0.01)
-    t_rot = time.perf_counter() - t0
-    t0 = time.perf_counter()
-    lam = float(ham.c[0]) * op.apply(psi, int(ham.x[0]), int(ham.z[0]))
-    t_term = time.perf_counter() - t0
-    t0 = time.perf_counter()
-    np.vdot(lam, psi)
-    t_dot = time.perf_counter() - t0
+    with threadpool_limits(limits=1):  # one thread for BLAS/OpenMP pools too
+        psi = osv.basis_state(n, (1 << (n // 2)) - 1)
+        x, z = int(rot.x[0]), int(rot.z[0])
+        t0 = time.perf_counter()
+        psi = osv.rotate(psi, x, z, 0.01)
+        t_rot = time.perf_counter() - t0
+        t0 = time.perf_counter()
+        lam = float(ham.c[0]) * op.apply(psi, int(ham.x[0]), int(ham.z[0]))
+        t_term = time.perf_counter() - t0
+        t0 = time.perf_counter()
+        np.vdot(lam, psi)
+        t_dot = time.perf_counter() - t0
     R, T = len(rot), len(ham)
     # forward: R rotations; H psi: T string applications; reverse: per
     # rotation two inverse rotations, one rotation and one string application
