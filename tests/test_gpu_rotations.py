@@ -84,3 +84,31 @@ def test_rotation_list_validation():
     with pytest.raises(B.Q2svError):
         s.apply_rotations(np.array([1], dtype=np.uint64), np.array([0], dtype=np.uint64), [np.nan])
     s.apply_rotations(np.array([], dtype=np.uint64), np.array([], dtype=np.uint64), [])
+
+
+@pytest.mark.parametrize("n", [5, 15])
+@pytest.mark.parametrize("dtype", ["c128", "c64"])
+def test_degenerate_rotations(n, dtype):
+    """The identity string (a global phase), phi = 0 and 2 pi (R = I and -I), a
+    rotation followed by its inverse, the same string repeated, and a run of
+    more same-x strings than one fused run holds (9 > 8) so the planner splits
+    it; against the oracle, one call."""
+    announce(f"degenerate rotations n={n} {dtype}")
+    rng = np.random.default_rng(900 + n)
+    xa, za = int(rng.integers(1, 1 << n)), int(rng.integers(0, 1 << n))
+    xs, zs, ph = [0, xa, xa, xa, xa, 0], [0, za, za, za, za, 5 % (1 << n)], [0.7, 0.0, 2 * np.pi, 0.3, -0.3, 1.1]
+    xs += [xa] * 3; zs += [za] * 3; ph += [0.2, 0.2, 0.2]
+    xb = int(rng.integers(1, 1 << n))
+    for k in range(9):
+        xs.append(xb); zs.append(int(rng.integers(0, 1 << n))); ph.append(float(rng.uniform(-1, 1)))
+    x = np.array(xs, dtype=np.uint64); z = np.array(zs, dtype=np.uint64)
+    v0 = random_state_tensor(n, 31 + n, dtype)
+    s = StateVector(n, dtype)
+    s.amps.copy_(torch.from_numpy(v0).to(s.amps.dtype))
+    s.apply_rotations(x, z, ph)
+    torch.cuda.synchronize()
+    got = to_np_state(s.amps)
+    want = osv.apply_rotations(v0.copy(), x, z, ph)
+    tol = 1e-12 if dtype == "c128" else 2e-5
+    assert np.abs(got - want).max() < tol
+    s.free()
