@@ -119,7 +119,11 @@ int sv_adjoint_grad_params(sv_state *psi, sv_state *lam, const sv_pauli *hp, con
                            int64_t n_params, double *energy_dev, double *grad_theta_dev);
 
 /* Resident Pauli sums: group and upload once, then evaluate many times.
- * The handle holds device memory on the device current at creation. */
+ * The handle holds device memory on the device current at creation.  Its
+ * device tables are built on first use (under a per-handle lock; the
+ * diagonal vector on the first caller's stream, which later callers on
+ * other streams wait for), so one handle may serve states on several
+ * streams and host threads. */
 int sv_hamiltonian_create(int n_qubits, const sv_pauli *p, const double *coef, int64_t n_terms,
                           sv_hamiltonian **out);
 int sv_hamiltonian_free(sv_hamiltonian *h);

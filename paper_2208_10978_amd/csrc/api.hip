@@ -222,7 +222,9 @@ struct sv_hamiltonian {
   bool built[2][2] = {{false, false}, {false, false}};
   DevBuf diag_dev;                   // resident diagonal d[m], FP64, 2^n entries
   bool diag_built = false;
+  hipEvent_t diag_ready = nullptr;   // recorded after the diagonal's build
   int device = 0;
+  std::mutex mu;                     // the lazy builds (tilings, diagonal) of a shared handle
 };
 
 static int num_cus() {
@@ -236,6 +238,7 @@ static int num_cus() {
 }
 
 static int tiling_get(sv_hamiltonian* h, int dtype, int role, DevTiling** out) {
+  std::lock_guard<std::mutex> lk(h->mu);
   DevTiling& t = h->tilings[dtype][role];
   if (!h->built[dtype][role]) {
     const int b = role == 0 ? tile_bits_one(dtype) : tile_bits_lambda(dtype);
@@ -264,13 +267,15 @@ static int tiling_get(sv_hamiltonian* h, int dtype, int role, DevTiling** out) {
   return SV_OK;
 }
 
-// The diagonal part of H as a resident FP64 vector, built once on the
-// caller's stream (8 bytes per amplitude).
+// The diagonal part of H as a resident FP64 vector, built once on the first
+// caller's stream (8 bytes per amplitude); later callers on other streams
+// wait for that build through an event.
 static int diag_get(sv_hamiltonian* h, hipStream_t st, const double** out) {
   if (h->diag_z.empty()) {
     *out = nullptr;
     return SV_OK;
   }
+  std::lock_guard<std::mutex> lk(h->mu);
   if (!h->diag_built) {
     const uint64_t n_amp = uint64_t(1) << h->n;
     const size_t tb = h->diag_z.size() * (sizeof(uint64_t) + sizeof(double));
@@ -283,8 +288,12 @@ static int diag_get(sv_hamiltonian* h, hipStream_t st, const double** out) {
     HIP_TRY(hipMemcpy(dc, h->diag_c.data(), h->diag_c.size() * sizeof(double), hipMemcpyHostToDevice));
     ProfScope prof(st, kPSmall, double(n_amp) * 8.0);
     HIP_TRY(launch_diag_build(reinterpret_cast<double*>(base), n_amp, dz, dc, int(h->diag_z.size()), st));
+    if (!h->diag_ready) HIP_TRY(hipEventCreateWithFlags(&h->diag_ready, hipEventDisableTiming));
+    HIP_TRY(hipEventRecord(h->diag_ready, st));
     h->diag_built = true;
   }
+  // a caller on another stream waits for the build (a no-op on the building stream)
+  HIP_TRY(hipStreamWaitEvent(st, h->diag_ready, 0));
   *out = static_cast<const double*>(h->diag_dev.p);
   return SV_OK;
 }
@@ -336,6 +345,7 @@ static void hamiltonian_destroy(sv_hamiltonian* h) {
   for (auto& row : h->tilings)
     for (auto& t : row) t.buf.release();
   h->diag_dev.release();
+  if (h->diag_ready) hipEventDestroy(h->diag_ready);
   delete h;
 }
 

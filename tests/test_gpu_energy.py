@@ -183,3 +183,37 @@ def test_expectation_is_bitwise_reproducible(n):
         s.apply_rotations(rx, rz, rphi)
         outs.append(s.expect_terms(hx, hz, hc).cpu().numpy().copy())
     assert all(np.array_equal(outs[0], o) for o in outs[1:])
+
+
+def test_one_hamiltonian_shared_by_states_on_two_streams():
+    """A resident Hamiltonian used first on one stream and at once on another
+    (its diagonal is built on the first): both expectations match the oracle."""
+    from paper_2208_10978_amd.engine import Hamiltonian
+    from paper_2208_10978_amd.problem import PauliSum
+    announce("shared Hamiltonian, two streams")
+    n = 14
+    hx, hz, hc = random_pauli_sum(n, 400, 4700)
+    H = Hamiltonian(PauliSum(n, np.asarray(hx, np.uint64), np.asarray(hz, np.uint64), np.asarray(hc)))
+    s1, s2 = torch.cuda.Stream(), torch.cuda.Stream()
+    vs = [np.random.default_rng(k).normal(size=1 << n) + 1j * np.random.default_rng(k + 9).normal(size=1 << n)
+          for k in (1, 2)]
+    vs = [v / np.linalg.norm(v) for v in vs]
+    states = []
+    for v, st in zip(vs, (s1, s2)):
+        with torch.cuda.stream(st):
+            s = StateVector(n, "c128", stream=st)
+            s.amps.copy_(torch.from_numpy(v))
+        states.append(s)
+    torch.cuda.synchronize()
+    outs = []
+    for s, st in zip(states, (s1, s2)):
+        with torch.cuda.stream(st):
+            outs.append(s.expect(H))
+    torch.cuda.synchronize()
+    for v, o in zip(vs, outs):
+        e, nrm = osv.expectation(v, hx, hz, hc)
+        got = o.cpu().numpy()
+        assert abs(got[0] - e.real / nrm) < 1e-10 * max(1.0, abs(e.real))
+    for s in states:
+        s.free()
+    H.free()
