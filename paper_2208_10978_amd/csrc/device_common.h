@@ -115,6 +115,16 @@ __device__ __forceinline__ double wave_sum(double v) {
   return __hiloint2double(hi, lo);
 }
 
+// Sum over each row of 16 lanes, valid in the row's last lane (15, 31, 47,
+// 63): the first four steps of wave_sum.
+__device__ __forceinline__ double row_sum(double v) {
+  v += dpp_f64<0x111, 0xf>(v);  // row_shr:1
+  v += dpp_f64<0x112, 0xf>(v);  // row_shr:2
+  v += dpp_f64<0x114, 0xf>(v);  // row_shr:4
+  v += dpp_f64<0x118, 0xf>(v);  // row_shr:8
+  return v;
+}
+
 // Sum over the block; result valid in thread 0.  `scratch` holds one double
 // per wavefront.
 template <int NT>

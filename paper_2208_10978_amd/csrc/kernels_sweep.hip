@@ -566,12 +566,13 @@ __global__ void __launch_bounds__(NT) k_tile_forward(T* __restrict__ psi, FrameD
 // ---------------------------------------------------------------------------
 // LDS tile, reverse: psi and lam tiles; runs of the pass in pass order (the
 // reverse of list order) each give their gradient factor, then are undone on
-// both.  Gradient partials per local slot are summed per wavefront in LDS
-// and written once per block: partials[slot_map[i] * nb + block].
+// both.  Gradient partials per local slot are summed per row of 16 lanes
+// in LDS (one cell per wavefront and row) and written once per block in a
+// fixed order: partials[slot_map[i] * nb + block].
 // ---------------------------------------------------------------------------
 template <int NW, int MAXS>
 struct GradAcc {
-  double v[MAXS][NW];
+  double v[MAXS][NW * 4];  // per slot: one cell per (wavefront, row of 16 lanes)
 };
 
 template <typename T, int B, int NT, int GRAD, int MAXS, bool FULL>
@@ -590,7 +591,7 @@ __global__ void __launch_bounds__(NT) k_tile_reverse(T* __restrict__ psi, T* __r
   const uint32_t lane = threadIdx.x & 63u;
   const uint32_t wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
   const LaneBits lbits(lane);
-  for (int i = threadIdx.x; i < MAXS * NW; i += NT) (&gacc.v[0][0])[i] = 0.0;
+  for (int i = threadIdx.x; i < MAXS * NW * 4; i += NT) (&gacc.v[0][0])[i] = 0.0;
   auto apply_runs = [&](uint64_t base) {
     for (int si = 0; si < n_segs; ++si) {
       const SegDesc sg = segs[si];
@@ -608,8 +609,10 @@ __global__ void __launch_bounds__(NT) k_tile_reverse(T* __restrict__ psi, T* __r
             const int nk = GRAD == 2 ? int(run.n_str) : 1;
             for (int k = 0; k < (GRAD == 2 ? kMaxRunStrings : 1); ++k) {
               if (k >= nk) break;
-              const double v = wave_sum(acc[k]);
-              if (lane == 0) lds_add(&gacc.v[h.slot + k][wave], v);  // only this wavefront adds here
+              // row sums only: the row's last lane adds into the cell of its
+              // (wavefront, row), which nothing else writes
+              const double v = row_sum(acc[k]);
+              if ((lane & 15u) == 15u) lds_add(&gacc.v[h.slot + k][wave * 4 + (lane >> 4)], v);
             }
           }
         }
@@ -682,7 +685,7 @@ __global__ void __launch_bounds__(NT) k_tile_reverse(T* __restrict__ psi, T* __r
     __syncthreads();
     for (int i = threadIdx.x; i < n_slots; i += NT) {
       double s = 0.0;
-      for (int w = 0; w < NW; ++w) s += gacc.v[i][w];
+      for (int w = 0; w < NW * 4; ++w) s += gacc.v[i][w];
       partials[uint64_t(slot_map[i]) * nb_stride + blockIdx.x] = s;
     }
   }

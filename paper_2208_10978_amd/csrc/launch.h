@@ -18,7 +18,7 @@ constexpr int kTileThreads = 512;
 constexpr int kTileRegionBits = 3;                   // 8 wavefronts own 8 regions of a segment
 constexpr int kLambdaThreads = 1024;                 // 16 wavefronts share one tile
 constexpr int kExpectThreads = 1024;                 // 16 wavefronts share one tile
-constexpr int kMaxPassSlots = 128;                   // gradient slots per reverse tile pass
+constexpr int kMaxPassSlots = 96;                    // gradient slots per reverse tile pass (24 KiB of LDS cells)
 constexpr int kMaxPassRuns = 1 << 16;                // runs per tile pass
 constexpr int kMaxPassRecs = 1 << 20;                // run records per tile pass
 constexpr uint32_t kPartialStride = 1024;            // max blocks of a gradient pass
