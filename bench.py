@@ -206,6 +206,53 @@ def bench_serve(n_req: int, rhos, seed: int):
     return out
 
 
+def bench_small(reps: int = 10):
+    """The two small UCCSD configurations: 8 qubits (integrals seed 1008,
+    amplitudes U[-0.1, 0.1] seed 2008), launch-bound, and 20 qubits (seeds
+    1020 / 2020, U[-0.05, 0.05]), whose 16 MiB complex128 state stays in the
+    on-package cache (a cache-resident rate, not an HBM fraction), in
+    complex128 and in complex64 with FP64 reductions: the complex64 energy's
+    distance from the complex128 one beside its a-priori bound
+    2 ||H||_1 P gamma u (P = fused passes, one per excitation; gamma = 4;
+    u = 2^-24)."""
+    import torch
+    from paper_2208_10978_amd.engine import UCCSDEvaluator
+    from paper_2208_10978_amd.problem import jordan_wigner, uccsd_rotations
+    from workloads import synthetic_integrals, uniform_amplitudes
+
+    def timed(fn):
+        fn()
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for _ in range(reps):
+            fn()
+        torch.cuda.synchronize()
+        return 1e3 * (time.perf_counter() - t0) / reps
+
+    out = {}
+    for n, amp in ((8, 0.1), (20, 0.05)):
+        ne = n // 2
+        h, eri = synthetic_integrals(n, 1000 + n)
+        ham = jordan_wigner(h, eri)
+        rot = uccsd_rotations(n, ne)
+        theta = uniform_amplitudes(rot.n_params, amp, 2000 + n)
+        row = {"n_qubits": n, "pauli_strings": len(ham), "parameters": rot.n_params, "rotations": len(rot)}
+        energies = {}
+        for dt in ("c128", "c64") if n == 20 else ("c128",):
+            ev = UCCSDEvaluator(ham, rot, ne, dt)
+            row[f"{dt}_energy_ms"] = timed(lambda: ev.energy(theta))
+            row[f"{dt}_energy_grad_ms"] = timed(lambda: ev.energy_and_grad(theta))
+            energies[dt] = float(ev.energy(theta)[0].item())
+            ev.free()
+        row["energy_c128"] = energies["c128"]
+        if "c64" in energies:
+            row["c64_minus_c128"] = energies["c64"] - energies["c128"]
+            row["c64_a_priori_bound"] = 2.0 * ham.one_norm() * rot.n_params * 4.0 * 2.0 ** -24
+        out[f"{n}q"] = row
+        log(f"small configs: {n} qubits done")
+    return out
+
+
 def bench_next(n: int = 20, reps: int = 3):
     """Figures of the rows beyond the UCCSD hot path on the 20-qubit
     configuration (10 electrons, synthetic integrals seed 1020, amplitudes
@@ -289,7 +336,7 @@ def main():
     ap.add_argument("--no-c4", action="store_true", help="skip the 32-qubit complex64 raw-sweep figures")
     ap.add_argument("--c4-rotations", type=int, default=1000)
     ap.add_argument("--no-serve", action="store_true", help="skip the served-stream figures")
-    ap.add_argument("--no-next", action="store_true", help="skip the 20-qubit figures of the pool/VQD rows")
+    ap.add_argument("--no-next", action="store_true", help="skip the 8- and 20-qubit figures (small configurations, pool/VQD rows)")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="only run a plain 4 GiB device copy three times (calibrates HBM byte counters)")
     ap.add_argument("--serve-requests", type=int, default=40)
@@ -407,6 +454,7 @@ def main():
     if not args.no_serve:
         result["serving"] = bench_serve(args.serve_requests, (0.5, 0.8, 1.0), 5151)
     if not args.no_next:
+        result["small_configs"] = bench_small()
         result["next_rows"] = bench_next()
     if not args.no_cpu_baseline:
         log("timing the oracle sample on the host")
