@@ -12,8 +12,10 @@ order across wavefronts is not fixed).
 
 Host-side preparation (the JW Pauli sum and the rotation list) runs in a
 thread pool ahead of admission.  ``fifo=True`` gives the one-request-at-a-
-time baseline on the same trace.  The device work is behind an executor
-(``GpuExecutor``); the scheduling logic itself is plain Python.
+time baseline on the same trace.  ``Server.start`` / ``submit`` /
+``stop`` serve requests submitted online, each resolving a Future.  The
+device work is behind an executor (``GpuExecutor``); the scheduling logic
+itself is plain Python.
 """
 from __future__ import annotations
 
@@ -126,6 +128,10 @@ class GpuExecutor:
 
 
 class Server:
+    """``run(trace)`` serves a whole trace and returns it; ``start()`` /
+    ``submit(req) -> Future[(energy, norm, grad)]`` / ``stop()`` serve
+    requests submitted online from any thread.  Both use the same loop."""
+
     def __init__(self, executor=None, hbm_budget_bytes: int | None = None, max_slots: int = 8,
                  prep_workers: int = 4, fifo: bool = False):
         self.ex = executor if executor is not None else GpuExecutor()
@@ -135,28 +141,26 @@ class Server:
         self.fifo = fifo
         self.peak_bytes = 0
         self.peak_slots = 0
+        self._thread = None
 
-    def run(self, requests, realtime: bool = True, on_done=None):
-        """Serve a trace.  With ``realtime`` a request becomes visible at its
-        arrival time (relative to the start); otherwise all are present at
-        once.  Returns the requests with results and timestamps."""
-        reqs = sorted(requests, key=lambda r: (r.t_arrival, r.rid))
-        for r in reqs:
-            if r.device_bytes() > self.budget:
-                r.error = "request can never fit the HBM budget"
-        futures = {r.rid: self.pool.submit(prepare, r) for r in reqs if r.error is None}
-        t0 = time.perf_counter()
+    # -- the loop ---------------------------------------------------------
+    def _serve(self, t0, arrivals, no_more, prep, on_done, idle_wait):
+        """``arrivals(now)`` returns the requests that became visible (they
+        must have an entry in ``prep``, their host preparation future);
+        ``no_more()`` is true once nothing else will arrive; ``on_done(r)``
+        sees every finished request (result or error); ``idle_wait(now)`` is
+        how long to sleep when nothing is waiting or running."""
         waiting: list = []
         active: list = []
         used = 0
-        nxt = 0
-        n_done = sum(1 for r in reqs if r.error is not None)
-        while n_done < len(reqs):
+        while True:
             now = time.perf_counter() - t0
-            while nxt < len(reqs) and (not realtime or reqs[nxt].t_arrival <= now):
-                if reqs[nxt].error is None:
-                    waiting.append(reqs[nxt])
-                nxt += 1
+            for r in arrivals(now):
+                if r.error is not None:
+                    r.t_done = now
+                    on_done(r)
+                else:
+                    waiting.append(r)
             for job, r in list(active):  # completions (a launch that failed fails its request alone)
                 try:
                     if not job.ready():
@@ -167,13 +171,11 @@ class Server:
                 r.t_done = time.perf_counter() - t0
                 used -= r.device_bytes()
                 active.remove((job, r))
-                n_done += 1
-                if on_done:
-                    on_done(r)
+                on_done(r)
             i = 0  # admissions
             while i < len(waiting) and len(active) < self.max_slots:
                 r = waiting[i]
-                fut = futures[r.rid]
+                fut = prep[id(r)]
                 if not fut.done() or used + r.device_bytes() > self.budget:
                     if self.fifo:
                         break
@@ -190,12 +192,121 @@ class Server:
                 except Exception as exc:  # a malformed request fails alone
                     r.error = f"{type(exc).__name__}: {exc}"
                     r.t_done = time.perf_counter() - t0
-                    n_done += 1
-            if not active and not waiting and nxt < len(reqs) and realtime:
-                time.sleep(max(0.0, min(0.01, reqs[nxt].t_arrival - (time.perf_counter() - t0))))
+                    on_done(r)
+            if not active and not waiting:
+                if no_more():
+                    return
+                time.sleep(idle_wait(time.perf_counter() - t0))
             else:
                 time.sleep(0.0002)
+
+    def _check_fits(self, r):
+        if r.device_bytes() > self.budget:
+            r.error = "request can never fit the HBM budget"
+
+    # -- a whole trace ----------------------------------------------------
+    def run(self, requests, realtime: bool = True, on_done=None):
+        """Serve a trace.  With ``realtime`` a request becomes visible at its
+        arrival time (relative to the start); otherwise all are present at
+        once.  Host preparation of every request starts at once.  Returns the
+        requests with results and timestamps."""
+        reqs = sorted(requests, key=lambda r: (r.t_arrival, r.rid))
+        prep = {}
+        for r in reqs:
+            self._check_fits(r)
+            if r.error is None:
+                prep[id(r)] = self.pool.submit(prepare, r)
+        t0 = time.perf_counter()
+        nxt = [0]
+        done = [0]
+
+        def arrivals(now):
+            out = []
+            while nxt[0] < len(reqs) and (not realtime or reqs[nxt[0]].t_arrival <= now):
+                out.append(reqs[nxt[0]])
+                nxt[0] += 1
+            return out
+
+        def finish(r):
+            done[0] += 1
+            if on_done:
+                on_done(r)
+
+        def idle_wait(now):
+            if realtime and nxt[0] < len(reqs):
+                return max(0.0, min(0.01, reqs[nxt[0]].t_arrival - now))
+            return 0.0002
+
+        self._serve(t0, arrivals, lambda: nxt[0] >= len(reqs), prep, finish, idle_wait)
         return reqs
+
+    # -- online -------------------------------------------------------------
+    def start(self):
+        """Start serving submitted requests on a background thread."""
+        import queue
+        import threading
+        if self._thread is not None:
+            raise RuntimeError("server already started")
+        self._queue = queue.Queue()
+        self._stop = threading.Event()
+        self._t0 = time.perf_counter()
+        prep, futs = {}, {}
+
+        def arrivals(now):
+            out = []
+            while True:
+                try:
+                    r, fut = self._queue.get_nowait()
+                except queue.Empty:
+                    return out
+                r.t_arrival = now
+                self._check_fits(r)
+                futs[id(r)] = fut
+                if r.error is None:
+                    prep[id(r)] = self.pool.submit(prepare, r)
+                out.append(r)
+
+        def finish(r):
+            fut = futs.pop(id(r))
+            prep.pop(id(r), None)
+            if r.error is None:
+                fut.set_result((r.energy, r.norm, r.grad))
+            else:
+                fut.set_exception(RuntimeError(r.error))
+
+        def loop():
+            self._serve(self._t0, arrivals, lambda: self._stop.is_set() and self._queue.empty(), prep, finish,
+                        lambda now: 0.001)
+            while True:  # a submit that raced with stop()
+                try:
+                    _, fut = self._queue.get_nowait()
+                except queue.Empty:
+                    break
+                fut.set_exception(RuntimeError("server stopped"))
+
+        self._thread = threading.Thread(target=loop, name="q2sv-serve", daemon=True)
+        self._thread.start()
+        return self
+
+    def submit(self, req: Request) -> cf.Future:
+        """Queue a request; the future resolves to (energy, norm, grad) or
+        raises with the request's error."""
+        if self._thread is None:
+            raise RuntimeError("call start() first")
+        if self._stop.is_set():
+            raise RuntimeError("server is stopping")
+        fut: cf.Future = cf.Future()
+        self._queue.put((req, fut))
+        return fut
+
+    def stop(self, wait: bool = True):
+        """Finish everything submitted so far, then end the loop."""
+        if self._thread is None:
+            return
+        self._stop.set()
+        if wait:
+            self._thread.join()
+            self._thread = None
 
 
 def latency_stats(reqs):

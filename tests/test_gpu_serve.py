@@ -43,3 +43,18 @@ def test_alone_equals_mix_and_oracle():
         tol = 1e-10 if r.dtype == "c128" else 1e-5
         assert abs(r.energy - e_ref) <= tol * abs(e_ref)
         assert np.abs(r.grad - g_ref).max() <= tol * 10 * max(1.0, np.abs(g_ref).max())
+
+
+def test_online_submit_on_the_gpu():
+    announce("serve online submit")
+    srv = Server(max_slots=4).start()
+    reqs = trace()[:5]
+    futs = [srv.submit(r) for r in reqs]
+    out = [f.result(timeout=120) for f in futs]
+    srv.stop()
+    for r, (e, norm, g) in zip(reqs, out):
+        alone = Server(max_slots=1).run([Request(r.rid, r.n_qubits, r.n_electrons, r.h_seed, r.theta_seed,
+                                                 0.0, r.theta_amplitude, r.dtype)], realtime=False)[0]
+        same = 1e-12 if r.dtype == "c128" else 1e-6
+        assert abs(alone.energy - e) <= same * abs(e)
+        assert np.abs(alone.grad - g).max() <= same * max(1.0, np.abs(g).max())

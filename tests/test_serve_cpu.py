@@ -123,3 +123,36 @@ def test_a_device_failure_after_launch_fails_its_request_alone():
     assert "device error" in by[2].error and by[2].t_done is not None
     assert all(by[r].error is None and by[r].energy is not None for r in (0, 1, 3, 4))
     assert ex.live == 0
+
+
+def test_online_submit_from_two_threads_matches_the_trace_results():
+    import threading
+    reqs = trace(6, gap=0.0)
+    srv = Server(FakeExecutor(device_time=0.005), max_slots=3).start()
+    futs = {}
+
+    def client(part):
+        for r in part:
+            futs[r.rid] = srv.submit(r)
+    ts = [threading.Thread(target=client, args=(reqs[k::2],)) for k in range(2)]
+    for t in ts:
+        t.start()
+    for t in ts:
+        t.join()
+    got = {rid: f.result(timeout=30) for rid, f in futs.items()}
+    srv.stop()
+    for r in trace(6, gap=0.0):
+        alone = Server(FakeExecutor(), max_slots=1).run([r], realtime=False)[0]
+        e, norm, g = got[r.rid]
+        assert e == alone.energy and np.array_equal(g, alone.grad)
+
+
+def test_online_errors_and_lifecycle():
+    import pytest
+    srv = Server(FakeExecutor(), hbm_budget_bytes=1 << 20).start()
+    big = Request(rid=1, n_qubits=20, n_electrons=10, h_seed=1, theta_seed=2)
+    with pytest.raises(RuntimeError, match="never fit"):
+        srv.submit(big).result(timeout=30)
+    srv.stop()
+    with pytest.raises(RuntimeError):
+        srv.submit(big)
