@@ -4,7 +4,9 @@
 #include <algorithm>
 #include <cmath>
 #include <cstring>
+#include <functional>
 #include <map>
+#include <unordered_map>
 
 namespace q2sv {
 
@@ -169,6 +171,103 @@ RunDesc make_run_desc(const Run& r, const RunData& d, uint64_t qmask, uint32_t s
   return rd;
 }
 
+// Rank over GF(2) of the low `bits` bits of v[0..n).
+static int low_rank(const uint32_t* v, int n, int bits) {
+  uint32_t piv[32] = {};
+  int r = 0;
+  for (int i = 0; i < n; ++i) {
+    uint32_t x = v[i] & ((1u << bits) - 1u);
+    for (int k = bits - 1; k >= 0 && x; --k) {
+      if (!((x >> k) & 1u)) continue;
+      if (!piv[k]) {
+        piv[k] = x;
+        ++r;
+        x = 0;
+      } else {
+        x ^= piv[k];
+      }
+    }
+  }
+  return r;
+}
+
+// Which free bits the lane index carries, in lane-bit order.  The LDS slots
+// of 16 consecutive lanes fall on distinct banks for 8-byte words when the
+// low four bits of the slots of lane bits 0..3 are independent over GF(2),
+// and those of 8 lanes for 16-byte words when the low three bits of the
+// slots of lane bits 0..2 are; the slot map is linear, so the first four lane
+// bits are chosen to minimise the resulting conflict degrees.  The remaining
+// lane bits are the lowest free bits left; bits past kWalkLaneBits go to the
+// walk's loop index.
+static uint32_t order_lane_bits_search(uint32_t free_bits, uint32_t (&lane_p)[kWalkLaneBits]) {
+  uint32_t cand[32];
+  int k = 0;
+  for (uint32_t m = free_bits; m; m &= m - 1) cand[k++] = m & (~m + 1u);
+  const int head = std::min(k, 4);
+  int best[4] = {0, 1, 2, 3};
+  double best_cost = 1e30;
+  int pick[4];
+  // cost of a choice: mean conflict degree of 8-byte words over 16 lanes plus
+  // half that of 16-byte words over 8 lanes
+  auto cost = [&](const int* ix) {
+    uint32_t q[4];
+    for (int i = 0; i < head; ++i) q[i] = lds_slot(cand[ix[i]]);
+    const int h3 = std::min(head, 3);
+    return double(1u << head) / double(1u << low_rank(q, head, 4)) +
+           0.5 * double(1u << h3) / double(1u << low_rank(q, h3, 3));
+  };
+  std::function<bool(int)> search = [&](int d) {
+    if (d == head) {
+      const double c = cost(pick);
+      if (c < best_cost) {
+        best_cost = c;
+        std::copy(pick, pick + head, best);
+      }
+      return best_cost <= 1.5;  // no conflicts: stop
+    }
+    for (int i = 0; i < k; ++i) {
+      bool used = false;
+      for (int j = 0; j < d; ++j) used |= pick[j] == i;
+      if (used) continue;
+      pick[d] = i;
+      if (search(d + 1)) return true;
+    }
+    return false;
+  };
+  if (head > 0) search(0);
+  int n = 0;
+  uint32_t taken = 0;
+  for (int i = 0; i < head; ++i) {
+    lane_p[n++] = cand[best[i]];
+    taken |= cand[best[i]];
+  }
+  for (int i = 0; i < k && n < kWalkLaneBits; ++i)
+    if (!(taken & cand[i])) {
+      lane_p[n++] = cand[i];
+      taken |= cand[i];
+    }
+  for (int i = n; i < kWalkLaneBits; ++i) lane_p[i] = 0;
+  return taken;
+}
+
+// The choice depends on free_bits alone; walks of one plan repeat a few
+// hundred patterns, so each thread keeps the choices it has made.
+static uint32_t order_lane_bits(uint32_t free_bits, uint32_t (&lane_p)[kWalkLaneBits]) {
+  struct Choice {
+    uint32_t lane_p[kWalkLaneBits];
+    uint32_t taken;
+  };
+  thread_local std::unordered_map<uint32_t, Choice> memo;
+  auto it = memo.find(free_bits);
+  if (it == memo.end()) {
+    Choice c;
+    c.taken = order_lane_bits_search(free_bits, c.lane_p);
+    it = memo.emplace(free_bits, c).first;
+  }
+  std::copy(it->second.lane_p, it->second.lane_p + kWalkLaneBits, lane_p);
+  return it->second.taken;
+}
+
 void set_tile_walk(RunDesc& rd, uint32_t wb_mask, int b) {
   uint32_t ins = wb_mask;
   if (rd.mode == kRunEnum) {
@@ -177,21 +276,17 @@ void set_tile_walk(RunDesc& rd, uint32_t wb_mask, int b) {
     ins |= 1u << rd.pivot;
   }
   const uint32_t all = (1u << b) - 1u;
-  uint32_t free_bits = all & ~ins;
+  const uint32_t free_bits = all & ~ins;
   rd.walk_log = uint32_t(popc(uint64_t(free_bits)));
   rd.zlane = 0;
+  uint32_t lane_p[kWalkLaneBits];
+  const uint32_t on_lanes = order_lane_bits(free_bits, lane_p);
   for (int i = 0; i < kWalkLaneBits; ++i) {
-    if (free_bits) {
-      const uint32_t p = free_bits & (~free_bits + 1u);
-      rd.dep_p[i] = p;
-      rd.dep_q[i] = lds_slot(p);
-      if (uint32_t(rd.z0_loc) & p) rd.zlane |= 1u << i;
-      free_bits &= free_bits - 1;
-    } else {
-      rd.dep_p[i] = rd.dep_q[i] = 0;
-    }
+    rd.dep_p[i] = lane_p[i];
+    rd.dep_q[i] = lane_p[i] ? lds_slot(lane_p[i]) : 0u;
+    if (uint32_t(rd.z0_loc) & lane_p[i]) rd.zlane |= 1u << i;
   }
-  rd.hi_mask = free_bits;
+  rd.hi_mask = free_bits & ~on_lanes;
 }
 
 void set_short_form(RunDesc& rd, const RunRec* recs) {
@@ -479,14 +574,14 @@ static void pack_blob(HTiling& t, const std::vector<HGroup>& gs, const std::vect
       f.w_out = g.w[0] & ~qmask;
       uint32_t free_bits = ((1u << popc(qmask)) - 1u) & ~f.sup_mask;
       f.walk_log = uint32_t(popc(uint64_t(free_bits)));
+      uint32_t lane_p[kWalkLaneBits];
+      const uint32_t on_lanes = order_lane_bits(free_bits, lane_p);
       for (int i = 0; i < kWalkLaneBits; ++i) {
-        const uint32_t p = free_bits & (~free_bits + 1u);
-        f.dep_p[i] = p;
-        f.dep_q[i] = lds_slot(p);
-        if (f.w_loc & p) f.wlane |= 1u << i;
-        free_bits &= free_bits - 1;
+        f.dep_p[i] = lane_p[i];
+        f.dep_q[i] = lds_slot(lane_p[i]);
+        if (f.w_loc & lane_p[i]) f.wlane |= 1u << i;
       }
-      f.hi_mask = free_bits;
+      f.hi_mask = free_bits & ~on_lanes;
       f.sx = lds_slot(f.x_loc);
       for (int r = 0; r < g.n_rec(); ++r) {
         f.bits[r] = g.enumerated ? uint32_t(compress(g.rec_v[r], qmask)) : f.sup_mask;
