@@ -8,7 +8,7 @@ import pytest
 import torch
 
 from oracle import fermion
-from paper_2208_10978_amd.engine import StateVector, UCCSDEvaluator
+from paper_2208_10978_amd.engine import StateVector, UCCEnergy, UCCSDEvaluator
 from paper_2208_10978_amd.problem import PauliSum, jordan_wigner, uccsd_rotations
 from tests.gpu_common import announce
 from workloads import synthetic_integrals, uccsd_excitation_order, uniform_amplitudes
@@ -71,10 +71,9 @@ def test_single_excitation_closed_form(problem, which):
     assert np.allclose(amps, [np.cos(th), 0.0, sgn * np.sin(th), 0.0], atol=1e-14)
 
 
-def test_invariants_and_finite_differences(problem):
-    """Random amplitudes: unit norm, <N> = n_e, <S_z> = 0, Var(N) = 0, the
-    reverse sweep returns psi to |HF>, and the adjoint gradient agrees with a
-    4-point finite difference of the GPU energy on 4 seeded parameters."""
+def test_invariants_and_return_to_hf(problem):
+    """Random amplitudes: unit norm, <N> = n_e, <S_z> = 0, Var(N) = 0, and the
+    reverse sweep returns psi to |HF>."""
     announce("28q random theta")
     ev = problem["ev"]
     theta = uniform_amplitudes(ev.rot.n_params, 0.02, 2000 + N)
@@ -97,14 +96,27 @@ def test_invariants_and_finite_differences(problem):
     assert abs(sz[0]) < 1e-10
     assert abs(n2[0] - NE * NE) < 1e-8
 
-    e0, g = ev.energy_and_grad(theta)
-    g = g.cpu().numpy().copy()
+    ev.energy_and_grad(theta)
     back = ev.psi.amplitudes([problem["hf"]]).cpu().numpy()
     assert abs(back[0] - 1.0) < 1e-12 and abs(back[1]) < 1e-12
-    rng = np.random.default_rng(3000 + N)
-    picks = rng.choice(ev.rot.n_params, size=4, replace=False)
+
+
+@pytest.mark.parametrize("half", [0, 1])
+def test_gradient_finite_differences(problem, half):
+    """The adjoint gradient (Algorithm 1, through the autograd Function's
+    backward) against a 4-point central difference of the GPU energy on 20
+    seeded random parameters, ten per case, at theta ~ U[-0.02, 0.02]."""
+    announce(f"28q finite differences, half {half}")
+    ev = problem["ev"]
+    theta = uniform_amplitudes(ev.rot.n_params, 0.02, 2000 + N)
+    th_t = torch.tensor(theta, dtype=torch.float64, requires_grad=True)
+    e = UCCEnergy.apply(th_t, ev)
+    e.backward()
+    g = th_t.grad.numpy().copy()
+    assert abs(e.item() - ev.energy(theta)[0].item()) <= 1e-12 * abs(e.item())
+    picks = np.random.default_rng(3000 + N).choice(ev.rot.n_params, size=20, replace=False)
     d = 1e-3
-    for p in picks:
+    for p in picks[10 * half:10 * half + 10]:
         vals = []
         for s in (2, 1, -1, -2):
             th = theta.copy()
