@@ -118,12 +118,27 @@ int sv_adjoint_grad_params(sv_state *psi, sv_state *lam, const sv_pauli *hp, con
                            const int32_t *param_of_rot, const double *dphi_dtheta,
                            int64_t n_params, double *energy_dev, double *grad_theta_dev);
 
-/* Resident Pauli sums: group and upload once, then evaluate many times.
- * The handle holds device memory on the device current at creation.  Its
- * device tables are built on first use (under a per-handle lock; the
- * diagonal vector on the first caller's stream, which later callers on
- * other streams wait for), so one handle may serve states on several
- * streams and host threads. */
+/* Resident Pauli sums (Eq. 1): group and upload once, then evaluate many
+ * times.  sv_expect_pauli_sum and sv_adjoint_grad* with host term arrays keep
+ * the grouped form of the last sum per state and reuse it when a later call
+ * passes the same terms (compared entry by entry); a resident handle makes
+ * that sharing explicit and lets several states use one copy.
+ *   sv_hamiltonian_create  p, coef: host arrays of n_terms >= 0 entries,
+ *                          copied before return; every (x | z) < 2^n_qubits,
+ *                          every coef finite; 1 <= n_qubits <= SV_MAX_QUBITS.
+ *                          Groups the terms by x on the host; the device
+ *                          tables and the FP64 diagonal vector (8 bytes per
+ *                          amplitude) are built on first use, under a
+ *                          per-handle lock, the diagonal on the first caller's
+ *                          stream, which later callers on other streams wait
+ *                          for.  One handle may serve states on several streams
+ *                          and host threads of the device current at creation.
+ *   sv_hamiltonian_free    waits for the device, then releases the handle.
+ *   sv_expect_hamiltonian  as sv_expect_pauli_sum with the resident sum (same
+ *                          n as the state).
+ *   sv_adjoint_grad_params_h  as sv_adjoint_grad_params with the resident sum.
+ * Errors as the calls they mirror; SV_EINVAL when the handle's n differs from
+ * the state's. */
 int sv_hamiltonian_create(int n_qubits, const sv_pauli *p, const double *coef, int64_t n_terms,
                           sv_hamiltonian **out);
 int sv_hamiltonian_free(sv_hamiltonian *h);

@@ -215,6 +215,8 @@ struct sv_hamiltonian {
   int n = 0;
   int64_t n_terms = 0;
   uint64_t key = 0;
+  std::vector<sv_pauli> src_p;       // the term list of a per-state cached sum (compared on reuse)
+  std::vector<double> src_c;
   std::vector<HGroup> groups;        // non-diagonal groups
   std::vector<uint64_t> diag_z;      // diagonal (x = 0) terms
   std::vector<double> diag_c;
@@ -388,7 +390,10 @@ static int get_cached_h(sv_state* s, const sv_pauli* p, const double* coef, int6
     key = fnv(p, size_t(n_terms) * sizeof(sv_pauli), key);
     key = fnv(coef, size_t(n_terms) * sizeof(double), key);
   }
-  if (s->cached_h && s->cached_h->key == key && s->cached_h->n_terms == n_terms) {
+  // the hash only rejects quickly; a hit is confirmed on the terms themselves
+  if (s->cached_h && s->cached_h->key == key && s->cached_h->n_terms == n_terms &&
+      (n_terms == 0 || (std::memcmp(s->cached_h->src_p.data(), p, size_t(n_terms) * sizeof(sv_pauli)) == 0 &&
+                        std::memcmp(s->cached_h->src_c.data(), coef, size_t(n_terms) * sizeof(double)) == 0))) {
     *out = s->cached_h;
     return SV_OK;
   }
@@ -400,6 +405,8 @@ static int get_cached_h(sv_state* s, const sv_pauli* p, const double* coef, int6
   rc = hamiltonian_make(s->n, p, coef, n_terms, &s->cached_h);
   if (rc) return rc;
   s->cached_h->key = key;
+  s->cached_h->src_p.assign(p, p + n_terms);
+  s->cached_h->src_c.assign(coef, coef + n_terms);
   *out = s->cached_h;
   return SV_OK;
 }

@@ -141,6 +141,7 @@ class Server:
         self.fifo = fifo
         self.peak_bytes = 0
         self.peak_slots = 0
+        self.loop_error = None  # what ended the online loop, if it failed
         self._thread = None
 
     # -- the loop ---------------------------------------------------------
@@ -259,6 +260,10 @@ class Server:
                     r, fut = self._queue.get_nowait()
                 except queue.Empty:
                     return out
+                # from here on the future cannot be cancelled; a request
+                # cancelled before the loop took it is dropped
+                if not fut.set_running_or_notify_cancel():
+                    continue
                 r.t_arrival = now
                 self._check_fits(r)
                 futs[id(r)] = fut
@@ -274,15 +279,30 @@ class Server:
             else:
                 fut.set_exception(RuntimeError(r.error))
 
-        def loop():
-            self._serve(self._t0, arrivals, lambda: self._stop.is_set() and self._queue.empty(), prep, finish,
-                        lambda now: 0.001)
-            while True:  # a submit that raced with stop()
+        def fail_queued(msg):
+            while True:
                 try:
                     _, fut = self._queue.get_nowait()
                 except queue.Empty:
                     break
-                fut.set_exception(RuntimeError("server stopped"))
+                if fut.set_running_or_notify_cancel():
+                    fut.set_exception(RuntimeError(msg))
+
+        def loop():
+            try:
+                self._serve(self._t0, arrivals, lambda: self._stop.is_set() and self._queue.empty(), prep, finish,
+                            lambda now: 0.001)
+            except BaseException as exc:  # a failure of the loop itself fails every open request
+                self._stop.set()
+                msg = f"serving loop failed: {type(exc).__name__}: {exc}"
+                for fut in list(futs.values()):
+                    if not fut.done():
+                        fut.set_exception(RuntimeError(msg))
+                futs.clear()
+                fail_queued(msg)
+                self.loop_error = exc
+                return
+            fail_queued("server stopped")  # a submit that raced with stop()
 
         self._thread = threading.Thread(target=loop, name="q2sv-serve", daemon=True)
         self._thread.start()

@@ -217,3 +217,25 @@ def test_one_hamiltonian_shared_by_states_on_two_streams():
     for s in states:
         s.free()
     H.free()
+
+
+def test_cached_sum_follows_changed_coefficients():
+    """A state keeps the grouped form of its last Pauli sum; a later call with
+    the same strings but one changed coefficient must not reuse it."""
+    announce("cached sum, changed coefficient")
+    n = 9
+    hx, hz, hc = random_pauli_sum(n, 120, 777)
+    rng = np.random.default_rng(778)
+    v = rng.normal(size=1 << n) + 1j * rng.normal(size=1 << n)
+    v /= np.linalg.norm(v)
+    s = StateVector(n, "c128")
+    s.amps.copy_(torch.from_numpy(v))
+    first = s.expect_terms(hx, hz, hc).cpu().numpy().copy()
+    hc2 = hc.copy()
+    hc2[len(hc2) // 2] += 0.25
+    second = s.expect_terms(hx, hz, hc2).cpu().numpy().copy()
+    e1, _ = osv.expectation(v, hx, hz, hc)
+    e2, _ = osv.expectation(v, hx, hz, hc2)
+    assert abs(first[0] - e1.real) < 1e-10 * max(1.0, abs(e1.real))
+    assert abs(second[0] - e2.real) < 1e-10 * max(1.0, abs(e2.real))
+    s.free()

@@ -156,3 +156,45 @@ def test_online_errors_and_lifecycle():
     srv.stop()
     with pytest.raises(RuntimeError):
         srv.submit(big)
+
+
+def test_online_cancelled_request_does_not_stop_the_loop():
+    """A future cancelled before the loop takes its request is dropped; one
+    already taken cannot be cancelled.  Either way the loop keeps serving."""
+    reqs = trace(3, gap=0.0)
+    srv = Server(FakeExecutor(device_time=0.005), max_slots=2).start()
+    a = srv.submit(reqs[0])
+    b = srv.submit(reqs[1])
+    b_cancelled = b.cancel()
+    c = srv.submit(reqs[2])
+    assert a.result(timeout=30)[2] is not None
+    assert c.result(timeout=30)[2] is not None
+    if not b_cancelled:
+        assert b.result(timeout=30)[2] is not None
+    srv.stop()
+
+
+class _BrokenExecutor(FakeExecutor):
+    """Its jobs raise from ready() with an error the loop does not expect
+    to handle per request (a BaseException outside Exception)."""
+
+    class Job(FakeExecutor.Job):
+        def ready(self):
+            raise KeyboardInterrupt("simulated")
+
+    def launch(self, req):
+        return _BrokenExecutor.Job(self, req)
+
+
+def test_online_loop_failure_fails_every_open_request():
+    import pytest
+    reqs = trace(2, gap=0.0)
+    srv = Server(_BrokenExecutor(), max_slots=2).start()
+    futs = [srv.submit(r) for r in reqs]
+    for f in futs:
+        with pytest.raises(RuntimeError, match="serving loop failed"):
+            f.result(timeout=30)
+    srv._thread.join(timeout=30)
+    assert isinstance(srv.loop_error, KeyboardInterrupt)
+    with pytest.raises(RuntimeError):
+        srv.submit(reqs[0])
