@@ -18,25 +18,10 @@ from oracle import statevector as osv
 from paper_2208_10978_amd.engine import Hamiltonian, StateVector
 from paper_2208_10978_amd.problem import PauliSum
 from tests.gpu_common import announce
+from tests.sparse_host import closure, rotate_sparse
 from workloads import random_pauli_sum, random_rotations
 
 N = 32
-
-
-def closure(m, xs):
-    out = {int(m)}
-    for x in xs:
-        out |= {v ^ int(x) for v in out}
-    return out
-
-
-def rotate_sparse(amp: dict, x, z, phi):
-    """R(P, phi) on a dict of amplitudes closed under XOR with x (the oracle's
-    convention: P|k> = i^{|x & z|} (-1)^{|k & z|} |k ^ x>)."""
-    x, z = int(x), int(z)
-    w = 1j ** (pauli.popcount(x & z) % 4)
-    c, s = np.cos(phi / 2), np.sin(phi / 2)
-    return {j: c * v - 1j * s * w * (-1) ** pauli.popcount((j ^ x) & z) * amp[j ^ x] for j, v in amp.items()}
 
 
 def test_sparse_helper_matches_the_oracle_rotation():
