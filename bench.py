@@ -146,6 +146,8 @@ def bench_c4(n_rot: int, n_terms: int):
     groups = int(np.unique(hx).shape[0])
     rot_bytes = sum(v["bytes"] for v in prof_rot.values())
     rot_ms = sum(v["ms"] for v in prof_rot.values())
+    exp_bytes = sum(v["bytes"] for v in prof_exp.values())
+    exp_ms = sum(v["ms"] for v in prof_exp.values())
     res = {
         "workload": f"{n_rot}-rotation prefix of the 10^5-rotation stream + {n_terms}-term expectation, "
                     f"{n} qubits complex64",
@@ -156,6 +158,8 @@ def bench_c4(n_rot: int, n_terms: int):
         "rotation_sweep_hbm_frac": (rot_bytes / (rot_ms / 1e3) / 1e9) / HBM_PEAK_GBS if rot_ms else None,
         "expectation_s": t_exp,
         "x_groups_per_s": groups / t_exp,
+        "expectation_GB_s": exp_bytes / (exp_ms / 1e3) / 1e9 if exp_ms else None,
+        "expectation_hbm_frac": (exp_bytes / (exp_ms / 1e3) / 1e9) / HBM_PEAK_GBS if exp_ms else None,
         "expectation_kernels": {k: {"ms": round(v["ms"], 3), "launches": v["launches"]} for k, v in prof_exp.items()},
         "norm_after": norm,
     }
@@ -402,6 +406,16 @@ def main():
     torch.cuda.synchronize()
     fwd_s = start.elapsed_time(stop) / 1e3 / reps
 
+    # a plain device copy of one state (read + write) as the attainable-bandwidth reference
+    copy_s = []
+    for _ in range(3):
+        start.record()
+        ev.lam.amps.copy_(ev.psi.amps)
+        stop.record()
+        torch.cuda.synchronize()
+        copy_s.append(start.elapsed_time(stop) / 1e3)
+    copy_gbs = 2 * ev.psi.amps.numel() * ev.psi.amps.element_size() / min(copy_s) / 1e9
+
     # dominant kernel class by time in the timed region
     dom_name, dom = max(((k, v) for k, v in prof.items() if v["bytes"] > 0), key=lambda kv: kv[1]["ms"])
     achieved = dom["bytes"] / (dom["ms"] / 1e3) / 1e9
@@ -416,6 +430,8 @@ def main():
         "kernel": dom_name,
         "avg_launch_ms": round(dom["ms"] / dom["launches"], 4),
         "launches_per_step": dom["launches"] / args.steps,
+        "copy_GB_s": round(copy_gbs, 1),
+        "frac_of_copy": round(achieved / copy_gbs, 4),
     }
     kernels = {k: {"ms_per_step": round(v["ms"] / args.steps, 3),
                    "GB_s": round(v["bytes"] / (v["ms"] / 1e3) / 1e9, 1) if v["ms"] > 0 else None,
