@@ -218,6 +218,7 @@ struct sv_hamiltonian {
   std::vector<sv_pauli> src_p;       // the term list of a per-state cached sum (compared on reuse)
   std::vector<double> src_c;
   std::vector<HGroup> groups;        // non-diagonal groups
+  bool real = true;                  // every group coefficient is real (then a real psi gives a real lambda)
   std::vector<uint64_t> diag_z;      // diagonal (x = 0) terms
   std::vector<double> diag_c;
   DevTiling tilings[2][2];           // [dtype][role: 0 expectation, 1 lambda]
@@ -334,6 +335,7 @@ static int hamiltonian_make(int n, const sv_pauli* p, const double* coef, int64_
         h->diag_c.push_back(g.t_re[w]);
       }
     } else {
+      for (double v : g.t_im) h->real &= v == 0.0;
       h->groups.push_back(std::move(g));
     }
   }
@@ -611,6 +613,25 @@ static int lambda_impl(sv_state* s, sv_state* lam, sv_hamiltonian* h, double* en
   rc = diag_get(h, s->stream, &diag);
   if (rc) return rc;
   const HTiling& ht = t->host;
+  const int gdot = dot_grid(s);
+  rc = s->small.ensure(16 * sizeof(double), s->stream);
+  if (rc) return rc;
+  rc = s->scratch.ensure((3 * size_t(gdot) + 8) * sizeof(double), s->stream);
+  if (rc) return rc;
+  double* part = static_cast<double*>(s->scratch.p);
+  double* sm = static_cast<double*>(s->small.p);
+  // with real coefficients, count psi's nonzero imaginary parts on the device;
+  // the tile kernels build a real lambda when there are none (no host wait)
+  const double* imag_count = nullptr;
+  if (h->real) {
+    {
+      ProfScope prof(s->stream, kPDot, s->bytes());
+      HIP_TRY(launch_imag_count(s->dtype, s->amps, s->amp_count(), gdot, part, s->stream));
+    }
+    ProfScope prof(s->stream, kPSmall, 0.0);
+    HIP_TRY(launch_reduce_rows(part, 0, uint32_t(gdot), 1, sm + 15, s->stream));
+    imag_count = sm + 15;
+  }
   const int T = int(ht.frames.size());
   for (int tt = 0; tt < T; ++tt) {
     const FrameDesc& fr = ht.frames[tt];
@@ -618,7 +639,8 @@ static int lambda_impl(sv_state* s, sv_state* lam, sv_hamiltonian* h, double* en
     const int grid = int(std::min<uint64_t>(n_tb, uint64_t(num_cus())));
     ProfScope prof(s->stream, kPTileHLam, (tt == 0 ? (diag ? 2.5 : 2.0) : 3.0) * s->bytes());
     const hipError_t e = launch_tile_lambda(s->dtype, tt == 0, s->amps, lam->amps, diag, fr,
-                                            dptr<uint4>(t->buf, t->o_blob) + ht.blob_off[tt], n_tb, grid, s->stream);
+                                            dptr<uint4>(t->buf, t->o_blob) + ht.blob_off[tt], n_tb, grid, imag_count,
+                                            s->stream);
     if (e != hipSuccess) return fail(SV_EDEVICE, std::string("lambda tile: ") + hipGetErrorString(e));
   }
   const int gfull = full_grid(s->amp_count() / 2);
@@ -629,13 +651,6 @@ static int lambda_impl(sv_state* s, sv_state* lam, sv_hamiltonian* h, double* en
                                            dptr<uint64_t>(t->buf, t->o_recs), s->n, gfull, nullptr, s->stream);
     if (e != hipSuccess) return fail(SV_EDEVICE, std::string("lambda group: ") + hipGetErrorString(e));
   }
-  const int gdot = dot_grid(s);
-  rc = s->small.ensure(16 * sizeof(double), s->stream);
-  if (rc) return rc;
-  rc = s->scratch.ensure((3 * size_t(gdot) + 8) * sizeof(double), s->stream);
-  if (rc) return rc;
-  double* part = static_cast<double*>(s->scratch.p);
-  double* sm = static_cast<double*>(s->small.p);
   {
     ProfScope prof(s->stream, kPDot, 2.0 * s->bytes());
     HIP_TRY(launch_dot(s->dtype, s->amps, lam->amps, nullptr, s->amp_count(), gdot, part, s->stream));

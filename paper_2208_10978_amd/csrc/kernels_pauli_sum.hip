@@ -200,39 +200,54 @@ __device__ __forceinline__ void general_g(const BlobView& bv, const TGroup& g, u
 // plus the uniform part rest: all loads first, then the updates.  The index
 // and slot of a record's m' are dl | rest | bits and ds ^ slot(rest | bits)
 // (the LDS slot map is linear).
-template <int NR, typename T>
+// REAL: psi and every coefficient are real, so lambda is real; only the real
+// parts are read and accumulated (the imaginary ones are exactly zero)
+template <int NR, bool REAL, typename T>
 __device__ __forceinline__ void fast_pairs(const FastHead& f, uint32_t ds, unsigned zp, uint32_t srest, unsigned so,
                                            const T* tp, double* tlr, double* tli) {
+  using R = typename Real<T>::type;
   uint32_t smp[NR];
   T pm[NR], pp[NR];
+  R pmx[NR], ppx[NR];
 #pragma unroll
   for (int r = 0; r < NR; ++r) {
     smp[r] = ds ^ srest ^ f.sbits[r];
-    pm[r] = tp[smp[r] ^ f.sx];
-    pp[r] = tp[smp[r]];
+    if (REAL) {
+      pmx[r] = tp[smp[r] ^ f.sx].x;
+      ppx[r] = tp[smp[r]].x;
+    } else {
+      pm[r] = tp[smp[r] ^ f.sx];
+      pp[r] = tp[smp[r]];
+    }
   }
 #pragma unroll
   for (int r = 0; r < NR; ++r) {
     const unsigned sg = zp + f.pbits[r] + so;
-    const double gre = signed_by(f.coef[2 * r], sg), gim = signed_by(f.coef[2 * r + 1], sg);
     const uint32_t sm = smp[r] ^ f.sx;
-    lds_add(&tlr[sm], gre * (double)pp[r].x - gim * (double)pp[r].y);  // lam[m] += G psi[m']
-    lds_add(&tli[sm], gre * (double)pp[r].y + gim * (double)pp[r].x);
-    lds_add(&tlr[smp[r]], gre * (double)pm[r].x + gim * (double)pm[r].y);  // lam[m'] += conj(G) psi[m]
-    lds_add(&tli[smp[r]], gre * (double)pm[r].y - gim * (double)pm[r].x);
+    if (REAL) {
+      const double gre = signed_by(f.coef[2 * r], sg);
+      lds_add(&tlr[sm], gre * (double)ppx[r]);
+      lds_add(&tlr[smp[r]], gre * (double)pmx[r]);
+    } else {
+      const double gre = signed_by(f.coef[2 * r], sg), gim = signed_by(f.coef[2 * r + 1], sg);
+      lds_add(&tlr[sm], gre * (double)pp[r].x - gim * (double)pp[r].y);  // lam[m] += G psi[m']
+      lds_add(&tli[sm], gre * (double)pp[r].y + gim * (double)pp[r].x);
+      lds_add(&tlr[smp[r]], gre * (double)pm[r].x + gim * (double)pm[r].y);  // lam[m'] += conj(G) psi[m]
+      lds_add(&tli[smp[r]], gre * (double)pm[r].y - gim * (double)pm[r].x);
+    }
   }
 }
 
-template <typename T, int B, int NT, int MODE, bool FULL>
-__global__ void __launch_bounds__(NT) k_tile_lambda(const T* __restrict__ psi, T* __restrict__ lam,
-                                                    const double* __restrict__ diag, FrameDesc fr,
-                                                    const uint4* __restrict__ blob, uint64_t n_tb) {
+// The tile passes of a lambda build, on the block's LDS arrays (tp: psi tile;
+// tlr, tli: FP64 lambda accumulator; fB: factored-group values).
+template <typename T, int B, int NT, int MODE, bool FULL, bool REAL>
+__device__ __forceinline__ void lambda_tiles(const T* __restrict__ psi, T* __restrict__ lam,
+                                             const double* __restrict__ diag, const FrameDesc& fr,
+                                             const uint4* __restrict__ blob, uint64_t n_tb, T* tp, double* tlr,
+                                             double* tli, double2* fB) {
   using R = typename Real<T>::type;
   constexpr int NW = NT / 64;
   constexpr int PER = (1 << B) / NT;
-  __shared__ T tp[1 << B];
-  __shared__ double tlr[1 << B], tli[1 << B];
-  __shared__ double2 fB[kMaxFactored * kFactRecs];
   const BlobView bv(blob);
   const int lane = threadIdx.x & 63;
   const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
@@ -258,11 +273,16 @@ __global__ void __launch_bounds__(NT) k_tile_lambda(const T* __restrict__ psi, T
         double gre, gim;  // G(m)
         general_g(bv, g, r, lmp, base, fB, gre, gim);
         const uint32_t smp = lds_swz(lmp), sm = lds_swz(lm);
-        const T pm = tp[sm], pp = tp[smp];
-        lds_add(&tlr[sm], gre * (double)pp.x - gim * (double)pp.y);  // lam[m] += G psi[m']
-        lds_add(&tli[sm], gre * (double)pp.y + gim * (double)pp.x);
-        lds_add(&tlr[smp], gre * (double)pm.x + gim * (double)pm.y);  // lam[m'] += conj(G) psi[m]
-        lds_add(&tli[smp], gre * (double)pm.y - gim * (double)pm.x);
+        if (REAL) {
+          lds_add(&tlr[sm], gre * (double)tp[smp].x);
+          lds_add(&tlr[smp], gre * (double)tp[sm].x);
+        } else {
+          const T pm = tp[sm], pp = tp[smp];
+          lds_add(&tlr[sm], gre * (double)pp.x - gim * (double)pp.y);  // lam[m] += G psi[m']
+          lds_add(&tli[sm], gre * (double)pp.y + gim * (double)pp.x);
+          lds_add(&tlr[smp], gre * (double)pm.x + gim * (double)pm.y);  // lam[m'] += conj(G) psi[m]
+          lds_add(&tli[smp], gre * (double)pm.y - gim * (double)pm.x);
+        }
       };
       if (nf >= 6) {
         // 2^nf >= 64: a wavefront's positions share one record, so its index
@@ -283,10 +303,10 @@ __global__ void __launch_bounds__(NT) k_tile_lambda(const T* __restrict__ psi, T
                       [&](const FastHead& f, uint32_t ds, unsigned zp, uint32_t srest, unsigned sgn, bool on) {
                         if (!on) return;
                         switch (f.n_rec) {
-                          case 1: fast_pairs<1>(f, ds, zp, srest, sgn, tp, tlr, tli); break;
-                          case 2: fast_pairs<2>(f, ds, zp, srest, sgn, tp, tlr, tli); break;
-                          case 3: fast_pairs<3>(f, ds, zp, srest, sgn, tp, tlr, tli); break;
-                          default: fast_pairs<4>(f, ds, zp, srest, sgn, tp, tlr, tli); break;
+                          case 1: fast_pairs<1, REAL>(f, ds, zp, srest, sgn, tp, tlr, tli); break;
+                          case 2: fast_pairs<2, REAL>(f, ds, zp, srest, sgn, tp, tlr, tli); break;
+                          case 3: fast_pairs<3, REAL>(f, ds, zp, srest, sgn, tp, tlr, tli); break;
+                          default: fast_pairs<4, REAL>(f, ds, zp, srest, sgn, tp, tlr, tli); break;
                         }
                       });
     }
@@ -322,7 +342,7 @@ __global__ void __launch_bounds__(NT) k_tile_lambda(const T* __restrict__ psi, T
       for (int i = 0; i < PER; ++i) {
         const uint32_t sl = lds_swz(threadIdx.x + uint32_t(i) * NT);
         tlr[sl] = MODE == 1 ? rd[i] * (double)rp.re[i] : (double)rl.re[i];
-        tli[sl] = MODE == 1 ? rd[i] * (double)rp.im[i] : (double)rl.im[i];
+        if (!REAL) tli[sl] = MODE == 1 ? rd[i] * (double)rp.im[i] : (double)rl.im[i];
       }
     };
     if (tb < n_tb) {
@@ -340,7 +360,7 @@ __global__ void __launch_bounds__(NT) k_tile_lambda(const T* __restrict__ psi, T
       for (int i = 0; i < PER; ++i) {
         const uint32_t sl = lds_swz(threadIdx.x + uint32_t(i) * NT);
         out.re[i] = R(tlr[sl]);
-        out.im[i] = R(tli[sl]);
+        out.im[i] = REAL ? R(0) : R(tli[sl]);
       }
       if (nx < n_tb) put();
       tile_send<T, PER, NT>(lam, ta, base, out);
@@ -379,7 +399,7 @@ __global__ void __launch_bounds__(NT) k_tile_lambda(const T* __restrict__ psi, T
         if (l < nloc) {
           const uint32_t sl = lds_swz(l);
           tlr[sl] = MODE == 1 ? rd[i] * (double)rp.re[i] : (double)rl.re[i];
-          tli[sl] = MODE == 1 ? rd[i] * (double)rp.im[i] : (double)rl.im[i];
+          if (!REAL) tli[sl] = MODE == 1 ? rd[i] * (double)rp.im[i] : (double)rl.im[i];
         }
       }
       __syncthreads();
@@ -391,11 +411,30 @@ __global__ void __launch_bounds__(NT) k_tile_lambda(const T* __restrict__ psi, T
         const uint32_t l = threadIdx.x + uint32_t(i) * NT;
         if (l < nloc) {
           const uint32_t sl = lds_swz(l);
-          lam[base | frame_deposit(lut, l)] = cmake<T>(R(tlr[sl]), R(tli[sl]));
+          lam[base | frame_deposit(lut, l)] = cmake<T>(R(tlr[sl]), REAL ? R(0) : R(tli[sl]));
         }
       }
     }
   }
+}
+
+// lambda = H psi over the tiles of one frame.  MODE 1 starts from the
+// diagonal part, MODE 2 adds to lam.  imag_count (device, may be NULL) is the
+// number of amplitudes of psi with a nonzero imaginary part, written by an
+// earlier kernel on the stream for a sum whose coefficients are all real:
+// when it is zero, lambda is real and only real parts are read and added.
+template <typename T, int B, int NT, int MODE, bool FULL>
+__global__ void __launch_bounds__(NT) k_tile_lambda(const T* __restrict__ psi, T* __restrict__ lam,
+                                                    const double* __restrict__ diag, FrameDesc fr,
+                                                    const uint4* __restrict__ blob, uint64_t n_tb,
+                                                    const double* __restrict__ imag_count) {
+  __shared__ T tp[1 << B];
+  __shared__ double tlr[1 << B], tli[1 << B];
+  __shared__ double2 fB[kMaxFactored * kFactRecs];
+  if (imag_count && *imag_count == 0.0)
+    lambda_tiles<T, B, NT, MODE, FULL, true>(psi, lam, diag, fr, blob, n_tb, tp, tlr, tli, fB);
+  else
+    lambda_tiles<T, B, NT, MODE, FULL, false>(psi, lam, diag, fr, blob, n_tb, tp, tlr, tli, fB);
 }
 
 // ---------------------------------------------------------------------------
@@ -591,25 +630,26 @@ __global__ void __launch_bounds__(256) k_group_full(const T* __restrict__ psi, T
 // ---------------------------------------------------------------------------
 template <typename T, int B, int M>
 static void tile_lambda_t(const void* psi, void* lam, const double* diag, const FrameDesc& fr, const uint4* blob,
-                          uint64_t n_tb, int grid, hipStream_t st) {
+                          uint64_t n_tb, int grid, const double* imag_count, hipStream_t st) {
   const T* p = static_cast<const T*>(psi);
   T* l = static_cast<T*>(lam);
   if (fr.b == B)
     hipLaunchKernelGGL((k_tile_lambda<T, B, kLambdaThreads, M, true>), dim3(grid), dim3(kLambdaThreads), 0, st, p,
-                       l, diag, fr, blob, n_tb);
+                       l, diag, fr, blob, n_tb, imag_count);
   else
     hipLaunchKernelGGL((k_tile_lambda<T, B, kLambdaThreads, M, false>), dim3(grid), dim3(kLambdaThreads), 0, st, p,
-                       l, diag, fr, blob, n_tb);
+                       l, diag, fr, blob, n_tb, imag_count);
 }
 
 hipError_t launch_tile_lambda(int dtype, bool first, const void* psi, void* lam, const double* diag,
-                              const FrameDesc& fr, const uint4* blob, uint64_t n_tb, int grid, hipStream_t st) {
+                              const FrameDesc& fr, const uint4* blob, uint64_t n_tb, int grid,
+                              const double* imag_count, hipStream_t st) {
   if (dtype == 0) {
-    if (first) tile_lambda_t<double2, kTileLamC128, 1>(psi, lam, diag, fr, blob, n_tb, grid, st);
-    else tile_lambda_t<double2, kTileLamC128, 2>(psi, lam, diag, fr, blob, n_tb, grid, st);
+    if (first) tile_lambda_t<double2, kTileLamC128, 1>(psi, lam, diag, fr, blob, n_tb, grid, imag_count, st);
+    else tile_lambda_t<double2, kTileLamC128, 2>(psi, lam, diag, fr, blob, n_tb, grid, imag_count, st);
   } else {
-    if (first) tile_lambda_t<float2, kTileLamC64, 1>(psi, lam, diag, fr, blob, n_tb, grid, st);
-    else tile_lambda_t<float2, kTileLamC64, 2>(psi, lam, diag, fr, blob, n_tb, grid, st);
+    if (first) tile_lambda_t<float2, kTileLamC64, 1>(psi, lam, diag, fr, blob, n_tb, grid, imag_count, st);
+    else tile_lambda_t<float2, kTileLamC64, 2>(psi, lam, diag, fr, blob, n_tb, grid, imag_count, st);
   }
   return hipGetLastError();
 }

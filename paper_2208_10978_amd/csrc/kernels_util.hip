@@ -31,6 +31,19 @@ __global__ void __launch_bounds__(256) k_dot(const T* __restrict__ a, const T* _
   if (threadIdx.x == 0) partials[2 * gridDim.x + blockIdx.x] = s2;
 }
 
+// partials[block] = how many of the block's amplitudes have a nonzero
+// imaginary part (exact in FP64 below 2^53)
+template <typename T>
+__global__ void __launch_bounds__(256) k_imag_count(const T* __restrict__ a, uint64_t n_amp,
+                                                    double* __restrict__ partials) {
+  __shared__ double red[4];
+  const uint64_t stride = uint64_t(gridDim.x) * 256;
+  double c = 0.0;
+  for (uint64_t i = uint64_t(blockIdx.x) * 256 + threadIdx.x; i < n_amp; i += stride) c += a[i].y != 0 ? 1.0 : 0.0;
+  const double s = block_sum<256>(c, red);
+  if (threadIdx.x == 0) partials[blockIdx.x] = s;
+}
+
 // out[row] = sum_{j < len} in[row * stride + j], fixed order (one block per row)
 __global__ void __launch_bounds__(256) k_reduce_rows(const double* __restrict__ in, uint64_t stride, uint32_t len,
                                                      double* __restrict__ out) {
@@ -167,6 +180,16 @@ hipError_t launch_dot(int dtype, const void* a, const void* b, const double* d, 
   else
     hipLaunchKernelGGL((k_dot<float2>), dim3(grid), dim3(256), 0, st, static_cast<const float2*>(a),
                        static_cast<const float2*>(b), d, n_amp, partials);
+  return hipGetLastError();
+}
+
+hipError_t launch_imag_count(int dtype, const void* a, uint64_t n_amp, int grid, double* partials, hipStream_t st) {
+  if (dtype == 0)
+    hipLaunchKernelGGL((k_imag_count<double2>), dim3(grid), dim3(256), 0, st, static_cast<const double2*>(a), n_amp,
+                       partials);
+  else
+    hipLaunchKernelGGL((k_imag_count<float2>), dim3(grid), dim3(256), 0, st, static_cast<const float2*>(a), n_amp,
+                       partials);
   return hipGetLastError();
 }
 

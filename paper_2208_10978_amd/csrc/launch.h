@@ -36,8 +36,14 @@ hipError_t launch_tile_reverse(int dtype, int grad, void* psi, void* lam, const 
                                const RunDesc* runs, const RunRec* recs, const SegDesc* segs, int n_segs,
                                const uint32_t* slot_map, int n_slots, double* partials, uint32_t nb_stride,
                                uint64_t n_tb, int grid, hipStream_t st);
+// imag_count: device count of psi's amplitudes with a nonzero imaginary part
+// (launch_imag_count), given only for a sum with real coefficients, or NULL;
+// when it is zero the kernels build a real lambda from real parts only
 hipError_t launch_tile_lambda(int dtype, bool first, const void* psi, void* lam, const double* diag,
-                              const FrameDesc& fr, const uint4* blob, uint64_t n_tb, int grid, hipStream_t st);
+                              const FrameDesc& fr, const uint4* blob, uint64_t n_tb, int grid,
+                              const double* imag_count, hipStream_t st);
+// partials[block] = number of the block's amplitudes with a nonzero imaginary part (grid blocks of 256)
+hipError_t launch_imag_count(int dtype, const void* a, uint64_t n_amp, int grid, double* partials, hipStream_t st);
 hipError_t launch_tile_expect(int dtype, const void* psi, const FrameDesc& fr, const uint4* blob, uint64_t n_tb,
                               int grid, double* partials, hipStream_t st);
 hipError_t launch_diag_build(double* d, uint64_t n_amp, const uint64_t* z, const double* c, int n_terms,

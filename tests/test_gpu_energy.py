@@ -4,6 +4,7 @@ import pytest
 import torch
 
 from oracle import fermion
+from oracle import pauli
 from oracle import statevector as osv
 from paper_2208_10978_amd import binding as B
 from paper_2208_10978_amd.engine import StateVector, UCCSDEvaluator, UCCEnergy
@@ -239,3 +240,41 @@ def test_cached_sum_follows_changed_coefficients():
     assert abs(first[0] - e1.real) < 1e-10 * max(1.0, abs(e1.real))
     assert abs(second[0] - e2.real) < 1e-10 * max(1.0, abs(e2.real))
     s.free()
+
+
+@pytest.mark.parametrize("case", ["real_psi_real_h", "complex_psi_real_h", "one_imag_real_h",
+                                  "real_psi_complex_h"])
+def test_lambda_real_and_complex_paths(case):
+    """lambda = H psi element by element against the oracle, for the real
+    build (psi real, every coefficient real) and the complex one (a complex
+    psi, one nonzero imaginary amplitude, or a sum with odd-Y strings).  One
+    rotation at phi = 0 leaves psi as it is, so lam returns H psi."""
+    announce(f"lambda paths: {case}")
+    n = 14
+    h, eri = synthetic_integrals(n, 1000 + n)
+    ham = jordan_wigner(h, eri)
+    hx, hz, hc = np.asarray(ham.x, np.uint64), np.asarray(ham.z, np.uint64), np.asarray(ham.c)
+    if case == "real_psi_complex_h":
+        rx_, rz_, rc_ = random_pauli_sum(n, 200, 4900)
+        odd = np.array([pauli.popcount(int(a) & int(b)) % 2 == 1 for a, b in zip(rx_, rz_)])
+        hx = np.concatenate([hx, rx_[odd]]); hz = np.concatenate([hz, rz_[odd]]); hc = np.concatenate([hc, rc_[odd]])
+    rng = np.random.default_rng(4901)
+    v = rng.normal(size=1 << n) + (1j * rng.normal(size=1 << n) if case == "complex_psi_real_h" else 0.0)
+    if case == "one_imag_real_h":
+        v = v + 0j
+        v[12345] += 1e-3j
+    v = v / np.linalg.norm(v)
+    psi = StateVector(n, "c128"); lam = StateVector(n, "c128")
+    psi.amps.copy_(torch.from_numpy(np.asarray(v, np.complex128)))
+    energy = torch.empty(2, dtype=torch.float64, device="cuda")
+    grad = torch.empty(1, dtype=torch.float64, device="cuda")
+    B.sv_adjoint_grad(psi.handle, lam.handle, hx, hz, hc, np.array([1], np.uint64), np.array([1], np.uint64),
+                      np.array([0.0]), energy, grad)
+    torch.cuda.synchronize()
+    want = osv.apply_hamiltonian(np.asarray(v, np.complex128), hx, hz, hc)
+    got = to_np_state(lam.amps)
+    scale = max(1.0, float(np.abs(hc).sum()))
+    assert np.abs(got - want).max() <= 1e-12 * scale
+    e_ref, _ = osv.expectation(np.asarray(v, np.complex128), hx, hz, hc)
+    assert abs(energy[0].item() - e_ref.real) <= 1e-12 * scale
+    psi.free(); lam.free()
