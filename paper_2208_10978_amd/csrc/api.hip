@@ -438,8 +438,9 @@ static void plan_rotations(const sv_state* s, const sv_pauli* p, const double* p
 }
 
 // Launch a plan: forward (rev = false) or reverse with gradient partials.
+// imag_count: see launch_tile_reverse (reverse sweeps only; NULL otherwise)
 static int launch_rotations(sv_state* s, sv_state* lam, const RotPlan& pl, bool rev, int grad_mode,
-                            double* partials) {
+                            double* partials, const double* imag_count = nullptr) {
   const int c = std::min(s->dtype == 0 ? 3 : 4, s->n);
   // descriptors and records of every pass, one upload
   std::vector<RunDesc> descs;
@@ -514,7 +515,7 @@ static int launch_rotations(sv_state* s, sv_state* lam, const RotPlan& pl, bool 
       else
         e = launch_tile_reverse(s->dtype, grad_mode, s->amps, lam_amps, fr, d_desc + po[i].desc0,
                                 d_recs + po[i].rec0, d_segs + po[i].seg0, po[i].nsegs, d_slot + po[i].slot0,
-                                po[i].nslots, partials, kPartialStride, n_tb, grid, s->stream);
+                                po[i].nslots, partials, kPartialStride, n_tb, grid, imag_count, s->stream);
       if (e != hipSuccess) return fail(SV_EDEVICE, std::string("tile pass launch: ") + hipGetErrorString(e));
     } else {
       const RunDesc& rd = descs[po[i].desc0];
@@ -720,6 +721,29 @@ static int adjoint_impl(sv_state* psi, sv_state* lam, sv_hamiltonian* h, const s
   const int grad_mode = param ? 1 : 2;
   RotPlan pl;
   plan_rotations(psi, rp, phi, dphi, param, n_rot, true, grad_mode, pl);
+  // every run a real rotation (omega0 odd, no diagonal run): with psi and lam
+  // real on entry they stay real, and the tile passes may take the real walk
+  // once a device count of their nonzero imaginary parts reads zero
+  bool real_runs = !pl.runs.empty();
+  for (const RunData& d : pl.data) real_runs &= d.mode != kRunDiag && (d.omega0 & 1u);
+  const double* imag_count = nullptr;
+  if (real_runs) {
+    const int g = dot_grid(psi);
+    rc = psi->scratch.ensure((2 * size_t(g) + 8) * sizeof(double), psi->stream);
+    if (rc) return rc;
+    rc = psi->small.ensure(16 * sizeof(double), psi->stream);
+    if (rc) return rc;
+    double* part = static_cast<double*>(psi->scratch.p);
+    double* sm = static_cast<double*>(psi->small.p);
+    {
+      ProfScope prof(psi->stream, kPDot, 2.0 * psi->bytes());
+      HIP_TRY(launch_imag_count(psi->dtype, psi->amps, psi->amp_count(), g, part, psi->stream));
+      HIP_TRY(launch_imag_count(lam->dtype, lam->amps, lam->amp_count(), g, part + g, psi->stream));
+    }
+    ProfScope prof(psi->stream, kPSmall, 0.0);
+    HIP_TRY(launch_reduce_rows(part, 0, uint32_t(2 * g), 1, sm + 14, psi->stream));
+    imag_count = sm + 14;
+  }
   const size_t n_slots = grad_mode == 1 ? pl.runs.size() : size_t(n_rot);
   const size_t part_n = std::max<size_t>(n_slots, 1) * kPartialStride;
   rc = lam->scratch.ensure((part_n + n_slots + 8) * sizeof(double), lam->stream);
@@ -730,7 +754,7 @@ static int adjoint_impl(sv_state* psi, sv_state* lam, sv_hamiltonian* h, const s
     ProfScope prof(psi->stream, kPSmall, 0.0);
     HIP_TRY(launch_fill_f64(partials, part_n, 0.0, psi->stream));
   }
-  rc = launch_rotations(psi, lam, pl, true, grad_mode, partials);
+  rc = launch_rotations(psi, lam, pl, true, grad_mode, partials, imag_count);
   if (rc) return rc;
   ProfScope prof(psi->stream, kPSmall, 0.0);
   if (grad_mode == 2) {

@@ -350,6 +350,27 @@ __device__ __forceinline__ double grad_w(V pa, V pb, V la, V lb, unsigned sgn, u
   return sgn ? -w : w;
 }
 
+// The same two operations for a real rotation (omega0 = 1 or 3, omega = +-i)
+// on a real pair, where every imaginary part is zero: rot_pair becomes
+// a' = c a + q b, b' = c b - q a with q = +-s, and grad_w becomes
+// +-(lam[m] psi[m'] - lam[m'] psi[m]).
+template <unsigned OM, typename R>
+__device__ __forceinline__ void rot_pair_real(R& a, R& b, R c, R s, unsigned sgn) {
+  const R ss = sgn ? -s : s;
+  const R q = OM == 1 ? ss : -ss;
+  const R na = c * a + q * b;
+  const R nb = c * b - q * a;
+  a = na;
+  b = nb;
+}
+
+template <unsigned OM, typename R>
+__device__ __forceinline__ double grad_w_real(R pa, R pb, R la, R lb, unsigned sgn) {
+  double w = (double)la * (double)pb - (double)lb * (double)pa;
+  if (OM == 3) w = -w;
+  return sgn ? -w : w;
+}
+
 // pattern index of m' (frame-local l2, block base) for kRunFull / kRunDiag
 __device__ __forceinline__ unsigned run_pattern(const RunDesc& r, uint64_t l2, uint64_t base) {
   unsigned p = 0;

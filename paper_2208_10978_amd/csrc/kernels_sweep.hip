@@ -273,32 +273,49 @@ __device__ __forceinline__ ShortHead load_head(const RunDesc& run) {
 // One record, or two (every double excitation): the records' pairs are
 // disjoint, so all LDS reads of the run leave first, then the updates, then
 // the writes; one LDS round trip per run.
-template <typename T, bool REV, int GRAD, unsigned OM, int NR>
+// REALV (reverse sweep, real rotation, psi and lam real): only the real
+// parts are read, updated and written; the imaginary parts stay zero.
+template <typename T, bool REV, int GRAD, unsigned OM, int NR, bool REALV = false>
 __device__ __forceinline__ void short_walk(const ShortHead& h, const RunDesc& run, T* tp, T* tl, uint32_t ds,
                                            unsigned sgn0, uint32_t swb, bool lane_on,
                                            double (&acc)[GRAD == 2 ? kMaxRunStrings : 1]) {
   using R = typename Real<T>::type;
+  static_assert(!REALV || (REV && (OM & 1u)), "the real walk is for real rotations in the reverse sweep");
   double w[NR];
 #pragma unroll
   for (int r = 0; r < NR; ++r) w[r] = 0.0;
   if (lane_on) {
     uint32_t s1[NR], s2[NR];
     T a[NR], b[NR], la[NR], lb[NR];
+    R ar[NR], br[NR], lar[NR], lbr[NR];
 #pragma unroll
     for (int r = 0; r < NR; ++r) {
       s2[r] = ds ^ h.sb[r] ^ swb;  // slot of m'
       s1[r] = s2[r] ^ h.sx;        // slot of m
-      a[r] = tp[s1[r]];
-      b[r] = tp[s2[r]];
-      if (REV) {
-        la[r] = tl[s1[r]];
-        lb[r] = tl[s2[r]];
+      if (REALV) {
+        ar[r] = tp[s1[r]].x;
+        br[r] = tp[s2[r]].x;
+        lar[r] = tl[s1[r]].x;
+        lbr[r] = tl[s2[r]].x;
+      } else {
+        a[r] = tp[s1[r]];
+        b[r] = tp[s2[r]];
+        if (REV) {
+          la[r] = tl[s1[r]];
+          lb[r] = tl[s2[r]];
+        }
       }
     }
 #pragma unroll
     for (int r = 0; r < NR; ++r) {
       const R c = R(h.c[r]), s = REV ? R(-h.s[r]) : R(h.s[r]);
       const unsigned sg = sgn0 ^ h.pb[r];
+      if (REALV) {
+        if (GRAD) w[r] = grad_w_real<OM>(ar[r], br[r], lar[r], lbr[r], sg);
+        rot_pair_real<OM>(lar[r], lbr[r], c, s, sg);
+        rot_pair_real<OM>(ar[r], br[r], c, s, sg);
+        continue;
+      }
       if (REV) {
         if (GRAD) w[r] = grad_w_om<OM>(a[r], b[r], la[r], lb[r], sg);
         rot_pair_om<OM>(la[r], lb[r], c, s, sg);
@@ -307,6 +324,13 @@ __device__ __forceinline__ void short_walk(const ShortHead& h, const RunDesc& ru
     }
 #pragma unroll
     for (int r = 0; r < NR; ++r) {
+      if (REALV) {
+        tp[s1[r]].x = ar[r];
+        tp[s2[r]].x = br[r];
+        tl[s1[r]].x = lar[r];
+        tl[s2[r]].x = lbr[r];
+        continue;
+      }
       tp[s1[r]] = a[r];
       tp[s2[r]] = b[r];
       if (REV) {
@@ -330,15 +354,30 @@ __device__ __forceinline__ void short_walk(const ShortHead& h, const RunDesc& ru
 // record, so each lane updates one pair of psi and one of lambda and no lane
 // idles (the forward sweep, with half the work per pair, gains nothing).  The record's constants are
 // selected per lane; the lane bits below walk_log are the walk position.
-template <typename T, bool REV, int GRAD, unsigned OM>
+template <typename T, bool REV, int GRAD, unsigned OM, bool REALV = false>
 __device__ __forceinline__ void short_walk_split(const ShortHead& h, const RunDesc& run, T* tp, T* tl, uint32_t ds,
                                                  unsigned sgn0, uint32_t swb, uint32_t lane,
                                                  double (&acc)[GRAD == 2 ? kMaxRunStrings : 1]) {
   using R = typename Real<T>::type;
+  static_assert(!REALV || (REV && (OM & 1u)), "the real walk is for real rotations in the reverse sweep");
   const bool r1 = (lane >> h.walk_log) & 1u;
   const bool lane_on = lane < (2u << h.walk_log);
   double w = 0.0;
-  if (lane_on) {
+  if (lane_on && REALV) {
+    const uint32_t s2 = ds ^ (r1 ? h.sb[1] : h.sb[0]) ^ swb;  // slot of m'
+    const uint32_t s1 = s2 ^ h.sx;                            // slot of m
+    R a = tp[s1].x, b = tp[s2].x, la = tl[s1].x, lb = tl[s2].x;
+    const R c = R(r1 ? h.c[1] : h.c[0]);
+    const R s = R(-(r1 ? h.s[1] : h.s[0]));
+    const unsigned sg = sgn0 ^ (r1 ? h.pb[1] : h.pb[0]);
+    if (GRAD) w = grad_w_real<OM>(a, b, la, lb, sg);
+    rot_pair_real<OM>(la, lb, c, s, sg);
+    rot_pair_real<OM>(a, b, c, s, sg);
+    tl[s1].x = la;
+    tl[s2].x = lb;
+    tp[s1].x = a;
+    tp[s2].x = b;
+  } else if (lane_on) {
     const uint32_t s2 = ds ^ (r1 ? h.sb[1] : h.sb[0]) ^ swb;  // slot of m'
     const uint32_t s1 = s2 ^ h.sx;                            // slot of m
     T a = tp[s1], b = tp[s2];
@@ -368,25 +407,41 @@ __device__ __forceinline__ void short_walk_split(const ShortHead& h, const RunDe
   }
 }
 
+// real: psi and lam are real (reverse sweep of a list of real rotations), so
+// a run with omega0 = 1 or 3 takes the real walk
 template <typename T, bool REV, int GRAD>
 __device__ __forceinline__ void short_run(const ShortHead& h, const RunDesc& run, T* tp, T* tl, uint64_t base,
                                           uint32_t wbits, uint32_t swb, uint32_t lane, const LaneBits& lb,
-                                          double (&acc)[GRAD == 2 ? kMaxRunStrings : 1]) {
+                                          double (&acc)[GRAD == 2 ? kMaxRunStrings : 1], bool real = false) {
   uint32_t ds = 0;
 #pragma unroll
   for (int i = 0; i < kWalkLaneBits; ++i) ds ^= lb.m[i] & h.dep_q[i];
   const unsigned sgn0 = (parity64(base & h.z0_out) ^ parity32(wbits & h.z0_loc)) ^ parity32(lane & h.zlane);
   const bool lane_on = lane < (1u << h.walk_log);
   const bool split = REV && h.n_rec == 2 && h.walk_log < uint32_t(kWalkLaneBits);
-#define Q2SV_SHORT(OMV)                                                                        \
-  if (split) short_walk_split<T, REV, GRAD, OMV>(h, run, tp, tl, ds, sgn0, swb, lane, acc);        \
-  else if (h.n_rec == 2) short_walk<T, REV, GRAD, OMV, 2>(h, run, tp, tl, ds, sgn0, swb, lane_on, acc); \
-  else short_walk<T, REV, GRAD, OMV, 1>(h, run, tp, tl, ds, sgn0, swb, lane_on, acc);
+#define Q2SV_SHORT(OMV, RV)                                                                          \
+  {                                                                                                  \
+    if (split) short_walk_split<T, REV, GRAD, OMV, RV>(h, run, tp, tl, ds, sgn0, swb, lane, acc);        \
+    else if (h.n_rec == 2) short_walk<T, REV, GRAD, OMV, 2, RV>(h, run, tp, tl, ds, sgn0, swb, lane_on, acc); \
+    else short_walk<T, REV, GRAD, OMV, 1, RV>(h, run, tp, tl, ds, sgn0, swb, lane_on, acc);                \
+  }
   switch (h.omega0 & 3u) {
-    case 0: Q2SV_SHORT(0) break;
-    case 1: Q2SV_SHORT(1) break;
-    case 2: Q2SV_SHORT(2) break;
-    default: Q2SV_SHORT(3) break;
+    case 0: Q2SV_SHORT(0, false) break;
+    case 1:
+      if constexpr (REV) {
+        if (real) Q2SV_SHORT(1, true) else Q2SV_SHORT(1, false)
+      } else {
+        Q2SV_SHORT(1, false)
+      }
+      break;
+    case 2: Q2SV_SHORT(2, false) break;
+    default:
+      if constexpr (REV) {
+        if (real) Q2SV_SHORT(3, true) else Q2SV_SHORT(3, false)
+      } else {
+        Q2SV_SHORT(3, false)
+      }
+      break;
   }
 #undef Q2SV_SHORT
 }
@@ -582,11 +637,15 @@ __global__ void __launch_bounds__(NT) k_tile_reverse(T* __restrict__ psi, T* __r
                                                      const SegDesc* __restrict__ segs, int n_segs,
                                                      const uint32_t* __restrict__ slot_map, int n_slots,
                                                      double* __restrict__ partials, uint32_t nb_stride,
-                                                     uint64_t n_tb) {
+                                                     uint64_t n_tb, const double* __restrict__ imag_count) {
   constexpr int NW = NT / 64;
   constexpr int PER = (1 << B) / NT;
   __shared__ T tp[1 << B];
   __shared__ T tl[1 << B];
+  // imag_count (device, may be NULL): nonzero imaginary parts of psi and lam,
+  // given for a list of real rotations only; zero lets real runs take the
+  // real walk (psi and lam then stay real through the whole sweep)
+  const bool real = imag_count && *imag_count == 0.0;
   __shared__ GradAcc<NW, MAXS> gacc;
   const uint32_t lane = threadIdx.x & 63u;
   const uint32_t wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
@@ -603,7 +662,7 @@ __global__ void __launch_bounds__(NT) k_tile_reverse(T* __restrict__ psi, T* __r
 #pragma unroll
           for (int k = 0; k < (GRAD == 2 ? kMaxRunStrings : 1); ++k) acc[k] = 0.0;
           const ShortHead h = load_head<GRAD>(run);
-          if (h.short_form) short_run<T, true, GRAD>(h, run, tp, tl, base, wbits, swb, lane, lbits, acc);
+          if (h.short_form) short_run<T, true, GRAD>(h, run, tp, tl, base, wbits, swb, lane, lbits, acc, real);
           else tile_run<T, true, GRAD>(run, recs, tp, tl, base, wbits, lane, lbits, acc);
           if (GRAD) {
             const int nk = GRAD == 2 ? int(run.n_str) : 1;
@@ -749,42 +808,44 @@ hipError_t launch_tile_forward(int dtype, void* psi, const FrameDesc& fr, const 
 template <typename T, int B, int GRAD, int MAXS>
 static hipError_t tile_reverse_g(void* psi, void* lam, const FrameDesc& fr, const RunDesc* runs, const RunRec* recs,
                                  const SegDesc* segs, int n_segs, const uint32_t* slot_map, int n_slots,
-                                 double* partials, uint32_t nb, uint64_t n_tb, int grid, hipStream_t st) {
+                                 double* partials, uint32_t nb, uint64_t n_tb, int grid, const double* imag_count,
+                                 hipStream_t st) {
   T* p = static_cast<T*>(psi);
   T* l = static_cast<T*>(lam);
   if (fr.b == B)
     hipLaunchKernelGGL((k_tile_reverse<T, B, kTileThreads, GRAD, MAXS, true>), dim3(grid), dim3(kTileThreads), 0,
-                       st, p, l, fr, runs, recs, segs, n_segs, slot_map, n_slots, partials, nb, n_tb);
+                       st, p, l, fr, runs, recs, segs, n_segs, slot_map, n_slots, partials, nb, n_tb, imag_count);
   else
     hipLaunchKernelGGL((k_tile_reverse<T, B, kTileThreads, GRAD, MAXS, false>), dim3(grid), dim3(kTileThreads), 0,
-                       st, p, l, fr, runs, recs, segs, n_segs, slot_map, n_slots, partials, nb, n_tb);
+                       st, p, l, fr, runs, recs, segs, n_segs, slot_map, n_slots, partials, nb, n_tb, imag_count);
   return hipGetLastError();
 }
 
 template <typename T, int B>
 static hipError_t tile_reverse_t(int grad, void* psi, void* lam, const FrameDesc& fr, const RunDesc* runs,
                                  const RunRec* recs, const SegDesc* segs, int n_segs, const uint32_t* slot_map,
-                                 int n_slots, double* partials, uint32_t nb, uint64_t n_tb, int grid, hipStream_t st) {
+                                 int n_slots, double* partials, uint32_t nb, uint64_t n_tb, int grid,
+                                 const double* imag_count, hipStream_t st) {
   if (grad == 0)
     return tile_reverse_g<T, B, 0, 1>(psi, lam, fr, runs, recs, segs, n_segs, slot_map, n_slots, partials, nb, n_tb,
-                                      grid, st);
+                                      grid, imag_count, st);
   if (grad == 1)
     return tile_reverse_g<T, B, 1, kMaxPassSlots>(psi, lam, fr, runs, recs, segs, n_segs, slot_map, n_slots,
-                                                  partials, nb, n_tb, grid, st);
+                                                  partials, nb, n_tb, grid, imag_count, st);
   return tile_reverse_g<T, B, 2, kMaxPassSlots>(psi, lam, fr, runs, recs, segs, n_segs, slot_map, n_slots, partials,
-                                                nb, n_tb, grid, st);
+                                                nb, n_tb, grid, imag_count, st);
 }
 
 hipError_t launch_tile_reverse(int dtype, int grad, void* psi, void* lam, const FrameDesc& fr,
                                const RunDesc* runs, const RunRec* recs, const SegDesc* segs, int n_segs,
                                const uint32_t* slot_map, int n_slots, double* partials, uint32_t nb_stride,
-                               uint64_t n_tb, int grid, hipStream_t st) {
+                               uint64_t n_tb, int grid, const double* imag_count, hipStream_t st) {
   if (n_slots > kMaxPassSlots) return hipErrorInvalidValue;
   if (dtype == 0)
     return tile_reverse_t<double2, kTileTwoC128>(grad, psi, lam, fr, runs, recs, segs, n_segs, slot_map, n_slots,
-                                                 partials, nb_stride, n_tb, grid, st);
+                                                 partials, nb_stride, n_tb, grid, imag_count, st);
   return tile_reverse_t<float2, kTileTwoC64>(grad, psi, lam, fr, runs, recs, segs, n_segs, slot_map, n_slots,
-                                             partials, nb_stride, n_tb, grid, st);
+                                             partials, nb_stride, n_tb, grid, imag_count, st);
 }
 
 }  // namespace q2sv

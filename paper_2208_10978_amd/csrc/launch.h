@@ -32,10 +32,13 @@ hipError_t launch_run_full(int dtype, bool rev, int grad, void* psi, void* lam, 
 // and every descriptor's walk matches its segment's region bits.
 hipError_t launch_tile_forward(int dtype, void* psi, const FrameDesc& fr, const RunDesc* runs, const RunRec* recs,
                                const SegDesc* segs, int n_segs, uint64_t n_tb, int grid, hipStream_t st);
+// imag_count: device count of the nonzero imaginary parts of psi and lam
+// (launch_imag_count), given only when every run of the list is a real
+// rotation, or NULL; when it is zero, real runs take the real walk
 hipError_t launch_tile_reverse(int dtype, int grad, void* psi, void* lam, const FrameDesc& fr,
                                const RunDesc* runs, const RunRec* recs, const SegDesc* segs, int n_segs,
                                const uint32_t* slot_map, int n_slots, double* partials, uint32_t nb_stride,
-                               uint64_t n_tb, int grid, hipStream_t st);
+                               uint64_t n_tb, int grid, const double* imag_count, hipStream_t st);
 // imag_count: device count of psi's amplitudes with a nonzero imaginary part
 // (launch_imag_count), given only for a sum with real coefficients, or NULL;
 // when it is zero the kernels build a real lambda from real parts only
