@@ -221,8 +221,8 @@ struct sv_hamiltonian {
   bool real = true;                  // every group coefficient is real (then a real psi gives a real lambda)
   std::vector<uint64_t> diag_z;      // diagonal (x = 0) terms
   std::vector<double> diag_c;
-  DevTiling tilings[2][2];           // [dtype][role: 0 expectation, 1 lambda]
-  bool built[2][2] = {{false, false}, {false, false}};
+  DevTiling tilings[2][3];           // [dtype][role: 0 expectation, 1 lambda, 2 real lambda]
+  bool built[2][3] = {{false, false, false}, {false, false, false}};
   DevBuf diag_dev;                   // resident diagonal d[m], FP64, 2^n entries
   bool diag_built = false;
   hipEvent_t diag_ready = nullptr;   // recorded after the diagonal's build
@@ -244,7 +244,7 @@ static int tiling_get(sv_hamiltonian* h, int dtype, int role, DevTiling** out) {
   std::lock_guard<std::mutex> lk(h->mu);
   DevTiling& t = h->tilings[dtype][role];
   if (!h->built[dtype][role]) {
-    const int b = role == 0 ? tile_bits_one(dtype) : tile_bits_lambda(dtype);
+    const int b = role == 0 ? tile_bits_one(dtype) : role == 1 ? tile_bits_lambda(dtype) : kTileLamReal;
     const int c = std::min(dtype == 0 ? 3 : 4, h->n);
     // kernels read the tables through scalar loads, so a tile's groups need
     // not be split
@@ -607,23 +607,18 @@ static int expect_impl(sv_state* s, sv_hamiltonian* h, double* out_dev) {
 
 // lam = H psi; energy_dev = (<psi|lam>/<psi|psi>, <psi|psi>)
 static int lambda_impl(sv_state* s, sv_state* lam, sv_hamiltonian* h, double* energy_dev) {
-  DevTiling* t = nullptr;
-  int rc = tiling_get(h, s->dtype, 1, &t);
-  if (rc) return rc;
-  const double* diag = nullptr;
-  rc = diag_get(h, s->stream, &diag);
-  if (rc) return rc;
-  const HTiling& ht = t->host;
   const int gdot = dot_grid(s);
-  rc = s->small.ensure(16 * sizeof(double), s->stream);
+  int rc = s->small.ensure(16 * sizeof(double), s->stream);
   if (rc) return rc;
   rc = s->scratch.ensure((3 * size_t(gdot) + 8) * sizeof(double), s->stream);
   if (rc) return rc;
   double* part = static_cast<double*>(s->scratch.p);
   double* sm = static_cast<double*>(s->small.p);
-  // with real coefficients, count psi's nonzero imaginary parts on the device;
-  // the tile kernels build a real lambda when there are none (no host wait)
-  const double* imag_count = nullptr;
+  // With real coefficients, count psi's nonzero imaginary parts; with none,
+  // lambda is real and is built on the real-part tiling (one qubit more per
+  // frame, fewer passes).  The choice of frames is the host's, so this waits
+  // once for the state's stream.
+  bool real = false;
   if (h->real) {
     {
       ProfScope prof(s->stream, kPDot, s->bytes());
@@ -631,17 +626,26 @@ static int lambda_impl(sv_state* s, sv_state* lam, sv_hamiltonian* h, double* en
     }
     ProfScope prof(s->stream, kPSmall, 0.0);
     HIP_TRY(launch_reduce_rows(part, 0, uint32_t(gdot), 1, sm + 15, s->stream));
-    imag_count = sm + 15;
+    double count = -1.0;
+    HIP_TRY(hipMemcpyAsync(&count, sm + 15, sizeof(double), hipMemcpyDeviceToHost, s->stream));
+    HIP_TRY(hipStreamSynchronize(s->stream));
+    real = count == 0.0;
   }
+  DevTiling* t = nullptr;
+  rc = tiling_get(h, s->dtype, real ? 2 : 1, &t);
+  if (rc) return rc;
+  const double* diag = nullptr;
+  rc = diag_get(h, s->stream, &diag);
+  if (rc) return rc;
+  const HTiling& ht = t->host;
   const int T = int(ht.frames.size());
   for (int tt = 0; tt < T; ++tt) {
     const FrameDesc& fr = ht.frames[tt];
     const uint64_t n_tb = uint64_t(1) << fr.n_comp;
     const int grid = int(std::min<uint64_t>(n_tb, uint64_t(num_cus())));
     ProfScope prof(s->stream, kPTileHLam, (tt == 0 ? (diag ? 2.5 : 2.0) : 3.0) * s->bytes());
-    const hipError_t e = launch_tile_lambda(s->dtype, tt == 0, s->amps, lam->amps, diag, fr,
-                                            dptr<uint4>(t->buf, t->o_blob) + ht.blob_off[tt], n_tb, grid, imag_count,
-                                            s->stream);
+    const hipError_t e = launch_tile_lambda(s->dtype, tt == 0, real, s->amps, lam->amps, diag, fr,
+                                            dptr<uint4>(t->buf, t->o_blob) + ht.blob_off[tt], n_tb, grid, s->stream);
     if (e != hipSuccess) return fail(SV_EDEVICE, std::string("lambda tile: ") + hipGetErrorString(e));
   }
   const int gfull = full_grid(s->amp_count() / 2);

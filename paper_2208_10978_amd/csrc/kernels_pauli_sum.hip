@@ -212,7 +212,7 @@ __device__ __forceinline__ void fast_pairs(const FastHead& f, uint32_t ds, unsig
 #pragma unroll
   for (int r = 0; r < NR; ++r) {
     smp[r] = ds ^ srest ^ f.sbits[r];
-    if (REAL) {
+    if constexpr (REAL) {
       pmx[r] = tp[smp[r] ^ f.sx].x;
       ppx[r] = tp[smp[r]].x;
     } else {
@@ -224,7 +224,7 @@ __device__ __forceinline__ void fast_pairs(const FastHead& f, uint32_t ds, unsig
   for (int r = 0; r < NR; ++r) {
     const unsigned sg = zp + f.pbits[r] + so;
     const uint32_t sm = smp[r] ^ f.sx;
-    if (REAL) {
+    if constexpr (REAL) {
       const double gre = signed_by(f.coef[2 * r], sg);
       lds_add(&tlr[sm], gre * (double)ppx[r]);
       lds_add(&tlr[smp[r]], gre * (double)pmx[r]);
@@ -238,14 +238,25 @@ __device__ __forceinline__ void fast_pairs(const FastHead& f, uint32_t ds, unsig
   }
 }
 
-// The tile passes of a lambda build, on the block's LDS arrays (tp: psi tile;
-// tlr, tli: FP64 lambda accumulator; fB: factored-group values).
-template <typename T, int B, int NT, int MODE, bool FULL, bool REAL>
+// An LDS slot of a real psi tile: the amplitude's real part in FP64.
+struct RealSlot {
+  double x;
+};
+template <> struct Real<RealSlot> { using type = double; };
+
+// The tile passes of a lambda build, on the block's LDS arrays (tp: psi tile
+// of TT slots; tlr, tli: FP64 lambda accumulator; fB: factored-group
+// values).  REAL: psi and every coefficient are real, so only real parts are
+// read and accumulated and tli is not used; TT = RealSlot keeps only the
+// real parts of psi in the tile.
+template <typename T, int B, int NT, int MODE, bool FULL, bool REAL, typename TT = T>
 __device__ __forceinline__ void lambda_tiles(const T* __restrict__ psi, T* __restrict__ lam,
                                              const double* __restrict__ diag, const FrameDesc& fr,
-                                             const uint4* __restrict__ blob, uint64_t n_tb, T* tp, double* tlr,
+                                             const uint4* __restrict__ blob, uint64_t n_tb, TT* tp, double* tlr,
                                              double* tli, double2* fB) {
+  static_assert(REAL || std::is_same<TT, T>::value, "a real-part tile needs the real build");
   using R = typename Real<T>::type;
+  constexpr bool kRealTile = std::is_same<TT, RealSlot>::value;
   constexpr int NW = NT / 64;
   constexpr int PER = (1 << B) / NT;
   const BlobView bv(blob);
@@ -273,7 +284,7 @@ __device__ __forceinline__ void lambda_tiles(const T* __restrict__ psi, T* __res
         double gre, gim;  // G(m)
         general_g(bv, g, r, lmp, base, fB, gre, gim);
         const uint32_t smp = lds_swz(lmp), sm = lds_swz(lm);
-        if (REAL) {
+        if constexpr (REAL) {
           lds_add(&tlr[sm], gre * (double)tp[smp].x);
           lds_add(&tlr[smp], gre * (double)tp[sm].x);
         } else {
@@ -337,7 +348,12 @@ __device__ __forceinline__ void lambda_tiles(const T* __restrict__ psi, T* __res
       }
     };
     auto put = [&]() {
-      tile_put_full<T, PER, NT>(tp, rp);
+      if constexpr (kRealTile) {
+#pragma unroll
+        for (int i = 0; i < PER; ++i) tp[lds_swz(threadIdx.x + uint32_t(i) * NT)].x = double(rp.re[i]);
+      } else {
+        tile_put_full<T, PER, NT>(tp, rp);
+      }
 #pragma unroll
       for (int i = 0; i < PER; ++i) {
         const uint32_t sl = lds_swz(threadIdx.x + uint32_t(i) * NT);
@@ -392,7 +408,15 @@ __device__ __forceinline__ void lambda_tiles(const T* __restrict__ psi, T* __res
     if (tb < n_tb) fetch(tb);
     for (; tb < n_tb; tb += gridDim.x) {
       const uint64_t base = frame_base(fr, tb);
-      tile_put<T, PER, NT>(tp, nloc, rp);
+      if constexpr (kRealTile) {
+#pragma unroll
+        for (int i = 0; i < PER; ++i) {
+          const uint32_t l = threadIdx.x + uint32_t(i) * NT;
+          if (l < nloc) tp[lds_swz(l)].x = double(rp.re[i]);
+        }
+      } else {
+        tile_put<T, PER, NT>(tp, nloc, rp);
+      }
 #pragma unroll
       for (int i = 0; i < PER; ++i) {
         const uint32_t l = threadIdx.x + uint32_t(i) * NT;
@@ -419,22 +443,29 @@ __device__ __forceinline__ void lambda_tiles(const T* __restrict__ psi, T* __res
 }
 
 // lambda = H psi over the tiles of one frame.  MODE 1 starts from the
-// diagonal part, MODE 2 adds to lam.  imag_count (device, may be NULL) is the
-// number of amplitudes of psi with a nonzero imaginary part, written by an
-// earlier kernel on the stream for a sum whose coefficients are all real:
-// when it is zero, lambda is real and only real parts are read and added.
+// diagonal part, MODE 2 adds to lam.
 template <typename T, int B, int NT, int MODE, bool FULL>
 __global__ void __launch_bounds__(NT) k_tile_lambda(const T* __restrict__ psi, T* __restrict__ lam,
                                                     const double* __restrict__ diag, FrameDesc fr,
-                                                    const uint4* __restrict__ blob, uint64_t n_tb,
-                                                    const double* __restrict__ imag_count) {
+                                                    const uint4* __restrict__ blob, uint64_t n_tb) {
   __shared__ T tp[1 << B];
   __shared__ double tlr[1 << B], tli[1 << B];
   __shared__ double2 fB[kMaxFactored * kFactRecs];
-  if (imag_count && *imag_count == 0.0)
-    lambda_tiles<T, B, NT, MODE, FULL, true>(psi, lam, diag, fr, blob, n_tb, tp, tlr, tli, fB);
-  else
-    lambda_tiles<T, B, NT, MODE, FULL, false>(psi, lam, diag, fr, blob, n_tb, tp, tlr, tli, fB);
+  lambda_tiles<T, B, NT, MODE, FULL, false>(psi, lam, diag, fr, blob, n_tb, tp, tlr, tli, fB);
+}
+
+// The same for a real psi and a sum with real coefficients: lambda is real,
+// the tile keeps psi's real parts (8 bytes a slot) and one FP64 accumulator,
+// so a frame holds one qubit more in the same LDS; lam's imaginary parts are
+// written as zero.
+template <typename T, int B, int NT, int MODE, bool FULL>
+__global__ void __launch_bounds__(NT) k_tile_lambda_real(const T* __restrict__ psi, T* __restrict__ lam,
+                                                         const double* __restrict__ diag, FrameDesc fr,
+                                                         const uint4* __restrict__ blob, uint64_t n_tb) {
+  __shared__ RealSlot tp[1 << B];
+  __shared__ double tlr[1 << B];
+  __shared__ double2 fB[kMaxFactored * kFactRecs];
+  lambda_tiles<T, B, NT, MODE, FULL, true, RealSlot>(psi, lam, diag, fr, blob, n_tb, tp, tlr, nullptr, fB);
 }
 
 // ---------------------------------------------------------------------------
@@ -628,28 +659,46 @@ __global__ void __launch_bounds__(256) k_group_full(const T* __restrict__ psi, T
 // ---------------------------------------------------------------------------
 // launchers
 // ---------------------------------------------------------------------------
-template <typename T, int B, int M>
+template <typename T, int B, int M, bool RT>
 static void tile_lambda_t(const void* psi, void* lam, const double* diag, const FrameDesc& fr, const uint4* blob,
-                          uint64_t n_tb, int grid, const double* imag_count, hipStream_t st) {
+                          uint64_t n_tb, int grid, hipStream_t st) {
   const T* p = static_cast<const T*>(psi);
   T* l = static_cast<T*>(lam);
-  if (fr.b == B)
-    hipLaunchKernelGGL((k_tile_lambda<T, B, kLambdaThreads, M, true>), dim3(grid), dim3(kLambdaThreads), 0, st, p,
-                       l, diag, fr, blob, n_tb, imag_count);
-  else
-    hipLaunchKernelGGL((k_tile_lambda<T, B, kLambdaThreads, M, false>), dim3(grid), dim3(kLambdaThreads), 0, st, p,
-                       l, diag, fr, blob, n_tb, imag_count);
+  if constexpr (RT) {
+    if (fr.b == B)
+      hipLaunchKernelGGL((k_tile_lambda_real<T, B, kLambdaThreads, M, true>), dim3(grid), dim3(kLambdaThreads), 0,
+                         st, p, l, diag, fr, blob, n_tb);
+    else
+      hipLaunchKernelGGL((k_tile_lambda_real<T, B, kLambdaThreads, M, false>), dim3(grid), dim3(kLambdaThreads), 0,
+                         st, p, l, diag, fr, blob, n_tb);
+  } else {
+    if (fr.b == B)
+      hipLaunchKernelGGL((k_tile_lambda<T, B, kLambdaThreads, M, true>), dim3(grid), dim3(kLambdaThreads), 0, st, p,
+                         l, diag, fr, blob, n_tb);
+    else
+      hipLaunchKernelGGL((k_tile_lambda<T, B, kLambdaThreads, M, false>), dim3(grid), dim3(kLambdaThreads), 0, st, p,
+                         l, diag, fr, blob, n_tb);
+  }
 }
 
-hipError_t launch_tile_lambda(int dtype, bool first, const void* psi, void* lam, const double* diag,
-                              const FrameDesc& fr, const uint4* blob, uint64_t n_tb, int grid,
-                              const double* imag_count, hipStream_t st) {
+hipError_t launch_tile_lambda(int dtype, bool first, bool real, const void* psi, void* lam, const double* diag,
+                              const FrameDesc& fr, const uint4* blob, uint64_t n_tb, int grid, hipStream_t st) {
   if (dtype == 0) {
-    if (first) tile_lambda_t<double2, kTileLamC128, 1>(psi, lam, diag, fr, blob, n_tb, grid, imag_count, st);
-    else tile_lambda_t<double2, kTileLamC128, 2>(psi, lam, diag, fr, blob, n_tb, grid, imag_count, st);
+    if (real) {
+      if (first) tile_lambda_t<double2, kTileLamReal, 1, true>(psi, lam, diag, fr, blob, n_tb, grid, st);
+      else tile_lambda_t<double2, kTileLamReal, 2, true>(psi, lam, diag, fr, blob, n_tb, grid, st);
+    } else {
+      if (first) tile_lambda_t<double2, kTileLamC128, 1, false>(psi, lam, diag, fr, blob, n_tb, grid, st);
+      else tile_lambda_t<double2, kTileLamC128, 2, false>(psi, lam, diag, fr, blob, n_tb, grid, st);
+    }
   } else {
-    if (first) tile_lambda_t<float2, kTileLamC64, 1>(psi, lam, diag, fr, blob, n_tb, grid, imag_count, st);
-    else tile_lambda_t<float2, kTileLamC64, 2>(psi, lam, diag, fr, blob, n_tb, grid, imag_count, st);
+    if (real) {
+      if (first) tile_lambda_t<float2, kTileLamReal, 1, true>(psi, lam, diag, fr, blob, n_tb, grid, st);
+      else tile_lambda_t<float2, kTileLamReal, 2, true>(psi, lam, diag, fr, blob, n_tb, grid, st);
+    } else {
+      if (first) tile_lambda_t<float2, kTileLamC64, 1, false>(psi, lam, diag, fr, blob, n_tb, grid, st);
+      else tile_lambda_t<float2, kTileLamC64, 2, false>(psi, lam, diag, fr, blob, n_tb, grid, st);
+    }
   }
   return hipGetLastError();
 }

@@ -14,6 +14,7 @@ namespace q2sv {
 constexpr int kTileFwdC128 = 13, kTileFwdC64 = 14;   // one state tile
 constexpr int kTileTwoC128 = 12, kTileTwoC64 = 13;   // two tiles (psi and lam)
 constexpr int kTileLamC128 = 12, kTileLamC64 = 12;   // psi tile + FP64 lambda accumulator
+constexpr int kTileLamReal = 13;                      // real parts of psi + one FP64 accumulator (real lambda)
 constexpr int kTileThreads = 512;
 constexpr int kTileRegionBits = 3;                   // 8 wavefronts own 8 regions of a segment
 constexpr int kLambdaThreads = 1024;                 // 16 wavefronts share one tile
@@ -39,12 +40,11 @@ hipError_t launch_tile_reverse(int dtype, int grad, void* psi, void* lam, const 
                                const RunDesc* runs, const RunRec* recs, const SegDesc* segs, int n_segs,
                                const uint32_t* slot_map, int n_slots, double* partials, uint32_t nb_stride,
                                uint64_t n_tb, int grid, const double* imag_count, hipStream_t st);
-// imag_count: device count of psi's amplitudes with a nonzero imaginary part
-// (launch_imag_count), given only for a sum with real coefficients, or NULL;
-// when it is zero the kernels build a real lambda from real parts only
-hipError_t launch_tile_lambda(int dtype, bool first, const void* psi, void* lam, const double* diag,
-                              const FrameDesc& fr, const uint4* blob, uint64_t n_tb, int grid,
-                              const double* imag_count, hipStream_t st);
+// real: psi has no nonzero imaginary part and every coefficient of the sum is
+// real; the frames are then those of a kTileLamReal-bit tiling (role 2) and
+// lambda is built from real parts only
+hipError_t launch_tile_lambda(int dtype, bool first, bool real, const void* psi, void* lam, const double* diag,
+                              const FrameDesc& fr, const uint4* blob, uint64_t n_tb, int grid, hipStream_t st);
 // partials[block] = number of the block's amplitudes with a nonzero imaginary part (grid blocks of 256)
 hipError_t launch_imag_count(int dtype, const void* a, uint64_t n_amp, int grid, double* partials, hipStream_t st);
 hipError_t launch_tile_expect(int dtype, const void* psi, const FrameDesc& fr, const uint4* blob, uint64_t n_tb,
