@@ -22,10 +22,11 @@
  * Memory and streams.  The caller owns the amplitude buffer (device memory,
  * for example a contiguous torch tensor) and the HIP stream.  Every call only
  * enqueues work on the state's stream and returns (except that the adjoint
- * calls, given a sum whose coefficients are all real, wait once for that
- * stream to learn whether psi is real, which selects a real-arithmetic build
- * of lambda); outputs named *_dev are device pointers to FP64 values written
- * on that stream.  Host arrays passed
+ * calls, given a sum whose coefficients are all real and a state large
+ * enough to fill the device with 13-qubit tiles (21 qubits and more on 256
+ * compute units), wait once for that stream to learn whether psi is real,
+ * which selects a real-arithmetic build of lambda); outputs named *_dev are
+ * device pointers to FP64 values written on that stream.  Host arrays passed
  * to a call are read before the call returns; the caller may free them
  * afterwards.  A handle is not re-entrant: calls on one handle must not be
  * made concurrently from several host threads.  Distinct handles may be used

@@ -366,6 +366,7 @@ struct sv_state {
   DevBuf tables;       // per-call uploaded tables
   DevBuf small;        // a few FP64 values
   Staging staging;
+  double* host_word = nullptr;  // pinned FP64 word for a device value the host must read
   sv_hamiltonian* cached_h = nullptr;  // last Pauli sum passed as raw arrays
   uint64_t amp_count() const { return uint64_t(1) << n; }
   double bytes() const { return double(amp_count()) * (dtype == SV_C128 ? 16.0 : 8.0); }
@@ -617,19 +618,25 @@ static int lambda_impl(sv_state* s, sv_state* lam, sv_hamiltonian* h, double* en
   // With real coefficients, count psi's nonzero imaginary parts; with none,
   // lambda is real and is built on the real-part tiling (one qubit more per
   // frame, fewer passes).  The choice of frames is the host's, so this waits
-  // once for the state's stream.
+  // once for the state's stream.  Only states whose real-part tiles still
+  // give every compute unit a block (2^(n - kTileLamReal) >= CUs) take it;
+  // smaller ones keep the complex build and skip the wait.
   bool real = false;
-  if (h->real) {
+  if (h->real && s->n > kTileLamReal && (uint64_t(1) << (s->n - kTileLamReal)) >= uint64_t(num_cus())) {
     {
       ProfScope prof(s->stream, kPDot, s->bytes());
       HIP_TRY(launch_imag_count(s->dtype, s->amps, s->amp_count(), gdot, part, s->stream));
     }
     ProfScope prof(s->stream, kPSmall, 0.0);
     HIP_TRY(launch_reduce_rows(part, 0, uint32_t(gdot), 1, sm + 15, s->stream));
-    double count = -1.0;
-    HIP_TRY(hipMemcpyAsync(&count, sm + 15, sizeof(double), hipMemcpyDeviceToHost, s->stream));
+    if (!s->host_word && hipHostMalloc(reinterpret_cast<void**>(&s->host_word), sizeof(double)) != hipSuccess) {
+      s->host_word = nullptr;
+      return fail(SV_ENOMEM, "pinned host word allocation failed");
+    }
+    *s->host_word = -1.0;
+    HIP_TRY(hipMemcpyAsync(s->host_word, sm + 15, sizeof(double), hipMemcpyDeviceToHost, s->stream));
     HIP_TRY(hipStreamSynchronize(s->stream));
-    real = count == 0.0;
+    real = *s->host_word == 0.0;
   }
   DevTiling* t = nullptr;
   rc = tiling_get(h, s->dtype, real ? 2 : 1, &t);
@@ -870,6 +877,7 @@ int sv_free(sv_state* s) {
   s->tables.release();
   s->small.release();
   s->staging.release();
+  if (s->host_word) hipHostFree(s->host_word);
   delete s;
   return SV_OK;
 }
