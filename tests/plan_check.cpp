@@ -228,7 +228,7 @@ static void check_rotations(int n, int n_occ, long* nw, double* cs, double* bs) 
   }
 }
 
-static void check_lambda(int n, long* nw, double* cs, double* bs) {
+static void check_lambda(int n, int b, long* nw, double* cs, double* bs) {
   // one- and two-body shaped terms: x on 0, 2 or 4 orbitals, Z chains, odd Y
   std::vector<PauliIn> p;
   std::vector<double> coef;
@@ -263,7 +263,6 @@ static void check_lambda(int n, long* nw, double* cs, double* bs) {
   std::vector<HGroup> nd;
   for (const HGroup& g : gs)
     if (!g.diag) nd.push_back(g);
-  const int b = 12;
   const HTiling T = build_tiling(nd, n, b, 3, true, size_t(1) << 24);
   long n_fast = 0;
   for (size_t t = 0; t < T.frames.size(); ++t) {
@@ -284,7 +283,8 @@ int main() {
   double cs = 0.0, bs = 0.0;
   check_rotations(18, 6, &nw, &cs, &bs);
   check_rotations(14, 4, &nw, &cs, &bs);
-  check_lambda(18, &nw, &cs, &bs);
+  check_lambda(18, 12, &nw, &cs, &bs);  // complex build
+  check_lambda(18, 13, &nw, &cs, &bs);  // real-part tiles
   if (g_fail) {
     std::printf("%d failures over %ld walks\n", g_fail, nw);
     return 1;
