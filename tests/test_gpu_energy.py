@@ -318,14 +318,19 @@ def test_reverse_sweep_real_and_complex_paths(case):
     psi.free(); lam.free()
 
 
+@pytest.mark.parametrize("dtype", ["c128", "c64"])
 @pytest.mark.parametrize("case", ["real_psi", "one_imag"])
-def test_lambda_real_tiling_at_21_qubits(case):
+def test_lambda_real_tiling_at_21_qubits(case, dtype):
     """At 21 qubits the real-coefficient build of lambda = H psi takes 13-qubit
     real-part tiles when psi is real (enough tiles to fill the device), and
     the complex 12-qubit build when one amplitude has an imaginary part.
     Element by element against the oracle, on a seeded sum of even-Y strings
-    of weight <= 4 (real coefficients)."""
-    announce(f"lambda 21 qubits: {case}")
+    of weight <= 4 (real coefficients).  complex64: the oracle takes the
+    state's own rounded amplitudes; lambda is accumulated in FP64 within a
+    pass but kept in complex64 between passes, so each pass rounds it once:
+    |error| <= u (passes) ||c||_1 max|psi| with u = 2^-24 and at most one pass
+    per x-group plus one."""
+    announce(f"lambda 21 qubits: {case} {dtype}")
     n = 21
     rx_, rz_, rc_ = random_pauli_sum(n, 300, 5200)
     even = np.array([pauli.popcount(int(a) & int(b)) % 2 == 0 for a, b in zip(rx_, rz_)])
@@ -335,8 +340,9 @@ def test_lambda_real_tiling_at_21_qubits(case):
     if case == "one_imag":
         v[(1 << 20) + 12345] += 1e-3j
     v /= np.linalg.norm(v)
-    psi = StateVector(n, "c128"); lam = StateVector(n, "c128")
-    psi.amps.copy_(torch.from_numpy(v))
+    psi = StateVector(n, dtype); lam = StateVector(n, dtype)
+    psi.amps.copy_(torch.from_numpy(v).to(psi.amps.dtype))
+    v = to_np_state(psi.amps)  # the amplitudes as stored (rounded for complex64)
     energy = torch.empty(2, dtype=torch.float64, device="cuda")
     grad = torch.empty(1, dtype=torch.float64, device="cuda")
     B.sv_adjoint_grad(psi.handle, lam.handle, hx, hz, hc, np.array([1], np.uint64), np.array([1], np.uint64),
@@ -345,7 +351,10 @@ def test_lambda_real_tiling_at_21_qubits(case):
     want = osv.apply_hamiltonian(v, hx, hz, hc)
     got = to_np_state(lam.amps)
     scale = max(1.0, float(np.abs(hc).sum()))
-    assert np.abs(got - want).max() <= 1e-12 * scale
-    e_ref = float(np.vdot(v, want).real)  # <psi|H psi> from the oracle's H psi (psi normalized)
-    assert abs(energy[0].item() - e_ref) <= 1e-12 * scale
+    passes = len(set(int(x) for x in hx)) + 1
+    tol = 1e-12 * scale if dtype == "c128" else 2.0 ** -24 * passes * float(np.abs(hc).sum()) * float(np.abs(v).max())
+    assert np.abs(got - want).max() <= tol
+    e_ref = float(np.vdot(v, want).real / np.vdot(v, v).real)  # Rayleigh quotient from the oracle's H psi
+    e_tol = 1e-12 * scale if dtype == "c128" else 1e-6 * scale
+    assert abs(energy[0].item() - e_ref) <= e_tol
     psi.free(); lam.free()
