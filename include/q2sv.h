@@ -5,7 +5,7 @@
  * int: SV_OK (0) on success, a negative SV_E* code on failure, with a
  * thread-local message in sv_last_error().  No call throws or exits.
  *
- * Conventions (Section 3.1 Eq. 1-2, Section 3.2 Eq. 6, Section 4.1 Eq. 7,
+ * Conventions (Section 3.1 Eq. 1-2, Section 3.2 Eq. 6, Section 4.2 Eq. 7,
  * Section 5.1 Eq. 10-11, Algorithm 1):
  *   - A state on n qubits is 2^n complex amplitudes; qubit q is bit q of the
  *     amplitude index (little-endian).  Amplitudes are interleaved (re, im):
@@ -188,7 +188,7 @@ int sv_normalize(sv_state *s, double *norm2_dev);
  * 2 * count values (re, im); used to check single amplitudes at scale. */
 int sv_gather_amplitudes(sv_state *s, const uint64_t *idx, int64_t count, double *out_dev);
 
-/* Kernel timing (Section 4.2 reports time per iteration; this gives it per
+/* Kernel timing (Section 6.1 reports time per iteration; this gives it per
  * kernel class).  sv_profile_begin starts recording a HIP event pair around
  * every kernel the library launches, on the stream it is launched on, with
  * the algorithmic bytes the launch must move (state reads and writes, not

@@ -26,5 +26,7 @@ determinant-space Hamiltonian built without Pauli algebra for the JW
 transform; fermionic ``expm`` of each excitation for the UCC rotation list;
 closed forms (Slater-Condon, single-excitation energy and slope); the
 Table 1 H2 CNOT count for the UCCSD string set under Algorithm 2; finite
-differences for Algorithm 1.  No function here is "parity unpinned".
+differences for Algorithm 1; a hand-built sum with entries at, above and
+below the threshold, and the dense-matrix bound on the removed weight, for
+the truncation of the 28-qubit workload's Hamiltonian (Eq. 1).
 """

@@ -245,10 +245,12 @@ def test_cached_sum_follows_changed_coefficients():
 @pytest.mark.parametrize("case", ["real_psi_real_h", "complex_psi_real_h", "one_imag_real_h",
                                   "real_psi_complex_h"])
 def test_lambda_real_and_complex_paths(case):
-    """lambda = H psi element by element against the oracle, for the real
-    build (psi real, every coefficient real) and the complex one (a complex
-    psi, one nonzero imaginary amplitude, or a sum with odd-Y strings).  One
-    rotation at phi = 0 leaves psi as it is, so lam returns H psi."""
+    """lambda = H psi element by element against the oracle at 14 qubits, with
+    a real psi and a real sum, a complex psi, one nonzero imaginary amplitude,
+    and a sum with odd-Y strings.  A 14-qubit state is too small for the
+    real-part tiling (it would leave compute units idle), so every case here
+    runs the complex build; the 21-qubit test covers the real-part tiling.
+    One rotation at phi = 0 leaves psi as it is, so lam returns H psi."""
     announce(f"lambda paths: {case}")
     n = 14
     h, eri = synthetic_integrals(n, 1000 + n)

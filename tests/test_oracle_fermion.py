@@ -169,3 +169,37 @@ def test_tile_order_rotation_list_equals_fermionic_exponentials(n, ne):
 def test_order_validation():
     with pytest.raises(ValueError):
         fermion.uccsd_rotations(4, 2, [(0, 2), (1, 3)])
+
+
+def test_truncate_on_a_hand_built_sum():
+    """The 28-qubit workload's truncation (terms with |c| above 1e-6 kept):
+    strict inequality on |c|, the sign ignored, the identity kept whatever
+    its size.  Hand-built sum, expected result written out."""
+    terms = {(0, 0): 1e-9,            # identity below the threshold: kept
+             (0, 1): 2e-6,            # above: kept
+             (0, 2): 1e-6,            # equal: dropped (strict)
+             (1, 0): -3e-6,           # negative, |c| above: kept
+             (1, 1): -1e-6,           # negative, equal: dropped
+             (3, 0): 9.99e-7,         # just below: dropped
+             (2, 2): -0.5}            # large: kept
+    got = fermion.truncate(terms, 1e-6)
+    assert got == {(0, 0): 1e-9, (0, 1): 2e-6, (1, 0): -3e-6, (2, 2): -0.5}
+    # an identity term that is absent stays absent
+    assert fermion.truncate({(1, 0): 0.1}, 1e-6) == {(1, 0): 0.1}
+    assert fermion.truncate({}, 1e-6) == {}
+
+
+@pytest.mark.parametrize("thr", [1e-3, 5e-3])
+def test_truncation_error_is_bounded_by_the_dropped_weight(thr):
+    """Dropping terms changes H by their sum, whose operator norm is at most
+    the sum of their |c| (each string is unitary): checked on dense matrices
+    at 8 qubits, with the removed terms recovered as full minus kept."""
+    n = 8
+    _, _, terms = h_and_terms(n, 1008)
+    kept = fermion.truncate(terms, thr)
+    dropped = {k: c for k, c in terms.items() if k not in kept}
+    assert dropped and all(abs(c) <= thr for c in dropped.values())
+    assert all(abs(c) > thr or k == (0, 0) for k, c in kept.items())
+    diff = dense.hamiltonian_matrix(terms, n) - dense.hamiltonian_matrix(kept, n)
+    assert np.abs(diff - dense.hamiltonian_matrix(dropped, n)).max() < 1e-13
+    assert np.linalg.norm(diff, 2) <= sum(abs(c) for c in dropped.values()) + 1e-12

@@ -27,6 +27,24 @@ def test_truncation_keeps_identity_and_strict_threshold():
     assert len(t) < len(full)
 
 
+@pytest.mark.parametrize("pick", ["1e-3", "1e-2", "exact"])
+def test_truncation_equals_the_oracle(pick):
+    """PauliSum.truncated against the oracle's truncate on a 12-qubit sum.
+    "exact" takes the threshold equal to one coefficient's |c|, so that term
+    must go (strict inequality)."""
+    h, eri = synthetic_integrals(12, 1012)
+    full = jordan_wigner(h, eri)
+    nonid = np.abs(full.c[(full.x != 0) | (full.z != 0)])
+    thr = float(np.sort(nonid)[len(nonid) // 3]) if pick == "exact" else float(pick)
+    got = full.truncated(thr)
+    want = fermion.truncate(fermion.jw_hamiltonian(h, eri), thr)
+    d = {(int(a), int(b)): c for a, b, c in zip(got.x, got.z, got.c)}
+    assert set(d) == set(want)
+    assert max(abs(d[k] - want[k]) for k in want) < 1e-13
+    if pick == "exact":
+        assert not np.any(np.abs(got.c[(got.x != 0) | (got.z != 0)]) == thr)
+
+
 @pytest.mark.parametrize("n,ne,order", [(4, 2, "lex"), (8, 4, "lex"), (8, 4, "tile"), (12, 6, "tile"), (10, 5, "tile")])
 def test_uccsd_rotations_match_oracle(n, ne, order):
     seq = uccsd_excitation_order(n, ne, order)
