@@ -25,17 +25,29 @@
  * calls, given a sum whose coefficients are all real and a state large
  * enough to fill the device with 13-qubit tiles (21 qubits and more on 256
  * compute units), wait once for that stream to learn whether psi is real,
- * which selects a real-arithmetic build of lambda); outputs named *_dev are
- * device pointers to FP64 values written on that stream.  Host arrays passed
- * to a call are read before the call returns; the caller may free them
- * afterwards.  A handle is not re-entrant: calls on one handle must not be
- * made concurrently from several host threads.  Distinct handles may be used
- * concurrently on different streams.
+ * which selects a real-arithmetic build of lambda, unless the caller has
+ * declared psi real with sv_set_real_hint); outputs named *_dev are device
+ * pointers to FP64 values written on that stream.  Host arrays passed to a
+ * call are read before the call returns; the caller may free them
+ * afterwards.  Distinct handles may be used concurrently on different
+ * streams and host threads.
  *
- * Errors.  Arguments are validated before any device work; on SV_EINVAL the
- * state is untouched.  SV_ENOMEM: a device or pinned allocation of the
- * library's own scratch failed.  SV_EDEVICE: a HIP launch or runtime call
- * failed; the device may be unusable afterwards.
+ * Errors.
+ *   SV_EINVAL   an argument is invalid; arguments are validated before any
+ *               device work, and the state is untouched.
+ *   SV_ENOMEM   a device or pinned allocation of the library's own scratch
+ *               failed; nothing else is affected.
+ *   SV_EDEVICE  a HIP launch or runtime call failed.  The failure is sticky
+ *               per device: from then on every call that would use that
+ *               device (sv_alloc and sv_hamiltonian_create included)
+ *               returns SV_EDEVICE, with the first failure's message in
+ *               sv_last_error(), and does no device work.  sv_free and
+ *               sv_hamiltonian_free still release their handle (and return
+ *               SV_EDEVICE).  A caller should drain its work and report.
+ *   SV_EBUSY    a handle is not re-entrant: a call made while another call
+ *               on the same state handle (a state it writes to or whose
+ *               scratch it uses) is in progress on another host thread
+ *               returns SV_EBUSY at once and changes nothing.
  */
 #ifndef Q2SV_H
 #define Q2SV_H
@@ -52,7 +64,7 @@ typedef struct sv_hamiltonian sv_hamiltonian; /* opaque: resident Pauli sum    *
 typedef struct { uint64_t x, z; } sv_pauli;
 
 enum { SV_C128 = 0, SV_C64 = 1 };
-enum { SV_OK = 0, SV_EINVAL = -1, SV_ENOMEM = -2, SV_EDEVICE = -3 };
+enum { SV_OK = 0, SV_EINVAL = -1, SV_ENOMEM = -2, SV_EDEVICE = -3, SV_EBUSY = -4 };
 
 /* Largest supported qubit count (a 2^34 complex128 state is 256 GiB). */
 #define SV_MAX_QUBITS 34
@@ -76,6 +88,17 @@ int sv_free(sv_state *s);
 
 /* Change the stream of a handle (later calls enqueue there). */
 int sv_set_stream(sv_state *s, void *hip_stream);
+
+/* Declare whether psi is real when an adjoint call starts (Algorithm 1's
+ * lambda = H psi), for example after sv_prepare_hf and rotations whose
+ * strings all have an odd number of Y factors (every UCC string).  With a
+ * real declaration the adjoint calls build lambda with real arithmetic
+ * without waiting for the stream; the kernels still count psi's nonzero
+ * imaginary parts on the device, and if any is found the declaration was
+ * wrong: lambda, the energy and the gradient come out NaN (never silently
+ * wrong).  psi_is_real = 0 (the default) restores the checked choice with
+ * its one stream wait.  The declaration stays until changed. */
+int sv_set_real_hint(sv_state *s, int psi_is_real);
 
 /* psi <- |occ_mask>, the Hartree-Fock determinant of Eq. 6 as a basis state
  * (occupation of qubit q = bit q).  occ_mask < 2^n. */
@@ -200,6 +223,12 @@ int sv_profile_end(char *buf, size_t buflen);
 
 /* Message of the last failed call on this host thread ("" if none). */
 const char *sv_last_error(void);
+
+/* Mark the current device as failed, exactly as a failed HIP call would (see
+ * SV_EDEVICE above), without touching the device.  For tests of a caller's
+ * failure handling (draining, reporting); the mark lasts until the process
+ * ends. */
+int sv_inject_device_failure(const char *msg);
 
 #ifdef __cplusplus
 }

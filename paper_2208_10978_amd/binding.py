@@ -17,7 +17,7 @@ LIB_PATH = os.path.join(os.path.dirname(os.path.abspath(__file__)), "libq2sv.so"
 
 SV_C128 = 0
 SV_C64 = 1
-SV_OK, SV_EINVAL, SV_ENOMEM, SV_EDEVICE = 0, -1, -2, -3
+SV_OK, SV_EINVAL, SV_ENOMEM, SV_EDEVICE, SV_EBUSY = 0, -1, -2, -3, -4
 SV_MAX_QUBITS = 34
 
 
@@ -25,6 +25,14 @@ class Q2svError(RuntimeError):
     def __init__(self, code, msg):
         super().__init__(f"q2sv error {code}: {msg}")
         self.code = code
+
+
+class DeviceFailure(Q2svError):
+    """SV_EDEVICE: the device failed and stays unusable for this process."""
+
+
+class Busy(Q2svError):
+    """SV_EBUSY: another call on the same state handle is in progress."""
 
 
 _lib = None
@@ -43,6 +51,8 @@ def lib():
             "sv_alloc": [_c.c_int, _c.c_int, _vp, _c.c_size_t, _vp, _c.POINTER(_vp)],
             "sv_free": [_vp],
             "sv_set_stream": [_vp, _vp],
+            "sv_set_real_hint": [_vp, _c.c_int],
+            "sv_inject_device_failure": [_c.c_char_p],
             "sv_prepare_hf": [_vp, _c.c_uint64],
             "sv_apply_pauli_rotations": [_vp, _vp, _vp, _i64],
             "sv_expect_pauli_sum": [_vp, _vp, _vp, _i64, _vp],
@@ -71,7 +81,8 @@ def lib():
 
 
 EXPORTED = (
-    "sv_alloc", "sv_free", "sv_set_stream", "sv_prepare_hf", "sv_apply_pauli_rotations",
+    "sv_alloc", "sv_free", "sv_set_stream", "sv_set_real_hint", "sv_inject_device_failure", "sv_prepare_hf",
+    "sv_apply_pauli_rotations",
     "sv_expect_pauli_sum", "sv_adjoint_grad", "sv_adjoint_grad_params", "sv_hamiltonian_create",
     "sv_hamiltonian_free", "sv_expect_hamiltonian", "sv_adjoint_grad_params_h",
     "sv_adjoint_grad_params_deflated", "sv_overlap", "sv_normalize",
@@ -85,7 +96,8 @@ def sv_last_error() -> str:
 
 def _check(rc):
     if rc != SV_OK:
-        raise Q2svError(rc, sv_last_error())
+        cls = DeviceFailure if rc == SV_EDEVICE else Busy if rc == SV_EBUSY else Q2svError
+        raise cls(rc, sv_last_error())
 
 
 def _paulis(x, z) -> np.ndarray:
@@ -138,6 +150,14 @@ def sv_free(s):
 
 def sv_set_stream(s, stream):
     _check(lib().sv_set_stream(s, _stream_handle(stream)))
+
+
+def sv_set_real_hint(s, psi_is_real: bool):
+    _check(lib().sv_set_real_hint(s, int(bool(psi_is_real))))
+
+
+def sv_inject_device_failure(msg: str = ""):
+    _check(lib().sv_inject_device_failure(msg.encode()))
 
 
 def sv_prepare_hf(s, occ_mask: int):

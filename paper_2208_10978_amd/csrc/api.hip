@@ -4,6 +4,7 @@
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
+#include <atomic>
 #include <cmath>
 #include <cstring>
 #include <memory>
@@ -26,10 +27,44 @@ int fail(int code, const std::string& msg) {
   return code;
 }
 
+// Sticky device failure.  The first failed HIP call on a device marks it, and
+// every later call that would use that device returns SV_EDEVICE with the
+// first message: after a launch or runtime failure the device's state (and
+// any work queued on it) can no longer be trusted.  t_dev is the device of
+// the call in progress on this host thread.
+constexpr int kMaxDevices = 64;
+struct DeviceHealth {
+  std::atomic<int> bad{0};
+  std::mutex mu;
+  std::string first;
+};
+DeviceHealth g_health[kMaxDevices];
+thread_local int t_dev = 0;
+
+DeviceHealth& health(int dev) { return g_health[(dev >= 0 && dev < kMaxDevices) ? dev : 0]; }
+
+int device_fail(const std::string& msg) {
+  DeviceHealth& h = health(t_dev);
+  {
+    std::lock_guard<std::mutex> lk(h.mu);
+    if (!h.bad.load()) h.first = msg;
+    h.bad.store(1);
+  }
+  return fail(SV_EDEVICE, msg);
+}
+
+// SV_OK, or SV_EDEVICE when the device has failed before
+int device_check(int dev) {
+  DeviceHealth& h = health(dev);
+  if (!h.bad.load()) return SV_OK;
+  std::lock_guard<std::mutex> lk(h.mu);
+  return fail(SV_EDEVICE, "device " + std::to_string(dev) + " is unusable after an earlier failure: " + h.first);
+}
+
 #define HIP_TRY(expr)                                                                       \
   do {                                                                                      \
     hipError_t e_ = (expr);                                                                 \
-    if (e_ != hipSuccess) return fail(SV_EDEVICE, std::string(#expr) + ": " + hipGetErrorString(e_)); \
+    if (e_ != hipSuccess) return device_fail(std::string(#expr) + ": " + hipGetErrorString(e_)); \
   } while (0)
 
 uint64_t fnv(const void* data, size_t bytes, uint64_t h = 1469598103934665603ull) {
@@ -48,7 +83,7 @@ struct DevBuf {
   int ensure(size_t bytes, hipStream_t st) {
     if (bytes <= cap) return SV_OK;
     if (p) {
-      if (hipStreamSynchronize(st) != hipSuccess) return fail(SV_EDEVICE, "hipStreamSynchronize failed");
+      if (hipStreamSynchronize(st) != hipSuccess) return device_fail("hipStreamSynchronize failed");
       hipFree(p);
       p = nullptr;
       cap = 0;
@@ -77,9 +112,9 @@ struct Staging {
   bool pending = false;
   int ensure(size_t bytes) {
     if (!done && hipEventCreateWithFlags(&done, hipEventDisableTiming) != hipSuccess)
-      return fail(SV_EDEVICE, "hipEventCreate failed");
+      return device_fail("hipEventCreate failed");
     if (pending) {
-      if (hipEventSynchronize(done) != hipSuccess) return fail(SV_EDEVICE, "hipEventSynchronize failed");
+      if (hipEventSynchronize(done) != hipSuccess) return device_fail("hipEventSynchronize failed");
       pending = false;
     }
     if (bytes <= cap) return SV_OK;
@@ -368,6 +403,8 @@ struct sv_state {
   Staging staging;
   double* host_word = nullptr;  // pinned FP64 word for a device value the host must read
   sv_hamiltonian* cached_h = nullptr;  // last Pauli sum passed as raw arrays
+  bool real_hint = false;              // the caller asserts psi is real on entry to the adjoint calls
+  std::atomic<int> busy{0};            // a call on this handle is in progress
   uint64_t amp_count() const { return uint64_t(1) << n; }
   double bytes() const { return double(amp_count()) * (dtype == SV_C128 ? 16.0 : 8.0); }
 };
@@ -375,11 +412,44 @@ struct sv_state {
 struct DeviceGuard {
   int prev = -1;
   explicit DeviceGuard(int dev) {
+    t_dev = dev;
     if (hipGetDevice(&prev) == hipSuccess && prev != dev) hipSetDevice(dev);
     else prev = -1;
   }
   ~DeviceGuard() {
     if (prev >= 0) hipSetDevice(prev);
+  }
+};
+
+// One ABI call on the handles it writes to or whose scratch it uses: each is
+// taken for the duration of the call (a concurrent second call on any of
+// them returns SV_EBUSY and changes nothing), then the device of the first
+// is made current and checked for an earlier failure (SV_EDEVICE).
+struct Call {
+  sv_state* held[2] = {nullptr, nullptr};
+  int n_held = 0;
+  int rc = SV_OK;
+  int prev_dev = -1;
+  Call(sv_state* a, sv_state* b = nullptr) {
+    for (sv_state* s : {a, b}) {
+      if (!s) continue;
+      int idle = 0;
+      if (!s->busy.compare_exchange_strong(idle, 1)) {
+        rc = fail(SV_EBUSY, "state handle is in use by another call (a handle is not re-entrant)");
+        return;
+      }
+      held[n_held++] = s;
+    }
+    if (!n_held) return;
+    const int dev = held[0]->device;
+    t_dev = dev;
+    if (hipGetDevice(&prev_dev) == hipSuccess && prev_dev != dev) hipSetDevice(dev);
+    else prev_dev = -1;
+    rc = device_check(dev);
+  }
+  ~Call() {
+    if (prev_dev >= 0) hipSetDevice(prev_dev);
+    for (int i = 0; i < n_held; ++i) held[i]->busy.store(0);
   }
 };
 
@@ -517,7 +587,7 @@ static int launch_rotations(sv_state* s, sv_state* lam, const RotPlan& pl, bool 
         e = launch_tile_reverse(s->dtype, grad_mode, s->amps, lam_amps, fr, d_desc + po[i].desc0,
                                 d_recs + po[i].rec0, d_segs + po[i].seg0, po[i].nsegs, d_slot + po[i].slot0,
                                 po[i].nslots, partials, kPartialStride, n_tb, grid, imag_count, s->stream);
-      if (e != hipSuccess) return fail(SV_EDEVICE, std::string("tile pass launch: ") + hipGetErrorString(e));
+      if (e != hipSuccess) return device_fail(std::string("tile pass launch: ") + hipGetErrorString(e));
     } else {
       const RunDesc& rd = descs[po[i].desc0];
       const Run& r = pl.runs[ps.runs[0]];
@@ -531,7 +601,7 @@ static int launch_rotations(sv_state* s, sv_state* lam, const RotPlan& pl, bool 
       ProfScope prof(s->stream, kPRunFull, touched * amp * 2.0 * (rev ? 2.0 : 1.0));
       const hipError_t e = launch_run_full(s->dtype, rev, rev ? grad_mode : 0, s->amps, lam_amps, rd, d_recs,
                                            partials, s->n, kPartialStride, full_grid(work), s->stream);
-      if (e != hipSuccess) return fail(SV_EDEVICE, std::string("run launch: ") + hipGetErrorString(e));
+      if (e != hipSuccess) return device_fail(std::string("run launch: ") + hipGetErrorString(e));
     }
   }
   return SV_OK;
@@ -581,7 +651,7 @@ static int expect_impl(sv_state* s, sv_hamiltonian* h, double* out_dev) {
     ProfScope prof(s->stream, kPTileHExp, s->bytes());
     e = launch_tile_expect(s->dtype, s->amps, ht.frames[tt], blobs + ht.blob_off[tt], n_tb, int(bpt),
                            part + size_t(tt) * bpt, s->stream);
-    if (e != hipSuccess) return fail(SV_EDEVICE, std::string("expectation tiles: ") + hipGetErrorString(e));
+    if (e != hipSuccess) return device_fail(std::string("expectation tiles: ") + hipGetErrorString(e));
   }
   size_t off = size_t(T) * bpt;
   for (size_t gi = 0; gi < n_full; ++gi) {
@@ -589,7 +659,7 @@ static int expect_impl(sv_state* s, sv_hamiltonian* h, double* out_dev) {
     e = launch_group_full(s->dtype, 0, s->amps, nullptr, ht.groups[gi], dptr<SubDesc>(t->buf, t->o_subs),
                           dptr<double2>(t->buf, t->o_coef), dptr<uint64_t>(t->buf, t->o_recs), s->n, gfull,
                           part + off, s->stream);
-    if (e != hipSuccess) return fail(SV_EDEVICE, std::string("expectation group: ") + hipGetErrorString(e));
+    if (e != hipSuccess) return device_fail(std::string("expectation group: ") + hipGetErrorString(e));
     off += size_t(gfull);
   }
   double* dpart = part + n_h;
@@ -597,7 +667,7 @@ static int expect_impl(sv_state* s, sv_hamiltonian* h, double* out_dev) {
     ProfScope prof(s->stream, kPDot, s->bytes() * (diag ? 1.5 : 1.0));
     e = launch_dot(s->dtype, s->amps, nullptr, diag, s->amp_count(), gdot, dpart, s->stream);
   }
-  if (e != hipSuccess) return fail(SV_EDEVICE, "norm launch failed");
+  if (e != hipSuccess) return device_fail("norm launch failed");
   ProfScope prof(s->stream, kPSmall, 0.0);
   HIP_TRY(launch_reduce_rows(part, 0, uint32_t(n_h), 1, sm, s->stream));
   HIP_TRY(launch_reduce_rows(dpart + 2 * gdot, 0, uint32_t(gdot), 1, sm + 1, s->stream));
@@ -617,11 +687,15 @@ static int lambda_impl(sv_state* s, sv_state* lam, sv_hamiltonian* h, double* en
   double* sm = static_cast<double*>(s->small.p);
   // With real coefficients, count psi's nonzero imaginary parts; with none,
   // lambda is real and is built on the real-part tiling (one qubit more per
-  // frame, fewer passes).  The choice of frames is the host's, so this waits
-  // once for the state's stream.  Only states whose real-part tiles still
-  // give every compute unit a block (2^(n - kTileLamReal) >= CUs) take it;
-  // smaller ones keep the complex build and skip the wait.
+  // frame, fewer passes).  The choice of frames is the host's.  When the
+  // caller has declared psi real (sv_set_real_hint) the real build is taken
+  // without waiting, and its kernels check the device count themselves (a
+  // nonzero count turns lambda into NaN); otherwise the host waits once for
+  // the state's stream to read the count.  Only states whose real-part tiles
+  // still give every compute unit a block (2^(n - kTileLamReal) >= CUs) take
+  // the real build; smaller ones keep the complex build and skip the count.
   bool real = false;
+  const double* guard = nullptr;
   if (h->real && s->n > kTileLamReal && (uint64_t(1) << (s->n - kTileLamReal)) >= uint64_t(num_cus())) {
     {
       ProfScope prof(s->stream, kPDot, s->bytes());
@@ -629,14 +703,19 @@ static int lambda_impl(sv_state* s, sv_state* lam, sv_hamiltonian* h, double* en
     }
     ProfScope prof(s->stream, kPSmall, 0.0);
     HIP_TRY(launch_reduce_rows(part, 0, uint32_t(gdot), 1, sm + 15, s->stream));
-    if (!s->host_word && hipHostMalloc(reinterpret_cast<void**>(&s->host_word), sizeof(double)) != hipSuccess) {
-      s->host_word = nullptr;
-      return fail(SV_ENOMEM, "pinned host word allocation failed");
+    if (s->real_hint) {
+      real = true;
+      guard = sm + 15;
+    } else {
+      if (!s->host_word && hipHostMalloc(reinterpret_cast<void**>(&s->host_word), sizeof(double)) != hipSuccess) {
+        s->host_word = nullptr;
+        return fail(SV_ENOMEM, "pinned host word allocation failed");
+      }
+      *s->host_word = -1.0;
+      HIP_TRY(hipMemcpyAsync(s->host_word, sm + 15, sizeof(double), hipMemcpyDeviceToHost, s->stream));
+      HIP_TRY(hipStreamSynchronize(s->stream));
+      real = *s->host_word == 0.0;
     }
-    *s->host_word = -1.0;
-    HIP_TRY(hipMemcpyAsync(s->host_word, sm + 15, sizeof(double), hipMemcpyDeviceToHost, s->stream));
-    HIP_TRY(hipStreamSynchronize(s->stream));
-    real = *s->host_word == 0.0;
   }
   DevTiling* t = nullptr;
   rc = tiling_get(h, s->dtype, real ? 2 : 1, &t);
@@ -652,8 +731,9 @@ static int lambda_impl(sv_state* s, sv_state* lam, sv_hamiltonian* h, double* en
     const int grid = int(std::min<uint64_t>(n_tb, uint64_t(num_cus())));
     ProfScope prof(s->stream, kPTileHLam, (tt == 0 ? (diag ? 2.5 : 2.0) : 3.0) * s->bytes());
     const hipError_t e = launch_tile_lambda(s->dtype, tt == 0, real, s->amps, lam->amps, diag, fr,
-                                            dptr<uint4>(t->buf, t->o_blob) + ht.blob_off[tt], n_tb, grid, s->stream);
-    if (e != hipSuccess) return fail(SV_EDEVICE, std::string("lambda tile: ") + hipGetErrorString(e));
+                                            dptr<uint4>(t->buf, t->o_blob) + ht.blob_off[tt], n_tb, grid, guard,
+                                            s->stream);
+    if (e != hipSuccess) return device_fail(std::string("lambda tile: ") + hipGetErrorString(e));
   }
   const int gfull = full_grid(s->amp_count() / 2);
   for (size_t gi = 0; gi < ht.groups.size(); ++gi) {
@@ -661,7 +741,7 @@ static int lambda_impl(sv_state* s, sv_state* lam, sv_hamiltonian* h, double* en
     const hipError_t e = launch_group_full(s->dtype, 2, s->amps, lam->amps, ht.groups[gi],
                                            dptr<SubDesc>(t->buf, t->o_subs), dptr<double2>(t->buf, t->o_coef),
                                            dptr<uint64_t>(t->buf, t->o_recs), s->n, gfull, nullptr, s->stream);
-    if (e != hipSuccess) return fail(SV_EDEVICE, std::string("lambda group: ") + hipGetErrorString(e));
+    if (e != hipSuccess) return device_fail(std::string("lambda group: ") + hipGetErrorString(e));
   }
   {
     ProfScope prof(s->stream, kPDot, 2.0 * s->bytes());
@@ -800,6 +880,15 @@ extern "C" {
 
 const char* sv_last_error(void) { return g_err.c_str(); }
 
+int sv_inject_device_failure(const char* msg) {
+  int dev = 0;
+  if (hipGetDevice(&dev) != hipSuccess) dev = 0;
+  t_dev = dev;
+  device_fail(std::string("injected: ") + (msg ? msg : ""));
+  g_err.clear();
+  return SV_OK;
+}
+
 int sv_profile_begin(void) {
   std::lock_guard<std::mutex> lk(g_prof.mu);
   g_prof.on = true;
@@ -813,6 +902,11 @@ int sv_profile_end(char* buf, size_t buflen) {
     g_prof.on = false;
     recs.swap(g_prof.recs);
   }
+  int dev = 0;
+  if (hipGetDevice(&dev) != hipSuccess) dev = 0;
+  t_dev = dev;
+  int rc = device_check(dev);
+  if (rc) return rc;
   HIP_TRY(hipDeviceSynchronize());
   double ms[kPCount] = {}, bytes[kPCount] = {};
   long count[kPCount] = {};
@@ -857,12 +951,16 @@ int sv_alloc(int n_qubits, int dtype, void* amps, size_t amps_bytes, void* hip_s
   if (reinterpret_cast<uintptr_t>(amps) % 16) return fail(SV_EINVAL, "amps is not 16-byte aligned");
   const size_t need = (size_t(1) << n_qubits) * (dtype == SV_C128 ? 16 : 8);
   if (amps_bytes < need) return fail(SV_EINVAL, "amps buffer smaller than 2^n amplitudes");
+  int dev = 0;
+  if (hipGetDevice(&dev) != hipSuccess) dev = 0;
+  const int rc = device_check(dev);
+  if (rc) return rc;
   sv_state* s = new sv_state();
   s->n = n_qubits;
   s->dtype = dtype;
   s->amps = amps;
   s->stream = static_cast<hipStream_t>(hip_stream);
-  hipGetDevice(&s->device);
+  s->device = dev;
   *out = s;
   g_err.clear();
   return SV_OK;
@@ -870,30 +968,46 @@ int sv_alloc(int n_qubits, int dtype, void* amps, size_t amps_bytes, void* hip_s
 
 int sv_free(sv_state* s) {
   if (!s) return SV_OK;
-  DeviceGuard g(s->device);
-  hipStreamSynchronize(s->stream);
-  if (s->cached_h) hamiltonian_destroy(s->cached_h);
-  s->scratch.release();
-  s->tables.release();
-  s->small.release();
-  s->staging.release();
-  if (s->host_word) hipHostFree(s->host_word);
+  int rc;
+  {
+    Call call(s);
+    if (call.rc == SV_EBUSY) return call.rc;
+    rc = call.rc;
+    // a failed device still gets its handle released; its stream is not waited for
+    if (rc == SV_OK) hipStreamSynchronize(s->stream);
+    if (s->cached_h) hamiltonian_destroy(s->cached_h);
+    s->scratch.release();
+    s->tables.release();
+    s->small.release();
+    s->staging.release();
+    if (s->host_word) hipHostFree(s->host_word);
+  }
   delete s;
-  return SV_OK;
+  return rc;
 }
 
 int sv_set_stream(sv_state* s, void* hip_stream) {
   if (!s) return fail(SV_EINVAL, "NULL state");
-  DeviceGuard g(s->device);
+  Call call(s);
+  if (call.rc) return call.rc;
   HIP_TRY(hipStreamSynchronize(s->stream));
   s->stream = static_cast<hipStream_t>(hip_stream);
   return SV_OK;
 }
 
+int sv_set_real_hint(sv_state* s, int psi_is_real) {
+  if (!s) return fail(SV_EINVAL, "NULL state");
+  Call call(s);
+  if (call.rc) return call.rc;
+  s->real_hint = psi_is_real != 0;
+  return SV_OK;
+}
+
 int sv_prepare_hf(sv_state* s, uint64_t occ_mask) {
   if (!s) return fail(SV_EINVAL, "NULL state");
+  Call call(s);
+  if (call.rc) return call.rc;
   if (occ_mask >> s->n) return fail(SV_EINVAL, "occ_mask has bits >= n");
-  DeviceGuard g(s->device);
   ProfScope prof(s->stream, kPFill, s->bytes());
   HIP_TRY(launch_fill_basis(s->dtype, s->amps, s->amp_count(), occ_mask, s->stream));
   return SV_OK;
@@ -901,12 +1015,13 @@ int sv_prepare_hf(sv_state* s, uint64_t occ_mask) {
 
 int sv_apply_pauli_rotations(sv_state* s, const sv_pauli* p, const double* phi, int64_t n_rot) {
   if (!s) return fail(SV_EINVAL, "NULL state");
+  Call call(s);
+  if (call.rc) return call.rc;
   int rc = validate_paulis(p, n_rot, s->n, "rotation");
   if (rc) return rc;
   rc = validate_finite(phi, n_rot, "phi");
   if (rc) return rc;
   if (n_rot == 0) return SV_OK;
-  DeviceGuard g(s->device);
   RotPlan pl;
   plan_rotations(s, p, phi, nullptr, nullptr, n_rot, false, 0, pl);
   return launch_rotations(s, nullptr, pl, false, 0, nullptr);
@@ -914,8 +1029,9 @@ int sv_apply_pauli_rotations(sv_state* s, const sv_pauli* p, const double* phi, 
 
 int sv_expect_pauli_sum(sv_state* s, const sv_pauli* p, const double* coef, int64_t n_terms, double* out_dev) {
   if (!s) return fail(SV_EINVAL, "NULL state");
+  Call call(s);
+  if (call.rc) return call.rc;
   if (!out_dev) return fail(SV_EINVAL, "out_dev is NULL");
-  DeviceGuard g(s->device);
   sv_hamiltonian* h = nullptr;
   int rc = get_cached_h(s, p, coef, n_terms, &h);
   if (rc) return rc;
@@ -927,22 +1043,28 @@ int sv_hamiltonian_create(int n_qubits, const sv_pauli* p, const double* coef, i
   if (!out) return fail(SV_EINVAL, "out is NULL");
   *out = nullptr;
   if (n_qubits < 1 || n_qubits > SV_MAX_QUBITS) return fail(SV_EINVAL, "n_qubits out of range");
+  int dev = 0;
+  if (hipGetDevice(&dev) != hipSuccess) dev = 0;
+  const int rc = device_check(dev);
+  if (rc) return rc;
   return hamiltonian_make(n_qubits, p, coef, n_terms, out);
 }
 
 int sv_hamiltonian_free(sv_hamiltonian* h) {
   if (!h) return SV_OK;
   DeviceGuard g(h->device);
-  hipDeviceSynchronize();
+  const int rc = device_check(h->device);
+  if (rc == SV_OK) hipDeviceSynchronize();
   hamiltonian_destroy(h);
-  return SV_OK;
+  return rc;
 }
 
 int sv_expect_hamiltonian(sv_state* s, const sv_hamiltonian* hc, double* out_dev) {
   if (!s || !hc) return fail(SV_EINVAL, "NULL argument");
+  Call call(s);
+  if (call.rc) return call.rc;
   if (!out_dev) return fail(SV_EINVAL, "out_dev is NULL");
   if (hc->n != s->n) return fail(SV_EINVAL, "Pauli sum and state differ in n");
-  DeviceGuard g(s->device);
   return expect_impl(s, const_cast<sv_hamiltonian*>(hc), out_dev);
 }
 
@@ -950,12 +1072,13 @@ int sv_adjoint_grad(sv_state* psi, sv_state* lam, const sv_pauli* hp, const doub
                     const sv_pauli* rp, const double* phi, int64_t n_rot, double* energy_dev, double* grad_dev) {
   int rc = check_pair(psi, lam);
   if (rc) return rc;
+  Call call(psi, lam);
+  if (call.rc) return call.rc;
   if (!energy_dev || (n_rot > 0 && !grad_dev)) return fail(SV_EINVAL, "NULL output");
   rc = validate_paulis(rp, n_rot, psi->n, "rotation");
   if (rc) return rc;
   rc = validate_finite(phi, n_rot, "phi");
   if (rc) return rc;
-  DeviceGuard g(psi->device);
   sv_hamiltonian* h = nullptr;
   rc = get_cached_h(psi, hp, hcoef, n_terms, &h);
   if (rc) return rc;
@@ -976,6 +1099,8 @@ int sv_adjoint_grad_params(sv_state* psi, sv_state* lam, const sv_pauli* hp, con
                            const double* dphi, int64_t n_params, double* energy_dev, double* grad_theta_dev) {
   int rc = check_pair(psi, lam);
   if (rc) return rc;
+  Call call(psi, lam);
+  if (call.rc) return call.rc;
   if (!energy_dev || (n_params > 0 && !grad_theta_dev)) return fail(SV_EINVAL, "NULL output");
   rc = validate_paulis(rp, n_rot, psi->n, "rotation");
   if (rc) return rc;
@@ -983,7 +1108,6 @@ int sv_adjoint_grad_params(sv_state* psi, sv_state* lam, const sv_pauli* hp, con
   if (rc) return rc;
   rc = check_params(param, dphi, n_rot, n_params);
   if (rc) return rc;
-  DeviceGuard g(psi->device);
   sv_hamiltonian* h = nullptr;
   rc = get_cached_h(psi, hp, hcoef, n_terms, &h);
   if (rc) return rc;
@@ -995,6 +1119,8 @@ int sv_adjoint_grad_params_h(sv_state* psi, sv_state* lam, const sv_hamiltonian*
                              int64_t n_params, double* energy_dev, double* grad_theta_dev) {
   int rc = check_pair(psi, lam);
   if (rc) return rc;
+  Call call(psi, lam);
+  if (call.rc) return call.rc;
   if (!hc) return fail(SV_EINVAL, "NULL Pauli sum");
   if (hc->n != psi->n) return fail(SV_EINVAL, "Pauli sum and state differ in n");
   if (!energy_dev || (n_params > 0 && !grad_theta_dev)) return fail(SV_EINVAL, "NULL output");
@@ -1004,7 +1130,6 @@ int sv_adjoint_grad_params_h(sv_state* psi, sv_state* lam, const sv_hamiltonian*
   if (rc) return rc;
   rc = check_params(param, dphi, n_rot, n_params);
   if (rc) return rc;
-  DeviceGuard g(psi->device);
   return adjoint_impl(psi, lam, const_cast<sv_hamiltonian*>(hc), rp, phi, n_rot, param, dphi, n_params,
                       energy_dev, grad_theta_dev);
 }
@@ -1016,6 +1141,8 @@ int sv_adjoint_grad_params_deflated(sv_state* psi, sv_state* lam, const sv_hamil
                                     double* grad_theta_dev) {
   int rc = check_pair(psi, lam);
   if (rc) return rc;
+  Call call(psi, lam);
+  if (call.rc) return call.rc;
   if (!hc) return fail(SV_EINVAL, "NULL Pauli sum");
   if (hc->n != psi->n) return fail(SV_EINVAL, "Pauli sum and state differ in n");
   if (!energy_dev || (n_params > 0 && !grad_theta_dev)) return fail(SV_EINVAL, "NULL output");
@@ -1039,18 +1166,18 @@ int sv_adjoint_grad_params_deflated(sv_state* psi, sv_state* lam, const sv_hamil
   if (rc) return rc;
   rc = check_params(param, dphi, n_rot, n_params);
   if (rc) return rc;
-  DeviceGuard g(psi->device);
   return adjoint_impl(psi, lam, const_cast<sv_hamiltonian*>(hc), rp, phi, n_rot, param, dphi, n_params,
                       energy_dev, grad_theta_dev, &pa, ovl_dev);
 }
 
 int sv_overlap(const sv_state* a, const sv_state* b, double* out_dev) {
   if (!a || !b) return fail(SV_EINVAL, "NULL state");
+  sv_state* s = const_cast<sv_state*>(b);
+  Call call(s);
+  if (call.rc) return call.rc;
   if (!out_dev) return fail(SV_EINVAL, "NULL output");
   if (a->n != b->n || a->dtype != b->dtype) return fail(SV_EINVAL, "states differ in n or dtype");
   if (a->device != b->device) return fail(SV_EINVAL, "states on different devices");
-  DeviceGuard g(b->device);
-  sv_state* s = const_cast<sv_state*>(b);
   ProjArgs pa{};
   pa.k = 1;
   pa.p[0] = a->amps;
@@ -1070,7 +1197,8 @@ int sv_overlap(const sv_state* a, const sv_state* b, double* out_dev) {
 
 int sv_normalize(sv_state* s, double* norm2_dev) {
   if (!s) return fail(SV_EINVAL, "NULL state");
-  DeviceGuard g(s->device);
+  Call call(s);
+  if (call.rc) return call.rc;
   const int gdot = dot_grid(s);
   int rc = s->scratch.ensure((3 * size_t(gdot) + 8) * sizeof(double), s->stream);
   if (rc) return rc;
@@ -1091,11 +1219,12 @@ int sv_normalize(sv_state* s, double* norm2_dev) {
 
 int sv_gather_amplitudes(sv_state* s, const uint64_t* idx, int64_t count, double* out_dev) {
   if (!s) return fail(SV_EINVAL, "NULL state");
+  Call call(s);
+  if (call.rc) return call.rc;
   if (count < 0 || (count > 0 && (!idx || !out_dev))) return fail(SV_EINVAL, "bad arguments");
   for (int64_t i = 0; i < count; ++i)
     if (idx[i] >> s->n) return fail(SV_EINVAL, "index out of range");
   if (count == 0) return SV_OK;
-  DeviceGuard g(s->device);
   Packer pk;
   const size_t o = pk.add(idx, size_t(count) * sizeof(uint64_t));
   int rc = upload(s->staging, s->tables, pk, s->stream);

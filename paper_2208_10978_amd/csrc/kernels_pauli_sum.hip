@@ -458,13 +458,40 @@ __global__ void __launch_bounds__(NT) k_tile_lambda(const T* __restrict__ psi, T
 // the tile keeps psi's real parts (8 bytes a slot) and one FP64 accumulator,
 // so a frame holds one qubit more in the same LDS; lam's imaginary parts are
 // written as zero.
+//
+// guard (device, may be NULL): the number of psi's nonzero imaginary parts,
+// given when the real build was chosen on the caller's word rather than on
+// that count.  If it is not zero the caller's word was wrong: the pass
+// writes NaN over its tiles of lambda instead, so the energy and gradient
+// computed from it are NaN rather than silently wrong.
+template <typename T, int NT>
+__device__ __forceinline__ void lambda_poison(T* __restrict__ lam, const FrameDesc& fr, uint64_t n_tb) {
+  using R = typename Real<T>::type;
+  const R nan = R(__builtin_nan(""));
+  const uint32_t nloc = 1u << fr.b;
+  for (uint64_t tb = blockIdx.x; tb < n_tb; tb += gridDim.x) {
+    const uint64_t base = frame_base(fr, tb);
+    for (uint32_t l = threadIdx.x; l < nloc; l += NT) {
+      uint64_t g = 0;
+      for (int j = 0; j < int(fr.b); ++j)
+        if ((l >> j) & 1u) g |= uint64_t(1) << fr.q[j];
+      lam[base | g] = cmake<T>(nan, nan);
+    }
+  }
+}
+
 template <typename T, int B, int NT, int MODE, bool FULL>
 __global__ void __launch_bounds__(NT) k_tile_lambda_real(const T* __restrict__ psi, T* __restrict__ lam,
                                                          const double* __restrict__ diag, FrameDesc fr,
-                                                         const uint4* __restrict__ blob, uint64_t n_tb) {
+                                                         const uint4* __restrict__ blob, uint64_t n_tb,
+                                                         const double* __restrict__ guard) {
   __shared__ RealSlot tp[1 << B];
   __shared__ double tlr[1 << B];
   __shared__ double2 fB[kMaxFactored * kFactRecs];
+  if (guard && *guard != 0.0) {
+    lambda_poison<T, NT>(lam, fr, n_tb);
+    return;
+  }
   lambda_tiles<T, B, NT, MODE, FULL, true, RealSlot>(psi, lam, diag, fr, blob, n_tb, tp, tlr, nullptr, fB);
 }
 
@@ -661,16 +688,16 @@ __global__ void __launch_bounds__(256) k_group_full(const T* __restrict__ psi, T
 // ---------------------------------------------------------------------------
 template <typename T, int B, int M, bool RT>
 static void tile_lambda_t(const void* psi, void* lam, const double* diag, const FrameDesc& fr, const uint4* blob,
-                          uint64_t n_tb, int grid, hipStream_t st) {
+                          uint64_t n_tb, int grid, const double* guard, hipStream_t st) {
   const T* p = static_cast<const T*>(psi);
   T* l = static_cast<T*>(lam);
   if constexpr (RT) {
     if (fr.b == B)
       hipLaunchKernelGGL((k_tile_lambda_real<T, B, kLambdaThreads, M, true>), dim3(grid), dim3(kLambdaThreads), 0,
-                         st, p, l, diag, fr, blob, n_tb);
+                         st, p, l, diag, fr, blob, n_tb, guard);
     else
       hipLaunchKernelGGL((k_tile_lambda_real<T, B, kLambdaThreads, M, false>), dim3(grid), dim3(kLambdaThreads), 0,
-                         st, p, l, diag, fr, blob, n_tb);
+                         st, p, l, diag, fr, blob, n_tb, guard);
   } else {
     if (fr.b == B)
       hipLaunchKernelGGL((k_tile_lambda<T, B, kLambdaThreads, M, true>), dim3(grid), dim3(kLambdaThreads), 0, st, p,
@@ -682,22 +709,23 @@ static void tile_lambda_t(const void* psi, void* lam, const double* diag, const 
 }
 
 hipError_t launch_tile_lambda(int dtype, bool first, bool real, const void* psi, void* lam, const double* diag,
-                              const FrameDesc& fr, const uint4* blob, uint64_t n_tb, int grid, hipStream_t st) {
+                              const FrameDesc& fr, const uint4* blob, uint64_t n_tb, int grid, const double* guard,
+                              hipStream_t st) {
   if (dtype == 0) {
     if (real) {
-      if (first) tile_lambda_t<double2, kTileLamReal, 1, true>(psi, lam, diag, fr, blob, n_tb, grid, st);
-      else tile_lambda_t<double2, kTileLamReal, 2, true>(psi, lam, diag, fr, blob, n_tb, grid, st);
+      if (first) tile_lambda_t<double2, kTileLamReal, 1, true>(psi, lam, diag, fr, blob, n_tb, grid, guard, st);
+      else tile_lambda_t<double2, kTileLamReal, 2, true>(psi, lam, diag, fr, blob, n_tb, grid, guard, st);
     } else {
-      if (first) tile_lambda_t<double2, kTileLamC128, 1, false>(psi, lam, diag, fr, blob, n_tb, grid, st);
-      else tile_lambda_t<double2, kTileLamC128, 2, false>(psi, lam, diag, fr, blob, n_tb, grid, st);
+      if (first) tile_lambda_t<double2, kTileLamC128, 1, false>(psi, lam, diag, fr, blob, n_tb, grid, guard, st);
+      else tile_lambda_t<double2, kTileLamC128, 2, false>(psi, lam, diag, fr, blob, n_tb, grid, guard, st);
     }
   } else {
     if (real) {
-      if (first) tile_lambda_t<float2, kTileLamReal, 1, true>(psi, lam, diag, fr, blob, n_tb, grid, st);
-      else tile_lambda_t<float2, kTileLamReal, 2, true>(psi, lam, diag, fr, blob, n_tb, grid, st);
+      if (first) tile_lambda_t<float2, kTileLamReal, 1, true>(psi, lam, diag, fr, blob, n_tb, grid, guard, st);
+      else tile_lambda_t<float2, kTileLamReal, 2, true>(psi, lam, diag, fr, blob, n_tb, grid, guard, st);
     } else {
-      if (first) tile_lambda_t<float2, kTileLamC64, 1, false>(psi, lam, diag, fr, blob, n_tb, grid, st);
-      else tile_lambda_t<float2, kTileLamC64, 2, false>(psi, lam, diag, fr, blob, n_tb, grid, st);
+      if (first) tile_lambda_t<float2, kTileLamC64, 1, false>(psi, lam, diag, fr, blob, n_tb, grid, guard, st);
+      else tile_lambda_t<float2, kTileLamC64, 2, false>(psi, lam, diag, fr, blob, n_tb, grid, guard, st);
     }
   }
   return hipGetLastError();

@@ -42,9 +42,12 @@ hipError_t launch_tile_reverse(int dtype, int grad, void* psi, void* lam, const 
                                uint64_t n_tb, int grid, const double* imag_count, hipStream_t st);
 // real: psi has no nonzero imaginary part and every coefficient of the sum is
 // real; the frames are then those of a kTileLamReal-bit tiling (role 2) and
-// lambda is built from real parts only
+// lambda is built from real parts only.  guard (real builds only, may be
+// NULL): device count of psi's nonzero imaginary parts; when it is not zero
+// the pass writes NaN over lambda instead
 hipError_t launch_tile_lambda(int dtype, bool first, bool real, const void* psi, void* lam, const double* diag,
-                              const FrameDesc& fr, const uint4* blob, uint64_t n_tb, int grid, hipStream_t st);
+                              const FrameDesc& fr, const uint4* blob, uint64_t n_tb, int grid, const double* guard,
+                              hipStream_t st);
 // partials[block] = number of the block's amplitudes with a nonzero imaginary part (grid blocks of 256)
 hipError_t launch_imag_count(int dtype, const void* a, uint64_t n_amp, int grid, double* partials, hipStream_t st);
 hipError_t launch_tile_expect(int dtype, const void* psi, const FrameDesc& fr, const uint4* blob, uint64_t n_tb,

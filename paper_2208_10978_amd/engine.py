@@ -114,6 +114,14 @@ class UCCSDEvaluator:
         self.h = Hamiltonian(ham) if hamiltonian is None else hamiltonian
         self.psi = StateVector(self.n, dtype, stream=stream)
         self.lam = StateVector(self.n, dtype, stream=stream)
+        # HF is real and a rotation whose string has an odd number of Y
+        # factors is a real orthogonal matrix, so with such a list psi stays
+        # real: the library may then build lambda without a stream wait (it
+        # still checks on the device, and a wrong declaration gives NaN)
+        x = np.asarray(rot.x, dtype=np.uint64)
+        z = np.asarray(rot.z, dtype=np.uint64)
+        self.real_circuit = bool(np.all(np.bitwise_count(x & z) % 2 == 1))
+        B.sv_set_real_hint(self.psi.handle, self.real_circuit)
         self.renormalize = (dtype == "c64") if renormalize is None else renormalize
         dev = self.psi.amps.device
         self.energy_buf = torch.empty(2, dtype=torch.float64, device=dev)

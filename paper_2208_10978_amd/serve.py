@@ -10,6 +10,10 @@ device.  A request's plans depend only on the request, so its result is the
 same alone and in any mix up to the rounding of lambda's accumulation (whose
 order across wavefronts is not fixed).
 
+A failed device (the library's sticky SV_EDEVICE, raised as DeviceFailure)
+ends admission: every request in flight, waiting or arriving later fails
+with the device's message, and ``device_error`` keeps that message.
+
 Host-side preparation (the JW Pauli sum and the rotation list) runs in a
 thread pool ahead of admission.  ``fifo=True`` gives the one-request-at-a-
 time baseline on the same trace.  ``Server.start`` / ``submit`` /
@@ -25,6 +29,7 @@ from dataclasses import dataclass
 
 import numpy as np
 
+from .binding import DeviceFailure
 from .problem import PauliSum, RotationList, jordan_wigner, uccsd_rotations
 
 
@@ -142,6 +147,7 @@ class Server:
         self.peak_bytes = 0
         self.peak_slots = 0
         self.loop_error = None  # what ended the online loop, if it failed
+        self.device_error = None  # the device's failure message, once it has failed
         self._thread = None
 
     # -- the loop ---------------------------------------------------------
@@ -154,9 +160,29 @@ class Server:
         waiting: list = []
         active: list = []
         used = 0
+
+        def device_lost(exc):
+            # the device is unusable from here on: fail everything in flight
+            # and waiting; later arrivals fail as they come
+            self.device_error = str(exc)
+            msg = f"device failed: {exc}"
+            for _, r in active:
+                r.error = msg
+                r.t_done = time.perf_counter() - t0
+                on_done(r)
+            for r in waiting:
+                r.error = msg
+                r.t_done = time.perf_counter() - t0
+                on_done(r)
+            active.clear()
+            waiting.clear()
+
         while True:
             now = time.perf_counter() - t0
-            for r in arrivals(now):
+            # once the device has failed, everything still to come is drained at once
+            for r in arrivals(float("inf") if self.device_error else now):
+                if r.error is None and self.device_error:
+                    r.error = f"device failed: {self.device_error}"
                 if r.error is not None:
                     r.t_done = now
                     on_done(r)
@@ -167,12 +193,17 @@ class Server:
                     if not job.ready():
                         continue
                     r.energy, r.norm, r.grad = job.result()
+                except DeviceFailure as exc:
+                    device_lost(exc)
+                    break
                 except Exception as exc:
                     r.error = f"{type(exc).__name__}: {exc}"
                 r.t_done = time.perf_counter() - t0
                 used -= r.device_bytes()
                 active.remove((job, r))
                 on_done(r)
+            if self.device_error:
+                used = 0
             i = 0  # admissions
             while i < len(waiting) and len(active) < self.max_slots:
                 r = waiting[i]
@@ -190,6 +221,10 @@ class Server:
                     used += r.device_bytes()
                     self.peak_bytes = max(self.peak_bytes, used)
                     self.peak_slots = max(self.peak_slots, len(active))
+                except DeviceFailure as exc:
+                    waiting.insert(0, r)
+                    device_lost(exc)
+                    break
                 except Exception as exc:  # a malformed request fails alone
                     r.error = f"{type(exc).__name__}: {exc}"
                     r.t_done = time.perf_counter() - t0

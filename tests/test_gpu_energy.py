@@ -360,3 +360,38 @@ def test_lambda_real_tiling_at_21_qubits(case, dtype):
     e_tol = 1e-12 * scale if dtype == "c128" else 1e-6 * scale
     assert abs(energy[0].item() - e_ref) <= e_tol
     psi.free(); lam.free()
+
+
+@pytest.mark.parametrize("case", ["real_psi", "one_imag"])
+def test_real_hint_at_21_qubits(case):
+    """sv_set_real_hint: with psi declared real the adjoint call builds lambda
+    on the real-part tiling without a stream wait.  A real psi gives the
+    oracle's H psi; a psi with one imaginary amplitude (a wrong declaration)
+    must give NaN in lambda and the energy, never a silently wrong value."""
+    announce(f"real hint 21 qubits: {case}")
+    n = 21
+    rx_, rz_, rc_ = random_pauli_sum(n, 300, 5200)
+    even = np.array([pauli.popcount(int(a) & int(b)) % 2 == 0 for a, b in zip(rx_, rz_)])
+    hx, hz, hc = rx_[even], rz_[even], rc_[even]
+    rng = np.random.default_rng(5201)
+    v = rng.normal(size=1 << n).astype(np.complex128)
+    if case == "one_imag":
+        v[(1 << 20) + 12345] += 1e-3j
+    v /= np.linalg.norm(v)
+    psi = StateVector(n, "c128"); lam = StateVector(n, "c128")
+    psi.amps.copy_(torch.from_numpy(v))
+    B.sv_set_real_hint(psi.handle, True)
+    energy = torch.empty(2, dtype=torch.float64, device="cuda")
+    grad = torch.empty(1, dtype=torch.float64, device="cuda")
+    B.sv_adjoint_grad(psi.handle, lam.handle, hx, hz, hc, np.array([1], np.uint64), np.array([1], np.uint64),
+                      np.array([0.0]), energy, grad)
+    torch.cuda.synchronize()
+    got = to_np_state(lam.amps)
+    if case == "real_psi":
+        want = osv.apply_hamiltonian(v, hx, hz, hc)
+        assert np.abs(got - want).max() <= 1e-12 * max(1.0, float(np.abs(hc).sum()))
+        assert np.isfinite(energy[0].item())
+    else:
+        assert np.isnan(energy[0].item()) and np.isnan(grad[0].item())
+        assert np.isnan(got.real).all()
+    psi.free(); lam.free()

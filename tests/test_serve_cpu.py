@@ -198,3 +198,66 @@ def test_online_loop_failure_fails_every_open_request():
     assert isinstance(srv.loop_error, KeyboardInterrupt)
     with pytest.raises(RuntimeError):
         srv.submit(reqs[0])
+
+
+class FailingExecutor(FakeExecutor):
+    """Reports a failed device (the library's sticky SV_EDEVICE) when the
+    third request completes, and at every launch after that."""
+
+    def __init__(self, **kw):
+        super().__init__(**kw)
+        self.dead = False
+        self.completed = 0
+
+    class Job(FakeExecutor.Job):
+        def result(self):
+            from paper_2208_10978_amd.binding import DeviceFailure, SV_EDEVICE
+            self.ex.completed += 1
+            if self.ex.completed == 3:
+                self.ex.dead = True
+            if self.ex.dead:
+                raise DeviceFailure(SV_EDEVICE, "planted device failure")
+            return super().result()
+
+    def launch(self, req):
+        from paper_2208_10978_amd.binding import DeviceFailure, SV_EDEVICE
+        if self.dead:
+            raise DeviceFailure(SV_EDEVICE, "planted device failure")
+        self.launch_order.append(req.rid)
+        return FailingExecutor.Job(self, req)
+
+
+def test_a_failed_device_drains_and_reports():
+    reqs = trace(10, gap=0.004)
+    srv = Server(FailingExecutor(device_time=0.02), max_slots=2)
+    out = srv.run(reqs, realtime=True)
+    assert srv.device_error is not None and "planted" in srv.device_error
+    ok = [r for r in out if r.error is None]
+    bad = [r for r in out if r.error is not None]
+    assert len(ok) == 2 and len(bad) == 8          # two finished before the failure
+    assert all("device failed" in r.error and r.t_done is not None for r in bad)
+    for r in ok:                                    # results before the failure are intact
+        alone = Server(FakeExecutor(), max_slots=1).run([Request(r.rid, r.n_qubits, r.n_electrons, r.h_seed,
+                                                                 r.theta_seed, 0.0, r.theta_amplitude)],
+                                                        realtime=False)[0]
+        assert alone.energy == r.energy
+
+
+def test_online_server_fails_open_and_later_requests_after_a_device_failure():
+    srv = Server(FailingExecutor(device_time=0.01), max_slots=2).start()
+    futs = [srv.submit(r) for r in trace(5, gap=0.0)]
+    errs = []
+    for f in futs:
+        try:
+            f.result(timeout=30)
+        except RuntimeError as exc:
+            errs.append(str(exc))
+    assert len(errs) == 3 and all("device failed" in e for e in errs)
+    late = srv.submit(trace(1)[0])
+    try:
+        late.result(timeout=30)
+        raise AssertionError("a request after the failure must fail")
+    except RuntimeError as exc:
+        assert "device failed" in str(exc)
+    srv.stop()
+    assert srv.device_error is not None
