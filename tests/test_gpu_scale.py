@@ -50,6 +50,50 @@ def test_hf_energy_and_gradient_at_zero(problem):
     assert np.abs(g - want).max() <= 1e-12 * max(1.0, np.abs(want).max())
 
 
+def test_truncated_hamiltonian_at_zero(problem):
+    """The Hamiltonian the benchmark runs (the 28-qubit sum with |c| > 1e-6
+    and the identity kept), in both Pauli-sum paths.  At theta = 0 psi is
+    |HF>, where P|HF> = i^{|x&z|} (-1)^{|HF & z|} |HF ^ x>, so from the term
+    list alone: E(0) = sum over its diagonal strings of c (-1)^{|HF & z|},
+    and dE/dtheta_X(0) = 2 sgn_X <K_X|H|HF> with <K|H|HF> the sum over its
+    strings with x = K ^ HF of c i^{|x&z|} (-1)^{|HF & z|}."""
+    announce("28q truncated H at theta=0")
+    hf = problem["hf"]
+    ham_t = problem["ham"].truncated(1e-6)
+    assert len(ham_t) == 52725
+    ev = UCCSDEvaluator(ham_t, problem["rot"], NE, "c128")
+    try:
+        zero = np.zeros(ev.rot.n_params)
+        e_exp = ev.energy(zero).cpu().numpy()
+        e, g = ev.energy_and_grad(zero)
+        torch.cuda.synchronize()
+        e = e.cpu().numpy()
+        g = g.cpu().numpy()
+    finally:
+        ev.free()
+    hx, hz, hc = ham_t.x.astype(np.int64), ham_t.z.astype(np.int64), ham_t.c
+    zpar = np.bitwise_count(np.int64(hf) & hz) % 2
+    term = hc * (1j ** (np.bitwise_count(hx & hz) % 4)) * (1.0 - 2.0 * zpar)
+    row: dict = {}
+    for x, v in zip(hx.tolist(), term.tolist()):
+        row[x] = row.get(x, 0.0) + v
+    e0 = row[0].real
+    assert abs(row[0].imag) == 0.0
+    for got in (e_exp[0], e[0]):
+        assert abs(got - e0) <= 1e-12 * abs(e0), (got, e0)
+    want = np.zeros(len(g))
+    for idx, exc in enumerate(problem["order"]):
+        kx, sgn = fermion.excited_determinant(exc, NE)
+        v = row.get(kx ^ hf, 0.0)
+        assert abs(v.imag) <= 1e-15
+        want[idx] = 2.0 * sgn * v.real
+    assert np.abs(g - want).max() <= 1e-12 * max(1.0, np.abs(want).max())
+    # the truncation moves E(0) by at most the removed weight
+    e_full = fermion.slater_condon_hf_energy(problem["h"], problem["eri"], NE)
+    removed = problem["ham"].one_norm() - ham_t.one_norm()
+    assert abs(e0 - e_full) <= removed + 1e-12
+
+
 @pytest.mark.parametrize("which", [0, 50, 2000])
 def test_single_excitation_closed_form(problem, which):
     """One nonzero amplitude: psi = cos th |HF> + sin th tau|HF>; two

@@ -45,6 +45,20 @@ def test_truncation_equals_the_oracle(pick):
         assert not np.any(np.abs(got.c[(got.x != 0) | (got.z != 0)]) == thr)
 
 
+def test_benchmark_hamiltonian_truncation_equals_the_oracle():
+    """The 28-qubit Hamiltonian the benchmark runs (integrals seed 1028,
+    |c| > 1e-6 and the identity): the product's list against the oracle's
+    JW sum and truncation (about 10 s for the oracle's Pauli algebra)."""
+    h, eri = synthetic_integrals(28, 1028)
+    got = jordan_wigner(h, eri).truncated(1e-6)
+    want = fermion.truncate(fermion.jw_hamiltonian(h, eri), 1e-6)
+    d = {(int(a), int(b)): c for a, b, c in zip(got.x, got.z, got.c)}
+    assert len(d) == len(got) == 52725
+    assert set(d) == set(want)
+    # the two builders sum the like terms in different orders
+    assert max(abs(d[k] - want[k]) / max(1.0, abs(want[k])) for k in want) < 1e-13
+
+
 @pytest.mark.parametrize("n,ne,order", [(4, 2, "lex"), (8, 4, "lex"), (8, 4, "tile"), (12, 6, "tile"), (10, 5, "tile")])
 def test_uccsd_rotations_match_oracle(n, ne, order):
     seq = uccsd_excitation_order(n, ne, order)
