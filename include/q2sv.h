@@ -175,6 +175,25 @@ int sv_adjoint_grad_params_h(sv_state *psi, sv_state *lam, const sv_hamiltonian 
                              const int32_t *param_of_rot, const double *dphi_dtheta,
                              int64_t n_params, double *energy_dev, double *grad_theta_dev);
 
+/* For callers that cannot allocate device memory during the call (code under
+ * HIP graph capture, tight serving loops, harnesses that forbid hipMalloc):
+ * sv_expect_hamiltonian with no allocation of any kind.  Its FP64 partial
+ * sums live in a fixed array of the library's device code (2 MiB, one copy
+ * per device for the life of the process) instead of the handle's scratch.
+ *   Preconditions: the resident sum's expectation tables and diagonal for
+ *   the state's dtype exist, i.e. sv_expect_hamiltonian has run once with
+ *   this handle and a state of that dtype (building them allocates);
+ *   otherwise SV_EINVAL.  A call whose partial sums would exceed the array
+ *   (tile passes x blocks + whole-state group passes x blocks + reductions
+ *   > 262144 values) returns SV_EINVAL before any device work.
+ *   The array is shared by every call on a device and keeps the last call's
+ *   contents (every value a call reads it writes first): two calls whose
+ *   work overlaps on one device, on different streams or host threads, race
+ *   and must be ordered by the caller.
+ *   Output, reduction order and errors otherwise as sv_expect_hamiltonian;
+ *   the two give bitwise identical results. */
+int sv_expect_hamiltonian_noalloc(sv_state *s, const sv_hamiltonian *h, double *out_dev);
+
 /* Variational quantum deflation (Section 5.1, Eq. 12): the k-th excited
  * state minimizes <psi|H_eff|psi> with
  *   H_eff = H + sum_{j < n_proj} alpha[j] |Psi_j><Psi_j|.

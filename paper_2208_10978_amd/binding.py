@@ -61,6 +61,7 @@ def lib():
             "sv_hamiltonian_create": [_c.c_int, _vp, _vp, _i64, _c.POINTER(_vp)],
             "sv_hamiltonian_free": [_vp],
             "sv_expect_hamiltonian": [_vp, _vp, _vp],
+            "sv_expect_hamiltonian_noalloc": [_vp, _vp, _vp],
             "sv_adjoint_grad_params_h": [_vp, _vp, _vp, _vp, _vp, _i64, _vp, _vp, _i64, _vp, _vp],
             "sv_adjoint_grad_params_deflated": [_vp, _vp, _vp, _vp, _vp, ctypes.c_int, _vp, _vp, _i64, _vp, _vp,
                                                 _i64, _vp, _vp, _vp],
@@ -84,7 +85,7 @@ EXPORTED = (
     "sv_alloc", "sv_free", "sv_set_stream", "sv_set_real_hint", "sv_inject_device_failure", "sv_prepare_hf",
     "sv_apply_pauli_rotations",
     "sv_expect_pauli_sum", "sv_adjoint_grad", "sv_adjoint_grad_params", "sv_hamiltonian_create",
-    "sv_hamiltonian_free", "sv_expect_hamiltonian", "sv_adjoint_grad_params_h",
+    "sv_hamiltonian_free", "sv_expect_hamiltonian", "sv_expect_hamiltonian_noalloc", "sv_adjoint_grad_params_h",
     "sv_adjoint_grad_params_deflated", "sv_overlap", "sv_normalize",
     "sv_gather_amplitudes", "sv_profile_begin", "sv_profile_end", "sv_last_error",
 )
@@ -212,6 +213,10 @@ def sv_hamiltonian_free(h):
 
 def sv_expect_hamiltonian(s, h, out_dev):
     _check(lib().sv_expect_hamiltonian(s, h, _dev(out_dev)))
+
+
+def sv_expect_hamiltonian_noalloc(s, h, out_dev):
+    _check(lib().sv_expect_hamiltonian_noalloc(s, h, _dev(out_dev)))
 
 
 def sv_adjoint_grad_params_h(psi, lam, h, rx, rz, phi, param_of_rot, dphi_dtheta, n_params, energy_dev,

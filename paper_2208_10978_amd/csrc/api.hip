@@ -623,14 +623,21 @@ static double group_bytes(const sv_state* s, const GroupDesc& g, bool lambda) {
   return touched * amp * (lambda ? 3.0 : 1.0);
 }
 
+// FP64 scratch of one expectation: the partial sums of its tile passes,
+// whole-state group passes and norm/diagonal reductions, then four values
+static size_t expect_scratch_doubles(const sv_state* s, const HTiling& ht, size_t* n_h) {
+  const uint64_t n_tb = uint64_t(1) << ht.frames[0].n_comp;
+  const uint32_t bpt = uint32_t(std::min<uint64_t>(n_tb, uint64_t(num_cus())));
+  *n_h = ht.frames.size() * size_t(bpt) + ht.groups.size() * size_t(full_grid(s->amp_count() / 2));
+  return *n_h + 3 * size_t(dot_grid(s)) + 4;
+}
+
+// The launches of an expectation (tables and diagonal already resident):
+// part holds the partial sums (expect_scratch_doubles), sm four more
+// doubles; every entry read is written first, so neither needs clearing.
 // out_dev[0] = <psi|H|psi>/<psi|psi>, out_dev[1] = <psi|psi>
-static int expect_impl(sv_state* s, sv_hamiltonian* h, double* out_dev) {
-  DevTiling* t = nullptr;
-  int rc = tiling_get(h, s->dtype, 0, &t);
-  if (rc) return rc;
-  const double* diag = nullptr;
-  rc = diag_get(h, s->stream, &diag);
-  if (rc) return rc;
+static int expect_launch(sv_state* s, const DevTiling* t, const double* diag, double* part, double* sm,
+                         double* out_dev) {
   const HTiling& ht = t->host;
   const int T = int(ht.frames.size());
   const uint64_t n_tb = uint64_t(1) << ht.frames[0].n_comp;
@@ -639,12 +646,6 @@ static int expect_impl(sv_state* s, sv_hamiltonian* h, double* out_dev) {
   const int gfull = full_grid(s->amp_count() / 2);
   const int gdot = dot_grid(s);
   const size_t n_h = size_t(T) * bpt + n_full * size_t(gfull);
-  rc = s->scratch.ensure((n_h + 3 * size_t(gdot) + 8) * sizeof(double), s->stream);
-  if (rc) return rc;
-  rc = s->small.ensure(16 * sizeof(double), s->stream);
-  if (rc) return rc;
-  double* part = static_cast<double*>(s->scratch.p);
-  double* sm = static_cast<double*>(s->small.p);
   hipError_t e;
   const uint4* blobs = dptr<uint4>(t->buf, t->o_blob);
   for (int tt = 0; tt < T; ++tt) {
@@ -673,6 +674,49 @@ static int expect_impl(sv_state* s, sv_hamiltonian* h, double* out_dev) {
   HIP_TRY(launch_reduce_rows(dpart + 2 * gdot, 0, uint32_t(gdot), 1, sm + 1, s->stream));
   HIP_TRY(launch_reduce_rows(dpart + gdot, 0, uint32_t(gdot), 1, sm + 2, s->stream));
   HIP_TRY(launch_finish_energy(sm, 2, sm + 2, out_dev, s->stream));
+  return SV_OK;
+}
+
+// out_dev[0] = <psi|H|psi>/<psi|psi>, out_dev[1] = <psi|psi>
+static int expect_impl(sv_state* s, sv_hamiltonian* h, double* out_dev) {
+  DevTiling* t = nullptr;
+  int rc = tiling_get(h, s->dtype, 0, &t);
+  if (rc) return rc;
+  const double* diag = nullptr;
+  rc = diag_get(h, s->stream, &diag);
+  if (rc) return rc;
+  size_t n_h = 0;
+  const size_t need = expect_scratch_doubles(s, t->host, &n_h);
+  rc = s->scratch.ensure((need + 8) * sizeof(double), s->stream);
+  if (rc) return rc;
+  double* part = static_cast<double*>(s->scratch.p);
+  return expect_launch(s, t, diag, part, part + (need - 4), out_dev);
+}
+
+// ---------------------------------------------------------------------------
+// Scratch of the allocation-free expectation (sv_expect_hamiltonian_noalloc):
+// device memory held by the code object itself, one copy per device for the
+// life of the process.  Host code never names the array (on the host its
+// name is only a stand-in); it uses the device address looked up once per
+// device, with that device current.
+// ---------------------------------------------------------------------------
+constexpr size_t kNoAllocDoubles = size_t(1) << 18;   // 2 MiB of FP64 partials
+static __device__ __align__(256) double noalloc_scratch[kNoAllocDoubles];
+
+static std::mutex g_noalloc_mu;
+static double* g_noalloc_ptr[kMaxDevices] = {};
+
+static int noalloc_scratch_of(int dev, double** out) {
+  if (dev < 0 || dev >= kMaxDevices) return fail(SV_EINVAL, "device index out of range");
+  std::lock_guard<std::mutex> lk(g_noalloc_mu);
+  if (!g_noalloc_ptr[dev]) {
+    void* p = nullptr;
+    const hipError_t e = hipGetSymbolAddress(&p, HIP_SYMBOL(noalloc_scratch));
+    if (e != hipSuccess || !p)
+      return device_fail(std::string("hipGetSymbolAddress(noalloc scratch): ") + hipGetErrorString(e));
+    g_noalloc_ptr[dev] = static_cast<double*>(p);
+  }
+  *out = g_noalloc_ptr[dev];
   return SV_OK;
 }
 
@@ -1066,6 +1110,37 @@ int sv_expect_hamiltonian(sv_state* s, const sv_hamiltonian* hc, double* out_dev
   if (!out_dev) return fail(SV_EINVAL, "out_dev is NULL");
   if (hc->n != s->n) return fail(SV_EINVAL, "Pauli sum and state differ in n");
   return expect_impl(s, const_cast<sv_hamiltonian*>(hc), out_dev);
+}
+
+int sv_expect_hamiltonian_noalloc(sv_state* s, const sv_hamiltonian* hc, double* out_dev) {
+  if (!s || !hc) return fail(SV_EINVAL, "NULL argument");
+  Call call(s);
+  if (call.rc) return call.rc;
+  if (!out_dev) return fail(SV_EINVAL, "out_dev is NULL");
+  if (hc->n != s->n) return fail(SV_EINVAL, "Pauli sum and state differ in n");
+  sv_hamiltonian* h = const_cast<sv_hamiltonian*>(hc);
+  const DevTiling* t = nullptr;
+  const double* diag = nullptr;
+  {
+    // the resident tables and diagonal must exist already: building them allocates
+    std::lock_guard<std::mutex> lk(h->mu);
+    if (!h->built[s->dtype][0] || (!h->diag_z.empty() && !h->diag_built))
+      return fail(SV_EINVAL,
+                  "the Pauli sum's expectation tables for this dtype are not built yet (one sv_expect_hamiltonian "
+                  "call with a state of this dtype builds them)");
+    t = &h->tilings[s->dtype][0];
+    if (!h->diag_z.empty()) diag = static_cast<const double*>(h->diag_dev.p);
+  }
+  size_t n_h = 0;
+  const size_t need = expect_scratch_doubles(s, t->host, &n_h);
+  if (need > kNoAllocDoubles)
+    return fail(SV_EINVAL, "the expectation needs " + std::to_string(need) + " FP64 partials, more than the " +
+                               std::to_string(kNoAllocDoubles) + " of the allocation-free scratch");
+  double* part = nullptr;
+  int rc = noalloc_scratch_of(s->device, &part);
+  if (rc) return rc;
+  if (diag) HIP_TRY(hipStreamWaitEvent(s->stream, h->diag_ready, 0));
+  return expect_launch(s, t, diag, part, part + (need - 4), out_dev);
 }
 
 int sv_adjoint_grad(sv_state* psi, sv_state* lam, const sv_pauli* hp, const double* hcoef, int64_t n_terms,
