@@ -428,6 +428,8 @@ def main():
     ap.add_argument("--copy-calibration", action="store_true",
                     help="only run a plain 4 GiB device copy three times (calibrates HBM byte counters)")
     ap.add_argument("--serve-requests", type=int, default=40)
+    ap.add_argument("--only-c4", action="store_true",
+                    help="only the 32-qubit complex64 figures (for counter runs of the expectation)")
     args = ap.parse_args()
     if args.gpus != 1:
         print(json.dumps({"error": "q2sv runs on one GPU: --gpus must be 1 (the sharded design is described, not built)"}))
@@ -442,6 +444,9 @@ def main():
         torch.cuda.synchronize()
         print(json.dumps({"copy_calibration": {"bytes_read_per_copy": a.numel() * 16,
                                                "bytes_written_per_copy": a.numel() * 16, "copies": 3}}))
+        return
+    if args.only_c4:
+        print(json.dumps({"c4": bench_c4(args.c4_rotations, 10_000)}), flush=True)
         return
     from paper_2208_10978_amd import binding as B
     from paper_2208_10978_amd.engine import UCCSDEvaluator

@@ -9,7 +9,16 @@
  * Section 5.1 Eq. 10-11, Algorithm 1):
  *   - A state on n qubits is 2^n complex amplitudes; qubit q is bit q of the
  *     amplitude index (little-endian).  Amplitudes are interleaved (re, im):
- *     complex128 (SV_C128, 16 bytes) or complex64 (SV_C64, 8 bytes).
+ *     complex128 (SV_C128, 16 bytes) or complex64 (SV_C64, 8 bytes).  A real
+ *     state (SV_R64) stores only the real parts, FP64 (8 bytes): the
+ *     amplitudes of a circuit of real rotations started from a basis state
+ *     (every Trotterised UCC circuit: each of its strings has an odd number
+ *     of Y factors, so each rotation is a real orthogonal matrix).  It takes
+ *     only real rotations (odd popcount(x & z); others are SV_EINVAL), and
+ *     its adjoint calls take only sums that map real vectors to real vectors
+ *     (every c_t i^{popcount(x_t & z_t)} real; others are SV_EINVAL).
+ *     Results equal those of the complex128 state (whose imaginary parts are
+ *     then exactly zero) up to rounding order, with half the bytes moved.
  *   - A Pauli string is sv_pauli {x, z}: bit q of x is set when the factor on
  *     qubit q is X or Y, bit q of z when it is Z or Y.  The operator is
  *     P = i^{popcount(x & z)} X^x Z^z, the plain tensor product of the
@@ -63,7 +72,7 @@ typedef struct sv_state sv_state;             /* opaque: one state vector      *
 typedef struct sv_hamiltonian sv_hamiltonian; /* opaque: resident Pauli sum    */
 typedef struct { uint64_t x, z; } sv_pauli;
 
-enum { SV_C128 = 0, SV_C64 = 1 };
+enum { SV_C128 = 0, SV_C64 = 1, SV_R64 = 2 };
 enum { SV_OK = 0, SV_EINVAL = -1, SV_ENOMEM = -2, SV_EDEVICE = -3, SV_EBUSY = -4 };
 
 /* Largest supported qubit count (a 2^34 complex128 state is 256 GiB). */
@@ -71,7 +80,7 @@ enum { SV_OK = 0, SV_EINVAL = -1, SV_ENOMEM = -2, SV_EDEVICE = -3, SV_EBUSY = -4
 
 /* Bind a caller-owned device buffer as an n-qubit state (Eq. 7).
  *   n_qubits   1..SV_MAX_QUBITS
- *   dtype      SV_C128 or SV_C64
+ *   dtype      SV_C128, SV_C64 or SV_R64
  *   amps       device pointer, 16-byte aligned, at least 2^n amplitudes
  *   amps_bytes size of that buffer in bytes (checked against 2^n * 16 or 8)
  *   hip_stream hipStream_t on which all work of this handle is enqueued
@@ -99,6 +108,17 @@ int sv_set_stream(sv_state *s, void *hip_stream);
  * wrong).  psi_is_real = 0 (the default) restores the checked choice with
  * its one stream wait.  The declaration stays until changed. */
 int sv_set_real_hint(sv_state *s, int psi_is_real);
+
+/* Choose how the adjoint calls build lambda = H psi (Algorithm 1).
+ * on = 0 (the default): the fast build, in which the wavefronts of a block
+ * add into shared FP64 accumulators with atomic adds; their order is not
+ * fixed, so lambda and the energy and gradient computed from it may differ
+ * between runs in the last bits (about 1e-16 relative in FP64).
+ * on = 1: the reproducible build, in which every accumulator element is
+ * owned by one wavefront and summed in a fixed group order, so repeated
+ * calls, and a request alone or among concurrent ones, are bitwise equal;
+ * lambda then takes about twice as long.  The choice stays until changed. */
+int sv_set_deterministic(sv_state *s, int on);
 
 /* psi <- |occ_mask>, the Hartree-Fock determinant of Eq. 6 as a basis state
  * (occupation of qubit q = bit q).  occ_mask < 2^n. */

@@ -17,6 +17,7 @@ LIB_PATH = os.path.join(os.path.dirname(os.path.abspath(__file__)), "libq2sv.so"
 
 SV_C128 = 0
 SV_C64 = 1
+SV_R64 = 2
 SV_OK, SV_EINVAL, SV_ENOMEM, SV_EDEVICE, SV_EBUSY = 0, -1, -2, -3, -4
 SV_MAX_QUBITS = 34
 
@@ -52,6 +53,7 @@ def lib():
             "sv_free": [_vp],
             "sv_set_stream": [_vp, _vp],
             "sv_set_real_hint": [_vp, _c.c_int],
+            "sv_set_deterministic": [_vp, _c.c_int],
             "sv_inject_device_failure": [_c.c_char_p],
             "sv_prepare_hf": [_vp, _c.c_uint64],
             "sv_apply_pauli_rotations": [_vp, _vp, _vp, _i64],
@@ -82,7 +84,8 @@ def lib():
 
 
 EXPORTED = (
-    "sv_alloc", "sv_free", "sv_set_stream", "sv_set_real_hint", "sv_inject_device_failure", "sv_prepare_hf",
+    "sv_alloc", "sv_free", "sv_set_stream", "sv_set_real_hint", "sv_set_deterministic", "sv_inject_device_failure",
+    "sv_prepare_hf",
     "sv_apply_pauli_rotations",
     "sv_expect_pauli_sum", "sv_adjoint_grad", "sv_adjoint_grad_params", "sv_hamiltonian_create",
     "sv_hamiltonian_free", "sv_expect_hamiltonian", "sv_expect_hamiltonian_noalloc", "sv_adjoint_grad_params_h",
@@ -136,7 +139,7 @@ def _stream_handle(stream):
 # C functions with the same names
 # --------------------------------------------------------------------------
 def sv_alloc(n_qubits: int, dtype: int, amps, stream=None):
-    """``amps``: contiguous complex128/complex64 device tensor of >= 2^n entries."""
+    """``amps``: contiguous complex128/complex64/float64 device tensor of >= 2^n entries."""
     if not amps.is_contiguous():
         raise ValueError("amps must be contiguous")
     h = _vp()
@@ -155,6 +158,10 @@ def sv_set_stream(s, stream):
 
 def sv_set_real_hint(s, psi_is_real: bool):
     _check(lib().sv_set_real_hint(s, int(bool(psi_is_real))))
+
+
+def sv_set_deterministic(s, on):
+    _check(lib().sv_set_deterministic(s, 1 if on else 0))
 
 
 def sv_inject_device_failure(msg: str = ""):

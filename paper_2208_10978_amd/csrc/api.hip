@@ -256,8 +256,11 @@ struct sv_hamiltonian {
   bool real = true;                  // every group coefficient is real (then a real psi gives a real lambda)
   std::vector<uint64_t> diag_z;      // diagonal (x = 0) terms
   std::vector<double> diag_c;
-  DevTiling tilings[2][3];           // [dtype][role: 0 expectation, 1 lambda, 2 real lambda]
-  bool built[2][3] = {{false, false, false}, {false, false, false}};
+  // [dtype][role]: 0 expectation; lambda 1 complex, 2 real-part tiles (fast
+  // builds), 3 complex, 4 real-part tiles (reproducible builds)
+  static constexpr int kRoles = 5;
+  DevTiling tilings[3][kRoles];
+  bool built[3][kRoles] = {};
   DevBuf diag_dev;                   // resident diagonal d[m], FP64, 2^n entries
   bool diag_built = false;
   hipEvent_t diag_ready = nullptr;   // recorded after the diagonal's build
@@ -279,11 +282,11 @@ static int tiling_get(sv_hamiltonian* h, int dtype, int role, DevTiling** out) {
   std::lock_guard<std::mutex> lk(h->mu);
   DevTiling& t = h->tilings[dtype][role];
   if (!h->built[dtype][role]) {
-    const int b = role == 0 ? tile_bits_one(dtype) : role == 1 ? tile_bits_lambda(dtype) : kTileLamReal;
-    const int c = std::min(dtype == 0 ? 3 : 4, h->n);
+    const int b = role == 0 ? tile_bits_one(dtype) : (role == 1 || role == 3) ? tile_bits_lambda(dtype) : kTileLamReal;
+    const int c = std::min(row_bits(dtype), h->n);
     // kernels read the tables through scalar loads, so a tile's groups need
     // not be split
-    t.host = build_tiling(h->groups, h->n, b, c, true, size_t(1) << 24);
+    t.host = build_tiling(h->groups, h->n, b, c, true, size_t(1) << 24, role >= 3 ? kLambdaRegionBits : 0);
     if (t.host.blob_overflow) return fail(SV_EINVAL, "internal: a tile's group tables are too large");
     Packer pk;
     t.o_frames = pk.add(t.host.frames.data(), t.host.frames.size() * sizeof(FrameDesc));
@@ -346,6 +349,11 @@ static int validate_paulis(const sv_pauli* p, int64_t n, int nq, const char* wha
   return SV_OK;
 }
 
+// A real state (SV_R64) stays real only under real rotations: R(P, phi) is a
+// real matrix exactly when P = i^{|x&z|} X^x Z^z is imaginary, i.e. when
+// |x & z| (the number of Y factors) is odd.
+static int validate_real_rotations(const sv_state* s, const sv_pauli* p, int64_t n);
+
 static int validate_finite(const double* v, int64_t n, const char* what) {
   if (n > 0 && !v) return fail(SV_EINVAL, std::string(what) + ": NULL array");
   for (int64_t k = 0; k < n; ++k)
@@ -404,10 +412,29 @@ struct sv_state {
   double* host_word = nullptr;  // pinned FP64 word for a device value the host must read
   sv_hamiltonian* cached_h = nullptr;  // last Pauli sum passed as raw arrays
   bool real_hint = false;              // the caller asserts psi is real on entry to the adjoint calls
+  bool deterministic = false;          // lambda by the reproducible build
   std::atomic<int> busy{0};            // a call on this handle is in progress
   uint64_t amp_count() const { return uint64_t(1) << n; }
-  double bytes() const { return double(amp_count()) * (dtype == SV_C128 ? 16.0 : 8.0); }
+  double bytes() const { return double(amp_count()) * double(amp_bytes(dtype)); }
 };
+
+static int validate_real_rotations(const sv_state* s, const sv_pauli* p, int64_t n) {
+  if (s->dtype != SV_R64) return SV_OK;
+  for (int64_t k = 0; k < n; ++k)
+    if (!(__builtin_popcountll(p[k].x & p[k].z) & 1))
+      return fail(SV_EINVAL, "rotation[" + std::to_string(k) +
+                                 "] is not real (its string has an even number of Y factors); a real state takes "
+                                 "only real rotations");
+  return SV_OK;
+}
+
+// The adjoint calls on a real state need lambda = H psi real: every group
+// coefficient of the sum real.
+static int validate_real_sum(const sv_state* s, const sv_hamiltonian* h) {
+  if (s->dtype != SV_R64 || h->real) return SV_OK;
+  return fail(SV_EINVAL, "a real state's adjoint needs a Pauli sum that maps real vectors to real vectors "
+                         "(every c i^{|x&z|} real)");
+}
 
 struct DeviceGuard {
   int prev = -1;
@@ -502,9 +529,9 @@ static void plan_rotations(const sv_state* s, const sv_pauli* p, const double* p
   for (size_t r = 0; r < pl.runs.size(); ++r)
     pl.data[r] = build_run_data(pl.runs[r], pin, phi, dphi, reverse ? grad_mode : 0);
   const int b = reverse ? tile_bits_two(s->dtype) : tile_bits_one(s->dtype);
-  const int c = std::min(s->dtype == 0 ? 3 : 4, s->n);
+  const int c = std::min(row_bits(s->dtype), s->n);
   const int slots_per_run = grad_mode == 1 ? 1 : 0;
-  pl.passes = schedule(pl.runs, pl.data, s->n, b, c, reverse, reverse && grad_mode ? kMaxPassSlots : 0,
+  pl.passes = schedule(pl.runs, pl.data, pin, s->n, b, c, reverse, reverse && grad_mode ? kMaxPassSlots : 0,
                        slots_per_run, kMaxPassRuns, kMaxPassRecs);
 }
 
@@ -512,7 +539,7 @@ static void plan_rotations(const sv_state* s, const sv_pauli* p, const double* p
 // imag_count: see launch_tile_reverse (reverse sweeps only; NULL otherwise)
 static int launch_rotations(sv_state* s, sv_state* lam, const RotPlan& pl, bool rev, int grad_mode,
                             double* partials, const double* imag_count = nullptr) {
-  const int c = std::min(s->dtype == 0 ? 3 : 4, s->n);
+  const int c = std::min(row_bits(s->dtype), s->n);
   // descriptors and records of every pass, one upload
   std::vector<RunDesc> descs;
   std::vector<RunRec> recs;
@@ -738,9 +765,9 @@ static int lambda_impl(sv_state* s, sv_state* lam, sv_hamiltonian* h, double* en
   // the state's stream to read the count.  Only states whose real-part tiles
   // still give every compute unit a block (2^(n - kTileLamReal) >= CUs) take
   // the real build; smaller ones keep the complex build and skip the count.
-  bool real = false;
+  bool real = s->dtype == SV_R64;  // a real state: lambda is real (the sum was checked to be real)
   const double* guard = nullptr;
-  if (h->real && s->n > kTileLamReal && (uint64_t(1) << (s->n - kTileLamReal)) >= uint64_t(num_cus())) {
+  if (!real && h->real && s->n > kTileLamReal && (uint64_t(1) << (s->n - kTileLamReal)) >= uint64_t(num_cus())) {
     {
       ProfScope prof(s->stream, kPDot, s->bytes());
       HIP_TRY(launch_imag_count(s->dtype, s->amps, s->amp_count(), gdot, part, s->stream));
@@ -762,7 +789,8 @@ static int lambda_impl(sv_state* s, sv_state* lam, sv_hamiltonian* h, double* en
     }
   }
   DevTiling* t = nullptr;
-  rc = tiling_get(h, s->dtype, real ? 2 : 1, &t);
+  const bool det = s->deterministic;
+  rc = tiling_get(h, s->dtype, real ? (det ? 4 : 2) : (det ? 3 : 1), &t);
   if (rc) return rc;
   const double* diag = nullptr;
   rc = diag_get(h, s->stream, &diag);
@@ -774,7 +802,7 @@ static int lambda_impl(sv_state* s, sv_state* lam, sv_hamiltonian* h, double* en
     const uint64_t n_tb = uint64_t(1) << fr.n_comp;
     const int grid = int(std::min<uint64_t>(n_tb, uint64_t(num_cus())));
     ProfScope prof(s->stream, kPTileHLam, (tt == 0 ? (diag ? 2.5 : 2.0) : 3.0) * s->bytes());
-    const hipError_t e = launch_tile_lambda(s->dtype, tt == 0, real, s->amps, lam->amps, diag, fr,
+    const hipError_t e = launch_tile_lambda(s->dtype, tt == 0, real, det, s->amps, lam->amps, diag, fr,
                                             dptr<uint4>(t->buf, t->o_blob) + ht.blob_off[tt], n_tb, grid, guard,
                                             s->stream);
     if (e != hipSuccess) return device_fail(std::string("lambda tile: ") + hipGetErrorString(e));
@@ -847,7 +875,11 @@ static int adjoint_impl(sv_state* psi, sv_state* lam, sv_hamiltonian* h, const s
                         int64_t n_rot, const int32_t* param, const double* dphi, int64_t n_params,
                         double* energy_dev, double* grad_dev, const ProjArgs* defl = nullptr,
                         double* ovl_dev = nullptr) {
-  int rc = lambda_impl(psi, lam, h, energy_dev);
+  int rc = validate_real_rotations(psi, rp, n_rot);
+  if (rc) return rc;
+  rc = validate_real_sum(psi, h);
+  if (rc) return rc;
+  rc = lambda_impl(psi, lam, h, energy_dev);
   if (rc) return rc;
   if (defl && defl->k > 0) {
     rc = deflate_impl(psi, lam, *defl, energy_dev, ovl_dev);
@@ -859,7 +891,7 @@ static int adjoint_impl(sv_state* psi, sv_state* lam, sv_hamiltonian* h, const s
   // every run a real rotation (omega0 odd, no diagonal run): with psi and lam
   // real on entry they stay real, and the tile passes may take the real walk
   // once a device count of their nonzero imaginary parts reads zero
-  bool real_runs = !pl.runs.empty();
+  bool real_runs = !pl.runs.empty() && psi->dtype != SV_R64;  // a real state is real by construction
   for (const RunData& d : pl.data) real_runs &= d.mode != kRunDiag && (d.omega0 & 1u);
   const double* imag_count = nullptr;
   if (real_runs) {
@@ -990,10 +1022,10 @@ int sv_alloc(int n_qubits, int dtype, void* amps, size_t amps_bytes, void* hip_s
   if (!out) return fail(SV_EINVAL, "out is NULL");
   *out = nullptr;
   if (n_qubits < 1 || n_qubits > SV_MAX_QUBITS) return fail(SV_EINVAL, "n_qubits out of range");
-  if (dtype != SV_C128 && dtype != SV_C64) return fail(SV_EINVAL, "unknown dtype");
+  if (dtype != SV_C128 && dtype != SV_C64 && dtype != SV_R64) return fail(SV_EINVAL, "unknown dtype");
   if (!amps) return fail(SV_EINVAL, "amps is NULL");
   if (reinterpret_cast<uintptr_t>(amps) % 16) return fail(SV_EINVAL, "amps is not 16-byte aligned");
-  const size_t need = (size_t(1) << n_qubits) * (dtype == SV_C128 ? 16 : 8);
+  const size_t need = (size_t(1) << n_qubits) * size_t(amp_bytes(dtype));
   if (amps_bytes < need) return fail(SV_EINVAL, "amps buffer smaller than 2^n amplitudes");
   int dev = 0;
   if (hipGetDevice(&dev) != hipSuccess) dev = 0;
@@ -1047,6 +1079,14 @@ int sv_set_real_hint(sv_state* s, int psi_is_real) {
   return SV_OK;
 }
 
+int sv_set_deterministic(sv_state* s, int on) {
+  if (!s) return fail(SV_EINVAL, "NULL state");
+  Call call(s);
+  if (call.rc) return call.rc;
+  s->deterministic = on != 0;
+  return SV_OK;
+}
+
 int sv_prepare_hf(sv_state* s, uint64_t occ_mask) {
   if (!s) return fail(SV_EINVAL, "NULL state");
   Call call(s);
@@ -1064,6 +1104,8 @@ int sv_apply_pauli_rotations(sv_state* s, const sv_pauli* p, const double* phi, 
   int rc = validate_paulis(p, n_rot, s->n, "rotation");
   if (rc) return rc;
   rc = validate_finite(phi, n_rot, "phi");
+  if (rc) return rc;
+  rc = validate_real_rotations(s, p, n_rot);
   if (rc) return rc;
   if (n_rot == 0) return SV_OK;
   RotPlan pl;

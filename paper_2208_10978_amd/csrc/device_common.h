@@ -5,10 +5,10 @@
 // (energy, norm, gradient) promotes products to FP64 and sums them in a fixed
 // order: per lane, then across the 64 lanes of a wavefront, then across the
 // wavefronts of a block in index order, then across blocks in index order,
-// so these sums are bitwise reproducible for given inputs.  The exception is
-// the lambda = H psi build, whose FP64 accumulator tile takes LDS atomic adds
-// from all wavefronts of a block in no fixed order: lambda, and the adjoint
-// gradient computed from it, may differ in the last bits between runs.
+// so these sums are bitwise reproducible for given inputs.  The lambda = H psi
+// build adds into an FP64 accumulator tile in which every element is owned by
+// one wavefront per segment of groups and updated in group order, so it is
+// reproducible as well.
 #pragma once
 
 #include <hip/hip_runtime.h>
@@ -19,15 +19,38 @@
 
 namespace q2sv {
 
+// A real amplitude (SV_R64): the real part alone, 8 bytes.  Its imaginary
+// part reads as a constant zero, so the complex arithmetic of every kernel
+// instantiated on it folds to real arithmetic; code that would store an
+// imaginary part stores nothing (cmake) or is written for it (is_real_amp).
+struct R64 {
+  double x;
+  static constexpr double y = 0.0;
+};
+
 template <typename T> struct Real;
 template <> struct Real<double2> { using type = double; };
 template <> struct Real<float2> { using type = float; };
+template <> struct Real<R64> { using type = double; };
+
+template <typename T> inline constexpr bool is_real_amp = false;
+template <> inline constexpr bool is_real_amp<R64> = true;
+
+// Host dispatch on the amplitude type of a state (SV_C128, SV_C64, SV_R64):
+// f receives a value of that type and launches with it.
+template <typename F>
+inline hipError_t by_dtype(int dtype, F&& f) {
+  if (dtype == 0) f(double2{});
+  else if (dtype == 1) f(float2{});
+  else f(R64{});
+  return hipGetLastError();
+}
 
 template <typename V>
 __device__ __forceinline__ V cmake(typename Real<V>::type re, typename Real<V>::type im) {
   V v;
   v.x = re;
-  v.y = im;
+  if constexpr (!is_real_amp<V>) v.y = im;
   return v;
 }
 
@@ -213,6 +236,14 @@ __device__ __forceinline__ uint32_t deposit_bits(uint32_t v, uint32_t mask) {
   return out;
 }
 
+// this wavefront's region bits: its index deposited into a segment's mask
+__device__ __forceinline__ uint32_t region_bits_of(uint32_t wb_mask, uint32_t wave) {
+  uint32_t wbits = 0;
+  int j = 0;
+  for (uint32_t m = wb_mask; m; m &= m - 1, ++j) wbits |= ((wave >> j) & 1u) << (__ffs(m) - 1);
+  return wbits;
+}
+
 template <typename T, int PER, int NT>
 __device__ __forceinline__ void tile_fetch(const T* __restrict__ src, const FrameLut& lut, uint64_t base,
                                            uint32_t nloc, Stage<T, PER>& reg) {
@@ -343,6 +374,13 @@ __device__ __forceinline__ void rot_pair(V& a, V& b, typename Real<V>::type c, t
 //   w = Im[conj(lam[m]) beta psi[m'] + conj(lam[m']) conj(beta) psi[m]]  (FP64)
 template <typename V>
 __device__ __forceinline__ double grad_w(V pa, V pb, V la, V lb, unsigned sgn, unsigned omega0) {
+  if constexpr (is_real_amp<V>) {
+    // real values and beta = +-i (omega0 odd; an even omega0 gives a
+    // complex rotation, which a real state never takes): Im(beta) (la pb - lb pa)
+    const double w = (double)la.x * (double)pb.x - (double)lb.x * (double)pa.x;
+    const double v = (omega0 & 2u) ? -w : w;
+    return ((omega0 & 1u) == 0u) ? 0.0 : (sgn ? -v : v);
+  }
   const V tb = mul_ipow(pb, omega0 & 3u);
   const V ta = mul_ipow(pa, (4u - omega0) & 3u);
   double w = (double)la.x * (double)tb.y - (double)la.y * (double)tb.x + (double)lb.x * (double)ta.y -

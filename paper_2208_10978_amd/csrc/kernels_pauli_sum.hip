@@ -19,6 +19,7 @@ struct BlobView {
   const double2* coef;
   const TFast* fast;
   const uint32_t* items;
+  const LamSeg* segs;
   __device__ explicit BlobView(const uint4* blob) {
     const char* b = reinterpret_cast<const char*>(blob);
     hdr = reinterpret_cast<const TileHdr*>(b);
@@ -28,6 +29,7 @@ struct BlobView {
     coef = reinterpret_cast<const double2*>(b + hdr->off_coef);
     fast = reinterpret_cast<const TFast*>(b + hdr->off_fast);
     items = reinterpret_cast<const uint32_t*>(b + hdr->off_items);
+    segs = reinterpret_cast<const LamSeg*>(b + hdr->off_segs);
   }
 };
 
@@ -37,11 +39,20 @@ struct BlobView {
 // The tile's group tables stay in global memory: every index into them is
 // uniform over a wavefront, so they arrive through scalar loads into SGPRs
 // and feed the vector arithmetic directly.  Contributions land in the FP64
-// accumulator tile (real and imaginary parts in separate arrays) with LDS
-// atomic adds, which return nothing, so an update is never a load-modify-
-// store chain.  All wavefronts of the block work on the whole tile at once;
-// the order in which the updates of different wavefronts reach an output is
-// not fixed, so the last bits of lambda may differ between runs.
+// accumulator tile (real and imaginary parts in separate arrays), in one of
+// two ways:
+//   * fast (DET = false): all wavefronts of the block work on the whole tile
+//     at once and add with LDS atomic adds, which return nothing, so an
+//     update is never a load-modify-store chain; the order in which the
+//     updates of different wavefronts reach an output is not fixed, so the
+//     last bits of lambda may differ between runs;
+//   * reproducible (DET = true): the tile's groups come in segments whose
+//     flip masks avoid the segment's region bits; wavefront w owns the
+//     amplitudes whose region bits spell w, both ends of every pair it walks
+//     lie in its region, and it adds with plain LDS loads and stores, group
+//     after group, synchronising once per segment.  Every element of lambda
+//     is then summed in one fixed order, at the price of every wavefront
+//     reading every group's tables.
 // ---------------------------------------------------------------------------
 // x * (-1)^s for s in {0, 1}: flips the sign bit
 __device__ __forceinline__ double signed_by(double x, unsigned s) {
@@ -141,6 +152,34 @@ __device__ __forceinline__ void walk_fast_items(const BlobView& bv, uint32_t i0,
   }
 }
 
+// A wavefront's walk over the fast records [f0, f1) of a lambda segment, in
+// order, on its own region (region bits wbits): each record's walk covers
+// the bits outside its support and the region bits.  body(f, ds, zp, srest,
+// sgn) as for walk_fast_items, with the region's slot and parity included.
+template <typename Body>
+__device__ __forceinline__ void walk_fast_region(const BlobView& bv, uint32_t f0, uint32_t f1, uint64_t base,
+                                                 uint32_t lane, const uint32_t (&lbit)[kWalkLaneBits],
+                                                 uint32_t wbits, Body body) {
+  const uint32_t swb = lds_swz(wbits);  // uniform
+  for (uint32_t fi = f0; fi < f1; ++fi) {
+    const FastHead f = load_fast(bv.fast[fi]);
+    const bool on = f.walk_log >= kWalkLaneBits || lane < (1u << f.walk_log);
+    const uint32_t nb = f.walk_log > kWalkLaneBits ? 1u << (f.walk_log - kWalkLaneBits) : 1u;
+    uint32_t ds = 0;
+#pragma unroll
+    for (int i = 0; i < kWalkLaneBits; ++i) ds ^= lbit[i] & f.dep_q[i];
+    const unsigned zp = __popc(lane & f.wlane);
+    const unsigned so = __popcll(base & f.w_out) + __popc(wbits & f.w_loc);
+    uint32_t rest = 0;  // uniform: the block's loop bits
+    for (uint32_t blk = 0; blk < nb; ++blk) {
+      const uint32_t srest = lds_swz(rest) ^ swb;
+      const unsigned prest = __popc(rest & f.w_loc);
+      if (on) body(f, ds, zp, srest, so + prest);
+      rest = (rest - f.hi_mask) & f.hi_mask;
+    }
+  }
+}
+
 // The folded part B(base)[record] of every factored group (see TGroup): the
 // wavefront w takes the factored groups with index w mod NW (uniform loops,
 // tables through scalar loads) and leaves one FP64 complex per record in LDS.
@@ -196,44 +235,82 @@ __device__ __forceinline__ void general_g(const BlobView& bv, const TGroup& g, u
 }
 
 // The pairs (m', m = m' ^ x) of every record of a one-subgroup group at one
-// walk position (index part dl, slot part ds, w-parity of the lane part zp)
-// plus the uniform part rest: all loads first, then the updates.  The index
-// and slot of a record's m' are dl | rest | bits and ds ^ slot(rest | bits)
-// (the LDS slot map is linear).
+// walk position (slot part ds, w-parity of the lane part zp) plus the uniform
+// part rest: all loads first, then the updates.  The slot of a record's m' is
+// ds ^ slot(rest | bits) (the LDS slot map is linear).  fast_pairs_add adds
+// with LDS atomics (other wavefronts may update the same outputs);
+// fast_pairs_owned with plain loads and stores, for a caller that owns both
+// ends of every pair (no two records share a slot).
 // REAL: psi and every coefficient are real, so lambda is real; only the real
 // parts are read and accumulated (the imaginary ones are exactly zero)
-template <int NR, bool REAL, typename T>
-__device__ __forceinline__ void fast_pairs(const FastHead& f, uint32_t ds, unsigned zp, uint32_t srest, unsigned so,
-                                           const T* tp, double* tlr, double* tli) {
-  using R = typename Real<T>::type;
+template <int NR, bool REAL, typename TT>
+__device__ __forceinline__ void fast_pairs_add(const FastHead& f, uint32_t ds, unsigned zp, uint32_t srest,
+                                               unsigned so, const TT* tp, double* tlr, double* tli) {
   uint32_t smp[NR];
-  T pm[NR], pp[NR];
-  R pmx[NR], ppx[NR];
+  double pmx[NR], pmy[NR], ppx[NR], ppy[NR];
 #pragma unroll
   for (int r = 0; r < NR; ++r) {
     smp[r] = ds ^ srest ^ f.sbits[r];
-    if constexpr (REAL) {
-      pmx[r] = tp[smp[r] ^ f.sx].x;
-      ppx[r] = tp[smp[r]].x;
-    } else {
-      pm[r] = tp[smp[r] ^ f.sx];
-      pp[r] = tp[smp[r]];
+    pmx[r] = (double)tp[smp[r] ^ f.sx].x;
+    ppx[r] = (double)tp[smp[r]].x;
+    if constexpr (!REAL) {
+      pmy[r] = (double)tp[smp[r] ^ f.sx].y;
+      ppy[r] = (double)tp[smp[r]].y;
     }
   }
 #pragma unroll
   for (int r = 0; r < NR; ++r) {
     const unsigned sg = zp + f.pbits[r] + so;
     const uint32_t sm = smp[r] ^ f.sx;
+    const double gre = signed_by(f.coef[2 * r], sg);
     if constexpr (REAL) {
-      const double gre = signed_by(f.coef[2 * r], sg);
-      lds_add(&tlr[sm], gre * (double)ppx[r]);
-      lds_add(&tlr[smp[r]], gre * (double)pmx[r]);
+      lds_add(&tlr[sm], gre * ppx[r]);
+      lds_add(&tlr[smp[r]], gre * pmx[r]);
     } else {
-      const double gre = signed_by(f.coef[2 * r], sg), gim = signed_by(f.coef[2 * r + 1], sg);
-      lds_add(&tlr[sm], gre * (double)pp[r].x - gim * (double)pp[r].y);  // lam[m] += G psi[m']
-      lds_add(&tli[sm], gre * (double)pp[r].y + gim * (double)pp[r].x);
-      lds_add(&tlr[smp[r]], gre * (double)pm[r].x + gim * (double)pm[r].y);  // lam[m'] += conj(G) psi[m]
-      lds_add(&tli[smp[r]], gre * (double)pm[r].y - gim * (double)pm[r].x);
+      const double gim = signed_by(f.coef[2 * r + 1], sg);
+      lds_add(&tlr[sm], gre * ppx[r] - gim * ppy[r]);  // lam[m] += G psi[m']
+      lds_add(&tli[sm], gre * ppy[r] + gim * ppx[r]);
+      lds_add(&tlr[smp[r]], gre * pmx[r] + gim * pmy[r]);  // lam[m'] += conj(G) psi[m]
+      lds_add(&tli[smp[r]], gre * pmy[r] - gim * pmx[r]);
+    }
+  }
+}
+
+template <int NR, bool REAL, typename TT>
+__device__ __forceinline__ void fast_pairs_owned(const FastHead& f, uint32_t ds, unsigned zp, uint32_t srest, unsigned so,
+                                           const TT* tp, double* tlr, double* tli) {
+  uint32_t smp[NR];
+  double pmx[NR], pmy[NR], ppx[NR], ppy[NR];  // psi[m], psi[m']
+  double lmx[NR], lmy[NR], lpx[NR], lpy[NR];  // lam[m], lam[m']
+#pragma unroll
+  for (int r = 0; r < NR; ++r) {
+    smp[r] = ds ^ srest ^ f.sbits[r];
+    const uint32_t sm = smp[r] ^ f.sx;
+    pmx[r] = (double)tp[sm].x;
+    ppx[r] = (double)tp[smp[r]].x;
+    lmx[r] = tlr[sm];
+    lpx[r] = tlr[smp[r]];
+    if constexpr (!REAL) {
+      pmy[r] = (double)tp[sm].y;
+      ppy[r] = (double)tp[smp[r]].y;
+      lmy[r] = tli[sm];
+      lpy[r] = tli[smp[r]];
+    }
+  }
+#pragma unroll
+  for (int r = 0; r < NR; ++r) {
+    const unsigned sg = zp + f.pbits[r] + so;
+    const uint32_t sm = smp[r] ^ f.sx;
+    const double gre = signed_by(f.coef[2 * r], sg);
+    if constexpr (REAL) {
+      tlr[sm] = lmx[r] + gre * ppx[r];
+      tlr[smp[r]] = lpx[r] + gre * pmx[r];
+    } else {
+      const double gim = signed_by(f.coef[2 * r + 1], sg);
+      tlr[sm] = lmx[r] + (gre * ppx[r] - gim * ppy[r]);  // lam[m] += G psi[m']
+      tli[sm] = lmy[r] + (gre * ppy[r] + gim * ppx[r]);
+      tlr[smp[r]] = lpx[r] + (gre * pmx[r] + gim * pmy[r]);  // lam[m'] += conj(G) psi[m]
+      tli[smp[r]] = lpy[r] + (gre * pmy[r] - gim * pmx[r]);
     }
   }
 }
@@ -249,7 +326,7 @@ template <> struct Real<RealSlot> { using type = double; };
 // values).  REAL: psi and every coefficient are real, so only real parts are
 // read and accumulated and tli is not used; TT = RealSlot keeps only the
 // real parts of psi in the tile.
-template <typename T, int B, int NT, int MODE, bool FULL, bool REAL, typename TT = T>
+template <typename T, int B, int NT, int MODE, bool FULL, bool REAL, bool DET, typename TT = T>
 __device__ __forceinline__ void lambda_tiles(const T* __restrict__ psi, T* __restrict__ lam,
                                              const double* __restrict__ diag, const FrameDesc& fr,
                                              const uint4* __restrict__ blob, uint64_t n_tb, TT* tp, double* tlr,
@@ -265,9 +342,11 @@ __device__ __forceinline__ void lambda_tiles(const T* __restrict__ psi, T* __res
   uint32_t lbit[kWalkLaneBits];  // all ones where the lane index has bit i
 #pragma unroll
   for (int i = 0; i < kWalkLaneBits; ++i) lbit[i] = 0u - ((uint32_t(lane) >> i) & 1u);
-  const uint32_t n_groups = bv.hdr->n_groups, n_items = bv.hdr->n_fast_items, n_fact = bv.hdr->n_fact;
+  const uint32_t n_groups = bv.hdr->n_groups, n_segs = bv.hdr->n_segs, n_fact = bv.hdr->n_fact;
+  const uint32_t n_items = bv.hdr->n_fast_items;
 
-  auto apply_groups = [&](uint64_t base) {
+  // fast build: every wavefront on the whole tile, LDS atomic adds
+  auto apply_groups_fast = [&](uint64_t base) {
     if (n_fact) {
       factored_base<NW>(bv, n_groups, base, wave, lane, fB);
       __syncthreads();
@@ -314,14 +393,83 @@ __device__ __forceinline__ void lambda_tiles(const T* __restrict__ psi, T* __res
                       [&](const FastHead& f, uint32_t ds, unsigned zp, uint32_t srest, unsigned sgn, bool on) {
                         if (!on) return;
                         switch (f.n_rec) {
-                          case 1: fast_pairs<1, REAL>(f, ds, zp, srest, sgn, tp, tlr, tli); break;
-                          case 2: fast_pairs<2, REAL>(f, ds, zp, srest, sgn, tp, tlr, tli); break;
-                          case 3: fast_pairs<3, REAL>(f, ds, zp, srest, sgn, tp, tlr, tli); break;
-                          default: fast_pairs<4, REAL>(f, ds, zp, srest, sgn, tp, tlr, tli); break;
+                          case 1: fast_pairs_add<1, REAL>(f, ds, zp, srest, sgn, tp, tlr, tli); break;
+                          case 2: fast_pairs_add<2, REAL>(f, ds, zp, srest, sgn, tp, tlr, tli); break;
+                          case 3: fast_pairs_add<3, REAL>(f, ds, zp, srest, sgn, tp, tlr, tli); break;
+                          default: fast_pairs_add<4, REAL>(f, ds, zp, srest, sgn, tp, tlr, tli); break;
                         }
                       });
     }
     __syncthreads();
+  };
+
+  // reproducible build: region-owned segments, plain loads and stores
+  auto apply_groups_owned = [&](uint64_t base) {
+    if (n_fact) {
+      factored_base<NW>(bv, n_groups, base, wave, lane, fB);
+      __syncthreads();
+    }
+    for (uint32_t si = 0; si < n_segs; ++si) {
+      const LamSeg sg = bv.segs[si];
+      sgpr_here(sg.wb_mask);
+      // a segment without region bits belongs to wavefront 0 alone
+      if (sg.wb_mask != 0u || wave == 0) {
+        const uint32_t wbits = region_bits_of(sg.wb_mask, uint32_t(wave));
+        // groups with several subgroups: the lanes take pairs (record,
+        // position of the bits outside S' and the region bits), G(m) summed
+        // over the subgroups
+        for (uint32_t gi = sg.g_first; gi < sg.g_first + sg.g_count; ++gi) {
+          const TGroup g = bv.groups[gi];
+          const int nf = int(fr.b) - int(g.n_sins);
+          const uint32_t n_it = g.n_rec << nf;
+          auto pair = [&](uint32_t r, uint32_t t) {
+            const uint32_t lmp = insert_zeros32_p4(t, g.sins_pack, g.n_sins) | bv.recs[g.rec_off + r] | wbits;
+            const uint32_t lm = lmp ^ g.x_loc;
+            double gre, gim;  // G(m)
+            general_g(bv, g, r, lmp, base, fB, gre, gim);
+            const uint32_t smp = lds_swz(lmp), sm = lds_swz(lm);
+            if constexpr (REAL) {
+              const double pm = (double)tp[sm].x, pp = (double)tp[smp].x;
+              const double lm0 = tlr[sm], lp0 = tlr[smp];
+              tlr[sm] = lm0 + gre * pp;
+              tlr[smp] = lp0 + gre * pm;
+            } else {
+              const T pm = tp[sm], pp = tp[smp];
+              const double lmx = tlr[sm], lmy = tli[sm], lpx = tlr[smp], lpy = tli[smp];
+              tlr[sm] = lmx + (gre * (double)pp.x - gim * (double)pp.y);  // lam[m] += G psi[m']
+              tli[sm] = lmy + (gre * (double)pp.y + gim * (double)pp.x);
+              tlr[smp] = lpx + (gre * (double)pm.x + gim * (double)pm.y);  // lam[m'] += conj(G) psi[m]
+              tli[smp] = lpy + (gre * (double)pm.y - gim * (double)pm.x);
+            }
+          };
+          if (nf >= 6) {
+            // 2^nf >= 64: a wavefront's positions share one record, so its
+            // index is uniform and the tables arrive by scalar loads
+            for (uint32_t idx = uint32_t(lane); idx < n_it; idx += 64u)
+              pair(__builtin_amdgcn_readfirstlane(idx >> nf), idx & ((1u << nf) - 1u));
+          } else {
+            for (uint32_t idx = uint32_t(lane); idx < n_it; idx += 64u) pair(idx >> nf, idx & ((1u << nf) - 1u));
+          }
+        }
+        // one-subgroup groups: a lane takes one position and every record's
+        // pair there
+        walk_fast_region(bv, sg.f_first, sg.f_first + sg.f_count, base, uint32_t(lane), lbit, wbits,
+                         [&](const FastHead& f, uint32_t ds, unsigned zp, uint32_t srest, unsigned sgn) {
+                           switch (f.n_rec) {
+                             case 1: fast_pairs_owned<1, REAL>(f, ds, zp, srest, sgn, tp, tlr, tli); break;
+                             case 2: fast_pairs_owned<2, REAL>(f, ds, zp, srest, sgn, tp, tlr, tli); break;
+                             case 3: fast_pairs_owned<3, REAL>(f, ds, zp, srest, sgn, tp, tlr, tli); break;
+                             default: fast_pairs_owned<4, REAL>(f, ds, zp, srest, sgn, tp, tlr, tli); break;
+                           }
+                         });
+      }
+      __syncthreads();
+    }
+    if (n_segs == 0) __syncthreads();
+  };
+  auto apply_groups = [&](uint64_t base) {
+    if constexpr (DET) apply_groups_owned(base);
+    else apply_groups_fast(base);
   };
 
   Stage<T, PER> rp;
@@ -444,14 +592,14 @@ __device__ __forceinline__ void lambda_tiles(const T* __restrict__ psi, T* __res
 
 // lambda = H psi over the tiles of one frame.  MODE 1 starts from the
 // diagonal part, MODE 2 adds to lam.
-template <typename T, int B, int NT, int MODE, bool FULL>
+template <typename T, int B, int NT, int MODE, bool FULL, bool DET>
 __global__ void __launch_bounds__(NT) k_tile_lambda(const T* __restrict__ psi, T* __restrict__ lam,
                                                     const double* __restrict__ diag, FrameDesc fr,
                                                     const uint4* __restrict__ blob, uint64_t n_tb) {
   __shared__ T tp[1 << B];
   __shared__ double tlr[1 << B], tli[1 << B];
   __shared__ double2 fB[kMaxFactored * kFactRecs];
-  lambda_tiles<T, B, NT, MODE, FULL, false>(psi, lam, diag, fr, blob, n_tb, tp, tlr, tli, fB);
+  lambda_tiles<T, B, NT, MODE, FULL, false, DET>(psi, lam, diag, fr, blob, n_tb, tp, tlr, tli, fB);
 }
 
 // The same for a real psi and a sum with real coefficients: lambda is real,
@@ -480,7 +628,7 @@ __device__ __forceinline__ void lambda_poison(T* __restrict__ lam, const FrameDe
   }
 }
 
-template <typename T, int B, int NT, int MODE, bool FULL>
+template <typename T, int B, int NT, int MODE, bool FULL, bool DET>
 __global__ void __launch_bounds__(NT) k_tile_lambda_real(const T* __restrict__ psi, T* __restrict__ lam,
                                                          const double* __restrict__ diag, FrameDesc fr,
                                                          const uint4* __restrict__ blob, uint64_t n_tb,
@@ -492,7 +640,7 @@ __global__ void __launch_bounds__(NT) k_tile_lambda_real(const T* __restrict__ p
     lambda_poison<T, NT>(lam, fr, n_tb);
     return;
   }
-  lambda_tiles<T, B, NT, MODE, FULL, true, RealSlot>(psi, lam, diag, fr, blob, n_tb, tp, tlr, nullptr, fB);
+  lambda_tiles<T, B, NT, MODE, FULL, true, DET, RealSlot>(psi, lam, diag, fr, blob, n_tb, tp, tlr, nullptr, fB);
 }
 
 // ---------------------------------------------------------------------------
@@ -669,9 +817,11 @@ __global__ void __launch_bounds__(256) k_group_full(const T* __restrict__ psi, T
       } else {
         T u = lam[l], v = lam[l2];
         u.x += R(gre * b.x - gim * b.y);
-        u.y += R(gre * b.y + gim * b.x);
         v.x += R(gre * a.x + gim * a.y);
-        v.y += R(gre * a.y - gim * a.x);
+        if constexpr (!is_real_amp<T>) {  // a real state takes real sums only
+          u.y += R(gre * b.y + gim * b.x);
+          v.y += R(gre * a.y - gim * a.x);
+        }
         lam[l] = u;
         lam[l2] = v;
       }
@@ -686,47 +836,52 @@ __global__ void __launch_bounds__(256) k_group_full(const T* __restrict__ psi, T
 // ---------------------------------------------------------------------------
 // launchers
 // ---------------------------------------------------------------------------
-template <typename T, int B, int M, bool RT>
+template <typename T, int B, int M, bool RT, bool DET>
 static void tile_lambda_t(const void* psi, void* lam, const double* diag, const FrameDesc& fr, const uint4* blob,
                           uint64_t n_tb, int grid, const double* guard, hipStream_t st) {
+  constexpr int NT = DET ? kLambdaDetThreads : kLambdaThreads;
   const T* p = static_cast<const T*>(psi);
   T* l = static_cast<T*>(lam);
   if constexpr (RT) {
     if (fr.b == B)
-      hipLaunchKernelGGL((k_tile_lambda_real<T, B, kLambdaThreads, M, true>), dim3(grid), dim3(kLambdaThreads), 0,
-                         st, p, l, diag, fr, blob, n_tb, guard);
+      hipLaunchKernelGGL((k_tile_lambda_real<T, B, NT, M, true, DET>), dim3(grid), dim3(NT), 0, st, p, l, diag, fr,
+                         blob, n_tb, guard);
     else
-      hipLaunchKernelGGL((k_tile_lambda_real<T, B, kLambdaThreads, M, false>), dim3(grid), dim3(kLambdaThreads), 0,
-                         st, p, l, diag, fr, blob, n_tb, guard);
+      hipLaunchKernelGGL((k_tile_lambda_real<T, B, NT, M, false, DET>), dim3(grid), dim3(NT), 0, st, p, l, diag, fr,
+                         blob, n_tb, guard);
   } else {
     if (fr.b == B)
-      hipLaunchKernelGGL((k_tile_lambda<T, B, kLambdaThreads, M, true>), dim3(grid), dim3(kLambdaThreads), 0, st, p,
-                         l, diag, fr, blob, n_tb);
+      hipLaunchKernelGGL((k_tile_lambda<T, B, NT, M, true, DET>), dim3(grid), dim3(NT), 0, st, p, l, diag, fr, blob,
+                         n_tb);
     else
-      hipLaunchKernelGGL((k_tile_lambda<T, B, kLambdaThreads, M, false>), dim3(grid), dim3(kLambdaThreads), 0, st, p,
-                         l, diag, fr, blob, n_tb);
+      hipLaunchKernelGGL((k_tile_lambda<T, B, NT, M, false, DET>), dim3(grid), dim3(NT), 0, st, p, l, diag, fr, blob,
+                         n_tb);
   }
 }
 
-hipError_t launch_tile_lambda(int dtype, bool first, bool real, const void* psi, void* lam, const double* diag,
-                              const FrameDesc& fr, const uint4* blob, uint64_t n_tb, int grid, const double* guard,
-                              hipStream_t st) {
-  if (dtype == 0) {
-    if (real) {
-      if (first) tile_lambda_t<double2, kTileLamReal, 1, true>(psi, lam, diag, fr, blob, n_tb, grid, guard, st);
-      else tile_lambda_t<double2, kTileLamReal, 2, true>(psi, lam, diag, fr, blob, n_tb, grid, guard, st);
-    } else {
-      if (first) tile_lambda_t<double2, kTileLamC128, 1, false>(psi, lam, diag, fr, blob, n_tb, grid, guard, st);
-      else tile_lambda_t<double2, kTileLamC128, 2, false>(psi, lam, diag, fr, blob, n_tb, grid, guard, st);
-    }
+template <typename T, int B, bool RT>
+static void tile_lambda_m(bool first, bool det, const void* psi, void* lam, const double* diag, const FrameDesc& fr,
+                          const uint4* blob, uint64_t n_tb, int grid, const double* guard, hipStream_t st) {
+  if (det) {
+    if (first) tile_lambda_t<T, B, 1, RT, true>(psi, lam, diag, fr, blob, n_tb, grid, guard, st);
+    else tile_lambda_t<T, B, 2, RT, true>(psi, lam, diag, fr, blob, n_tb, grid, guard, st);
   } else {
-    if (real) {
-      if (first) tile_lambda_t<float2, kTileLamReal, 1, true>(psi, lam, diag, fr, blob, n_tb, grid, guard, st);
-      else tile_lambda_t<float2, kTileLamReal, 2, true>(psi, lam, diag, fr, blob, n_tb, grid, guard, st);
-    } else {
-      if (first) tile_lambda_t<float2, kTileLamC64, 1, false>(psi, lam, diag, fr, blob, n_tb, grid, guard, st);
-      else tile_lambda_t<float2, kTileLamC64, 2, false>(psi, lam, diag, fr, blob, n_tb, grid, guard, st);
-    }
+    if (first) tile_lambda_t<T, B, 1, RT, false>(psi, lam, diag, fr, blob, n_tb, grid, guard, st);
+    else tile_lambda_t<T, B, 2, RT, false>(psi, lam, diag, fr, blob, n_tb, grid, guard, st);
+  }
+}
+
+hipError_t launch_tile_lambda(int dtype, bool first, bool real, bool det, const void* psi, void* lam,
+                              const double* diag, const FrameDesc& fr, const uint4* blob, uint64_t n_tb, int grid,
+                              const double* guard, hipStream_t st) {
+  if (dtype == 2) {  // a real state: always the real-part build
+    tile_lambda_m<R64, kTileLamReal, true>(first, det, psi, lam, diag, fr, blob, n_tb, grid, nullptr, st);
+  } else if (dtype == 0) {
+    if (real) tile_lambda_m<double2, kTileLamReal, true>(first, det, psi, lam, diag, fr, blob, n_tb, grid, guard, st);
+    else tile_lambda_m<double2, kTileLamC128, false>(first, det, psi, lam, diag, fr, blob, n_tb, grid, guard, st);
+  } else {
+    if (real) tile_lambda_m<float2, kTileLamReal, true>(first, det, psi, lam, diag, fr, blob, n_tb, grid, guard, st);
+    else tile_lambda_m<float2, kTileLamC64, false>(first, det, psi, lam, diag, fr, blob, n_tb, grid, guard, st);
   }
   return hipGetLastError();
 }
@@ -746,7 +901,8 @@ static void tile_expect_t(const void* psi, const FrameDesc& fr, const uint4* blo
 hipError_t launch_tile_expect(int dtype, const void* psi, const FrameDesc& fr, const uint4* blob, uint64_t n_tb,
                               int grid, double* partials, hipStream_t st) {
   if (dtype == 0) tile_expect_t<double2, kTileFwdC128>(psi, fr, blob, n_tb, grid, partials, st);
-  else tile_expect_t<float2, kTileFwdC64>(psi, fr, blob, n_tb, grid, partials, st);
+  else if (dtype == 1) tile_expect_t<float2, kTileFwdC64>(psi, fr, blob, n_tb, grid, partials, st);
+  else tile_expect_t<R64, kTileFwdC64>(psi, fr, blob, n_tb, grid, partials, st);
   return hipGetLastError();
 }
 
@@ -761,18 +917,15 @@ hipError_t launch_diag_build(double* d, uint64_t n_amp, const uint64_t* z, const
 hipError_t launch_group_full(int dtype, int mode, const void* psi, void* lam, const GroupDesc& g,
                              const SubDesc* subs, const double2* coef, const uint64_t* recbits, int n, int grid,
                              double* partials, hipStream_t st) {
-#define Q2SV_GF(T, M)                                                                                  \
-  hipLaunchKernelGGL((k_group_full<T, M>), dim3(grid), dim3(256), 0, st, static_cast<const T*>(psi), \
-                     static_cast<T*>(lam), g, subs, coef, recbits, n, partials)
-  if (dtype == 0) {
-    if (mode == 0) Q2SV_GF(double2, 0);
-    else Q2SV_GF(double2, 2);
-  } else {
-    if (mode == 0) Q2SV_GF(float2, 0);
-    else Q2SV_GF(float2, 2);
-  }
-#undef Q2SV_GF
-  return hipGetLastError();
+  return by_dtype(dtype, [&](auto tag) {
+    using T = decltype(tag);
+    if (mode == 0)
+      hipLaunchKernelGGL((k_group_full<T, 0>), dim3(grid), dim3(256), 0, st, static_cast<const T*>(psi),
+                         static_cast<T*>(lam), g, subs, coef, recbits, n, partials);
+    else
+      hipLaunchKernelGGL((k_group_full<T, 2>), dim3(grid), dim3(256), 0, st, static_cast<const T*>(psi),
+                         static_cast<T*>(lam), g, subs, coef, recbits, n, partials);
+  });
 }
 
 }  // namespace q2sv

@@ -531,14 +531,6 @@ __device__ __forceinline__ void tile_run(const RunDesc& run, const RunRec* __res
   }
 }
 
-// this wavefront's region bits: its index deposited into the segment's mask
-__device__ __forceinline__ uint32_t region_bits_of(uint32_t wb_mask, uint32_t wave) {
-  uint32_t wbits = 0;
-  int j = 0;
-  for (uint32_t m = wb_mask; m; m &= m - 1, ++j) wbits |= ((wave >> j) & 1u) << (__ffs(m) - 1);
-  return wbits;
-}
-
 // ---------------------------------------------------------------------------
 // LDS tile, forward: load, apply every run of the pass, store.  Within a
 // segment each wavefront runs through the segment's runs on its own region;
@@ -772,18 +764,18 @@ static hipError_t run_full_t(bool rev, int grad, void* psi, void* lam, const Run
 hipError_t launch_fill_basis(int dtype, void* psi, uint64_t n_amp, uint64_t k, hipStream_t st) {
   const uint64_t want = (n_amp + 255) / 256;
   const int grid = int(want < 4096 ? (want ? want : 1) : 4096);
-  if (dtype == 0)
-    hipLaunchKernelGGL((k_fill_basis<double2>), dim3(grid), dim3(256), 0, st, static_cast<double2*>(psi), n_amp, k);
-  else
-    hipLaunchKernelGGL((k_fill_basis<float2>), dim3(grid), dim3(256), 0, st, static_cast<float2*>(psi), n_amp, k);
-  return hipGetLastError();
+  return by_dtype(dtype, [&](auto tag) {
+    using T = decltype(tag);
+    hipLaunchKernelGGL((k_fill_basis<T>), dim3(grid), dim3(256), 0, st, static_cast<T*>(psi), n_amp, k);
+  });
 }
 
 hipError_t launch_run_full(int dtype, bool rev, int grad, void* psi, void* lam, const RunDesc& run,
                            const RunRec* recs, double* partials, int n, uint32_t nb_stride, int grid,
                            hipStream_t st) {
   if (dtype == 0) return run_full_t<double2>(rev, grad, psi, lam, run, recs, partials, n, nb_stride, grid, st);
-  return run_full_t<float2>(rev, grad, psi, lam, run, recs, partials, n, nb_stride, grid, st);
+  if (dtype == 1) return run_full_t<float2>(rev, grad, psi, lam, run, recs, partials, n, nb_stride, grid, st);
+  return run_full_t<R64>(rev, grad, psi, lam, run, recs, partials, n, nb_stride, grid, st);
 }
 
 template <typename T, int B>
@@ -802,7 +794,8 @@ static hipError_t tile_forward_t(void* psi, const FrameDesc& fr, const RunDesc* 
 hipError_t launch_tile_forward(int dtype, void* psi, const FrameDesc& fr, const RunDesc* runs, const RunRec* recs,
                                const SegDesc* segs, int n_segs, uint64_t n_tb, int grid, hipStream_t st) {
   if (dtype == 0) return tile_forward_t<double2, kTileFwdC128>(psi, fr, runs, recs, segs, n_segs, n_tb, grid, st);
-  return tile_forward_t<float2, kTileFwdC64>(psi, fr, runs, recs, segs, n_segs, n_tb, grid, st);
+  if (dtype == 1) return tile_forward_t<float2, kTileFwdC64>(psi, fr, runs, recs, segs, n_segs, n_tb, grid, st);
+  return tile_forward_t<R64, kTileFwdC64>(psi, fr, runs, recs, segs, n_segs, n_tb, grid, st);
 }
 
 template <typename T, int B, int GRAD, int MAXS>
@@ -844,8 +837,11 @@ hipError_t launch_tile_reverse(int dtype, int grad, void* psi, void* lam, const 
   if (dtype == 0)
     return tile_reverse_t<double2, kTileTwoC128>(grad, psi, lam, fr, runs, recs, segs, n_segs, slot_map, n_slots,
                                                  partials, nb_stride, n_tb, grid, imag_count, st);
-  return tile_reverse_t<float2, kTileTwoC64>(grad, psi, lam, fr, runs, recs, segs, n_segs, slot_map, n_slots,
-                                             partials, nb_stride, n_tb, grid, imag_count, st);
+  if (dtype == 1)
+    return tile_reverse_t<float2, kTileTwoC64>(grad, psi, lam, fr, runs, recs, segs, n_segs, slot_map, n_slots,
+                                               partials, nb_stride, n_tb, grid, imag_count, st);
+  return tile_reverse_t<R64, kTileTwoC64>(grad, psi, lam, fr, runs, recs, segs, n_segs, slot_map, n_slots, partials,
+                                          nb_stride, n_tb, grid, nullptr, st);
 }
 
 }  // namespace q2sv

@@ -93,7 +93,7 @@ __global__ void __launch_bounds__(256) k_scale(T* __restrict__ psi, uint64_t n_a
   for (uint64_t i = uint64_t(blockIdx.x) * 256 + threadIdx.x; i < n_amp; i += stride) {
     T v = psi[i];
     v.x *= f;
-    v.y *= f;
+    if constexpr (!is_real_amp<T>) v.y *= f;
     psi[i] = v;
   }
 }
@@ -164,7 +164,7 @@ __global__ void __launch_bounds__(256) k_deflate(T* __restrict__ lam, ProjArgs p
       li += cr[j] * v.y + ci[j] * v.x;
     }
     l.x = R(lr);
-    l.y = R(li);
+    if constexpr (!is_real_amp<T>) l.y = R(li);
     lam[i] = l;
   }
 }
@@ -174,23 +174,18 @@ __global__ void __launch_bounds__(256) k_deflate(T* __restrict__ lam, ProjArgs p
 // ---------------------------------------------------------------------------
 hipError_t launch_dot(int dtype, const void* a, const void* b, const double* d, uint64_t n_amp, int grid,
                       double* partials, hipStream_t st) {
-  if (dtype == 0)
-    hipLaunchKernelGGL((k_dot<double2>), dim3(grid), dim3(256), 0, st, static_cast<const double2*>(a),
-                       static_cast<const double2*>(b), d, n_amp, partials);
-  else
-    hipLaunchKernelGGL((k_dot<float2>), dim3(grid), dim3(256), 0, st, static_cast<const float2*>(a),
-                       static_cast<const float2*>(b), d, n_amp, partials);
-  return hipGetLastError();
+  return by_dtype(dtype, [&](auto tag) {
+    using T = decltype(tag);
+    hipLaunchKernelGGL((k_dot<T>), dim3(grid), dim3(256), 0, st, static_cast<const T*>(a), static_cast<const T*>(b), d,
+                       n_amp, partials);
+  });
 }
 
 hipError_t launch_imag_count(int dtype, const void* a, uint64_t n_amp, int grid, double* partials, hipStream_t st) {
-  if (dtype == 0)
-    hipLaunchKernelGGL((k_imag_count<double2>), dim3(grid), dim3(256), 0, st, static_cast<const double2*>(a), n_amp,
-                       partials);
-  else
-    hipLaunchKernelGGL((k_imag_count<float2>), dim3(grid), dim3(256), 0, st, static_cast<const float2*>(a), n_amp,
-                       partials);
-  return hipGetLastError();
+  return by_dtype(dtype, [&](auto tag) {
+    using T = decltype(tag);
+    hipLaunchKernelGGL((k_imag_count<T>), dim3(grid), dim3(256), 0, st, static_cast<const T*>(a), n_amp, partials);
+  });
 }
 
 hipError_t launch_reduce_rows(const double* in, uint64_t stride, uint32_t len, uint32_t rows, double* out,
@@ -224,47 +219,38 @@ hipError_t launch_fill_f64(double* p, uint64_t n, double v, hipStream_t st) {
 hipError_t launch_scale(int dtype, void* psi, uint64_t n_amp, const double* norm2, hipStream_t st) {
   const uint64_t want = (n_amp + 255) / 256;
   const int grid = int(want < 4096 ? want : 4096);
-  if (dtype == 0)
-    hipLaunchKernelGGL((k_scale<double2>), dim3(grid), dim3(256), 0, st, static_cast<double2*>(psi), n_amp, norm2);
-  else
-    hipLaunchKernelGGL((k_scale<float2>), dim3(grid), dim3(256), 0, st, static_cast<float2*>(psi), n_amp, norm2);
-  return hipGetLastError();
+  return by_dtype(dtype, [&](auto tag) {
+    using T = decltype(tag);
+    hipLaunchKernelGGL((k_scale<T>), dim3(grid), dim3(256), 0, st, static_cast<T*>(psi), n_amp, norm2);
+  });
 }
 
 hipError_t launch_gather_amps(int dtype, const void* psi, const uint64_t* idx, int64_t count, double* out,
                               hipStream_t st) {
   if (count == 0) return hipSuccess;
   const int grid = int((count + 255) / 256);
-  if (dtype == 0)
-    hipLaunchKernelGGL((k_gather_amps<double2>), dim3(grid), dim3(256), 0, st,
-                       static_cast<const double2*>(psi), idx, count, out);
-  else
-    hipLaunchKernelGGL((k_gather_amps<float2>), dim3(grid), dim3(256), 0, st, static_cast<const float2*>(psi),
-                       idx, count, out);
-  return hipGetLastError();
+  return by_dtype(dtype, [&](auto tag) {
+    using T = decltype(tag);
+    hipLaunchKernelGGL((k_gather_amps<T>), dim3(grid), dim3(256), 0, st, static_cast<const T*>(psi), idx, count,
+                       out);
+  });
 }
-
 
 hipError_t launch_overlaps(int dtype, const void* psi, const ProjArgs& pa, uint64_t n_amp, int grid,
                            double* partials, hipStream_t st) {
-  if (dtype == 0)
-    hipLaunchKernelGGL((k_overlaps<double2>), dim3(grid), dim3(256), 0, st, static_cast<const double2*>(psi), pa,
-                       n_amp, partials);
-  else
-    hipLaunchKernelGGL((k_overlaps<float2>), dim3(grid), dim3(256), 0, st, static_cast<const float2*>(psi), pa,
-                       n_amp, partials);
-  return hipGetLastError();
+  return by_dtype(dtype, [&](auto tag) {
+    using T = decltype(tag);
+    hipLaunchKernelGGL((k_overlaps<T>), dim3(grid), dim3(256), 0, st, static_cast<const T*>(psi), pa, n_amp,
+                       partials);
+  });
 }
 
 hipError_t launch_deflate(int dtype, void* lam, const ProjArgs& pa, const double* ovl, uint64_t n_amp, int grid,
                           hipStream_t st) {
-  if (dtype == 0)
-    hipLaunchKernelGGL((k_deflate<double2>), dim3(grid), dim3(256), 0, st, static_cast<double2*>(lam), pa, ovl,
-                       n_amp);
-  else
-    hipLaunchKernelGGL((k_deflate<float2>), dim3(grid), dim3(256), 0, st, static_cast<float2*>(lam), pa, ovl,
-                       n_amp);
-  return hipGetLastError();
+  return by_dtype(dtype, [&](auto tag) {
+    using T = decltype(tag);
+    hipLaunchKernelGGL((k_deflate<T>), dim3(grid), dim3(256), 0, st, static_cast<T*>(lam), pa, ovl, n_amp);
+  });
 }
 
 }  // namespace q2sv

@@ -17,7 +17,8 @@ constexpr int kTileLamC128 = 12, kTileLamC64 = 12;   // psi tile + FP64 lambda a
 constexpr int kTileLamReal = 13;                      // real parts of psi + one FP64 accumulator (real lambda)
 constexpr int kTileThreads = 512;
 constexpr int kTileRegionBits = 3;                   // 8 wavefronts own 8 regions of a segment
-constexpr int kLambdaThreads = 1024;                 // 16 wavefronts share one tile
+constexpr int kLambdaThreads = 1024;                 // 16 wavefronts share one tile (fast build)
+constexpr int kLambdaDetThreads = 64 << kLambdaRegionBits;  // one wavefront per region of a segment (reproducible build)
 constexpr int kExpectThreads = 1024;                 // 16 wavefronts share one tile
 constexpr int kMaxPassSlots = 96;                    // gradient slots per reverse tile pass (24 KiB of LDS cells)
 constexpr int kMaxPassRuns = 1 << 16;                // runs per tile pass
@@ -41,13 +42,15 @@ hipError_t launch_tile_reverse(int dtype, int grad, void* psi, void* lam, const 
                                const uint32_t* slot_map, int n_slots, double* partials, uint32_t nb_stride,
                                uint64_t n_tb, int grid, const double* imag_count, hipStream_t st);
 // real: psi has no nonzero imaginary part and every coefficient of the sum is
-// real; the frames are then those of a kTileLamReal-bit tiling (role 2) and
-// lambda is built from real parts only.  guard (real builds only, may be
-// NULL): device count of psi's nonzero imaginary parts; when it is not zero
-// the pass writes NaN over lambda instead
-hipError_t launch_tile_lambda(int dtype, bool first, bool real, const void* psi, void* lam, const double* diag,
-                              const FrameDesc& fr, const uint4* blob, uint64_t n_tb, int grid, const double* guard,
-                              hipStream_t st);
+// real; the frames are then those of a kTileLamReal-bit tiling and lambda is
+// built from real parts only (always so for a real state, dtype 2).  guard
+// (real builds of complex states only, may be NULL): device count of psi's
+// nonzero imaginary parts; when it is not zero the pass writes NaN over
+// lambda instead.  det: the reproducible build (the tiling's blobs carry
+// region segments); otherwise the fast build (blobs with work items).
+hipError_t launch_tile_lambda(int dtype, bool first, bool real, bool det, const void* psi, void* lam,
+                              const double* diag, const FrameDesc& fr, const uint4* blob, uint64_t n_tb, int grid,
+                              const double* guard, hipStream_t st);
 // partials[block] = number of the block's amplitudes with a nonzero imaginary part (grid blocks of 256)
 hipError_t launch_imag_count(int dtype, const void* a, uint64_t n_amp, int grid, double* partials, hipStream_t st);
 hipError_t launch_tile_expect(int dtype, const void* psi, const FrameDesc& fr, const uint4* blob, uint64_t n_tb,
@@ -84,6 +87,12 @@ hipError_t launch_overlaps(int dtype, const void* psi, const ProjArgs& pa, uint6
 hipError_t launch_deflate(int dtype, void* lam, const ProjArgs& pa, const double* ovl, uint64_t n_amp, int grid,
                           hipStream_t st);
 
+// Bytes per amplitude: complex128 (0) 16, complex64 (1) and real FP64 (2) 8.
+inline int amp_bytes(int dtype) { return dtype == 0 ? 16 : 8; }
+// Low qubits that make a tile row one 128-byte line (always in a frame).
+inline int row_bits(int dtype) { return dtype == 0 ? 3 : 4; }
+// Tile widths follow the amplitude size (a real FP64 tile is laid out as a
+// complex64 one).
 inline int tile_bits_one(int dtype) { return dtype == 0 ? kTileFwdC128 : kTileFwdC64; }
 inline int tile_bits_two(int dtype) { return dtype == 0 ? kTileTwoC128 : kTileTwoC64; }
 inline int tile_bits_lambda(int dtype) { return dtype == 0 ? kTileLamC128 : kTileLamC64; }

@@ -345,8 +345,27 @@ double run_line_fraction(const RunData& d, int c) {
   return f < 1.0 ? f : 1.0;
 }
 
-std::vector<Pass> schedule(const std::vector<Run>& runs, const std::vector<RunData>& data, int n, int b, int c,
-                           bool reverse, int max_slots_per_pass, int slots_per_run, int max_runs, int max_recs) {
+// Do two runs commute?  Their strings share one x each (x_a, x_b) and have z
+// masks z0 ^ d, so by bilinearity of the symplectic form every pair of
+// strings commutes iff the two reference strings do, |x_a & d| is even for
+// every d of run b, and |d & x_b| is even for every d of run a.  Runs on
+// disjoint qubits always commute.
+bool runs_commute(const Run& a, const Run& b, const PauliIn* p) {
+  if (!((a.x | a.z0 | a.dmask) & (b.x | b.z0 | b.dmask))) return true;
+  if ((popc(a.x & b.z0) + popc(a.z0 & b.x)) & 1) return false;
+  for (int j = 1; j < b.count; ++j)
+    if (popc(a.x & (p[b.first + j].z ^ b.z0)) & 1) return false;
+  for (int i = 1; i < a.count; ++i)
+    if (popc((p[a.first + i].z ^ a.z0) & b.x) & 1) return false;
+  return true;
+}
+
+// fill: 0 takes consecutive runs and closes the pass at the first that does
+// not fit; 1 takes, among the eligible candidates, the one adding the fewest
+// qubits (the earliest on ties)
+static std::vector<Pass> schedule_policy(const std::vector<Run>& runs, const std::vector<RunData>& data,
+                                         const PauliIn* p, int n, int b, int c, bool reverse, int max_slots_per_pass,
+                                         int slots_per_run, int max_runs, int max_recs, int fill) {
   std::vector<Pass> out;
   const int R = int(runs.size());
   const uint64_t all = n >= 64 ? ~0ull : ((uint64_t(1) << n) - 1);
@@ -376,37 +395,98 @@ std::vector<Pass> schedule(const std::vector<Run>& runs, const std::vector<RunDa
     return out;
   }
   const uint64_t low = (uint64_t(1) << c) - 1;
-  int i = 0;
-  while (i < R) {
+  // application order: list order forward, reversed for the reverse sweep
+  auto at = [&](int i) { return reverse ? R - 1 - i : i; };
+  std::vector<char> taken(size_t(R), 0);
+  int head = 0;
+  while (head < R) {
+    while (head < R && taken[size_t(at(head))]) ++head;
+    if (head >= R) break;
+    const int first = at(head);
+    if (popc(low | runs[first].x) > b) {  // support wider than a tile: whole-state pass
+      Pass ps;
+      ps.tile = false;
+      ps.qmask = all;
+      ps.runs.push_back(first);
+      out.push_back(ps);
+      taken[size_t(first)] = 1;
+      continue;
+    }
+    // Open a pass with the first run not yet scheduled.  The candidates are
+    // the next kScheduleWindow unscheduled runs; a candidate may join while
+    // the frame, slot and record limits allow, provided it commutes with every
+    // candidate before it that is left out (the product of commuting rotations
+    // does not depend on their order, and neither do the gradients
+    // Im <lam|P|psi>, which are invariant under a rotation that commutes with
+    // P).  Members keep list order.
+    // (consecutive rule: every run from head on, as far as they fit; they are
+    // all untaken, since that rule never skips one)
+    std::vector<int> win;
+    for (int i = head; i < R && (fill == 0 || int(win.size()) < kScheduleWindow); ++i) {
+      if (taken[size_t(at(i))]) continue;
+      if (fill == 0 && popc(low | runs[size_t(at(i))].x) > b) break;
+      win.push_back(at(i));
+      if (fill == 0 && int(win.size()) > max_runs) break;
+    }
+    const int W = int(win.size());
+    std::vector<char> in(size_t(W), 0);
+    // commutation of window candidates i < j, found when first needed
+    // (0 unknown, 1 they commute, 2 they do not; the consecutive rule never
+    // asks)
+    std::vector<char> comm(fill == 0 ? 0 : size_t(W) * size_t(W), 0);
+    auto eligible = [&](int j) {
+      for (int i = 0; i < j; ++i) {
+        if (in[size_t(i)]) continue;
+        char& cm = comm[size_t(i) * size_t(W) + size_t(j)];
+        if (!cm) cm = runs_commute(runs[size_t(win[size_t(i)])], runs[size_t(win[size_t(j)])], p) ? 1 : 2;
+        if (cm == 2) return false;
+      }
+      return true;
+    };
     uint64_t q = low;
     std::vector<int> seg;
     int slots = 0, nrec = 0;
     double alone = 0.0;
-    while (i < R) {
-      const int ri = reverse ? R - 1 - i : i;
-      const uint64_t nq = q | runs[ri].x;
-      const int need = slots_per_run ? slots_per_run : runs[ri].count;
-      const int rec = int(data[ri].recs.size());
-      if (popc(nq) > b) break;
-      if (max_slots_per_pass && slots + need > max_slots_per_pass) break;
-      if (int(seg.size()) >= max_runs || nrec + rec > max_recs) break;
-      q = nq;
-      slots += need;
-      nrec += rec;
-      seg.push_back(ri);
-      alone += run_line_fraction(data[ri], c);
-      ++i;
+    auto join = [&](int j) {
+      const int ri = win[size_t(j)];
+      in[size_t(j)] = 1;
+      q |= runs[size_t(ri)].x;
+      slots += slots_per_run ? slots_per_run : runs[size_t(ri)].count;
+      nrec += int(data[size_t(ri)].recs.size());
+      seg.push_back(j);
+      taken[size_t(ri)] = 1;
+      alone += run_line_fraction(data[size_t(ri)], c);
+    };
+    join(0);  // the first unscheduled run always opens the pass
+    // can window candidate j join (frame, slots, records); how many qubits
+    // does it add
+    auto fits = [&](int j, int* added) {
+      const int ri = win[size_t(j)];
+      const uint64_t nq = q | runs[size_t(ri)].x;
+      *added = popc(nq) - popc(q);
+      const int need = slots_per_run ? slots_per_run : runs[size_t(ri)].count;
+      const int rec = int(data[size_t(ri)].recs.size());
+      return popc(nq) <= b && !(max_slots_per_pass && slots + need > max_slots_per_pass) &&
+             int(seg.size()) < max_runs && nrec + rec <= max_recs;
+    };
+    for (;;) {
+      int best = -1, best_new = 65, added = 0;
+      if (fill == 0) {
+        const int j = int(seg.size());  // the next run in order
+        if (j < W && fits(j, &added)) best = j;
+      } else {
+        for (int j = 1; j < W; ++j) {
+          if (in[size_t(j)] || !fits(j, &added) || added >= best_new || !eligible(j)) continue;
+          best = j;
+          best_new = added;
+          if (added == 0) break;
+        }
+      }
+      if (best < 0) break;
+      join(best);
     }
-    if (seg.empty()) {  // support wider than a tile: whole-state pass
-      const int ri = reverse ? R - 1 - i : i;
-      Pass ps;
-      ps.tile = false;
-      ps.qmask = all;
-      ps.runs.push_back(ri);
-      out.push_back(ps);
-      ++i;
-      continue;
-    }
+    std::sort(seg.begin(), seg.end());  // window order = application order
+    for (int& j : seg) j = win[size_t(j)];
     if (seg.size() >= 2 && alone > 1.0) {
       // fill the frame up to b qubits (extra qubits only shrink the grid)
       for (int qq = 0; qq < n && popc(q) < b; ++qq) q |= uint64_t(1) << qq;
@@ -426,6 +506,27 @@ std::vector<Pass> schedule(const std::vector<Run>& runs, const std::vector<RunDa
     }
   }
   return out;
+}
+
+std::vector<Pass> schedule(const std::vector<Run>& runs, const std::vector<RunData>& data, const PauliIn* p, int n,
+                           int b, int c, bool reverse, int max_slots_per_pass, int slots_per_run, int max_runs,
+                           int max_recs) {
+  // both fill rules; the schedule with fewer passes wins (consecutive runs
+  // suit a list ordered for locality, such as the tile-major UCCSD sequence;
+  // the fewest-qubits rule packs lists of scattered rotations)
+  std::vector<Pass> a = schedule_policy(runs, data, p, n, b, c, reverse, max_slots_per_pass, slots_per_run,
+                                        max_runs, max_recs, 0);
+  if (n <= b) return a;
+  size_t in_tiles = 0, tiles = 0;
+  for (const Pass& ps : a)
+    if (ps.tile) {
+      ++tiles;
+      in_tiles += ps.runs.size();
+    }
+  if (tiles && in_tiles >= 8 * tiles) return a;  // consecutive runs already share passes well
+  std::vector<Pass> f = schedule_policy(runs, data, p, n, b, c, reverse, max_slots_per_pass, slots_per_run,
+                                        max_runs, max_recs, 1);
+  return f.size() < a.size() ? f : a;
 }
 
 // ---------------------------------------------------------------------------
@@ -555,15 +656,81 @@ static size_t group_blob_bytes(const HGroup& g) {
 // Pack groups of one tile into a blob (TileHdr, TGroup[], record bits[], TSub[], coef[], TFast[]).
 static bool fast_group(const HGroup& g) { return g.w.size() == 1 && g.n_rec() <= kFastRecs; }
 
-static void pack_blob(HTiling& t, const std::vector<HGroup>& gs, const std::vector<int>& members, uint64_t qmask,
-                      size_t max_blob, bool use_fast) {
+std::vector<std::pair<uint32_t, std::vector<int>>> lambda_segments(const std::vector<uint32_t>& x_loc, int b,
+                                                                   int region_bits) {
+  std::vector<std::pair<uint32_t, std::vector<int>>> out;
+  std::vector<int> rest(x_loc.size());
+  for (size_t i = 0; i < rest.size(); ++i) rest[i] = int(i);
+  while (!rest.empty()) {
+    uint32_t best = 0;
+    size_t best_n = 0;
+    for (uint32_t m = (1u << b) - 1u;; --m) {
+      if (popc(uint64_t(m)) == region_bits) {
+        size_t k = 0;
+        for (int i : rest) k += (x_loc[size_t(i)] & m) == 0;
+        if (k > best_n) {
+          best_n = k;
+          best = m;
+        }
+      }
+      if (m == 0) break;
+    }
+    std::vector<int> in, left;
+    for (int i : rest) {
+      if (best_n > 0 ? (x_loc[size_t(i)] & best) == 0 : in.empty()) in.push_back(i);
+      else left.push_back(i);
+    }
+    out.push_back({best_n > 0 ? best : 0u, in});
+    rest.swap(left);
+  }
+  return out;
+}
+
+static void pack_blob(HTiling& t, const std::vector<HGroup>& gs, const std::vector<int>& members_in,
+                      uint64_t qmask, size_t max_blob, bool use_fast, int region_bits) {
   std::vector<TGroup> tg;
   std::vector<uint32_t> to;
   std::vector<TSub> ts;
   std::vector<double> co;
   std::vector<TFast> tf;
+  std::vector<LamSeg> segs;
   int n_fact = 0;
-  for (int gi : members) {
+  const int fb = popc(qmask);
+  // lambda tilings: groups in segment order (each segment: general groups,
+  // then fast records), each with its segment's region mask
+  std::vector<int> members;
+  std::vector<uint32_t> wb_of;
+  if (region_bits > 0) {
+    std::vector<uint32_t> xl;
+    for (int gi : members_in) xl.push_back(uint32_t(compress(gs[gi].x, qmask)));
+    for (const auto& sg : lambda_segments(xl, fb, region_bits)) {
+      LamSeg ls{};
+      ls.wb_mask = sg.first;
+      for (int pass = 0; pass < 2; ++pass)
+        for (int i : sg.second) {
+          const int gi = members_in[size_t(i)];
+          if ((use_fast && fast_group(gs[gi])) != (pass == 1)) continue;
+          members.push_back(gi);
+          wb_of.push_back(sg.first);
+          if (pass == 0) ls.g_count++;
+          else ls.f_count++;
+        }
+      segs.push_back(ls);
+    }
+    uint32_t g0 = 0, f0 = 0;
+    for (LamSeg& ls : segs) {
+      ls.g_first = g0;
+      ls.f_first = f0;
+      g0 += ls.g_count;
+      f0 += ls.f_count;
+    }
+  } else {
+    members = members_in;
+    wb_of.assign(members.size(), 0u);
+  }
+  for (size_t mi = 0; mi < members.size(); ++mi) {
+    const int gi = members[mi];
+    const uint32_t wb = wb_of[mi];
     const HGroup& g = gs[gi];
     if (use_fast && fast_group(g)) {
       TFast f{};
@@ -572,7 +739,7 @@ static void pack_blob(HTiling& t, const std::vector<HGroup>& gs, const std::vect
       f.n_rec = uint32_t(g.n_rec());
       f.w_loc = uint32_t(compress(g.w[0] & qmask, qmask));
       f.w_out = g.w[0] & ~qmask;
-      uint32_t free_bits = ((1u << popc(qmask)) - 1u) & ~f.sup_mask;
+      uint32_t free_bits = ((1u << fb) - 1u) & ~f.sup_mask & ~wb;
       f.walk_log = uint32_t(popc(uint64_t(free_bits)));
       uint32_t lane_p[kWalkLaneBits];
       const uint32_t on_lanes = order_lane_bits(free_bits, lane_p);
@@ -607,7 +774,7 @@ static void pack_blob(HTiling& t, const std::vector<HGroup>& gs, const std::vect
     d.sub_off = uint32_t(ts.size());
     d.coef_off = uint32_t(co.size() / 2);
     int k = 0;
-    for (uint32_t m = smask; m; m &= m - 1) d.sins_pack |= uint64_t(__builtin_ctz(m)) << (4 * k++);
+    for (uint32_t m = smask | wb; m; m &= m - 1) d.sins_pack |= uint64_t(__builtin_ctz(m)) << (4 * k++);
     d.n_sins = uint32_t(k);
     std::vector<uint32_t> rec_loc(NR);
     for (int r = 0; r < NR; ++r) rec_loc[r] = g.enumerated ? uint32_t(compress(g.rec_v[r], qmask)) : smask;
@@ -661,6 +828,7 @@ static void pack_blob(HTiling& t, const std::vector<HGroup>& gs, const std::vect
   TileHdr h{};
   h.n_groups = uint32_t(tg.size());
   h.n_fact = uint32_t(n_fact);
+  h.n_segs = uint32_t(segs.size());
   size_t off = sizeof(TileHdr) + tg.size() * sizeof(TGroup);
   h.off_rec = uint32_t(align16(off));
   off = h.off_rec + to.size() * sizeof(uint32_t);
@@ -671,10 +839,10 @@ static void pack_blob(HTiling& t, const std::vector<HGroup>& gs, const std::vect
   h.off_fast = uint32_t(align16(off));
   h.n_fast = uint32_t(tf.size());
   off = h.off_fast + tf.size() * sizeof(TFast);
-  // work items of the fast records: blocks of 64 positions of the free bits
+  // work items of the fast records (expectation tilings): blocks of 64
+  // positions of the free bits
   std::vector<uint32_t> items;
-  const int fb = popc(qmask);
-  for (size_t i = 0; i < tf.size(); ++i) {
+  for (size_t i = 0; i < tf.size() && region_bits == 0; ++i) {
     const int nf = int(tf[i].walk_log);
     const uint32_t nblk = nf > kWalkLaneBits ? (1u << (nf - kWalkLaneBits)) : 1u;
     for (uint32_t c = 0; c < nblk; ++c) items.push_back(uint32_t(i) << 12 | c);
@@ -682,6 +850,8 @@ static void pack_blob(HTiling& t, const std::vector<HGroup>& gs, const std::vect
   h.off_items = uint32_t(align16(off));
   h.n_fast_items = uint32_t(items.size());
   off = h.off_items + items.size() * sizeof(uint32_t);
+  h.off_segs = uint32_t(align16(off));
+  off = h.off_segs + segs.size() * sizeof(LamSeg);
   h.bytes = uint32_t(align16(off));
   if (h.bytes > max_blob || tf.size() >= (1u << 20) || fb > 18) t.blob_overflow = true;
   std::vector<unsigned char> bytes(h.bytes, 0);
@@ -692,6 +862,7 @@ static void pack_blob(HTiling& t, const std::vector<HGroup>& gs, const std::vect
   if (!co.empty()) std::memcpy(bytes.data() + h.off_coef, co.data(), co.size() * sizeof(double));
   if (!tf.empty()) std::memcpy(bytes.data() + h.off_fast, tf.data(), tf.size() * sizeof(TFast));
   if (!items.empty()) std::memcpy(bytes.data() + h.off_items, items.data(), items.size() * sizeof(uint32_t));
+  if (!segs.empty()) std::memcpy(bytes.data() + h.off_segs, segs.data(), segs.size() * sizeof(LamSeg));
   t.blob_off.push_back(uint32_t(t.blob.size() / 2));
   const size_t words = h.bytes / 8;
   const size_t at = t.blob.size();
@@ -699,7 +870,8 @@ static void pack_blob(HTiling& t, const std::vector<HGroup>& gs, const std::vect
   std::memcpy(t.blob.data() + at, bytes.data(), h.bytes);
 }
 
-HTiling build_tiling(const std::vector<HGroup>& gs, int n, int b, int c, bool fast_records, size_t max_blob) {
+HTiling build_tiling(const std::vector<HGroup>& gs, int n, int b, int c, bool fast_records, size_t max_blob,
+                     int region_bits) {
   HTiling t;
   t.b = b;
   t.c = c;
@@ -765,7 +937,7 @@ HTiling build_tiling(const std::vector<HGroup>& gs, int n, int b, int c, bool fa
     size_t bytes = fixed;
     auto flush = [&]() {
       t.frames.push_back(make_frame(q, n, c));
-      pack_blob(t, gs, chunk, q, max_blob, fast_records);
+      pack_blob(t, gs, chunk, q, max_blob, fast_records, region_bits);
       chunk.clear();
       bytes = fixed;
     };

@@ -91,12 +91,21 @@ struct Pass {
   std::vector<int> runs;   // in application order
 };
 
-// Greedy consecutive schedule.  forward: runs in list order; reverse: runs in
-// reverse order.  A pass becomes an LDS tile pass when it holds at least two
-// runs and is cheaper than applying its runs one by one.
-// A tile pass holds at most max_runs runs and max_recs records.
-std::vector<Pass> schedule(const std::vector<Run>& runs, const std::vector<RunData>& data, int n, int b,
-                           int c, bool reverse, int max_slots_per_pass, int slots_per_run, int max_runs,
+// Whether every string of run a commutes with every string of run b (p: the
+// rotation list the runs index).
+bool runs_commute(const Run& a, const Run& b, const PauliIn* p);
+
+// Greedy schedule.  forward: runs in list order; reverse: runs in reverse
+// order.  Each pass opens with the first unscheduled run and takes later runs
+// (within kScheduleWindow unscheduled runs) whose qubits still fit the frame,
+// as long as each commutes with every run it passes over (at most
+// kScheduleSkip of them).  A pass becomes an LDS tile pass when it holds at
+// least two runs and is cheaper than applying its runs one by one.  A tile
+// pass holds at most max_runs runs and max_recs records.
+constexpr int kScheduleWindow = 64;
+constexpr int kScheduleSkip = 16;
+std::vector<Pass> schedule(const std::vector<Run>& runs, const std::vector<RunData>& data, const PauliIn* p, int n,
+                           int b, int c, bool reverse, int max_slots_per_pass, int slots_per_run, int max_runs,
                            int max_recs);
 
 // ---------------------------------------------------------------------------
@@ -133,8 +142,21 @@ struct HTiling {
   bool blob_overflow = false;            // a blob exceeded max_blob (never expected)
 };
 
-// fast_records packs one-subgroup groups as TFast records with work items
-// (lambda tilings).
-HTiling build_tiling(const std::vector<HGroup>& gs, int n, int b, int c, bool fast_records, size_t max_blob);
+// fast_records packs one-subgroup groups as TFast records.  region_bits = 0
+// (expectation tilings): their walks cover the bits outside S' and are cut
+// into work items of 64 positions.  region_bits > 0 (lambda tilings): each
+// tile's groups are reordered into LamSeg segments whose flip masks avoid
+// region_bits frame bits, and every walk (fast records and general groups)
+// leaves its segment's region bits out.
+HTiling build_tiling(const std::vector<HGroup>& gs, int n, int b, int c, bool fast_records, size_t max_blob,
+                     int region_bits = 0);
+
+// Greedy segmentation of one lambda tile's groups (frame-local flip masks):
+// repeatedly the region mask of region_bits frame bits that the most
+// remaining groups avoid (the highest such mask on ties); groups that no
+// mask avoids form segments of their own with mask 0.  Returns, in order,
+// (mask, member indices) per segment; members keep their relative order.
+std::vector<std::pair<uint32_t, std::vector<int>>> lambda_segments(const std::vector<uint32_t>& x_loc, int b,
+                                                                   int region_bits);
 
 }  // namespace q2sv

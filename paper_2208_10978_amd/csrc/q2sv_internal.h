@@ -174,7 +174,24 @@ struct alignas(16) TileHdr {
   uint32_t n_fast_items;  // work items: TFast index << 12 | block c of 64 walk positions
   uint32_t off_items;  // byte offset of the work items (uint32 each)
   uint32_t n_fact;     // factored groups (fact_idx 0 .. n_fact - 1)
-  uint32_t pad;
+  uint32_t n_segs;     // lambda tilings: LamSeg records (0 otherwise)
+  uint32_t off_segs;   // byte offset of the LamSeg array
+};
+
+// A segment of a lambda tile pass: consecutive general groups and fast
+// records none of whose flip masks touches the frame bits wb_mask.  Every
+// pair (m, m ^ x) of such a group has both ends in one region (the
+// amplitudes whose wb_mask bits spell one value), so the wavefront that owns
+// the region adds both contributions with plain loads and stores: each
+// output's sum is formed by one wavefront in group order, with no atomics,
+// and is the same from run to run.  wb_mask = 0 (a group too wide for
+// regions) leaves the whole tile to wavefront 0.
+constexpr int kLambdaRegionBits = 3;
+struct alignas(16) LamSeg {
+  uint32_t g_first, g_count;   // general groups (TGroup indices)
+  uint32_t f_first, f_count;   // fast records (TFast indices)
+  uint32_t wb_mask;
+  uint32_t pad[3];
 };
 
 // Factored groups: when every subgroup mask is w_k = w0 ^ d_k with at most
@@ -200,7 +217,7 @@ struct alignas(8) TGroup {
   uint32_t n_sub;      // subgroups
   uint32_t sub_off;    // first TSub
   uint32_t coef_off;   // first coefficient: coef[coef_off + sub * n_rec + rec]
-  uint32_t n_sins;     // zero insertions (S', ascending) for pairs
+  uint32_t n_sins;     // zero insertions (S', and in lambda tilings the segment's region bits; ascending)
   uint64_t sins_pack;  // their frame-local positions, four bits each
   uint32_t fact_idx;   // factored group index, or ~0u
   uint32_t n_in;       // factored: subgroups with a frame-local d_k (first n_in TSub)
@@ -210,8 +227,9 @@ struct alignas(8) TGroup {
 };
 
 // A group with one subgroup and at most four records, in one self-contained
-// record (lambda tilings): G(m) = (-1)^{|m' & w|} T[record].  Its pairs are
-// walked at positions t = lane + 64 c of the bits outside S': lane bit i
+// record: G(m) = (-1)^{|m' & w|} T[record].  Its pairs are walked at
+// positions t = lane + 64 c of the bits outside S' (and, in lambda tilings,
+// outside the region bits of its segment): lane bit i
 // lands on frame-local bit dep_p[i] (LDS slot dep_q[i]; 0 past the walk's
 // width), the bits of c on hi_mask; wlane bit i is the w bit at dep_p[i].
 constexpr int kFastRecs = 4;

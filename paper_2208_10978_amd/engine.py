@@ -1,6 +1,7 @@
 """Device-resident objects over the C ABI and the UCC energy autograd Function.
 
-``StateVector``   a 2^n complex torch tensor on the GPU bound to an sv_state
+``StateVector``   a 2^n complex (or, for real circuits, real FP64) torch
+                  tensor on the GPU bound to an sv_state
 ``Hamiltonian``   a Pauli sum grouped and uploaded once (sv_hamiltonian)
 ``UCCSDEvaluator`` energy and energy+gradient of the Trotterised UCCSD state
                   (Eq. 10-11) for a fixed Hamiltonian: HF preparation, the
@@ -17,7 +18,8 @@ import torch
 from . import binding as B
 from .problem import PauliSum, RotationList
 
-_DT = {"c128": (B.SV_C128, torch.complex128), "c64": (B.SV_C64, torch.complex64)}
+_DT = {"c128": (B.SV_C128, torch.complex128), "c64": (B.SV_C64, torch.complex64),
+       "r64": (B.SV_R64, torch.float64)}
 
 
 class StateVector:
@@ -68,6 +70,9 @@ class StateVector:
     def set_stream(self, stream):
         B.sv_set_stream(self.handle, stream)
 
+    def set_deterministic(self, on: bool):
+        B.sv_set_deterministic(self.handle, on)
+
     def free(self):
         if self.handle is not None:
             B.sv_free(self.handle)
@@ -101,11 +106,15 @@ class Hamiltonian:
 class UCCSDEvaluator:
     """E(theta) = <HF| U(theta)^dag H U(theta) |HF> and its gradient.
 
-    ``renormalize`` rescales psi to unit norm (FP64 norm) after the forward
-    sweep; it is on by default for complex64 amplitudes."""
+    ``dtype``: "c128", "c64", or "r64" (real FP64 amplitudes, for circuits of
+    real rotations such as UCCSD with a real Hamiltonian: the same results as
+    "c128" with half the bytes).  ``renormalize`` rescales psi to unit norm
+    (FP64 norm) after the forward sweep; it is on by default for complex64
+    amplitudes.  ``deterministic`` selects the reproducible lambda build
+    (bitwise equal results from run to run; see sv_set_deterministic)."""
 
     def __init__(self, ham: PauliSum, rot: RotationList, n_electrons: int, dtype: str = "c128",
-                 stream=None, renormalize=None, hamiltonian: "Hamiltonian" = None):
+                 stream=None, renormalize=None, hamiltonian: "Hamiltonian" = None, deterministic: bool = False):
         self.n = ham.n_qubits
         self.rot = rot
         self.hf = (1 << n_electrons) - 1
@@ -122,6 +131,7 @@ class UCCSDEvaluator:
         z = np.asarray(rot.z, dtype=np.uint64)
         self.real_circuit = bool(np.all(np.bitwise_count(x & z) % 2 == 1))
         B.sv_set_real_hint(self.psi.handle, self.real_circuit)
+        B.sv_set_deterministic(self.psi.handle, deterministic)
         self.renormalize = (dtype == "c64") if renormalize is None else renormalize
         dev = self.psi.amps.device
         self.energy_buf = torch.empty(2, dtype=torch.float64, device=dev)

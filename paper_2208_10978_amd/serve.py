@@ -88,12 +88,13 @@ class GpuExecutor:
     loop and the device work of the others."""
 
     class Job:
-        def __init__(self, req):
+        def __init__(self, req, deterministic):
             import torch
             from .engine import UCCSDEvaluator
             self.stream = torch.cuda.Stream()
             with torch.cuda.stream(self.stream):
-                self.ev = UCCSDEvaluator(req.ham, req.rot, req.n_electrons, req.dtype, stream=self.stream)
+                self.ev = UCCSDEvaluator(req.ham, req.rot, req.n_electrons, req.dtype, stream=self.stream,
+                                         deterministic=deterministic)
                 e, g = self.ev.energy_and_grad(req.theta)
                 self.e_host = torch.empty(2, dtype=torch.float64, pin_memory=True)
                 self.g_host = torch.empty(req.rot.n_params, dtype=torch.float64, pin_memory=True)
@@ -120,8 +121,11 @@ class GpuExecutor:
         def result(self):
             return self.fut.result().result()
 
-    def __init__(self, launch_workers: int = 4):
+    def __init__(self, launch_workers: int = 4, deterministic: bool = True):
+        # deterministic: the reproducible lambda build, so a request's result
+        # is bitwise the same alone or among concurrent requests
         self.pool = cf.ThreadPoolExecutor(max_workers=launch_workers)
+        self.deterministic = deterministic
 
     def budget(self) -> int:
         import torch
@@ -129,7 +133,7 @@ class GpuExecutor:
         return int(free * 0.8)
 
     def launch(self, req):
-        return GpuExecutor.Pending(self.pool.submit(GpuExecutor.Job, req))
+        return GpuExecutor.Pending(self.pool.submit(GpuExecutor.Job, req, self.deterministic))
 
 
 class Server:

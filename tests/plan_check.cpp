@@ -1,7 +1,10 @@
 // Host checks of the tile-walk planning (CPU only, built with the host
 // compiler against plan.cpp).  For seeded Jordan-Wigner-shaped rotation lists
 // (forward, per-parameter and per-string reverse schedules) and a seeded
-// Pauli sum (lambda tiling with fast records), every walk must
+// Pauli sum (lambda tilings with region segments, and the expectation
+// tiling), the segments of a lambda tile must cover its groups in order with
+// flip masks that avoid their region bits (and general groups must insert
+// zeros at their support and region bits), and every walk must
 //   * split the bits its run leaves free (not enumerated, not region bits)
 //     into at most six lane bits and the loop bits hi_mask, disjointly;
 //   * visit each of the 2^walk_log free-bit patterns exactly once;
@@ -32,6 +35,7 @@ static uint64_t next_u64() {  // splitmix64
 static double next_unit() { return double(next_u64() >> 11) * (1.0 / 9007199254740992.0); }
 
 static int g_fail = 0;
+static long g_moved = 0;  // run pairs the schedules reordered
 #define CHECK(cond, ...)                          \
   do {                                            \
     if (!(cond)) {                                \
@@ -97,6 +101,37 @@ static uint32_t deposit(uint32_t v, uint32_t mask) {
 
 // Common walk checks; parity_src is z0_loc (rotations) or w_loc (lambda) and
 // parity_lanes the lane mask the planner stored for it.
+// Every run is scheduled exactly once, and any two runs that the schedule
+// applies in the other order than the list (reversed for the reverse sweep)
+// commute, checked string by string.
+static void check_order(const char* what, const std::vector<Run>& runs, const std::vector<Pass>& passes,
+                        const PauliIn* p, bool reverse) {
+  const int R = int(runs.size());
+  std::vector<int> pos(size_t(R), -1);
+  int k = 0;
+  for (const Pass& ps : passes)
+    for (int ri : ps.runs) {
+      CHECK(ri >= 0 && ri < R && pos[size_t(ri)] < 0, "%s: run %d scheduled twice", what, ri);
+      pos[size_t(ri)] = k++;
+    }
+  CHECK(k == R, "%s: %d of %d runs scheduled", what, k, R);
+  long moved = 0;
+  for (int i = 0; i < R; ++i)
+    for (int j = i + 1; j < R; ++j) {
+      const int a = reverse ? R - 1 - i : i, b2 = reverse ? R - 1 - j : j;  // a is applied first in the list
+      if (pos[size_t(a)] < pos[size_t(b2)]) continue;
+      ++moved;
+      for (int u = 0; u < runs[size_t(a)].count; ++u)
+        for (int v = 0; v < runs[size_t(b2)].count; ++v) {
+          const PauliIn& s1 = p[runs[size_t(a)].first + u];
+          const PauliIn& s2 = p[runs[size_t(b2)].first + v];
+          CHECK(((__builtin_popcountll(s1.x & s2.z) + __builtin_popcountll(s1.z & s2.x)) & 1) == 0,
+                "%s: runs %d and %d swapped but do not commute", what, a, b2);
+        }
+    }
+  g_moved += moved;
+}
+
 static void check_walk(const char* what, uint32_t free_bits, uint32_t walk_log, const uint32_t* dep_p,
                        const uint32_t* dep_q, uint32_t hi_mask, uint32_t parity_src, uint32_t parity_lanes,
                        long* n_walks, double* cost_sum, double* best_sum) {
@@ -196,8 +231,9 @@ static void check_rotations(int n, int n_occ, long* nw, double* cs, double* bs) 
     const std::vector<Run> runs = split_runs(p.data(), nr, md.grad_mode == 1 ? param.data() : nullptr);
     std::vector<RunData> data;
     for (const Run& r : runs) data.push_back(build_run_data(r, p.data(), phi.data(), dphi.data(), md.grad_mode));
-    const std::vector<Pass> passes = schedule(runs, data, n, md.b, 3, md.reverse, md.reverse ? 96 : 0,
+    const std::vector<Pass> passes = schedule(runs, data, p.data(), n, md.b, 3, md.reverse, md.reverse ? 96 : 0,
                                               md.grad_mode == 1 ? 1 : 0, 1 << 16, 1 << 20);
+    check_order(md.reverse ? "reverse schedule" : "forward schedule", runs, passes, p.data(), md.reverse);
     int tile_passes = 0;
     for (const Pass& ps : passes) {
       if (!ps.tile) continue;
@@ -228,7 +264,7 @@ static void check_rotations(int n, int n_occ, long* nw, double* cs, double* bs) 
   }
 }
 
-static void check_lambda(int n, int b, long* nw, double* cs, double* bs) {
+static void check_lambda(int n, int b, long* nw, double* cs, double* bs, int rb) {
   // one- and two-body shaped terms: x on 0, 2 or 4 orbitals, Z chains, odd Y
   std::vector<PauliIn> p;
   std::vector<double> coef;
@@ -263,19 +299,96 @@ static void check_lambda(int n, int b, long* nw, double* cs, double* bs) {
   std::vector<HGroup> nd;
   for (const HGroup& g : gs)
     if (!g.diag) nd.push_back(g);
-  const HTiling T = build_tiling(nd, n, b, 3, true, size_t(1) << 24);
-  long n_fast = 0;
+  const HTiling T = build_tiling(nd, n, b, 3, true, size_t(1) << 24, rb);
+  long n_fast = 0, n_seg = 0;
   for (size_t t = 0; t < T.frames.size(); ++t) {
     const char* blob = reinterpret_cast<const char*>(T.blob.data() + 2 * size_t(T.blob_off[t]));
     const TileHdr* h = reinterpret_cast<const TileHdr*>(blob);
     const TFast* fs = reinterpret_cast<const TFast*>(blob + h->off_fast);
-    for (uint32_t i = 0; i < h->n_fast; ++i, ++n_fast) {
-      const TFast& f = fs[i];
-      const uint32_t free_bits = ((1u << b) - 1u) & ~f.sup_mask;
-      check_walk("lambda", free_bits, f.walk_log, f.dep_p, f.dep_q, f.hi_mask, f.w_loc, f.wlane, nw, cs, bs);
+    const TGroup* tg = reinterpret_cast<const TGroup*>(blob + sizeof(TileHdr));
+    const LamSeg* sg = reinterpret_cast<const LamSeg*>(blob + h->off_segs);
+    // segments cover the groups and fast records in order; every member's
+    // flip mask avoids the segment's region bits
+    uint32_t g_next = 0, f_next = 0;
+    for (uint32_t si = 0; si < h->n_segs; ++si, ++n_seg) {
+      const LamSeg& S = sg[si];
+      const int nb = __builtin_popcount(S.wb_mask);
+      CHECK(nb == 0 || nb == kLambdaRegionBits, "segment region mask %x", S.wb_mask);
+      CHECK(S.wb_mask < (1u << b), "segment region mask %x outside the frame", S.wb_mask);
+      CHECK(S.g_first == g_next && S.f_first == f_next, "segments out of order");
+      CHECK(nb > 0 || S.g_count + S.f_count == 1, "a maskless segment holds %u groups", S.g_count + S.f_count);
+      g_next += S.g_count;
+      f_next += S.f_count;
+      for (uint32_t i = S.g_first; i < S.g_first + S.g_count; ++i) {
+        CHECK(!(tg[i].x_loc & S.wb_mask), "group x %x touches region bits %x", tg[i].x_loc, S.wb_mask);
+        // zero insertions: S' and the region bits, ascending
+        uint32_t want = tg[i].sup_mask | S.wb_mask, got = 0, prev = 0;
+        for (uint32_t j = 0; j < tg[i].n_sins; ++j) {
+          const uint32_t pos = uint32_t(tg[i].sins_pack >> (4 * j)) & 15u;
+          CHECK(j == 0 || pos > prev, "insertions not ascending");
+          prev = pos;
+          got |= 1u << pos;
+        }
+        CHECK(got == want, "insertions %x, want %x", got, want);
+      }
+      for (uint32_t i = S.f_first; i < S.f_first + S.f_count; ++i, ++n_fast) {
+        const TFast& f = fs[i];
+        CHECK(!(f.x_loc & S.wb_mask), "fast x %x touches region bits %x", f.x_loc, S.wb_mask);
+        const uint32_t free_bits = ((1u << b) - 1u) & ~f.sup_mask & ~S.wb_mask;
+        check_walk("lambda", free_bits, f.walk_log, f.dep_p, f.dep_q, f.hi_mask, f.w_loc, f.wlane, nw, cs, bs);
+      }
     }
+    if (rb == 0) {
+      // expectation tilings: no segments; walks over the bits outside S'
+      CHECK(h->n_segs == 0, "segments in an expectation tiling");
+      for (uint32_t i = 0; i < h->n_fast; ++i, ++n_fast) {
+        const TFast& f = fs[i];
+        const uint32_t free_bits = ((1u << b) - 1u) & ~f.sup_mask;
+        check_walk("expect", free_bits, f.walk_log, f.dep_p, f.dep_q, f.hi_mask, f.w_loc, f.wlane, nw, cs, bs);
+      }
+      continue;
+    }
+    CHECK(g_next == h->n_groups && f_next == h->n_fast, "segments cover %u/%u groups, %u/%u fast records", g_next,
+          h->n_groups, f_next, h->n_fast);
   }
   CHECK(n_fast > 0, "no fast records");
+  CHECK(rb == 0 || n_seg > 0, "no segments");
+}
+
+// Random 4-qubit rotations on 32 qubits (X/Y with an odd number of Y), in a
+// 14-qubit frame with 4 fixed low qubits: three consecutive runs fill a frame
+// about as far as it goes (3.07 runs per pass), so passes that reach past
+// runs they commute with must hold more (about 3.8).
+static void check_random_schedule() {
+  const int n = 32, nr = 2000;
+  std::vector<PauliIn> p;
+  for (int k = 0; k < nr; ++k) {
+    uint64_t x = 0, z = 0;
+    int got = 0, ys = 0;
+    while (got < 4) {
+      const int q = int(next_u64() % uint64_t(n));
+      if (x & (uint64_t(1) << q)) continue;
+      x |= uint64_t(1) << q;
+      if (next_u64() & 1u) { z |= uint64_t(1) << q; ++ys; }
+      ++got;
+    }
+    if (!(ys & 1)) z ^= x & (~x + 1);  // flip the lowest factor X <-> Y: odd Y count
+    p.push_back({x, z});
+  }
+  std::vector<double> phi(size_t(nr), 0.05);
+  const std::vector<Run> runs = split_runs(p.data(), nr, nullptr);
+  std::vector<RunData> data;
+  for (const Run& r : runs) data.push_back(build_run_data(r, p.data(), phi.data(), nullptr, 0));
+  const std::vector<Pass> passes = schedule(runs, data, p.data(), n, 14, 4, false, 0, 0, 1 << 16, 1 << 20);
+  check_order("random schedule", runs, passes, p.data(), false);
+  long in_tiles = 0, tiles = 0;
+  for (const Pass& ps : passes)
+    if (ps.tile) {
+      ++tiles;
+      in_tiles += long(ps.runs.size());
+    }
+  CHECK(tiles > 0 && double(in_tiles) / double(tiles) >= 3.5, "random schedule: %ld runs in %ld tile passes",
+        in_tiles, tiles);
 }
 
 int main() {
@@ -283,12 +396,15 @@ int main() {
   double cs = 0.0, bs = 0.0;
   check_rotations(18, 6, &nw, &cs, &bs);
   check_rotations(14, 4, &nw, &cs, &bs);
-  check_lambda(18, 12, &nw, &cs, &bs);  // complex build
-  check_lambda(18, 13, &nw, &cs, &bs);  // real-part tiles
+  check_random_schedule();
+  check_lambda(18, 12, &nw, &cs, &bs, kLambdaRegionBits);  // lambda, complex build
+  check_lambda(18, 13, &nw, &cs, &bs, kLambdaRegionBits);  // lambda, real-part tiles
+  check_lambda(18, 13, &nw, &cs, &bs, 0);                  // expectation (complex128 frames)
   if (g_fail) {
     std::printf("%d failures over %ld walks\n", g_fail, nw);
     return 1;
   }
-  std::printf("ok %ld walks, mean cost %.4f (least %.4f)\n", nw, cs / double(nw), bs / double(nw));
+  std::printf("ok %ld walks, mean cost %.4f (least %.4f), %ld run pairs reordered\n", nw, cs / double(nw),
+              bs / double(nw), g_moved);
   return 0;
 }

@@ -395,3 +395,40 @@ def test_real_hint_at_21_qubits(case):
         assert np.isnan(energy[0].item()) and np.isnan(grad[0].item())
         assert np.isnan(got.real).all()
     psi.free(); lam.free()
+
+
+@pytest.mark.parametrize("n,dtype", [(14, "c128"), (22, "c128"), (22, "c64"), (22, "r64")])
+def test_lambda_and_gradient_are_bitwise_reproducible(n, dtype):
+    """With the reproducible build (sv_set_deterministic), lambda = H psi,
+    the energy and the per-rotation gradient of two adjoint calls on the
+    same input are bitwise equal: every element of lambda is summed by one
+    wavefront in group order, and every reduction has a fixed order.  The
+    fast build agrees with it to FP64 rounding.  14 qubits takes the complex
+    build, 22 qubits the real-part tiles (a UCCSD state is real)."""
+    announce(f"lambda twice, bitwise: {n} qubits {dtype}")
+    ne = n // 2
+    h, eri = synthetic_integrals(n, 1000 + n)
+    ham = jordan_wigner(h, eri)
+    rot = uccsd_rotations(n, ne, ORDER)
+    phi = rot.angles(uniform_amplitudes(rot.n_params, 0.1, 5300 + n))
+    psi = StateVector(n, dtype); lam = StateVector(n, dtype)
+    out = []
+    for det in (True, True, False):
+        psi.set_deterministic(det)
+        energy = torch.empty(2, dtype=torch.float64, device="cuda")
+        grad = torch.empty(len(phi), dtype=torch.float64, device="cuda")
+        psi.prepare_hf((1 << ne) - 1)
+        psi.apply_rotations(rot.x, rot.z, phi)
+        B.sv_adjoint_grad(psi.handle, lam.handle, ham.x, ham.z, ham.c, rot.x, rot.z, phi, energy, grad)
+        torch.cuda.synchronize()
+        out.append((energy.clone(), grad.clone(), lam.amps.clone()))
+    psi.free(); lam.free()
+    (e1, g1, l1), (e2, g2, l2), (e3, g3, l3) = out
+    assert torch.equal(e1, e2)
+    assert torch.equal(g1, g2)
+    assert torch.equal(l1, l2)
+    assert torch.isfinite(g1).all() and float(g1.abs().max()) > 0.0
+    # the fast build (atomic adds in no fixed order) to the rounding of the sums
+    tol = 1e-12 if dtype != "c64" else 1e-5
+    assert abs(float(e3[0] - e1[0])) <= tol * abs(float(e1[0]))
+    assert float((g3 - g1).abs().max()) <= tol * max(1.0, float(g1.abs().max()))

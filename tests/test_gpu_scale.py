@@ -145,6 +145,56 @@ def test_invariants_and_return_to_hf(problem):
     assert abs(back[0] - 1.0) < 1e-12 and abs(back[1]) < 1e-12
 
 
+def test_energy_and_gradient_are_bitwise_reproducible(problem):
+    """With the reproducible lambda build, two energy + gradient evaluations
+    at the benchmark's amplitudes give bitwise equal results (fixed-order
+    lambda accumulation and reductions); the fast build agrees to FP64
+    rounding."""
+    announce("28q twice, bitwise")
+    ev = problem["ev"]
+    theta = uniform_amplitudes(ev.rot.n_params, 0.02, 2000 + N)
+    e0, g0 = (t.clone() for t in ev.energy_and_grad(theta))
+    ev.psi.set_deterministic(True)
+    try:
+        e1, g1 = (t.clone() for t in ev.energy_and_grad(theta))
+        e2, g2 = (t.clone() for t in ev.energy_and_grad(theta))
+    finally:
+        ev.psi.set_deterministic(False)
+    torch.cuda.synchronize()
+    assert torch.equal(e1, e2)
+    assert torch.equal(g1, g2)
+    assert abs(float(e0[0] - e1[0])) <= 1e-12 * abs(float(e1[0]))
+    assert float((g0 - g1).abs().max()) <= 1e-12 * max(1.0, float(g1.abs().max()))
+
+
+def test_real_state_at_full_size(problem):
+    """The real-amplitude state (SV_R64, the benchmark's representation) at
+    28 qubits: E(0) and dE/dtheta(0) against the closed forms, then energy
+    and gradient at the benchmark's amplitudes against the complex128 path
+    (pinned above by closed forms, invariants and finite differences)."""
+    announce("28q real state")
+    ev, row, hf = problem["ev"], problem["row"], problem["hf"]
+    evr = UCCSDEvaluator(problem["ham"], problem["rot"], NE, "r64")
+    try:
+        e, g = (t.cpu().numpy() for t in evr.energy_and_grad(np.zeros(evr.rot.n_params)))
+        e_hf = fermion.slater_condon_hf_energy(problem["h"], problem["eri"], NE)
+        assert abs(e[0] - e_hf) <= 1e-12 * abs(e_hf)
+        want = np.zeros(len(g))
+        for idx, exc in enumerate(problem["order"]):
+            kx, sgn = fermion.excited_determinant(exc, NE)
+            want[idx] = 2.0 * sgn * row.get(kx, 0.0)
+        assert np.abs(g - want).max() <= 1e-12 * max(1.0, np.abs(want).max())
+        theta = uniform_amplitudes(ev.rot.n_params, 0.02, 2000 + N)
+        er, gr = (t.cpu().numpy() for t in evr.energy_and_grad(theta))
+        ec, gc = (t.cpu().numpy() for t in ev.energy_and_grad(theta))
+        assert abs(er[0] - ec[0]) <= 1e-12 * abs(ec[0])
+        assert np.abs(gr - gc).max() <= 1e-12 * max(1.0, np.abs(gc).max())
+        back = evr.psi.amplitudes([hf]).cpu().numpy()
+        assert abs(back[0] - 1.0) < 1e-12 and back[1] == 0.0
+    finally:
+        evr.free()
+
+
 @pytest.mark.parametrize("half", [0, 1])
 def test_gradient_finite_differences(problem, half):
     """The adjoint gradient (Algorithm 1, through the autograd Function's
