@@ -1,7 +1,9 @@
 #!/usr/bin/env python3
 """Benchmark of the UCCSD state-vector path on one MI355X.
 
-Workload (default): 28 qubits, 14 electrons, complex128.  Seeded synthetic
+Workload (default): 28 qubits, 14 electrons, real FP64 amplitudes (the
+UCCSD state of a real Hamiltonian is real; the complex128 step is timed
+beside it).  Seeded synthetic
 integrals (seed 1028) -> JW Pauli sum truncated at |c| > 1e-6; spin-orbital
 UCCSD with 3,381 amplitudes theta ~ U[-0.02, 0.02] (seed 2028) -> 26,460
 Pauli rotations.  One step is one energy + full adjoint gradient evaluation:
@@ -35,6 +37,36 @@ def log(msg):
     print(f"[bench] {msg}", file=sys.stderr, flush=True)
 
 
+AMP_LABEL = {"r64": "real FP64 amplitudes (the UCCSD state of a real Hamiltonian is real; complex128 gives the same "
+                    "results with exactly zero imaginary parts)",
+             "c128": "complex128", "c64": "complex64 with FP64 reductions"}
+
+
+def step_c128(ham, rot, ne, theta, steps, energy_r64):
+    """The same energy + gradient step on complex128 states, timed after one
+    warm-up: its time per step and per kernel class, and its distance from
+    the real-state energy."""
+    import torch
+    from paper_2208_10978_amd import binding as B
+    from paper_2208_10978_amd.engine import UCCSDEvaluator
+    ev = UCCSDEvaluator(ham, rot, ne, "c128")
+    ev.energy_and_grad(theta)
+    torch.cuda.synchronize()
+    B.sv_profile_begin()
+    t0 = time.perf_counter()
+    for _ in range(steps):
+        e, _ = ev.energy_and_grad(theta)
+        torch.cuda.synchronize()
+    dt = (time.perf_counter() - t0) / steps
+    prof = B.sv_profile_end()
+    out = {"ms_per_step": 1e3 * dt, "evals_per_s": 1.0 / dt, "steps": steps,
+           "energy_minus_real_state": float(e[0].item()) - energy_r64,
+           "kernels_ms_per_step": {k: round(v["ms"] / steps, 3) for k, v in prof.items()}}
+    ev.free()
+    log(f"complex128 step: {1e3 * dt:.1f} ms")
+    return out
+
+
 def cpu_model():
     try:
         out = subprocess.run(["lscpu"], capture_output=True, text=True).stdout
@@ -46,7 +78,7 @@ def cpu_model():
     return platform.processor()
 
 
-TRAFFIC_FILE = os.path.join(ROOT, "profiles", "hbm_traffic_uccsd_28q_c128.md")
+TRAFFIC_FILES = {d: os.path.join(ROOT, "profiles", f"hbm_traffic_uccsd_28q_{d}.md") for d in ("r64", "c128")}
 KERNEL_SOURCES = ["kernels_sweep.hip", "kernels_pauli_sum.hip", "device_common.h", "q2sv_internal.h", "launch.h",
                   "plan.cpp"]
 
@@ -56,13 +88,13 @@ def measured_traffic(kernel_class: str, n: int, dtype: str):
     summary (calibrated FETCH_SIZE + WRITE_SIZE), or None when the summary is
     for another workload or the kernel sources changed since it was taken."""
     import hashlib
-    if n != 28 or dtype != "c128" or not os.path.exists(TRAFFIC_FILE):
+    if n != 28 or dtype not in TRAFFIC_FILES or not os.path.exists(TRAFFIC_FILES[dtype]):
         return None
     h = hashlib.sha256()
     for f in KERNEL_SOURCES:
         with open(os.path.join(ROOT, "paper_2208_10978_amd", "csrc", f), "rb") as fh:
             h.update(fh.read())
-    text = open(TRAFFIC_FILE).read()
+    text = open(TRAFFIC_FILES[dtype]).read()
     if f"`{h.hexdigest()[:16]}`" not in text:
         return None
     for line in text.splitlines():
@@ -419,7 +451,10 @@ def main():
     ap.add_argument("--steps", type=int, default=5)
     ap.add_argument("--warmup", type=int, default=1)
     ap.add_argument("--qubits", type=int, default=28)
-    ap.add_argument("--dtype", default="c128", choices=["c128", "c64"])
+    ap.add_argument("--dtype", default="r64", choices=["r64", "c128", "c64"],
+                    help="amplitude type of the 28-qubit step: r64 real FP64 (a UCCSD state of a real Hamiltonian "
+                         "is real), c128, c64")
+    ap.add_argument("--no-c128", action="store_true", help="skip the complex128 step timed beside a real-state run")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-c4", action="store_true", help="skip the 32-qubit complex64 raw-sweep figures")
     ap.add_argument("--c4-rotations", type=int, default=1000)
@@ -465,7 +500,7 @@ def main():
     t0 = time.perf_counter()
     ev = UCCSDEvaluator(ham, rot, ne, args.dtype)
     torch.cuda.synchronize()
-    log(f"states allocated ({2 * (1 << n) * (16 if args.dtype == 'c128' else 8) / 2**30:.1f} GiB)")
+    log(f"states allocated ({2 * (1 << n) * (16 if args.dtype == 'c128' else 8) / 2**30:.1f} GiB, {args.dtype})")
     for w in range(args.warmup):
         ev.energy_and_grad(theta)
         torch.cuda.synchronize()
@@ -537,10 +572,10 @@ def main():
         "higher_is_better": True,
         "scaling": "weak",
         "vs_baseline": None,
-        "dtype": "f64" if args.dtype == "c128" else "f32",
+        "dtype": "f32" if args.dtype == "c64" else "f64",
         "data": "synthetic",
         "config": {"workload": f"UCCSD energy + adjoint gradient, {n} qubits, {ne} electrons, "
-                               f"{'complex128' if args.dtype == 'c128' else 'complex64'}",
+                               f"{AMP_LABEL[args.dtype]}",
                    "n_qubits": n, "n_electrons": ne, "pauli_strings": len(ham), "x_groups": ham.n_groups,
                    "parameters": rot.n_params, "rotations": len(rot)},
         "rotations_per_s": len(rot) / fwd_s,
@@ -554,6 +589,9 @@ def main():
     ev.free()
     del ev
     torch.cuda.empty_cache()
+    if args.dtype == "r64" and not args.no_c128:
+        result["complex128_step"] = step_c128(ham, rot, ne, theta, max(1, min(args.steps, 3)), energy)
+        torch.cuda.empty_cache()
     if not args.no_c4:
         result["c4"] = bench_c4(args.c4_rotations, 10_000)
     if not args.no_serve:

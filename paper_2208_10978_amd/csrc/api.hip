@@ -528,7 +528,7 @@ static void plan_rotations(const sv_state* s, const sv_pauli* p, const double* p
   pl.data.resize(pl.runs.size());
   for (size_t r = 0; r < pl.runs.size(); ++r)
     pl.data[r] = build_run_data(pl.runs[r], pin, phi, dphi, reverse ? grad_mode : 0);
-  const int b = reverse ? tile_bits_two(s->dtype) : tile_bits_one(s->dtype);
+  const int b = reverse ? tile_bits_two(s->dtype) : tile_bits_fwd(s->dtype);
   const int c = std::min(row_bits(s->dtype), s->n);
   const int slots_per_run = grad_mode == 1 ? 1 : 0;
   pl.passes = schedule(pl.runs, pl.data, pin, s->n, b, c, reverse, reverse && grad_mode ? kMaxPassSlots : 0,
@@ -604,7 +604,8 @@ static int launch_rotations(sv_state* s, sv_state* lam, const RotPlan& pl, bool 
     if (ps.tile) {
       const FrameDesc fr = make_frame(ps.qmask, s->n, c);
       const uint64_t n_tb = uint64_t(1) << fr.n_comp;
-      const int grid = int(std::min<uint64_t>(n_tb, uint64_t(std::min<int>(num_cus(), int(kPartialStride)))));
+      const int grid = int(std::min<uint64_t>(
+          n_tb, uint64_t(std::min<int>(num_cus() * sweep_blocks_per_cu(s->dtype, rev), int(kPartialStride)))));
       hipError_t e;
       ProfScope prof(s->stream, rev ? kPTileRev : kPTileFwd, (rev ? 4.0 : 2.0) * s->bytes());
       if (!rev)

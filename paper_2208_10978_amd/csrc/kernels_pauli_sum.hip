@@ -152,6 +152,59 @@ __device__ __forceinline__ void walk_fast_items(const BlobView& bv, uint32_t i0,
   }
 }
 
+// As walk_fast_items, but two consecutive blocks of one group go to body2
+// together (twice the LDS operations in flight per lane, half the loop and
+// slot arithmetic per block); a lone block goes to body.
+template <typename Body, typename Body2>
+__device__ __forceinline__ void walk_fast_items_paired(const BlobView& bv, uint32_t i0, uint32_t i1, uint64_t base,
+                                                       uint32_t lane, const uint32_t (&lbit)[kWalkLaneBits],
+                                                       Body body, Body2 body2) {
+  if (i0 >= i1) return;
+  const uint32_t w0 = bv.items[i0];
+  uint32_t cur = w0 >> 12, blk = w0 & 0xfffu;
+  FastHead f = load_fast(bv.fast[cur]);
+  auto setup = [&](uint32_t& ds, unsigned& zp, unsigned& so, bool& on, uint32_t& nb) {
+    on = f.walk_log >= kWalkLaneBits || lane < (1u << f.walk_log);
+    nb = f.walk_log > kWalkLaneBits ? 1u << (f.walk_log - kWalkLaneBits) : 1u;
+    ds = 0;
+#pragma unroll
+    for (int i = 0; i < kWalkLaneBits; ++i) ds ^= lbit[i] & f.dep_q[i];
+    zp = __popc(lane & f.wlane);
+    so = __popcll(base & f.w_out);
+  };
+  uint32_t ds, nb;
+  unsigned zp, so;
+  bool on;
+  setup(ds, zp, so, on, nb);
+  uint32_t rest = deposit_bits(blk, f.hi_mask);  // uniform
+  for (uint32_t it = i0; it < i1;) {
+    const uint32_t srest = lds_swz(rest);  // uniform: slot and w parity of the block's high bits
+    const unsigned prest = __popc(rest & f.w_loc) & 1u;
+    uint32_t step = 1;
+    if (it + 1 < i1 && blk + 1 < nb) {
+      const uint32_t rest1 = (rest - f.hi_mask) & f.hi_mask;
+      body2(f, ds, zp, srest, so ^ prest, lds_swz(rest1), so ^ (__popc(rest1 & f.w_loc) & 1u), on);
+      rest = rest1;
+      step = 2;
+    } else {
+      body(f, ds, zp, srest, so ^ prest, on);
+    }
+    it += step;
+    blk += step;
+    if (blk == nb) {
+      if (it < i1) {
+        ++cur;
+        blk = 0;
+        rest = 0;
+        f = load_fast(bv.fast[cur]);
+        setup(ds, zp, so, on, nb);
+      }
+    } else {
+      rest = (rest - f.hi_mask) & f.hi_mask;  // the next block of the same group
+    }
+  }
+}
+
 // A wavefront's walk over the fast records [f0, f1) of a lambda segment, in
 // order, on its own region (region bits wbits): each record's walk covers
 // the bits outside its support and the region bits.  body(f, ds, zp, srest,
@@ -276,6 +329,46 @@ __device__ __forceinline__ void fast_pairs_add(const FastHead& f, uint32_t ds, u
   }
 }
 
+// fast_pairs_add at two walk positions of one lane (two blocks of a group):
+// every load of both first, then the atomic adds.
+template <int NR, bool REAL, typename TT>
+__device__ __forceinline__ void fast_pairs_add2(const FastHead& f, uint32_t ds, unsigned zp, uint32_t srest0,
+                                                unsigned so0, uint32_t srest1, unsigned so1, const TT* tp,
+                                                double* tlr, double* tli) {
+  uint32_t smp[2][NR];
+  double pmx[2][NR], pmy[2][NR], ppx[2][NR], ppy[2][NR];
+#pragma unroll
+  for (int b = 0; b < 2; ++b)
+#pragma unroll
+    for (int r = 0; r < NR; ++r) {
+      smp[b][r] = ds ^ (b ? srest1 : srest0) ^ f.sbits[r];
+      pmx[b][r] = (double)tp[smp[b][r] ^ f.sx].x;
+      ppx[b][r] = (double)tp[smp[b][r]].x;
+      if constexpr (!REAL) {
+        pmy[b][r] = (double)tp[smp[b][r] ^ f.sx].y;
+        ppy[b][r] = (double)tp[smp[b][r]].y;
+      }
+    }
+#pragma unroll
+  for (int b = 0; b < 2; ++b)
+#pragma unroll
+    for (int r = 0; r < NR; ++r) {
+      const unsigned sg = zp + f.pbits[r] + (b ? so1 : so0);
+      const uint32_t sm = smp[b][r] ^ f.sx;
+      const double gre = signed_by(f.coef[2 * r], sg);
+      if constexpr (REAL) {
+        lds_add(&tlr[sm], gre * ppx[b][r]);
+        lds_add(&tlr[smp[b][r]], gre * pmx[b][r]);
+      } else {
+        const double gim = signed_by(f.coef[2 * r + 1], sg);
+        lds_add(&tlr[sm], gre * ppx[b][r] - gim * ppy[b][r]);  // lam[m] += G psi[m']
+        lds_add(&tli[sm], gre * ppy[b][r] + gim * ppx[b][r]);
+        lds_add(&tlr[smp[b][r]], gre * pmx[b][r] + gim * pmy[b][r]);  // lam[m'] += conj(G) psi[m]
+        lds_add(&tli[smp[b][r]], gre * pmy[b][r] - gim * pmx[b][r]);
+      }
+    }
+}
+
 template <int NR, bool REAL, typename TT>
 __device__ __forceinline__ void fast_pairs_owned(const FastHead& f, uint32_t ds, unsigned zp, uint32_t srest, unsigned so,
                                            const TT* tp, double* tlr, double* tli) {
@@ -388,17 +481,27 @@ __device__ __forceinline__ void lambda_tiles(const T* __restrict__ psi, T* __res
     // a lane takes one position and every record's pair there
     {
       const uint32_t per = (n_items + NW - 1) / NW;
-      walk_fast_items(bv, min(n_items, uint32_t(wave) * per), min(n_items, uint32_t(wave + 1) * per), base,
-                      uint32_t(lane), lbit,
-                      [&](const FastHead& f, uint32_t ds, unsigned zp, uint32_t srest, unsigned sgn, bool on) {
-                        if (!on) return;
-                        switch (f.n_rec) {
-                          case 1: fast_pairs_add<1, REAL>(f, ds, zp, srest, sgn, tp, tlr, tli); break;
-                          case 2: fast_pairs_add<2, REAL>(f, ds, zp, srest, sgn, tp, tlr, tli); break;
-                          case 3: fast_pairs_add<3, REAL>(f, ds, zp, srest, sgn, tp, tlr, tli); break;
-                          default: fast_pairs_add<4, REAL>(f, ds, zp, srest, sgn, tp, tlr, tli); break;
-                        }
-                      });
+      walk_fast_items_paired(
+          bv, min(n_items, uint32_t(wave) * per), min(n_items, uint32_t(wave + 1) * per), base, uint32_t(lane), lbit,
+          [&](const FastHead& f, uint32_t ds, unsigned zp, uint32_t srest, unsigned sgn, bool on) {
+            if (!on) return;
+            switch (f.n_rec) {
+              case 1: fast_pairs_add<1, REAL>(f, ds, zp, srest, sgn, tp, tlr, tli); break;
+              case 2: fast_pairs_add<2, REAL>(f, ds, zp, srest, sgn, tp, tlr, tli); break;
+              case 3: fast_pairs_add<3, REAL>(f, ds, zp, srest, sgn, tp, tlr, tli); break;
+              default: fast_pairs_add<4, REAL>(f, ds, zp, srest, sgn, tp, tlr, tli); break;
+            }
+          },
+          [&](const FastHead& f, uint32_t ds, unsigned zp, uint32_t s0, unsigned g0, uint32_t s1, unsigned g1,
+              bool on) {
+            if (!on) return;
+            switch (f.n_rec) {
+              case 1: fast_pairs_add2<1, REAL>(f, ds, zp, s0, g0, s1, g1, tp, tlr, tli); break;
+              case 2: fast_pairs_add2<2, REAL>(f, ds, zp, s0, g0, s1, g1, tp, tlr, tli); break;
+              case 3: fast_pairs_add2<3, REAL>(f, ds, zp, s0, g0, s1, g1, tp, tlr, tli); break;
+              default: fast_pairs_add2<4, REAL>(f, ds, zp, s0, g0, s1, g1, tp, tlr, tli); break;
+            }
+          });
     }
     __syncthreads();
   };
@@ -671,6 +774,89 @@ __device__ __forceinline__ double fast_expect(const FastHead& f, uint32_t ds, un
   return e;
 }
 
+// The expectation's share of one general group (several subgroups, or more
+// records than a fast record holds) with at least 64 positions per record,
+// for one wavefront.  The group's n_rec x 2^ns pairs are cut into chunks of
+// one record and 64 J consecutive positions, taken by the wavefronts in turn;
+// within a chunk the record is uniform, so the wavefront reads each
+// subgroup's mask and coefficient once (scalar loads) and applies them to
+// the J pairs its lanes hold in registers, and every index and LDS slot is a
+// per-lane part (the lane's position bits deposited once per group) XOR a
+// uniform part (the slot map is linear).  Returns the lane's sum of
+// Re(conj(psi[m]) G(m) psi[m']) = Re(G(m) P), P = conj(psi[m]) psi[m'].
+// J = 4 positions per lane for complex128 tiles, 2 for the 8-byte types
+// (whose larger tiles hold more prefetch registers): within 128 VGPRs.
+template <typename T> constexpr int kExpectChunkLog = sizeof(T) == 16 ? 2 : 1;
+template <int NW, typename T>
+__device__ __forceinline__ double general_expect_chunks(const BlobView& bv, const TGroup& g, int ns, uint64_t base,
+                                                        const double2* fB, const T* tp, uint32_t lane,
+                                                        uint32_t wave) {
+  constexpr int J = 1 << kExpectChunkLog<T>;
+  const int jl = ns - 6 < kExpectChunkLog<T> ? ns - 6 : kExpectChunkLog<T>;  // log2 of the positions a lane takes
+  const uint32_t nj = 1u << jl;
+  const int cpl = ns - 6 - jl;                      // log2 of the chunks per record
+  const uint32_t n_chunks = g.n_rec << cpl;
+  const uint32_t dl = insert_zeros32_p4(lane, g.sins_pack, g.n_sins);  // the lane's position bits, deposited
+  const uint32_t sdl = lds_swz(dl), sx = lds_swz(g.x_loc);
+  const bool fact = g.fact_idx != ~0u;
+  const uint32_t n_k = fact ? g.n_in : g.n_sub;
+  double e = 0.0;
+  for (uint32_t c = wave; c < n_chunks; c += NW) {
+    const uint32_t r = c >> cpl;                    // uniform
+    const uint32_t h0 = (c & ((1u << cpl) - 1u)) << jl;
+    const uint32_t rb = bv.recs[g.rec_off + r];
+    uint32_t u[J];                                  // uniform: m' bits of position block h0 + j, and record
+    double pr[J], pi[J], gr[J], gi[J];              // P = conj(psi[m]) psi[m'], and G(m)
+#pragma unroll
+    for (int j = 0; j < J; ++j) {
+      gr[j] = gi[j] = 0.0;
+      pr[j] = pi[j] = 0.0;
+      u[j] = 0;
+      if (uint32_t(j) < nj) {
+        u[j] = insert_zeros32_p4((h0 + uint32_t(j)) << 6, g.sins_pack, g.n_sins) | rb;
+        const uint32_t s2 = sdl ^ lds_swz(u[j]);   // slot of m'
+        const T a = tp[s2 ^ sx], b = tp[s2];
+        pr[j] = (double)a.x * (double)b.x + (double)a.y * (double)b.y;
+        pi[j] = (double)a.x * (double)b.y - (double)a.y * (double)b.x;
+      }
+    }
+    if (fact) {
+      const double2 b0 = fB[g.fact_idx * kFactRecs + r];
+#pragma unroll
+      for (int j = 0; j < J; ++j) {
+        gr[j] = b0.x;
+        gi[j] = b0.y;
+      }
+    }
+    for (uint32_t k = 0; k < n_k; ++k) {
+      const TSub sd = bv.subs[g.sub_off + k];
+      const double2 cv = bv.coef[g.coef_off + k * g.n_rec + r];
+      const unsigned sb = fact ? 0u : unsigned(__popcll(base & sd.w_out));
+      const unsigned pl = __popc(dl & sd.w_loc);    // the lane's part of the parity
+#pragma unroll
+      for (int j = 0; j < J; ++j) {
+        if (uint32_t(j) >= nj) break;
+        const unsigned sg = pl + unsigned(__popc(u[j] & sd.w_loc)) + sb;
+        gr[j] += signed_by(cv.x, sg);
+        gi[j] += signed_by(cv.y, sg);
+      }
+    }
+    const unsigned s0 = fact ? unsigned(__popc(dl & g.w0_loc) + __popcll(base & g.w0_out)) : 0u;
+#pragma unroll
+    for (int j = 0; j < J; ++j) {
+      if (uint32_t(j) >= nj) break;
+      double grr = gr[j], gii = gi[j];
+      if (fact) {
+        const unsigned sg = s0 + unsigned(__popc(u[j] & g.w0_loc));
+        grr = signed_by(grr, sg);
+        gii = signed_by(gii, sg);
+      }
+      e += grr * pr[j] - gii * pi[j];  // Re(G conj(psi[m]) psi[m'])
+    }
+  }
+  return e;
+}
+
 template <typename T, int B, int NT, bool FULL>
 __global__ void __launch_bounds__(NT) k_tile_expect(const T* __restrict__ psi, FrameDesc fr,
                                                     const uint4* __restrict__ blob, uint64_t n_tb,
@@ -707,8 +893,7 @@ __global__ void __launch_bounds__(NT) k_tile_expect(const T* __restrict__ psi, F
         e += (double)a.x * gbr + (double)a.y * gbi;
       };
       if (ns >= 6) {
-        for (uint32_t idx = threadIdx.x; idx < np; idx += NT)
-          pair(__builtin_amdgcn_readfirstlane(idx >> ns), idx & ((1u << ns) - 1u));
+        e += general_expect_chunks<NW>(bv, g, ns, base, fB, tp, uint32_t(lane), uint32_t(wave));
       } else {
         for (uint32_t idx = threadIdx.x; idx < np; idx += NT) pair(idx >> ns, idx & ((1u << ns) - 1u));
       }

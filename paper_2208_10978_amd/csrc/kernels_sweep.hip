@@ -544,8 +544,8 @@ __device__ __forceinline__ void tile_run(const RunDesc& run, const RunRec* __res
 // waits for them.  Frames narrower than B (states of fewer than B qubits)
 // take the guarded loop.
 // ---------------------------------------------------------------------------
-template <typename T, int B, int NT, bool FULL>
-__global__ void __launch_bounds__(NT) k_tile_forward(T* __restrict__ psi, FrameDesc fr,
+template <typename T, int B, int NT, bool FULL, int MINB>
+__global__ void __launch_bounds__(NT, MINB) k_tile_forward(T* __restrict__ psi, FrameDesc fr,
                                                      const RunDesc* __restrict__ runs,
                                                      const RunRec* __restrict__ recs,
                                                      const SegDesc* __restrict__ segs, int n_segs, uint64_t n_tb) {
@@ -622,8 +622,8 @@ struct GradAcc {
   double v[MAXS][NW * 4];  // per slot: one cell per (wavefront, row of 16 lanes)
 };
 
-template <typename T, int B, int NT, int GRAD, int MAXS, bool FULL>
-__global__ void __launch_bounds__(NT) k_tile_reverse(T* __restrict__ psi, T* __restrict__ lam, FrameDesc fr,
+template <typename T, int B, int NT, int GRAD, int MAXS, bool FULL, int MINB>
+__global__ void __launch_bounds__(NT, MINB) k_tile_reverse(T* __restrict__ psi, T* __restrict__ lam, FrameDesc fr,
                                                      const RunDesc* __restrict__ runs,
                                                      const RunRec* __restrict__ recs,
                                                      const SegDesc* __restrict__ segs, int n_segs,
@@ -778,27 +778,28 @@ hipError_t launch_run_full(int dtype, bool rev, int grad, void* psi, void* lam, 
   return run_full_t<R64>(rev, grad, psi, lam, run, recs, partials, n, nb_stride, grid, st);
 }
 
-template <typename T, int B>
+template <typename T, int B, int MINB = 1>
 static hipError_t tile_forward_t(void* psi, const FrameDesc& fr, const RunDesc* runs, const RunRec* recs,
                                  const SegDesc* segs, int n_segs, uint64_t n_tb, int grid, hipStream_t st) {
   T* p = static_cast<T*>(psi);
   if (fr.b == B)
-    hipLaunchKernelGGL((k_tile_forward<T, B, kTileThreads, true>), dim3(grid), dim3(kTileThreads), 0, st, p, fr,
-                       runs, recs, segs, n_segs, n_tb);
+    hipLaunchKernelGGL((k_tile_forward<T, B, kTileThreads, true, MINB>), dim3(grid), dim3(kTileThreads), 0, st, p,
+                       fr, runs, recs, segs, n_segs, n_tb);
   else
-    hipLaunchKernelGGL((k_tile_forward<T, B, kTileThreads, false>), dim3(grid), dim3(kTileThreads), 0, st, p, fr,
-                       runs, recs, segs, n_segs, n_tb);
+    hipLaunchKernelGGL((k_tile_forward<T, B, kTileThreads, false, MINB>), dim3(grid), dim3(kTileThreads), 0, st, p,
+                       fr, runs, recs, segs, n_segs, n_tb);
   return hipGetLastError();
 }
 
 hipError_t launch_tile_forward(int dtype, void* psi, const FrameDesc& fr, const RunDesc* runs, const RunRec* recs,
                                const SegDesc* segs, int n_segs, uint64_t n_tb, int grid, hipStream_t st) {
-  if (dtype == 0) return tile_forward_t<double2, kTileFwdC128>(psi, fr, runs, recs, segs, n_segs, n_tb, grid, st);
-  if (dtype == 1) return tile_forward_t<float2, kTileFwdC64>(psi, fr, runs, recs, segs, n_segs, n_tb, grid, st);
-  return tile_forward_t<R64, kTileFwdC64>(psi, fr, runs, recs, segs, n_segs, n_tb, grid, st);
+  if (dtype == 0) return tile_forward_t<double2, kTileSweepC128>(psi, fr, runs, recs, segs, n_segs, n_tb, grid, st);
+  if (dtype == 1)
+    return tile_forward_t<float2, kTileSweepC64, kSweepBlocks8>(psi, fr, runs, recs, segs, n_segs, n_tb, grid, st);
+  return tile_forward_t<R64, kTileSweepR64, kSweepBlocks8>(psi, fr, runs, recs, segs, n_segs, n_tb, grid, st);
 }
 
-template <typename T, int B, int GRAD, int MAXS>
+template <typename T, int B, int GRAD, int MAXS, int MINB>
 static hipError_t tile_reverse_g(void* psi, void* lam, const FrameDesc& fr, const RunDesc* runs, const RunRec* recs,
                                  const SegDesc* segs, int n_segs, const uint32_t* slot_map, int n_slots,
                                  double* partials, uint32_t nb, uint64_t n_tb, int grid, const double* imag_count,
@@ -806,27 +807,29 @@ static hipError_t tile_reverse_g(void* psi, void* lam, const FrameDesc& fr, cons
   T* p = static_cast<T*>(psi);
   T* l = static_cast<T*>(lam);
   if (fr.b == B)
-    hipLaunchKernelGGL((k_tile_reverse<T, B, kTileThreads, GRAD, MAXS, true>), dim3(grid), dim3(kTileThreads), 0,
-                       st, p, l, fr, runs, recs, segs, n_segs, slot_map, n_slots, partials, nb, n_tb, imag_count);
+    hipLaunchKernelGGL((k_tile_reverse<T, B, kTileThreads, GRAD, MAXS, true, MINB>), dim3(grid), dim3(kTileThreads),
+                       0, st, p, l, fr, runs, recs, segs, n_segs, slot_map, n_slots, partials, nb, n_tb, imag_count);
   else
-    hipLaunchKernelGGL((k_tile_reverse<T, B, kTileThreads, GRAD, MAXS, false>), dim3(grid), dim3(kTileThreads), 0,
-                       st, p, l, fr, runs, recs, segs, n_segs, slot_map, n_slots, partials, nb, n_tb, imag_count);
+    hipLaunchKernelGGL((k_tile_reverse<T, B, kTileThreads, GRAD, MAXS, false, MINB>), dim3(grid),
+                       dim3(kTileThreads), 0, st, p, l, fr, runs, recs, segs, n_segs, slot_map, n_slots, partials, nb,
+                       n_tb, imag_count);
   return hipGetLastError();
 }
 
-template <typename T, int B>
+template <typename T, int B, int MAXS = kMaxPassSlots, int MINB = 1>
 static hipError_t tile_reverse_t(int grad, void* psi, void* lam, const FrameDesc& fr, const RunDesc* runs,
                                  const RunRec* recs, const SegDesc* segs, int n_segs, const uint32_t* slot_map,
                                  int n_slots, double* partials, uint32_t nb, uint64_t n_tb, int grid,
                                  const double* imag_count, hipStream_t st) {
+  if (n_slots > MAXS) return hipErrorInvalidValue;
   if (grad == 0)
-    return tile_reverse_g<T, B, 0, 1>(psi, lam, fr, runs, recs, segs, n_segs, slot_map, n_slots, partials, nb, n_tb,
-                                      grid, imag_count, st);
+    return tile_reverse_g<T, B, 0, 1, MINB>(psi, lam, fr, runs, recs, segs, n_segs, slot_map, n_slots, partials, nb,
+                                            n_tb, grid, imag_count, st);
   if (grad == 1)
-    return tile_reverse_g<T, B, 1, kMaxPassSlots>(psi, lam, fr, runs, recs, segs, n_segs, slot_map, n_slots,
-                                                  partials, nb, n_tb, grid, imag_count, st);
-  return tile_reverse_g<T, B, 2, kMaxPassSlots>(psi, lam, fr, runs, recs, segs, n_segs, slot_map, n_slots, partials,
-                                                nb, n_tb, grid, imag_count, st);
+    return tile_reverse_g<T, B, 1, MAXS, MINB>(psi, lam, fr, runs, recs, segs, n_segs, slot_map, n_slots, partials,
+                                               nb, n_tb, grid, imag_count, st);
+  return tile_reverse_g<T, B, 2, MAXS, MINB>(psi, lam, fr, runs, recs, segs, n_segs, slot_map, n_slots, partials, nb,
+                                             n_tb, grid, imag_count, st);
 }
 
 hipError_t launch_tile_reverse(int dtype, int grad, void* psi, void* lam, const FrameDesc& fr,
@@ -840,7 +843,7 @@ hipError_t launch_tile_reverse(int dtype, int grad, void* psi, void* lam, const 
   if (dtype == 1)
     return tile_reverse_t<float2, kTileTwoC64>(grad, psi, lam, fr, runs, recs, segs, n_segs, slot_map, n_slots,
                                                partials, nb_stride, n_tb, grid, imag_count, st);
-  return tile_reverse_t<R64, kTileTwoC64>(grad, psi, lam, fr, runs, recs, segs, n_segs, slot_map, n_slots, partials,
+  return tile_reverse_t<R64, kTileTwoR64>(grad, psi, lam, fr, runs, recs, segs, n_segs, slot_map, n_slots, partials,
                                           nb_stride, n_tb, grid, nullptr, st);
 }
 

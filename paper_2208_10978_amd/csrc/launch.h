@@ -13,6 +13,17 @@ namespace q2sv {
 // tiles fill at most 128 KiB of the 160 KiB LDS of a gfx950 compute unit.
 constexpr int kTileFwdC128 = 13, kTileFwdC64 = 14;   // one state tile
 constexpr int kTileTwoC128 = 12, kTileTwoC64 = 13;   // two tiles (psi and lam)
+// The forward sweep of the 8-byte types runs on 64 KiB tiles (2^13
+// amplitudes) so that two blocks share a compute unit: four wavefronts per
+// SIMD hide the LDS and scalar-load latency of the per-run chains (real
+// states at 28 qubits: 317 ms on one 128 KiB block, 163 ms; the 32-qubit
+// complex64 stream: 151 -> 191 rotations/s).  complex128 keeps 2^13-amplitude
+// tiles on one block (2^12 tiles and two blocks took 334 ms against 305 ms:
+// more passes and whole-state runs).  The reverse sweep keeps one block of
+// two 64 KiB tiles (two 32 KiB tiles and two blocks: 377 -> 456 ms).
+constexpr int kTileSweepC128 = 13, kTileSweepC64 = 13, kTileSweepR64 = 13;
+constexpr int kTileTwoR64 = 13;
+constexpr int kSweepBlocks8 = 2;                     // blocks per compute unit, forward sweep, 8-byte types
 constexpr int kTileLamC128 = 12, kTileLamC64 = 12;   // psi tile + FP64 lambda accumulator
 constexpr int kTileLamReal = 13;                      // real parts of psi + one FP64 accumulator (real lambda)
 constexpr int kTileThreads = 512;
@@ -94,7 +105,10 @@ inline int row_bits(int dtype) { return dtype == 0 ? 3 : 4; }
 // Tile widths follow the amplitude size (a real FP64 tile is laid out as a
 // complex64 one).
 inline int tile_bits_one(int dtype) { return dtype == 0 ? kTileFwdC128 : kTileFwdC64; }
-inline int tile_bits_two(int dtype) { return dtype == 0 ? kTileTwoC128 : kTileTwoC64; }
+// forward and reverse sweep tiles
+inline int tile_bits_fwd(int dtype) { return dtype == 0 ? kTileSweepC128 : dtype == 1 ? kTileSweepC64 : kTileSweepR64; }
+inline int tile_bits_two(int dtype) { return dtype == 0 ? kTileTwoC128 : dtype == 1 ? kTileTwoC64 : kTileTwoR64; }
+inline int sweep_blocks_per_cu(int dtype, bool reverse) { return reverse || dtype == 0 ? 1 : kSweepBlocks8; }
 inline int tile_bits_lambda(int dtype) { return dtype == 0 ? kTileLamC128 : kTileLamC64; }
 
 }  // namespace q2sv
