@@ -307,6 +307,41 @@ struct TileAddr {
   }
 };
 
+// The same addressing with only the thread's part in registers (two VGPRs
+// instead of 2 PER): the element's part comes from the frame, which the
+// kernel holds in SGPRs, at each fetch.  For kernels whose work between the
+// fetches needs the VGPRs.
+template <int NT, int PER>
+struct TileAddrLean {
+  static constexpr int kT = ilog2c(NT), kE = ilog2c(PER);
+  uint64_t thr;
+  __device__ __forceinline__ explicit TileAddrLean(const FrameDesc& fr) {
+    thr = 0;
+#pragma unroll
+    for (int j = 0; j < kT; ++j) thr |= uint64_t((threadIdx.x >> j) & 1u) << fr.q[j];
+  }
+};
+
+template <typename T, int PER, int NT>
+__device__ __forceinline__ void tile_fetch_full(const T* __restrict__ src, const TileAddrLean<NT, PER>& a,
+                                                const FrameDesc& fr, uint64_t base, Stage<T, PER>& reg) {
+  constexpr int kT = TileAddrLean<NT, PER>::kT, kE = TileAddrLean<NT, PER>::kE;
+  const T* p = src + base;
+#pragma unroll
+  for (int i = 0; i < PER; ++i) {
+    uint64_t el = 0;  // uniform
+#pragma unroll
+    for (int k = 0; k < kE; ++k)
+      if ((i >> k) & 1) el |= uint64_t(1) << fr.q[kT + k];
+    // opaque to the optimiser: recomputed at each fetch (SALU) rather than
+    // hoisted out of the tile loop as PER 64-bit VGPR addresses
+    asm volatile("" : "+s"(el));
+    const T v = p[a.thr | el];
+    reg.re[i] = v.x;
+    reg.im[i] = v.y;
+  }
+}
+
 template <typename T, int PER, int NT>
 __device__ __forceinline__ void tile_fetch_full(const T* __restrict__ src, const TileAddr<NT, PER>& a, uint64_t base,
                                                 Stage<T, PER>& reg) {

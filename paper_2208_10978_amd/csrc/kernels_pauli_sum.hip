@@ -110,51 +110,11 @@ __device__ __forceinline__ FastHead load_fast(const TFast& t) {
 // order, each 64 walk positions of one group.  A group's items are its
 // blocks 0, 1, ... in a row and groups follow in index order, so only the
 // first item is read: the walk steps block and group arithmetically, and a
-// group's record is fetched once, when the walk reaches it.  body(f, ds, zp,
-// srest, sgn, on) gets the lane's slot part, lane parity, the block's slot
-// and the uniform sign parity.
-template <typename Body>
-__device__ __forceinline__ void walk_fast_items(const BlobView& bv, uint32_t i0, uint32_t i1, uint64_t base,
-                                                uint32_t lane, const uint32_t (&lbit)[kWalkLaneBits], Body body) {
-  if (i0 >= i1) return;
-  const uint32_t w0 = bv.items[i0];
-  uint32_t cur = w0 >> 12, blk = w0 & 0xfffu;
-  FastHead f = load_fast(bv.fast[cur]);
-  auto setup = [&](uint32_t& ds, unsigned& zp, unsigned& so, bool& on, uint32_t& nb) {
-    on = f.walk_log >= kWalkLaneBits || lane < (1u << f.walk_log);
-    nb = f.walk_log > kWalkLaneBits ? 1u << (f.walk_log - kWalkLaneBits) : 1u;
-    ds = 0;
-#pragma unroll
-    for (int i = 0; i < kWalkLaneBits; ++i) ds ^= lbit[i] & f.dep_q[i];
-    zp = __popc(lane & f.wlane);
-    so = __popcll(base & f.w_out);
-  };
-  uint32_t ds, nb;
-  unsigned zp, so;
-  bool on;
-  setup(ds, zp, so, on, nb);
-  uint32_t rest = deposit_bits(blk, f.hi_mask);  // uniform
-  for (uint32_t it = i0; it < i1; ++it) {
-    const uint32_t srest = lds_swz(rest);  // uniform: slot and w parity of the block's high bits
-    const unsigned prest = __popc(rest & f.w_loc) & 1u;
-    body(f, ds, zp, srest, so ^ prest, on);
-    if (++blk == nb) {
-      if (it + 1 < i1) {
-        ++cur;
-        blk = 0;
-        rest = 0;
-        f = load_fast(bv.fast[cur]);
-        setup(ds, zp, so, on, nb);
-      }
-    } else {
-      rest = (rest - f.hi_mask) & f.hi_mask;  // the next block of the same group
-    }
-  }
-}
-
-// As walk_fast_items, but two consecutive blocks of one group go to body2
-// together (twice the LDS operations in flight per lane, half the loop and
-// slot arithmetic per block); a lone block goes to body.
+// group's record is fetched once, when the walk reaches it.  Two consecutive
+// blocks of one group go to body2 together (twice the LDS operations in
+// flight per lane, half the loop and slot arithmetic per block); a lone
+// block goes to body.  body(f, ds, zp, srest, sgn, on) gets the lane's slot
+// part, lane parity, the block's slot and the uniform sign parity.
 template <typename Body, typename Body2>
 __device__ __forceinline__ void walk_fast_items_paired(const BlobView& bv, uint32_t i0, uint32_t i1, uint64_t base,
                                                        uint32_t lane, const uint32_t (&lbit)[kWalkLaneBits],
@@ -747,114 +707,176 @@ __global__ void __launch_bounds__(NT) k_tile_lambda_real(const T* __restrict__ p
 }
 
 // ---------------------------------------------------------------------------
-// Expectation over one tile: the sum over the tile's groups of
-// 2 Re(conj(psi[m]) G(m) psi[m']) over their pairs (the diagonal part comes
-// from the resident diagonal).  Tables read in place as in the lambda build;
-// each lane accumulates its own FP64 sum, reduced per block in a fixed order.
+// Expectation over one tile (projected sums, see XBatch).  The tile's groups
+// come in batches; wavefront w takes the batches of its work list (balanced
+// on the host) and, for each record, sums P = conj(psi[m]) psi[m'] over the
+// batch's pairs into one FP64 accumulator per register pattern v: per pair
+// two LDS reads, the slot arithmetic and four FMAs (plus the conversions of
+// complex64), whatever the number of subgroups.  The subgroups then take
+// their sums from the Walsh-Hadamard transform of the accumulators, with the
+// sign of their lane, record and out-of-frame bits; each lane keeps its FP64
+// sum, reduced per block in a fixed order.
 // ---------------------------------------------------------------------------
-template <int NR, typename T>
-__device__ __forceinline__ double fast_expect(const FastHead& f, uint32_t ds, unsigned zp, uint32_t srest, unsigned so,
-                                              const T* tp) {
-  T pm[NR], pp[NR];
-#pragma unroll
-  for (int r = 0; r < NR; ++r) {
-    const uint32_t smp = ds ^ srest ^ f.sbits[r];
-    pm[r] = tp[smp ^ f.sx];
-    pp[r] = tp[smp];
+struct XView {
+  const XHdr* hdr;
+  const XBatch* batches;
+  const XItem* items;
+  const uint32_t* start;
+  const XRec* recs;
+  const TSub* subs;
+  const double2* coef;
+  __device__ explicit XView(const uint4* blob) {
+    const char* b = reinterpret_cast<const char*>(blob);
+    hdr = reinterpret_cast<const XHdr*>(b);
+    batches = reinterpret_cast<const XBatch*>(b + hdr->off_batch);
+    items = reinterpret_cast<const XItem*>(b + hdr->off_items);
+    start = reinterpret_cast<const uint32_t*>(b + hdr->off_start);
+    recs = reinterpret_cast<const XRec*>(b + hdr->off_rec);
+    subs = reinterpret_cast<const TSub*>(b + hdr->off_sub);
+    coef = reinterpret_cast<const double2*>(b + hdr->off_coef);
   }
-  double e = 0.0;
+};
+
+// (hr, hi) += conj(a) b
+template <typename T>
+__device__ __forceinline__ void acc_pair(const T& a, const T& b, double& hr, double& hi) {
+  const double ax = (double)a.x, bx = (double)b.x;
+  if constexpr (is_real_amp<T>) {
+    hr = fma(ax, bx, hr);
+    (void)hi;
+  } else {
+    const double ay = (double)a.y, by = (double)b.y;
+    hr = fma(ax, bx, fma(ay, by, hr));
+    hi = fma(ax, by, fma(-ay, bx, hi));
+  }
+}
+
+// a with its sign bits XORed with sgn (0 or 0x80000000): -a or a
+__device__ __forceinline__ float2 sign_xor(float2 a, uint32_t sgn) {
+  return make_float2(__uint_as_float(__float_as_uint(a.x) ^ sgn), __uint_as_float(__float_as_uint(a.y) ^ sgn));
+}
+__device__ __forceinline__ double sign_xor1(double v, uint32_t sgn) {
+  return __hiloint2double(__double2hiint(v) ^ int(sgn), __double2loint(v));
+}
+__device__ __forceinline__ double2 sign_xor(double2 a, uint32_t sgn) {
+  return make_double2(sign_xor1(a.x, sgn), sign_xor1(a.y, sgn));
+}
+__device__ __forceinline__ R64 sign_xor(R64 a, uint32_t sgn) { return R64{sign_xor1(a.x, sgn)}; }
+
+// An LDS element by byte offset (the tile sits at a fixed LDS address, which
+// the read instruction takes as its immediate offset).
+template <typename T>
+__device__ __forceinline__ T lds_at(const T* tp, uint32_t off) {
+  return *reinterpret_cast<const T*>(reinterpret_cast<const char*>(tp) + off);
+}
+
+// One work item of a batch: NR register bits (2^NR positions per lane and
+// chunk); MULTI: subgroups of several classes (one accumulator per v), else
+// every subgroup has class 0 and one accumulator takes every position;
+// SIGNED: some chunk words carry the sign of w0 on their bits (the first
+// amplitude of the pair is negated in its raw bits), else none do.  Slots
+// travel as byte offsets (slot * sizeof(T); the map stays linear), and the
+// next chunk word is fetched while the current chunk is summed.
+template <typename T, int NR, bool MULTI, bool SIGNED>
+__device__ __forceinline__ double x_records(const XView& xv, const XBatch* bp, const XItem& it, uint64_t base,
+                                            const T* tp, uint32_t dl, uint32_t sdl) {
+  constexpr int NV = 1 << NR;
+  constexpr int NA = MULTI ? NV : 1;
+  constexpr int LG = ilog2c(sizeof(T));
+  uint32_t vs[NV];
 #pragma unroll
-  for (int r = 0; r < NR; ++r) {
-    const unsigned sg = zp + f.pbits[r] + so;
-    const double gre = signed_by(f.coef[2 * r], sg), gim = signed_by(f.coef[2 * r + 1], sg);
-    const double gbr = gre * (double)pp[r].x - gim * (double)pp[r].y;  // G psi[m']
-    const double gbi = gre * (double)pp[r].y + gim * (double)pp[r].x;
-    e += (double)pm[r].x * gbr + (double)pm[r].y * gbi;
+  for (int v = 0; v < NV; ++v) vs[v] = bp->vslot[v] << LG;
+  const uint32_t sx = bp->sx << LG, n_rec = bp->n_rec, rec_off = bp->rec_off;
+  const uint32_t n_sub = bp->n_sub, sub_off = bp->sub_off, coef_off = bp->coef_off;
+  const uint32_t r1 = it.recs >> 16, c0 = it.chunks & 0xffffu, c1 = it.chunks >> 16;
+  const uint32_t sdl_b = sdl << LG;
+  double e = 0.0;
+  for (uint32_t r = it.recs & 0xffffu; r < r1; ++r) {
+    const XRec rc = xv.recs[rec_off + r];
+    const uint32_t lb = sdl_b ^ (rc.slot << LG);
+    double hr[NA], hi[NA];
+#pragma unroll
+    for (int v = 0; v < NA; ++v) hr[v] = hi[v] = 0.0;
+    uint32_t cw = bp->cword[c0];
+    for (uint32_t c = c0; c < c1; ++c) {
+      const uint32_t cn = c + 1 < c1 ? bp->cword[c + 1] : 0u;  // prefetch
+      const uint32_t u = lb ^ ((cw & 0x7fffffffu) << LG);
+      const uint32_t sg = cw & 0x80000000u;
+      T a[NV], b[NV];
+#pragma unroll
+      for (int v = 0; v < NV; ++v) {
+        const uint32_t ob = u ^ vs[v];  // m'
+        a[v] = lds_at(tp, ob ^ sx);     // m = m' ^ x
+        b[v] = lds_at(tp, ob);
+      }
+      // every read of the chunk in flight before the arithmetic starts
+      __builtin_amdgcn_sched_barrier(0);
+#pragma unroll
+      for (int v = 0; v < NV; ++v) {
+        if constexpr (SIGNED) a[v] = sign_xor(a[v], sg);
+        acc_pair(a[v], b[v], hr[MULTI ? v : 0], hi[MULTI ? v : 0]);
+      }
+      cw = cn;
+    }
+    if constexpr (MULTI) {
+#pragma unroll
+      for (int h = 1; h < NV; h <<= 1)
+#pragma unroll
+        for (int v = 0; v < NV; ++v)
+          if (!(v & h)) {
+            const double r0 = hr[v], r1v = hr[v | h], i0 = hi[v], i1 = hi[v | h];
+            hr[v] = r0 + r1v;
+            hr[v | h] = r0 - r1v;
+            hi[v] = i0 + i1;
+            hi[v | h] = i0 - i1;
+          }
+    }
+    uint32_t k0 = 0;
+#pragma unroll
+    for (int cls = 0; cls < NA; ++cls) {
+      const uint32_t k1 = MULTI ? bp->cls_end[cls] : n_sub;
+      for (uint32_t k = k0; k < k1; ++k) {
+        const TSub sd = xv.subs[sub_off + k];
+        const double2 cv = xv.coef[coef_off + k * n_rec + r];
+        const unsigned par = unsigned(__popc(dl & sd.w_loc)) + unsigned(__popc(rc.bits & sd.w_loc)) +
+                             unsigned(__popcll(base & sd.w_out));
+        double t = cv.x * hr[cls];
+        if constexpr (!is_real_amp<T>) t = fma(-cv.y, hi[cls], t);
+        e += signed_by(t, par);
+      }
+      k0 = k1;
+    }
   }
   return e;
 }
 
-// The expectation's share of one general group (several subgroups, or more
-// records than a fast record holds) with at least 64 positions per record,
-// for one wavefront.  The group's n_rec x 2^ns pairs are cut into chunks of
-// one record and 64 J consecutive positions, taken by the wavefronts in turn;
-// within a chunk the record is uniform, so the wavefront reads each
-// subgroup's mask and coefficient once (scalar loads) and applies them to
-// the J pairs its lanes hold in registers, and every index and LDS slot is a
-// per-lane part (the lane's position bits deposited once per group) XOR a
-// uniform part (the slot map is linear).  Returns the lane's sum of
-// Re(conj(psi[m]) G(m) psi[m']) = Re(G(m) P), P = conj(psi[m]) psi[m'].
-// J = 4 positions per lane for complex128 tiles, 2 for the 8-byte types
-// (whose larger tiles hold more prefetch registers): within 128 VGPRs.
-template <typename T> constexpr int kExpectChunkLog = sizeof(T) == 16 ? 2 : 1;
-template <int NW, typename T>
-__device__ __forceinline__ double general_expect_chunks(const BlobView& bv, const TGroup& g, int ns, uint64_t base,
-                                                        const double2* fB, const T* tp, uint32_t lane,
-                                                        uint32_t wave) {
-  constexpr int J = 1 << kExpectChunkLog<T>;
-  const int jl = ns - 6 < kExpectChunkLog<T> ? ns - 6 : kExpectChunkLog<T>;  // log2 of the positions a lane takes
-  const uint32_t nj = 1u << jl;
-  const int cpl = ns - 6 - jl;                      // log2 of the chunks per record
-  const uint32_t n_chunks = g.n_rec << cpl;
-  const uint32_t dl = insert_zeros32_p4(lane, g.sins_pack, g.n_sins);  // the lane's position bits, deposited
-  const uint32_t sdl = lds_swz(dl), sx = lds_swz(g.x_loc);
-  const bool fact = g.fact_idx != ~0u;
-  const uint32_t n_k = fact ? g.n_in : g.n_sub;
+template <typename T, int NR, bool MULTI>
+__device__ __forceinline__ double x_records_s(const XView& xv, const XBatch* bp, const XItem& it, uint64_t base,
+                                              const T* tp, uint32_t dl, uint32_t sdl) {
+  return bp->signed_chunks ? x_records<T, NR, MULTI, true>(xv, bp, it, base, tp, dl, sdl)
+                           : x_records<T, NR, MULTI, false>(xv, bp, it, base, tp, dl, sdl);
+}
+
+template <typename T>
+__device__ __forceinline__ double x_item(const XView& xv, const XItem& it, uint64_t base, const T* tp, uint32_t lane) {
+  const XBatch* bp = xv.batches + it.batch;
+  const uint32_t lp = bp->lane_pack, nl = bp->n_lane;
+  uint32_t dl = 0;
+#pragma unroll
+  for (int i = 0; i < kXLaneBits; ++i)
+    if (uint32_t(i) < nl) dl |= ((lane >> i) & 1u) << ((lp >> (4 * i)) & 15u);
+  const uint32_t sdl = lds_swz(dl);
   double e = 0.0;
-  for (uint32_t c = wave; c < n_chunks; c += NW) {
-    const uint32_t r = c >> cpl;                    // uniform
-    const uint32_t h0 = (c & ((1u << cpl) - 1u)) << jl;
-    const uint32_t rb = bv.recs[g.rec_off + r];
-    uint32_t u[J];                                  // uniform: m' bits of position block h0 + j, and record
-    double pr[J], pi[J], gr[J], gi[J];              // P = conj(psi[m]) psi[m'], and G(m)
-#pragma unroll
-    for (int j = 0; j < J; ++j) {
-      gr[j] = gi[j] = 0.0;
-      pr[j] = pi[j] = 0.0;
-      u[j] = 0;
-      if (uint32_t(j) < nj) {
-        u[j] = insert_zeros32_p4((h0 + uint32_t(j)) << 6, g.sins_pack, g.n_sins) | rb;
-        const uint32_t s2 = sdl ^ lds_swz(u[j]);   // slot of m'
-        const T a = tp[s2 ^ sx], b = tp[s2];
-        pr[j] = (double)a.x * (double)b.x + (double)a.y * (double)b.y;
-        pi[j] = (double)a.x * (double)b.y - (double)a.y * (double)b.x;
-      }
-    }
-    if (fact) {
-      const double2 b0 = fB[g.fact_idx * kFactRecs + r];
-#pragma unroll
-      for (int j = 0; j < J; ++j) {
-        gr[j] = b0.x;
-        gi[j] = b0.y;
-      }
-    }
-    for (uint32_t k = 0; k < n_k; ++k) {
-      const TSub sd = bv.subs[g.sub_off + k];
-      const double2 cv = bv.coef[g.coef_off + k * g.n_rec + r];
-      const unsigned sb = fact ? 0u : unsigned(__popcll(base & sd.w_out));
-      const unsigned pl = __popc(dl & sd.w_loc);    // the lane's part of the parity
-#pragma unroll
-      for (int j = 0; j < J; ++j) {
-        if (uint32_t(j) >= nj) break;
-        const unsigned sg = pl + unsigned(__popc(u[j] & sd.w_loc)) + sb;
-        gr[j] += signed_by(cv.x, sg);
-        gi[j] += signed_by(cv.y, sg);
-      }
-    }
-    const unsigned s0 = fact ? unsigned(__popc(dl & g.w0_loc) + __popcll(base & g.w0_out)) : 0u;
-#pragma unroll
-    for (int j = 0; j < J; ++j) {
-      if (uint32_t(j) >= nj) break;
-      double grr = gr[j], gii = gi[j];
-      if (fact) {
-        const unsigned sg = s0 + unsigned(__popc(u[j] & g.w0_loc));
-        grr = signed_by(grr, sg);
-        gii = signed_by(gii, sg);
-      }
-      e += grr * pr[j] - gii * pi[j];  // Re(G conj(psi[m]) psi[m'])
-    }
+  static_assert(kXRegBits == 2, "one case per register-bit count");
+  switch (bp->n_reg + (bp->n_cls > 1 ? 4u : 0u)) {
+    case 0: e = x_records_s<T, 0, false>(xv, bp, it, base, tp, dl, sdl); break;
+    case 1: e = x_records_s<T, 1, false>(xv, bp, it, base, tp, dl, sdl); break;
+    case 2: e = x_records_s<T, 2, false>(xv, bp, it, base, tp, dl, sdl); break;
+    case 5: e = x_records_s<T, 1, true>(xv, bp, it, base, tp, dl, sdl); break;
+    case 6: e = x_records_s<T, 2, true>(xv, bp, it, base, tp, dl, sdl); break;
+    default: break;  // several classes need a register bit: not planned
   }
-  return e;
+  return (lane >> nl) == 0u ? e : 0.0;  // lanes past a small frame's free bits
 }
 
 template <typename T, int B, int NT, bool FULL>
@@ -865,66 +887,31 @@ __global__ void __launch_bounds__(NT) k_tile_expect(const T* __restrict__ psi, F
   constexpr int PER = (1 << B) / NT;
   __shared__ T tp[1 << B];
   __shared__ double red[NW];
-  __shared__ double2 fB[kMaxFactored * kFactRecs];
-  const BlobView bv(blob);
-  const int lane = threadIdx.x & 63;
-  const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
-  uint32_t lbit[kWalkLaneBits];
-#pragma unroll
-  for (int i = 0; i < kWalkLaneBits; ++i) lbit[i] = 0u - ((uint32_t(lane) >> i) & 1u);
-  const uint32_t n_groups = bv.hdr->n_groups, n_items = bv.hdr->n_fast_items, n_fact = bv.hdr->n_fact;
+  const XView xv(blob);
+  const uint32_t lane = threadIdx.x & 63u;
+  const uint32_t wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+  // the host balanced the work lists for NW wavefronts; any other count
+  // takes the items round robin
+  const bool lists = xv.hdr->n_waves == uint32_t(NW);
+  const uint32_t i0 = lists ? xv.start[wave] : wave;
+  const uint32_t i1 = lists ? xv.start[wave + 1] : xv.hdr->n_items;
+  const uint32_t step = lists ? 1u : uint32_t(NW);
   double e = 0.0;
   auto apply_groups = [&](uint64_t base) {
-    if (n_fact) {
-      factored_base<NW>(bv, n_groups, base, wave, lane, fB);
-      __syncthreads();
-    }
-    for (uint32_t gi = 0; gi < n_groups; ++gi) {
-      const TGroup g = bv.groups[gi];
-      const int ns = int(fr.b) - int(g.n_sins);
-      const uint32_t np = g.n_rec << ns;
-      auto pair = [&](uint32_t r, uint32_t t) {
-        const uint32_t l2 = insert_zeros32_p4(t, g.sins_pack, g.n_sins) | bv.recs[g.rec_off + r];  // m'
-        const uint32_t l = l2 ^ g.x_loc;
-        double gre, gim;  // G(m)
-        general_g(bv, g, r, l2, base, fB, gre, gim);
-        const T a = tp[lds_swz(l)], b = tp[lds_swz(l2)];
-        const double gbr = gre * (double)b.x - gim * (double)b.y, gbi = gre * (double)b.y + gim * (double)b.x;
-        e += (double)a.x * gbr + (double)a.y * gbi;
-      };
-      if (ns >= 6) {
-        e += general_expect_chunks<NW>(bv, g, ns, base, fB, tp, uint32_t(lane), uint32_t(wave));
-      } else {
-        for (uint32_t idx = threadIdx.x; idx < np; idx += NT) pair(idx >> ns, idx & ((1u << ns) - 1u));
-      }
-    }
-    {
-      const uint32_t per = (n_items + NW - 1) / NW;
-      walk_fast_items(bv, min(n_items, uint32_t(wave) * per), min(n_items, uint32_t(wave + 1) * per), base,
-                      uint32_t(lane), lbit,
-                      [&](const FastHead& f, uint32_t ds, unsigned zp, uint32_t srest, unsigned sgn, bool on) {
-                        if (!on) return;
-                        switch (f.n_rec) {
-                          case 1: e += fast_expect<1>(f, ds, zp, srest, sgn, tp); break;
-                          case 2: e += fast_expect<2>(f, ds, zp, srest, sgn, tp); break;
-                          case 3: e += fast_expect<3>(f, ds, zp, srest, sgn, tp); break;
-                          default: e += fast_expect<4>(f, ds, zp, srest, sgn, tp); break;
-                        }
-                      });
-    }
+    for (uint32_t i = i0; i < i1; i += step) e += x_item<T>(xv, xv.items[i], base, tp, lane);
     __syncthreads();
   };
   Stage<T, PER> rp;
   uint64_t tb = blockIdx.x;
   if constexpr (FULL) {
-    const TileAddr<NT, PER> ta(fr);
-    if (tb < n_tb) tile_fetch_full<T, PER, NT>(psi, ta, frame_base(fr, tb), rp);
+    const TileAddrLean<NT, PER> ta(fr);
+    if (tb < n_tb) tile_fetch_full<T, PER, NT>(psi, ta, fr, frame_base(fr, tb), rp);
     for (; tb < n_tb; tb += gridDim.x) {
       const uint64_t base = frame_base(fr, tb);
       tile_put_full<T, PER, NT>(tp, rp);
       __syncthreads();
       const uint64_t nx = tb + gridDim.x;
-      if (nx < n_tb) tile_fetch_full<T, PER, NT>(psi, ta, frame_base(fr, nx), rp);
+      if (nx < n_tb) tile_fetch_full<T, PER, NT>(psi, ta, fr, frame_base(fr, nx), rp);
       apply_groups(base);
     }
   } else {

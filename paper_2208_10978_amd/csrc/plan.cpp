@@ -870,8 +870,294 @@ static void pack_blob(HTiling& t, const std::vector<HGroup>& gs, const std::vect
   std::memcpy(t.blob.data() + at, bytes.data(), h.bytes);
 }
 
+// ---------------------------------------------------------------------------
+// expectation blobs (projected sums; see XBatch)
+// ---------------------------------------------------------------------------
+namespace {
+
+// Bits of v spread over the set bits of mask, ascending.
+uint32_t deposit_bits(uint32_t v, uint32_t mask) {
+  uint32_t out = 0;
+  for (int j = 0; mask; ++j, mask &= mask - 1)
+    if ((v >> j) & 1u) out |= mask & (~mask + 1u);
+  return out;
+}
+
+// The lane / register / chunk split of one batch's free bits.
+struct XSplit {
+  uint32_t lane[kXLaneBits] = {};  // single-bit masks, lane-bit order
+  int n_lane = 0;
+  uint32_t lane_mask = 0, reg_mask = 0, chunk_mask = 0;
+};
+
+// Free bits F of a group: the first four lane bits are the bank-conflict-free
+// choice for F; the deviation bits D (where the batch's subgroups differ
+// from w0) go to the remaining lane bits and then to the register bits, which
+// are padded with bits that no subgroup mask touches where possible (a
+// register bit of a subgroup would give it a nonzero class).  Returns false
+// when D does not fit.
+bool x_split(uint32_t F, uint32_t D, uint32_t W, XSplit& out) {
+  const int nf = popc(uint64_t(F));
+  uint32_t lp[kWalkLaneBits];
+  order_lane_bits(F, lp);
+  out = XSplit{};
+  out.n_lane = std::min(kXLaneBits, nf);
+  const int head = std::min(4, out.n_lane);
+  uint32_t used = 0;
+  for (int i = 0; i < head; ++i) {
+    out.lane[i] = lp[i];
+    used |= lp[i];
+  }
+  // remaining lane bits: deviation bits first, then the lowest free bits
+  int li = head;
+  for (uint32_t m = D & F & ~used; m && li < out.n_lane; m &= m - 1, ++li) {
+    out.lane[li] = m & (~m + 1u);
+    used |= out.lane[li];
+  }
+  for (uint32_t m = F & ~used; m && li < out.n_lane; m &= m - 1, ++li) {
+    out.lane[li] = m & (~m + 1u);
+    used |= out.lane[li];
+  }
+  out.lane_mask = used;
+  const int n_reg = std::min(kXRegBits, nf - out.n_lane);
+  uint32_t reg = 0;
+  int ri = 0;
+  for (uint32_t m = D & F & ~used; m; m &= m - 1) {
+    if (ri == n_reg) return false;
+    reg |= m & (~m + 1u);
+    ++ri;
+  }
+  for (uint32_t m = F & ~used & ~reg & ~W; m && ri < n_reg; m &= m - 1, ++ri) reg |= m & (~m + 1u);
+  for (uint32_t m = F & ~used & ~reg; m && ri < n_reg; m &= m - 1, ++ri) reg |= m & (~m + 1u);
+  out.reg_mask = reg;
+  out.chunk_mask = F & ~used & ~reg;
+  return true;
+}
+
+// Bitwise majority of masks (ties: 0).
+uint32_t majority(const std::vector<uint32_t>& v, const std::vector<int>& idx) {
+  uint32_t out = 0;
+  for (int bit = 0; bit < 32; ++bit) {
+    int ones = 0;
+    for (int k : idx) ones += int((v[size_t(k)] >> bit) & 1u);
+    if (2 * ones > int(idx.size())) out |= 1u << bit;
+  }
+  return out;
+}
+
+uint32_t deviation(const std::vector<uint32_t>& v, const std::vector<int>& idx, uint32_t w0) {
+  uint32_t d = 0;
+  for (int k : idx) d |= v[size_t(k)] ^ w0;
+  return d;
+}
+
+}  // namespace
+
+void pack_expect_blob(HTiling& t, const std::vector<HGroup>& gs, const std::vector<int>& members, uint64_t qmask,
+                      size_t max_blob, int n_waves) {
+  const int fb = popc(qmask);
+  const uint32_t all = fb >= 32 ? ~0u : ((1u << fb) - 1u);
+  std::vector<XBatch> xb;
+  std::vector<double> cost;
+  std::vector<XRec> xr;
+  std::vector<TSub> ts;
+  std::vector<double> co;
+  for (int gi : members) {
+    const HGroup& g = gs[size_t(gi)];
+    const uint32_t x_loc = uint32_t(compress(g.x, qmask));
+    const uint32_t smask = g.enumerated ? x_loc : (1u << local_pos(highest_bit(g.x), qmask));
+    const uint32_t F = all & ~smask;
+    const int NR = g.n_rec();
+    const uint32_t rec_off = uint32_t(xr.size());
+    for (int r = 0; r < NR; ++r) {
+      XRec rc{};
+      rc.bits = g.enumerated ? uint32_t(compress(g.rec_v[size_t(r)], qmask)) : smask;
+      rc.slot = lds_slot(rc.bits);
+      xr.push_back(rc);
+    }
+    const int K = int(g.w.size());
+    std::vector<uint32_t> wl(static_cast<size_t>(K)), wf(static_cast<size_t>(K));
+    uint32_t W = 0;
+    for (int k = 0; k < K; ++k) {
+      wl[size_t(k)] = uint32_t(compress(g.w[size_t(k)] & qmask, qmask));
+      wf[size_t(k)] = wl[size_t(k)] & F;
+      W |= wf[size_t(k)];
+    }
+    // batches: every subgroup at once with w0 = 0 (no chunk signs) when
+    // their free bits fit, else with the majority mask when the deviation
+    // fits, else greedy from the first remaining subgroup
+    std::vector<std::pair<std::vector<int>, uint32_t>> batches;
+    std::vector<int> rest(static_cast<size_t>(K));
+    for (int k = 0; k < K; ++k) rest[size_t(k)] = k;
+    XSplit sp;
+    if (x_split(F, W, W, sp)) {
+      batches.emplace_back(rest, 0u);
+      rest.clear();
+    }
+    while (!rest.empty()) {
+      uint32_t w0 = majority(wf, rest);
+      if (x_split(F, deviation(wf, rest, w0), W, sp)) {
+        batches.emplace_back(rest, w0);
+        break;
+      }
+      w0 = wf[size_t(rest[0])];
+      std::vector<int> take{rest[0]}, left;
+      uint32_t D = 0;
+      for (size_t i = 1; i < rest.size(); ++i) {
+        const uint32_t d2 = D | (wf[size_t(rest[i])] ^ w0);
+        if (x_split(F, d2, W, sp)) {
+          take.push_back(rest[i]);
+          D = d2;
+        } else {
+          left.push_back(rest[i]);
+        }
+      }
+      const uint32_t wm = majority(wf, take);
+      const uint32_t dm = deviation(wf, take, wm);
+      if (popc(uint64_t(dm)) < popc(uint64_t(D)) && x_split(F, dm, W, sp)) w0 = wm;
+      batches.emplace_back(take, w0);
+      rest.swap(left);
+    }
+    for (auto& bt : batches) {
+      const std::vector<int>& mem = bt.first;
+      const uint32_t w0 = bt.second;
+      const bool ok = x_split(F, deviation(wf, mem, w0), W, sp);
+      if (!ok) t.blob_overflow = true;  // a one-subgroup batch always fits
+      XBatch b{};
+      for (int i = 0; i < kXLaneBits; ++i)
+        if (i < sp.n_lane) b.lane_pack |= uint32_t(__builtin_ctz(sp.lane[i])) << (4 * i);
+      b.n_lane = uint32_t(sp.n_lane);
+      b.n_reg = uint32_t(popc(uint64_t(sp.reg_mask)));
+      b.n_chunk = 1u << popc(uint64_t(sp.chunk_mask));
+      if (b.n_chunk > uint32_t(kXChunkWords)) t.blob_overflow = true;
+      b.sx = lds_slot(x_loc);
+      b.n_rec = uint32_t(NR);
+      b.rec_off = rec_off;
+      for (uint32_t v = 0; v < (1u << kXRegBits); ++v)
+        b.vslot[v] = v < (1u << b.n_reg) ? lds_slot(deposit_bits(v, sp.reg_mask)) : 0u;
+      for (uint32_t cc = 0; cc < b.n_chunk && cc < uint32_t(kXChunkWords); ++cc) {
+        const uint32_t u = deposit_bits(cc, sp.chunk_mask);
+        b.cword[cc] = lds_slot(u) | (uint32_t(popc(uint64_t(u & w0)) & 1) << 31);
+        b.signed_chunks |= b.cword[cc] >> 31;
+      }
+      // subgroups sorted by class (their register bits, in v coordinates)
+      std::vector<std::pair<uint32_t, int>> by_cls;
+      for (int k : mem) by_cls.emplace_back(uint32_t(compress(wl[size_t(k)], sp.reg_mask)), k);
+      std::stable_sort(by_cls.begin(), by_cls.end(),
+                       [](const std::pair<uint32_t, int>& a, const std::pair<uint32_t, int>& c2) { return a.first < c2.first; });
+      b.n_sub = uint32_t(mem.size());
+      b.sub_off = uint32_t(ts.size());
+      b.coef_off = uint32_t(co.size() / 2);
+      uint32_t seen = 0;
+      for (size_t i = 0; i < by_cls.size(); ++i) {
+        const int k = by_cls[i].second;
+        seen |= 1u << by_cls[i].first;
+        TSub sd{};
+        sd.w_loc = wl[size_t(k)];
+        sd.w_out = g.w[size_t(k)] & ~qmask;
+        ts.push_back(sd);
+        for (int r = 0; r < NR; ++r) {
+          co.push_back(g.t_re[size_t(k) * size_t(NR) + size_t(r)]);
+          co.push_back(g.t_im[size_t(k) * size_t(NR) + size_t(r)]);
+        }
+      }
+      for (uint32_t v = 0; v < (1u << kXRegBits); ++v) {
+        uint32_t end = 0;
+        for (const auto& e : by_cls)
+          if (e.first <= v) ++end;
+        b.cls_end[v] = end;
+      }
+      b.n_cls = seen == 1u ? 1u : uint32_t(popc(uint64_t(seen))) + 1u;  // 1: class 0 alone
+      xb.push_back(b);
+      const double pos = double(NR) * double(uint64_t(1) << popc(uint64_t(F))) / 64.0;
+      cost.push_back(pos * 11.0 + double(NR) * (40.0 + 8.0 * double(mem.size()) + (b.n_cls > 1 ? 16.0 : 0.0)));
+    }
+  }
+  // work items: batches cut (by records, then by chunks) to at most a third
+  // of a wavefront's share, then longest first onto the least loaded
+  // wavefront
+  const int NW = std::max(1, n_waves);
+  double total = 0.0;
+  for (double v : cost) total += v;
+  const double target = std::max(1.0, total / double(NW) / 3.0);
+  std::vector<XItem> items;
+  std::vector<double> icost;
+  for (size_t bi = 0; bi < xb.size(); ++bi) {
+    const XBatch& b = xb[bi];
+    const uint32_t parts = uint32_t(std::min(1024.0, std::ceil(cost[bi] / target)));
+    auto add = [&](uint32_t r0, uint32_t r1, uint32_t c0, uint32_t c1) {
+      XItem it{};
+      it.batch = uint32_t(bi);
+      it.recs = r0 | r1 << 16;
+      it.chunks = c0 | c1 << 16;
+      items.push_back(it);
+      icost.push_back(cost[bi] * double(r1 - r0) * double(c1 - c0) / (double(b.n_rec) * double(b.n_chunk)));
+    };
+    if (parts <= b.n_rec) {
+      for (uint32_t p = 0; p < parts; ++p) add(b.n_rec * p / parts, b.n_rec * (p + 1) / parts, 0, b.n_chunk);
+    } else {
+      const uint32_t cp = std::min(b.n_chunk, (parts + b.n_rec - 1) / b.n_rec);
+      for (uint32_t r = 0; r < b.n_rec; ++r)
+        for (uint32_t p = 0; p < cp; ++p) add(r, r + 1, b.n_chunk * p / cp, b.n_chunk * (p + 1) / cp);
+    }
+  }
+  std::vector<int> order(items.size());
+  for (size_t i = 0; i < order.size(); ++i) order[i] = int(i);
+  std::stable_sort(order.begin(), order.end(), [&](int a, int c2) { return icost[size_t(a)] > icost[size_t(c2)]; });
+  std::vector<double> load(size_t(NW), 0.0);
+  std::vector<std::vector<int>> lists(static_cast<size_t>(NW));
+  for (int i : order) {
+    const size_t w = size_t(std::min_element(load.begin(), load.end()) - load.begin());
+    load[w] += icost[size_t(i)];
+    lists[w].push_back(i);
+  }
+  std::vector<XItem> list;
+  std::vector<uint32_t> start;
+  for (auto& l : lists) {
+    std::sort(l.begin(), l.end());
+    start.push_back(uint32_t(list.size()));
+    for (int i : l) list.push_back(items[size_t(i)]);
+  }
+  start.push_back(uint32_t(list.size()));
+  auto align16 = [](size_t v) { return (v + 15) & ~size_t(15); };
+  XHdr h{};
+  h.n_batches = uint32_t(xb.size());
+  h.n_items = uint32_t(list.size());
+  h.n_waves = uint32_t(NW);
+  size_t off = sizeof(XHdr);
+  h.off_batch = uint32_t(align16(off));
+  off = h.off_batch + xb.size() * sizeof(XBatch);
+  h.off_items = uint32_t(align16(off));
+  off = h.off_items + list.size() * sizeof(XItem);
+  h.off_start = uint32_t(align16(off));
+  off = h.off_start + start.size() * sizeof(uint32_t);
+  h.off_rec = uint32_t(align16(off));
+  off = h.off_rec + xr.size() * sizeof(XRec);
+  h.off_sub = uint32_t(align16(off));
+  off = h.off_sub + ts.size() * sizeof(TSub);
+  h.off_coef = uint32_t(align16(off));
+  off = h.off_coef + co.size() * sizeof(double);
+  h.bytes = uint32_t(align16(off));
+  if (h.bytes > max_blob) t.blob_overflow = true;
+  std::vector<unsigned char> bytes(h.bytes, 0);
+  std::memcpy(bytes.data(), &h, sizeof(h));
+  auto put = [&](uint32_t at, const void* src, size_t n) {
+    if (n) std::memcpy(bytes.data() + at, src, n);
+  };
+  put(h.off_batch, xb.data(), xb.size() * sizeof(XBatch));
+  put(h.off_items, list.data(), list.size() * sizeof(XItem));
+  put(h.off_start, start.data(), start.size() * sizeof(uint32_t));
+  put(h.off_rec, xr.data(), xr.size() * sizeof(XRec));
+  put(h.off_sub, ts.data(), ts.size() * sizeof(TSub));
+  put(h.off_coef, co.data(), co.size() * sizeof(double));
+  t.blob_off.push_back(uint32_t(t.blob.size() / 2));
+  const size_t at = t.blob.size();
+  t.blob.resize(at + h.bytes / 8);
+  std::memcpy(t.blob.data() + at, bytes.data(), h.bytes);
+}
+
 HTiling build_tiling(const std::vector<HGroup>& gs, int n, int b, int c, bool fast_records, size_t max_blob,
-                     int region_bits) {
+                     int region_bits, int expect_waves) {
   HTiling t;
   t.b = b;
   t.c = c;
@@ -937,7 +1223,8 @@ HTiling build_tiling(const std::vector<HGroup>& gs, int n, int b, int c, bool fa
     size_t bytes = fixed;
     auto flush = [&]() {
       t.frames.push_back(make_frame(q, n, c));
-      pack_blob(t, gs, chunk, q, max_blob, fast_records, region_bits);
+      if (expect_waves > 0) pack_expect_blob(t, gs, chunk, q, max_blob, expect_waves);
+      else pack_blob(t, gs, chunk, q, max_blob, fast_records, region_bits);
       chunk.clear();
       bytes = fixed;
     };

@@ -148,8 +148,14 @@ struct HTiling {
 // tile's groups are reordered into LamSeg segments whose flip masks avoid
 // region_bits frame bits, and every walk (fast records and general groups)
 // leaves its segment's region bits out.
+// expect_waves > 0: expectation tilings in the projected-sum format (XHdr
+// blobs), with per-wavefront work lists balanced for that many wavefronts.
 HTiling build_tiling(const std::vector<HGroup>& gs, int n, int b, int c, bool fast_records, size_t max_blob,
-                     int region_bits = 0);
+                     int region_bits = 0, int expect_waves = 0);
+
+// One expectation blob (XHdr) of a tile's groups, appended to t.
+void pack_expect_blob(HTiling& t, const std::vector<HGroup>& gs, const std::vector<int>& members, uint64_t qmask,
+                      size_t max_blob, int n_waves);
 
 // Greedy segmentation of one lambda tile's groups (frame-local flip masks):
 // repeatedly the region mask of region_bits frame bits that the most

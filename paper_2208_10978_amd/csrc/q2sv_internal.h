@@ -259,6 +259,71 @@ struct alignas(16) TSub {
   uint32_t pad;
 };
 
+// ---------------------------------------------------------------------------
+// Expectation tile passes (projected sums).  For one group and record r the
+// pairs' contribution is Re sum_k T_k[r] S_k with
+//   S_k = sum_{m'} (-1)^{|m' & w_k|} conj(psi[m' ^ x]) psi[m'].
+// The free bits F of the group (frame bits outside S') are split into
+//   L  six lane bits (the lane index, deposited),
+//   R  up to kXRegBits register bits (a position block v held in registers;
+//      two: with eight the accumulators and loads of complex64 spill),
+//   C  chunk bits (the loop index),
+// with every w_k agreeing with one reference mask w0 on C.  A lane then sums
+// P = conj(psi[m]) psi[m'] over its chunks, signed by (-1)^{|m' & w0|}, into
+// one accumulator per v; at the end of the record the Walsh-Hadamard
+// transform over v gives each subgroup's sum from the entry of its R bits,
+// and the lane, record and out-of-frame bits of w_k give its sign.  Per pair
+// the work no longer grows with the number of subgroups.  A group whose
+// subgroups differ on more free bits than L and R hold is split into batches
+// (each batch one pass over the pairs).
+// ---------------------------------------------------------------------------
+constexpr int kXLaneBits = 6;
+constexpr int kXRegBits = 2;
+constexpr int kXChunkWords = 32;   // 2^|C| at most (|F| <= 13 in a 14-bit frame)
+
+struct alignas(16) XHdr {
+  uint32_t n_batches;
+  uint32_t n_waves;    // wavefronts the work lists were balanced for
+  uint32_t off_batch;  // byte offsets from the start of the blob
+  uint32_t off_items;  // XItem work items in wavefront order: wave w takes [start[w], start[w + 1])
+  uint32_t off_start;  // n_waves + 1 list starts
+  uint32_t off_rec;    // XRec per record
+  uint32_t off_sub;    // TSub per subgroup, each batch's sorted by class
+  uint32_t off_coef;   // T_k[r] (re, im) at coef_off + k * n_rec + r
+  uint32_t bytes;
+  uint32_t n_items;
+  uint32_t pad[2];
+};
+
+struct alignas(16) XBatch {
+  uint32_t lane_pack;  // frame-local position of lane bit i in bits 4i..4i+3
+  uint32_t n_lane;     // lane bits (6 unless the frame is small)
+  uint32_t n_reg;      // register bits
+  uint32_t n_chunk;    // 2^|C|
+  uint32_t sx;         // LDS slot of x_loc
+  uint32_t n_cls;      // classes present: 1 means every subgroup has class 0
+  uint32_t n_rec, rec_off;
+  uint32_t n_sub, sub_off, coef_off;
+  uint32_t signed_chunks;  // some chunk word carries a sign (w0 meets C)
+  uint32_t cls_end[1 << kXRegBits];  // subgroups of class v: [cls_end[v - 1], cls_end[v]) (from 0)
+  uint32_t vslot[1 << kXRegBits];    // LDS slot of register pattern v
+  uint32_t cword[kXChunkWords];  // chunk c: LDS slot of its bits | parity(bits & w0) << 31
+};
+
+// A work item: records [r0, r1) and chunks [c0, c1) of one batch (a large
+// batch is split so that the wavefronts' lists balance).
+struct alignas(16) XItem {
+  uint32_t batch;
+  uint32_t recs;       // r0 | r1 << 16
+  uint32_t chunks;     // c0 | c1 << 16
+  uint32_t pad;
+};
+
+struct alignas(8) XRec {
+  uint32_t bits;       // frame-local bits of m' on S'
+  uint32_t slot;       // their LDS slot
+};
+
 // Frame of a tile pass.
 struct alignas(16) FrameDesc {
   uint8_t q[kMaxFrameBits];   // global position of frame-local bit j (q[j] = j for j < c)

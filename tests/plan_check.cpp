@@ -1,8 +1,8 @@
 // Host checks of the tile-walk planning (CPU only, built with the host
 // compiler against plan.cpp).  For seeded Jordan-Wigner-shaped rotation lists
 // (forward, per-parameter and per-string reverse schedules) and a seeded
-// Pauli sum (lambda tilings with region segments, and the expectation
-// tiling), the segments of a lambda tile must cover its groups in order with
+// Pauli sum (lambda tilings with and without region segments), the
+// segments of a lambda tile must cover its groups in order with
 // flip masks that avoid their region bits (and general groups must insert
 // zeros at their support and region bits), and every walk must
 //   * split the bits its run leaves free (not enumerated, not region bits)
@@ -12,9 +12,12 @@
 //   * use lane bits whose bank-conflict cost (largest number of lanes on one
 //     bank word: 16 lanes for 8-byte words, 8 lanes for 16-byte words, the
 //     latter weighted by one half) is the least over every ordered choice of
-//     free bits for lane bits 0..3.
+//     free bits for lane bits 0..3;
+// and the expectation tilings must reproduce the expectation of seeded sums
+// when walked on the CPU as the tile kernel walks them (check_expect).
 // Prints "ok ..." and exits 0, or names the first failure and exits 1.
 #include <algorithm>
+#include <cmath>
 #include <cstdio>
 #include <cstdlib>
 #include <map>
@@ -339,7 +342,7 @@ static void check_lambda(int n, int b, long* nw, double* cs, double* bs, int rb)
       }
     }
     if (rb == 0) {
-      // expectation tilings: no segments; walks over the bits outside S'
+      // tilings without region bits: no segments; walks over the bits outside S'
       CHECK(h->n_segs == 0, "segments in an expectation tiling");
       for (uint32_t i = 0; i < h->n_fast; ++i, ++n_fast) {
         const TFast& f = fs[i];
@@ -353,6 +356,195 @@ static void check_lambda(int n, int b, long* nw, double* cs, double* bs, int rb)
   }
   CHECK(n_fast > 0, "no fast records");
   CHECK(rb == 0 || n_seg > 0, "no segments");
+}
+
+// Expectation tilings (projected sums): a CPU walk of every work item of
+// every blob, the way the tile kernel takes it (lane deposit, register
+// patterns, chunk words and their signs, Walsh-Hadamard transform over the
+// register patterns, the subgroups' signs), must reproduce
+//   sum_t c_t <psi|P_t|psi>,  <psi|P|psi> = sum_m conj(psi[m]) i^{|x&z|} (-1)^{|(m^x)&z|} psi[m^x],
+// summed directly over the terms, on a seeded random state; and each batch's
+// items must cover its records x chunks exactly once.  The sums mix random
+// strings of weight <= 4, Jordan-Wigner hopping strings with number-operator
+// variants (many subgroups over a Z chain) and strings whose support is too
+// wide to enumerate.
+static long g_x_batches = 0, g_x_multi = 0;
+static double g_x_diff = 0.0;  // largest |walk - direct| / (sum |c| <psi|psi>)
+static void check_expect(int n, int b, int c, int n_terms) {
+  const uint64_t all = (uint64_t(1) << n) - 1;
+  const uint64_t low = (uint64_t(1) << c) - 1;
+  std::vector<PauliIn> p;
+  std::vector<double> coef;
+  std::set<std::pair<uint64_t, uint64_t>> seen;
+  while (int(p.size()) < n_terms) {
+    const int kind = int(next_u64() % 3);
+    uint64_t x = 0, z = 0;
+    if (kind == 0) {
+      const int w = 1 + int(next_u64() % 4);
+      for (int i = 0; i < w; ++i) {
+        const int q = int(next_u64() % uint64_t(n));
+        const int k = int(next_u64() % 3);  // X, Y, Z
+        if (k < 2) x |= uint64_t(1) << q;
+        if (k > 0) z |= uint64_t(1) << q;
+      }
+    } else if (kind == 1) {
+      int a = int(next_u64() % uint64_t(n)), d = int(next_u64() % uint64_t(n));
+      if (a == d) continue;
+      if (a > d) std::swap(a, d);
+      x = (uint64_t(1) << a) | (uint64_t(1) << d);
+      for (int q = a + 1; q < d; ++q) z |= uint64_t(1) << q;
+      if (next_u64() & 1u) z |= uint64_t(1) << a;                     // X Y or Y X ends
+      else z |= uint64_t(1) << d;
+      if (next_u64() % 3 == 0) z ^= uint64_t(1) << (next_u64() % uint64_t(n));  // a number operator
+    } else {
+      const int w = kMaxSup + 1 + int(next_u64() % 2);
+      for (int i = 0; i < w; ++i) x |= uint64_t(1) << (next_u64() % uint64_t(n));
+      z = next_u64() & all;
+    }
+    x &= all;
+    z &= all;
+    if (!x || popc(x | low) > b || !seen.insert({x, z}).second) continue;
+    p.push_back({x, z});
+    coef.push_back(2.0 * next_unit() - 1.0);
+  }
+  std::vector<double> pr(size_t(1) << n), pi(size_t(1) << n);
+  double nrm = 0.0;
+  for (size_t m = 0; m < pr.size(); ++m) {
+    pr[m] = 2.0 * next_unit() - 1.0;
+    pi[m] = 2.0 * next_unit() - 1.0;
+    nrm += pr[m] * pr[m] + pi[m] * pi[m];
+  }
+  // direct sum over the terms
+  double want = 0.0, scale = 0.0;
+  for (size_t t = 0; t < p.size(); ++t) {
+    double re = 0.0, im = 0.0;  // sum_m conj(psi[m]) (-1)^{|(m^x)&z|} psi[m^x]
+    for (uint64_t m = 0; m <= all; ++m) {
+      const uint64_t m2 = m ^ p[t].x;
+      const double sg = (popc(m2 & p[t].z) & 1) ? -1.0 : 1.0;
+      re += sg * (pr[m] * pr[m2] + pi[m] * pi[m2]);
+      im += sg * (pr[m] * pi[m2] - pi[m] * pr[m2]);
+    }
+    const int ph = popc(p[t].x & p[t].z) & 3;  // times i^ph
+    const double v = ph == 0 ? re : ph == 1 ? -im : ph == 2 ? -re : im;
+    want += coef[t] * v;
+    scale += std::fabs(coef[t]);
+  }
+  std::string err;
+  const std::vector<HGroup> gs = build_groups(p.data(), coef.data(), int64_t(p.size()), &err);
+  CHECK(err.empty(), "build_groups: %s", err.c_str());
+  const int NW = 16;
+  const HTiling T = build_tiling(gs, n, b, c, true, size_t(1) << 24, 0, NW);
+  CHECK(!T.blob_overflow, "expectation blob overflow");
+  CHECK(T.groups.empty(), "%zu whole-state groups", T.groups.size());
+  double got = 0.0;
+  long multi = 0, batches = 0;
+  for (size_t tt = 0; tt < T.frames.size(); ++tt) {
+    const FrameDesc& fr = T.frames[tt];
+    const char* bl = reinterpret_cast<const char*>(T.blob.data() + 2 * size_t(T.blob_off[tt]));
+    const XHdr* h = reinterpret_cast<const XHdr*>(bl);
+    const XBatch* xb = reinterpret_cast<const XBatch*>(bl + h->off_batch);
+    const XItem* items = reinterpret_cast<const XItem*>(bl + h->off_items);
+    const uint32_t* start = reinterpret_cast<const uint32_t*>(bl + h->off_start);
+    const XRec* recs = reinterpret_cast<const XRec*>(bl + h->off_rec);
+    const TSub* subs = reinterpret_cast<const TSub*>(bl + h->off_sub);
+    const double* co = reinterpret_cast<const double*>(bl + h->off_coef);
+    CHECK(h->n_waves == uint32_t(NW) && start[0] == 0 && start[NW] == h->n_items, "work lists");
+    batches += h->n_batches;
+    // each batch's records x chunks covered once
+    std::vector<std::vector<int>> cover(h->n_batches);
+    for (uint32_t bi = 0; bi < h->n_batches; ++bi) {
+      cover[bi].assign(size_t(xb[bi].n_rec) * xb[bi].n_chunk, 0);
+      CHECK(xb[bi].n_chunk <= uint32_t(kXChunkWords) && xb[bi].n_reg <= uint32_t(kXRegBits), "batch shape");
+      multi += xb[bi].n_cls > 1;
+    }
+    for (uint32_t i = 0; i < h->n_items; ++i) {
+      const XItem& it = items[i];
+      for (uint32_t r = it.recs & 0xffffu; r < (it.recs >> 16); ++r)
+        for (uint32_t cc = it.chunks & 0xffffu; cc < (it.chunks >> 16); ++cc)
+          cover[it.batch][size_t(r) * xb[it.batch].n_chunk + cc]++;
+    }
+    for (uint32_t bi = 0; bi < h->n_batches; ++bi)
+      for (int v : cover[bi]) CHECK(v == 1, "batch %u: a record x chunk covered %d times", bi, v);
+    const int nb = fr.b;
+    uint64_t qm = 0;
+    for (int j = 0; j < nb; ++j) qm |= uint64_t(1) << fr.q[j];
+    const uint64_t comp = all & ~qm;
+    std::vector<double> tr(size_t(1) << nb), ti(size_t(1) << nb);
+    for (uint64_t tb = 0; tb < (uint64_t(1) << popc(comp)); ++tb) {
+      uint64_t base = 0;
+      {
+        uint64_t mm = comp;
+        for (int j = 0; mm; ++j, mm &= mm - 1)
+          if ((tb >> j) & 1u) base |= mm & (~mm + 1);
+      }
+      for (uint32_t l = 0; l < (1u << nb); ++l) {
+        uint64_t g = base;
+        for (int j = 0; j < nb; ++j)
+          if ((l >> j) & 1u) g |= uint64_t(1) << fr.q[j];
+        tr[lds_slot(l)] = pr[g];
+        ti[lds_slot(l)] = pi[g];
+      }
+      for (int w = 0; w < NW; ++w)
+        for (uint32_t i = start[w]; i < start[w + 1]; ++i) {
+          const XItem& it = items[i];
+          const XBatch& B = xb[it.batch];
+          const bool MULTI = B.n_cls > 1;
+          const uint32_t nv = 1u << B.n_reg;
+          for (uint32_t lane = 0; lane < 64; ++lane) {
+            if (lane >> B.n_lane) continue;
+            uint32_t dl = 0;
+            for (uint32_t k = 0; k < B.n_lane; ++k) dl |= ((lane >> k) & 1u) << ((B.lane_pack >> (4 * k)) & 15u);
+            const uint32_t sdl = lds_slot(dl);
+            for (uint32_t r = it.recs & 0xffffu; r < (it.recs >> 16); ++r) {
+              const XRec rc = recs[B.rec_off + r];
+              double hr[4] = {0, 0, 0, 0}, hi[4] = {0, 0, 0, 0};
+              for (uint32_t cc = it.chunks & 0xffffu; cc < (it.chunks >> 16); ++cc) {
+                const uint32_t u = sdl ^ rc.slot ^ (B.cword[cc] & 0x7fffffffu);
+                const double sg = (B.cword[cc] >> 31) ? -1.0 : 1.0;
+                for (uint32_t v = 0; v < nv; ++v) {
+                  const uint32_t s2 = u ^ B.vslot[v];
+                  CHECK(s2 < (1u << nb) && (s2 ^ B.sx) < (1u << nb), "slot out of the tile");
+                  const double ar = tr[s2 ^ B.sx], ai = ti[s2 ^ B.sx], br = tr[s2], bi2 = ti[s2];
+                  const uint32_t a = MULTI ? v : 0;
+                  hr[a] += sg * (ar * br + ai * bi2);
+                  hi[a] += sg * (ar * bi2 - ai * br);
+                }
+              }
+              if (MULTI)
+                for (uint32_t hh = 1; hh < nv; hh <<= 1)
+                  for (uint32_t v = 0; v < nv; ++v)
+                    if (!(v & hh)) {
+                      const double r0 = hr[v], r1 = hr[v | hh], i0 = hi[v], i1 = hi[v | hh];
+                      hr[v] = r0 + r1;
+                      hr[v | hh] = r0 - r1;
+                      hi[v] = i0 + i1;
+                      hi[v | hh] = i0 - i1;
+                    }
+              uint32_t k0 = 0;
+              for (uint32_t cls = 0; cls < (MULTI ? nv : 1u); ++cls) {
+                const uint32_t k1 = MULTI ? B.cls_end[cls] : B.n_sub;
+                for (uint32_t k = k0; k < k1; ++k) {
+                  const TSub& sd = subs[B.sub_off + k];
+                  const double* cv = co + 2 * (size_t(B.coef_off) + size_t(k) * B.n_rec + r);
+                  const int par = popc(dl & sd.w_loc) + popc(rc.bits & sd.w_loc) + popc(base & sd.w_out);
+                  const double t = cv[0] * hr[cls] - cv[1] * hi[cls];
+                  got += (par & 1) ? -t : t;
+                }
+                k0 = k1;
+              }
+              if (MULTI) CHECK(k0 == B.n_sub, "classes cover %u of %u subgroups", k0, B.n_sub);
+            }
+          }
+        }
+    }
+  }
+  got *= 2.0;
+  CHECK(std::fabs(got - want) <= 1e-12 * scale * nrm, "expectation n=%d b=%d: blob walk %.17g, direct %.17g", n, b,
+        got, want);
+  CHECK(multi > 0 || n_terms < 200, "no multi-class batch (n=%d)", n);
+  g_x_batches += batches;
+  g_x_multi += multi;
+  g_x_diff = std::max(g_x_diff, std::fabs(got - want) / (scale * nrm));
 }
 
 // Random 4-qubit rotations on 32 qubits (X/Y with an odd number of Y), in a
@@ -399,12 +591,16 @@ int main() {
   check_random_schedule();
   check_lambda(18, 12, &nw, &cs, &bs, kLambdaRegionBits);  // lambda, complex build
   check_lambda(18, 13, &nw, &cs, &bs, kLambdaRegionBits);  // lambda, real-part tiles
-  check_lambda(18, 13, &nw, &cs, &bs, 0);                  // expectation (complex128 frames)
+  check_lambda(18, 13, &nw, &cs, &bs, 0);                  // lambda, fast build (no region bits)
+  check_expect(12, 8, 3, 400);                             // several frames and tiles
+  check_expect(9, 14, 3, 150);                             // one frame smaller than a tile
+  check_expect(14, 10, 4, 600);
   if (g_fail) {
     std::printf("%d failures over %ld walks\n", g_fail, nw);
     return 1;
   }
-  std::printf("ok %ld walks, mean cost %.4f (least %.4f), %ld run pairs reordered\n", nw, cs / double(nw),
-              bs / double(nw), g_moved);
+  std::printf("ok %ld walks, mean cost %.4f (least %.4f), %ld run pairs reordered; expectation: %ld batches (%ld "
+              "multi-class), relative difference %.3g\n",
+              nw, cs / double(nw), bs / double(nw), g_moved, g_x_batches, g_x_multi, g_x_diff);
   return 0;
 }
