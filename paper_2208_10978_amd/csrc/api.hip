@@ -287,7 +287,7 @@ static int tiling_get(sv_hamiltonian* h, int dtype, int role, DevTiling** out) {
     // kernels read the tables through scalar loads, so a tile's groups need
     // not be split
     t.host = build_tiling(h->groups, h->n, b, c, true, size_t(1) << 24, role >= 3 ? kLambdaRegionBits : 0,
-                          role == 0 ? kExpectThreads / 64 : 0);
+                          role == 0 ? kExpectThreads / 64 : role <= 2 ? kLambdaThreads / 64 : 0);
     if (t.host.blob_overflow) return fail(SV_EINVAL, "internal: a tile's group tables are too large");
     Packer pk;
     t.o_frames = pk.add(t.host.frames.data(), t.host.frames.size() * sizeof(FrameDesc));

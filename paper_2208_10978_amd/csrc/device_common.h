@@ -322,24 +322,40 @@ struct TileAddrLean {
   }
 };
 
+// Offset of element i of the thread's share: the element's part is built on
+// the scalar unit and made opaque to the optimiser, so it is recomputed at
+// each use rather than hoisted out of the tile loop as PER 64-bit VGPR
+// addresses.
+template <int NT, int PER>
+__device__ __forceinline__ uint64_t lean_off(const TileAddrLean<NT, PER>& a, const FrameDesc& fr, int i) {
+  constexpr int kT = TileAddrLean<NT, PER>::kT, kE = TileAddrLean<NT, PER>::kE;
+  uint64_t el = 0;  // uniform
+#pragma unroll
+  for (int k = 0; k < kE; ++k)
+    if ((i >> k) & 1) el |= uint64_t(1) << fr.q[kT + k];
+  uint32_t lo = __builtin_amdgcn_readfirstlane(uint32_t(el)), hi = __builtin_amdgcn_readfirstlane(uint32_t(el >> 32));
+  asm volatile("" : "+s"(lo), "+s"(hi));
+  return a.thr | (uint64_t(hi) << 32 | lo);
+}
+
 template <typename T, int PER, int NT>
 __device__ __forceinline__ void tile_fetch_full(const T* __restrict__ src, const TileAddrLean<NT, PER>& a,
                                                 const FrameDesc& fr, uint64_t base, Stage<T, PER>& reg) {
-  constexpr int kT = TileAddrLean<NT, PER>::kT, kE = TileAddrLean<NT, PER>::kE;
   const T* p = src + base;
 #pragma unroll
   for (int i = 0; i < PER; ++i) {
-    uint64_t el = 0;  // uniform
-#pragma unroll
-    for (int k = 0; k < kE; ++k)
-      if ((i >> k) & 1) el |= uint64_t(1) << fr.q[kT + k];
-    // opaque to the optimiser: recomputed at each fetch (SALU) rather than
-    // hoisted out of the tile loop as PER 64-bit VGPR addresses
-    asm volatile("" : "+s"(el));
-    const T v = p[a.thr | el];
+    const T v = p[lean_off(a, fr, i)];
     reg.re[i] = v.x;
     reg.im[i] = v.y;
   }
+}
+
+template <typename T, int PER, int NT>
+__device__ __forceinline__ void tile_send(T* __restrict__ dst, const TileAddrLean<NT, PER>& a, const FrameDesc& fr,
+                                          uint64_t base, const Stage<T, PER>& reg) {
+  T* p = dst + base;
+#pragma unroll
+  for (int i = 0; i < PER; ++i) p[lean_off(a, fr, i)] = cmake<T>(reg.re[i], reg.im[i]);
 }
 
 template <typename T, int PER, int NT>

@@ -368,6 +368,182 @@ __device__ __forceinline__ void fast_pairs_owned(const FastHead& f, uint32_t ds,
   }
 }
 
+// ---------------------------------------------------------------------------
+// Projected-sum tables (XHdr blobs, see XBatch): the expectation tilings and
+// the fast lambda tilings share them.
+// ---------------------------------------------------------------------------
+struct XView {
+  const XHdr* hdr;
+  const XBatch* batches;
+  const XItem* items;
+  const uint32_t* start;
+  const XRec* recs;
+  const TSub* subs;
+  const double2* coef;
+  __device__ explicit XView(const uint4* blob) {
+    const char* b = reinterpret_cast<const char*>(blob);
+    hdr = reinterpret_cast<const XHdr*>(b);
+    batches = reinterpret_cast<const XBatch*>(b + hdr->off_batch);
+    items = reinterpret_cast<const XItem*>(b + hdr->off_items);
+    start = reinterpret_cast<const uint32_t*>(b + hdr->off_start);
+    recs = reinterpret_cast<const XRec*>(b + hdr->off_rec);
+    subs = reinterpret_cast<const TSub*>(b + hdr->off_sub);
+    coef = reinterpret_cast<const double2*>(b + hdr->off_coef);
+  }
+};
+
+// (hr, hi) += conj(a) b
+template <typename T>
+__device__ __forceinline__ void acc_pair(const T& a, const T& b, double& hr, double& hi) {
+  const double ax = (double)a.x, bx = (double)b.x;
+  if constexpr (is_real_amp<T>) {
+    hr = fma(ax, bx, hr);
+    (void)hi;
+  } else {
+    const double ay = (double)a.y, by = (double)b.y;
+    hr = fma(ax, bx, fma(ay, by, hr));
+    hi = fma(ax, by, fma(-ay, bx, hi));
+  }
+}
+
+// a with its sign bits XORed with sgn (0 or 0x80000000): -a or a
+__device__ __forceinline__ float2 sign_xor(float2 a, uint32_t sgn) {
+  return make_float2(__uint_as_float(__float_as_uint(a.x) ^ sgn), __uint_as_float(__float_as_uint(a.y) ^ sgn));
+}
+__device__ __forceinline__ double sign_xor1(double v, uint32_t sgn) {
+  return __hiloint2double(__double2hiint(v) ^ int(sgn), __double2loint(v));
+}
+__device__ __forceinline__ double2 sign_xor(double2 a, uint32_t sgn) {
+  return make_double2(sign_xor1(a.x, sgn), sign_xor1(a.y, sgn));
+}
+__device__ __forceinline__ R64 sign_xor(R64 a, uint32_t sgn) { return R64{sign_xor1(a.x, sgn)}; }
+
+// An LDS element by byte offset (the tile sits at a fixed LDS address, which
+// the read instruction takes as its immediate offset).
+template <typename T>
+__device__ __forceinline__ T lds_at(const T* tp, uint32_t off) {
+  return *reinterpret_cast<const T*>(reinterpret_cast<const char*>(tp) + off);
+}
+
+// lambda over one work item of a batch (the fast build).  Per record each
+// lane first forms G at its 2^NR register patterns from the subgroups: one
+// signed sum of T_k[r] per class (the signs of the lane's, the record's and
+// the out-of-frame bits of w_k), then the butterfly over v, since
+// G(v) = sum_cls (-1)^{|v & cls|} A_cls.  G is then the same for every chunk
+// but for the chunk's w0 sign.  The chunk walk reads both ends of each pair
+// and adds lam[m] += G psi[m'] and lam[m'] += conj(G) psi[m] with LDS atomics
+// (other wavefronts may update the same outputs).  REAL: psi, T and lambda
+// are real; only real parts are read and added.
+template <typename TT, bool REAL, int NR, bool MULTI, bool SIGNED>
+__device__ __forceinline__ void x_lambda_records(const XView& xv, const XBatch* bp, const XItem& it, uint64_t base,
+                                                 const TT* tp, double* tlr, double* tli, uint32_t dl, uint32_t sdl) {
+  constexpr int NV = 1 << NR;
+  constexpr int NA = MULTI ? NV : 1;
+  uint32_t vs[NV];
+#pragma unroll
+  for (int v = 0; v < NV; ++v) vs[v] = bp->vslot[v];
+  const uint32_t sx = bp->sx, n_rec = bp->n_rec, rec_off = bp->rec_off;
+  const uint32_t n_sub = bp->n_sub, sub_off = bp->sub_off, coef_off = bp->coef_off;
+  const uint32_t r1 = it.recs >> 16, c0 = it.chunks & 0xffffu, c1 = it.chunks >> 16;
+  for (uint32_t r = it.recs & 0xffffu; r < r1; ++r) {
+    const XRec rc = xv.recs[rec_off + r];
+    double gr[NA], gi[NA];
+#pragma unroll
+    for (int v = 0; v < NA; ++v) gr[v] = gi[v] = 0.0;
+    uint32_t k0 = 0;
+#pragma unroll
+    for (int cls = 0; cls < NA; ++cls) {
+      const uint32_t k1 = MULTI ? bp->cls_end[cls] : n_sub;
+      for (uint32_t k = k0; k < k1; ++k) {
+        const TSub sd = xv.subs[sub_off + k];
+        const double2 cv = xv.coef[coef_off + k * n_rec + r];
+        const unsigned par = unsigned(__popc(dl & sd.w_loc)) + unsigned(__popc(rc.bits & sd.w_loc)) +
+                             unsigned(__popcll(base & sd.w_out));
+        gr[cls] += signed_by(cv.x, par);
+        if constexpr (!REAL) gi[cls] += signed_by(cv.y, par);
+      }
+      k0 = k1;
+    }
+    if constexpr (MULTI) {
+#pragma unroll
+      for (int h = 1; h < NV; h <<= 1)
+#pragma unroll
+        for (int v = 0; v < NV; ++v)
+          if (!(v & h)) {
+            const double r0 = gr[v], r1v = gr[v | h], i0 = gi[v], i1 = gi[v | h];
+            gr[v] = r0 + r1v;
+            gr[v | h] = r0 - r1v;
+            gi[v] = i0 + i1;
+            gi[v | h] = i0 - i1;
+          }
+    }
+    const uint32_t lb = sdl ^ rc.slot;
+    uint32_t cw = bp->cword[c0];
+    for (uint32_t c = c0; c < c1; ++c) {
+      const uint32_t cn = c + 1 < c1 ? bp->cword[c + 1] : 0u;  // prefetch
+      const uint32_t u = lb ^ (cw & 0x7fffffffu);
+      const uint32_t sg = cw & 0x80000000u;
+      uint32_t ob[NV];
+      TT pm[NV], pp[NV];
+#pragma unroll
+      for (int v = 0; v < NV; ++v) {
+        ob[v] = u ^ vs[v];      // m'
+        pm[v] = tp[ob[v] ^ sx];  // m = m' ^ x
+        pp[v] = tp[ob[v]];
+      }
+      __builtin_amdgcn_sched_barrier(0);
+#pragma unroll
+      for (int v = 0; v < NV; ++v) {
+        const uint32_t om = ob[v] ^ sx;
+        double g_r = gr[MULTI ? v : 0];
+        if constexpr (SIGNED) g_r = sign_xor1(g_r, sg);
+        if constexpr (REAL) {
+          lds_add(&tlr[om], g_r * (double)pp[v].x);  // lam[m] += G psi[m']
+          lds_add(&tlr[ob[v]], g_r * (double)pm[v].x);  // lam[m'] += G psi[m]
+        } else {
+          double g_i = gi[MULTI ? v : 0];
+          if constexpr (SIGNED) g_i = sign_xor1(g_i, sg);
+          const double ppx = (double)pp[v].x, ppy = (double)pp[v].y, pmx = (double)pm[v].x, pmy = (double)pm[v].y;
+          lds_add(&tlr[om], g_r * ppx - g_i * ppy);  // lam[m] += G psi[m']
+          lds_add(&tli[om], g_r * ppy + g_i * ppx);
+          lds_add(&tlr[ob[v]], g_r * pmx + g_i * pmy);  // lam[m'] += conj(G) psi[m]
+          lds_add(&tli[ob[v]], g_r * pmy - g_i * pmx);
+        }
+      }
+      cw = cn;
+    }
+  }
+}
+
+template <typename TT, bool REAL, int NR, bool MULTI>
+__device__ __forceinline__ void x_lambda_records_s(const XView& xv, const XBatch* bp, const XItem& it, uint64_t base,
+                                                   const TT* tp, double* tlr, double* tli, uint32_t dl, uint32_t sdl) {
+  if (bp->signed_chunks) x_lambda_records<TT, REAL, NR, MULTI, true>(xv, bp, it, base, tp, tlr, tli, dl, sdl);
+  else x_lambda_records<TT, REAL, NR, MULTI, false>(xv, bp, it, base, tp, tlr, tli, dl, sdl);
+}
+
+template <typename TT, bool REAL>
+__device__ __forceinline__ void x_lambda_item(const XView& xv, const XItem& it, uint64_t base, const TT* tp,
+                                              double* tlr, double* tli, uint32_t lane) {
+  const XBatch* bp = xv.batches + it.batch;
+  const uint32_t lp = bp->lane_pack, nl = bp->n_lane;
+  if ((lane >> nl) != 0u) return;  // lanes past a small frame's free bits
+  uint32_t dl = 0;
+#pragma unroll
+  for (int i = 0; i < kXLaneBits; ++i)
+    if (uint32_t(i) < nl) dl |= ((lane >> i) & 1u) << ((lp >> (4 * i)) & 15u);
+  const uint32_t sdl = lds_swz(dl);
+  static_assert(kXRegBits == 2, "one case per register-bit count");
+  switch (bp->n_reg + (bp->n_cls > 1 ? 4u : 0u)) {
+    case 0: x_lambda_records_s<TT, REAL, 0, false>(xv, bp, it, base, tp, tlr, tli, dl, sdl); break;
+    case 1: x_lambda_records_s<TT, REAL, 1, false>(xv, bp, it, base, tp, tlr, tli, dl, sdl); break;
+    case 2: x_lambda_records_s<TT, REAL, 2, false>(xv, bp, it, base, tp, tlr, tli, dl, sdl); break;
+    case 5: x_lambda_records_s<TT, REAL, 1, true>(xv, bp, it, base, tp, tlr, tli, dl, sdl); break;
+    case 6: x_lambda_records_s<TT, REAL, 2, true>(xv, bp, it, base, tp, tlr, tli, dl, sdl); break;
+    default: break;  // several classes need a register bit: not planned
+  }
+}
+
 // An LDS slot of a real psi tile: the amplitude's real part in FP64.
 struct RealSlot {
   double x;
@@ -389,85 +565,28 @@ __device__ __forceinline__ void lambda_tiles(const T* __restrict__ psi, T* __res
   constexpr bool kRealTile = std::is_same<TT, RealSlot>::value;
   constexpr int NW = NT / 64;
   constexpr int PER = (1 << B) / NT;
-  const BlobView bv(blob);
   const int lane = threadIdx.x & 63;
   const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
-  uint32_t lbit[kWalkLaneBits];  // all ones where the lane index has bit i
-#pragma unroll
-  for (int i = 0; i < kWalkLaneBits; ++i) lbit[i] = 0u - ((uint32_t(lane) >> i) & 1u);
-  const uint32_t n_groups = bv.hdr->n_groups, n_segs = bv.hdr->n_segs, n_fact = bv.hdr->n_fact;
-  const uint32_t n_items = bv.hdr->n_fast_items;
 
-  // fast build: every wavefront on the whole tile, LDS atomic adds
+  // fast build: every wavefront on the whole tile, LDS atomic adds; the
+  // tables are projected-sum batches with per-wavefront work lists
   auto apply_groups_fast = [&](uint64_t base) {
-    if (n_fact) {
-      factored_base<NW>(bv, n_groups, base, wave, lane, fB);
-      __syncthreads();
-    }
-    // groups with several subgroups: every thread of the block takes pairs
-    // (record, position of the free bits), G(m) summed over the subgroups
-    for (uint32_t gi = 0; gi < n_groups; ++gi) {
-      const TGroup g = bv.groups[gi];
-      const int nf = int(fr.b) - int(g.n_sins);
-      const uint32_t n_it = g.n_rec << nf;
-      auto pair = [&](uint32_t r, uint32_t t) {
-        const uint32_t lmp = insert_zeros32_p4(t, g.sins_pack, g.n_sins) | bv.recs[g.rec_off + r];
-        const uint32_t lm = lmp ^ g.x_loc;
-        double gre, gim;  // G(m)
-        general_g(bv, g, r, lmp, base, fB, gre, gim);
-        const uint32_t smp = lds_swz(lmp), sm = lds_swz(lm);
-        if constexpr (REAL) {
-          lds_add(&tlr[sm], gre * (double)tp[smp].x);
-          lds_add(&tlr[smp], gre * (double)tp[sm].x);
-        } else {
-          const T pm = tp[sm], pp = tp[smp];
-          lds_add(&tlr[sm], gre * (double)pp.x - gim * (double)pp.y);  // lam[m] += G psi[m']
-          lds_add(&tli[sm], gre * (double)pp.y + gim * (double)pp.x);
-          lds_add(&tlr[smp], gre * (double)pm.x + gim * (double)pm.y);  // lam[m'] += conj(G) psi[m]
-          lds_add(&tli[smp], gre * (double)pm.y - gim * (double)pm.x);
-        }
-      };
-      if (nf >= 6) {
-        // 2^nf >= 64: a wavefront's positions share one record, so its index
-        // is uniform and the tables arrive by scalar loads (a vector load here
-        // would also wait for the tile loads in flight)
-        for (uint32_t idx = threadIdx.x; idx < n_it; idx += NT)
-          pair(__builtin_amdgcn_readfirstlane(idx >> nf), idx & ((1u << nf) - 1u));
-      } else {
-        for (uint32_t idx = threadIdx.x; idx < n_it; idx += NT) pair(idx >> nf, idx & ((1u << nf) - 1u));
-      }
-    }
-    // one-subgroup groups: a wavefront takes a contiguous run of work items;
-    // a lane takes one position and every record's pair there
-    {
-      const uint32_t per = (n_items + NW - 1) / NW;
-      walk_fast_items_paired(
-          bv, min(n_items, uint32_t(wave) * per), min(n_items, uint32_t(wave + 1) * per), base, uint32_t(lane), lbit,
-          [&](const FastHead& f, uint32_t ds, unsigned zp, uint32_t srest, unsigned sgn, bool on) {
-            if (!on) return;
-            switch (f.n_rec) {
-              case 1: fast_pairs_add<1, REAL>(f, ds, zp, srest, sgn, tp, tlr, tli); break;
-              case 2: fast_pairs_add<2, REAL>(f, ds, zp, srest, sgn, tp, tlr, tli); break;
-              case 3: fast_pairs_add<3, REAL>(f, ds, zp, srest, sgn, tp, tlr, tli); break;
-              default: fast_pairs_add<4, REAL>(f, ds, zp, srest, sgn, tp, tlr, tli); break;
-            }
-          },
-          [&](const FastHead& f, uint32_t ds, unsigned zp, uint32_t s0, unsigned g0, uint32_t s1, unsigned g1,
-              bool on) {
-            if (!on) return;
-            switch (f.n_rec) {
-              case 1: fast_pairs_add2<1, REAL>(f, ds, zp, s0, g0, s1, g1, tp, tlr, tli); break;
-              case 2: fast_pairs_add2<2, REAL>(f, ds, zp, s0, g0, s1, g1, tp, tlr, tli); break;
-              case 3: fast_pairs_add2<3, REAL>(f, ds, zp, s0, g0, s1, g1, tp, tlr, tli); break;
-              default: fast_pairs_add2<4, REAL>(f, ds, zp, s0, g0, s1, g1, tp, tlr, tli); break;
-            }
-          });
-    }
+    const XView xv(blob);
+    const bool lists = xv.hdr->n_waves == uint32_t(NW);
+    const uint32_t i0 = lists ? xv.start[wave] : uint32_t(wave);
+    const uint32_t i1 = lists ? xv.start[wave + 1] : xv.hdr->n_items;
+    const uint32_t step = lists ? 1u : uint32_t(NW);
+    for (uint32_t i = i0; i < i1; i += step) x_lambda_item<TT, REAL>(xv, xv.items[i], base, tp, tlr, tli, uint32_t(lane));
     __syncthreads();
   };
 
   // reproducible build: region-owned segments, plain loads and stores
   auto apply_groups_owned = [&](uint64_t base) {
+    const BlobView bv(blob);
+    uint32_t lbit[kWalkLaneBits];  // all ones where the lane index has bit i
+#pragma unroll
+    for (int i = 0; i < kWalkLaneBits; ++i) lbit[i] = 0u - ((uint32_t(lane) >> i) & 1u);
+    const uint32_t n_groups = bv.hdr->n_groups, n_segs = bv.hdr->n_segs, n_fact = bv.hdr->n_fact;
     if (n_fact) {
       factored_base<NW>(bv, n_groups, base, wave, lane, fB);
       __syncthreads();
@@ -542,20 +661,20 @@ __device__ __forceinline__ void lambda_tiles(const T* __restrict__ psi, T* __res
   if constexpr (FULL) {
     // next loads before the groups; this tile's lambda leaves only after the
     // next tile is in place, so its stores overlap the next tile's groups
-    const TileAddr<NT, PER> ta(fr);
+    const TileAddrLean<NT, PER> ta(fr);
     auto fetch = [&](uint64_t bx) {
-      tile_fetch_full<T, PER, NT>(psi, ta, bx, rp);
+      tile_fetch_full<T, PER, NT>(psi, ta, fr, bx, rp);
       if (MODE == 1) {
         if (diag) {
           const double* d = diag + bx;
 #pragma unroll
-          for (int i = 0; i < PER; ++i) rd[i] = d[ta.off[i]];
+          for (int i = 0; i < PER; ++i) rd[i] = d[lean_off(ta, fr, i)];
         } else {
 #pragma unroll
           for (int i = 0; i < PER; ++i) rd[i] = 0.0;
         }
       } else {
-        tile_fetch_full<T, PER, NT>(lam, ta, bx, rl);
+        tile_fetch_full<T, PER, NT>(lam, ta, fr, bx, rl);
       }
     };
     auto put = [&]() {
@@ -590,7 +709,7 @@ __device__ __forceinline__ void lambda_tiles(const T* __restrict__ psi, T* __res
         out.im[i] = REAL ? R(0) : R(tli[sl]);
       }
       if (nx < n_tb) put();
-      tile_send<T, PER, NT>(lam, ta, base, out);
+      tile_send<T, PER, NT>(lam, ta, fr, base, out);
       __syncthreads();
     }
   } else {
@@ -717,59 +836,6 @@ __global__ void __launch_bounds__(NT) k_tile_lambda_real(const T* __restrict__ p
 // sign of their lane, record and out-of-frame bits; each lane keeps its FP64
 // sum, reduced per block in a fixed order.
 // ---------------------------------------------------------------------------
-struct XView {
-  const XHdr* hdr;
-  const XBatch* batches;
-  const XItem* items;
-  const uint32_t* start;
-  const XRec* recs;
-  const TSub* subs;
-  const double2* coef;
-  __device__ explicit XView(const uint4* blob) {
-    const char* b = reinterpret_cast<const char*>(blob);
-    hdr = reinterpret_cast<const XHdr*>(b);
-    batches = reinterpret_cast<const XBatch*>(b + hdr->off_batch);
-    items = reinterpret_cast<const XItem*>(b + hdr->off_items);
-    start = reinterpret_cast<const uint32_t*>(b + hdr->off_start);
-    recs = reinterpret_cast<const XRec*>(b + hdr->off_rec);
-    subs = reinterpret_cast<const TSub*>(b + hdr->off_sub);
-    coef = reinterpret_cast<const double2*>(b + hdr->off_coef);
-  }
-};
-
-// (hr, hi) += conj(a) b
-template <typename T>
-__device__ __forceinline__ void acc_pair(const T& a, const T& b, double& hr, double& hi) {
-  const double ax = (double)a.x, bx = (double)b.x;
-  if constexpr (is_real_amp<T>) {
-    hr = fma(ax, bx, hr);
-    (void)hi;
-  } else {
-    const double ay = (double)a.y, by = (double)b.y;
-    hr = fma(ax, bx, fma(ay, by, hr));
-    hi = fma(ax, by, fma(-ay, bx, hi));
-  }
-}
-
-// a with its sign bits XORed with sgn (0 or 0x80000000): -a or a
-__device__ __forceinline__ float2 sign_xor(float2 a, uint32_t sgn) {
-  return make_float2(__uint_as_float(__float_as_uint(a.x) ^ sgn), __uint_as_float(__float_as_uint(a.y) ^ sgn));
-}
-__device__ __forceinline__ double sign_xor1(double v, uint32_t sgn) {
-  return __hiloint2double(__double2hiint(v) ^ int(sgn), __double2loint(v));
-}
-__device__ __forceinline__ double2 sign_xor(double2 a, uint32_t sgn) {
-  return make_double2(sign_xor1(a.x, sgn), sign_xor1(a.y, sgn));
-}
-__device__ __forceinline__ R64 sign_xor(R64 a, uint32_t sgn) { return R64{sign_xor1(a.x, sgn)}; }
-
-// An LDS element by byte offset (the tile sits at a fixed LDS address, which
-// the read instruction takes as its immediate offset).
-template <typename T>
-__device__ __forceinline__ T lds_at(const T* tp, uint32_t off) {
-  return *reinterpret_cast<const T*>(reinterpret_cast<const char*>(tp) + off);
-}
-
 // One work item of a batch: NR register bits (2^NR positions per lane and
 // chunk); MULTI: subgroups of several classes (one accumulator per v), else
 // every subgroup has class 0 and one accumulator takes every position;

@@ -358,13 +358,14 @@ static void check_lambda(int n, int b, long* nw, double* cs, double* bs, int rb)
   CHECK(rb == 0 || n_seg > 0, "no segments");
 }
 
-// Expectation tilings (projected sums): a CPU walk of every work item of
-// every blob, the way the tile kernel takes it (lane deposit, register
-// patterns, chunk words and their signs, Walsh-Hadamard transform over the
-// register patterns, the subgroups' signs), must reproduce
+// Projected-sum tilings (expectation and fast lambda): a CPU walk of every
+// work item of every blob, the way the tile kernels take it (lane deposit,
+// register patterns, chunk words and their signs, Walsh-Hadamard transform
+// over the register patterns, the subgroups' signs), must reproduce
 //   sum_t c_t <psi|P_t|psi>,  <psi|P|psi> = sum_m conj(psi[m]) i^{|x&z|} (-1)^{|(m^x)&z|} psi[m^x],
-// summed directly over the terms, on a seeded random state; and each batch's
-// items must cover its records x chunks exactly once.  The sums mix random
+// and lambda = sum_t c_t P_t psi element by element, both summed directly
+// over the terms, on a seeded random state; and each batch's items must
+// cover its records x chunks exactly once.  The sums mix random
 // strings of weight <= 4, Jordan-Wigner hopping strings with number-operator
 // variants (many subgroups over a Z chain) and strings whose support is too
 // wide to enumerate.
@@ -414,7 +415,19 @@ static void check_expect(int n, int b, int c, int n_terms) {
     pi[m] = 2.0 * next_unit() - 1.0;
     nrm += pr[m] * pr[m] + pi[m] * pi[m];
   }
-  // direct sum over the terms
+  // direct sum over the terms, and lambda = H psi term by term
+  std::vector<double> lr_want(pr.size(), 0.0), li_want(pr.size(), 0.0);
+  for (size_t t = 0; t < p.size(); ++t) {
+    const int ph = popc(p[t].x & p[t].z) & 3;  // (P psi)[m] = i^ph (-1)^{|(m^x)&z|} psi[m^x]
+    for (uint64_t m = 0; m <= all; ++m) {
+      const uint64_t m2 = m ^ p[t].x;
+      const double sg = (popc(m2 & p[t].z) & 1) ? -coef[t] : coef[t];
+      const double a = sg * pr[m2], b = sg * pi[m2];
+      lr_want[m] += ph == 0 ? a : ph == 1 ? -b : ph == 2 ? -a : b;
+      li_want[m] += ph == 0 ? b : ph == 1 ? a : ph == 2 ? -b : -a;
+    }
+  }
+  std::vector<double> lr_got(pr.size(), 0.0), li_got(pr.size(), 0.0);
   double want = 0.0, scale = 0.0;
   for (size_t t = 0; t < p.size(); ++t) {
     double re = 0.0, im = 0.0;  // sum_m conj(psi[m]) (-1)^{|(m^x)&z|} psi[m^x]
@@ -470,6 +483,7 @@ static void check_expect(int n, int b, int c, int n_terms) {
     for (int j = 0; j < nb; ++j) qm |= uint64_t(1) << fr.q[j];
     const uint64_t comp = all & ~qm;
     std::vector<double> tr(size_t(1) << nb), ti(size_t(1) << nb);
+    std::vector<uint64_t> glob(size_t(1) << nb);  // global index of each LDS slot
     for (uint64_t tb = 0; tb < (uint64_t(1) << popc(comp)); ++tb) {
       uint64_t base = 0;
       {
@@ -483,6 +497,7 @@ static void check_expect(int n, int b, int c, int n_terms) {
           if ((l >> j) & 1u) g |= uint64_t(1) << fr.q[j];
         tr[lds_slot(l)] = pr[g];
         ti[lds_slot(l)] = pi[g];
+        glob[lds_slot(l)] = g;
       }
       for (int w = 0; w < NW; ++w)
         for (uint32_t i = start[w]; i < start[w + 1]; ++i) {
@@ -533,6 +548,45 @@ static void check_expect(int n, int b, int c, int n_terms) {
                 k0 = k1;
               }
               if (MULTI) CHECK(k0 == B.n_sub, "classes cover %u of %u subgroups", k0, B.n_sub);
+              // lambda, as the fast lambda build walks the item: G at the
+              // lane's register patterns, then lam[m] += G psi[m'] and
+              // lam[m'] += conj(G) psi[m] over the chunks
+              double gr[4] = {0, 0, 0, 0}, gi[4] = {0, 0, 0, 0};
+              uint32_t q0 = 0;
+              for (uint32_t cls = 0; cls < (MULTI ? nv : 1u); ++cls) {
+                const uint32_t q1 = MULTI ? B.cls_end[cls] : B.n_sub;
+                for (uint32_t k = q0; k < q1; ++k) {
+                  const TSub& sd = subs[B.sub_off + k];
+                  const double* cv = co + 2 * (size_t(B.coef_off) + size_t(k) * B.n_rec + r);
+                  const int par = popc(dl & sd.w_loc) + popc(rc.bits & sd.w_loc) + popc(base & sd.w_out);
+                  gr[cls] += (par & 1) ? -cv[0] : cv[0];
+                  gi[cls] += (par & 1) ? -cv[1] : cv[1];
+                }
+                q0 = q1;
+              }
+              if (MULTI)
+                for (uint32_t hh = 1; hh < nv; hh <<= 1)
+                  for (uint32_t v = 0; v < nv; ++v)
+                    if (!(v & hh)) {
+                      const double r0 = gr[v], r1 = gr[v | hh], i0 = gi[v], i1 = gi[v | hh];
+                      gr[v] = r0 + r1;
+                      gr[v | hh] = r0 - r1;
+                      gi[v] = i0 + i1;
+                      gi[v | hh] = i0 - i1;
+                    }
+              for (uint32_t cc = it.chunks & 0xffffu; cc < (it.chunks >> 16); ++cc) {
+                const uint32_t u = sdl ^ rc.slot ^ (B.cword[cc] & 0x7fffffffu);
+                const double sg = (B.cword[cc] >> 31) ? -1.0 : 1.0;
+                for (uint32_t v = 0; v < nv; ++v) {
+                  const uint32_t s2 = u ^ B.vslot[v], s1 = s2 ^ B.sx;  // m', m
+                  const double g_r = sg * gr[MULTI ? v : 0], g_i = sg * gi[MULTI ? v : 0];
+                  const uint64_t gm = glob[s1], gp = glob[s2];
+                  lr_got[gm] += g_r * tr[s2] - g_i * ti[s2];  // lam[m] += G psi[m']
+                  li_got[gm] += g_r * ti[s2] + g_i * tr[s2];
+                  lr_got[gp] += g_r * tr[s1] + g_i * ti[s1];  // lam[m'] += conj(G) psi[m]
+                  li_got[gp] += g_r * ti[s1] - g_i * tr[s1];
+                }
+              }
             }
           }
         }
@@ -541,6 +595,11 @@ static void check_expect(int n, int b, int c, int n_terms) {
   got *= 2.0;
   CHECK(std::fabs(got - want) <= 1e-12 * scale * nrm, "expectation n=%d b=%d: blob walk %.17g, direct %.17g", n, b,
         got, want);
+  double lmax = 0.0;
+  for (size_t m = 0; m < pr.size(); ++m)
+    lmax = std::max(lmax, std::hypot(lr_got[m] - lr_want[m], li_got[m] - li_want[m]));
+  CHECK(lmax <= 1e-12 * scale, "lambda n=%d b=%d: blob walk differs from H psi by %.3g", n, b, lmax);
+  g_x_diff = std::max(g_x_diff, lmax / scale);
   CHECK(multi > 0 || n_terms < 200, "no multi-class batch (n=%d)", n);
   g_x_batches += batches;
   g_x_multi += multi;
