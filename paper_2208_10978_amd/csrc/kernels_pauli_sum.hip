@@ -18,7 +18,6 @@ struct BlobView {
   const TSub* subs;
   const double2* coef;
   const TFast* fast;
-  const uint32_t* items;
   const LamSeg* segs;
   __device__ explicit BlobView(const uint4* blob) {
     const char* b = reinterpret_cast<const char*>(blob);
@@ -28,7 +27,6 @@ struct BlobView {
     subs = reinterpret_cast<const TSub*>(b + hdr->off_sub);
     coef = reinterpret_cast<const double2*>(b + hdr->off_coef);
     fast = reinterpret_cast<const TFast*>(b + hdr->off_fast);
-    items = reinterpret_cast<const uint32_t*>(b + hdr->off_items);
     segs = reinterpret_cast<const LamSeg*>(b + hdr->off_segs);
   }
 };
@@ -41,11 +39,12 @@ struct BlobView {
 // and feed the vector arithmetic directly.  Contributions land in the FP64
 // accumulator tile (real and imaginary parts in separate arrays), in one of
 // two ways:
-//   * fast (DET = false): all wavefronts of the block work on the whole tile
-//     at once and add with LDS atomic adds, which return nothing, so an
-//     update is never a load-modify-store chain; the order in which the
-//     updates of different wavefronts reach an output is not fixed, so the
-//     last bits of lambda may differ between runs;
+//   * fast (DET = false): the tables are projected-sum batches (XBatch); all
+//     wavefronts of the block work on the whole tile at once, each on its
+//     host-balanced list of work items, and add with LDS atomic adds, which
+//     return nothing, so an update is never a load-modify-store chain; the
+//     order in which the updates of different wavefronts reach an output is
+//     not fixed, so the last bits of lambda may differ between runs;
 //   * reproducible (DET = true): the tile's groups come in segments whose
 //     flip masks avoid the segment's region bits; wavefront w owns the
 //     amplitudes whose region bits spell w, both ends of every pair it walks
@@ -106,69 +105,11 @@ __device__ __forceinline__ FastHead load_fast(const TFast& t) {
   return f;
 }
 
-// A wavefront's share of the one-subgroup work items: items [i0, i1) in
-// order, each 64 walk positions of one group.  A group's items are its
-// blocks 0, 1, ... in a row and groups follow in index order, so only the
-// first item is read: the walk steps block and group arithmetically, and a
-// group's record is fetched once, when the walk reaches it.  Two consecutive
-// blocks of one group go to body2 together (twice the LDS operations in
-// flight per lane, half the loop and slot arithmetic per block); a lone
-// block goes to body.  body(f, ds, zp, srest, sgn, on) gets the lane's slot
-// part, lane parity, the block's slot and the uniform sign parity.
-template <typename Body, typename Body2>
-__device__ __forceinline__ void walk_fast_items_paired(const BlobView& bv, uint32_t i0, uint32_t i1, uint64_t base,
-                                                       uint32_t lane, const uint32_t (&lbit)[kWalkLaneBits],
-                                                       Body body, Body2 body2) {
-  if (i0 >= i1) return;
-  const uint32_t w0 = bv.items[i0];
-  uint32_t cur = w0 >> 12, blk = w0 & 0xfffu;
-  FastHead f = load_fast(bv.fast[cur]);
-  auto setup = [&](uint32_t& ds, unsigned& zp, unsigned& so, bool& on, uint32_t& nb) {
-    on = f.walk_log >= kWalkLaneBits || lane < (1u << f.walk_log);
-    nb = f.walk_log > kWalkLaneBits ? 1u << (f.walk_log - kWalkLaneBits) : 1u;
-    ds = 0;
-#pragma unroll
-    for (int i = 0; i < kWalkLaneBits; ++i) ds ^= lbit[i] & f.dep_q[i];
-    zp = __popc(lane & f.wlane);
-    so = __popcll(base & f.w_out);
-  };
-  uint32_t ds, nb;
-  unsigned zp, so;
-  bool on;
-  setup(ds, zp, so, on, nb);
-  uint32_t rest = deposit_bits(blk, f.hi_mask);  // uniform
-  for (uint32_t it = i0; it < i1;) {
-    const uint32_t srest = lds_swz(rest);  // uniform: slot and w parity of the block's high bits
-    const unsigned prest = __popc(rest & f.w_loc) & 1u;
-    uint32_t step = 1;
-    if (it + 1 < i1 && blk + 1 < nb) {
-      const uint32_t rest1 = (rest - f.hi_mask) & f.hi_mask;
-      body2(f, ds, zp, srest, so ^ prest, lds_swz(rest1), so ^ (__popc(rest1 & f.w_loc) & 1u), on);
-      rest = rest1;
-      step = 2;
-    } else {
-      body(f, ds, zp, srest, so ^ prest, on);
-    }
-    it += step;
-    blk += step;
-    if (blk == nb) {
-      if (it < i1) {
-        ++cur;
-        blk = 0;
-        rest = 0;
-        f = load_fast(bv.fast[cur]);
-        setup(ds, zp, so, on, nb);
-      }
-    } else {
-      rest = (rest - f.hi_mask) & f.hi_mask;  // the next block of the same group
-    }
-  }
-}
-
 // A wavefront's walk over the fast records [f0, f1) of a lambda segment, in
 // order, on its own region (region bits wbits): each record's walk covers
 // the bits outside its support and the region bits.  body(f, ds, zp, srest,
-// sgn) as for walk_fast_items, with the region's slot and parity included.
+// sgn) gets the lane's slot part and w parity, and the block's slot and
+// uniform sign parity, the region's included.
 template <typename Body>
 __device__ __forceinline__ void walk_fast_region(const BlobView& bv, uint32_t f0, uint32_t f1, uint64_t base,
                                                  uint32_t lane, const uint32_t (&lbit)[kWalkLaneBits],
@@ -249,86 +190,12 @@ __device__ __forceinline__ void general_g(const BlobView& bv, const TGroup& g, u
 
 // The pairs (m', m = m' ^ x) of every record of a one-subgroup group at one
 // walk position (slot part ds, w-parity of the lane part zp) plus the uniform
-// part rest: all loads first, then the updates.  The slot of a record's m' is
-// ds ^ slot(rest | bits) (the LDS slot map is linear).  fast_pairs_add adds
-// with LDS atomics (other wavefronts may update the same outputs);
-// fast_pairs_owned with plain loads and stores, for a caller that owns both
-// ends of every pair (no two records share a slot).
+// part rest: all loads first, then the updates, with plain loads and stores
+// for a caller that owns both ends of every pair (no two records share a
+// slot).  The slot of a record's m' is ds ^ slot(rest | bits) (the LDS slot
+// map is linear).
 // REAL: psi and every coefficient are real, so lambda is real; only the real
 // parts are read and accumulated (the imaginary ones are exactly zero)
-template <int NR, bool REAL, typename TT>
-__device__ __forceinline__ void fast_pairs_add(const FastHead& f, uint32_t ds, unsigned zp, uint32_t srest,
-                                               unsigned so, const TT* tp, double* tlr, double* tli) {
-  uint32_t smp[NR];
-  double pmx[NR], pmy[NR], ppx[NR], ppy[NR];
-#pragma unroll
-  for (int r = 0; r < NR; ++r) {
-    smp[r] = ds ^ srest ^ f.sbits[r];
-    pmx[r] = (double)tp[smp[r] ^ f.sx].x;
-    ppx[r] = (double)tp[smp[r]].x;
-    if constexpr (!REAL) {
-      pmy[r] = (double)tp[smp[r] ^ f.sx].y;
-      ppy[r] = (double)tp[smp[r]].y;
-    }
-  }
-#pragma unroll
-  for (int r = 0; r < NR; ++r) {
-    const unsigned sg = zp + f.pbits[r] + so;
-    const uint32_t sm = smp[r] ^ f.sx;
-    const double gre = signed_by(f.coef[2 * r], sg);
-    if constexpr (REAL) {
-      lds_add(&tlr[sm], gre * ppx[r]);
-      lds_add(&tlr[smp[r]], gre * pmx[r]);
-    } else {
-      const double gim = signed_by(f.coef[2 * r + 1], sg);
-      lds_add(&tlr[sm], gre * ppx[r] - gim * ppy[r]);  // lam[m] += G psi[m']
-      lds_add(&tli[sm], gre * ppy[r] + gim * ppx[r]);
-      lds_add(&tlr[smp[r]], gre * pmx[r] + gim * pmy[r]);  // lam[m'] += conj(G) psi[m]
-      lds_add(&tli[smp[r]], gre * pmy[r] - gim * pmx[r]);
-    }
-  }
-}
-
-// fast_pairs_add at two walk positions of one lane (two blocks of a group):
-// every load of both first, then the atomic adds.
-template <int NR, bool REAL, typename TT>
-__device__ __forceinline__ void fast_pairs_add2(const FastHead& f, uint32_t ds, unsigned zp, uint32_t srest0,
-                                                unsigned so0, uint32_t srest1, unsigned so1, const TT* tp,
-                                                double* tlr, double* tli) {
-  uint32_t smp[2][NR];
-  double pmx[2][NR], pmy[2][NR], ppx[2][NR], ppy[2][NR];
-#pragma unroll
-  for (int b = 0; b < 2; ++b)
-#pragma unroll
-    for (int r = 0; r < NR; ++r) {
-      smp[b][r] = ds ^ (b ? srest1 : srest0) ^ f.sbits[r];
-      pmx[b][r] = (double)tp[smp[b][r] ^ f.sx].x;
-      ppx[b][r] = (double)tp[smp[b][r]].x;
-      if constexpr (!REAL) {
-        pmy[b][r] = (double)tp[smp[b][r] ^ f.sx].y;
-        ppy[b][r] = (double)tp[smp[b][r]].y;
-      }
-    }
-#pragma unroll
-  for (int b = 0; b < 2; ++b)
-#pragma unroll
-    for (int r = 0; r < NR; ++r) {
-      const unsigned sg = zp + f.pbits[r] + (b ? so1 : so0);
-      const uint32_t sm = smp[b][r] ^ f.sx;
-      const double gre = signed_by(f.coef[2 * r], sg);
-      if constexpr (REAL) {
-        lds_add(&tlr[sm], gre * ppx[b][r]);
-        lds_add(&tlr[smp[b][r]], gre * pmx[b][r]);
-      } else {
-        const double gim = signed_by(f.coef[2 * r + 1], sg);
-        lds_add(&tlr[sm], gre * ppx[b][r] - gim * ppy[b][r]);  // lam[m] += G psi[m']
-        lds_add(&tli[sm], gre * ppy[b][r] + gim * ppx[b][r]);
-        lds_add(&tlr[smp[b][r]], gre * pmx[b][r] + gim * pmy[b][r]);  // lam[m'] += conj(G) psi[m]
-        lds_add(&tli[smp[b][r]], gre * pmy[b][r] - gim * pmx[b][r]);
-      }
-    }
-}
-
 template <int NR, bool REAL, typename TT>
 __device__ __forceinline__ void fast_pairs_owned(const FastHead& f, uint32_t ds, unsigned zp, uint32_t srest, unsigned so,
                                            const TT* tp, double* tlr, double* tli) {

@@ -839,17 +839,6 @@ static void pack_blob(HTiling& t, const std::vector<HGroup>& gs, const std::vect
   h.off_fast = uint32_t(align16(off));
   h.n_fast = uint32_t(tf.size());
   off = h.off_fast + tf.size() * sizeof(TFast);
-  // work items of the fast records (expectation tilings): blocks of 64
-  // positions of the free bits
-  std::vector<uint32_t> items;
-  for (size_t i = 0; i < tf.size() && region_bits == 0; ++i) {
-    const int nf = int(tf[i].walk_log);
-    const uint32_t nblk = nf > kWalkLaneBits ? (1u << (nf - kWalkLaneBits)) : 1u;
-    for (uint32_t c = 0; c < nblk; ++c) items.push_back(uint32_t(i) << 12 | c);
-  }
-  h.off_items = uint32_t(align16(off));
-  h.n_fast_items = uint32_t(items.size());
-  off = h.off_items + items.size() * sizeof(uint32_t);
   h.off_segs = uint32_t(align16(off));
   off = h.off_segs + segs.size() * sizeof(LamSeg);
   h.bytes = uint32_t(align16(off));
@@ -861,7 +850,6 @@ static void pack_blob(HTiling& t, const std::vector<HGroup>& gs, const std::vect
   if (!ts.empty()) std::memcpy(bytes.data() + h.off_sub, ts.data(), ts.size() * sizeof(TSub));
   if (!co.empty()) std::memcpy(bytes.data() + h.off_coef, co.data(), co.size() * sizeof(double));
   if (!tf.empty()) std::memcpy(bytes.data() + h.off_fast, tf.data(), tf.size() * sizeof(TFast));
-  if (!items.empty()) std::memcpy(bytes.data() + h.off_items, items.data(), items.size() * sizeof(uint32_t));
   if (!segs.empty()) std::memcpy(bytes.data() + h.off_segs, segs.data(), segs.size() * sizeof(LamSeg));
   t.blob_off.push_back(uint32_t(t.blob.size() / 2));
   const size_t words = h.bytes / 8;

@@ -142,18 +142,17 @@ struct HTiling {
   bool blob_overflow = false;            // a blob exceeded max_blob (never expected)
 };
 
-// fast_records packs one-subgroup groups as TFast records.  region_bits = 0
-// (expectation tilings): their walks cover the bits outside S' and are cut
-// into work items of 64 positions.  region_bits > 0 (lambda tilings): each
-// tile's groups are reordered into LamSeg segments whose flip masks avoid
-// region_bits frame bits, and every walk (fast records and general groups)
-// leaves its segment's region bits out.
-// expect_waves > 0: expectation tilings in the projected-sum format (XHdr
-// blobs), with per-wavefront work lists balanced for that many wavefronts.
+// expect_waves > 0: projected-sum blobs (XHdr; the expectation and the fast
+// lambda build), with per-wavefront work lists balanced for that many
+// wavefronts.  Otherwise TileHdr blobs for the reproducible lambda build:
+// fast_records packs one-subgroup groups as TFast records, each tile's groups
+// are reordered into LamSeg segments whose flip masks avoid region_bits frame
+// bits, and every walk (fast records and general groups) leaves its
+// segment's region bits out.
 HTiling build_tiling(const std::vector<HGroup>& gs, int n, int b, int c, bool fast_records, size_t max_blob,
                      int region_bits = 0, int expect_waves = 0);
 
-// One expectation blob (XHdr) of a tile's groups, appended to t.
+// One projected-sum blob (XHdr) of a tile's groups, appended to t.
 void pack_expect_blob(HTiling& t, const std::vector<HGroup>& gs, const std::vector<int>& members, uint64_t qmask,
                       size_t max_blob, int n_waves);
 

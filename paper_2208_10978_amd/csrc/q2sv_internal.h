@@ -150,11 +150,11 @@ struct alignas(16) SubDesc {
 };
 
 // ---------------------------------------------------------------------------
-// Group tables of one Hamiltonian tile pass (the expectation kernel copies
-// them into LDS once per block; the lambda kernel reads them in place).  A
-// blob is a TileHdr followed by TGroup records, record bits, TSub records,
-// complex FP64 coefficients and TFast records (offsets in bytes from the
-// start of the blob).
+// Group tables of one Hamiltonian tile pass of the reproducible lambda build
+// (read in place through scalar loads).  A blob is a TileHdr followed by
+// TGroup records, record bits, TSub records, complex FP64 coefficients,
+// TFast records and LamSeg segments (offsets in bytes from the start of the
+// blob).
 //
 // Every non-diagonal group is treated as pairs (m, m' = m ^ x) with the pivot
 // (highest) bit of m clear.  "Enumerated bits" S' are the support of x (when
@@ -169,12 +169,11 @@ struct alignas(16) TileHdr {
   uint32_t off_sub;    // byte offset of the TSub array
   uint32_t off_coef;   // byte offset of the coefficients (double2)
   uint32_t bytes;      // blob size in bytes (multiple of 16)
-  uint32_t n_fast;     // TFast records (lambda tilings only)
+  uint32_t n_fast;     // TFast records
   uint32_t off_fast;   // byte offset of the TFast array
-  uint32_t n_fast_items;  // work items: TFast index << 12 | block c of 64 walk positions
-  uint32_t off_items;  // byte offset of the work items (uint32 each)
+  uint32_t pad0[2];
   uint32_t n_fact;     // factored groups (fact_idx 0 .. n_fact - 1)
-  uint32_t n_segs;     // lambda tilings: LamSeg records (0 otherwise)
+  uint32_t n_segs;     // LamSeg records
   uint32_t off_segs;   // byte offset of the LamSeg array
 };
 

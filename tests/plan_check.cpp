@@ -1,7 +1,7 @@
 // Host checks of the tile-walk planning (CPU only, built with the host
 // compiler against plan.cpp).  For seeded Jordan-Wigner-shaped rotation lists
 // (forward, per-parameter and per-string reverse schedules) and a seeded
-// Pauli sum (lambda tilings with and without region segments), the
+// Pauli sum (reproducible lambda tilings with region segments), the
 // segments of a lambda tile must cover its groups in order with
 // flip masks that avoid their region bits (and general groups must insert
 // zeros at their support and region bits), and every walk must
@@ -341,21 +341,11 @@ static void check_lambda(int n, int b, long* nw, double* cs, double* bs, int rb)
         check_walk("lambda", free_bits, f.walk_log, f.dep_p, f.dep_q, f.hi_mask, f.w_loc, f.wlane, nw, cs, bs);
       }
     }
-    if (rb == 0) {
-      // tilings without region bits: no segments; walks over the bits outside S'
-      CHECK(h->n_segs == 0, "segments in an expectation tiling");
-      for (uint32_t i = 0; i < h->n_fast; ++i, ++n_fast) {
-        const TFast& f = fs[i];
-        const uint32_t free_bits = ((1u << b) - 1u) & ~f.sup_mask;
-        check_walk("expect", free_bits, f.walk_log, f.dep_p, f.dep_q, f.hi_mask, f.w_loc, f.wlane, nw, cs, bs);
-      }
-      continue;
-    }
     CHECK(g_next == h->n_groups && f_next == h->n_fast, "segments cover %u/%u groups, %u/%u fast records", g_next,
           h->n_groups, f_next, h->n_fast);
   }
   CHECK(n_fast > 0, "no fast records");
-  CHECK(rb == 0 || n_seg > 0, "no segments");
+  CHECK(n_seg > 0, "no segments");
 }
 
 // Projected-sum tilings (expectation and fast lambda): a CPU walk of every
@@ -650,7 +640,6 @@ int main() {
   check_random_schedule();
   check_lambda(18, 12, &nw, &cs, &bs, kLambdaRegionBits);  // lambda, complex build
   check_lambda(18, 13, &nw, &cs, &bs, kLambdaRegionBits);  // lambda, real-part tiles
-  check_lambda(18, 13, &nw, &cs, &bs, 0);                  // lambda, fast build (no region bits)
   check_expect(12, 8, 3, 400);                             // several frames and tiles
   check_expect(9, 14, 3, 150);                             // one frame smaller than a tile
   check_expect(14, 10, 4, 600);
