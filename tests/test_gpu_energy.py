@@ -9,6 +9,7 @@ from oracle import statevector as osv
 from paper_2208_10978_amd import binding as B
 from paper_2208_10978_amd.engine import StateVector, UCCSDEvaluator, UCCEnergy
 from paper_2208_10978_amd.problem import jordan_wigner, uccsd_rotations
+from tests import c64_bounds as cb
 from tests.gpu_common import announce, to_np_state
 from workloads import (random_pauli_sum, random_rotations, synthetic_integrals, uccsd_excitation_order,
                        uniform_amplitudes)
@@ -107,8 +108,18 @@ def test_adjoint_parameter_gradient(n, ne, dtype):
         assert abs(e[0] - e_ref) <= 1e-10 * abs(e_ref)
         assert np.abs(g - g_ref).max() <= 1e-10 * max(1.0, np.abs(g_ref).max())
     else:
-        assert abs(e[0] - e_ref) <= 1e-5 * abs(e_ref)
-        assert np.abs(g - g_ref).max() <= 1e-4 * max(1.0, np.abs(g_ref).max())
+        # stated errors (tests/c64_bounds.py) with sigma_H and ||H psi|| of
+        # the oracle's final state; one run per excitation plus the
+        # renormalisation
+        rot = uccsd_rotations(n, ne, ORDER)
+        psi_n = osv.apply_rotations(psi0, rx, rz, phis)
+        h_psi = osv.apply_hamiltonian(psi_n, hx, hz, hc)
+        hn = float(np.linalg.norm(h_psi))
+        sigma = float(np.sqrt(max(hn * hn - e_ref * e_ref, 0.0)))
+        h1 = float(np.abs(hc).sum())
+        runs = rot.n_params + 1
+        assert abs(e[0] - e_ref) <= min(cb.energy_bound_probabilistic(runs, sigma, h1), cb.energy_bound(runs, sigma, h1))
+        assert np.all(np.abs(g - g_ref) <= cb.parameter_gradient_bounds(rot, runs, h1, hn))
 
 
 def test_autograd_function_matches_evaluator():
