@@ -3,12 +3,15 @@
 Requests arrive with their own qubit count, Hamiltonian and amplitudes.  The
 server keeps every admitted request's state vectors and Hamiltonian resident
 in HBM, admits a waiting request as soon as a slot is free and its bytes fit
-the HBM budget (in arrival order; a request that does not fit yet may be
-passed by a smaller one that does), and runs each admitted request on its own
-HIP stream, so the work of requests in flight together overlaps on the
-device.  A request's plans depend only on the request, so its result is the
-same alone and in any mix up to the rounding of lambda's accumulation (whose
-order across wavefronts is not fixed).
+the HBM budget, and runs each admitted request on its own HIP stream, so the
+work of requests in flight together overlaps on the device.  Waiting
+requests are admitted smallest state first (arrival order among equals), and
+at most ``max_heavy`` requests of ``heavy_qubits`` or more run at once: a
+request of 24 or 26 qubits fills the device by itself, so running two
+together only stretches both, while small requests fit beside one and need
+not queue behind it.  A request's plans depend only on the request and the
+executor uses the reproducible lambda build, so its result is bitwise the
+same alone and in any mix.
 
 A failed device (the library's sticky SV_EDEVICE, raised as DeviceFailure)
 ends admission: every request in flight, waiting or arriving later fails
@@ -142,10 +145,12 @@ class Server:
     requests submitted online from any thread.  Both use the same loop."""
 
     def __init__(self, executor=None, hbm_budget_bytes: int | None = None, max_slots: int = 8,
-                 prep_workers: int = 4, fifo: bool = False):
+                 prep_workers: int = 4, fifo: bool = False, heavy_qubits: int = 24, max_heavy: int = 1):
         self.ex = executor if executor is not None else GpuExecutor()
         self.budget = int(hbm_budget_bytes if hbm_budget_bytes is not None else self.ex.budget())
         self.max_slots = 1 if fifo else int(max_slots)
+        self.heavy_qubits = int(heavy_qubits)
+        self.max_heavy = int(max_heavy)
         self.pool = cf.ThreadPoolExecutor(max_workers=prep_workers)
         self.fifo = fifo
         self.peak_bytes = 0
@@ -208,11 +213,15 @@ class Server:
                 on_done(r)
             if self.device_error:
                 used = 0
+            if not self.fifo:  # smallest state first, arrival order among equals (a stable sort)
+                waiting.sort(key=lambda q: q.n_qubits)
+            heavy = sum(1 for _, q in active if q.n_qubits >= self.heavy_qubits)
             i = 0  # admissions
             while i < len(waiting) and len(active) < self.max_slots:
                 r = waiting[i]
                 fut = prep[id(r)]
-                if not fut.done() or used + r.device_bytes() > self.budget:
+                is_heavy = not self.fifo and r.n_qubits >= self.heavy_qubits
+                if not fut.done() or used + r.device_bytes() > self.budget or (is_heavy and heavy >= self.max_heavy):
                     if self.fifo:
                         break
                     i += 1
@@ -222,6 +231,7 @@ class Server:
                     fut.result()
                     r.t_admit = time.perf_counter() - t0
                     active.append((self.ex.launch(r), r))
+                    heavy += int(is_heavy)
                     used += r.device_bytes()
                     self.peak_bytes = max(self.peak_bytes, used)
                     self.peak_slots = max(self.peak_slots, len(active))

@@ -261,3 +261,37 @@ def test_online_server_fails_open_and_later_requests_after_a_device_failure():
         assert "device failed" in str(exc)
     srv.stop()
     assert srv.device_error is not None
+
+
+def test_smallest_state_first_and_one_heavy_request_at_a_time():
+    """Waiting requests are admitted smallest state first (arrival order among
+    equals), and at most max_heavy requests of heavy_qubits or more run at
+    once while smaller ones are admitted beside them."""
+    class Tracking(FakeExecutor):
+        def __init__(self, **kw):
+            super().__init__(**kw)
+            self.running = []
+            self.max_heavy_live = 0
+
+        def launch(self, req):
+            self.running = [q for q in self.running if not q[1].ready()]
+            job = super().launch(req)
+            self.running.append((req, job))
+            self.max_heavy_live = max(self.max_heavy_live, sum(1 for q, _ in self.running if q.n_qubits >= 6))
+            return job
+
+    # (qubits, electrons): request 0 arrives first and holds the one slot
+    # while the others arrive and finish their host preparation
+    sizes = [(2, 1), (6, 3), (6, 3), (4, 2), (6, 3), (2, 1), (4, 2)]
+    reqs = [Request(rid=i, n_qubits=q, n_electrons=e, h_seed=300 + i, theta_seed=400 + i, theta_amplitude=0.3,
+                    t_arrival=0.0 if i == 0 else 0.01) for i, (q, e) in enumerate(sizes)]
+    ex = Tracking(device_time=0.3)
+    out = Server(ex, max_slots=1, heavy_qubits=6, max_heavy=1).run(reqs, realtime=True)
+    assert all(r.error is None for r in out)
+    assert ex.launch_order == [0, 5, 3, 6, 1, 2, 4]        # then 2, 4, 4 and the 6-qubit ones in arrival order
+    ex2 = Tracking(device_time=0.05)
+    out2 = Server(ex2, max_slots=4, heavy_qubits=6, max_heavy=1).run(reqs, realtime=False)
+    assert all(r.error is None for r in out2)
+    assert ex2.max_heavy_live == 1 and ex2.max_live >= 2    # small ones ran beside a heavy one
+    for a, b in zip(sorted(out, key=lambda r: r.rid), sorted(out2, key=lambda r: r.rid)):
+        assert a.energy == b.energy and np.array_equal(a.grad, b.grad)
