@@ -284,6 +284,45 @@ def bench_c4(n_rot: int, n_terms: int):
     return res
 
 
+def bench_c4_stream(n_rot: int, chunk: int):
+    """The whole random rotation stream at 32 qubits, complex64 (not part of
+    the default run): n_rot seeded 4-support rotations with odd Y count
+    (real rotations, so the state stays real) applied to the Hartree-Fock
+    state in calls of `chunk` rotations, each timed; after each call the
+    FP64 norm <psi|psi> shows the accumulated rounding drift (each rotation
+    is unitary, so any departure from 1 is rounding)."""
+    import torch
+    from paper_2208_10978_amd import binding as B
+    from paper_2208_10978_amd.engine import StateVector
+    from workloads import random_rotations
+
+    n = 32
+    x, z, phi = random_rotations(n, n_rot, 4242)
+    s = StateVector(n, "c64")
+    s.prepare_hf((1 << 16) - 1)
+    s.apply_rotations(x[:64], z[:64], np.zeros(64))   # warm-up at angle 0 (the identity): plans, code load
+    torch.cuda.synchronize()
+    rows, total_s, passes = [], 0.0, 0
+    for k0 in range(0, n_rot, chunk):
+        k1 = min(n_rot, k0 + chunk)
+        B.sv_profile_begin()
+        t0 = time.perf_counter()
+        s.apply_rotations(x[k0:k1], z[k0:k1], phi[k0:k1])
+        torch.cuda.synchronize()
+        dt = time.perf_counter() - t0
+        prof = B.sv_profile_end()
+        total_s += dt
+        p = int(sum(v["launches"] for kk, v in prof.items() if kk in ("k_run_full", "k_tile_forward")))
+        passes += p
+        nrm = float(s.overlap(s)[0].item())
+        rows.append({"rotations": k1, "seconds": round(dt, 3), "passes": p, "norm_minus_1": nrm - 1.0})
+        log(f"C4 stream: {k1} rotations, {k1 / total_s:.1f} rotations/s, {passes} passes, |psi|^2 - 1 = {nrm - 1.0:.3e}")
+    s.free()
+    return {"workload": f"{n_rot} random 4-support rotations (seed 4242), {n} qubits complex64, calls of {chunk}",
+            "rotations_per_s": n_rot / total_s, "seconds": total_s, "passes": passes,
+            "rotations_per_pass": n_rot / passes, "chunks": rows}
+
+
 def bench_serve(n_req: int, rhos, seed: int):
     """Served stream (continuous batching) against the one-request-at-a-time
     path on the same Poisson trace: energy + gradient requests with qubit
@@ -308,6 +347,7 @@ def bench_serve(n_req: int, rhos, seed: int):
     if any(r.error for r in alone):
         raise RuntimeError(f"serving: {[r.error for r in alone if r.error][:3]}")
     fifo_rate = n_req / span
+    log(f"serving: {n_req} requests one at a time in {span:.1f} s")
     out = {
         "workload": f"{n_req} Poisson energy+gradient requests, qubits uniform in {{12,16,20,24,26}}, complex64, "
                     f"offered at rho x the one-at-a-time throughput (seed {seed})",
@@ -319,7 +359,9 @@ def bench_serve(n_req: int, rhos, seed: int):
         log(f"serving: one-at-a-time {fifo_rate:.2f} evals/s; offering {rate:.2f} requests/s (rho {rho:g})")
         srv = Server(max_slots=8)
         mixed = srv.run(trace(rate), realtime=True)
+        log(f"serving: rho {rho:g} continuous batching done, p50 {latency_stats(mixed).get('p50_s', 0):.3f} s")
         fifo = Server(fifo=True).run(trace(rate), realtime=True)
+        log(f"serving: rho {rho:g} one-at-a-time done, p50 {latency_stats(fifo).get('p50_s', 0):.3f} s")
         out["loads"].append({"rho": rho, "offered_requests_per_s": rate,
                              "continuous_batching": latency_stats(mixed), "fifo_same_trace": latency_stats(fifo),
                              "peak_slots": srv.peak_slots, "peak_hbm_bytes": srv.peak_bytes})
@@ -467,6 +509,8 @@ def main():
     ap.add_argument("--only-c4", action="store_true",
                     help="only the 32-qubit complex64 figures (for counter runs of the expectation)")
     ap.add_argument("--only-serve", action="store_true", help="only the served-stream figures")
+    ap.add_argument("--c4-stream", type=int, default=0,
+                    help="only apply this many rotations of the 32-qubit random stream, in calls of 10^4 (drift record)")
     args = ap.parse_args()
     if args.gpus != 1:
         print(json.dumps({"error": "q2sv runs on one GPU: --gpus must be 1 (the sharded design is described, not built)"}))
@@ -484,6 +528,9 @@ def main():
         return
     if args.only_c4:
         print(json.dumps({"c4": bench_c4(args.c4_rotations, 10_000)}), flush=True)
+        return
+    if args.c4_stream:
+        print(json.dumps({"c4_stream": bench_c4_stream(args.c4_stream, 10_000)}), flush=True)
         return
     if args.only_serve:
         print(json.dumps({"serving": bench_serve(args.serve_requests, (0.8, 1.0), 5151)}), flush=True)
