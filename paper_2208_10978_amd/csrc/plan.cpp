@@ -1194,6 +1194,28 @@ HTiling build_tiling(const std::vector<HGroup>& gs, int n, int b, int c, bool fa
       }
       todo.swap(rest);
     }
+    // The cover fills its first frames with every group they happen to
+    // contain, which leaves those passes bound by their pair arithmetic and
+    // the last ones by HBM.  Reassign each group, largest first, to the
+    // least loaded frame that contains its support (load: the pairs its
+    // records enumerate, a little more per subgroup).
+    std::vector<int> order;
+    for (int g = 0; g < G; ++g)
+      if (tile_of[g] >= 0) order.push_back(g);
+    auto cost = [&](int g) {
+      const HGroup& h = gs[g];
+      const int s = h.enumerated ? popc(h.x) : 1;
+      return double(h.n_rec()) * std::ldexp(1.0, b - s) * (1.0 + 0.1 * double(h.w.size()));
+    };
+    std::stable_sort(order.begin(), order.end(), [&](int a, int c2) { return cost(a) > cost(c2); });
+    std::vector<double> load(tile_q.size(), 0.0);
+    for (int g : order) {
+      int best = -1;
+      for (size_t tt = 0; tt < tile_q.size(); ++tt)
+        if ((gs[g].x & ~tile_q[tt]) == 0 && (best < 0 || load[tt] < load[size_t(best)])) best = int(tt);
+      tile_of[g] = best;
+      load[size_t(best)] += cost(g);
+    }
     if (tile_q.empty()) {
       uint64_t q = low;
       for (int qq = c; qq < n && popc(q) < b; ++qq) q |= uint64_t(1) << qq;
