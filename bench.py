@@ -374,9 +374,13 @@ def bench_small(reps: int = 10):
     1020 / 2020, U[-0.05, 0.05]), whose 16 MiB complex128 state stays in the
     on-package cache (a cache-resident rate, not an HBM fraction), in
     complex128 and in complex64 with FP64 reductions: the complex64 energy's
-    distance from the complex128 one beside its a-priori bound
-    2 ||H||_1 P gamma u (P = fused passes, one per excitation; gamma = 4;
-    u = 2^-24)."""
+    distance from the complex128 one beside its stated bounds.  With R fused
+    runs (one per excitation, plus the renormalisation), u = 2^-24 and
+    eps = 3 sqrt(2) u R the rigorous bound on ||d psi||, the energy is within
+    (2 sigma_H eps + 2 ||H||_1 eps^2) / (1 - eps)^2, and with the Hoeffding
+    form (probability 1 - 3e-8) within 72 u sigma_H sqrt(R) + the same
+    second-order term; sigma_H = ||(H - E) psi|| is taken from the complex128
+    state (lambda = H psi from the adjoint call with one rotation at angle 0)."""
     import torch
     from paper_2208_10978_amd.engine import UCCSDEvaluator
     from paper_2208_10978_amd.problem import jordan_wigner, uccsd_rotations
@@ -408,8 +412,27 @@ def bench_small(reps: int = 10):
             ev.free()
         row["energy_c128"] = energies["c128"]
         if "c64" in energies:
+            import math
+            from paper_2208_10978_amd import binding as B
+            from paper_2208_10978_amd.engine import StateVector
+            ev = UCCSDEvaluator(ham, rot, ne, "c128")
+            psi = ev.state(theta)
+            lam = StateVector(n, "c128")
+            eh = torch.empty(2, dtype=torch.float64, device="cuda")
+            gh = torch.empty(1, dtype=torch.float64, device="cuda")
+            B.sv_adjoint_grad(psi.handle, lam.handle, ham.x, ham.z, ham.c, np.array([1], np.uint64),
+                              np.array([1], np.uint64), np.array([0.0]), eh, gh)
+            torch.cuda.synchronize()
+            hpsi = float(torch.linalg.vector_norm(lam.amps).item())
+            sigma = math.sqrt(max(hpsi * hpsi - float(eh[0].item()) ** 2, 0.0))
+            psi.free(); lam.free(); ev.free()
+            u, runs, h1 = 2.0 ** -24, rot.n_params + 1, ham.one_norm()
+            eps = 3.0 * math.sqrt(2.0) * u * runs
+            second = 2.0 * h1 * eps * eps / (1.0 - eps) ** 2
             row["c64_minus_c128"] = energies["c64"] - energies["c128"]
-            row["c64_a_priori_bound"] = 2.0 * ham.one_norm() * rot.n_params * 4.0 * 2.0 ** -24
+            row["sigma_H"] = sigma
+            row["c64_energy_bound_rigorous"] = 2.0 * sigma * eps / (1.0 - eps) ** 2 + second
+            row["c64_energy_bound_probabilistic"] = 72.0 * u * sigma * math.sqrt(runs) + second
         out[f"{n}q"] = row
         log(f"small configs: {n} qubits done")
     return out
