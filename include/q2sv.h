@@ -70,6 +70,7 @@ extern "C" {
 
 typedef struct sv_state sv_state;             /* opaque: one state vector      */
 typedef struct sv_hamiltonian sv_hamiltonian; /* opaque: resident Pauli sum    */
+typedef struct sv_rotations sv_rotations;     /* opaque: resident rotation list */
 typedef struct { uint64_t x, z; } sv_pauli;
 
 enum { SV_C128 = 0, SV_C64 = 1, SV_R64 = 2 };
@@ -194,6 +195,36 @@ int sv_adjoint_grad_params_h(sv_state *psi, sv_state *lam, const sv_hamiltonian 
                              const sv_pauli *rp, const double *phi, int64_t n_rot,
                              const int32_t *param_of_rot, const double *dphi_dtheta,
                              int64_t n_params, double *energy_dev, double *grad_theta_dev);
+
+/* Resident rotation lists (Eq. 10-11: U(theta) = prod_k exp(-i phi_k P_k / 2)
+ * with phi_k = dphi_dtheta[k] theta[param_of_rot[k]]; Algorithm 1 for the
+ * gradient): split into runs once; the pass schedule of the last call per
+ * amplitude type and direction is kept and reused while the run tables it was
+ * made from keep their kinds and record counts (as for every nonzero theta_p
+ * of a UCC list), so such a call only writes the angle tables of its theta.
+ *   sv_rotations_create  p, param_of_rot, dphi_dtheta: host arrays of n_rot
+ *                        >= 0 entries, copied before return; every (x | z) <
+ *                        2^n_qubits, 0 <= param_of_rot[k] < n_params, every
+ *                        dphi finite.  No device work.
+ *   sv_rotations_free    releases the handle (host memory only).
+ *   sv_apply_rotations_h as sv_apply_pauli_rotations with phi_k =
+ *                        dphi_dtheta[k] theta[param_of_rot[k]]; theta: host,
+ *                        n_params entries, finite.
+ *   sv_adjoint_grad_params_hr  as sv_adjoint_grad_params_h with the resident
+ *                        list and theta in place of (rp, phi, param_of_rot,
+ *                        dphi_dtheta, n_params).
+ * A call's plan equals the one the non-resident calls make from the same
+ * (p, phi, param_of_rot, dphi_dtheta), so results agree with them bit for bit.
+ * One handle may serve several states and threads (its kept schedules are
+ * read and replaced under a lock).  Errors as the calls they mirror; SV_EINVAL when the list's
+ * n differs from the state's, or a real state meets a string with an even
+ * number of Y factors. */
+int sv_rotations_create(int n_qubits, const sv_pauli *p, int64_t n_rot, const int32_t *param_of_rot,
+                        const double *dphi_dtheta, int64_t n_params, sv_rotations **out);
+int sv_rotations_free(sv_rotations *r);
+int sv_apply_rotations_h(sv_state *s, sv_rotations *r, const double *theta);
+int sv_adjoint_grad_params_hr(sv_state *psi, sv_state *lam, const sv_hamiltonian *h, sv_rotations *r,
+                              const double *theta, double *energy_dev, double *grad_theta_dev);
 
 /* For callers that cannot allocate device memory during the call (code under
  * HIP graph capture, tight serving loops, harnesses that forbid hipMalloc):

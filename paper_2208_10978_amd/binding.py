@@ -65,6 +65,10 @@ def lib():
             "sv_expect_hamiltonian": [_vp, _vp, _vp],
             "sv_expect_hamiltonian_noalloc": [_vp, _vp, _vp],
             "sv_adjoint_grad_params_h": [_vp, _vp, _vp, _vp, _vp, _i64, _vp, _vp, _i64, _vp, _vp],
+            "sv_rotations_create": [_c.c_int, _vp, _i64, _vp, _vp, _i64, _c.POINTER(_vp)],
+            "sv_rotations_free": [_vp],
+            "sv_apply_rotations_h": [_vp, _vp, _vp],
+            "sv_adjoint_grad_params_hr": [_vp, _vp, _vp, _vp, _vp, _vp, _vp],
             "sv_adjoint_grad_params_deflated": [_vp, _vp, _vp, _vp, _vp, ctypes.c_int, _vp, _vp, _i64, _vp, _vp,
                                                 _i64, _vp, _vp, _vp],
             "sv_overlap": [_vp, _vp, _vp],
@@ -89,6 +93,7 @@ EXPORTED = (
     "sv_apply_pauli_rotations",
     "sv_expect_pauli_sum", "sv_adjoint_grad", "sv_adjoint_grad_params", "sv_hamiltonian_create",
     "sv_hamiltonian_free", "sv_expect_hamiltonian", "sv_expect_hamiltonian_noalloc", "sv_adjoint_grad_params_h",
+    "sv_rotations_create", "sv_rotations_free", "sv_apply_rotations_h", "sv_adjoint_grad_params_hr",
     "sv_adjoint_grad_params_deflated", "sv_overlap", "sv_normalize",
     "sv_gather_amplitudes", "sv_profile_begin", "sv_profile_end", "sv_last_error",
 )
@@ -234,6 +239,32 @@ def sv_adjoint_grad_params_h(psi, lam, h, rx, rz, phi, param_of_rot, dphi_dtheta
     d = _f64(dphi_dtheta)
     _check(lib().sv_adjoint_grad_params_h(psi, lam, h, _ptr(rp), _ptr(ph), len(ph), _ptr(pr), _ptr(d),
                                           int(n_params), _dev(energy_dev), _dev(grad_theta_dev)))
+
+
+def sv_rotations_create(n_qubits: int, rx, rz, param_of_rot, dphi_dtheta, n_params: int):
+    rp = _paulis(rx, rz)
+    pr = np.ascontiguousarray(param_of_rot, dtype=np.int32)
+    d = _f64(dphi_dtheta)
+    if not (len(pr) == len(d) == len(rp)):
+        raise ValueError("rotation arrays differ in length")
+    r = _vp()
+    _check(lib().sv_rotations_create(int(n_qubits), _ptr(rp), len(rp), _ptr(pr), _ptr(d), int(n_params),
+                                     ctypes.byref(r)))
+    return r
+
+
+def sv_rotations_free(r):
+    _check(lib().sv_rotations_free(r))
+
+
+def sv_apply_rotations_h(s, r, theta):
+    th = _f64(theta)
+    _check(lib().sv_apply_rotations_h(s, r, _ptr(th)))
+
+
+def sv_adjoint_grad_params_hr(psi, lam, h, r, theta, energy_dev, grad_theta_dev):
+    th = _f64(theta)
+    _check(lib().sv_adjoint_grad_params_hr(psi, lam, h, r, _ptr(th), _dev(energy_dev), _dev(grad_theta_dev)))
 
 
 def sv_adjoint_grad_params_deflated(psi, lam, h, proj, alpha, rx, rz, phi, param_of_rot, dphi_dtheta, n_params,

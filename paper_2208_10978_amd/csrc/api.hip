@@ -9,6 +9,7 @@
 #include <cstring>
 #include <memory>
 #include <mutex>
+#include <new>
 #include <string>
 #include <vector>
 
@@ -873,10 +874,12 @@ static int deflate_impl(sv_state* psi, sv_state* lam, const ProjArgs& pa, double
   return SV_OK;
 }
 
+// given (optional): the reverse plan of a resident rotation list, made by the
+// caller with this call's angles (parameter mode)
 static int adjoint_impl(sv_state* psi, sv_state* lam, sv_hamiltonian* h, const sv_pauli* rp, const double* phi,
                         int64_t n_rot, const int32_t* param, const double* dphi, int64_t n_params,
                         double* energy_dev, double* grad_dev, const ProjArgs* defl = nullptr,
-                        double* ovl_dev = nullptr) {
+                        double* ovl_dev = nullptr, RotPlan* given = nullptr) {
   int rc = validate_real_rotations(psi, rp, n_rot);
   if (rc) return rc;
   rc = validate_real_sum(psi, h);
@@ -888,8 +891,9 @@ static int adjoint_impl(sv_state* psi, sv_state* lam, sv_hamiltonian* h, const s
     if (rc) return rc;
   }
   const int grad_mode = param ? 1 : 2;
-  RotPlan pl;
-  plan_rotations(psi, rp, phi, dphi, param, n_rot, true, grad_mode, pl);
+  RotPlan own;
+  if (!given) plan_rotations(psi, rp, phi, dphi, param, n_rot, true, grad_mode, own);
+  RotPlan& pl = given ? *given : own;
   // every run a real rotation (omega0 odd, no diagonal run): with psi and lam
   // real on entry they stay real, and the tile passes may take the real walk
   // once a device count of their nonzero imaginary parts reads zero
@@ -949,6 +953,63 @@ static int adjoint_impl(sv_state* psi, sv_state* lam, sv_hamiltonian* h, const s
   HIP_TRY(launch_gather_slots(slot_val, dptr<uint32_t>(lam->tables, o_off), dptr<uint32_t>(lam->tables, o_idx),
                               dptr<double>(lam->tables, o_w), int(n_params), grad_dev, psi->stream));
   return SV_OK;
+}
+
+// ---------------------------------------------------------------------------
+// resident rotation lists (sv_rotations)
+// ---------------------------------------------------------------------------
+struct sv_rotations {
+  int n = 0;
+  std::vector<PauliIn> p;             // the list, in application order
+  std::vector<int32_t> param;         // parameter of each rotation
+  std::vector<double> dphi;           // d phi_k / d theta_param
+  int64_t n_params = 0;
+  std::vector<Run> runs[2];           // split once: [0] forward, [1] per parameter (gradient)
+  std::vector<Pass> passes[3][2];     // [dtype][reverse]: the last schedule made
+  std::vector<uint32_t> key[3][2];    // what that schedule was made from (run_key)
+  std::mutex mu;
+};
+
+// The schedule reads a run's tables only through their mode and record count
+// (pass record budget, line fraction); equal keys give the same schedule.
+static std::vector<uint32_t> run_key(const std::vector<RunData>& data) {
+  std::vector<uint32_t> k(data.size());
+  for (size_t i = 0; i < data.size(); ++i) k[i] = uint32_t(data[i].mode) << 24 | uint32_t(data[i].recs.size());
+  return k;
+}
+
+// A call's plan from a resident list: the runs split once, this call's
+// angles phi_k = dphi_k theta[param_k] in the run tables, and the schedule of
+// the last call reused while the tables it depends on (run_key) are unchanged;
+// otherwise it is made again from this call's tables.  The plan is the one the
+// call would make for itself from (p, phi, param, dphi).
+static void resident_plan(sv_rotations* r, const sv_state* s, const double* theta, bool reverse, RotPlan& pl) {
+  const int dtype = s->dtype;
+  std::vector<double> phi(r->p.size());
+  for (size_t k = 0; k < phi.size(); ++k) phi[k] = r->dphi[k] * theta[r->param[k]];
+  pl.runs = r->runs[reverse];
+  pl.data.resize(pl.runs.size());
+  for (size_t i = 0; i < pl.runs.size(); ++i)
+    pl.data[i] = build_run_data(pl.runs[i], r->p.data(), phi.data(), reverse ? r->dphi.data() : nullptr,
+                                reverse ? 1 : 0);
+  std::vector<uint32_t> key = run_key(pl.data);
+  std::lock_guard<std::mutex> lk(r->mu);
+  if (r->key[dtype][reverse] != key || r->passes[dtype][reverse].empty()) {
+    const int b = reverse ? tile_bits_two(dtype) : tile_bits_fwd(dtype);
+    const int c = std::min(row_bits(dtype), s->n);
+    r->passes[dtype][reverse] = schedule(pl.runs, pl.data, r->p.data(), s->n, b, c, reverse,
+                                         reverse ? kMaxPassSlots : 0, reverse ? 1 : 0, kMaxPassRuns, kMaxPassRecs);
+    r->key[dtype][reverse] = std::move(key);
+  }
+  pl.passes = r->passes[dtype][reverse];
+}
+
+static int check_resident(const sv_state* s, const sv_rotations* r, const double* theta) {
+  if (!r) return fail(SV_EINVAL, "NULL rotation list");
+  if (r->n != s->n) return fail(SV_EINVAL, "rotation list and state differ in n");
+  int rc = validate_finite(theta, r->n_params, "theta");
+  if (rc) return rc;
+  return validate_real_rotations(s, reinterpret_cast<const sv_pauli*>(r->p.data()), int64_t(r->p.size()));
 }
 
 // ---------------------------------------------------------------------------
@@ -1251,6 +1312,64 @@ int sv_adjoint_grad_params_h(sv_state* psi, sv_state* lam, const sv_hamiltonian*
   if (rc) return rc;
   return adjoint_impl(psi, lam, const_cast<sv_hamiltonian*>(hc), rp, phi, n_rot, param, dphi, n_params,
                       energy_dev, grad_theta_dev);
+}
+
+int sv_rotations_create(int n_qubits, const sv_pauli* p, int64_t n_rot, const int32_t* param_of_rot,
+                        const double* dphi_dtheta, int64_t n_params, sv_rotations** out) {
+  if (!out) return fail(SV_EINVAL, "out is NULL");
+  *out = nullptr;
+  if (n_qubits < 1 || n_qubits > SV_MAX_QUBITS) return fail(SV_EINVAL, "n_qubits out of range");
+  int rc = validate_paulis(p, n_rot, n_qubits, "rotation");
+  if (rc) return rc;
+  rc = check_params(param_of_rot, dphi_dtheta, n_rot, n_params);
+  if (rc) return rc;
+  sv_rotations* r = new (std::nothrow) sv_rotations();
+  if (!r) return fail(SV_ENOMEM, "rotation list handle");
+  r->n = n_qubits;
+  r->n_params = n_params;
+  const PauliIn* pin = reinterpret_cast<const PauliIn*>(p);
+  r->p.assign(pin, pin + n_rot);
+  r->param.assign(param_of_rot, param_of_rot + n_rot);
+  r->dphi.assign(dphi_dtheta, dphi_dtheta + n_rot);
+  r->runs[0] = split_runs(r->p.data(), n_rot, nullptr);
+  r->runs[1] = split_runs(r->p.data(), n_rot, r->param.data());
+  *out = r;
+  return SV_OK;
+}
+
+int sv_rotations_free(sv_rotations* r) {
+  delete r;
+  return SV_OK;
+}
+
+int sv_apply_rotations_h(sv_state* s, sv_rotations* r, const double* theta) {
+  if (!s) return fail(SV_EINVAL, "NULL state");
+  Call call(s);
+  if (call.rc) return call.rc;
+  int rc = check_resident(s, r, theta);
+  if (rc) return rc;
+  if (r->p.empty()) return SV_OK;
+  RotPlan pl;
+  resident_plan(r, s, theta, false, pl);
+  return launch_rotations(s, nullptr, pl, false, 0, nullptr);
+}
+
+int sv_adjoint_grad_params_hr(sv_state* psi, sv_state* lam, const sv_hamiltonian* hc, sv_rotations* r,
+                              const double* theta, double* energy_dev, double* grad_theta_dev) {
+  int rc = check_pair(psi, lam);
+  if (rc) return rc;
+  Call call(psi, lam);
+  if (call.rc) return call.rc;
+  if (!hc) return fail(SV_EINVAL, "NULL Pauli sum");
+  if (hc->n != psi->n) return fail(SV_EINVAL, "Pauli sum and state differ in n");
+  rc = check_resident(psi, r, theta);
+  if (rc) return rc;
+  if (!energy_dev || (r->n_params > 0 && !grad_theta_dev)) return fail(SV_EINVAL, "NULL output");
+  RotPlan pl;
+  resident_plan(r, psi, theta, true, pl);
+  return adjoint_impl(psi, lam, const_cast<sv_hamiltonian*>(hc), reinterpret_cast<const sv_pauli*>(r->p.data()),
+                      nullptr, int64_t(r->p.size()), r->param.data(), r->dphi.data(), r->n_params, energy_dev,
+                      grad_theta_dev, nullptr, nullptr, &pl);
 }
 
 int sv_adjoint_grad_params_deflated(sv_state* psi, sv_state* lam, const sv_hamiltonian* hc,

@@ -4,9 +4,10 @@
                   tensor on the GPU bound to an sv_state
 ``Hamiltonian``   a Pauli sum grouped and uploaded once (sv_hamiltonian)
 ``UCCSDEvaluator`` energy and energy+gradient of the Trotterised UCCSD state
-                  (Eq. 10-11) for a fixed Hamiltonian: HF preparation, the
-                  rotation sweep, the grouped expectation or lambda = H psi
-                  with the reverse sweep (Algorithm 1)
+                  (Eq. 10-11) for a fixed Hamiltonian and rotation list, both
+                  resident in the library: HF preparation, the rotation sweep,
+                  the grouped expectation or lambda = H psi with the reverse
+                  sweep (Algorithm 1)
 ``UCCEnergy``     torch.autograd.Function whose backward returns dE/dtheta
                   computed by the reverse sweep
 """
@@ -132,18 +133,20 @@ class UCCSDEvaluator:
         self.real_circuit = bool(np.all(np.bitwise_count(x & z) % 2 == 1))
         B.sv_set_real_hint(self.psi.handle, self.real_circuit)
         B.sv_set_deterministic(self.psi.handle, deterministic)
+        # the rotation list resident in the library: split and scheduled once
+        self.rh = B.sv_rotations_create(self.n, rot.x, rot.z, rot.param, rot.dphi_dtheta, rot.n_params)
         self.renormalize = (dtype == "c64") if renormalize is None else renormalize
         dev = self.psi.amps.device
         self.energy_buf = torch.empty(2, dtype=torch.float64, device=dev)
         self.grad_buf = torch.empty(rot.n_params, dtype=torch.float64, device=dev)
 
     def forward_state(self, theta):
-        phi = self.rot.angles(np.asarray(theta, dtype=np.float64))
+        th = np.asarray(theta, dtype=np.float64)
         self.psi.prepare_hf(self.hf)
-        self.psi.apply_rotations(self.rot.x, self.rot.z, phi)
+        B.sv_apply_rotations_h(self.psi.handle, self.rh, th)
         if self.renormalize:
             self.psi.normalize()
-        return phi
+        return self.rot.angles(th)
 
     def energy(self, theta) -> torch.Tensor:
         """Device tensor [E, <psi|psi>] (E is the Rayleigh quotient)."""
@@ -151,10 +154,10 @@ class UCCSDEvaluator:
         return self.psi.expect(self.h, self.energy_buf)
 
     def energy_and_grad(self, theta):
-        phi = self.forward_state(theta)
-        B.sv_adjoint_grad_params_h(self.psi.handle, self.lam.handle, self.h.handle, self.rot.x, self.rot.z, phi,
-                                   self.rot.param, self.rot.dphi_dtheta, self.rot.n_params, self.energy_buf,
-                                   self.grad_buf)
+        th = np.asarray(theta, dtype=np.float64)
+        self.forward_state(th)
+        B.sv_adjoint_grad_params_hr(self.psi.handle, self.lam.handle, self.h.handle, self.rh, th, self.energy_buf,
+                                    self.grad_buf)
         return self.energy_buf, self.grad_buf
 
     def pool_gradients(self, theta, pool: RotationList) -> torch.Tensor:
@@ -190,8 +193,13 @@ class UCCSDEvaluator:
         return self.psi.clone()
 
     def free_states(self):
+        """Release the states and the resident rotation list (a shared
+        Hamiltonian stays)."""
         self.psi.free()
         self.lam.free()
+        if self.rh is not None:
+            B.sv_rotations_free(self.rh)
+            self.rh = None
 
     def free(self):
         self.free_states()

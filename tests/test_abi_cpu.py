@@ -41,6 +41,24 @@ def test_argument_validation_needs_no_device():
     assert lib.sv_hamiltonian_create(0, None, None, 0, ctypes.byref(h)) == binding.SV_EINVAL
 
 
+@pytest.mark.skipif(not os.path.exists(binding.LIB_PATH), reason="library not built")
+def test_resident_rotation_list_validation_needs_no_device():
+    """sv_rotations_create copies and splits the list on the host: bad input is
+    refused with a message, a good list gives a handle that frees cleanly."""
+    import numpy as np
+    x = np.array([0b0011, 0b1100], np.uint64)
+    z = np.array([0b0001, 0b0100], np.uint64)
+    with pytest.raises(binding.Q2svError, match="param_of_rot"):
+        binding.sv_rotations_create(4, x, z, [0, 2], [0.5, -0.5], 2)          # parameter index out of range
+    with pytest.raises(binding.Q2svError, match="qubit"):
+        binding.sv_rotations_create(3, x, z, [0, 1], [0.5, -0.5], 2)          # acts on qubit 3 of a 3-qubit state
+    with pytest.raises(binding.Q2svError, match="dphi"):
+        binding.sv_rotations_create(4, x, z, [0, 1], [0.5, float("nan")], 2)
+    r = binding.sv_rotations_create(4, x, z, [0, 1], [0.5, -0.5], 2)
+    assert r.value
+    binding.sv_rotations_free(r)
+
+
 def _fresh(code: str) -> str:
     """Run code in a new interpreter: a device's failure mark lasts for the
     process, so it must not leak into the other tests."""
