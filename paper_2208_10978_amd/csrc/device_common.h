@@ -113,6 +113,38 @@ __device__ __forceinline__ void lds_add(double* p, double v) {
   __hip_atomic_fetch_add(p, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
 }
 
+// ---------------------------------------------------------------------------
+// order-independent sums in fixed point
+// ---------------------------------------------------------------------------
+// For |x| < 2^51, t = x + 1.5 * 2^52 lies in [2^52, 2^53), where consecutive
+// doubles are 1 apart: forming t rounds x to an integer q, and t's bit
+// pattern minus that of 1.5 * 2^52 (whose low word is zero) is q in two's
+// complement.  Integer adds are associative, so a sum of such q comes out
+// the same in any order of arrival.
+constexpr double kFxMagic = 6755399441055744.0;  // 1.5 * 2^52
+constexpr int kFxNone = -4000;                   // exponent of a zero tile
+
+__device__ __forceinline__ unsigned long long fx_bits(double t) {
+  const uint32_t hi = uint32_t(__double2hiint(t)) - 0x43380000u;
+  return (static_cast<unsigned long long>(hi) << 32) | uint32_t(__double2loint(t));
+}
+
+// Integer add into LDS that returns nothing; t = x * scale + kFxMagic.
+__device__ __forceinline__ void lds_add_fx(unsigned long long* p, double t) {
+  __hip_atomic_fetch_add(p, fx_bits(t), __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
+}
+
+// e with 2^(e-1) <= a < 2^e for a > 0; kFxNone for a = 0
+__device__ __forceinline__ int fx_exp(double a) {
+  return a > 0.0 ? __builtin_amdgcn_frexp_exp(a) : kFxNone;
+}
+
+__device__ __forceinline__ int wave_max_i32(int v) {
+#pragma unroll
+  for (int o = 32; o > 0; o >>= 1) v = max(v, __shfl_xor(v, o, 64));
+  return v;
+}
+
 // One DPP data movement of a double (both halves); lanes the pattern does
 // not feed, or rows row_mask leaves out, read 0.
 template <int CTRL, int ROW_MASK>

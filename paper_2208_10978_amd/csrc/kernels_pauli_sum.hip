@@ -298,12 +298,16 @@ __device__ __forceinline__ T lds_at(const T* tp, uint32_t off) {
 // the out-of-frame bits of w_k), then the butterfly over v, since
 // G(v) = sum_cls (-1)^{|v & cls|} A_cls.  G is then the same for every chunk
 // but for the chunk's w0 sign.  The chunk walk reads both ends of each pair
-// and adds lam[m] += G psi[m'] and lam[m'] += conj(G) psi[m] with LDS atomics
-// (other wavefronts may update the same outputs).  REAL: psi, T and lambda
-// are real; only real parts are read and added.
+// and adds lam[m] += G psi[m'] and lam[m'] += conj(G) psi[m] into the tile's
+// fixed-point accumulators (G pre-scaled by the tile's scale sc, each term
+// rounded to an integer by the fused add of kFxMagic) with LDS integer atomic
+// adds: other wavefronts may update the same outputs, in any order, and the
+// sums do not depend on it.  REAL: psi, T and lambda are real; only real
+// parts are read and added.
 template <typename TT, bool REAL, int NR, bool MULTI, bool SIGNED>
 __device__ __forceinline__ void x_lambda_records(const XView& xv, const XBatch* bp, const XItem& it, uint64_t base,
-                                                 const TT* tp, double* tlr, double* tli, uint32_t dl, uint32_t sdl) {
+                                                 const TT* tp, unsigned long long* alr, unsigned long long* ali,
+                                                 double sc, uint32_t dl, uint32_t sdl) {
   constexpr int NV = 1 << NR;
   constexpr int NA = MULTI ? NV : 1;
   uint32_t vs[NV];
@@ -344,6 +348,11 @@ __device__ __forceinline__ void x_lambda_records(const XView& xv, const XBatch* 
             gi[v | h] = i0 - i1;
           }
     }
+#pragma unroll
+    for (int v = 0; v < NA; ++v) {
+      gr[v] *= sc;
+      gi[v] *= sc;
+    }
     const uint32_t lb = sdl ^ rc.slot;
     uint32_t cw = bp->cword[c0];
     for (uint32_t c = c0; c < c1; ++c) {
@@ -365,16 +374,16 @@ __device__ __forceinline__ void x_lambda_records(const XView& xv, const XBatch* 
         double g_r = gr[MULTI ? v : 0];
         if constexpr (SIGNED) g_r = sign_xor1(g_r, sg);
         if constexpr (REAL) {
-          lds_add(&tlr[om], g_r * (double)pp[v].x);  // lam[m] += G psi[m']
-          lds_add(&tlr[ob[v]], g_r * (double)pm[v].x);  // lam[m'] += G psi[m]
+          lds_add_fx(&alr[om], fma(g_r, (double)pp[v].x, kFxMagic));     // lam[m] += G psi[m']
+          lds_add_fx(&alr[ob[v]], fma(g_r, (double)pm[v].x, kFxMagic));  // lam[m'] += G psi[m]
         } else {
           double g_i = gi[MULTI ? v : 0];
           if constexpr (SIGNED) g_i = sign_xor1(g_i, sg);
           const double ppx = (double)pp[v].x, ppy = (double)pp[v].y, pmx = (double)pm[v].x, pmy = (double)pm[v].y;
-          lds_add(&tlr[om], g_r * ppx - g_i * ppy);  // lam[m] += G psi[m']
-          lds_add(&tli[om], g_r * ppy + g_i * ppx);
-          lds_add(&tlr[ob[v]], g_r * pmx + g_i * pmy);  // lam[m'] += conj(G) psi[m]
-          lds_add(&tli[ob[v]], g_r * pmy - g_i * pmx);
+          lds_add_fx(&alr[om], fma(g_r, ppx, fma(-g_i, ppy, kFxMagic)));  // lam[m] += G psi[m']
+          lds_add_fx(&ali[om], fma(g_r, ppy, fma(g_i, ppx, kFxMagic)));
+          lds_add_fx(&alr[ob[v]], fma(g_r, pmx, fma(g_i, pmy, kFxMagic)));  // lam[m'] += conj(G) psi[m]
+          lds_add_fx(&ali[ob[v]], fma(g_r, pmy, fma(-g_i, pmx, kFxMagic)));
         }
       }
       cw = cn;
@@ -384,14 +393,16 @@ __device__ __forceinline__ void x_lambda_records(const XView& xv, const XBatch* 
 
 template <typename TT, bool REAL, int NR, bool MULTI>
 __device__ __forceinline__ void x_lambda_records_s(const XView& xv, const XBatch* bp, const XItem& it, uint64_t base,
-                                                   const TT* tp, double* tlr, double* tli, uint32_t dl, uint32_t sdl) {
-  if (bp->signed_chunks) x_lambda_records<TT, REAL, NR, MULTI, true>(xv, bp, it, base, tp, tlr, tli, dl, sdl);
-  else x_lambda_records<TT, REAL, NR, MULTI, false>(xv, bp, it, base, tp, tlr, tli, dl, sdl);
+                                                   const TT* tp, unsigned long long* alr, unsigned long long* ali,
+                                                   double sc, uint32_t dl, uint32_t sdl) {
+  if (bp->signed_chunks) x_lambda_records<TT, REAL, NR, MULTI, true>(xv, bp, it, base, tp, alr, ali, sc, dl, sdl);
+  else x_lambda_records<TT, REAL, NR, MULTI, false>(xv, bp, it, base, tp, alr, ali, sc, dl, sdl);
 }
 
 template <typename TT, bool REAL>
 __device__ __forceinline__ void x_lambda_item(const XView& xv, const XItem& it, uint64_t base, const TT* tp,
-                                              double* tlr, double* tli, uint32_t lane) {
+                                              unsigned long long* alr, unsigned long long* ali, double sc,
+                                              uint32_t lane) {
   const XBatch* bp = xv.batches + it.batch;
   const uint32_t lp = bp->lane_pack, nl = bp->n_lane;
   if ((lane >> nl) != 0u) return;  // lanes past a small frame's free bits
@@ -402,11 +413,11 @@ __device__ __forceinline__ void x_lambda_item(const XView& xv, const XItem& it, 
   const uint32_t sdl = lds_swz(dl);
   static_assert(kXRegBits == 2, "one case per register-bit count");
   switch (bp->n_reg + (bp->n_cls > 1 ? 4u : 0u)) {
-    case 0: x_lambda_records_s<TT, REAL, 0, false>(xv, bp, it, base, tp, tlr, tli, dl, sdl); break;
-    case 1: x_lambda_records_s<TT, REAL, 1, false>(xv, bp, it, base, tp, tlr, tli, dl, sdl); break;
-    case 2: x_lambda_records_s<TT, REAL, 2, false>(xv, bp, it, base, tp, tlr, tli, dl, sdl); break;
-    case 5: x_lambda_records_s<TT, REAL, 1, true>(xv, bp, it, base, tp, tlr, tli, dl, sdl); break;
-    case 6: x_lambda_records_s<TT, REAL, 2, true>(xv, bp, it, base, tp, tlr, tli, dl, sdl); break;
+    case 0: x_lambda_records_s<TT, REAL, 0, false>(xv, bp, it, base, tp, alr, ali, sc, dl, sdl); break;
+    case 1: x_lambda_records_s<TT, REAL, 1, false>(xv, bp, it, base, tp, alr, ali, sc, dl, sdl); break;
+    case 2: x_lambda_records_s<TT, REAL, 2, false>(xv, bp, it, base, tp, alr, ali, sc, dl, sdl); break;
+    case 5: x_lambda_records_s<TT, REAL, 1, true>(xv, bp, it, base, tp, alr, ali, sc, dl, sdl); break;
+    case 6: x_lambda_records_s<TT, REAL, 2, true>(xv, bp, it, base, tp, alr, ali, sc, dl, sdl); break;
     default: break;  // several classes need a register bit: not planned
   }
 }
@@ -422,11 +433,18 @@ template <> struct Real<RealSlot> { using type = double; };
 // values).  REAL: psi and every coefficient are real, so only real parts are
 // read and accumulated and tli is not used; TT = RealSlot keeps only the
 // real parts of psi in the tile.
+//
+// The fast build sums in fixed point: tlr and tli then hold 64-bit integer
+// accumulators, cleared per tile, while the tile's starting values (diag psi
+// or the lambda of earlier passes) wait in registers; the result is start +
+// accumulator * 2^-s.  The scale 2^s of a tile comes from the blob's
+// fx_shift and the exponent of the tile's largest |psi| (sexp: one entry per
+// wavefront), so that no term reaches 2^50 and no sum 2^62.
 template <typename T, int B, int NT, int MODE, bool FULL, bool REAL, bool DET, typename TT = T>
 __device__ __forceinline__ void lambda_tiles(const T* __restrict__ psi, T* __restrict__ lam,
                                              const double* __restrict__ diag, const FrameDesc& fr,
                                              const uint4* __restrict__ blob, uint64_t n_tb, TT* tp, double* tlr,
-                                             double* tli, double2* fB) {
+                                             double* tli, double2* fB, int* sexp) {
   static_assert(REAL || std::is_same<TT, T>::value, "a real-part tile needs the real build");
   using R = typename Real<T>::type;
   constexpr bool kRealTile = std::is_same<TT, RealSlot>::value;
@@ -435,16 +453,41 @@ __device__ __forceinline__ void lambda_tiles(const T* __restrict__ psi, T* __res
   const int lane = threadIdx.x & 63;
   const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
 
+  unsigned long long* const alr = reinterpret_cast<unsigned long long*>(tlr);
+  unsigned long long* const ali = reinterpret_cast<unsigned long long*>(tli);
+
   // fast build: every wavefront on the whole tile, LDS atomic adds; the
   // tables are projected-sum batches with per-wavefront work lists
-  auto apply_groups_fast = [&](uint64_t base) {
+  auto apply_groups_fast = [&](uint64_t base, double sc) {
     const XView xv(blob);
     const bool lists = xv.hdr->n_waves == uint32_t(NW);
     const uint32_t i0 = lists ? xv.start[wave] : uint32_t(wave);
     const uint32_t i1 = lists ? xv.start[wave + 1] : xv.hdr->n_items;
     const uint32_t step = lists ? 1u : uint32_t(NW);
-    for (uint32_t i = i0; i < i1; i += step) x_lambda_item<TT, REAL>(xv, xv.items[i], base, tp, tlr, tli, uint32_t(lane));
+    for (uint32_t i = i0; i < i1; i += step)
+      x_lambda_item<TT, REAL>(xv, xv.items[i], base, tp, alr, ali, sc, uint32_t(lane));
     __syncthreads();
+  };
+  // the fixed-point exponent s of the tile in place (after its sexp entries
+  // are written and a barrier has passed)
+  auto tile_shift = [&]() -> int {
+    int e = sexp[0];
+#pragma unroll
+    for (int w = 1; w < NW; ++w) e = max(e, sexp[w]);
+    const int sh = reinterpret_cast<const XHdr*>(blob)->fx_shift - e;
+    return __builtin_amdgcn_readfirstlane(min(max(sh, -1000), 1000));
+  };
+  // this wavefront's part of a tile's largest |psi|, from the staged values
+  auto note_exp = [&](const Stage<T, PER>& st, int n_valid) {
+    int e = kFxNone;
+#pragma unroll
+    for (int i = 0; i < PER; ++i)
+      if (i < n_valid) {
+        const double a = REAL ? fabs((double)st.re[i]) : fabs((double)st.re[i]) + fabs((double)st.im[i]);
+        e = max(e, fx_exp(a));
+      }
+    e = wave_max_i32(e);
+    if (lane == 0) sexp[wave] = e;
   };
 
   // reproducible build: region-owned segments, plain loads and stores
@@ -516,14 +559,15 @@ __device__ __forceinline__ void lambda_tiles(const T* __restrict__ psi, T* __res
     }
     if (n_segs == 0) __syncthreads();
   };
-  auto apply_groups = [&](uint64_t base) {
+  auto apply_groups = [&](uint64_t base, int sh) {
     if constexpr (DET) apply_groups_owned(base);
-    else apply_groups_fast(base);
+    else apply_groups_fast(base, __builtin_ldexp(1.0, sh));
   };
 
   Stage<T, PER> rp;
   Stage<T, PER> rl;
   double rd[PER];
+  double ir[PER], ii[PER];  // fast build: the tile's starting values
   uint64_t tb = blockIdx.x;
   if constexpr (FULL) {
     // next loads before the groups; this tile's lambda leaves only after the
@@ -554,9 +598,19 @@ __device__ __forceinline__ void lambda_tiles(const T* __restrict__ psi, T* __res
 #pragma unroll
       for (int i = 0; i < PER; ++i) {
         const uint32_t sl = lds_swz(threadIdx.x + uint32_t(i) * NT);
-        tlr[sl] = MODE == 1 ? rd[i] * (double)rp.re[i] : (double)rl.re[i];
-        if (!REAL) tli[sl] = MODE == 1 ? rd[i] * (double)rp.im[i] : (double)rl.im[i];
+        const double vr = MODE == 1 ? rd[i] * (double)rp.re[i] : (double)rl.re[i];
+        const double vi = REAL ? 0.0 : MODE == 1 ? rd[i] * (double)rp.im[i] : (double)rl.im[i];
+        if constexpr (DET) {
+          tlr[sl] = vr;
+          if (!REAL) tli[sl] = vi;
+        } else {
+          ir[i] = vr;
+          ii[i] = vi;
+          alr[sl] = 0ull;
+          if (!REAL) ali[sl] = 0ull;
+        }
       }
+      if constexpr (!DET) note_exp(rp, PER);
     };
     if (tb < n_tb) {
       fetch(frame_base(fr, tb));
@@ -566,14 +620,21 @@ __device__ __forceinline__ void lambda_tiles(const T* __restrict__ psi, T* __res
     for (; tb < n_tb; tb += gridDim.x) {
       const uint64_t base = frame_base(fr, tb);
       const uint64_t nx = tb + gridDim.x;
+      const int sh = DET ? 0 : tile_shift();
       if (nx < n_tb) fetch(frame_base(fr, nx));
-      apply_groups(base);
+      apply_groups(base, sh);
       Stage<T, PER> out;
+      const double unit = __builtin_ldexp(1.0, -sh);
 #pragma unroll
       for (int i = 0; i < PER; ++i) {
         const uint32_t sl = lds_swz(threadIdx.x + uint32_t(i) * NT);
-        out.re[i] = R(tlr[sl]);
-        out.im[i] = REAL ? R(0) : R(tli[sl]);
+        if constexpr (DET) {
+          out.re[i] = R(tlr[sl]);
+          out.im[i] = REAL ? R(0) : R(tli[sl]);
+        } else {
+          out.re[i] = R(fma(double(static_cast<long long>(alr[sl])), unit, ir[i]));
+          out.im[i] = REAL ? R(0) : R(fma(double(static_cast<long long>(ali[sl])), unit, ii[i]));
+        }
       }
       if (nx < n_tb) put();
       tile_send<T, PER, NT>(lam, ta, fr, base, out);
@@ -619,20 +680,42 @@ __device__ __forceinline__ void lambda_tiles(const T* __restrict__ psi, T* __res
         const uint32_t l = threadIdx.x + uint32_t(i) * NT;
         if (l < nloc) {
           const uint32_t sl = lds_swz(l);
-          tlr[sl] = MODE == 1 ? rd[i] * (double)rp.re[i] : (double)rl.re[i];
-          if (!REAL) tli[sl] = MODE == 1 ? rd[i] * (double)rp.im[i] : (double)rl.im[i];
+          const double vr = MODE == 1 ? rd[i] * (double)rp.re[i] : (double)rl.re[i];
+          const double vi = REAL ? 0.0 : MODE == 1 ? rd[i] * (double)rp.im[i] : (double)rl.im[i];
+          if constexpr (DET) {
+            tlr[sl] = vr;
+            if (!REAL) tli[sl] = vi;
+          } else {
+            ir[i] = vr;
+            ii[i] = vi;
+            alr[sl] = 0ull;
+            if (!REAL) ali[sl] = 0ull;
+          }
         }
       }
+      if constexpr (!DET) {
+        // lanes past the tile hold no amplitude: PER slots, the last partial
+        const int n_valid = int(nloc > threadIdx.x ? (nloc - threadIdx.x + NT - 1) / NT : 0u);
+        note_exp(rp, n_valid);
+      }
       __syncthreads();
+      const int sh = DET ? 0 : tile_shift();
       const uint64_t nx = tb + gridDim.x;
       if (nx < n_tb) fetch(nx);
-      apply_groups(base);
+      apply_groups(base, sh);
+      const double unit = __builtin_ldexp(1.0, -sh);
 #pragma unroll
       for (int i = 0; i < PER; ++i) {
         const uint32_t l = threadIdx.x + uint32_t(i) * NT;
         if (l < nloc) {
           const uint32_t sl = lds_swz(l);
-          lam[base | frame_deposit(lut, l)] = cmake<T>(R(tlr[sl]), REAL ? R(0) : R(tli[sl]));
+          if constexpr (DET) {
+            lam[base | frame_deposit(lut, l)] = cmake<T>(R(tlr[sl]), REAL ? R(0) : R(tli[sl]));
+          } else {
+            const double vr = fma(double(static_cast<long long>(alr[sl])), unit, ir[i]);
+            const double vi = REAL ? 0.0 : fma(double(static_cast<long long>(ali[sl])), unit, ii[i]);
+            lam[base | frame_deposit(lut, l)] = cmake<T>(R(vr), R(vi));
+          }
         }
       }
     }
@@ -648,7 +731,8 @@ __global__ void __launch_bounds__(NT) k_tile_lambda(const T* __restrict__ psi, T
   __shared__ T tp[1 << B];
   __shared__ double tlr[1 << B], tli[1 << B];
   __shared__ double2 fB[kMaxFactored * kFactRecs];
-  lambda_tiles<T, B, NT, MODE, FULL, false, DET>(psi, lam, diag, fr, blob, n_tb, tp, tlr, tli, fB);
+  __shared__ int sexp[NT / 64];
+  lambda_tiles<T, B, NT, MODE, FULL, false, DET>(psi, lam, diag, fr, blob, n_tb, tp, tlr, tli, fB, sexp);
 }
 
 // The same for a real psi and a sum with real coefficients: lambda is real,
@@ -685,11 +769,12 @@ __global__ void __launch_bounds__(NT) k_tile_lambda_real(const T* __restrict__ p
   __shared__ RealSlot tp[1 << B];
   __shared__ double tlr[1 << B];
   __shared__ double2 fB[kMaxFactored * kFactRecs];
+  __shared__ int sexp[NT / 64];
   if (guard && *guard != 0.0) {
     lambda_poison<T, NT>(lam, fr, n_tb);
     return;
   }
-  lambda_tiles<T, B, NT, MODE, FULL, true, DET, RealSlot>(psi, lam, diag, fr, blob, n_tb, tp, tlr, nullptr, fB);
+  lambda_tiles<T, B, NT, MODE, FULL, true, DET, RealSlot>(psi, lam, diag, fr, blob, n_tb, tp, tlr, nullptr, fB, sexp);
 }
 
 // ---------------------------------------------------------------------------

@@ -950,6 +950,7 @@ void pack_expect_blob(HTiling& t, const std::vector<HGroup>& gs, const std::vect
   std::vector<XRec> xr;
   std::vector<TSub> ts;
   std::vector<double> co;
+  double g_max = 0.0, g_sum = 0.0;  // bounds on |G| (largest, and summed over groups)
   for (int gi : members) {
     const HGroup& g = gs[size_t(gi)];
     const uint32_t x_loc = uint32_t(compress(g.x, qmask));
@@ -1006,6 +1007,9 @@ void pack_expect_blob(HTiling& t, const std::vector<HGroup>& gs, const std::vect
       batches.emplace_back(take, w0);
       rest.swap(left);
     }
+    // |re| + |im| of T_k[r] summed over the group's subgroups: a bound on
+    // |G| at the pairs of record r; a slot meets one record of the group
+    std::vector<double> rec_abs(static_cast<size_t>(NR), 0.0);
     for (auto& bt : batches) {
       const std::vector<int>& mem = bt.first;
       const uint32_t w0 = bt.second;
@@ -1047,6 +1051,7 @@ void pack_expect_blob(HTiling& t, const std::vector<HGroup>& gs, const std::vect
         for (int r = 0; r < NR; ++r) {
           co.push_back(g.t_re[size_t(k) * size_t(NR) + size_t(r)]);
           co.push_back(g.t_im[size_t(k) * size_t(NR) + size_t(r)]);
+          rec_abs[size_t(r)] += std::fabs(co[co.size() - 2]) + std::fabs(co.back());
         }
       }
       for (uint32_t v = 0; v < (1u << kXRegBits); ++v) {
@@ -1060,6 +1065,10 @@ void pack_expect_blob(HTiling& t, const std::vector<HGroup>& gs, const std::vect
       const double pos = double(NR) * double(uint64_t(1) << popc(uint64_t(F))) / 64.0;
       cost.push_back(pos * 11.0 + double(NR) * (40.0 + 8.0 * double(mem.size()) + (b.n_cls > 1 ? 16.0 : 0.0)));
     }
+    double worst = 0.0;
+    for (double a : rec_abs) worst = std::max(worst, a);
+    g_max = std::max(g_max, worst);
+    g_sum += worst;
   }
   // work items: batches cut (by records, then by chunks) to at most a third
   // of a wavefront's share, then longest first onto the least loaded
@@ -1109,6 +1118,13 @@ void pack_expect_blob(HTiling& t, const std::vector<HGroup>& gs, const std::vect
   start.push_back(uint32_t(list.size()));
   auto align16 = [](size_t v) { return (v + 15) & ~size_t(15); };
   XHdr h{};
+  {
+    // binary exponents with g_max < 2^e_g and g_sum < 2^e_s (frexp; 0 for 0)
+    int e_g = 0, e_s = 0;
+    std::frexp(g_max, &e_g);
+    std::frexp(g_sum * (1.0 + 1e-12), &e_s);
+    h.fx_shift = std::min(50 - e_g, 62 - e_s);
+  }
   h.n_batches = uint32_t(xb.size());
   h.n_items = uint32_t(list.size());
   h.n_waves = uint32_t(NW);

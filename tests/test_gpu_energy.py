@@ -410,12 +410,14 @@ def test_real_hint_at_21_qubits(case):
 
 @pytest.mark.parametrize("n,dtype", [(14, "c128"), (22, "c128"), (22, "c64"), (22, "r64")])
 def test_lambda_and_gradient_are_bitwise_reproducible(n, dtype):
-    """With the reproducible build (sv_set_deterministic), lambda = H psi,
-    the energy and the per-rotation gradient of two adjoint calls on the
-    same input are bitwise equal: every element of lambda is summed by one
-    wavefront in group order, and every reduction has a fixed order.  The
-    fast build agrees with it to FP64 rounding.  14 qubits takes the complex
-    build, 22 qubits the real-part tiles (a UCCSD state is real)."""
+    """lambda = H psi, the energy and the per-rotation gradient of two
+    adjoint calls on the same input are bitwise equal, in both builds: the
+    reproducible one (sv_set_deterministic; every element of lambda summed
+    by one wavefront in group order) and the fast one (fixed-point sums with
+    integer atomic adds, whose order does not matter); every reduction has a
+    fixed order.  The two builds agree to FP64 rounding.  14 qubits takes
+    the complex build, 22 qubits the real-part tiles (a UCCSD state is
+    real)."""
     announce(f"lambda twice, bitwise: {n} qubits {dtype}")
     ne = n // 2
     h, eri = synthetic_integrals(n, 1000 + n)
@@ -424,7 +426,7 @@ def test_lambda_and_gradient_are_bitwise_reproducible(n, dtype):
     phi = rot.angles(uniform_amplitudes(rot.n_params, 0.1, 5300 + n))
     psi = StateVector(n, dtype); lam = StateVector(n, dtype)
     out = []
-    for det in (True, True, False):
+    for det in (True, True, False, False):
         psi.set_deterministic(det)
         energy = torch.empty(2, dtype=torch.float64, device="cuda")
         grad = torch.empty(len(phi), dtype=torch.float64, device="cuda")
@@ -434,12 +436,15 @@ def test_lambda_and_gradient_are_bitwise_reproducible(n, dtype):
         torch.cuda.synchronize()
         out.append((energy.clone(), grad.clone(), lam.amps.clone()))
     psi.free(); lam.free()
-    (e1, g1, l1), (e2, g2, l2), (e3, g3, l3) = out
+    (e1, g1, l1), (e2, g2, l2), (e3, g3, l3), (e4, g4, l4) = out
     assert torch.equal(e1, e2)
     assert torch.equal(g1, g2)
     assert torch.equal(l1, l2)
+    assert torch.equal(e3, e4)
+    assert torch.equal(g3, g4)
+    assert torch.equal(l3, l4)
     assert torch.isfinite(g1).all() and float(g1.abs().max()) > 0.0
-    # the fast build (atomic adds in no fixed order) to the rounding of the sums
+    # the two builds to the rounding of the sums
     tol = 1e-12 if dtype != "c64" else 1e-5
     assert abs(float(e3[0] - e1[0])) <= tol * abs(float(e1[0]))
     assert float((g3 - g1).abs().max()) <= tol * max(1.0, float(g1.abs().max()))
