@@ -110,17 +110,6 @@ int sv_set_stream(sv_state *s, void *hip_stream);
  * its one stream wait.  The declaration stays until changed. */
 int sv_set_real_hint(sv_state *s, int psi_is_real);
 
-/* Choose how the adjoint calls build lambda = H psi (Algorithm 1).
- * on = 0 (the default): the fast build, in which the wavefronts of a block
- * add into shared FP64 accumulators with atomic adds; their order is not
- * fixed, so lambda and the energy and gradient computed from it may differ
- * between runs in the last bits (about 1e-16 relative in FP64).
- * on = 1: the reproducible build, in which every accumulator element is
- * owned by one wavefront and summed in a fixed group order, so repeated
- * calls, and a request alone or among concurrent ones, are bitwise equal;
- * lambda then takes about twice as long.  The choice stays until changed. */
-int sv_set_deterministic(sv_state *s, int on);
-
 /* psi <- |occ_mask>, the Hartree-Fock determinant of Eq. 6 as a basis state
  * (occupation of qubit q = bit q).  occ_mask < 2^n. */
 int sv_prepare_hf(sv_state *s, uint64_t occ_mask);
@@ -142,7 +131,12 @@ int sv_expect_pauli_sum(sv_state *s, const sv_pauli *p, const double *coef, int6
                         double *out_dev);
 
 /* Reverse-mode gradient (Algorithm 1) of E = <psi|H|psi> with respect to
- * every rotation angle.
+ * every rotation angle.  lambda = H psi is summed in 64-bit fixed point per
+ * tile (each term rounded at a power-of-two scale set by the tile's largest
+ * |psi|, about 2^-50 of the largest term), so the result does not depend on
+ * the order in which concurrent wavefronts add: lambda, the energy and the
+ * gradient are bitwise equal from run to run, and a request alone or among
+ * concurrent ones.
  *   psi     on entry U|psi0> from sv_apply_pauli_rotations with the same list;
  *           on return approximately psi0 (the rotations are undone).
  *   lam     scratch state with the same n and dtype; on return U^dag H U psi0.

@@ -53,7 +53,6 @@ def lib():
             "sv_free": [_vp],
             "sv_set_stream": [_vp, _vp],
             "sv_set_real_hint": [_vp, _c.c_int],
-            "sv_set_deterministic": [_vp, _c.c_int],
             "sv_inject_device_failure": [_c.c_char_p],
             "sv_prepare_hf": [_vp, _c.c_uint64],
             "sv_apply_pauli_rotations": [_vp, _vp, _vp, _i64],
@@ -88,7 +87,7 @@ def lib():
 
 
 EXPORTED = (
-    "sv_alloc", "sv_free", "sv_set_stream", "sv_set_real_hint", "sv_set_deterministic", "sv_inject_device_failure",
+    "sv_alloc", "sv_free", "sv_set_stream", "sv_set_real_hint", "sv_inject_device_failure",
     "sv_prepare_hf",
     "sv_apply_pauli_rotations",
     "sv_expect_pauli_sum", "sv_adjoint_grad", "sv_adjoint_grad_params", "sv_hamiltonian_create",
@@ -163,10 +162,6 @@ def sv_set_stream(s, stream):
 
 def sv_set_real_hint(s, psi_is_real: bool):
     _check(lib().sv_set_real_hint(s, int(bool(psi_is_real))))
-
-
-def sv_set_deterministic(s, on):
-    _check(lib().sv_set_deterministic(s, 1 if on else 0))
 
 
 def sv_inject_device_failure(msg: str = ""):

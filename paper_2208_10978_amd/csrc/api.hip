@@ -257,9 +257,8 @@ struct sv_hamiltonian {
   bool real = true;                  // every group coefficient is real (then a real psi gives a real lambda)
   std::vector<uint64_t> diag_z;      // diagonal (x = 0) terms
   std::vector<double> diag_c;
-  // [dtype][role]: 0 expectation; lambda 1 complex, 2 real-part tiles (fast
-  // builds), 3 complex, 4 real-part tiles (reproducible builds)
-  static constexpr int kRoles = 5;
+  // [dtype][role]: 0 expectation; lambda 1 complex, 2 real-part tiles
+  static constexpr int kRoles = 3;
   DevTiling tilings[3][kRoles];
   bool built[3][kRoles] = {};
   DevBuf diag_dev;                   // resident diagonal d[m], FP64, 2^n entries
@@ -283,12 +282,11 @@ static int tiling_get(sv_hamiltonian* h, int dtype, int role, DevTiling** out) {
   std::lock_guard<std::mutex> lk(h->mu);
   DevTiling& t = h->tilings[dtype][role];
   if (!h->built[dtype][role]) {
-    const int b = role == 0 ? tile_bits_one(dtype) : (role == 1 || role == 3) ? tile_bits_lambda(dtype) : kTileLamReal;
+    const int b = role == 0 ? tile_bits_one(dtype) : role == 1 ? tile_bits_lambda(dtype) : kTileLamReal;
     const int c = std::min(row_bits(dtype), h->n);
     // kernels read the tables through scalar loads, so a tile's groups need
     // not be split
-    t.host = build_tiling(h->groups, h->n, b, c, true, size_t(1) << 24, role >= 3 ? kLambdaRegionBits : 0,
-                          role == 0 ? kExpectThreads / 64 : role <= 2 ? kLambdaThreads / 64 : 0);
+    t.host = build_tiling(h->groups, h->n, b, c, size_t(1) << 24, role == 0 ? kExpectThreads / 64 : kLambdaThreads / 64);
     if (t.host.blob_overflow) return fail(SV_EINVAL, "internal: a tile's group tables are too large");
     Packer pk;
     t.o_frames = pk.add(t.host.frames.data(), t.host.frames.size() * sizeof(FrameDesc));
@@ -414,7 +412,6 @@ struct sv_state {
   double* host_word = nullptr;  // pinned FP64 word for a device value the host must read
   sv_hamiltonian* cached_h = nullptr;  // last Pauli sum passed as raw arrays
   bool real_hint = false;              // the caller asserts psi is real on entry to the adjoint calls
-  bool deterministic = false;          // lambda by the reproducible build
   std::atomic<int> busy{0};            // a call on this handle is in progress
   uint64_t amp_count() const { return uint64_t(1) << n; }
   double bytes() const { return double(amp_count()) * double(amp_bytes(dtype)); }
@@ -792,8 +789,7 @@ static int lambda_impl(sv_state* s, sv_state* lam, sv_hamiltonian* h, double* en
     }
   }
   DevTiling* t = nullptr;
-  const bool det = s->deterministic;
-  rc = tiling_get(h, s->dtype, real ? (det ? 4 : 2) : (det ? 3 : 1), &t);
+  rc = tiling_get(h, s->dtype, real ? 2 : 1, &t);
   if (rc) return rc;
   const double* diag = nullptr;
   rc = diag_get(h, s->stream, &diag);
@@ -805,7 +801,7 @@ static int lambda_impl(sv_state* s, sv_state* lam, sv_hamiltonian* h, double* en
     const uint64_t n_tb = uint64_t(1) << fr.n_comp;
     const int grid = int(std::min<uint64_t>(n_tb, uint64_t(num_cus())));
     ProfScope prof(s->stream, kPTileHLam, (tt == 0 ? (diag ? 2.5 : 2.0) : 3.0) * s->bytes());
-    const hipError_t e = launch_tile_lambda(s->dtype, tt == 0, real, det, s->amps, lam->amps, diag, fr,
+    const hipError_t e = launch_tile_lambda(s->dtype, tt == 0, real, s->amps, lam->amps, diag, fr,
                                             dptr<uint4>(t->buf, t->o_blob) + ht.blob_off[tt], n_tb, grid, guard,
                                             s->stream);
     if (e != hipSuccess) return device_fail(std::string("lambda tile: ") + hipGetErrorString(e));
@@ -1139,14 +1135,6 @@ int sv_set_real_hint(sv_state* s, int psi_is_real) {
   Call call(s);
   if (call.rc) return call.rc;
   s->real_hint = psi_is_real != 0;
-  return SV_OK;
-}
-
-int sv_set_deterministic(sv_state* s, int on) {
-  if (!s) return fail(SV_EINVAL, "NULL state");
-  Call call(s);
-  if (call.rc) return call.rc;
-  s->deterministic = on != 0;
   return SV_OK;
 }
 

@@ -3,241 +3,22 @@
 // LDS tiles, the diagonal part as a resident FP64 vector, and whole-state
 // passes for groups whose support does not fit a tile.
 //
-// The expectation copies a tile's group tables (TileHdr blob) into LDS once
-// per block; the lambda build reads them in place.  Only the pairs a group
-// actually reaches (its active support patterns) are enumerated.
+// Both read a tile's group tables (projected-sum blobs) in place through
+// scalar loads.  Only the pairs a group actually reaches (its active support
+// patterns) are enumerated.
 #include "device_common.h"
 #include "launch.h"
 
 namespace q2sv {
 
-struct BlobView {
-  const TileHdr* hdr;
-  const TGroup* groups;
-  const uint32_t* recs;
-  const TSub* subs;
-  const double2* coef;
-  const TFast* fast;
-  const LamSeg* segs;
-  __device__ explicit BlobView(const uint4* blob) {
-    const char* b = reinterpret_cast<const char*>(blob);
-    hdr = reinterpret_cast<const TileHdr*>(b);
-    groups = reinterpret_cast<const TGroup*>(b + sizeof(TileHdr));
-    recs = reinterpret_cast<const uint32_t*>(b + hdr->off_rec);
-    subs = reinterpret_cast<const TSub*>(b + hdr->off_sub);
-    coef = reinterpret_cast<const double2*>(b + hdr->off_coef);
-    fast = reinterpret_cast<const TFast*>(b + hdr->off_fast);
-    segs = reinterpret_cast<const LamSeg*>(b + hdr->off_segs);
-  }
-};
-
-// ---------------------------------------------------------------------------
-// lambda over one tile: MODE 1 lam = diag * psi + H_tile psi; MODE 2 lam += H_tile psi
-//
-// The tile's group tables stay in global memory: every index into them is
-// uniform over a wavefront, so they arrive through scalar loads into SGPRs
-// and feed the vector arithmetic directly.  Contributions land in the FP64
-// accumulator tile (real and imaginary parts in separate arrays), in one of
-// two ways:
-//   * fast (DET = false): the tables are projected-sum batches (XBatch); all
-//     wavefronts of the block work on the whole tile at once, each on its
-//     host-balanced list of work items, and add with LDS atomic adds, which
-//     return nothing, so an update is never a load-modify-store chain; the
-//     order in which the updates of different wavefronts reach an output is
-//     not fixed, so the last bits of lambda may differ between runs;
-//   * reproducible (DET = true): the tile's groups come in segments whose
-//     flip masks avoid the segment's region bits; wavefront w owns the
-//     amplitudes whose region bits spell w, both ends of every pair it walks
-//     lie in its region, and it adds with plain LDS loads and stores, group
-//     after group, synchronising once per segment.  Every element of lambda
-//     is then summed in one fixed order, at the price of every wavefront
-//     reading every group's tables.
-// ---------------------------------------------------------------------------
 // x * (-1)^s for s in {0, 1}: flips the sign bit
 __device__ __forceinline__ double signed_by(double x, unsigned s) {
   return __hiloint2double(__double2hiint(x) ^ int(s << 31), __double2loint(x));
 }
 
-// The uniform fields of a one-subgroup group record, fetched in one batch of
-// scalar loads and held in SGPRs (see sgpr_here).
-struct FastHead {
-  uint64_t w_out;
-  uint32_t w_loc, n_rec, walk_log, hi_mask, wlane, sx;
-  uint32_t dep_q[kWalkLaneBits];
-  uint32_t sbits[kFastRecs], pbits[kFastRecs];
-  double coef[2 * kFastRecs];
-};
-
-__device__ __forceinline__ FastHead load_fast(const TFast& t) {
-  FastHead f;
-  f.w_out = t.w_out;
-  f.w_loc = t.w_loc;
-  f.n_rec = t.n_rec;
-  f.walk_log = t.walk_log;
-  f.hi_mask = t.hi_mask;
-  f.wlane = t.wlane;
-  f.sx = t.sx;
-#pragma unroll
-  for (int i = 0; i < kWalkLaneBits; ++i) f.dep_q[i] = t.dep_q[i];
-#pragma unroll
-  for (int r = 0; r < kFastRecs; ++r) {
-    f.sbits[r] = t.sbits[r];
-    f.pbits[r] = t.pbits[r];
-    f.coef[2 * r] = t.coef[2 * r];
-    f.coef[2 * r + 1] = t.coef[2 * r + 1];
-  }
-  sgpr_here(f.w_out);
-  sgpr_here(f.w_loc);
-  sgpr_here(f.n_rec);
-  sgpr_here(f.walk_log);
-  sgpr_here(f.hi_mask);
-  sgpr_here(f.wlane);
-  sgpr_here(f.sx);
-#pragma unroll
-  for (int i = 0; i < kWalkLaneBits; ++i) sgpr_here(f.dep_q[i]);
-#pragma unroll
-  for (int r = 0; r < kFastRecs; ++r) {
-    sgpr_here(f.sbits[r]);
-    sgpr_here(f.pbits[r]);
-    sgpr_here(f.coef[2 * r]);
-    sgpr_here(f.coef[2 * r + 1]);
-  }
-  return f;
-}
-
-// A wavefront's walk over the fast records [f0, f1) of a lambda segment, in
-// order, on its own region (region bits wbits): each record's walk covers
-// the bits outside its support and the region bits.  body(f, ds, zp, srest,
-// sgn) gets the lane's slot part and w parity, and the block's slot and
-// uniform sign parity, the region's included.
-template <typename Body>
-__device__ __forceinline__ void walk_fast_region(const BlobView& bv, uint32_t f0, uint32_t f1, uint64_t base,
-                                                 uint32_t lane, const uint32_t (&lbit)[kWalkLaneBits],
-                                                 uint32_t wbits, Body body) {
-  const uint32_t swb = lds_swz(wbits);  // uniform
-  for (uint32_t fi = f0; fi < f1; ++fi) {
-    const FastHead f = load_fast(bv.fast[fi]);
-    const bool on = f.walk_log >= kWalkLaneBits || lane < (1u << f.walk_log);
-    const uint32_t nb = f.walk_log > kWalkLaneBits ? 1u << (f.walk_log - kWalkLaneBits) : 1u;
-    uint32_t ds = 0;
-#pragma unroll
-    for (int i = 0; i < kWalkLaneBits; ++i) ds ^= lbit[i] & f.dep_q[i];
-    const unsigned zp = __popc(lane & f.wlane);
-    const unsigned so = __popcll(base & f.w_out) + __popc(wbits & f.w_loc);
-    uint32_t rest = 0;  // uniform: the block's loop bits
-    for (uint32_t blk = 0; blk < nb; ++blk) {
-      const uint32_t srest = lds_swz(rest) ^ swb;
-      const unsigned prest = __popc(rest & f.w_loc);
-      if (on) body(f, ds, zp, srest, so + prest);
-      rest = (rest - f.hi_mask) & f.hi_mask;
-    }
-  }
-}
-
-// The folded part B(base)[record] of every factored group (see TGroup): the
-// wavefront w takes the factored groups with index w mod NW (uniform loops,
-// tables through scalar loads) and leaves one FP64 complex per record in LDS.
-template <int NW>
-__device__ __forceinline__ void factored_base(const BlobView& bv, uint32_t n_groups, uint64_t base, int wave,
-                                              int lane, double2* fB) {
-  for (uint32_t gi = 0; gi < n_groups; ++gi) {
-    const uint32_t fi = bv.groups[gi].fact_idx;
-    if (fi == ~0u || int(fi % uint32_t(NW)) != wave) continue;
-    const TGroup g = bv.groups[gi];
-    for (uint32_t r = 0; r < g.n_rec; ++r) {
-      double br = 0.0, bi = 0.0;
-      for (uint32_t k = g.n_in; k < g.n_sub; ++k) {
-        const unsigned sg = __popcll(base & bv.subs[g.sub_off + k].w_out);
-        const double2 cv = bv.coef[g.coef_off + k * g.n_rec + r];
-        br += signed_by(cv.x, sg);
-        bi += signed_by(cv.y, sg);
-      }
-      if (lane == 0) fB[fi * kFactRecs + r] = make_double2(br, bi);
-    }
-  }
-}
-
-// G(m) of a general group at the pair whose m' has frame-local bits lmp.
-__device__ __forceinline__ void general_g(const BlobView& bv, const TGroup& g, uint32_t r, uint32_t lmp,
-                                          uint64_t base, const double2* fB, double& gre, double& gim) {
-  gre = 0.0;
-  gim = 0.0;
-  if (g.fact_idx != ~0u) {
-    const double2 b0 = fB[g.fact_idx * kFactRecs + r];
-    gre = b0.x;
-    gim = b0.y;
-#pragma unroll 4
-    for (uint32_t k = 0; k < g.n_in; ++k) {
-      const unsigned sg = __popc(lmp & bv.subs[g.sub_off + k].w_loc);
-      const double2 cv = bv.coef[g.coef_off + k * g.n_rec + r];
-      gre += signed_by(cv.x, sg);
-      gim += signed_by(cv.y, sg);
-    }
-    const unsigned s0 = __popc(lmp & g.w0_loc) + __popcll(base & g.w0_out);
-    gre = signed_by(gre, s0);
-    gim = signed_by(gim, s0);
-    return;
-  }
-#pragma unroll 4
-  for (uint32_t k = 0; k < g.n_sub; ++k) {
-    const TSub sd = bv.subs[g.sub_off + k];
-    const double2 cv = bv.coef[g.coef_off + k * g.n_rec + r];
-    const unsigned sg = __popc(lmp & sd.w_loc) + __popcll(base & sd.w_out);
-    gre += signed_by(cv.x, sg);
-    gim += signed_by(cv.y, sg);
-  }
-}
-
-// The pairs (m', m = m' ^ x) of every record of a one-subgroup group at one
-// walk position (slot part ds, w-parity of the lane part zp) plus the uniform
-// part rest: all loads first, then the updates, with plain loads and stores
-// for a caller that owns both ends of every pair (no two records share a
-// slot).  The slot of a record's m' is ds ^ slot(rest | bits) (the LDS slot
-// map is linear).
-// REAL: psi and every coefficient are real, so lambda is real; only the real
-// parts are read and accumulated (the imaginary ones are exactly zero)
-template <int NR, bool REAL, typename TT>
-__device__ __forceinline__ void fast_pairs_owned(const FastHead& f, uint32_t ds, unsigned zp, uint32_t srest, unsigned so,
-                                           const TT* tp, double* tlr, double* tli) {
-  uint32_t smp[NR];
-  double pmx[NR], pmy[NR], ppx[NR], ppy[NR];  // psi[m], psi[m']
-  double lmx[NR], lmy[NR], lpx[NR], lpy[NR];  // lam[m], lam[m']
-#pragma unroll
-  for (int r = 0; r < NR; ++r) {
-    smp[r] = ds ^ srest ^ f.sbits[r];
-    const uint32_t sm = smp[r] ^ f.sx;
-    pmx[r] = (double)tp[sm].x;
-    ppx[r] = (double)tp[smp[r]].x;
-    lmx[r] = tlr[sm];
-    lpx[r] = tlr[smp[r]];
-    if constexpr (!REAL) {
-      pmy[r] = (double)tp[sm].y;
-      ppy[r] = (double)tp[smp[r]].y;
-      lmy[r] = tli[sm];
-      lpy[r] = tli[smp[r]];
-    }
-  }
-#pragma unroll
-  for (int r = 0; r < NR; ++r) {
-    const unsigned sg = zp + f.pbits[r] + so;
-    const uint32_t sm = smp[r] ^ f.sx;
-    const double gre = signed_by(f.coef[2 * r], sg);
-    if constexpr (REAL) {
-      tlr[sm] = lmx[r] + gre * ppx[r];
-      tlr[smp[r]] = lpx[r] + gre * pmx[r];
-    } else {
-      const double gim = signed_by(f.coef[2 * r + 1], sg);
-      tlr[sm] = lmx[r] + (gre * ppx[r] - gim * ppy[r]);  // lam[m] += G psi[m']
-      tli[sm] = lmy[r] + (gre * ppy[r] + gim * ppx[r]);
-      tlr[smp[r]] = lpx[r] + (gre * pmx[r] + gim * pmy[r]);  // lam[m'] += conj(G) psi[m]
-      tli[smp[r]] = lpy[r] + (gre * pmy[r] - gim * pmx[r]);
-    }
-  }
-}
-
 // ---------------------------------------------------------------------------
-// Projected-sum tables (XHdr blobs, see XBatch): the expectation tilings and
-// the fast lambda tilings share them.
+// Projected-sum tables (XHdr blobs, see XBatch): the expectation and lambda
+// tilings share them.
 // ---------------------------------------------------------------------------
 struct XView {
   const XHdr* hdr;
@@ -428,23 +209,34 @@ struct RealSlot {
 };
 template <> struct Real<RealSlot> { using type = double; };
 
-// The tile passes of a lambda build, on the block's LDS arrays (tp: psi tile
-// of TT slots; tlr, tli: FP64 lambda accumulator; fB: factored-group
-// values).  REAL: psi and every coefficient are real, so only real parts are
-// read and accumulated and tli is not used; TT = RealSlot keeps only the
-// real parts of psi in the tile.
+// ---------------------------------------------------------------------------
+// lambda over one tile: MODE 1 lam = diag * psi + H_tile psi; MODE 2 lam += H_tile psi
 //
-// The fast build sums in fixed point: tlr and tli then hold 64-bit integer
-// accumulators, cleared per tile, while the tile's starting values (diag psi
-// or the lambda of earlier passes) wait in registers; the result is start +
-// accumulator * 2^-s.  The scale 2^s of a tile comes from the blob's
-// fx_shift and the exponent of the tile's largest |psi| (sexp: one entry per
-// wavefront), so that no term reaches 2^50 and no sum 2^62.
-template <typename T, int B, int NT, int MODE, bool FULL, bool REAL, bool DET, typename TT = T>
+// The tile's group tables are projected-sum batches (XBatch) read from global
+// memory: every index into them is uniform over a wavefront, so they arrive
+// through scalar loads into SGPRs and feed the vector arithmetic directly.
+// All wavefronts of the block work on the whole tile at once, each on its
+// host-balanced list of work items, and add their terms into 64-bit
+// fixed-point accumulators with LDS integer atomic adds (which return
+// nothing, so an update is never a load-modify-store chain).  Integer sums do
+// not depend on the order in which the updates of different wavefronts
+// arrive, so lambda is the same from run to run.
+// ---------------------------------------------------------------------------
+// The tile passes of a lambda build, on the block's LDS arrays: tp, the psi
+// tile of TT slots; alr, ali, 64-bit fixed-point accumulators of lambda's
+// real and imaginary parts, cleared per tile, while the tile's starting
+// values (diag psi, or the lambda of earlier passes) wait in registers; the
+// result is start + accumulator * 2^-s.  The scale 2^s of a tile comes from
+// the blob's fx_shift and the exponent of the tile's largest |psi| (sexp:
+// one entry per wavefront), so that no term reaches 2^50 and no sum 2^62.
+// REAL: psi and every coefficient are real, so only real parts are read and
+// accumulated and ali is not used; TT = RealSlot keeps only the real parts
+// of psi in the tile.
+template <typename T, int B, int NT, int MODE, bool FULL, bool REAL, typename TT = T>
 __device__ __forceinline__ void lambda_tiles(const T* __restrict__ psi, T* __restrict__ lam,
                                              const double* __restrict__ diag, const FrameDesc& fr,
-                                             const uint4* __restrict__ blob, uint64_t n_tb, TT* tp, double* tlr,
-                                             double* tli, double2* fB, int* sexp) {
+                                             const uint4* __restrict__ blob, uint64_t n_tb, TT* tp,
+                                             unsigned long long* alr, unsigned long long* ali, int* sexp) {
   static_assert(REAL || std::is_same<TT, T>::value, "a real-part tile needs the real build");
   using R = typename Real<T>::type;
   constexpr bool kRealTile = std::is_same<TT, RealSlot>::value;
@@ -453,12 +245,9 @@ __device__ __forceinline__ void lambda_tiles(const T* __restrict__ psi, T* __res
   const int lane = threadIdx.x & 63;
   const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
 
-  unsigned long long* const alr = reinterpret_cast<unsigned long long*>(tlr);
-  unsigned long long* const ali = reinterpret_cast<unsigned long long*>(tli);
-
-  // fast build: every wavefront on the whole tile, LDS atomic adds; the
-  // tables are projected-sum batches with per-wavefront work lists
-  auto apply_groups_fast = [&](uint64_t base, double sc) {
+  // every wavefront on the whole tile, on its work list, scale 2^sh
+  auto apply_groups = [&](uint64_t base, int sh) {
+    const double sc = __builtin_ldexp(1.0, sh);
     const XView xv(blob);
     const bool lists = xv.hdr->n_waves == uint32_t(NW);
     const uint32_t i0 = lists ? xv.start[wave] : uint32_t(wave);
@@ -489,85 +278,15 @@ __device__ __forceinline__ void lambda_tiles(const T* __restrict__ psi, T* __res
     e = wave_max_i32(e);
     if (lane == 0) sexp[wave] = e;
   };
-
-  // reproducible build: region-owned segments, plain loads and stores
-  auto apply_groups_owned = [&](uint64_t base) {
-    const BlobView bv(blob);
-    uint32_t lbit[kWalkLaneBits];  // all ones where the lane index has bit i
-#pragma unroll
-    for (int i = 0; i < kWalkLaneBits; ++i) lbit[i] = 0u - ((uint32_t(lane) >> i) & 1u);
-    const uint32_t n_groups = bv.hdr->n_groups, n_segs = bv.hdr->n_segs, n_fact = bv.hdr->n_fact;
-    if (n_fact) {
-      factored_base<NW>(bv, n_groups, base, wave, lane, fB);
-      __syncthreads();
-    }
-    for (uint32_t si = 0; si < n_segs; ++si) {
-      const LamSeg sg = bv.segs[si];
-      sgpr_here(sg.wb_mask);
-      // a segment without region bits belongs to wavefront 0 alone
-      if (sg.wb_mask != 0u || wave == 0) {
-        const uint32_t wbits = region_bits_of(sg.wb_mask, uint32_t(wave));
-        // groups with several subgroups: the lanes take pairs (record,
-        // position of the bits outside S' and the region bits), G(m) summed
-        // over the subgroups
-        for (uint32_t gi = sg.g_first; gi < sg.g_first + sg.g_count; ++gi) {
-          const TGroup g = bv.groups[gi];
-          const int nf = int(fr.b) - int(g.n_sins);
-          const uint32_t n_it = g.n_rec << nf;
-          auto pair = [&](uint32_t r, uint32_t t) {
-            const uint32_t lmp = insert_zeros32_p4(t, g.sins_pack, g.n_sins) | bv.recs[g.rec_off + r] | wbits;
-            const uint32_t lm = lmp ^ g.x_loc;
-            double gre, gim;  // G(m)
-            general_g(bv, g, r, lmp, base, fB, gre, gim);
-            const uint32_t smp = lds_swz(lmp), sm = lds_swz(lm);
-            if constexpr (REAL) {
-              const double pm = (double)tp[sm].x, pp = (double)tp[smp].x;
-              const double lm0 = tlr[sm], lp0 = tlr[smp];
-              tlr[sm] = lm0 + gre * pp;
-              tlr[smp] = lp0 + gre * pm;
-            } else {
-              const T pm = tp[sm], pp = tp[smp];
-              const double lmx = tlr[sm], lmy = tli[sm], lpx = tlr[smp], lpy = tli[smp];
-              tlr[sm] = lmx + (gre * (double)pp.x - gim * (double)pp.y);  // lam[m] += G psi[m']
-              tli[sm] = lmy + (gre * (double)pp.y + gim * (double)pp.x);
-              tlr[smp] = lpx + (gre * (double)pm.x + gim * (double)pm.y);  // lam[m'] += conj(G) psi[m]
-              tli[smp] = lpy + (gre * (double)pm.y - gim * (double)pm.x);
-            }
-          };
-          if (nf >= 6) {
-            // 2^nf >= 64: a wavefront's positions share one record, so its
-            // index is uniform and the tables arrive by scalar loads
-            for (uint32_t idx = uint32_t(lane); idx < n_it; idx += 64u)
-              pair(__builtin_amdgcn_readfirstlane(idx >> nf), idx & ((1u << nf) - 1u));
-          } else {
-            for (uint32_t idx = uint32_t(lane); idx < n_it; idx += 64u) pair(idx >> nf, idx & ((1u << nf) - 1u));
-          }
-        }
-        // one-subgroup groups: a lane takes one position and every record's
-        // pair there
-        walk_fast_region(bv, sg.f_first, sg.f_first + sg.f_count, base, uint32_t(lane), lbit, wbits,
-                         [&](const FastHead& f, uint32_t ds, unsigned zp, uint32_t srest, unsigned sgn) {
-                           switch (f.n_rec) {
-                             case 1: fast_pairs_owned<1, REAL>(f, ds, zp, srest, sgn, tp, tlr, tli); break;
-                             case 2: fast_pairs_owned<2, REAL>(f, ds, zp, srest, sgn, tp, tlr, tli); break;
-                             case 3: fast_pairs_owned<3, REAL>(f, ds, zp, srest, sgn, tp, tlr, tli); break;
-                             default: fast_pairs_owned<4, REAL>(f, ds, zp, srest, sgn, tp, tlr, tli); break;
-                           }
-                         });
-      }
-      __syncthreads();
-    }
-    if (n_segs == 0) __syncthreads();
-  };
-  auto apply_groups = [&](uint64_t base, int sh) {
-    if constexpr (DET) apply_groups_owned(base);
-    else apply_groups_fast(base, __builtin_ldexp(1.0, sh));
+  // a finished slot: start + accumulator * unit
+  auto result = [&](double start, unsigned long long acc, double unit) {
+    return fma(double(static_cast<long long>(acc)), unit, start);
   };
 
   Stage<T, PER> rp;
   Stage<T, PER> rl;
   double rd[PER];
-  double ir[PER], ii[PER];  // fast build: the tile's starting values
+  double ir[PER], ii[PER];  // the tile's starting values
   uint64_t tb = blockIdx.x;
   if constexpr (FULL) {
     // next loads before the groups; this tile's lambda leaves only after the
@@ -598,19 +317,12 @@ __device__ __forceinline__ void lambda_tiles(const T* __restrict__ psi, T* __res
 #pragma unroll
       for (int i = 0; i < PER; ++i) {
         const uint32_t sl = lds_swz(threadIdx.x + uint32_t(i) * NT);
-        const double vr = MODE == 1 ? rd[i] * (double)rp.re[i] : (double)rl.re[i];
-        const double vi = REAL ? 0.0 : MODE == 1 ? rd[i] * (double)rp.im[i] : (double)rl.im[i];
-        if constexpr (DET) {
-          tlr[sl] = vr;
-          if (!REAL) tli[sl] = vi;
-        } else {
-          ir[i] = vr;
-          ii[i] = vi;
-          alr[sl] = 0ull;
-          if (!REAL) ali[sl] = 0ull;
-        }
+        ir[i] = MODE == 1 ? rd[i] * (double)rp.re[i] : (double)rl.re[i];
+        ii[i] = REAL ? 0.0 : MODE == 1 ? rd[i] * (double)rp.im[i] : (double)rl.im[i];
+        alr[sl] = 0ull;
+        if (!REAL) ali[sl] = 0ull;
       }
-      if constexpr (!DET) note_exp(rp, PER);
+      note_exp(rp, PER);
     };
     if (tb < n_tb) {
       fetch(frame_base(fr, tb));
@@ -620,7 +332,7 @@ __device__ __forceinline__ void lambda_tiles(const T* __restrict__ psi, T* __res
     for (; tb < n_tb; tb += gridDim.x) {
       const uint64_t base = frame_base(fr, tb);
       const uint64_t nx = tb + gridDim.x;
-      const int sh = DET ? 0 : tile_shift();
+      const int sh = tile_shift();
       if (nx < n_tb) fetch(frame_base(fr, nx));
       apply_groups(base, sh);
       Stage<T, PER> out;
@@ -628,13 +340,8 @@ __device__ __forceinline__ void lambda_tiles(const T* __restrict__ psi, T* __res
 #pragma unroll
       for (int i = 0; i < PER; ++i) {
         const uint32_t sl = lds_swz(threadIdx.x + uint32_t(i) * NT);
-        if constexpr (DET) {
-          out.re[i] = R(tlr[sl]);
-          out.im[i] = REAL ? R(0) : R(tli[sl]);
-        } else {
-          out.re[i] = R(fma(double(static_cast<long long>(alr[sl])), unit, ir[i]));
-          out.im[i] = REAL ? R(0) : R(fma(double(static_cast<long long>(ali[sl])), unit, ii[i]));
-        }
+        out.re[i] = R(result(ir[i], alr[sl], unit));
+        out.im[i] = REAL ? R(0) : R(result(ii[i], ali[sl], unit));
       }
       if (nx < n_tb) put();
       tile_send<T, PER, NT>(lam, ta, fr, base, out);
@@ -663,6 +370,8 @@ __device__ __forceinline__ void lambda_tiles(const T* __restrict__ psi, T* __res
         }
       }
     };
+    // lanes past a small tile hold no amplitude: a thread's valid slots
+    const int n_valid = int(nloc > threadIdx.x ? (nloc - threadIdx.x + NT - 1) / NT : 0u);
     if (tb < n_tb) fetch(tb);
     for (; tb < n_tb; tb += gridDim.x) {
       const uint64_t base = frame_base(fr, tb);
@@ -680,26 +389,15 @@ __device__ __forceinline__ void lambda_tiles(const T* __restrict__ psi, T* __res
         const uint32_t l = threadIdx.x + uint32_t(i) * NT;
         if (l < nloc) {
           const uint32_t sl = lds_swz(l);
-          const double vr = MODE == 1 ? rd[i] * (double)rp.re[i] : (double)rl.re[i];
-          const double vi = REAL ? 0.0 : MODE == 1 ? rd[i] * (double)rp.im[i] : (double)rl.im[i];
-          if constexpr (DET) {
-            tlr[sl] = vr;
-            if (!REAL) tli[sl] = vi;
-          } else {
-            ir[i] = vr;
-            ii[i] = vi;
-            alr[sl] = 0ull;
-            if (!REAL) ali[sl] = 0ull;
-          }
+          ir[i] = MODE == 1 ? rd[i] * (double)rp.re[i] : (double)rl.re[i];
+          ii[i] = REAL ? 0.0 : MODE == 1 ? rd[i] * (double)rp.im[i] : (double)rl.im[i];
+          alr[sl] = 0ull;
+          if (!REAL) ali[sl] = 0ull;
         }
       }
-      if constexpr (!DET) {
-        // lanes past the tile hold no amplitude: PER slots, the last partial
-        const int n_valid = int(nloc > threadIdx.x ? (nloc - threadIdx.x + NT - 1) / NT : 0u);
-        note_exp(rp, n_valid);
-      }
+      note_exp(rp, n_valid);
       __syncthreads();
-      const int sh = DET ? 0 : tile_shift();
+      const int sh = tile_shift();
       const uint64_t nx = tb + gridDim.x;
       if (nx < n_tb) fetch(nx);
       apply_groups(base, sh);
@@ -709,13 +407,9 @@ __device__ __forceinline__ void lambda_tiles(const T* __restrict__ psi, T* __res
         const uint32_t l = threadIdx.x + uint32_t(i) * NT;
         if (l < nloc) {
           const uint32_t sl = lds_swz(l);
-          if constexpr (DET) {
-            lam[base | frame_deposit(lut, l)] = cmake<T>(R(tlr[sl]), REAL ? R(0) : R(tli[sl]));
-          } else {
-            const double vr = fma(double(static_cast<long long>(alr[sl])), unit, ir[i]);
-            const double vi = REAL ? 0.0 : fma(double(static_cast<long long>(ali[sl])), unit, ii[i]);
-            lam[base | frame_deposit(lut, l)] = cmake<T>(R(vr), R(vi));
-          }
+          const double vr = result(ir[i], alr[sl], unit);
+          const double vi = REAL ? 0.0 : result(ii[i], ali[sl], unit);
+          lam[base | frame_deposit(lut, l)] = cmake<T>(R(vr), R(vi));
         }
       }
     }
@@ -724,15 +418,14 @@ __device__ __forceinline__ void lambda_tiles(const T* __restrict__ psi, T* __res
 
 // lambda = H psi over the tiles of one frame.  MODE 1 starts from the
 // diagonal part, MODE 2 adds to lam.
-template <typename T, int B, int NT, int MODE, bool FULL, bool DET>
+template <typename T, int B, int NT, int MODE, bool FULL>
 __global__ void __launch_bounds__(NT) k_tile_lambda(const T* __restrict__ psi, T* __restrict__ lam,
                                                     const double* __restrict__ diag, FrameDesc fr,
                                                     const uint4* __restrict__ blob, uint64_t n_tb) {
   __shared__ T tp[1 << B];
-  __shared__ double tlr[1 << B], tli[1 << B];
-  __shared__ double2 fB[kMaxFactored * kFactRecs];
+  __shared__ unsigned long long alr[1 << B], ali[1 << B];
   __shared__ int sexp[NT / 64];
-  lambda_tiles<T, B, NT, MODE, FULL, false, DET>(psi, lam, diag, fr, blob, n_tb, tp, tlr, tli, fB, sexp);
+  lambda_tiles<T, B, NT, MODE, FULL, false>(psi, lam, diag, fr, blob, n_tb, tp, alr, ali, sexp);
 }
 
 // The same for a real psi and a sum with real coefficients: lambda is real,
@@ -761,20 +454,19 @@ __device__ __forceinline__ void lambda_poison(T* __restrict__ lam, const FrameDe
   }
 }
 
-template <typename T, int B, int NT, int MODE, bool FULL, bool DET>
+template <typename T, int B, int NT, int MODE, bool FULL>
 __global__ void __launch_bounds__(NT) k_tile_lambda_real(const T* __restrict__ psi, T* __restrict__ lam,
                                                          const double* __restrict__ diag, FrameDesc fr,
                                                          const uint4* __restrict__ blob, uint64_t n_tb,
                                                          const double* __restrict__ guard) {
   __shared__ RealSlot tp[1 << B];
-  __shared__ double tlr[1 << B];
-  __shared__ double2 fB[kMaxFactored * kFactRecs];
+  __shared__ unsigned long long alr[1 << B];
   __shared__ int sexp[NT / 64];
   if (guard && *guard != 0.0) {
     lambda_poison<T, NT>(lam, fr, n_tb);
     return;
   }
-  lambda_tiles<T, B, NT, MODE, FULL, true, DET, RealSlot>(psi, lam, diag, fr, blob, n_tb, tp, tlr, nullptr, fB, sexp);
+  lambda_tiles<T, B, NT, MODE, FULL, true, RealSlot>(psi, lam, diag, fr, blob, n_tb, tp, alr, nullptr, sexp);
 }
 
 // ---------------------------------------------------------------------------
@@ -1026,52 +718,45 @@ __global__ void __launch_bounds__(256) k_group_full(const T* __restrict__ psi, T
 // ---------------------------------------------------------------------------
 // launchers
 // ---------------------------------------------------------------------------
-template <typename T, int B, int M, bool RT, bool DET>
+template <typename T, int B, int M, bool RT>
 static void tile_lambda_t(const void* psi, void* lam, const double* diag, const FrameDesc& fr, const uint4* blob,
                           uint64_t n_tb, int grid, const double* guard, hipStream_t st) {
-  constexpr int NT = DET ? kLambdaDetThreads : kLambdaThreads;
+  constexpr int NT = kLambdaThreads;
   const T* p = static_cast<const T*>(psi);
   T* l = static_cast<T*>(lam);
   if constexpr (RT) {
     if (fr.b == B)
-      hipLaunchKernelGGL((k_tile_lambda_real<T, B, NT, M, true, DET>), dim3(grid), dim3(NT), 0, st, p, l, diag, fr,
-                         blob, n_tb, guard);
+      hipLaunchKernelGGL((k_tile_lambda_real<T, B, NT, M, true>), dim3(grid), dim3(NT), 0, st, p, l, diag, fr, blob,
+                         n_tb, guard);
     else
-      hipLaunchKernelGGL((k_tile_lambda_real<T, B, NT, M, false, DET>), dim3(grid), dim3(NT), 0, st, p, l, diag, fr,
-                         blob, n_tb, guard);
+      hipLaunchKernelGGL((k_tile_lambda_real<T, B, NT, M, false>), dim3(grid), dim3(NT), 0, st, p, l, diag, fr, blob,
+                         n_tb, guard);
   } else {
     if (fr.b == B)
-      hipLaunchKernelGGL((k_tile_lambda<T, B, NT, M, true, DET>), dim3(grid), dim3(NT), 0, st, p, l, diag, fr, blob,
-                         n_tb);
+      hipLaunchKernelGGL((k_tile_lambda<T, B, NT, M, true>), dim3(grid), dim3(NT), 0, st, p, l, diag, fr, blob, n_tb);
     else
-      hipLaunchKernelGGL((k_tile_lambda<T, B, NT, M, false, DET>), dim3(grid), dim3(NT), 0, st, p, l, diag, fr, blob,
-                         n_tb);
+      hipLaunchKernelGGL((k_tile_lambda<T, B, NT, M, false>), dim3(grid), dim3(NT), 0, st, p, l, diag, fr, blob, n_tb);
   }
 }
 
 template <typename T, int B, bool RT>
-static void tile_lambda_m(bool first, bool det, const void* psi, void* lam, const double* diag, const FrameDesc& fr,
+static void tile_lambda_m(bool first, const void* psi, void* lam, const double* diag, const FrameDesc& fr,
                           const uint4* blob, uint64_t n_tb, int grid, const double* guard, hipStream_t st) {
-  if (det) {
-    if (first) tile_lambda_t<T, B, 1, RT, true>(psi, lam, diag, fr, blob, n_tb, grid, guard, st);
-    else tile_lambda_t<T, B, 2, RT, true>(psi, lam, diag, fr, blob, n_tb, grid, guard, st);
-  } else {
-    if (first) tile_lambda_t<T, B, 1, RT, false>(psi, lam, diag, fr, blob, n_tb, grid, guard, st);
-    else tile_lambda_t<T, B, 2, RT, false>(psi, lam, diag, fr, blob, n_tb, grid, guard, st);
-  }
+  if (first) tile_lambda_t<T, B, 1, RT>(psi, lam, diag, fr, blob, n_tb, grid, guard, st);
+  else tile_lambda_t<T, B, 2, RT>(psi, lam, diag, fr, blob, n_tb, grid, guard, st);
 }
 
-hipError_t launch_tile_lambda(int dtype, bool first, bool real, bool det, const void* psi, void* lam,
-                              const double* diag, const FrameDesc& fr, const uint4* blob, uint64_t n_tb, int grid,
-                              const double* guard, hipStream_t st) {
+hipError_t launch_tile_lambda(int dtype, bool first, bool real, const void* psi, void* lam, const double* diag,
+                              const FrameDesc& fr, const uint4* blob, uint64_t n_tb, int grid, const double* guard,
+                              hipStream_t st) {
   if (dtype == 2) {  // a real state: always the real-part build
-    tile_lambda_m<R64, kTileLamReal, true>(first, det, psi, lam, diag, fr, blob, n_tb, grid, nullptr, st);
+    tile_lambda_m<R64, kTileLamReal, true>(first, psi, lam, diag, fr, blob, n_tb, grid, nullptr, st);
   } else if (dtype == 0) {
-    if (real) tile_lambda_m<double2, kTileLamReal, true>(first, det, psi, lam, diag, fr, blob, n_tb, grid, guard, st);
-    else tile_lambda_m<double2, kTileLamC128, false>(first, det, psi, lam, diag, fr, blob, n_tb, grid, guard, st);
+    if (real) tile_lambda_m<double2, kTileLamReal, true>(first, psi, lam, diag, fr, blob, n_tb, grid, guard, st);
+    else tile_lambda_m<double2, kTileLamC128, false>(first, psi, lam, diag, fr, blob, n_tb, grid, guard, st);
   } else {
-    if (real) tile_lambda_m<float2, kTileLamReal, true>(first, det, psi, lam, diag, fr, blob, n_tb, grid, guard, st);
-    else tile_lambda_m<float2, kTileLamC64, false>(first, det, psi, lam, diag, fr, blob, n_tb, grid, guard, st);
+    if (real) tile_lambda_m<float2, kTileLamReal, true>(first, psi, lam, diag, fr, blob, n_tb, grid, guard, st);
+    else tile_lambda_m<float2, kTileLamC64, false>(first, psi, lam, diag, fr, blob, n_tb, grid, guard, st);
   }
   return hipGetLastError();
 }

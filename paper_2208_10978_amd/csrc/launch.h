@@ -28,8 +28,7 @@ constexpr int kTileLamC128 = 12, kTileLamC64 = 12;   // psi tile + FP64 lambda a
 constexpr int kTileLamReal = 13;                      // real parts of psi + one FP64 accumulator (real lambda)
 constexpr int kTileThreads = 512;
 constexpr int kTileRegionBits = 3;                   // 8 wavefronts own 8 regions of a segment
-constexpr int kLambdaThreads = 1024;                 // 16 wavefronts share one tile (fast build)
-constexpr int kLambdaDetThreads = 64 << kLambdaRegionBits;  // one wavefront per region of a segment (reproducible build)
+constexpr int kLambdaThreads = 1024;                 // 16 wavefronts share one tile
 constexpr int kExpectThreads = 1024;                 // 16 wavefronts share one tile
 constexpr int kMaxPassSlots = 96;                    // gradient slots per reverse tile pass (24 KiB of LDS cells)
 constexpr int kMaxPassRuns = 1 << 16;                // runs per tile pass
@@ -57,11 +56,10 @@ hipError_t launch_tile_reverse(int dtype, int grad, void* psi, void* lam, const 
 // built from real parts only (always so for a real state, dtype 2).  guard
 // (real builds of complex states only, may be NULL): device count of psi's
 // nonzero imaginary parts; when it is not zero the pass writes NaN over
-// lambda instead.  det: the reproducible build (the tiling's blobs carry
-// region segments); otherwise the fast build (blobs with work items).
-hipError_t launch_tile_lambda(int dtype, bool first, bool real, bool det, const void* psi, void* lam,
-                              const double* diag, const FrameDesc& fr, const uint4* blob, uint64_t n_tb, int grid,
-                              const double* guard, hipStream_t st);
+// lambda instead.
+hipError_t launch_tile_lambda(int dtype, bool first, bool real, const void* psi, void* lam, const double* diag,
+                              const FrameDesc& fr, const uint4* blob, uint64_t n_tb, int grid, const double* guard,
+                              hipStream_t st);
 // partials[block] = number of the block's amplitudes with a nonzero imaginary part (grid blocks of 256)
 hipError_t launch_imag_count(int dtype, const void* a, uint64_t n_amp, int grid, double* partials, hipStream_t st);
 hipError_t launch_tile_expect(int dtype, const void* psi, const FrameDesc& fr, const uint4* blob, uint64_t n_tb,

@@ -648,218 +648,15 @@ static void append_full_group(HTiling& t, const HGroup& g, uint64_t all) {
   for (uint64_t v : g.rec_v) t.recbits.push_back(v);
 }
 
+// A group's share of a blob (its records, subgroups, coefficients and a
+// batch), for cutting a tile's groups into blobs of bounded size.
 static size_t group_blob_bytes(const HGroup& g) {
   const size_t nr = size_t(g.n_rec());
-  return sizeof(TGroup) + nr * sizeof(uint32_t) + g.w.size() * sizeof(TSub) + g.w.size() * nr * 16;
-}
-
-// Pack groups of one tile into a blob (TileHdr, TGroup[], record bits[], TSub[], coef[], TFast[]).
-static bool fast_group(const HGroup& g) { return g.w.size() == 1 && g.n_rec() <= kFastRecs; }
-
-std::vector<std::pair<uint32_t, std::vector<int>>> lambda_segments(const std::vector<uint32_t>& x_loc, int b,
-                                                                   int region_bits) {
-  std::vector<std::pair<uint32_t, std::vector<int>>> out;
-  std::vector<int> rest(x_loc.size());
-  for (size_t i = 0; i < rest.size(); ++i) rest[i] = int(i);
-  while (!rest.empty()) {
-    uint32_t best = 0;
-    size_t best_n = 0;
-    for (uint32_t m = (1u << b) - 1u;; --m) {
-      if (popc(uint64_t(m)) == region_bits) {
-        size_t k = 0;
-        for (int i : rest) k += (x_loc[size_t(i)] & m) == 0;
-        if (k > best_n) {
-          best_n = k;
-          best = m;
-        }
-      }
-      if (m == 0) break;
-    }
-    std::vector<int> in, left;
-    for (int i : rest) {
-      if (best_n > 0 ? (x_loc[size_t(i)] & best) == 0 : in.empty()) in.push_back(i);
-      else left.push_back(i);
-    }
-    out.push_back({best_n > 0 ? best : 0u, in});
-    rest.swap(left);
-  }
-  return out;
-}
-
-static void pack_blob(HTiling& t, const std::vector<HGroup>& gs, const std::vector<int>& members_in,
-                      uint64_t qmask, size_t max_blob, bool use_fast, int region_bits) {
-  std::vector<TGroup> tg;
-  std::vector<uint32_t> to;
-  std::vector<TSub> ts;
-  std::vector<double> co;
-  std::vector<TFast> tf;
-  std::vector<LamSeg> segs;
-  int n_fact = 0;
-  const int fb = popc(qmask);
-  // lambda tilings: groups in segment order (each segment: general groups,
-  // then fast records), each with its segment's region mask
-  std::vector<int> members;
-  std::vector<uint32_t> wb_of;
-  if (region_bits > 0) {
-    std::vector<uint32_t> xl;
-    for (int gi : members_in) xl.push_back(uint32_t(compress(gs[gi].x, qmask)));
-    for (const auto& sg : lambda_segments(xl, fb, region_bits)) {
-      LamSeg ls{};
-      ls.wb_mask = sg.first;
-      for (int pass = 0; pass < 2; ++pass)
-        for (int i : sg.second) {
-          const int gi = members_in[size_t(i)];
-          if ((use_fast && fast_group(gs[gi])) != (pass == 1)) continue;
-          members.push_back(gi);
-          wb_of.push_back(sg.first);
-          if (pass == 0) ls.g_count++;
-          else ls.f_count++;
-        }
-      segs.push_back(ls);
-    }
-    uint32_t g0 = 0, f0 = 0;
-    for (LamSeg& ls : segs) {
-      ls.g_first = g0;
-      ls.f_first = f0;
-      g0 += ls.g_count;
-      f0 += ls.f_count;
-    }
-  } else {
-    members = members_in;
-    wb_of.assign(members.size(), 0u);
-  }
-  for (size_t mi = 0; mi < members.size(); ++mi) {
-    const int gi = members[mi];
-    const uint32_t wb = wb_of[mi];
-    const HGroup& g = gs[gi];
-    if (use_fast && fast_group(g)) {
-      TFast f{};
-      f.x_loc = uint32_t(compress(g.x, qmask));
-      f.sup_mask = g.enumerated ? f.x_loc : (1u << local_pos(highest_bit(g.x), qmask));
-      f.n_rec = uint32_t(g.n_rec());
-      f.w_loc = uint32_t(compress(g.w[0] & qmask, qmask));
-      f.w_out = g.w[0] & ~qmask;
-      uint32_t free_bits = ((1u << fb) - 1u) & ~f.sup_mask & ~wb;
-      f.walk_log = uint32_t(popc(uint64_t(free_bits)));
-      uint32_t lane_p[kWalkLaneBits];
-      const uint32_t on_lanes = order_lane_bits(free_bits, lane_p);
-      for (int i = 0; i < kWalkLaneBits; ++i) {
-        f.dep_p[i] = lane_p[i];
-        f.dep_q[i] = lds_slot(lane_p[i]);
-        if (f.w_loc & lane_p[i]) f.wlane |= 1u << i;
-      }
-      f.hi_mask = free_bits & ~on_lanes;
-      f.sx = lds_slot(f.x_loc);
-      for (int r = 0; r < g.n_rec(); ++r) {
-        f.bits[r] = g.enumerated ? uint32_t(compress(g.rec_v[r], qmask)) : f.sup_mask;
-        f.sbits[r] = lds_slot(f.bits[r]);
-        f.pbits[r] = uint32_t(popc(uint64_t(f.bits[r] & f.w_loc)) & 1);
-        f.coef[2 * r] = g.t_re[r];
-        f.coef[2 * r + 1] = g.t_im[r];
-      }
-      tf.push_back(f);
-      continue;
-    }
-    TGroup d{};
-    d.x_loc = uint32_t(compress(g.x, qmask));
-    // enumerated bits S': the support, or the pivot alone
-    uint32_t smask;
-    if (g.enumerated) smask = d.x_loc;
-    else smask = 1u << local_pos(highest_bit(g.x), qmask);
-    d.sup_mask = smask;
-    const int NR = g.n_rec();
-    d.n_rec = uint32_t(NR);
-    d.rec_off = uint32_t(to.size());
-    d.n_sub = uint32_t(g.w.size());
-    d.sub_off = uint32_t(ts.size());
-    d.coef_off = uint32_t(co.size() / 2);
-    int k = 0;
-    for (uint32_t m = smask | wb; m; m &= m - 1) d.sins_pack |= uint64_t(__builtin_ctz(m)) << (4 * k++);
-    d.n_sins = uint32_t(k);
-    std::vector<uint32_t> rec_loc(NR);
-    for (int r = 0; r < NR; ++r) rec_loc[r] = g.enumerated ? uint32_t(compress(g.rec_v[r], qmask)) : smask;
-    for (int r = 0; r < NR; ++r) to.push_back(rec_loc[r]);
-    auto push_sub = [&](size_t w, uint32_t w_loc, uint64_t w_out) {
-      TSub sd{};
-      sd.w_loc = w_loc;
-      sd.w_out = w_out;
-      ts.push_back(sd);
-      for (int r = 0; r < NR; ++r) {
-        co.push_back(g.t_re[w * NR + r]);
-        co.push_back(g.t_im[w * NR + r]);
-      }
-    };
-    // factor when a reference mask w0 leaves every d_k = w_k ^ w0 with at
-    // most one bit (worth it from three subgroups on)
-    int ref = -1;
-    if (n_fact < kMaxFactored && NR <= kFactRecs && g.w.size() >= 3) {
-      for (size_t a = 0; a < g.w.size() && ref < 0; ++a) {
-        bool ok = true;
-        for (uint64_t w : g.w)
-          if (popc(w ^ g.w[a]) > 1) {
-            ok = false;
-            break;
-          }
-        if (ok) ref = int(a);
-      }
-    }
-    d.fact_idx = ~0u;
-    if (ref < 0) {
-      for (size_t w = 0; w < g.w.size(); ++w)
-        push_sub(w, uint32_t(compress(g.w[w] & qmask, qmask)), g.w[w] & ~qmask);
-    } else {
-      const uint64_t w0 = g.w[size_t(ref)];
-      d.fact_idx = uint32_t(n_fact++);
-      d.w0_loc = uint32_t(compress(w0 & qmask, qmask));
-      d.w0_out = w0 & ~qmask;
-      for (size_t w = 0; w < g.w.size(); ++w) {
-        const uint64_t dk = g.w[w] ^ w0;
-        if (dk & qmask) push_sub(w, uint32_t(compress(dk, qmask)), 0);
-      }
-      d.n_in = uint32_t(ts.size() - d.sub_off);
-      for (size_t w = 0; w < g.w.size(); ++w) {
-        const uint64_t dk = g.w[w] ^ w0;
-        if (!(dk & qmask)) push_sub(w, 0, dk);
-      }
-    }
-    tg.push_back(d);
-  }
-  auto align16 = [](size_t v) { return (v + 15) & ~size_t(15); };
-  TileHdr h{};
-  h.n_groups = uint32_t(tg.size());
-  h.n_fact = uint32_t(n_fact);
-  h.n_segs = uint32_t(segs.size());
-  size_t off = sizeof(TileHdr) + tg.size() * sizeof(TGroup);
-  h.off_rec = uint32_t(align16(off));
-  off = h.off_rec + to.size() * sizeof(uint32_t);
-  h.off_sub = uint32_t(align16(off));
-  off = h.off_sub + ts.size() * sizeof(TSub);
-  h.off_coef = uint32_t(align16(off));
-  off = h.off_coef + co.size() * sizeof(double);
-  h.off_fast = uint32_t(align16(off));
-  h.n_fast = uint32_t(tf.size());
-  off = h.off_fast + tf.size() * sizeof(TFast);
-  h.off_segs = uint32_t(align16(off));
-  off = h.off_segs + segs.size() * sizeof(LamSeg);
-  h.bytes = uint32_t(align16(off));
-  if (h.bytes > max_blob || tf.size() >= (1u << 20) || fb > 18) t.blob_overflow = true;
-  std::vector<unsigned char> bytes(h.bytes, 0);
-  std::memcpy(bytes.data(), &h, sizeof(h));
-  if (!tg.empty()) std::memcpy(bytes.data() + sizeof(TileHdr), tg.data(), tg.size() * sizeof(TGroup));
-  if (!to.empty()) std::memcpy(bytes.data() + h.off_rec, to.data(), to.size() * sizeof(uint32_t));
-  if (!ts.empty()) std::memcpy(bytes.data() + h.off_sub, ts.data(), ts.size() * sizeof(TSub));
-  if (!co.empty()) std::memcpy(bytes.data() + h.off_coef, co.data(), co.size() * sizeof(double));
-  if (!tf.empty()) std::memcpy(bytes.data() + h.off_fast, tf.data(), tf.size() * sizeof(TFast));
-  if (!segs.empty()) std::memcpy(bytes.data() + h.off_segs, segs.data(), segs.size() * sizeof(LamSeg));
-  t.blob_off.push_back(uint32_t(t.blob.size() / 2));
-  const size_t words = h.bytes / 8;
-  const size_t at = t.blob.size();
-  t.blob.resize(at + words);
-  std::memcpy(t.blob.data() + at, bytes.data(), h.bytes);
+  return sizeof(XBatch) + sizeof(XItem) + nr * sizeof(XRec) + g.w.size() * (sizeof(TSub) + nr * 16);
 }
 
 // ---------------------------------------------------------------------------
-// expectation blobs (projected sums; see XBatch)
+// projected-sum blobs of the expectation and lambda (see XBatch)
 // ---------------------------------------------------------------------------
 namespace {
 
@@ -1160,8 +957,7 @@ void pack_expect_blob(HTiling& t, const std::vector<HGroup>& gs, const std::vect
   std::memcpy(t.blob.data() + at, bytes.data(), h.bytes);
 }
 
-HTiling build_tiling(const std::vector<HGroup>& gs, int n, int b, int c, bool fast_records, size_t max_blob,
-                     int region_bits, int expect_waves) {
+HTiling build_tiling(const std::vector<HGroup>& gs, int n, int b, int c, size_t max_blob, int n_waves) {
   HTiling t;
   t.b = b;
   t.c = c;
@@ -1170,7 +966,7 @@ HTiling build_tiling(const std::vector<HGroup>& gs, int n, int b, int c, bool fa
   const int G = int(gs.size());
   std::vector<int> tile_of(G, -1);
   std::vector<uint64_t> tile_q;
-  const size_t fixed = sizeof(TileHdr) + 64;
+  const size_t fixed = sizeof(XHdr) + 64;
   if (n <= b) {
     tile_q.push_back(all);
     for (int g = 0; g < G; ++g)
@@ -1249,8 +1045,7 @@ HTiling build_tiling(const std::vector<HGroup>& gs, int n, int b, int c, bool fa
     size_t bytes = fixed;
     auto flush = [&]() {
       t.frames.push_back(make_frame(q, n, c));
-      if (expect_waves > 0) pack_expect_blob(t, gs, chunk, q, max_blob, expect_waves);
-      else pack_blob(t, gs, chunk, q, max_blob, fast_records, region_bits);
+      pack_expect_blob(t, gs, chunk, q, max_blob, n_waves);
       chunk.clear();
       bytes = fixed;
     };

@@ -142,26 +142,15 @@ struct HTiling {
   bool blob_overflow = false;            // a blob exceeded max_blob (never expected)
 };
 
-// expect_waves > 0: projected-sum blobs (XHdr; the expectation and the fast
-// lambda build), with per-wavefront work lists balanced for that many
-// wavefronts.  Otherwise TileHdr blobs for the reproducible lambda build:
-// fast_records packs one-subgroup groups as TFast records, each tile's groups
-// are reordered into LamSeg segments whose flip masks avoid region_bits frame
-// bits, and every walk (fast records and general groups) leaves its
-// segment's region bits out.
-HTiling build_tiling(const std::vector<HGroup>& gs, int n, int b, int c, bool fast_records, size_t max_blob,
-                     int region_bits = 0, int expect_waves = 0);
+// Frames (greedy cover of the groups' flip masks, then each group moved to
+// the least loaded frame that contains it) and one projected-sum blob (XHdr)
+// per frame and at most max_blob bytes, with per-wavefront work lists
+// balanced for n_waves wavefronts; groups that fit no b-bit frame become
+// whole-state groups.
+HTiling build_tiling(const std::vector<HGroup>& gs, int n, int b, int c, size_t max_blob, int n_waves);
 
 // One projected-sum blob (XHdr) of a tile's groups, appended to t.
 void pack_expect_blob(HTiling& t, const std::vector<HGroup>& gs, const std::vector<int>& members, uint64_t qmask,
                       size_t max_blob, int n_waves);
-
-// Greedy segmentation of one lambda tile's groups (frame-local flip masks):
-// repeatedly the region mask of region_bits frame bits that the most
-// remaining groups avoid (the highest such mask on ties); groups that no
-// mask avoids form segments of their own with mask 0.  Returns, in order,
-// (mask, member indices) per segment; members keep their relative order.
-std::vector<std::pair<uint32_t, std::vector<int>>> lambda_segments(const std::vector<uint32_t>& x_loc, int b,
-                                                                   int region_bits);
 
 }  // namespace q2sv

@@ -150,108 +150,15 @@ struct alignas(16) SubDesc {
 };
 
 // ---------------------------------------------------------------------------
-// Group tables of one Hamiltonian tile pass of the reproducible lambda build
-// (read in place through scalar loads).  A blob is a TileHdr followed by
-// TGroup records, record bits, TSub records, complex FP64 coefficients,
-// TFast records and LamSeg segments (offsets in bytes from the start of the
-// blob).
-//
-// Every non-diagonal group is treated as pairs (m, m' = m ^ x) with the pivot
-// (highest) bit of m clear.  "Enumerated bits" S' are the support of x (when
-// it has at most kMaxSup bits) or the pivot alone; a record fixes the bits of
-// m' on S', and each record gives two outputs: m' (coefficient conj(G)) and
-// m (coefficient G), where
+// Group tables of one Hamiltonian tile pass (read in place through scalar
+// loads).  Every non-diagonal group is treated as pairs (m, m' = m ^ x) with
+// the pivot (highest) bit of m clear.  "Enumerated bits" S' are the support
+// of x (when it has at most kMaxSup bits) or the pivot alone; a record fixes
+// the bits of m' on S', and each record gives two outputs: m' (coefficient
+// conj(G)) and m (coefficient G), where
 //   G(m) = sum_w (-1)^{|m' & w|} T_w[record]   and  (H_x psi)[m] = G(m) psi[m'].
+// Each subgroup w is a TSub; the blob layout is XHdr (below).
 // ---------------------------------------------------------------------------
-struct alignas(16) TileHdr {
-  uint32_t n_groups;
-  uint32_t off_rec;    // byte offset of the record bits (uint32 each)
-  uint32_t off_sub;    // byte offset of the TSub array
-  uint32_t off_coef;   // byte offset of the coefficients (double2)
-  uint32_t bytes;      // blob size in bytes (multiple of 16)
-  uint32_t n_fast;     // TFast records
-  uint32_t off_fast;   // byte offset of the TFast array
-  uint32_t pad0[2];
-  uint32_t n_fact;     // factored groups (fact_idx 0 .. n_fact - 1)
-  uint32_t n_segs;     // LamSeg records
-  uint32_t off_segs;   // byte offset of the LamSeg array
-};
-
-// A segment of a lambda tile pass: consecutive general groups and fast
-// records none of whose flip masks touches the frame bits wb_mask.  Every
-// pair (m, m ^ x) of such a group has both ends in one region (the
-// amplitudes whose wb_mask bits spell one value), so the wavefront that owns
-// the region adds both contributions with plain loads and stores: each
-// output's sum is formed by one wavefront in group order, with no atomics,
-// and is the same from run to run.  wb_mask = 0 (a group too wide for
-// regions) leaves the whole tile to wavefront 0.
-constexpr int kLambdaRegionBits = 3;
-struct alignas(16) LamSeg {
-  uint32_t g_first, g_count;   // general groups (TGroup indices)
-  uint32_t f_first, f_count;   // fast records (TFast indices)
-  uint32_t wb_mask;
-  uint32_t pad[3];
-};
-
-// Factored groups: when every subgroup mask is w_k = w0 ^ d_k with at most
-// one bit in d_k (the Jordan-Wigner hopping groups: one Z string, with or
-// without one more Z), G(m) = (-1)^{|m' & w0|} (B(base) + sum_in T_k
-// (-1)^{|m' & d_k|}): the subgroups whose d_k lies outside the frame (or is
-// empty) fold into B, one uniform value per tile-block and record, and only
-// the frame-local d_k stay in the per-pair sum.  Their TSub entries come
-// first (w_loc = the d_k bit, w_out = 0), then the folded ones (w_loc = 0,
-// w_out = the d_k bit or 0).
-constexpr int kMaxFactored = 64;  // per blob
-constexpr int kFactRecs = 4;
-
-// Every field is a full 32 or 64 bits: a kernel reading these tables from
-// global memory with a uniform index then gets scalar loads (a sub-dword
-// field would become a vector load, whose wait also drains the tile loads
-// in flight).
-struct alignas(8) TGroup {
-  uint32_t x_loc;      // frame-local flip mask
-  uint32_t sup_mask;   // frame-local enumerated bits S'
-  uint32_t rec_off;    // first record: frame-local bits of m' on S'
-  uint32_t n_rec;
-  uint32_t n_sub;      // subgroups
-  uint32_t sub_off;    // first TSub
-  uint32_t coef_off;   // first coefficient: coef[coef_off + sub * n_rec + rec]
-  uint32_t n_sins;     // zero insertions (S', and in lambda tilings the segment's region bits; ascending)
-  uint64_t sins_pack;  // their frame-local positions, four bits each
-  uint32_t fact_idx;   // factored group index, or ~0u
-  uint32_t n_in;       // factored: subgroups with a frame-local d_k (first n_in TSub)
-  uint32_t w0_loc;     // factored: w0, frame-local bits
-  uint32_t pad;
-  uint64_t w0_out;     // factored: w0, global bits outside the frame
-};
-
-// A group with one subgroup and at most four records, in one self-contained
-// record: G(m) = (-1)^{|m' & w|} T[record].  Its pairs are walked at
-// positions t = lane + 64 c of the bits outside S' (and, in lambda tilings,
-// outside the region bits of its segment): lane bit i
-// lands on frame-local bit dep_p[i] (LDS slot dep_q[i]; 0 past the walk's
-// width), the bits of c on hi_mask; wlane bit i is the w bit at dep_p[i].
-constexpr int kFastRecs = 4;
-struct alignas(16) TFast {
-  uint64_t w_out;      // w, global bits outside the frame
-  uint32_t x_loc;      // frame-local flip mask
-  uint32_t sup_mask;   // frame-local enumerated bits S'
-  uint32_t w_loc;      // w, frame-local bits
-  uint32_t n_rec;
-  uint32_t walk_log;   // 2^walk_log positions
-  uint32_t hi_mask;
-  uint32_t wlane;
-  uint32_t sx;         // LDS slot of x_loc
-  uint32_t pad[2];
-  uint32_t dep_p[kWalkLaneBits];
-  uint32_t dep_q[kWalkLaneBits];
-  uint32_t bits[kFastRecs];   // m' of each record on S'
-  uint32_t sbits[kFastRecs];  // LDS slot of bits
-  uint32_t pbits[kFastRecs];  // parity(bits & w_loc)
-  uint32_t pad2[kFastRecs];
-  double coef[2 * kFastRecs]; // T[record] (re, im)
-};
-
 struct alignas(16) TSub {
   uint64_t w_out;      // w, global bits outside the frame
   uint32_t w_loc;      // w, frame-local bits
@@ -259,7 +166,7 @@ struct alignas(16) TSub {
 };
 
 // ---------------------------------------------------------------------------
-// Expectation tile passes (projected sums).  For one group and record r the
+// Tile passes of the expectation and of lambda (projected sums).  For one group and record r the
 // pairs' contribution is Re sum_k T_k[r] S_k with
 //   S_k = sum_{m'} (-1)^{|m' & w_k|} conj(psi[m' ^ x]) psi[m'].
 // The free bits F of the group (frame bits outside S') are split into

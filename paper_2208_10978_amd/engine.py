@@ -71,9 +71,6 @@ class StateVector:
     def set_stream(self, stream):
         B.sv_set_stream(self.handle, stream)
 
-    def set_deterministic(self, on: bool):
-        B.sv_set_deterministic(self.handle, on)
-
     def free(self):
         if self.handle is not None:
             B.sv_free(self.handle)
@@ -111,11 +108,11 @@ class UCCSDEvaluator:
     real rotations such as UCCSD with a real Hamiltonian: the same results as
     "c128" with half the bytes).  ``renormalize`` rescales psi to unit norm
     (FP64 norm) after the forward sweep; it is on by default for complex64
-    amplitudes.  ``deterministic`` selects the reproducible lambda build
-    (bitwise equal results from run to run; see sv_set_deterministic)."""
+    amplitudes.  Results are bitwise equal from run to run (lambda = H psi
+    is summed in fixed point, the reductions in a fixed order)."""
 
     def __init__(self, ham: PauliSum, rot: RotationList, n_electrons: int, dtype: str = "c128",
-                 stream=None, renormalize=None, hamiltonian: "Hamiltonian" = None, deterministic: bool = False):
+                 stream=None, renormalize=None, hamiltonian: "Hamiltonian" = None):
         self.n = ham.n_qubits
         self.rot = rot
         self.hf = (1 << n_electrons) - 1
@@ -132,7 +129,6 @@ class UCCSDEvaluator:
         z = np.asarray(rot.z, dtype=np.uint64)
         self.real_circuit = bool(np.all(np.bitwise_count(x & z) % 2 == 1))
         B.sv_set_real_hint(self.psi.handle, self.real_circuit)
-        B.sv_set_deterministic(self.psi.handle, deterministic)
         # the rotation list resident in the library: split and scheduled once
         self.rh = B.sv_rotations_create(self.n, rot.x, rot.z, rot.param, rot.dphi_dtheta, rot.n_params)
         self.renormalize = (dtype == "c64") if renormalize is None else renormalize

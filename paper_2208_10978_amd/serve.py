@@ -10,7 +10,8 @@ at most ``max_heavy`` requests of ``heavy_qubits`` or more run at once: a
 request of 24 or 26 qubits fills the device by itself, so running two
 together only stretches both, while small requests fit beside one and need
 not queue behind it.  A request's plans depend only on the request and the
-executor uses the reproducible lambda build, so its result is bitwise the
+library's sums do not depend on the order of concurrent work (lambda in
+fixed point, reductions in a fixed order), so its result is bitwise the
 same alone and in any mix.
 
 A failed device (the library's sticky SV_EDEVICE, raised as DeviceFailure)
@@ -91,13 +92,12 @@ class GpuExecutor:
     loop and the device work of the others."""
 
     class Job:
-        def __init__(self, req, deterministic):
+        def __init__(self, req):
             import torch
             from .engine import UCCSDEvaluator
             self.stream = torch.cuda.Stream()
             with torch.cuda.stream(self.stream):
-                self.ev = UCCSDEvaluator(req.ham, req.rot, req.n_electrons, req.dtype, stream=self.stream,
-                                         deterministic=deterministic)
+                self.ev = UCCSDEvaluator(req.ham, req.rot, req.n_electrons, req.dtype, stream=self.stream)
                 e, g = self.ev.energy_and_grad(req.theta)
                 self.e_host = torch.empty(2, dtype=torch.float64, pin_memory=True)
                 self.g_host = torch.empty(req.rot.n_params, dtype=torch.float64, pin_memory=True)
@@ -124,11 +124,8 @@ class GpuExecutor:
         def result(self):
             return self.fut.result().result()
 
-    def __init__(self, launch_workers: int = 4, deterministic: bool = True):
-        # deterministic: the reproducible lambda build, so a request's result
-        # is bitwise the same alone or among concurrent requests
+    def __init__(self, launch_workers: int = 4):
         self.pool = cf.ThreadPoolExecutor(max_workers=launch_workers)
-        self.deterministic = deterministic
 
     def budget(self) -> int:
         import torch
@@ -136,7 +133,7 @@ class GpuExecutor:
         return int(free * 0.8)
 
     def launch(self, req):
-        return GpuExecutor.Pending(self.pool.submit(GpuExecutor.Job, req, self.deterministic))
+        return GpuExecutor.Pending(self.pool.submit(GpuExecutor.Job, req))
 
 
 class Server:

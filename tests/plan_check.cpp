@@ -1,10 +1,6 @@
 // Host checks of the tile-walk planning (CPU only, built with the host
 // compiler against plan.cpp).  For seeded Jordan-Wigner-shaped rotation lists
-// (forward, per-parameter and per-string reverse schedules) and a seeded
-// Pauli sum (reproducible lambda tilings with region segments), the
-// segments of a lambda tile must cover its groups in order with
-// flip masks that avoid their region bits (and general groups must insert
-// zeros at their support and region bits), and every walk must
+// (forward, per-parameter and per-string reverse schedules) every walk must
 //   * split the bits its run leaves free (not enumerated, not region bits)
 //     into at most six lane bits and the loop bits hi_mask, disjointly;
 //   * visit each of the 2^walk_log free-bit patterns exactly once;
@@ -13,13 +9,15 @@
 //     bank word: 16 lanes for 8-byte words, 8 lanes for 16-byte words, the
 //     latter weighted by one half) is the least over every ordered choice of
 //     free bits for lane bits 0..3;
-// and the expectation tilings must reproduce the expectation of seeded sums
-// when walked on the CPU as the tile kernel walks them (check_expect).
+// and the projected-sum tilings must reproduce the expectation and lambda of
+// seeded sums when walked on the CPU as the tile kernels walk them, lambda
+// also in the kernels' fixed point (check_expect).
 // Prints "ok ..." and exits 0, or names the first failure and exits 1.
 #include <algorithm>
 #include <cmath>
 #include <cstdio>
 #include <cstdlib>
+#include <cstring>
 #include <map>
 #include <set>
 #include <vector>
@@ -267,87 +265,6 @@ static void check_rotations(int n, int n_occ, long* nw, double* cs, double* bs) 
   }
 }
 
-static void check_lambda(int n, int b, long* nw, double* cs, double* bs, int rb) {
-  // one- and two-body shaped terms: x on 0, 2 or 4 orbitals, Z chains, odd Y
-  std::vector<PauliIn> p;
-  std::vector<double> coef;
-  for (int t = 0; t < 6000; ++t) {
-    const int kind = int(next_u64() % 3);
-    uint64_t x = 0, z = 0;
-    if (kind == 0) {
-      z = next_u64() & next_u64() & ((uint64_t(1) << n) - 1);
-    } else {
-      const int nx = kind == 1 ? 2 : 4;
-      int idx[4];
-      for (int i = 0; i < nx;) {
-        const int q = int(next_u64() % uint64_t(n));
-        if (x & (uint64_t(1) << q)) continue;
-        x |= uint64_t(1) << q;
-        idx[i++] = q;
-      }
-      std::sort(idx, idx + nx);
-      for (int pr = 0; pr < nx; pr += 2)
-        for (int q = idx[pr] + 1; q < idx[pr + 1]; ++q) z |= uint64_t(1) << q;
-      uint32_t ys = 0;
-      while (!(__builtin_popcount(ys) & 1)) ys = uint32_t(next_u64() % (1u << nx));
-      for (int i = 0; i < nx; ++i)
-        if ((ys >> i) & 1u) z ^= uint64_t(1) << idx[i];
-    }
-    p.push_back({x, z});
-    coef.push_back(2.0 * next_unit() - 1.0);
-  }
-  std::string err;
-  const std::vector<HGroup> gs = build_groups(p.data(), coef.data(), int64_t(p.size()), &err);
-  CHECK(err.empty(), "build_groups: %s", err.c_str());
-  std::vector<HGroup> nd;
-  for (const HGroup& g : gs)
-    if (!g.diag) nd.push_back(g);
-  const HTiling T = build_tiling(nd, n, b, 3, true, size_t(1) << 24, rb);
-  long n_fast = 0, n_seg = 0;
-  for (size_t t = 0; t < T.frames.size(); ++t) {
-    const char* blob = reinterpret_cast<const char*>(T.blob.data() + 2 * size_t(T.blob_off[t]));
-    const TileHdr* h = reinterpret_cast<const TileHdr*>(blob);
-    const TFast* fs = reinterpret_cast<const TFast*>(blob + h->off_fast);
-    const TGroup* tg = reinterpret_cast<const TGroup*>(blob + sizeof(TileHdr));
-    const LamSeg* sg = reinterpret_cast<const LamSeg*>(blob + h->off_segs);
-    // segments cover the groups and fast records in order; every member's
-    // flip mask avoids the segment's region bits
-    uint32_t g_next = 0, f_next = 0;
-    for (uint32_t si = 0; si < h->n_segs; ++si, ++n_seg) {
-      const LamSeg& S = sg[si];
-      const int nb = __builtin_popcount(S.wb_mask);
-      CHECK(nb == 0 || nb == kLambdaRegionBits, "segment region mask %x", S.wb_mask);
-      CHECK(S.wb_mask < (1u << b), "segment region mask %x outside the frame", S.wb_mask);
-      CHECK(S.g_first == g_next && S.f_first == f_next, "segments out of order");
-      CHECK(nb > 0 || S.g_count + S.f_count == 1, "a maskless segment holds %u groups", S.g_count + S.f_count);
-      g_next += S.g_count;
-      f_next += S.f_count;
-      for (uint32_t i = S.g_first; i < S.g_first + S.g_count; ++i) {
-        CHECK(!(tg[i].x_loc & S.wb_mask), "group x %x touches region bits %x", tg[i].x_loc, S.wb_mask);
-        // zero insertions: S' and the region bits, ascending
-        uint32_t want = tg[i].sup_mask | S.wb_mask, got = 0, prev = 0;
-        for (uint32_t j = 0; j < tg[i].n_sins; ++j) {
-          const uint32_t pos = uint32_t(tg[i].sins_pack >> (4 * j)) & 15u;
-          CHECK(j == 0 || pos > prev, "insertions not ascending");
-          prev = pos;
-          got |= 1u << pos;
-        }
-        CHECK(got == want, "insertions %x, want %x", got, want);
-      }
-      for (uint32_t i = S.f_first; i < S.f_first + S.f_count; ++i, ++n_fast) {
-        const TFast& f = fs[i];
-        CHECK(!(f.x_loc & S.wb_mask), "fast x %x touches region bits %x", f.x_loc, S.wb_mask);
-        const uint32_t free_bits = ((1u << b) - 1u) & ~f.sup_mask & ~S.wb_mask;
-        check_walk("lambda", free_bits, f.walk_log, f.dep_p, f.dep_q, f.hi_mask, f.w_loc, f.wlane, nw, cs, bs);
-      }
-    }
-    CHECK(g_next == h->n_groups && f_next == h->n_fast, "segments cover %u/%u groups, %u/%u fast records", g_next,
-          h->n_groups, f_next, h->n_fast);
-  }
-  CHECK(n_fast > 0, "no fast records");
-  CHECK(n_seg > 0, "no segments");
-}
-
 // Projected-sum tilings (expectation and fast lambda): a CPU walk of every
 // work item of every blob, the way the tile kernels take it (lane deposit,
 // register patterns, chunk words and their signs, Walsh-Hadamard transform
@@ -355,11 +272,28 @@ static void check_lambda(int n, int b, long* nw, double* cs, double* bs, int rb)
 //   sum_t c_t <psi|P_t|psi>,  <psi|P|psi> = sum_m conj(psi[m]) i^{|x&z|} (-1)^{|(m^x)&z|} psi[m^x],
 // and lambda = sum_t c_t P_t psi element by element, both summed directly
 // over the terms, on a seeded random state; and each batch's items must
-// cover its records x chunks exactly once.  The sums mix random
+// cover its records x chunks exactly once.  Lambda is also summed as the
+// kernels sum it, in 64-bit fixed point per tile at the scale 2^s,
+// s = fx_shift - e_psi (e_psi: exponent of the tile's largest |re| + |im|):
+// every term must stay below 2^50 (the range of the rounding by 1.5 * 2^52)
+// and every slot's sum of |terms| below 2^62, and the result must match.  The sums mix random
 // strings of weight <= 4, Jordan-Wigner hopping strings with number-operator
 // variants (many subgroups over a Z chain) and strings whose support is too
 // wide to enumerate.
 static long g_x_batches = 0, g_x_multi = 0;
+static double g_fx_term = 0.0;  // largest |term| * 2^s over 2^50
+static double g_fx_diff = 0.0;  // largest |fixed-point lambda - H psi| / sum |c|
+
+// One fixed-point term as the kernels form it: fma(a, b, fma(c, d, M)) with
+// M = 1.5 * 2^52, read back as an integer.
+static int64_t fx_term(double a, double b, double c, double d) {
+  const double M = 6755399441055744.0;
+  const double t = std::fma(a, b, std::fma(c, d, M));
+  int64_t bits, mb;
+  std::memcpy(&bits, &t, 8);
+  std::memcpy(&mb, &M, 8);
+  return bits - mb;
+}
 static double g_x_diff = 0.0;  // largest |walk - direct| / (sum |c| <psi|psi>)
 static void check_expect(int n, int b, int c, int n_terms) {
   const uint64_t all = (uint64_t(1) << n) - 1;
@@ -418,6 +352,7 @@ static void check_expect(int n, int b, int c, int n_terms) {
     }
   }
   std::vector<double> lr_got(pr.size(), 0.0), li_got(pr.size(), 0.0);
+  std::vector<double> lr_fx(pr.size(), 0.0), li_fx(pr.size(), 0.0);
   double want = 0.0, scale = 0.0;
   for (size_t t = 0; t < p.size(); ++t) {
     double re = 0.0, im = 0.0;  // sum_m conj(psi[m]) (-1)^{|(m^x)&z|} psi[m^x]
@@ -436,7 +371,7 @@ static void check_expect(int n, int b, int c, int n_terms) {
   const std::vector<HGroup> gs = build_groups(p.data(), coef.data(), int64_t(p.size()), &err);
   CHECK(err.empty(), "build_groups: %s", err.c_str());
   const int NW = 16;
-  const HTiling T = build_tiling(gs, n, b, c, true, size_t(1) << 24, 0, NW);
+  const HTiling T = build_tiling(gs, n, b, c, size_t(1) << 24, NW);
   CHECK(!T.blob_overflow, "expectation blob overflow");
   CHECK(T.groups.empty(), "%zu whole-state groups", T.groups.size());
   double got = 0.0;
@@ -489,6 +424,20 @@ static void check_expect(int n, int b, int c, int n_terms) {
         ti[lds_slot(l)] = pi[g];
         glob[lds_slot(l)] = g;
       }
+      // the tile's fixed-point scale and accumulators
+      int e_psi = -4000;
+      for (uint32_t l = 0; l < (1u << nb); ++l) {
+        const double a = std::fabs(tr[l]) + std::fabs(ti[l]);
+        int e = 0;
+        if (a > 0.0) {
+          std::frexp(a, &e);
+          e_psi = std::max(e_psi, e);
+        }
+      }
+      const int sh = std::min(std::max(h->fx_shift - e_psi, -1000), 1000);
+      const double sc = std::ldexp(1.0, sh);
+      std::vector<int64_t> ar_fx(size_t(1) << nb, 0), ai_fx(size_t(1) << nb, 0);
+      std::vector<double> mag(size_t(1) << nb, 0.0);  // sum of |terms| per slot, scaled
       for (int w = 0; w < NW; ++w)
         for (uint32_t i = start[w]; i < start[w + 1]; ++i) {
           const XItem& it = items[i];
@@ -575,11 +524,31 @@ static void check_expect(int n, int b, int c, int n_terms) {
                   li_got[gm] += g_r * ti[s2] + g_i * tr[s2];
                   lr_got[gp] += g_r * tr[s1] + g_i * ti[s1];  // lam[m'] += conj(G) psi[m]
                   li_got[gp] += g_r * ti[s1] - g_i * tr[s1];
+                  // the same in fixed point
+                  const double fr_ = g_r * sc, fi_ = g_i * sc;
+                  const double t1 = std::fabs(fr_) * (std::fabs(tr[s2]) + std::fabs(ti[s2]));
+                  const double t2 = std::fabs(fr_) * (std::fabs(tr[s1]) + std::fabs(ti[s1]));
+                  const double t3 = std::fabs(fi_) * (std::fabs(tr[s2]) + std::fabs(ti[s2]));
+                  const double t4 = std::fabs(fi_) * (std::fabs(tr[s1]) + std::fabs(ti[s1]));
+                  const double tm = std::max(std::max(t1, t2), std::max(t3, t4));
+                  g_fx_term = std::max(g_fx_term, tm / std::ldexp(1.0, 50));
+                  CHECK(tm < std::ldexp(1.0, 50), "fixed-point term %.3g reaches 2^50", tm);
+                  mag[s1] += t1 + t3;
+                  mag[s2] += t2 + t4;
+                  ar_fx[s1] += fx_term(fr_, tr[s2], -fi_, ti[s2]);
+                  ai_fx[s1] += fx_term(fr_, ti[s2], fi_, tr[s2]);
+                  ar_fx[s2] += fx_term(fr_, tr[s1], fi_, ti[s1]);
+                  ai_fx[s2] += fx_term(fr_, ti[s1], -fi_, tr[s1]);
                 }
               }
             }
           }
         }
+      for (uint32_t l = 0; l < (1u << nb); ++l) {
+        CHECK(mag[l] < std::ldexp(1.0, 62), "fixed-point sum bound %.3g reaches 2^62", mag[l]);
+        lr_fx[glob[l]] += std::ldexp(double(ar_fx[l]), -sh);
+        li_fx[glob[l]] += std::ldexp(double(ai_fx[l]), -sh);
+      }
     }
   }
   got *= 2.0;
@@ -589,6 +558,11 @@ static void check_expect(int n, int b, int c, int n_terms) {
   for (size_t m = 0; m < pr.size(); ++m)
     lmax = std::max(lmax, std::hypot(lr_got[m] - lr_want[m], li_got[m] - li_want[m]));
   CHECK(lmax <= 1e-12 * scale, "lambda n=%d b=%d: blob walk differs from H psi by %.3g", n, b, lmax);
+  double fmax = 0.0;
+  for (size_t m = 0; m < pr.size(); ++m)
+    fmax = std::max(fmax, std::hypot(lr_fx[m] - lr_want[m], li_fx[m] - li_want[m]));
+  CHECK(fmax <= 1e-12 * scale, "lambda n=%d b=%d: fixed-point walk differs from H psi by %.3g", n, b, fmax);
+  g_fx_diff = std::max(g_fx_diff, fmax / scale);
   g_x_diff = std::max(g_x_diff, lmax / scale);
   CHECK(multi > 0 || n_terms < 200, "no multi-class batch (n=%d)", n);
   g_x_batches += batches;
@@ -638,8 +612,6 @@ int main() {
   check_rotations(18, 6, &nw, &cs, &bs);
   check_rotations(14, 4, &nw, &cs, &bs);
   check_random_schedule();
-  check_lambda(18, 12, &nw, &cs, &bs, kLambdaRegionBits);  // lambda, complex build
-  check_lambda(18, 13, &nw, &cs, &bs, kLambdaRegionBits);  // lambda, real-part tiles
   check_expect(12, 8, 3, 400);                             // several frames and tiles
   check_expect(9, 14, 3, 150);                             // one frame smaller than a tile
   check_expect(14, 10, 4, 600);
@@ -648,7 +620,8 @@ int main() {
     return 1;
   }
   std::printf("ok %ld walks, mean cost %.4f (least %.4f), %ld run pairs reordered; expectation: %ld batches (%ld "
-              "multi-class), relative difference %.3g\n",
-              nw, cs / double(nw), bs / double(nw), g_moved, g_x_batches, g_x_multi, g_x_diff);
+              "multi-class), relative difference %.3g; fixed-point lambda: largest term %.3g of 2^50, relative "
+              "difference %.3g\n",
+              nw, cs / double(nw), bs / double(nw), g_moved, g_x_batches, g_x_multi, g_x_diff, g_fx_term, g_fx_diff);
   return 0;
 }

@@ -410,24 +410,21 @@ def test_real_hint_at_21_qubits(case):
 
 @pytest.mark.parametrize("n,dtype", [(14, "c128"), (22, "c128"), (22, "c64"), (22, "r64")])
 def test_lambda_and_gradient_are_bitwise_reproducible(n, dtype):
-    """lambda = H psi, the energy and the per-rotation gradient of two
-    adjoint calls on the same input are bitwise equal, in both builds: the
-    reproducible one (sv_set_deterministic; every element of lambda summed
-    by one wavefront in group order) and the fast one (fixed-point sums with
-    integer atomic adds, whose order does not matter); every reduction has a
-    fixed order.  The two builds agree to FP64 rounding.  14 qubits takes
-    the complex build, 22 qubits the real-part tiles (a UCCSD state is
-    real)."""
-    announce(f"lambda twice, bitwise: {n} qubits {dtype}")
+    """lambda = H psi, the energy and the per-rotation gradient of repeated
+    adjoint calls on the same input are bitwise equal, on one pair of states
+    and on a second pair: lambda's sums are fixed point (integer atomic
+    adds, whose order does not matter) and every reduction has a fixed
+    order.  14 qubits takes the complex build, 22 qubits the real-part tiles
+    (a UCCSD state is real)."""
+    announce(f"lambda thrice, bitwise: {n} qubits {dtype}")
     ne = n // 2
     h, eri = synthetic_integrals(n, 1000 + n)
     ham = jordan_wigner(h, eri)
     rot = uccsd_rotations(n, ne, ORDER)
     phi = rot.angles(uniform_amplitudes(rot.n_params, 0.1, 5300 + n))
-    psi = StateVector(n, dtype); lam = StateVector(n, dtype)
+    states = [(StateVector(n, dtype), StateVector(n, dtype)), (StateVector(n, dtype), StateVector(n, dtype))]
     out = []
-    for det in (True, True, False, False):
-        psi.set_deterministic(det)
+    for psi, lam in (states[0], states[0], states[1]):
         energy = torch.empty(2, dtype=torch.float64, device="cuda")
         grad = torch.empty(len(phi), dtype=torch.float64, device="cuda")
         psi.prepare_hf((1 << ne) - 1)
@@ -435,16 +432,55 @@ def test_lambda_and_gradient_are_bitwise_reproducible(n, dtype):
         B.sv_adjoint_grad(psi.handle, lam.handle, ham.x, ham.z, ham.c, rot.x, rot.z, phi, energy, grad)
         torch.cuda.synchronize()
         out.append((energy.clone(), grad.clone(), lam.amps.clone()))
-    psi.free(); lam.free()
-    (e1, g1, l1), (e2, g2, l2), (e3, g3, l3), (e4, g4, l4) = out
-    assert torch.equal(e1, e2)
-    assert torch.equal(g1, g2)
-    assert torch.equal(l1, l2)
-    assert torch.equal(e3, e4)
-    assert torch.equal(g3, g4)
-    assert torch.equal(l3, l4)
+    for psi, lam in states:
+        psi.free(); lam.free()
+    (e1, g1, l1) = out[0]
     assert torch.isfinite(g1).all() and float(g1.abs().max()) > 0.0
-    # the two builds to the rounding of the sums
-    tol = 1e-12 if dtype != "c64" else 1e-5
-    assert abs(float(e3[0] - e1[0])) <= tol * abs(float(e1[0]))
-    assert float((g3 - g1).abs().max()) <= tol * max(1.0, float(g1.abs().max()))
+    for e2, g2, l2 in out[1:]:
+        assert torch.equal(e1, e2)
+        assert torch.equal(g1, g2)
+        assert torch.equal(l1, l2)
+
+
+@pytest.mark.parametrize("n,dtype,k", [(14, "c128", 300), (14, "c128", -300), (22, "r64", 300), (22, "r64", -300),
+                                       (14, "c64", 20), (14, "c64", -20)])
+def test_lambda_fixed_point_follows_the_state_scale(n, dtype, k):
+    """The fixed-point sums of the fast lambda build take their scale from
+    each tile's largest |psi|, so scaling psi by 2^k (exact in floating
+    point) scales lambda by exactly 2^k and the gradient by 4^k, bit for bit,
+    and leaves the energy <psi|H|psi>/<psi|psi> bitwise unchanged, far from
+    unit norm in both directions (complex64 lambda, stored in FP32 after the
+    reverse sweep: to one FP32 unit where it is a normal number)."""
+    announce(f"lambda under psi * 2^{k}: {n} qubits {dtype}")
+    ne = n // 2
+    h, eri = synthetic_integrals(n, 1000 + n)
+    ham = jordan_wigner(h, eri)
+    rot = uccsd_rotations(n, ne, ORDER)
+    phi = rot.angles(uniform_amplitudes(rot.n_params, 0.1, 5400 + n))
+    psi = StateVector(n, dtype); lam = StateVector(n, dtype)
+    out = []
+    for scale in (1.0, 2.0 ** k):
+        energy = torch.empty(2, dtype=torch.float64, device="cuda")
+        grad = torch.empty(len(phi), dtype=torch.float64, device="cuda")
+        psi.prepare_hf((1 << ne) - 1)
+        psi.apply_rotations(rot.x, rot.z, phi)
+        psi.amps.mul_(scale)
+        B.sv_adjoint_grad(psi.handle, lam.handle, ham.x, ham.z, ham.c, rot.x, rot.z, phi, energy, grad)
+        torch.cuda.synchronize()
+        out.append((energy.clone(), grad.clone(), lam.amps.clone()))
+    psi.free(); lam.free()
+    (e1, g1, l1), (e2, g2, l2) = out
+    assert float(g1.abs().max()) > 0.0
+    assert torch.equal(e2[0], e1[0])
+    assert torch.equal(e2[1], e1[1] * 4.0 ** k)
+    assert torch.equal(g2, g1 * 4.0 ** k)
+    if dtype == "c64":
+        # complex64 lambda after the FP32 reverse sweep: subnormal FP32
+        # intermediates (tiny amplitudes) round differently at each scale, so
+        # to one FP32 unit where the value is well inside the normal range
+        a, b = torch.view_as_real(l1).double(), torch.view_as_real(l2).double()
+        normal = a.abs() >= 2.0 ** -60  # far above the subnormal range at both scales
+        assert int(normal.sum()) >= 1000
+        assert torch.all((b[normal] - a[normal] * 2.0 ** k).abs() <= 2.0 ** -23 * (a[normal] * 2.0 ** k).abs())
+    else:
+        assert torch.equal(l2, l1 * 2.0 ** k)

@@ -20,7 +20,6 @@ def _planned_each_call(ham, rot, ne, dtype, theta):
     n = ham.n_qubits
     H = Hamiltonian(ham)
     psi, lam = StateVector(n, dtype), StateVector(n, dtype)
-    B.sv_set_deterministic(psi.handle, True)
     phi = rot.angles(theta)
     psi.prepare_hf((1 << ne) - 1)
     psi.apply_rotations(rot.x, rot.z, phi)
@@ -41,7 +40,7 @@ def _planned_each_call(ham, rot, ne, dtype, theta):
 @pytest.mark.parametrize("dtype", ["c128", "c64", "r64"])
 def test_resident_list_matches_planning_each_call(n, dtype):
     """Same plan, same arithmetic: the state, energy and gradient are bitwise
-    equal (reproducible lambda build on both sides), call after call on one
+    equal (lambda in fixed point on both sides), call after call on one
     handle: all amplitudes nonzero, then some exactly zero (their runs have no
     forward records, so the kept schedule is made again), then nonzero again."""
     announce(f"resident rotations n={n} {dtype}")
@@ -52,7 +51,7 @@ def test_resident_list_matches_planning_each_call(n, dtype):
     base = np.asarray(uniform_amplitudes(rot.n_params, 0.1, 7000 + n))
     zeros = base.copy()
     zeros[::5] = 0.0
-    ev = UCCSDEvaluator(ham, rot, ne, dtype, deterministic=True)
+    ev = UCCSDEvaluator(ham, rot, ne, dtype)
     for theta in (base, zeros, 0.5 * base):
         psi = ev.state(theta)
         e, g = ev.energy_and_grad(theta)
@@ -81,7 +80,6 @@ def test_one_handle_serves_two_amplitude_types():
     res = {}
     for dt in ("c128", "r64"):
         psi, lam = StateVector(n, dt), StateVector(n, dt)
-        B.sv_set_deterministic(psi.handle, True)
         psi.prepare_hf((1 << ne) - 1)
         B.sv_apply_rotations_h(psi.handle, r, theta)
         e = torch.empty(2, dtype=torch.float64, device="cuda")
@@ -90,7 +88,7 @@ def test_one_handle_serves_two_amplitude_types():
         torch.cuda.synchronize()
         res[dt] = (e.cpu().numpy(), g.cpu().numpy())
         psi.free(); lam.free()
-        ev = UCCSDEvaluator(ham, rot, ne, dt, deterministic=True)
+        ev = UCCSDEvaluator(ham, rot, ne, dt)
         e2, g2 = ev.energy_and_grad(theta)
         torch.cuda.synchronize()
         assert np.array_equal(res[dt][0], e2.cpu().numpy()) and np.array_equal(res[dt][1], g2.cpu().numpy())
