@@ -282,6 +282,14 @@ __device__ __forceinline__ void lambda_tiles(const T* __restrict__ psi, T* __res
   auto result = [&](double start, unsigned long long acc, double unit) {
     return fma(double(static_cast<long long>(acc)), unit, start);
   };
+  // the thread index, opaque to the optimiser: the LDS slots of the staged
+  // values are recomputed where they are used instead of being held across
+  // the tile loop (where they would spill)
+  auto tid_here = []() {
+    uint32_t t = threadIdx.x;
+    asm volatile("" : "+v"(t));
+    return t;
+  };
 
   Stage<T, PER> rp;
   Stage<T, PER> rl;
@@ -308,15 +316,15 @@ __device__ __forceinline__ void lambda_tiles(const T* __restrict__ psi, T* __res
       }
     };
     auto put = [&]() {
-      if constexpr (kRealTile) {
+      const uint32_t tid = tid_here();
 #pragma unroll
-        for (int i = 0; i < PER; ++i) tp[lds_swz(threadIdx.x + uint32_t(i) * NT)].x = double(rp.re[i]);
-      } else {
-        tile_put_full<T, PER, NT>(tp, rp);
+      for (int i = 0; i < PER; ++i) {
+        if constexpr (kRealTile) tp[lds_swz(tid + uint32_t(i) * NT)].x = double(rp.re[i]);
+        else tp[lds_swz(tid + uint32_t(i) * NT)] = cmake<T>(rp.re[i], rp.im[i]);
       }
 #pragma unroll
       for (int i = 0; i < PER; ++i) {
-        const uint32_t sl = lds_swz(threadIdx.x + uint32_t(i) * NT);
+        const uint32_t sl = lds_swz(tid + uint32_t(i) * NT);
         ir[i] = MODE == 1 ? rd[i] * (double)rp.re[i] : (double)rl.re[i];
         ii[i] = REAL ? 0.0 : MODE == 1 ? rd[i] * (double)rp.im[i] : (double)rl.im[i];
         alr[sl] = 0ull;
@@ -337,9 +345,10 @@ __device__ __forceinline__ void lambda_tiles(const T* __restrict__ psi, T* __res
       apply_groups(base, sh);
       Stage<T, PER> out;
       const double unit = __builtin_ldexp(1.0, -sh);
+      const uint32_t tid = tid_here();
 #pragma unroll
       for (int i = 0; i < PER; ++i) {
-        const uint32_t sl = lds_swz(threadIdx.x + uint32_t(i) * NT);
+        const uint32_t sl = lds_swz(tid + uint32_t(i) * NT);
         out.re[i] = R(result(ir[i], alr[sl], unit));
         out.im[i] = REAL ? R(0) : R(result(ii[i], ali[sl], unit));
       }
