@@ -131,9 +131,9 @@ int sv_expect_pauli_sum(sv_state *s, const sv_pauli *p, const double *coef, int6
                         double *out_dev);
 
 /* Reverse-mode gradient (Algorithm 1) of E = <psi|H|psi> with respect to
- * every rotation angle.  lambda = H psi is summed in 64-bit fixed point per
- * tile (each term rounded at a power-of-two scale set by the tile's largest
- * |psi|, about 2^-50 of the largest term), so the result does not depend on
+ * every rotation angle.  lambda = H psi is summed in 64-bit fixed point
+ * (each term rounded at a power-of-two scale set by psi's largest amplitude,
+ * about 2^-50 of the largest term a pass can form), so the result does not depend on
  * the order in which concurrent wavefronts add: lambda, the energy and the
  * gradient are bitwise equal from run to run, and a request alone or among
  * concurrent ones.

@@ -796,14 +796,21 @@ static int lambda_impl(sv_state* s, sv_state* lam, sv_hamiltonian* h, double* en
   if (rc) return rc;
   const HTiling& ht = t->host;
   const int T = int(ht.frames.size());
+  // psi's largest amplitude exponent, per block: the fixed-point scale of the
+  // tile passes (the third row of the scratch is free until the dot below)
+  double* ep = part + 2 * size_t(gdot);
+  if (T > 0) {
+    ProfScope prof(s->stream, kPDot, s->bytes());
+    HIP_TRY(launch_amp_exponent(s->dtype, s->amps, s->amp_count(), gdot, ep, s->stream));
+  }
   for (int tt = 0; tt < T; ++tt) {
     const FrameDesc& fr = ht.frames[tt];
     const uint64_t n_tb = uint64_t(1) << fr.n_comp;
     const int grid = int(std::min<uint64_t>(n_tb, uint64_t(num_cus())));
     ProfScope prof(s->stream, kPTileHLam, (tt == 0 ? (diag ? 2.5 : 2.0) : 3.0) * s->bytes());
     const hipError_t e = launch_tile_lambda(s->dtype, tt == 0, real, s->amps, lam->amps, diag, fr,
-                                            dptr<uint4>(t->buf, t->o_blob) + ht.blob_off[tt], n_tb, grid, guard,
-                                            s->stream);
+                                            dptr<uint4>(t->buf, t->o_blob) + ht.blob_off[tt], n_tb, grid, guard, ep,
+                                            gdot, s->stream);
     if (e != hipSuccess) return device_fail(std::string("lambda tile: ") + hipGetErrorString(e));
   }
   const int gfull = full_grid(s->amp_count() / 2);

@@ -222,13 +222,30 @@ template <> struct Real<RealSlot> { using type = double; };
 // not depend on the order in which the updates of different wavefronts
 // arrive, so lambda is the same from run to run.
 // ---------------------------------------------------------------------------
+// The fixed-point exponent s of a lambda launch: the blob's fx_shift minus
+// the largest exponent of |re| + |im| over psi (launch_amp_exponent's
+// partials ep[0..n_ep)), clamped; with it no term reaches 2^50 and no slot's
+// sum 2^62.  red: NT / 64 ints of LDS.  One barrier.
+template <int NT>
+__device__ __forceinline__ int lambda_shift(const uint4* __restrict__ blob, const double* __restrict__ ep, int n_ep,
+                                            int* red) {
+  int e = kFxNone;
+  for (int i = int(threadIdx.x); i < n_ep; i += NT) e = max(e, int(ep[i]));
+  e = wave_max_i32(e);
+  if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = e;
+  __syncthreads();
+  int m = red[0];
+#pragma unroll
+  for (int w = 1; w < NT / 64; ++w) m = max(m, red[w]);
+  const int sh = reinterpret_cast<const XHdr*>(blob)->fx_shift - m;
+  return __builtin_amdgcn_readfirstlane(min(max(sh, -1000), 1000));
+}
+
 // The tile passes of a lambda build, on the block's LDS arrays: tp, the psi
 // tile of TT slots; alr, ali, 64-bit fixed-point accumulators of lambda's
 // real and imaginary parts, cleared per tile, while the tile's starting
 // values (diag psi, or the lambda of earlier passes) wait in registers; the
-// result is start + accumulator * 2^-s.  The scale 2^s of a tile comes from
-// the blob's fx_shift and the exponent of the tile's largest |psi| (sexp:
-// one entry per wavefront), so that no term reaches 2^50 and no sum 2^62.
+// result is start + accumulator * 2^-sh, sh from lambda_shift.
 // REAL: psi and every coefficient are real, so only real parts are read and
 // accumulated and ali is not used; TT = RealSlot keeps only the real parts
 // of psi in the tile.
@@ -236,7 +253,7 @@ template <typename T, int B, int NT, int MODE, bool FULL, bool REAL, typename TT
 __device__ __forceinline__ void lambda_tiles(const T* __restrict__ psi, T* __restrict__ lam,
                                              const double* __restrict__ diag, const FrameDesc& fr,
                                              const uint4* __restrict__ blob, uint64_t n_tb, TT* tp,
-                                             unsigned long long* alr, unsigned long long* ali, int* sexp) {
+                                             unsigned long long* alr, unsigned long long* ali, int sh) {
   static_assert(REAL || std::is_same<TT, T>::value, "a real-part tile needs the real build");
   using R = typename Real<T>::type;
   constexpr bool kRealTile = std::is_same<TT, RealSlot>::value;
@@ -256,27 +273,6 @@ __device__ __forceinline__ void lambda_tiles(const T* __restrict__ psi, T* __res
     for (uint32_t i = i0; i < i1; i += step)
       x_lambda_item<TT, REAL>(xv, xv.items[i], base, tp, alr, ali, sc, uint32_t(lane));
     __syncthreads();
-  };
-  // the fixed-point exponent s of the tile in place (after its sexp entries
-  // are written and a barrier has passed)
-  auto tile_shift = [&]() -> int {
-    int e = sexp[0];
-#pragma unroll
-    for (int w = 1; w < NW; ++w) e = max(e, sexp[w]);
-    const int sh = reinterpret_cast<const XHdr*>(blob)->fx_shift - e;
-    return __builtin_amdgcn_readfirstlane(min(max(sh, -1000), 1000));
-  };
-  // this wavefront's part of a tile's largest |psi|, from the staged values
-  auto note_exp = [&](const Stage<T, PER>& st, int n_valid) {
-    int e = kFxNone;
-#pragma unroll
-    for (int i = 0; i < PER; ++i)
-      if (i < n_valid) {
-        const double a = REAL ? fabs((double)st.re[i]) : fabs((double)st.re[i]) + fabs((double)st.im[i]);
-        e = max(e, fx_exp(a));
-      }
-    e = wave_max_i32(e);
-    if (lane == 0) sexp[wave] = e;
   };
   // a finished slot: start + accumulator * unit
   auto result = [&](double start, unsigned long long acc, double unit) {
@@ -330,7 +326,6 @@ __device__ __forceinline__ void lambda_tiles(const T* __restrict__ psi, T* __res
         alr[sl] = 0ull;
         if (!REAL) ali[sl] = 0ull;
       }
-      note_exp(rp, PER);
     };
     if (tb < n_tb) {
       fetch(frame_base(fr, tb));
@@ -340,7 +335,6 @@ __device__ __forceinline__ void lambda_tiles(const T* __restrict__ psi, T* __res
     for (; tb < n_tb; tb += gridDim.x) {
       const uint64_t base = frame_base(fr, tb);
       const uint64_t nx = tb + gridDim.x;
-      const int sh = tile_shift();
       if (nx < n_tb) fetch(frame_base(fr, nx));
       apply_groups(base, sh);
       Stage<T, PER> out;
@@ -379,8 +373,6 @@ __device__ __forceinline__ void lambda_tiles(const T* __restrict__ psi, T* __res
         }
       }
     };
-    // lanes past a small tile hold no amplitude: a thread's valid slots
-    const int n_valid = int(nloc > threadIdx.x ? (nloc - threadIdx.x + NT - 1) / NT : 0u);
     if (tb < n_tb) fetch(tb);
     for (; tb < n_tb; tb += gridDim.x) {
       const uint64_t base = frame_base(fr, tb);
@@ -404,9 +396,7 @@ __device__ __forceinline__ void lambda_tiles(const T* __restrict__ psi, T* __res
           if (!REAL) ali[sl] = 0ull;
         }
       }
-      note_exp(rp, n_valid);
       __syncthreads();
-      const int sh = tile_shift();
       const uint64_t nx = tb + gridDim.x;
       if (nx < n_tb) fetch(nx);
       apply_groups(base, sh);
@@ -430,11 +420,13 @@ __device__ __forceinline__ void lambda_tiles(const T* __restrict__ psi, T* __res
 template <typename T, int B, int NT, int MODE, bool FULL>
 __global__ void __launch_bounds__(NT) k_tile_lambda(const T* __restrict__ psi, T* __restrict__ lam,
                                                     const double* __restrict__ diag, FrameDesc fr,
-                                                    const uint4* __restrict__ blob, uint64_t n_tb) {
+                                                    const uint4* __restrict__ blob, uint64_t n_tb,
+                                                    const double* __restrict__ ep, int n_ep) {
   __shared__ T tp[1 << B];
   __shared__ unsigned long long alr[1 << B], ali[1 << B];
-  __shared__ int sexp[NT / 64];
-  lambda_tiles<T, B, NT, MODE, FULL, false>(psi, lam, diag, fr, blob, n_tb, tp, alr, ali, sexp);
+  __shared__ int red[NT / 64];
+  const int sh = lambda_shift<NT>(blob, ep, n_ep, red);
+  lambda_tiles<T, B, NT, MODE, FULL, false>(psi, lam, diag, fr, blob, n_tb, tp, alr, ali, sh);
 }
 
 // The same for a real psi and a sum with real coefficients: lambda is real,
@@ -467,15 +459,17 @@ template <typename T, int B, int NT, int MODE, bool FULL>
 __global__ void __launch_bounds__(NT) k_tile_lambda_real(const T* __restrict__ psi, T* __restrict__ lam,
                                                          const double* __restrict__ diag, FrameDesc fr,
                                                          const uint4* __restrict__ blob, uint64_t n_tb,
-                                                         const double* __restrict__ guard) {
+                                                         const double* __restrict__ guard,
+                                                         const double* __restrict__ ep, int n_ep) {
   __shared__ RealSlot tp[1 << B];
   __shared__ unsigned long long alr[1 << B];
-  __shared__ int sexp[NT / 64];
+  __shared__ int red[NT / 64];
   if (guard && *guard != 0.0) {
     lambda_poison<T, NT>(lam, fr, n_tb);
     return;
   }
-  lambda_tiles<T, B, NT, MODE, FULL, true, RealSlot>(psi, lam, diag, fr, blob, n_tb, tp, alr, nullptr, sexp);
+  const int sh = lambda_shift<NT>(blob, ep, n_ep, red);
+  lambda_tiles<T, B, NT, MODE, FULL, true, RealSlot>(psi, lam, diag, fr, blob, n_tb, tp, alr, nullptr, sh);
 }
 
 // ---------------------------------------------------------------------------
@@ -729,43 +723,47 @@ __global__ void __launch_bounds__(256) k_group_full(const T* __restrict__ psi, T
 // ---------------------------------------------------------------------------
 template <typename T, int B, int M, bool RT>
 static void tile_lambda_t(const void* psi, void* lam, const double* diag, const FrameDesc& fr, const uint4* blob,
-                          uint64_t n_tb, int grid, const double* guard, hipStream_t st) {
+                          uint64_t n_tb, int grid, const double* guard, const double* ep, int n_ep, hipStream_t st) {
   constexpr int NT = kLambdaThreads;
   const T* p = static_cast<const T*>(psi);
   T* l = static_cast<T*>(lam);
   if constexpr (RT) {
     if (fr.b == B)
       hipLaunchKernelGGL((k_tile_lambda_real<T, B, NT, M, true>), dim3(grid), dim3(NT), 0, st, p, l, diag, fr, blob,
-                         n_tb, guard);
+                         n_tb, guard, ep, n_ep);
     else
       hipLaunchKernelGGL((k_tile_lambda_real<T, B, NT, M, false>), dim3(grid), dim3(NT), 0, st, p, l, diag, fr, blob,
-                         n_tb, guard);
+                         n_tb, guard, ep, n_ep);
   } else {
     if (fr.b == B)
-      hipLaunchKernelGGL((k_tile_lambda<T, B, NT, M, true>), dim3(grid), dim3(NT), 0, st, p, l, diag, fr, blob, n_tb);
+      hipLaunchKernelGGL((k_tile_lambda<T, B, NT, M, true>), dim3(grid), dim3(NT), 0, st, p, l, diag, fr, blob, n_tb,
+                         ep, n_ep);
     else
-      hipLaunchKernelGGL((k_tile_lambda<T, B, NT, M, false>), dim3(grid), dim3(NT), 0, st, p, l, diag, fr, blob, n_tb);
+      hipLaunchKernelGGL((k_tile_lambda<T, B, NT, M, false>), dim3(grid), dim3(NT), 0, st, p, l, diag, fr, blob, n_tb,
+                         ep, n_ep);
   }
 }
 
 template <typename T, int B, bool RT>
 static void tile_lambda_m(bool first, const void* psi, void* lam, const double* diag, const FrameDesc& fr,
-                          const uint4* blob, uint64_t n_tb, int grid, const double* guard, hipStream_t st) {
-  if (first) tile_lambda_t<T, B, 1, RT>(psi, lam, diag, fr, blob, n_tb, grid, guard, st);
-  else tile_lambda_t<T, B, 2, RT>(psi, lam, diag, fr, blob, n_tb, grid, guard, st);
+                          const uint4* blob, uint64_t n_tb, int grid, const double* guard, const double* ep, int n_ep,
+                          hipStream_t st) {
+  if (first) tile_lambda_t<T, B, 1, RT>(psi, lam, diag, fr, blob, n_tb, grid, guard, ep, n_ep, st);
+  else tile_lambda_t<T, B, 2, RT>(psi, lam, diag, fr, blob, n_tb, grid, guard, ep, n_ep, st);
 }
 
 hipError_t launch_tile_lambda(int dtype, bool first, bool real, const void* psi, void* lam, const double* diag,
                               const FrameDesc& fr, const uint4* blob, uint64_t n_tb, int grid, const double* guard,
-                              hipStream_t st) {
+                              const double* ep, int n_ep, hipStream_t st) {
+  if (n_ep < 1 || n_ep > kLambdaThreads) return hipErrorInvalidValue;
   if (dtype == 2) {  // a real state: always the real-part build
-    tile_lambda_m<R64, kTileLamReal, true>(first, psi, lam, diag, fr, blob, n_tb, grid, nullptr, st);
+    tile_lambda_m<R64, kTileLamReal, true>(first, psi, lam, diag, fr, blob, n_tb, grid, nullptr, ep, n_ep, st);
   } else if (dtype == 0) {
-    if (real) tile_lambda_m<double2, kTileLamReal, true>(first, psi, lam, diag, fr, blob, n_tb, grid, guard, st);
-    else tile_lambda_m<double2, kTileLamC128, false>(first, psi, lam, diag, fr, blob, n_tb, grid, guard, st);
+    if (real) tile_lambda_m<double2, kTileLamReal, true>(first, psi, lam, diag, fr, blob, n_tb, grid, guard, ep, n_ep, st);
+    else tile_lambda_m<double2, kTileLamC128, false>(first, psi, lam, diag, fr, blob, n_tb, grid, guard, ep, n_ep, st);
   } else {
-    if (real) tile_lambda_m<float2, kTileLamReal, true>(first, psi, lam, diag, fr, blob, n_tb, grid, guard, st);
-    else tile_lambda_m<float2, kTileLamC64, false>(first, psi, lam, diag, fr, blob, n_tb, grid, guard, st);
+    if (real) tile_lambda_m<float2, kTileLamReal, true>(first, psi, lam, diag, fr, blob, n_tb, grid, guard, ep, n_ep, st);
+    else tile_lambda_m<float2, kTileLamC64, false>(first, psi, lam, diag, fr, blob, n_tb, grid, guard, ep, n_ep, st);
   }
   return hipGetLastError();
 }

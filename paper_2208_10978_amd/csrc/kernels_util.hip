@@ -44,6 +44,23 @@ __global__ void __launch_bounds__(256) k_imag_count(const T* __restrict__ a, uin
   if (threadIdx.x == 0) partials[blockIdx.x] = s;
 }
 
+// partials[block] = the largest binary exponent e with 2^(e-1) <= |re| + |im|
+// over the block's amplitudes (kFxNone when all are zero), as a double: the
+// fixed-point scale of a lambda build comes from their maximum.
+template <typename T>
+__global__ void __launch_bounds__(256) k_amp_exponent(const T* __restrict__ a, uint64_t n_amp,
+                                                      double* __restrict__ partials) {
+  __shared__ int red[4];
+  const uint64_t stride = uint64_t(gridDim.x) * 256;
+  int e = kFxNone;
+  for (uint64_t i = uint64_t(blockIdx.x) * 256 + threadIdx.x; i < n_amp; i += stride)
+    e = max(e, fx_exp(fabs((double)a[i].x) + fabs((double)a[i].y)));
+  e = wave_max_i32(e);
+  if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = e;
+  __syncthreads();
+  if (threadIdx.x == 0) partials[blockIdx.x] = double(max(max(red[0], red[1]), max(red[2], red[3])));
+}
+
 // out[row] = sum_{j < len} in[row * stride + j], fixed order (one block per row)
 __global__ void __launch_bounds__(256) k_reduce_rows(const double* __restrict__ in, uint64_t stride, uint32_t len,
                                                      double* __restrict__ out) {
@@ -185,6 +202,13 @@ hipError_t launch_imag_count(int dtype, const void* a, uint64_t n_amp, int grid,
   return by_dtype(dtype, [&](auto tag) {
     using T = decltype(tag);
     hipLaunchKernelGGL((k_imag_count<T>), dim3(grid), dim3(256), 0, st, static_cast<const T*>(a), n_amp, partials);
+  });
+}
+
+hipError_t launch_amp_exponent(int dtype, const void* a, uint64_t n_amp, int grid, double* partials, hipStream_t st) {
+  return by_dtype(dtype, [&](auto tag) {
+    using T = decltype(tag);
+    hipLaunchKernelGGL((k_amp_exponent<T>), dim3(grid), dim3(256), 0, st, static_cast<const T*>(a), n_amp, partials);
   });
 }
 

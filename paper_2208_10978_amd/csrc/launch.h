@@ -34,6 +34,7 @@ constexpr int kMaxPassSlots = 96;                    // gradient slots per rever
 constexpr int kMaxPassRuns = 1 << 16;                // runs per tile pass
 constexpr int kMaxPassRecs = 1 << 20;                // run records per tile pass
 constexpr uint32_t kPartialStride = 1024;            // max blocks of a gradient pass
+static_assert(kPartialStride <= uint32_t(kLambdaThreads), "one amplitude-exponent partial per lambda thread");
 
 hipError_t launch_fill_basis(int dtype, void* psi, uint64_t n_amp, uint64_t k, hipStream_t st);
 hipError_t launch_run_full(int dtype, bool rev, int grad, void* psi, void* lam, const RunDesc& run,
@@ -56,12 +57,15 @@ hipError_t launch_tile_reverse(int dtype, int grad, void* psi, void* lam, const 
 // built from real parts only (always so for a real state, dtype 2).  guard
 // (real builds of complex states only, may be NULL): device count of psi's
 // nonzero imaginary parts; when it is not zero the pass writes NaN over
-// lambda instead.
+// lambda instead.  ep, n_ep: launch_amp_exponent's partials over psi (n_ep <=
+// kLambdaThreads), which set the fixed-point scale.
 hipError_t launch_tile_lambda(int dtype, bool first, bool real, const void* psi, void* lam, const double* diag,
                               const FrameDesc& fr, const uint4* blob, uint64_t n_tb, int grid, const double* guard,
-                              hipStream_t st);
+                              const double* ep, int n_ep, hipStream_t st);
 // partials[block] = number of the block's amplitudes with a nonzero imaginary part (grid blocks of 256)
 hipError_t launch_imag_count(int dtype, const void* a, uint64_t n_amp, int grid, double* partials, hipStream_t st);
+// partials[block] = largest exponent of |re| + |im| over the block's amplitudes (grid blocks of 256)
+hipError_t launch_amp_exponent(int dtype, const void* a, uint64_t n_amp, int grid, double* partials, hipStream_t st);
 hipError_t launch_tile_expect(int dtype, const void* psi, const FrameDesc& fr, const uint4* blob, uint64_t n_tb,
                               int grid, double* partials, hipStream_t st);
 hipError_t launch_diag_build(double* d, uint64_t n_amp, const uint64_t* z, const double* c, int n_terms,

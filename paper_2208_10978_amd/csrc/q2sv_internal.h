@@ -198,8 +198,8 @@ struct alignas(16) XHdr {
   uint32_t off_coef;   // T_k[r] (re, im) at coef_off + k * n_rec + r
   uint32_t bytes;
   uint32_t n_items;
-  // lambda builds: a tile's fixed-point sums use the scale 2^(fx_shift - e_psi),
-  // e_psi the binary exponent of the tile's largest |re| + |im| of psi
+  // lambda builds: the fixed-point sums use the scale 2^(fx_shift - e_psi),
+  // e_psi the binary exponent of psi's largest |re| + |im|
   // (fx_shift = min(50 - e_g, 62 - e_s), with every record's bound on |G|
   // below 2^e_g and the sum of those bounds below 2^e_s)
   int32_t fx_shift;

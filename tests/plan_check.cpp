@@ -274,7 +274,7 @@ static void check_rotations(int n, int n_occ, long* nw, double* cs, double* bs) 
 // over the terms, on a seeded random state; and each batch's items must
 // cover its records x chunks exactly once.  Lambda is also summed as the
 // kernels sum it, in 64-bit fixed point per tile at the scale 2^s,
-// s = fx_shift - e_psi (e_psi: exponent of the tile's largest |re| + |im|):
+// s = fx_shift - e_psi (e_psi: exponent of the state's largest |re| + |im|):
 // every term must stay below 2^50 (the range of the rounding by 1.5 * 2^52)
 // and every slot's sum of |terms| below 2^62, and the result must match.  The sums mix random
 // strings of weight <= 4, Jordan-Wigner hopping strings with number-operator
@@ -353,6 +353,15 @@ static void check_expect(int n, int b, int c, int n_terms) {
   }
   std::vector<double> lr_got(pr.size(), 0.0), li_got(pr.size(), 0.0);
   std::vector<double> lr_fx(pr.size(), 0.0), li_fx(pr.size(), 0.0);
+  int e_psi = -4000;  // largest exponent of |re| + |im| over the state
+  for (size_t m = 0; m < pr.size(); ++m) {
+    const double a = std::fabs(pr[m]) + std::fabs(pi[m]);
+    int e = 0;
+    if (a > 0.0) {
+      std::frexp(a, &e);
+      e_psi = std::max(e_psi, e);
+    }
+  }
   double want = 0.0, scale = 0.0;
   for (size_t t = 0; t < p.size(); ++t) {
     double re = 0.0, im = 0.0;  // sum_m conj(psi[m]) (-1)^{|(m^x)&z|} psi[m^x]
@@ -424,16 +433,7 @@ static void check_expect(int n, int b, int c, int n_terms) {
         ti[lds_slot(l)] = pi[g];
         glob[lds_slot(l)] = g;
       }
-      // the tile's fixed-point scale and accumulators
-      int e_psi = -4000;
-      for (uint32_t l = 0; l < (1u << nb); ++l) {
-        const double a = std::fabs(tr[l]) + std::fabs(ti[l]);
-        int e = 0;
-        if (a > 0.0) {
-          std::frexp(a, &e);
-          e_psi = std::max(e_psi, e);
-        }
-      }
+      // the pass's fixed-point scale and the tile's accumulators
       const int sh = std::min(std::max(h->fx_shift - e_psi, -1000), 1000);
       const double sc = std::ldexp(1.0, sh);
       std::vector<int64_t> ar_fx(size_t(1) << nb, 0), ai_fx(size_t(1) << nb, 0);

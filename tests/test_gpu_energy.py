@@ -445,9 +445,9 @@ def test_lambda_and_gradient_are_bitwise_reproducible(n, dtype):
 @pytest.mark.parametrize("n,dtype,k", [(14, "c128", 300), (14, "c128", -300), (22, "r64", 300), (22, "r64", -300),
                                        (14, "c64", 20), (14, "c64", -20)])
 def test_lambda_fixed_point_follows_the_state_scale(n, dtype, k):
-    """The fixed-point sums of the fast lambda build take their scale from
-    each tile's largest |psi|, so scaling psi by 2^k (exact in floating
-    point) scales lambda by exactly 2^k and the gradient by 4^k, bit for bit,
+    """The fixed-point sums of lambda take their scale from psi's largest
+    amplitude, so scaling psi by 2^k (exact in floating point) scales lambda
+    by exactly 2^k and the gradient by 4^k, bit for bit,
     and leaves the energy <psi|H|psi>/<psi|psi> bitwise unchanged, far from
     unit norm in both directions (complex64 lambda, stored in FP32 after the
     reverse sweep: to one FP32 unit where it is a normal number)."""
