@@ -177,6 +177,69 @@ __device__ __forceinline__ void enum_walk(const RunDesc& run, const RunRec* __re
   const uint32_t xl = uint32_t(run.x_loc), zl = uint32_t(run.z0_loc);
   const uint32_t sx = lds_swz(xl);  // slot(l ^ x) = slot(l) ^ slot(x)
   const uint32_t nj = run.walk_log > kWalkLaneBits ? 1u << (run.walk_log - kWalkLaneBits) : 1u;
+  if (nj == 1u) {
+    // one position per lane: the pairs of different records are disjoint, so
+    // the reads of RB records leave together, then their updates and writes
+    // (one LDS round trip per RB records instead of one per record)
+    constexpr int RB = 2;
+    for (uint32_t r0 = 0; r0 < run.n_rec; r0 += RB) {
+      R c[RB], s[RB];
+      uint32_t s1[RB], s2[RB];
+      unsigned sg[RB];
+      T a[RB], b[RB], la[RB], lb[RB];
+      double w[RB];
+#pragma unroll
+      for (int q = 0; q < RB; ++q) {
+        w[q] = 0.0;
+        if (r0 + uint32_t(q) < run.n_rec) {
+          const RunRec rec = recs[run.rec_off + r0 + uint32_t(q)];
+          c[q] = R(rec.c);
+          s[q] = REV ? R(-rec.s) : R(rec.s);
+          const uint32_t rest = uint32_t(rec.bits) | wbits;  // uniform
+          sg[q] = zlane_par ^ so ^ parity32(rest & zl);
+          s2[q] = ds ^ lds_swz(rest);  // slot of m'
+          s1[q] = s2[q] ^ sx;          // slot of m
+          if (lane_on) {
+            a[q] = tp[s1[q]];
+            b[q] = tp[s2[q]];
+            if (REV) {
+              la[q] = tl[s1[q]];
+              lb[q] = tl[s2[q]];
+            }
+          }
+        }
+      }
+      __builtin_amdgcn_sched_barrier(0);
+#pragma unroll
+      for (int q = 0; q < RB; ++q) {
+        if (r0 + uint32_t(q) < run.n_rec && lane_on) {
+          if (REV) {
+            if (GRAD) w[q] = grad_w_om<OM>(a[q], b[q], la[q], lb[q], sg[q]);
+            rot_pair_om<OM>(la[q], lb[q], c[q], s[q], sg[q]);
+            tl[s1[q]] = la[q];
+            tl[s2[q]] = lb[q];
+          }
+          rot_pair_om<OM>(a[q], b[q], c[q], s[q], sg[q]);
+          tp[s1[q]] = a[q];
+          tp[s2[q]] = b[q];
+        }
+      }
+      if (GRAD) {
+#pragma unroll
+        for (int q = 0; q < RB; ++q) {
+          if (r0 + uint32_t(q) >= run.n_rec) break;
+          const RunRec& rec = recs[run.rec_off + r0 + uint32_t(q)];
+          if (GRAD == 1) acc[0] += rec.a * w[q];
+          if (GRAD == 2) {
+#pragma unroll
+            for (int k = 0; k < kMaxRunStrings; ++k) acc[k] += ((rec.eps_neg >> k) & 1u) ? -w[q] : w[q];
+          }
+        }
+      }
+    }
+    (void)dl;
+    return;
+  }
   for (uint32_t r = 0; r < run.n_rec; ++r) {
     const RunRec rec = recs[run.rec_off + r];
     const R c = R(rec.c), s = REV ? R(-rec.s) : R(rec.s);
