@@ -80,7 +80,7 @@ __device__ __forceinline__ T lds_at(const T* tp, uint32_t off) {
 // G(v) = sum_cls (-1)^{|v & cls|} A_cls.  G is then the same for every chunk
 // but for the chunk's w0 sign.  The chunk walk reads both ends of each pair
 // and adds lam[m] += G psi[m'] and lam[m'] += conj(G) psi[m] into the tile's
-// fixed-point accumulators (G pre-scaled by the tile's scale sc, each term
+// fixed-point accumulators (G pre-scaled by the launch's 2^sh, each term
 // rounded to an integer by the fused add of kFxMagic) with LDS integer atomic
 // adds: other wavefronts may update the same outputs, in any order, and the
 // sums do not depend on it.  REAL: psi, T and lambda are real; only real
@@ -88,7 +88,7 @@ __device__ __forceinline__ T lds_at(const T* tp, uint32_t off) {
 template <typename TT, bool REAL, int NR, bool MULTI, bool SIGNED>
 __device__ __forceinline__ void x_lambda_records(const XView& xv, const XBatch* bp, const XItem& it, uint64_t base,
                                                  const TT* tp, unsigned long long* alr, unsigned long long* ali,
-                                                 double sc, uint32_t dl, uint32_t sdl) {
+                                                 int sh, uint32_t dl, uint32_t sdl) {
   constexpr int NV = 1 << NR;
   constexpr int NA = MULTI ? NV : 1;
   uint32_t vs[NV];
@@ -131,8 +131,8 @@ __device__ __forceinline__ void x_lambda_records(const XView& xv, const XBatch* 
     }
 #pragma unroll
     for (int v = 0; v < NA; ++v) {
-      gr[v] *= sc;
-      gi[v] *= sc;
+      gr[v] = __builtin_ldexp(gr[v], sh);
+      gi[v] = __builtin_ldexp(gi[v], sh);
     }
     const uint32_t lb = sdl ^ rc.slot;
     uint32_t cw = bp->cword[c0];
@@ -175,14 +175,14 @@ __device__ __forceinline__ void x_lambda_records(const XView& xv, const XBatch* 
 template <typename TT, bool REAL, int NR, bool MULTI>
 __device__ __forceinline__ void x_lambda_records_s(const XView& xv, const XBatch* bp, const XItem& it, uint64_t base,
                                                    const TT* tp, unsigned long long* alr, unsigned long long* ali,
-                                                   double sc, uint32_t dl, uint32_t sdl) {
-  if (bp->signed_chunks) x_lambda_records<TT, REAL, NR, MULTI, true>(xv, bp, it, base, tp, alr, ali, sc, dl, sdl);
-  else x_lambda_records<TT, REAL, NR, MULTI, false>(xv, bp, it, base, tp, alr, ali, sc, dl, sdl);
+                                                   int sh, uint32_t dl, uint32_t sdl) {
+  if (bp->signed_chunks) x_lambda_records<TT, REAL, NR, MULTI, true>(xv, bp, it, base, tp, alr, ali, sh, dl, sdl);
+  else x_lambda_records<TT, REAL, NR, MULTI, false>(xv, bp, it, base, tp, alr, ali, sh, dl, sdl);
 }
 
 template <typename TT, bool REAL>
 __device__ __forceinline__ void x_lambda_item(const XView& xv, const XItem& it, uint64_t base, const TT* tp,
-                                              unsigned long long* alr, unsigned long long* ali, double sc,
+                                              unsigned long long* alr, unsigned long long* ali, int sh,
                                               uint32_t lane) {
   const XBatch* bp = xv.batches + it.batch;
   const uint32_t lp = bp->lane_pack, nl = bp->n_lane;
@@ -194,11 +194,11 @@ __device__ __forceinline__ void x_lambda_item(const XView& xv, const XItem& it, 
   const uint32_t sdl = lds_swz(dl);
   static_assert(kXRegBits == 2, "one case per register-bit count");
   switch (bp->n_reg + (bp->n_cls > 1 ? 4u : 0u)) {
-    case 0: x_lambda_records_s<TT, REAL, 0, false>(xv, bp, it, base, tp, alr, ali, sc, dl, sdl); break;
-    case 1: x_lambda_records_s<TT, REAL, 1, false>(xv, bp, it, base, tp, alr, ali, sc, dl, sdl); break;
-    case 2: x_lambda_records_s<TT, REAL, 2, false>(xv, bp, it, base, tp, alr, ali, sc, dl, sdl); break;
-    case 5: x_lambda_records_s<TT, REAL, 1, true>(xv, bp, it, base, tp, alr, ali, sc, dl, sdl); break;
-    case 6: x_lambda_records_s<TT, REAL, 2, true>(xv, bp, it, base, tp, alr, ali, sc, dl, sdl); break;
+    case 0: x_lambda_records_s<TT, REAL, 0, false>(xv, bp, it, base, tp, alr, ali, sh, dl, sdl); break;
+    case 1: x_lambda_records_s<TT, REAL, 1, false>(xv, bp, it, base, tp, alr, ali, sh, dl, sdl); break;
+    case 2: x_lambda_records_s<TT, REAL, 2, false>(xv, bp, it, base, tp, alr, ali, sh, dl, sdl); break;
+    case 5: x_lambda_records_s<TT, REAL, 1, true>(xv, bp, it, base, tp, alr, ali, sh, dl, sdl); break;
+    case 6: x_lambda_records_s<TT, REAL, 2, true>(xv, bp, it, base, tp, alr, ali, sh, dl, sdl); break;
     default: break;  // several classes need a register bit: not planned
   }
 }
@@ -223,9 +223,11 @@ template <> struct Real<RealSlot> { using type = double; };
 // arrive, so lambda is the same from run to run.
 // ---------------------------------------------------------------------------
 // The fixed-point exponent s of a lambda launch: the blob's fx_shift minus
-// the largest exponent of |re| + |im| over psi (launch_amp_exponent's
-// partials ep[0..n_ep)), clamped; with it no term reaches 2^50 and no slot's
-// sum 2^62.  red: NT / 64 ints of LDS.  One barrier.
+// the largest exponent e of |re| + |im| over psi (launch_amp_exponent's
+// partials ep[0..n_ep)); with it no term reaches 2^50 and no slot's sum 2^62.
+// e is taken as at least -973 (a zero psi gives kFxNone): G 2^s then stays
+// below 2^1023, since fx_shift <= 50 - e_g.  red: NT / 64 ints of LDS.  One
+// barrier.
 template <int NT>
 __device__ __forceinline__ int lambda_shift(const uint4* __restrict__ blob, const double* __restrict__ ep, int n_ep,
                                             int* red) {
@@ -237,8 +239,7 @@ __device__ __forceinline__ int lambda_shift(const uint4* __restrict__ blob, cons
   int m = red[0];
 #pragma unroll
   for (int w = 1; w < NT / 64; ++w) m = max(m, red[w]);
-  const int sh = reinterpret_cast<const XHdr*>(blob)->fx_shift - m;
-  return __builtin_amdgcn_readfirstlane(min(max(sh, -1000), 1000));
+  return __builtin_amdgcn_readfirstlane(reinterpret_cast<const XHdr*>(blob)->fx_shift - max(m, -973));
 }
 
 // The tile passes of a lambda build, on the block's LDS arrays: tp, the psi
@@ -263,20 +264,19 @@ __device__ __forceinline__ void lambda_tiles(const T* __restrict__ psi, T* __res
   const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
 
   // every wavefront on the whole tile, on its work list, scale 2^sh
-  auto apply_groups = [&](uint64_t base, int sh) {
-    const double sc = __builtin_ldexp(1.0, sh);
+  auto apply_groups = [&](uint64_t base) {
     const XView xv(blob);
     const bool lists = xv.hdr->n_waves == uint32_t(NW);
     const uint32_t i0 = lists ? xv.start[wave] : uint32_t(wave);
     const uint32_t i1 = lists ? xv.start[wave + 1] : xv.hdr->n_items;
     const uint32_t step = lists ? 1u : uint32_t(NW);
     for (uint32_t i = i0; i < i1; i += step)
-      x_lambda_item<TT, REAL>(xv, xv.items[i], base, tp, alr, ali, sc, uint32_t(lane));
+      x_lambda_item<TT, REAL>(xv, xv.items[i], base, tp, alr, ali, sh, uint32_t(lane));
     __syncthreads();
   };
-  // a finished slot: start + accumulator * unit
-  auto result = [&](double start, unsigned long long acc, double unit) {
-    return fma(double(static_cast<long long>(acc)), unit, start);
+  // a finished slot: start + accumulator * 2^-sh (the scaling is exact)
+  auto result = [&](double start, unsigned long long acc) {
+    return start + __builtin_ldexp(double(static_cast<long long>(acc)), -sh);
   };
   // the thread index, opaque to the optimiser: the LDS slots of the staged
   // values are recomputed where they are used instead of being held across
@@ -336,15 +336,14 @@ __device__ __forceinline__ void lambda_tiles(const T* __restrict__ psi, T* __res
       const uint64_t base = frame_base(fr, tb);
       const uint64_t nx = tb + gridDim.x;
       if (nx < n_tb) fetch(frame_base(fr, nx));
-      apply_groups(base, sh);
+      apply_groups(base);
       Stage<T, PER> out;
-      const double unit = __builtin_ldexp(1.0, -sh);
       const uint32_t tid = tid_here();
 #pragma unroll
       for (int i = 0; i < PER; ++i) {
         const uint32_t sl = lds_swz(tid + uint32_t(i) * NT);
-        out.re[i] = R(result(ir[i], alr[sl], unit));
-        out.im[i] = REAL ? R(0) : R(result(ii[i], ali[sl], unit));
+        out.re[i] = R(result(ir[i], alr[sl]));
+        out.im[i] = REAL ? R(0) : R(result(ii[i], ali[sl]));
       }
       if (nx < n_tb) put();
       tile_send<T, PER, NT>(lam, ta, fr, base, out);
@@ -399,15 +398,14 @@ __device__ __forceinline__ void lambda_tiles(const T* __restrict__ psi, T* __res
       __syncthreads();
       const uint64_t nx = tb + gridDim.x;
       if (nx < n_tb) fetch(nx);
-      apply_groups(base, sh);
-      const double unit = __builtin_ldexp(1.0, -sh);
+      apply_groups(base);
 #pragma unroll
       for (int i = 0; i < PER; ++i) {
         const uint32_t l = threadIdx.x + uint32_t(i) * NT;
         if (l < nloc) {
           const uint32_t sl = lds_swz(l);
-          const double vr = result(ir[i], alr[sl], unit);
-          const double vi = REAL ? 0.0 : result(ii[i], ali[sl], unit);
+          const double vr = result(ir[i], alr[sl]);
+          const double vi = REAL ? 0.0 : result(ii[i], ali[sl]);
           lam[base | frame_deposit(lut, l)] = cmake<T>(R(vr), R(vi));
         }
       }

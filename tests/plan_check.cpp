@@ -434,7 +434,7 @@ static void check_expect(int n, int b, int c, int n_terms) {
         glob[lds_slot(l)] = g;
       }
       // the pass's fixed-point scale and the tile's accumulators
-      const int sh = std::min(std::max(h->fx_shift - e_psi, -1000), 1000);
+      const int sh = h->fx_shift - std::max(e_psi, -973);
       const double sc = std::ldexp(1.0, sh);
       std::vector<int64_t> ar_fx(size_t(1) << nb, 0), ai_fx(size_t(1) << nb, 0);
       std::vector<double> mag(size_t(1) << nb, 0.0);  // sum of |terms| per slot, scaled

@@ -484,3 +484,27 @@ def test_lambda_fixed_point_follows_the_state_scale(n, dtype, k):
         assert torch.all((b[normal] - a[normal] * 2.0 ** k).abs() <= 2.0 ** -23 * (a[normal] * 2.0 ** k).abs())
     else:
         assert torch.equal(l2, l1 * 2.0 ** k)
+
+
+@pytest.mark.parametrize("dtype", ["c128", "r64"])
+def test_lambda_of_a_zero_state_is_zero(dtype):
+    """A zero psi gives lambda = H psi = 0 exactly, also with coefficients
+    scaled by 2^40: the fixed-point scale of a zero state stays finite (its
+    amplitude exponent is floored), so no term becomes inf * 0."""
+    announce(f"lambda of a zero state: 22 qubits {dtype}")
+    n = 22
+    h, eri = synthetic_integrals(n, 1000 + n)
+    ham = jordan_wigner(h, eri)
+    coef = np.asarray(ham.c, dtype=np.float64) * 2.0 ** 40
+    psi = StateVector(n, dtype); lam = StateVector(n, dtype)
+    psi.amps.zero_()
+    energy = torch.empty(2, dtype=torch.float64, device="cuda")
+    grad = torch.empty(1, dtype=torch.float64, device="cuda")
+    # one rotation by angle 0 on a real string (a Y on qubit 0)
+    B.sv_adjoint_grad(psi.handle, lam.handle, ham.x, ham.z, coef, np.array([1], np.uint64),
+                      np.array([1], np.uint64), np.array([0.0]), energy, grad)
+    torch.cuda.synchronize()
+    values = torch.view_as_real(lam.amps) if lam.amps.is_complex() else lam.amps
+    assert int(torch.count_nonzero(values)) == 0
+    assert float(grad[0].item()) == 0.0
+    psi.free(); lam.free()
