@@ -42,7 +42,9 @@ def test_resident_list_matches_planning_each_call(n, dtype):
     """Same plan, same arithmetic: the state, energy and gradient are bitwise
     equal (lambda in fixed point on both sides), call after call on one
     handle: all amplitudes nonzero, then some exactly zero (their runs have no
-    forward records, so the kept schedule is made again), then nonzero again."""
+    forward records, so the kept schedule is made again), then nonzero again,
+    then all zero (every run the identity: the state stays the HF basis
+    state)."""
     announce(f"resident rotations n={n} {dtype}")
     ne = n // 2
     h, eri = synthetic_integrals(n, 1000 + n)
@@ -52,13 +54,17 @@ def test_resident_list_matches_planning_each_call(n, dtype):
     zeros = base.copy()
     zeros[::5] = 0.0
     ev = UCCSDEvaluator(ham, rot, ne, dtype)
-    for theta in (base, zeros, 0.5 * base):
+    for theta in (base, zeros, 0.5 * base, np.zeros_like(base)):
         psi = ev.state(theta)
         e, g = ev.energy_and_grad(theta)
         torch.cuda.synchronize()
         got = (e.cpu().numpy(), g.cpu().numpy(), psi.amps.cpu().numpy())
         psi.free()
         want = _planned_each_call(ham, rot, ne, dtype, theta)
+        if not np.any(theta):
+            hf_state = np.zeros_like(got[2])
+            hf_state[(1 << ne) - 1] = 1
+            assert np.array_equal(got[2], hf_state)
         assert np.array_equal(got[2], want[2])
         assert np.array_equal(got[0], want[0])
         assert np.array_equal(got[1], want[1])
