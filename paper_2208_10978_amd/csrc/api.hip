@@ -286,7 +286,11 @@ static int tiling_get(sv_hamiltonian* h, int dtype, int role, DevTiling** out) {
     const int c = std::min(row_bits(dtype), h->n);
     // kernels read the tables through scalar loads, so a tile's groups need
     // not be split
-    t.host = build_tiling(h->groups, h->n, b, c, size_t(1) << 24, role == 0 ? kExpectThreads / 64 : kLambdaThreads / 64);
+    // work items: a third of a wavefront's share for the expectation, two
+    // thirds for lambda (whose per-record set-up weighs more than its pair
+    // imbalance: 28-qubit real lambda 392 -> 378 ms)
+    t.host = build_tiling(h->groups, h->n, b, c, size_t(1) << 24, role == 0 ? kExpectThreads / 64 : kLambdaThreads / 64,
+                          role == 0 ? 3.0 : 1.5);
     if (t.host.blob_overflow) return fail(SV_EINVAL, "internal: a tile's group tables are too large");
     Packer pk;
     t.o_frames = pk.add(t.host.frames.data(), t.host.frames.size() * sizeof(FrameDesc));

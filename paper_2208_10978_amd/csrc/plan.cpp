@@ -739,7 +739,7 @@ uint32_t deviation(const std::vector<uint32_t>& v, const std::vector<int>& idx, 
 }  // namespace
 
 void pack_expect_blob(HTiling& t, const std::vector<HGroup>& gs, const std::vector<int>& members, uint64_t qmask,
-                      size_t max_blob, int n_waves) {
+                      size_t max_blob, int n_waves, double item_parts) {
   const int fb = popc(qmask);
   const uint32_t all = fb >= 32 ? ~0u : ((1u << fb) - 1u);
   std::vector<XBatch> xb;
@@ -867,13 +867,13 @@ void pack_expect_blob(HTiling& t, const std::vector<HGroup>& gs, const std::vect
     g_max = std::max(g_max, worst);
     g_sum += worst;
   }
-  // work items: batches cut (by records, then by chunks) to at most a third
-  // of a wavefront's share, then longest first onto the least loaded
-  // wavefront
+  // work items: batches cut (by records, then by chunks) to at most
+  // 1/item_parts of a wavefront's share, then longest first onto the least
+  // loaded wavefront
   const int NW = std::max(1, n_waves);
   double total = 0.0;
   for (double v : cost) total += v;
-  const double target = std::max(1.0, total / double(NW) / 3.0);
+  const double target = std::max(1.0, total / double(NW) / std::max(item_parts, 0.25));
   std::vector<XItem> items;
   std::vector<double> icost;
   for (size_t bi = 0; bi < xb.size(); ++bi) {
@@ -957,7 +957,8 @@ void pack_expect_blob(HTiling& t, const std::vector<HGroup>& gs, const std::vect
   std::memcpy(t.blob.data() + at, bytes.data(), h.bytes);
 }
 
-HTiling build_tiling(const std::vector<HGroup>& gs, int n, int b, int c, size_t max_blob, int n_waves) {
+HTiling build_tiling(const std::vector<HGroup>& gs, int n, int b, int c, size_t max_blob, int n_waves,
+                     double item_parts) {
   HTiling t;
   t.b = b;
   t.c = c;
@@ -1045,7 +1046,7 @@ HTiling build_tiling(const std::vector<HGroup>& gs, int n, int b, int c, size_t 
     size_t bytes = fixed;
     auto flush = [&]() {
       t.frames.push_back(make_frame(q, n, c));
-      pack_expect_blob(t, gs, chunk, q, max_blob, n_waves);
+      pack_expect_blob(t, gs, chunk, q, max_blob, n_waves, item_parts);
       chunk.clear();
       bytes = fixed;
     };

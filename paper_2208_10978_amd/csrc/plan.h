@@ -145,12 +145,14 @@ struct HTiling {
 // Frames (greedy cover of the groups' flip masks, then each group moved to
 // the least loaded frame that contains it) and one projected-sum blob (XHdr)
 // per frame and at most max_blob bytes, with per-wavefront work lists
-// balanced for n_waves wavefronts; groups that fit no b-bit frame become
-// whole-state groups.
-HTiling build_tiling(const std::vector<HGroup>& gs, int n, int b, int c, size_t max_blob, int n_waves);
+// balanced for n_waves wavefronts from work items of at most 1/item_parts of
+// a wavefront's share (finer items balance better but repeat each record's
+// set-up); groups that fit no b-bit frame become whole-state groups.
+HTiling build_tiling(const std::vector<HGroup>& gs, int n, int b, int c, size_t max_blob, int n_waves,
+                     double item_parts = 3.0);
 
 // One projected-sum blob (XHdr) of a tile's groups, appended to t.
 void pack_expect_blob(HTiling& t, const std::vector<HGroup>& gs, const std::vector<int>& members, uint64_t qmask,
-                      size_t max_blob, int n_waves);
+                      size_t max_blob, int n_waves, double item_parts = 3.0);
 
 }  // namespace q2sv

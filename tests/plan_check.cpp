@@ -295,7 +295,7 @@ static int64_t fx_term(double a, double b, double c, double d) {
   return bits - mb;
 }
 static double g_x_diff = 0.0;  // largest |walk - direct| / (sum |c| <psi|psi>)
-static void check_expect(int n, int b, int c, int n_terms) {
+static void check_expect(int n, int b, int c, int n_terms, double item_parts = 3.0) {
   const uint64_t all = (uint64_t(1) << n) - 1;
   const uint64_t low = (uint64_t(1) << c) - 1;
   std::vector<PauliIn> p;
@@ -380,7 +380,7 @@ static void check_expect(int n, int b, int c, int n_terms) {
   const std::vector<HGroup> gs = build_groups(p.data(), coef.data(), int64_t(p.size()), &err);
   CHECK(err.empty(), "build_groups: %s", err.c_str());
   const int NW = 16;
-  const HTiling T = build_tiling(gs, n, b, c, size_t(1) << 24, NW);
+  const HTiling T = build_tiling(gs, n, b, c, size_t(1) << 24, NW, item_parts);
   CHECK(!T.blob_overflow, "expectation blob overflow");
   CHECK(T.groups.empty(), "%zu whole-state groups", T.groups.size());
   double got = 0.0;
@@ -615,6 +615,7 @@ int main() {
   check_expect(12, 8, 3, 400);                             // several frames and tiles
   check_expect(9, 14, 3, 150);                             // one frame smaller than a tile
   check_expect(14, 10, 4, 600);
+  check_expect(14, 10, 4, 600, 1.5);                       // the lambda tilings' coarser work items
   if (g_fail) {
     std::printf("%d failures over %ld walks\n", g_fail, nw);
     return 1;
